@@ -1,0 +1,142 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+Holds problem definitions (coefficient families, boxes, sparsity parameters)
+and seeded random-input generators only; none of the method's arithmetic
+lives here.
+"""
+import math
+
+import numpy as np
+
+
+def amplitudes(d):
+    """0.5 j^-2, j = 1..d (all workloads)."""
+    return [0.5 * j ** -2.0 for j in range(1, d + 1)]
+
+
+def modes_diagonal(d):
+    """sin(j pi x1) sin(j pi x2): the 4-term CPU-scale workload."""
+    return list(range(1, d + 1)), list(range(1, d + 1))
+
+
+def modes_split(d):
+    """sin(ceil(j/2) pi x1) sin(floor(j/2 + 1) pi x2): the larger workloads."""
+    return [math.ceil(j / 2) for j in range(1, d + 1)], [j // 2 + 1 for j in range(1, d + 1)]
+
+
+def pde_problem(n, d, N, modes="split", a0=1.0):
+    m1, m2 = (modes_diagonal if modes == "diagonal" else modes_split)(d)
+    return dict(sampler="pde", mesh_n=n, d=d, k_lo=[-N] * d, k_hi=[N] * d,
+                a0=a0, amp=amplitudes(d), mode1=m1, mode2=m2)
+
+
+def params(s, r, theta, relative=True, **kw):
+    p = dict(s=s, s_local=s, r=r, theta=theta, theta_relative=relative,
+             lattice_c=2.0, lattice_tries=8, lattice_max=64, lattice_mmax=9601)
+    p.update(kw)
+    return p
+
+
+# The five synthetic workloads (uniform P1 meshes, periodic coefficient with
+# 0.5 j^-2 amplitudes, f = 1, zero Dirichlet data).
+WORKLOADS = {
+    # CPU scale: h = 1/16, d = 4, box [-16,16]^4, s = 50, rel. threshold 1e-4, r = 3
+    "cpu16_d4": (pde_problem(16, 4, 16, modes="diagonal"), params(50, 3, 1e-4)),
+    # h = 1/64 (3969 nodes), d = 10, box [-32,32]^10, s = 200, rel. threshold 1e-5, r = 5
+    "mesh64_d10": (pde_problem(64, 10, 32), params(200, 5, 1e-5)),
+    # h = 1/128 (16129 nodes), d = 20, box [-64,64]^20, s = 500, rel. threshold 1e-6, r = 5
+    "mesh128_d20": (pde_problem(128, 20, 64), params(500, 5, 1e-6)),
+}
+
+
+def uneven_batch(seed=1, jobs=12):
+    """12 jobs mixing meshes 32^2/64^2/128^2, d in {8,16,30}, N in {16,32,64}, s in {100,300,500}."""
+    g = np.random.default_rng(seed)
+    out = []
+    for _ in range(jobs):
+        n = int(g.choice([32, 64, 128]))
+        d = int(g.choice([8, 16, 30]))
+        N = int(g.choice([16, 32, 64]))
+        s = int(g.choice([100, 300, 500]))
+        out.append((pde_problem(n, d, N), params(s, 5, 1e-5), int(g.integers(1, 2 ** 31))))
+    return out
+
+
+def serving_stream(seed=1, rate=4.0, jobs=20, meshes=(32, 64), dims=(4, 30), Ns=(16, 64), ss=(50, 800)):
+    """Poisson arrivals (mean `rate` jobs/s) of jobs with random mesh, d, N and s."""
+    g = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(jobs):
+        t += float(g.exponential(1.0 / rate))
+        n = int(g.choice(list(meshes)))
+        d = int(g.integers(dims[0], dims[1] + 1))
+        N = int(g.choice([v for v in (16, 32, 64) if Ns[0] <= v <= Ns[1]]))
+        s = int(g.integers(ss[0], ss[1] + 1))
+        out.append((t, pde_problem(n, d, N), params(s, 5, 1e-5), int(g.integers(1, 2 ** 31))))
+    return out
+
+
+def trig_poly(seed, d, N, G, n_freq, max_active=4, kmax=4, cmin=1e-3, cmax=1.0, per_node=0.7):
+    """Seeded real trigonometric polynomials with a shared, +-closed support.
+
+    Returns (K, P): K (n x d) frequencies in [-N, N]^d with at most
+    `max_active` non-zero components of size <= kmax, closed under k -> -k;
+    P (n x G) complex coefficients with P[-k] = conj(P[k]); each node uses a
+    random +-closed subset of the support (fraction `per_node`), the others
+    are exactly zero.  Non-zero magnitudes lie in [cmin, cmax].
+    """
+    g = np.random.default_rng(seed)
+    kmax = min(kmax, N)
+    S = {tuple([0] * d)}
+    while len(S) < n_freq:
+        k = np.zeros(d, dtype=np.int64)
+        act = g.choice(d, size=int(g.integers(1, min(max_active, d) + 1)), replace=False)
+        k[act] = g.integers(1, kmax + 1, size=len(act)) * g.choice([-1, 1], size=len(act))
+        S.add(tuple(k))
+        S.add(tuple(-k))
+    K = np.array(sorted(S), dtype=np.int64)
+    index = {tuple(k): a for a, k in enumerate(K)}
+    P = np.zeros((len(K), G), dtype=np.complex128)
+    for a, k in enumerate(K):
+        b = index[tuple(-k)]
+        if b < a:
+            continue
+        use = g.random(G) < per_node
+        if a == b:  # k = 0: real coefficient
+            mag = g.uniform(cmin, cmax, G)
+            P[a] = np.where(use, mag * g.choice([-1.0, 1.0], G), 0.0)
+        else:
+            mag = g.uniform(cmin, cmax, G)
+            ph = g.uniform(0, 2 * np.pi, G)
+            c = np.where(use, mag * np.exp(1j * ph), 0.0)
+            P[a] = c
+            P[b] = np.conj(c)
+    return K, P
+
+
+def sample_matrix(seed, M, G, kind="smooth"):
+    """Seeded real test samples (M x G) for the lattice-DFT stage."""
+    g = np.random.default_rng(seed)
+    if kind == "smooth":
+        base = 0.05 + 0.01 * g.standard_normal(G)
+        return base[None, :] + 1e-3 * g.standard_normal((M, G))
+    return g.standard_normal((M, G))
+
+
+def candidate_set(seed, n_parent, t, n_child, kmax=4, max_active=4):
+    """A +-closed parent set (sorted) and a symmetric child range, shaped like
+    the detected sets of the workloads (few active dimensions, small |k_j|)."""
+    g = np.random.default_rng(seed)
+    S = {tuple([0] * (t - 1))}
+    if (t - 1) == 1 and n_parent > 2 * kmax + 1:
+        raise ValueError("a 1-D parent set holds at most 2*kmax+1 values")
+    while len(S) < n_parent:
+        k = np.zeros(t - 1, dtype=np.int64)
+        act = g.choice(t - 1, size=int(g.integers(1, min(max_active, t - 1) + 1)), replace=False)
+        k[act] = g.integers(1, kmax + 1, size=len(act)) * g.choice([-1, 1], size=len(act))
+        S.add(tuple(k))
+        S.add(tuple(-k))
+    parent = np.array(sorted(S), dtype=np.int64)
+    child = np.arange(-(n_child // 2), n_child // 2 + 1, dtype=np.int64)
+    return parent, child
