@@ -1,0 +1,162 @@
+"""Benchmark of the usFFT hot path on one MI355X.
+
+One step = one whole usFFT job (Alg. 1 steps 1-3: sampling nodes, batched
+PDE solves, lattice DFTs, selection, union, join, lattice planning) on the
+h = 1/64 workload: P1 FEM with 3969 nodes, d = 10, box [-32,32]^10, s = 200,
+relative threshold 1e-5, r = 5, seeded synthetic coefficient draws.
+
+The headline value is PDE sample solves per second of the batched float32
+path with float64 refinement (the job's solves divided by its wall time);
+the plain float64 GPU path is timed the same way beside it.  Prints one JSON
+line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PDE sample solves/s + lattice-FFT GB/s, batched-FP32 vs plain FP64; p50/p99 job"
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}  # MI355X vector peaks
+FLOPS_PER_NODE_ITER = 26  # Jacobi-PCG iteration on the 5-point operator, per node
+
+
+def pct(v, q):
+    v = sorted(v)
+    if not v:
+        return None
+    i = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
+    return v[i]
+
+
+def run_path(U, plan, seed, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        U.detect(plan, seed).close()
+    torch.cuda.synchronize()
+    lat, stats = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t = time.perf_counter()
+        r = U.detect(plan, seed)
+        lat.append(time.perf_counter() - t)
+        stats.append(r.stats)
+        n = r.n
+        r.close()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, lat, stats, n
+
+
+def cpu_baseline(prob, budget_s):
+    """Oracle solves (banded Cholesky, float64) on the host, one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.fem import PDESampler
+
+    S = PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    g = np.random.default_rng(0)
+    done = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            S.solve_one(g.random(prob["d"]))
+            done += 1
+        dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": "%d float64 banded-Cholesky P1 solves of the h=1/64, d=10 problem at random y "
+                      "(%.1f s, one thread)" % (done, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mesh64_d10")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for rocprof byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2109_04131_amd as U
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    prob, par = W.WORKLOADS[args.workload]
+    plan32 = U.Plan(prob, dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12))
+    wall32, lat32, st32, nI = run_path(U, plan32, args.seed, args.steps, args.warmup)
+    out = {}
+    if not args.skip_fp64:
+        plan64 = U.Plan(prob, dict(par, precision=U.FP64, pcg_rtol=1e-12))
+        wall64, lat64, st64, _ = run_path(U, plan64, args.seed, args.steps, args.warmup)
+        s64 = sum(s["samples"] for s in st64)
+        out["fp64_path"] = {
+            "samples_per_s": s64 / wall64, "ms_per_step": 1e3 * wall64 / args.steps,
+            "p50_job_s": pct(lat64, 50), "p99_job_s": pct(lat64, 99),
+            "pcg_iters_per_solve": sum(s["pcg_iterations"] for s in st64) / max(1, s64),
+            "fft_GBps": sum(s["dft_bytes"] for s in st64) / max(1e-9, sum(s["ms_dft"] for s in st64)) / 1e6,
+        }
+    samples = sum(s["samples"] for s in st32)
+    value = samples / wall32
+    ms_sample = sum(s["ms_sample"] for s in st32)
+    launches = sum(s["sample_launches"] for s in st32)
+    iters = sum(s["pcg_iterations"] for s in st32)
+    G = plan32.G
+    flops = iters * G * FLOPS_PER_NODE_ITER
+    avg_ms = ms_sample / max(1, launches)
+    achieved = (flops / max(1, launches)) / (avg_ms * 1e-3) / 1e12
+    fft_gbps = sum(s["dft_bytes"] for s in st32) / max(1e-9, sum(s["ms_dft"] for s in st32)) / 1e6
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 refinement)",
+        "data": "synthetic",
+        "config": {"workload": "mesh64_d10: P1 FEM h=1/64 (G=3969), d=10, box [-32,32]^10, s=200, "
+                               "rel. threshold 1e-5, r=5, seed %d" % args.seed,
+                   "samples_per_job": samples / args.steps, "detected_frequencies": nI,
+                   "lattices_per_job": sum(s["lattices"] for s in st32) / args.steps},
+        "p50_job_s": pct(lat32, 50),
+        "p99_job_s": pct(lat32, 99),
+        "fft_GBps": fft_gbps,
+        "pcg_iters_per_solve": iters / max(1, samples),
+        "roofline": {"kernel": "pcg32r (batched float32 Jacobi-PCG + float64 refinement)",
+                     "bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["f32"], "traffic": None,
+                     "avg_launch_ms": avg_ms, "launches": launches,
+                     "workgroup": [st32[0]["solver_block"], st32[0]["solver_npt"]]},
+    }
+    res.update(out)
+    if args.cpu_seconds > 0:
+        res["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * usfft.h — C ABI of the MI355X (gfx950) uniform sparse FFT hot path.
+ *
+ * The method is Alg. 1 of Kaemmerer, Potts, Taubert, "The uniform sparse FFT
+ * with application to PDEs with random coefficients": a dimension-incremental
+ * sparse FFT over the random parameters y that detects ONE frequency set I
+ * shared by the functions u(x_g, .) at all G spatial nodes, using one PDE
+ * solve per sampling node y for all nodes at once (Sec. 3.1).
+ *
+ * Conventions for every call:
+ *  - Every function returns usfft_status (0 = OK, < 0 = error).  No exception
+ *    or abort crosses the ABI; usfft_last_error() returns a thread-local
+ *    message describing the last failure.
+ *  - "_dev" pointers are device (HIP) memory owned by the caller; "_host"
+ *    pointers are host memory owned by the caller.  The library never keeps a
+ *    caller pointer beyond the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Work
+ *    is enqueued on it; calls that must read sizes back (detect, family,
+ *    compact) synchronise that stream before returning.
+ *  - Index sets are int32 row-major (n x t) and lexicographically ordered
+ *    where stated.  Coefficient/sample matrices are row-major with an explicit
+ *    leading dimension.
+ */
+#ifndef USFFT_H
+#define USFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  USFFT_OK = 0,
+  USFFT_EINVAL = -1,    /* bad argument, shape or unsupported size          */
+  USFFT_ENOMEM = -2,    /* device or host allocation failed                 */
+  USFFT_EHIP = -3,      /* a HIP runtime call failed (message has details)  */
+  USFFT_ENOCONV = -4,   /* a PCG solve missed its tolerance within maxit    */
+  USFFT_ELATTICE = -5   /* no lattice family within lattice_max attempts    */
+} usfft_status;
+
+enum { USFFT_SAMPLER_PDE = 0, USFFT_SAMPLER_TRIG_POLY = 1 };
+enum { USFFT_FP64 = 0, USFFT_FP32_REFINE = 1 };
+enum { USFFT_OUT_MAG2 = 0, USFFT_OUT_COMPLEX = 1 };
+
+typedef struct usfft_plan_s* usfft_plan_t;
+typedef struct usfft_result_s* usfft_result_t;
+
+/* Problem of Alg. 1 ("Input": Gamma, u, T_G).  All arrays are host memory and
+ * are copied by usfft_plan_create.
+ *  Gamma = box prod_j [k_lo[j], k_hi[j]] (Alg. 1 input; Table 4.1 uses
+ *  [-N, N]^d).
+ *  PDE sampler (eq. (1.1), (1.2), periodic model of Sec. 3.2 with
+ *  Theta_j(y) = sin(2 pi y_j)):
+ *     -div(a grad u) = 1 on (0,1)^2, u = 0 on the boundary,
+ *     a(x,y) = a0 + sum_j amp[j] sin(2 pi y_j) sin(mode1[j] pi x1) sin(mode2[j] pi x2),
+ *  P1 elements on the uniform mesh h = 1/mesh_n, every cell split along its
+ *  (i,j)-(i+1,j+1) diagonal, a evaluated at triangle centroids; T_G = the
+ *  G = (mesh_n-1)^2 interior nodes, g = (j-1)(mesh_n-1) + (i-1).
+ *  TRIG_POLY sampler (test functions of Theorem 1.1):
+ *     u_g(y) = Re sum_{a<n_poly} c[a,g] exp(2 pi i poly_k[a].y),
+ *  poly_c is n_poly x G x 2 doubles (re, im). */
+typedef struct {
+  int32_t d;
+  const int32_t* k_lo;
+  const int32_t* k_hi;
+  int32_t sampler;
+  /* PDE */
+  int32_t mesh_n;        /* 4 <= mesh_n <= 64                                */
+  double a0;
+  const double* amp;     /* d                                                */
+  const int32_t* mode1;  /* d                                                */
+  const int32_t* mode2;  /* d                                                */
+  /* TRIG_POLY */
+  int64_t G_poly;
+  int64_t n_poly;
+  const int32_t* poly_k; /* n_poly x d                                       */
+  const double* poly_c;  /* n_poly x G_poly x 2                              */
+} usfft_problem;
+
+/* Parameters of Alg. 1 ("Input": s, s_local, Algorithm A, theta, r) and of
+ * this implementation. */
+typedef struct {
+  int32_t s, s_local, r;   /* sparsity parameters and detection iterations   */
+  double theta;            /* threshold                                      */
+  int32_t theta_relative;  /* 1: theta_abs = theta * max |c| of stage t=1,i=1 */
+  double tie_rel;          /* values within tie_rel of tau_g^2 are ties (2^-30) */
+  int32_t precision;       /* USFFT_FP64 or USFFT_FP32_REFINE                */
+  double lattice_c;        /* lattice size factor c (2)                      */
+  int32_t lattice_tries;   /* generator candidates per attempt (8)           */
+  int32_t lattice_max;     /* attempts before USFFT_ELATTICE (64)            */
+  int32_t lattice_mmax;    /* largest lattice size (<= 9601)                 */
+  double pcg_rtol;         /* relative residual of every solve (1e-12)       */
+  int32_t pcg_maxit;       /* PCG iterations per solve (or inner solve)      */
+  double inner_rtol;       /* FP32_REFINE: inner float32 PCG tolerance (1e-5) */
+  int32_t max_refine;      /* FP32_REFINE: float64 residual corrections (8)  */
+  int32_t solver_config;   /* -1: autotune at plan time, -2: built-in choice,
+                              >= 0: force that workgroup shape              */
+} usfft_params;
+
+/* Statistics of one usfft_detect run. */
+typedef struct {
+  int64_t samples;          /* PDE solves (sampling nodes) used              */
+  int64_t samples_step1;
+  int64_t samples_step2;
+  int64_t samples_step3;
+  int64_t lattices;         /* rank-1 lattices over all families             */
+  int64_t max_candidates;   /* largest |J_t|                                 */
+  int64_t pcg_iterations;   /* sum over solves (inner iterations for FP32)   */
+  int64_t sample_launches;  /* sampler kernel launches                       */
+  int64_t dft_launches;     /* line + lattice DFT kernel launches            */
+  int64_t solver_block;     /* workgroup size of the PDE solver              */
+  int64_t solver_npt;       /* mesh nodes per thread of the PDE solver       */
+  double theta_abs;         /* absolute threshold used                       */
+  double ms_sample;         /* device time in the sampler kernels            */
+  double ms_dft;            /* device time in DFT kernels                    */
+  double ms_select;         /* device time in selection kernels              */
+  double ms_total;          /* wall time of the call                         */
+  double dft_bytes;         /* algorithmic bytes moved by lattice DFTs       */
+} usfft_stats;
+
+const char* usfft_last_error(void);
+const char* usfft_version(void);
+
+/* Plan: validate and copy the problem, upload static tables (coefficient
+ * tables of eq. (1.2) at triangle centroids, polynomial coefficients), size
+ * nothing data-dependent yet.  Errors: EINVAL, ENOMEM, EHIP. */
+usfft_status usfft_plan_create(const usfft_problem* prob, const usfft_params* par,
+                               usfft_plan_t* out);
+void usfft_plan_destroy(usfft_plan_t plan);
+/* G of the plan's node set T_G. */
+int64_t usfft_plan_nodes(usfft_plan_t plan);
+
+/* Alg. 1, steps 1 to 3, on the device.  Output: the detected set I
+ * (lexicographic) and the coefficients c_k(u_{x_g}), k in I, for every node
+ * (Alg. 1 "Output").  Synchronises `stream`.  Errors: ENOCONV, ELATTICE,
+ * ENOMEM, EHIP. */
+usfft_status usfft_detect(usfft_plan_t plan, uint64_t seed, void* stream,
+                          usfft_result_t* out);
+
+usfft_status usfft_result_info(usfft_result_t res, int64_t* n_freq, int32_t* d,
+                               int64_t* G, usfft_stats* stats);
+/* freqs_host: n_freq x d int32 (lexicographic); coeffs_host: n_freq x G x 2
+ * doubles (re, im), may be NULL. */
+usfft_status usfft_result_copy(usfft_result_t res, int32_t* freqs_host, double* coeffs_host);
+void usfft_result_destroy(usfft_result_t res);
+
+/* Evaluation formula of Sec. 3.1 (periodic model, eq. (3.1) with phi = id):
+ * out_dev[j*G + g] = Re sum_{k in I} c_k(u_{x_g}) exp(2 pi i k.y_j),
+ * y_dev: n x d doubles.  Not part of the timed hot path. */
+usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n,
+                        double* out_dev, void* stream);
+
+/* ---- Stage entry points: each step of the hot path as its own call ---- */
+
+/* Black-box sampler (Sec. 2.1; Alg. 1 steps 1&2a and 2c): one solve per row
+ * of y_dev (n x d doubles, components in [0,1)), sample of node g written to
+ * u_dev[g*ld + col0 + row] as float64 (out_fp32 = 0) or float32 (1).  With
+ * the plan's precision: FP64 = float64 Jacobi-PCG; FP32_REFINE = float32
+ * PCG with float64 residual correction.  iters_dev (n int32, may be NULL)
+ * receives the iteration count of each solve (-1 = not converged).
+ * Errors: EINVAL (ld < col0 + n), ENOCONV, EHIP. */
+usfft_status usfft_sample(usfft_plan_t plan, const double* y_dev, int64_t n,
+                          void* u_dev, int32_t out_fp32, int64_t ld, int64_t col0,
+                          int32_t* iters_dev, void* stream);
+
+/* Sampling nodes of one stage (Alg. 1 step 1&2a: l/K in coordinate `line`,
+ * tail elsewhere; step 2b / step 3: rank-1 lattice nodes (m z mod M)/M in the
+ * first t coordinates (App. A), tail in the others).  line >= 0 selects the
+ * 1-D form with K = M_host[0]; otherwise nlat lattices with sizes M_host and
+ * generators z_host (nlat x t).  Writes y_dev (sum M x d doubles). */
+usfft_status usfft_nodes(int32_t d, int32_t line, int32_t t, int32_t nlat,
+                         const int32_t* M_host, const int32_t* z_host,
+                         const double* tail_host, double* y_dev, void* stream);
+
+/* Length-K DFT of Alg. 1 step 1&2a for every node: for candidate a with
+ * bin b_a = bins_host[a] mod K,
+ *   F = (1/K) sum_l u[g*ld + col0 + l] exp(-2 pi i l b_a / K),
+ * read through the canonical bin min(b, K-b) (conjugated above K/2).
+ * out: USFFT_OUT_MAG2 -> |F|^2 doubles at out_dev[g*ldo + a];
+ *      USFFT_OUT_COMPLEX -> (re, im) doubles at out_dev[(a*G + g)*2]. */
+usfft_status usfft_line_dft(const void* u_dev, int32_t u_fp32, int64_t G, int64_t ld,
+                            int64_t col0, int32_t K, const int32_t* bins_host, int32_t nb,
+                            int32_t out_kind, void* out_dev, int64_t ldo, void* stream);
+
+/* Lattice DFT of Algorithm A (App. A): the length-M DFT of every node's
+ * samples along a rank-1 lattice of prime size M (M-1 7-smooth, M <= 9601)
+ * evaluated at the requested bins (same normalisation, canonical-bin rule
+ * and output layouts as usfft_line_dft; candidate a written at column
+ * pos_dev[a] of the output).  bins_dev, pos_dev: nb int32 device arrays.
+ * Errors: EINVAL (M not admissible). */
+usfft_status usfft_lattice_dft(const void* u_dev, int32_t u_fp32, int64_t G, int64_t ld,
+                               int64_t col0, int32_t M, const int32_t* bins_dev,
+                               const int32_t* pos_dev, int32_t nb, int32_t out_kind,
+                               void* out_dev, int64_t ldo, void* stream);
+
+/* Per-node selection and uniform union (Alg. 1 step 1&2a and 2d/2e): for
+ * every node g, tau_g^2 = s_tilde-th largest of v_dev[g*ld + a], a < n
+ * (0 when n < s_tilde); keep a when v >= max(theta2, (1 - tie_rel) tau_g^2);
+ * mask_dev (ceil(n/32) words, bit a) |= OR over g of keep.  theta2 is read
+ * from the device scalar theta2_dev.  thr_dev (G doubles, may be NULL)
+ * receives the per-node threshold. */
+usfft_status usfft_select(const double* v_dev, int64_t G, int64_t n, int64_t ld,
+                          int32_t s_tilde, const double* theta2_dev, double tie_rel,
+                          uint32_t* mask_dev, double* thr_dev, void* stream);
+
+/* Join (Alg. 1 step 2): Cartesian product J = parent x child in parent-major
+ * order (lexicographic when both inputs are): out_dev (np*nc) x (t+1). */
+usfft_status usfft_product(const int32_t* parent_dev, int64_t np, int32_t t,
+                           const int32_t* child_dev, int64_t nc, int32_t* out_dev,
+                           void* stream);
+
+/* Compaction of a detected set (Alg. 1 step 2e): rows of J_dev (n x t) whose
+ * mask bit is set, order kept.  *count_host receives the number of rows. */
+usfft_status usfft_compact(const int32_t* J_dev, const uint32_t* mask_dev, int64_t n,
+                           int32_t t, int32_t* out_dev, int64_t* count_host, void* stream);
+
+/* Algorithm A's sampling set for a candidate set (App. A; multiple rank-1
+ * lattices, Remark 4.2): greedy family on J_dev (n x t), reading of this
+ * build: sizes = admissible primes from min(max(3, ceil(c n)), mmax/2) up to
+ * mmax (cycled), `tries` SplitMix64 generators per attempt (stream kind
+ * `kind`, t-code `tcode`), keep the one freeing most uncovered candidates
+ * (lowest try on ties), drop lattices that free none.  Outputs: *nlat_host,
+ * M_host (cap entries), z_host (cap x t), assign_dev / bins_dev (n int32:
+ * lattice index and bin k.z mod M of each candidate).  Errors: ELATTICE,
+ * EINVAL (cap too small). */
+usfft_status usfft_family(const int32_t* J_dev, int64_t n, int32_t t, double c, int32_t mmax,
+                          int32_t tries, int32_t lmax, uint64_t seed, int32_t kind,
+                          int32_t tcode, int32_t cap, int32_t* nlat_host, int32_t* M_host,
+                          int32_t* z_host, int32_t* assign_dev, int32_t* bins_dev,
+                          void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* USFFT_H */

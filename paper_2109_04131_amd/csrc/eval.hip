@@ -1,0 +1,49 @@
+// Evaluation of the approximant (Sec. 3.1, eq. (3.1) for the periodic model):
+// out[j, g] = Re sum_{k in I} c_k(u_{x_g}) exp(2 pi i k . y_j).
+// One workgroup per evaluation point; the phases of a chunk of frequencies
+// are staged in LDS, coefficients are read k-major so a wave reads 64
+// consecutive nodes.  Not on the timed path.
+#include "kernels.h"
+
+namespace usfft {
+
+constexpr int kEvalChunk = 1024;
+
+__global__ __launch_bounds__(256) void eval_kernel(const int32_t* __restrict__ I, int64_t nI, int d,
+                                                   const double* __restrict__ C, int64_t G,
+                                                   const double* __restrict__ Y, double* __restrict__ out) {
+  __shared__ double cs[kEvalChunk];
+  __shared__ double sn[kEvalChunk];
+  const int64_t j = blockIdx.x;
+  const double* y = Y + j * d;
+  for (int64_t g0 = 0; g0 < G; g0 += 256) {
+    const int64_t g = g0 + threadIdx.x;
+    double acc = 0.0;
+    for (int64_t a0 = 0; a0 < nI; a0 += kEvalChunk) {
+      const int na = (int)min<int64_t>(kEvalChunk, nI - a0);
+      __syncthreads();
+      for (int a = threadIdx.x; a < na; a += 256) {
+        double ph = 0.0;
+        for (int q = 0; q < d; ++q) ph += (double)I[(a0 + a) * d + q] * y[q];
+        ph -= floor(ph);
+        sincospi(2.0 * ph, &sn[a], &cs[a]);
+      }
+      __syncthreads();
+      if (g < G)
+        for (int a = 0; a < na; ++a) {
+          const double* c = C + ((a0 + a) * G + g) * 2;
+          acc += c[0] * cs[a] - c[1] * sn[a];
+        }
+    }
+    if (g < G) out[j * G + g] = acc;
+  }
+}
+
+void launch_eval(const int32_t* I, int64_t nI, int d, const double* C, int64_t G, const double* Y, int64_t n,
+                 double* out, hipStream_t st) {
+  if (n <= 0 || G <= 0) return;
+  hipLaunchKernelGGL(eval_kernel, dim3((unsigned)n), dim3(256), 0, st, I, nI, d, C, G, Y, out);
+  USFFT_HIP(hipGetLastError());
+}
+
+}  // namespace usfft

@@ -1,0 +1,467 @@
+// Lattice DFTs of the usFFT on gfx950 (Alg. 1 step 1&2a and Algorithm A, App. A).
+//
+// Lattice DFT.  Sampling along a rank-1 lattice of prime size M turns the
+// coefficient of candidate k into bin k.z mod M of a length-M DFT.  Every
+// node needs that DFT, at the bins of the candidates assigned to the
+// lattice.  For prime M, Rader's algorithm (C. M. Rader, Proc. IEEE 1968)
+// writes X[g^-p] - x[0] as the cyclic convolution of a_q = x[g^q] with
+// b_j = exp(-2 pi i g^-j / M), q, j < L = M-1, g a generator mod M.  Lattice
+// sizes are restricted to primes with 7-smooth L, so the convolution is two
+// mixed-radix FFTs of length L plus one pointwise product with the
+// precomputed spectrum of b.  One workgroup handles two nodes (two real
+// columns packed as one complex column), keeps the whole length-L transform in
+// LDS (L <= 9600 complex doubles = 150 KB), reads its two sample rows once,
+// coalesced, and writes only the requested bins: HBM traffic is the
+// algorithmic minimum, M reads and n_bins writes per node.
+//
+// FFT in LDS: Stockham autosort radix passes (the formulation of Govindaraju
+// et al., SC 2008), one buffer: each pass reads its butterfly inputs into
+// registers, barrier, writes the outputs, barrier.
+//
+// Line DFT: the length-K_t DFT of the 1-D detection, evaluated directly.
+#include "kernels.h"
+
+#include <cmath>
+#include <vector>
+
+namespace usfft {
+
+constexpr int kLMax = kMaxLattice - 1;  // 9600
+constexpr int kFftBlock = 512;
+
+// correctly rounded cos / sin of 2 pi m / R
+template <int R>
+struct RootTab;
+template <>
+struct RootTab<3> {
+  static constexpr double c[3] = {1.0, -0.5, -0.5};
+  static constexpr double s[3] = {0.0, 0.8660254037844386, -0.8660254037844386};
+};
+template <>
+struct RootTab<5> {
+  static constexpr double c[5] = {1.0, 0.30901699437494745, -0.8090169943749475, -0.8090169943749475,
+                                  0.30901699437494745};
+  static constexpr double s[5] = {0.0, 0.9510565162951535, 0.5877852522924731, -0.5877852522924731,
+                                  -0.9510565162951535};
+};
+template <>
+struct RootTab<7> {
+  static constexpr double c[7] = {1.0, 0.6234898018587335, -0.2225209339563144, -0.9009688679024191,
+                                  -0.9009688679024191, -0.2225209339563144, 0.6234898018587335};
+  static constexpr double s[7] = {0.0, 0.7818314824680298, 0.9749279121818236, 0.4338837391175581,
+                                  -0.4338837391175581, -0.9749279121818236, -0.7818314824680298};
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> mul_mi(cplx<T> a) { return {a.y, -a.x}; }  // * (-i)
+template <typename T>
+__device__ __forceinline__ cplx<T> conjc(cplx<T> a) { return {a.x, -a.y}; }
+
+template <typename T>
+__device__ __forceinline__ void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx<T>& a3) {
+  const cplx<T> s02 = cadd(a0, a2), d02 = csub(a0, a2), s13 = cadd(a1, a3), d13 = mul_mi(csub(a1, a3));
+  a0 = cadd(s02, s13);
+  a2 = csub(s02, s13);
+  a1 = cadd(d02, d13);
+  a3 = csub(d02, d13);
+}
+
+// forward DFT of length R on v[0..R), in place
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cplx<T>* v) {
+  if constexpr (R == 2) {
+    const cplx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    dft4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 8) {
+    constexpr T h = (T)0.7071067811865476;
+    cplx<T> b[4], c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      b[j] = cadd(v[j], v[j + 4]);
+      c[j] = csub(v[j], v[j + 4]);
+    }
+    c[1] = {h * (c[1].x + c[1].y), h * (c[1].y - c[1].x)};   // * exp(-i pi/4)
+    c[2] = mul_mi(c[2]);                                       // * exp(-i pi/2)
+    c[3] = {h * (c[3].y - c[3].x), -h * (c[3].x + c[3].y)};  // * exp(-3 i pi/4)
+    dft4(b[0], b[1], b[2], b[3]);
+    dft4(c[0], c[1], c[2], c[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[2 * k] = b[k];
+      v[2 * k + 1] = c[k];
+    }
+  } else {
+    cplx<T> o[R];
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+      cplx<T> acc = v[0];
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        const int m = (p * q) % R;
+        const T c = (T)RootTab<R>::c[m], s = (T)RootTab<R>::s[m];
+        acc.x += v[q].x * c + v[q].y * s;
+        acc.y += v[q].y * c - v[q].x * s;
+      }
+      o[p] = acc;
+    }
+#pragma unroll
+    for (int p = 0; p < R; ++p) v[p] = o[p];
+  }
+}
+
+// One Stockham pass of radix R over buf[0..L).  Input element q of butterfly
+// j is buf[j + q L/R] (or buf[perm[.] - 1] for the Rader input permutation);
+// output p goes to (j / Ns) Ns R + j % Ns + p Ns.  With `mulB` the outputs are
+// multiplied by B and conjugated (the forward half of the convolution, set up
+// for the inverse transform by conjugation).
+template <typename T, int R>
+__device__ void fft_pass(cplx<T>* buf, int L, int Ns, const cplx<T>* __restrict__ tw,
+                         const int32_t* __restrict__ perm, const cplx<T>* __restrict__ mulB) {
+  constexpr int MAXB = (kLMax / R + kFftBlock - 1) / kFftBlock;
+  const int nb = L / R;
+  const int stride = L / (Ns * R);
+  cplx<T> v[MAXB][R];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = threadIdx.x + b * kFftBlock;
+    if (j < nb) {
+      const int k = j % Ns;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int idx = j + q * nb;
+        cplx<T> a = perm ? buf[perm[idx] - 1] : buf[idx];
+        if (q > 0 && k > 0) a = cmul(a, tw[q * k * stride]);
+        v[b][q] = a;
+      }
+      dft_small<T, R>(v[b]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    const int j = threadIdx.x + b * kFftBlock;
+    if (j < nb) {
+      const int k = j % Ns;
+      const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int p = 0; p < R; ++p) {
+        const int idx = base + p * Ns;
+        cplx<T> o = v[b][p];
+        if (mulB) o = conjc(cmul(o, mulB[idx]));
+        buf[idx] = o;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+struct FftPlanDev {
+  int L, nrad;
+  int radix[24];
+};
+
+template <typename T>
+__device__ void fft_run(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, const int32_t* perm,
+                        const cplx<T>* mulB) {
+  int Ns = 1;
+  for (int s = 0; s < F.nrad; ++s) {
+    const int R = F.radix[s];
+    const int32_t* pm = (s == 0) ? perm : nullptr;
+    const cplx<T>* mb = (s == F.nrad - 1) ? mulB : nullptr;
+    switch (R) {
+      case 2: fft_pass<T, 2>(buf, F.L, Ns, tw, pm, mb); break;
+      case 3: fft_pass<T, 3>(buf, F.L, Ns, tw, pm, mb); break;
+      case 4: fft_pass<T, 4>(buf, F.L, Ns, tw, pm, mb); break;
+      case 5: fft_pass<T, 5>(buf, F.L, Ns, tw, pm, mb); break;
+      case 7: fft_pass<T, 7>(buf, F.L, Ns, tw, pm, mb); break;
+      default: fft_pass<T, 8>(buf, F.L, Ns, tw, pm, mb); break;
+    }
+    Ns *= R;
+  }
+}
+
+// ---------------------------------------------------------------- setup
+// B = DFT_L(b) / L for b_j = exp(-2 pi i gen^-j / M), gen^-j = perm[(L - j) % L].
+__global__ __launch_bounds__(kFftBlock) void rader_setup_kernel(FftPlanDev F, int M, const int32_t* __restrict__ perm,
+                                                               const cplx<double>* __restrict__ tw,
+                                                               cplx<double>* __restrict__ B64,
+                                                               cplx<float>* __restrict__ B32,
+                                                               cplx<float>* __restrict__ tw32) {
+  extern __shared__ char smem[];
+  cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem);
+  const int L = F.L;
+  for (int j = threadIdx.x; j < L; j += kFftBlock) {
+    const int e = perm[(L - j) % L];
+    double s, c;
+    sincospi(-2.0 * (double)e / (double)M, &s, &c);
+    buf[j] = {c, s};
+  }
+  __syncthreads();
+  fft_run<double>(buf, F, tw, nullptr, nullptr);
+  const double invL = 1.0 / (double)L;
+  for (int k = threadIdx.x; k < L; k += kFftBlock) {
+    const cplx<double> v = {buf[k].x * invL, buf[k].y * invL};
+    B64[k] = v;
+    B32[k] = {(float)v.x, (float)v.y};
+    tw32[k] = {(float)tw[k].x, (float)tw[k].y};
+  }
+}
+
+bool lattice_size_ok(int M) {
+  if (M < 3 || M > kMaxLattice) return false;
+  for (int f = 2; (int64_t)f * f <= M; ++f)
+    if (M % f == 0) return false;
+  int r = M - 1;
+  for (int p : {2, 3, 5, 7})
+    while (r % p == 0) r /= p;
+  return r == 1;
+}
+
+static int64_t powmod(int64_t a, int64_t e, int64_t m) {
+  int64_t r = 1 % m;
+  a %= m;
+  while (e > 0) {
+    if (e & 1) r = r * a % m;
+    a = a * a % m;
+    e >>= 1;
+  }
+  return r;
+}
+
+void rader_free(RaderTables& T) {
+  for (void* p : {(void*)T.perm, (void*)T.outidx, T.tw64, T.tw32, T.B64, T.B32})
+    if (p) (void)hipFree(p);
+  T = RaderTables{};
+}
+
+void rader_build(RaderTables& T, int M, hipStream_t st) {
+  USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL,
+                "lattice size " + std::to_string(M) + " is not a prime <= 9601 with 7-smooth M-1");
+  T.M = M;
+  T.L = M - 1;
+  const int L = T.L;
+  // generator: g^(L/p) != 1 for every prime p | L
+  int gen = 2;
+  for (;; ++gen) {
+    bool ok = true;
+    for (int p : {2, 3, 5, 7})
+      if (L % p == 0 && powmod(gen, L / p, M) == 1) ok = false;
+    if (ok) break;
+  }
+  T.gen = gen;
+  // radix plan: 8s, then 4 / 2, then 3s, 5s, 7s
+  int r = L, c2 = 0;
+  while (r % 2 == 0) {
+    r /= 2;
+    ++c2;
+  }
+  T.nrad = 0;
+  while (c2 >= 3) {
+    T.radix[T.nrad++] = 8;
+    c2 -= 3;
+  }
+  if (c2 == 2) T.radix[T.nrad++] = 4;
+  if (c2 == 1) T.radix[T.nrad++] = 2;
+  for (int p : {3, 5, 7})
+    while (r % p == 0) {
+      T.radix[T.nrad++] = p;
+      r /= p;
+    }
+  std::vector<int32_t> perm(L), dlog(M, -1), outidx(M, 0);
+  int64_t v = 1;
+  for (int q = 0; q < L; ++q) {
+    perm[q] = (int32_t)v;
+    dlog[v] = q;
+    v = v * gen % M;
+  }
+  for (int b = 1; b < M; ++b) outidx[b] = (L - dlog[b]) % L;
+  std::vector<cplx<double>> tw(L);
+  for (int k = 0; k < L; ++k) {
+    const double a = -2.0 * M_PI * (double)k / (double)L;
+    tw[k] = {std::cos(a), std::sin(a)};
+  }
+  USFFT_HIP(hipMalloc(&T.perm, sizeof(int32_t) * L));
+  USFFT_HIP(hipMalloc(&T.outidx, sizeof(int32_t) * M));
+  USFFT_HIP(hipMalloc(&T.tw64, sizeof(cplx<double>) * L));
+  USFFT_HIP(hipMalloc(&T.tw32, sizeof(cplx<float>) * L));
+  USFFT_HIP(hipMalloc(&T.B64, sizeof(cplx<double>) * L));
+  USFFT_HIP(hipMalloc(&T.B32, sizeof(cplx<float>) * L));
+  USFFT_HIP(hipMemcpyAsync(T.perm, perm.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, st));
+  USFFT_HIP(hipMemcpyAsync(T.outidx, outidx.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
+  USFFT_HIP(hipMemcpyAsync(T.tw64, tw.data(), sizeof(cplx<double>) * L, hipMemcpyHostToDevice, st));
+  FftPlanDev F;
+  F.L = L;
+  F.nrad = T.nrad;
+  for (int i = 0; i < 24; ++i) F.radix[i] = T.radix[i];
+  hipLaunchKernelGGL(rader_setup_kernel, dim3(1), dim3(kFftBlock), sizeof(cplx<double>) * L, st, F, M, T.perm,
+                     (const cplx<double>*)T.tw64, (cplx<double>*)T.B64, (cplx<float>*)T.B32,
+                     (cplx<float>*)T.tw32);
+  USFFT_HIP(hipGetLastError());
+  USFFT_HIP(hipStreamSynchronize(st));  // host vectors above go out of scope
+}
+
+// ---------------------------------------------------------------- lattice DFT
+template <typename T>
+__global__ __launch_bounds__(kFftBlock) void rader_kernel(FftPlanDev F, int M, const int32_t* __restrict__ perm,
+                                                          const int32_t* __restrict__ outidx,
+                                                          const cplx<T>* __restrict__ tw,
+                                                          const cplx<T>* __restrict__ B, const T* __restrict__ u,
+                                                          int64_t G, int64_t ld, int64_t col0,
+                                                          const int32_t* __restrict__ bins,
+                                                          const int32_t* __restrict__ pos, int nb, int out_kind,
+                                                          void* __restrict__ out, int64_t ldo) {
+  extern __shared__ char smem[];
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  __shared__ double red[2 * (kFftBlock / kWave)];
+  const int64_t pair = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t g1 = 2 * pair, g2 = g1 + 1;
+  const bool has2 = g2 < G;
+  const T* u1 = u + g1 * ld + col0;
+  const T* u2 = u + (has2 ? g2 : g1) * ld + col0;
+  const int L = F.L;
+  // coalesced load of x[1..M-1] into buf[0..L), partial sums for X[0]
+  double s1 = 0.0, s2 = 0.0;
+  for (int m = 1 + threadIdx.x; m < M; m += kFftBlock) {
+    const T a = u1[m];
+    const T b = has2 ? u2[m] : (T)0;
+    buf[m - 1] = {a, b};
+    s1 += (double)a;
+    s2 += (double)b;
+  }
+  const T x01 = u1[0];
+  const T x02 = has2 ? u2[0] : (T)0;
+  block_sum2<kFftBlock>(s1, s2, red);  // also orders the LDS writes before the first pass
+  s1 += (double)x01;
+  s2 += (double)x02;
+  // c = a (*) b: forward FFT (input permuted by perm), times B, conjugate,
+  // forward FFT again; buf then holds conj(c).
+  fft_run<T>(buf, F, tw, perm, B);
+  fft_run<T>(buf, F, tw, nullptr, nullptr);
+  const double invM = 1.0 / (double)M;
+  for (int a = threadIdx.x; a < nb; a += kFftBlock) {
+    const int b = bins[a];
+    const int bc = min(b, M - b);
+    const bool flip = b > M - b;
+    double X1r, X1i, X2r, X2i;
+    if (bc == 0) {
+      X1r = s1 * invM;
+      X1i = 0.0;
+      X2r = s2 * invM;
+      X2i = 0.0;
+    } else {
+      const cplx<T> cp = buf[outidx[bc]];
+      const cplx<T> cm = buf[outidx[M - bc]];
+      // X[bc] = x0 + c, X[M-bc] = x0 + c', with c = conj(buf)
+      const double Xpr = (double)x01 + (double)cp.x, Xpi = (double)x02 - (double)cp.y;
+      const double Xmr = (double)x01 + (double)cm.x, Xmi = (double)x02 - (double)cm.y;
+      X1r = 0.5 * (Xpr + Xmr) * invM;
+      X1i = 0.5 * (Xpi - Xmi) * invM;
+      X2r = 0.5 * (Xpi + Xmi) * invM;
+      X2i = -0.5 * (Xpr - Xmr) * invM;
+    }
+    if (flip) {
+      X1i = -X1i;
+      X2i = -X2i;
+    }
+    const int64_t c = pos[a];
+    if (out_kind == USFFT_OUT_MAG2) {
+      double* o = static_cast<double*>(out);
+      o[g1 * ldo + c] = X1r * X1r + X1i * X1i;
+      if (has2) o[g2 * ldo + c] = X2r * X2r + X2i * X2i;
+    } else {
+      double* o = static_cast<double*>(out);
+      o[(c * G + g1) * 2] = X1r;
+      o[(c * G + g1) * 2 + 1] = X1i;
+      if (has2) {
+        o[(c * G + g2) * 2] = X2r;
+        o[(c * G + g2) * 2 + 1] = X2i;
+      }
+    }
+  }
+}
+
+void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0,
+                        const int32_t* bins, const int32_t* pos, int nb, int out_kind, void* out, int64_t ldo,
+                        hipStream_t st) {
+  if (G <= 0 || nb <= 0) return;
+  FftPlanDev F;
+  F.L = T.L;
+  F.nrad = T.nrad;
+  for (int i = 0; i < 24; ++i) F.radix[i] = T.radix[i];
+  const unsigned grid = (unsigned)ceil_div(G, 2);
+  if (u_fp32) {
+    hipLaunchKernelGGL(rader_kernel<float>, dim3(grid), dim3(kFftBlock), sizeof(cplx<float>) * T.L, st, F, T.M,
+                       T.perm, T.outidx, (const cplx<float>*)T.tw32, (const cplx<float>*)T.B32,
+                       (const float*)u, G, ld, col0, bins, pos, nb, out_kind, out, ldo);
+  } else {
+    hipLaunchKernelGGL(rader_kernel<double>, dim3(grid), dim3(kFftBlock), sizeof(cplx<double>) * T.L, st, F,
+                       T.M, T.perm, T.outidx, (const cplx<double>*)T.tw64, (const cplx<double>*)T.B64,
+                       (const double*)u, G, ld, col0, bins, pos, nb, out_kind, out, ldo);
+  }
+  USFFT_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- line DFT
+constexpr int kLineMax = 1024;
+template <typename T>
+__global__ __launch_bounds__(256) void line_dft_kernel(const T* __restrict__ u, int64_t G, int64_t ld, int64_t col0,
+                                                       int K, const int32_t* __restrict__ bins, int nb,
+                                                       int out_kind, void* __restrict__ out, int64_t ldo) {
+  __shared__ double x[kLineMax];
+  __shared__ double cs[kLineMax];
+  __shared__ double sn[kLineMax];
+  const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+  for (int l = threadIdx.x; l < K; l += 256) {
+    x[l] = (double)u[g * ld + col0 + l];
+    double s, c;
+    sincospi(2.0 * (double)l / (double)K, &s, &c);
+    cs[l] = c;
+    sn[l] = s;
+  }
+  __syncthreads();
+  const double invK = 1.0 / (double)K;
+  for (int a = threadIdx.x; a < nb; a += 256) {
+    const int b = ((bins[a] % K) + K) % K;
+    const int bc = min(b, K - b) % K;
+    double re = 0.0, im = 0.0;
+    int ph = 0;
+    for (int l = 0; l < K; ++l) {
+      re += x[l] * cs[ph];
+      im -= x[l] * sn[ph];
+      ph += bc;
+      if (ph >= K) ph -= K;
+    }
+    re *= invK;
+    im *= invK;
+    if (b > K - b) im = -im;
+    double* o = static_cast<double*>(out);
+    if (out_kind == USFFT_OUT_MAG2) {
+      o[g * ldo + a] = re * re + im * im;
+    } else {
+      o[((int64_t)a * G + g) * 2] = re;
+      o[((int64_t)a * G + g) * 2 + 1] = im;
+    }
+  }
+}
+
+void launch_line_dft(const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0, int K, const int32_t* bins,
+                     int nb, int out_kind, void* out, int64_t ldo, hipStream_t st) {
+  USFFT_REQUIRE(K >= 1 && K <= kLineMax, USFFT_EINVAL, "line DFT length out of range");
+  if (G <= 0 || nb <= 0) return;
+  if (u_fp32)
+    hipLaunchKernelGGL(line_dft_kernel<float>, dim3((unsigned)G), dim3(256), 0, st, (const float*)u, G, ld, col0,
+                       K, bins, nb, out_kind, out, ldo);
+  else
+    hipLaunchKernelGGL(line_dft_kernel<double>, dim3((unsigned)G), dim3(256), 0, st, (const double*)u, G, ld,
+                       col0, K, bins, nb, out_kind, out, ldo);
+  USFFT_HIP(hipGetLastError());
+}
+
+}  // namespace usfft

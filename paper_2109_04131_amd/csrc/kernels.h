@@ -1,0 +1,77 @@
+// Internal launch interface between the host driver and the HIP kernels.
+#pragma once
+#include "common.h"
+
+namespace usfft {
+
+constexpr int kMaxD = 64;          // largest parameter dimension d
+constexpr int kMaxMesh = 64;       // largest mesh_n of the on-chip solver
+constexpr int kMaxLattice = 9601;  // largest lattice size (L = M-1 complex values in LDS)
+
+// PDE sampler tables on the device (see sampler.hip).
+struct PdeDev {
+  int n, d;
+  double a0, h2;
+  const double* amp;  // d
+  const double* tab;  // 4 x d x n centroid sine tables
+};
+
+// ---- sampler.hip
+void launch_nodes(int d, int line, int t, int nlat, const int64_t* off, const int32_t* Ms, const int32_t* zs,
+                  const double* tail, double* Y, int64_t ns, hipStream_t st);
+int solver_config_count();
+bool solver_config_fits(int c, int G);
+void solver_config_shape(int c, int* block, int* npt);
+int solver_default_config(int G);
+void launch_pde_solve(int cfg, const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol,
+                      int maxit, double inner_rtol, int max_refine, void* out, int out_fp32, int64_t ld,
+                      int64_t col0, int* iters, hipStream_t st);
+void launch_trigpoly(int d, const double* Y, int64_t ns, const int32_t* K, int64_t np, const double* C,
+                     int64_t G, void* out, int out_fp32, int64_t ld, int64_t col0, hipStream_t st);
+
+// ---- fft.hip
+// Per-size tables of Rader's algorithm for a prime M with smooth L = M-1.
+struct RaderTables {
+  int M = 0, L = 0, gen = 0;
+  int nrad = 0;
+  int radix[24] = {0};
+  int32_t* perm = nullptr;    // L: gen^q mod M
+  int32_t* outidx = nullptr;  // M: index p with b = gen^(-p) mod M (entry 0 unused)
+  void* tw64 = nullptr;       // L complex double: exp(-2 pi i k / L)
+  void* tw32 = nullptr;       // L complex float
+  void* B64 = nullptr;        // L complex double: DFT_L(b) / L, b_j = exp(-2 pi i gen^(-j) / M)
+  void* B32 = nullptr;        // L complex float
+};
+bool lattice_size_ok(int M);
+void rader_build(RaderTables& T, int M, hipStream_t st);  // allocates + fills (synchronous)
+void rader_free(RaderTables& T);
+void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0,
+                        const int32_t* bins, const int32_t* pos, int nb, int out_kind, void* out, int64_t ldo,
+                        hipStream_t st);
+void launch_line_dft(const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0, int K, const int32_t* bins,
+                     int nb, int out_kind, void* out, int64_t ldo, hipStream_t st);
+
+// ---- select.hip
+void launch_select(const double* v, int64_t G, int64_t n, int64_t ld, int s_tilde, const double* theta2,
+                   double tie_rel, uint32_t* mask, double* thr, hipStream_t st);
+void launch_max_to_theta(const double* v, int64_t G, int64_t n, int64_t ld, double theta, double* theta2,
+                         uint64_t* scratch, hipStream_t st);
+
+// ---- sets.hip
+void launch_product(const int32_t* parent, int64_t np, int t, const int32_t* child, int64_t nc, int32_t* out,
+                    hipStream_t st);
+// Compaction; *count_dev receives the row count.
+void launch_compact(const int32_t* J, const uint32_t* mask, int64_t n, int t, int32_t* out, int64_t* count_dev,
+                    hipStream_t st);
+void launch_lattice_bins(const int32_t* J, int64_t n, int t, const int32_t* z, int T, int M, int32_t* bins,
+                         int32_t* counts, hipStream_t st);
+void launch_lattice_score(const int32_t* bins, const int32_t* counts, const uint8_t* covered, int64_t n, int T,
+                          int M, int32_t* scores, hipStream_t st);
+void launch_lattice_take(const int32_t* bins, const int32_t* counts, uint8_t* covered, int64_t n, int M, int lat,
+                         int32_t* assign, int32_t* bin_out, hipStream_t st);
+
+// ---- eval.hip
+void launch_eval(const int32_t* I, int64_t nI, int d, const double* C, int64_t G, const double* Y, int64_t n,
+                 double* out, hipStream_t st);
+
+}  // namespace usfft

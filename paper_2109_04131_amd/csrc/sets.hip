@@ -1,0 +1,142 @@
+// Integer set work of the usFFT (Alg. 1 step 2): candidate product, detected
+// set compaction and the alias tests of the lattice-family planner.  All of it
+// is exact integer arithmetic, so results are bit-identical to any correct
+// implementation.
+#include "kernels.h"
+
+namespace usfft {
+
+// J = parent x child, parent-major: row p*nc + c = (parent[p], child[c]).
+__global__ void product_kernel(const int32_t* __restrict__ parent, int64_t np, int t,
+                               const int32_t* __restrict__ child, int64_t nc, int32_t* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = t + 1;
+  if (e >= np * nc * w) return;
+  const int64_t row = e / w;
+  const int j = (int)(e % w);
+  const int64_t p = row / nc, c = row % nc;
+  out[e] = (j < t) ? parent[p * t + j] : child[c];
+}
+
+void launch_product(const int32_t* parent, int64_t np, int t, const int32_t* child, int64_t nc, int32_t* out,
+                    hipStream_t st) {
+  const int64_t tot = np * nc * (t + 1);
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(product_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, parent, np, t, child, nc,
+                     out);
+  USFFT_HIP(hipGetLastError());
+}
+
+// Order-keeping compaction with one workgroup: chunks of 1024 candidates,
+// ballot + popcount prefix within waves, wave offsets through LDS.
+constexpr int kCompactBlock = 1024;
+__global__ __launch_bounds__(kCompactBlock) void compact_kernel(const int32_t* __restrict__ J,
+                                                                const uint32_t* __restrict__ mask, int64_t n, int t,
+                                                                int32_t* __restrict__ out,
+                                                                int64_t* __restrict__ count) {
+  __shared__ int wave_cnt[kCompactBlock / kWave];
+  __shared__ int64_t base_s;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (threadIdx.x == 0) base_s = 0;
+  __syncthreads();
+  for (int64_t a0 = 0; a0 < n; a0 += kCompactBlock) {
+    const int64_t a = a0 + threadIdx.x;
+    const bool keep = a < n && ((mask[a >> 5] >> (a & 31)) & 1u);
+    const uint64_t bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_cnt[w] = __popcll(bal);
+    __syncthreads();
+    int64_t off = base_s;
+    for (int i = 0; i < w; ++i) off += wave_cnt[i];
+    if (keep) {
+      const int64_t dst = off + before;
+      for (int j = 0; j < t; ++j) out[dst * t + j] = J[a * t + j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t tot = 0;
+      for (int i = 0; i < kCompactBlock / kWave; ++i) tot += wave_cnt[i];
+      base_s += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = base_s;
+}
+
+void launch_compact(const int32_t* J, const uint32_t* mask, int64_t n, int t, int32_t* out, int64_t* count_dev,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(kCompactBlock), 0, st, J, mask, n, t, out, count_dev);
+  USFFT_HIP(hipGetLastError());
+}
+
+// bins[tr][a] = (k_a . z_tr) mod M for T candidate generators; counts[tr][b]
+// counts the candidates per bin (counts must be zero on entry).
+__global__ void lattice_bins_kernel(const int32_t* __restrict__ J, int64_t n, int t, const int32_t* __restrict__ z,
+                                    int T, int M, int32_t* __restrict__ bins, int32_t* __restrict__ counts) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * T) return;
+  const int tr = (int)(e / n);
+  const int64_t a = e % n;
+  int64_t acc = 0;
+  for (int j = 0; j < t; ++j) acc += (int64_t)J[a * t + j] * (int64_t)z[tr * t + j];
+  int64_t b = acc % M;
+  if (b < 0) b += M;
+  bins[e] = (int32_t)b;
+  atomicAdd(&counts[(int64_t)tr * M + b], 1);
+}
+
+void launch_lattice_bins(const int32_t* J, int64_t n, int t, const int32_t* z, int T, int M, int32_t* bins,
+                         int32_t* counts, hipStream_t st) {
+  const int64_t tot = n * T;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(lattice_bins_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, J, n, t, z, T, M,
+                     bins, counts);
+  USFFT_HIP(hipGetLastError());
+}
+
+// scores[tr] = #{a uncovered : counts[tr][bins[tr][a]] == 1}
+__global__ void lattice_score_kernel(const int32_t* __restrict__ bins, const int32_t* __restrict__ counts,
+                                     const uint8_t* __restrict__ covered, int64_t n, int T, int M,
+                                     int32_t* __restrict__ scores) {
+  const int tr = blockIdx.y;
+  int c = 0;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = bins[(int64_t)tr * n + a];
+    c += (!covered[a] && counts[(int64_t)tr * M + b] == 1) ? 1 : 0;
+  }
+  c = wave_sum(c);
+  if ((threadIdx.x & (kWave - 1)) == 0 && c) atomicAdd(&scores[tr], c);
+}
+
+void launch_lattice_score(const int32_t* bins, const int32_t* counts, const uint8_t* covered, int64_t n, int T,
+                          int M, int32_t* scores, hipStream_t st) {
+  if (n <= 0) return;
+  const unsigned gx = (unsigned)std::min<int64_t>(256, ceil_div(n, 256));
+  hipLaunchKernelGGL(lattice_score_kernel, dim3(gx, T), dim3(256), 0, st, bins, counts, covered, n, T, M, scores);
+  USFFT_HIP(hipGetLastError());
+}
+
+// Commit the chosen generator (bins/counts already offset to it).
+__global__ void lattice_take_kernel(const int32_t* __restrict__ bins, const int32_t* __restrict__ counts,
+                                    uint8_t* __restrict__ covered, int64_t n, int lat, int32_t* __restrict__ assign,
+                                    int32_t* __restrict__ bin_out) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const int32_t b = bins[a];
+  if (!covered[a] && counts[b] == 1) {
+    covered[a] = 1;
+    assign[a] = lat;
+    bin_out[a] = b;
+  }
+}
+
+void launch_lattice_take(const int32_t* bins, const int32_t* counts, uint8_t* covered, int64_t n, int M, int lat,
+                         int32_t* assign, int32_t* bin_out, hipStream_t st) {
+  (void)M;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(lattice_take_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, bins, counts, covered,
+                     n, lat, assign, bin_out);
+  USFFT_HIP(hipGetLastError());
+}
+
+}  // namespace usfft

@@ -1,0 +1,900 @@
+// Host driver of the usFFT hot path and the C ABI (include/usfft.h).
+//
+// Alg. 1 is run stage by stage on one HIP stream: every step (sampling nodes,
+// PDE solves, DFTs, selection, union, join, lattice alias tests) is a kernel;
+// the host only draws the SplitMix64 numbers of the stage, keeps the
+// lattice-family greedy loop (it needs the per-try scores back) and sizes
+// buffers from the set sizes it reads back once per dimension increment.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+
+namespace usfft {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------- SplitMix64
+// Steele, Lea, Flood (OOPSLA 2014): state += 0x9E3779B97F4A7C15, output the
+// variant-13 finalizer of the state.  Keyed per use as stated in the header of
+// the draws: key = out(seed + gamma*stream), draw(idx) = out(key + gamma*idx).
+namespace rng {
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+inline uint64_t fin(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+inline uint64_t stream(int kind, int t, int a, int b) {
+  return ((uint64_t)(kind & 0xFF) << 56) | ((uint64_t)(t & 0xFFFF) << 40) | ((uint64_t)(a & 0xFFFFFF) << 16) |
+         (uint64_t)(b & 0xFFFF);
+}
+inline uint64_t draw(uint64_t seed, uint64_t st, uint64_t idx) {
+  const uint64_t key = fin(seed + kGamma * (st + 1));
+  return fin(key + kGamma * (idx + 1));
+}
+inline double uniform01(uint64_t seed, uint64_t st, uint64_t idx) {
+  return (double)(draw(seed, st, idx) >> 11) * (1.0 / 9007199254740992.0);
+}
+enum { kTail1 = 1, kTail2 = 2, kLat2 = 3, kLat3 = 4 };
+}  // namespace rng
+
+// ---------------------------------------------------------------- buffers
+// Owning device buffer; move-only so that swaps and container moves never
+// duplicate (and later double-free) an allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  void ensure(size_t b) {
+    if (b <= bytes) return;
+    if (p) USFFT_HIP(hipFree(p));
+    p = nullptr;
+    bytes = 0;
+    const size_t nb = std::max<size_t>(b, 256);
+    const hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{USFFT_ENOMEM, "device allocation of " + std::to_string(nb) + " bytes failed"};
+    }
+    bytes = nb;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevBuf() { release(); }
+};
+
+struct Family {
+  std::vector<int> M;
+  std::vector<int32_t> z;  // nlat x t
+  std::vector<int64_t> off;
+  std::vector<int32_t> lat_first, lat_count;  // slices of the grouped (pos, bin) lists
+  int t = 0;
+  int64_t total() const { return off.empty() ? 0 : off.back(); }
+};
+
+}  // namespace usfft
+
+struct usfft_plan_s {
+  usfft_problem prob{};
+  usfft_params par{};
+  std::vector<int32_t> k_lo, k_hi, mode1, mode2, poly_k;
+  std::vector<double> amp, poly_c;
+  int64_t G = 0;
+  int solver_cfg = 0;
+  // static device tables
+  usfft::DevBuf d_amp, d_tab, d_polyk, d_polyc;
+  usfft::PdeDev pde{};
+  // Rader tables per lattice size
+  std::map<int, usfft::RaderTables> rader;
+  // workspaces (grown on demand, kept across calls)
+  usfft::DevBuf Y, U, V, iters, cnt, theta2, scratch, J, Jnext, Iprev, mask, cands, assign, bins, famz, fambins,
+      famcounts, famcov, famscores, lists, latM, latz, latoff, tail;
+  std::vector<usfft::DevBuf> I1;  // step-1 sets per coordinate
+  std::vector<int64_t> I1n;
+  std::mutex mu;
+  ~usfft_plan_s() {
+    for (auto& kv : rader) usfft::rader_free(kv.second);
+  }
+};
+
+struct usfft_result_s {
+  int32_t d = 0;
+  int64_t G = 0;
+  std::vector<int32_t> I;  // n x d
+  usfft::DevBuf C;         // n x G x 2 doubles
+  usfft_stats stats{};
+};
+
+namespace usfft {
+
+// ---------------------------------------------------------------- helpers
+static const RaderTables& rader_for(usfft_plan_s* P, int M, hipStream_t st) {
+  auto it = P->rader.find(M);
+  if (it != P->rader.end()) return it->second;
+  RaderTables T;
+  rader_build(T, M, st);
+  return P->rader.emplace(M, T).first->second;
+}
+
+static std::vector<int> admissible_sizes(int lo, int hi) {
+  std::vector<int> out;
+  for (int m = std::max(lo, 3); m <= hi; ++m)
+    if (lattice_size_ok(m)) out.push_back(m);
+  return out;
+}
+
+// Small per-stage uploads; synchronous because the host vectors are reused.
+template <typename T>
+static void h2d(usfft::DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+  b.ensure(sizeof(T) * std::max<size_t>(v.size(), 1));
+  if (!v.empty()) {
+    USFFT_HIP(hipMemcpyAsync(b.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+  }
+}
+
+// Greedy multiple rank-1 lattice family (reading stated in usfft.h).  The alias
+// tests run on the device; the host keeps the choice loop.
+static void plan_family(usfft_plan_s* P, const int32_t* J, int64_t n, int t, uint64_t seed, int kind, int tcode,
+                        Family& F, int32_t* assign, int32_t* bins_out, hipStream_t st) {
+  const usfft_params& par = P->par;
+  F = Family{};
+  F.t = t;
+  F.off.push_back(0);
+  if (n == 0) return;
+  int lo = std::max<int64_t>(3, (int64_t)std::ceil(par.lattice_c * (double)n));
+  lo = std::min(lo, par.lattice_mmax / 2);
+  const std::vector<int> sizes = admissible_sizes(lo, par.lattice_mmax);
+  USFFT_REQUIRE(!sizes.empty(), USFFT_ELATTICE, "no admissible lattice size in range");
+  const int T = par.lattice_tries;
+  P->famcov.ensure(n);
+  USFFT_HIP(hipMemsetAsync(P->famcov.p, 0, n, st));
+  P->fambins.ensure(sizeof(int32_t) * n * T);
+  P->famscores.ensure(sizeof(int32_t) * T);
+  int64_t remaining = n;
+  std::vector<int32_t> z((size_t)T * t), scores(T);
+  for (int attempt = 0; remaining > 0; ++attempt) {
+    USFFT_REQUIRE(attempt < par.lattice_max, USFFT_ELATTICE,
+                  "lattice family incomplete after " + std::to_string(par.lattice_max) + " attempts");
+    const int M = sizes[attempt % sizes.size()];
+    for (int b = 0; b < T; ++b)
+      for (int j = 0; j < t; ++j)
+        z[(size_t)b * t + j] = (int32_t)(1 + rng::draw(seed, rng::stream(kind, tcode, attempt, b), j) % (M - 1));
+    h2d(P->famz, z, st);
+    P->famcounts.ensure(sizeof(int32_t) * (size_t)T * M);
+    USFFT_HIP(hipMemsetAsync(P->famcounts.p, 0, sizeof(int32_t) * (size_t)T * M, st));
+    USFFT_HIP(hipMemsetAsync(P->famscores.p, 0, sizeof(int32_t) * T, st));
+    launch_lattice_bins(J, n, t, P->famz.as<int32_t>(), T, M, P->fambins.as<int32_t>(), P->famcounts.as<int32_t>(),
+                        st);
+    launch_lattice_score(P->fambins.as<int32_t>(), P->famcounts.as<int32_t>(), P->famcov.as<uint8_t>(), n, T, M,
+                         P->famscores.as<int32_t>(), st);
+    USFFT_HIP(hipMemcpyAsync(scores.data(), P->famscores.p, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+    int best = 0;
+    for (int b = 1; b < T; ++b)
+      if (scores[b] > scores[best]) best = b;
+    if (scores[best] == 0) continue;
+    const int lat = (int)F.M.size();
+    launch_lattice_take(P->fambins.as<int32_t>() + (size_t)best * n, P->famcounts.as<int32_t>() + (size_t)best * M,
+                        P->famcov.as<uint8_t>(), n, M, lat, assign, bins_out, st);
+    F.M.push_back(M);
+    for (int j = 0; j < t; ++j) F.z.push_back(z[(size_t)best * t + j]);
+    F.off.push_back(F.off.back() + M);
+    remaining -= scores[best];
+  }
+}
+
+// Group candidates by lattice: pos lists (ascending) and bins, uploaded to P->lists.
+static void group_by_lattice(usfft_plan_s* P, Family& F, const int32_t* assign, const int32_t* bins, int64_t n,
+                             hipStream_t st) {
+  std::vector<int32_t> ha(n), hb(n);
+  if (n > 0) {
+    USFFT_HIP(hipMemcpyAsync(ha.data(), assign, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipMemcpyAsync(hb.data(), bins, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+  }
+  const int nl = (int)F.M.size();
+  F.lat_count.assign(nl, 0);
+  for (int64_t a = 0; a < n; ++a) F.lat_count[ha[a]]++;
+  F.lat_first.assign(nl, 0);
+  for (int l = 1; l < nl; ++l) F.lat_first[l] = F.lat_first[l - 1] + F.lat_count[l - 1];
+  std::vector<int32_t> lists(2 * std::max<int64_t>(n, 1));
+  std::vector<int32_t> fill(F.lat_first);
+  for (int64_t a = 0; a < n; ++a) {
+    const int l = ha[a];
+    lists[fill[l]] = (int32_t)a;  // positions
+    lists[n + fill[l]] = hb[a];   // bins
+    fill[l]++;
+  }
+  h2d(P->lists, lists, st);
+}
+
+// Sampler call on rows [0, ns) of Y into U columns [col0, col0 + ns).
+static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, int out_fp32, int64_t ld,
+                        int64_t col0, int32_t* iters, hipStream_t st) {
+  if (ns <= 0) return;
+  const usfft_params& par = P->par;
+  if (P->prob.sampler == USFFT_SAMPLER_PDE) {
+    launch_pde_solve(P->solver_cfg, P->pde, par.precision, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
+                     par.max_refine, U, out_fp32, ld, col0, iters, st);
+  } else {
+    launch_trigpoly(P->prob.d, Y, ns, P->d_polyk.as<int32_t>(), P->prob.n_poly, P->d_polyc.as<double>(), P->G, U,
+                    out_fp32, ld, col0, st);
+    if (iters) USFFT_HIP(hipMemsetAsync(iters, 0, sizeof(int32_t) * ns, st));
+  }
+}
+
+__global__ void iter_stats_kernel(const int32_t* __restrict__ it, int64_t n, unsigned long long* __restrict__ acc) {
+  unsigned long long bad = 0, sum = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int v = it[i];
+    if (v < 0)
+      ++bad;
+    else
+      sum += (unsigned long long)v;
+  }
+  bad = wave_sum(bad);
+  sum = wave_sum(sum);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (bad) atomicAdd(&acc[0], bad);
+    if (sum) atomicAdd(&acc[1], sum);
+  }
+}
+
+static void accumulate_iters(usfft_plan_s* P, int64_t ns, hipStream_t st) {
+  if (ns <= 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(256, ceil_div(ns, 256));
+  hipLaunchKernelGGL(iter_stats_kernel, dim3(grid), dim3(256), 0, st, P->iters.as<int32_t>(), ns,
+                     P->cnt.as<unsigned long long>());
+  USFFT_HIP(hipGetLastError());
+}
+
+struct Timer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+  hipStream_t st;
+  explicit Timer(hipStream_t s) : st(s) {}
+  int open(int cat) {
+    hipEvent_t a, b;
+    USFFT_HIP(hipEventCreate(&a));
+    USFFT_HIP(hipEventCreate(&b));
+    USFFT_HIP(hipEventRecord(a, st));
+    ev[cat].push_back({a, b});
+    return (int)ev[cat].size() - 1;
+  }
+  void close(int cat, int i) { USFFT_HIP(hipEventRecord(ev[cat][i].second, st)); }
+  double total(int cat) {
+    double s = 0;
+    for (auto& e : ev[cat]) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) s += ms;
+    }
+    return s;
+  }
+  ~Timer() {
+    for (auto& v : ev)
+      for (auto& e : v) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
+  }
+};
+enum { kTSample = 0, kTDft = 1, kTSelect = 2 };
+
+// ---------------------------------------------------------------- Alg. 1
+static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_s* R) {
+  const usfft_problem& pb = P->prob;
+  const usfft_params& par = P->par;
+  const int d = pb.d;
+  const int64_t G = P->G;
+  const int ufp32 = par.precision == USFFT_FP32_REFINE ? 1 : 0;
+  const size_t ub = ufp32 ? sizeof(float) : sizeof(double);
+  Timer tm(st);
+  usfft_stats& S = R->stats;
+  auto sample_timed = [&](const double* Y, int64_t ns, int64_t ld) {
+    const int e = tm.open(kTSample);
+    run_sampler(P, Y, ns, P->U.p, ufp32, ld, 0, P->iters.as<int32_t>(), st);
+    tm.close(kTSample, e);
+    accumulate_iters(P, ns, st);
+    S.sample_launches += ns > 0 ? 1 : 0;
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+
+  P->cnt.ensure(2 * sizeof(unsigned long long));
+  USFFT_HIP(hipMemsetAsync(P->cnt.p, 0, 2 * sizeof(unsigned long long), st));
+  P->theta2.ensure(sizeof(double));
+  P->scratch.ensure(64);
+  if (!par.theta_relative) {
+    const double th2 = par.theta * par.theta;
+    USFFT_HIP(hipMemcpyAsync(P->theta2.p, &th2, sizeof(double), hipMemcpyHostToDevice, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+  }
+  P->tail.ensure(sizeof(double) * kMaxD);
+  std::vector<double> tail(d);
+  auto upload_tail = [&](int kind, int t, int i) {
+    for (int j = 0; j < d; ++j) tail[j] = rng::uniform01(seed, rng::stream(kind, t, i, 0), j);
+    USFFT_HIP(hipMemcpyAsync(P->tail.p, tail.data(), sizeof(double) * d, hipMemcpyHostToDevice, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+  };
+  auto check_conv = [&]() {
+    unsigned long long h[2];
+    USFFT_HIP(hipMemcpyAsync(h, P->cnt.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+    S.pcg_iterations = (int64_t)h[1];
+    USFFT_REQUIRE(h[0] == 0, USFFT_ENOCONV,
+                  std::to_string(h[0]) + " PCG solves missed pcg_rtol within pcg_maxit");
+  };
+
+  // ---------------- step 1 & 2a
+  P->I1.resize(d);
+  P->I1n.assign(d, 0);
+  bool theta_set = !par.theta_relative;
+  for (int t = 0; t < d; ++t) {
+    const int K = pb.k_hi[t] - pb.k_lo[t] + 1;
+    std::vector<int32_t> ks(K);
+    for (int a = 0; a < K; ++a) ks[a] = pb.k_lo[t] + a;
+    h2d(P->cands, ks, st);
+    const int64_t ld = ceil_div(K, 64) * 64;
+    P->U.ensure(ub * G * ld);
+    P->V.ensure(sizeof(double) * G * K);
+    P->Y.ensure(sizeof(double) * K * d);
+    P->iters.ensure(sizeof(int32_t) * K);
+    const int64_t words = ceil_div(K, 32);
+    P->mask.ensure(sizeof(uint32_t) * words);
+    USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * words, st));
+    std::vector<int32_t> Kv = {K};
+    h2d(P->latM, Kv, st);
+    for (int i = 0; i < par.r; ++i) {
+      upload_tail(rng::kTail1, t + 1, i + 1);
+      launch_nodes(d, t, 1, 1, nullptr, P->latM.as<int32_t>(), nullptr, P->tail.as<double>(), P->Y.as<double>(), K,
+                   st);
+      sample_timed(P->Y.as<double>(), K, ld);
+      S.samples_step1 += K;
+      int e = tm.open(kTDft);
+      launch_line_dft(P->U.p, ufp32, G, ld, 0, K, P->cands.as<int32_t>(), K, USFFT_OUT_MAG2, P->V.p, K, st);
+      tm.close(kTDft, e);
+      S.dft_launches += 1;
+      if (!theta_set) {
+        launch_max_to_theta(P->V.as<double>(), G, K, K, par.theta, P->theta2.as<double>(), P->scratch.as<uint64_t>(),
+                            st);
+        theta_set = true;
+      }
+      e = tm.open(kTSelect);
+      launch_select(P->V.as<double>(), G, K, K, par.s_local, P->theta2.as<double>(), par.tie_rel,
+                    P->mask.as<uint32_t>(), nullptr, st);
+      tm.close(kTSelect, e);
+    }
+    P->I1[t].ensure(sizeof(int32_t) * K);
+    P->cnt.ensure(2 * sizeof(unsigned long long));
+    P->scratch.ensure(64);
+    launch_compact(P->cands.as<int32_t>(), P->mask.as<uint32_t>(), K, 1, P->I1[t].as<int32_t>(),
+                   reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32), st);
+    int64_t cntI = 0;
+    USFFT_HIP(hipMemcpyAsync(&cntI, P->scratch.as<char>() + 32, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    check_conv();
+    P->I1n[t] = cntI;
+  }
+  {
+    double th2 = 0;
+    USFFT_HIP(hipMemcpyAsync(&th2, P->theta2.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+    S.theta_abs = std::sqrt(th2);
+  }
+
+  // ---------------- step 2
+  int64_t nprev = P->I1n[0];
+  P->Iprev.ensure(sizeof(int32_t) * std::max<int64_t>(nprev, 1));
+  if (nprev > 0)
+    USFFT_HIP(hipMemcpyAsync(P->Iprev.p, P->I1[0].p, sizeof(int32_t) * nprev, hipMemcpyDeviceToDevice, st));
+  Family F;
+  for (int t = 1; t < d; ++t) {
+    const bool last = t == d - 1;
+    const int r_t = last ? 1 : par.r;
+    const int s_t = last ? par.s : par.s_local;
+    const int64_t nc = P->I1n[t];
+    const int64_t n = nprev * nc;
+    S.max_candidates = std::max(S.max_candidates, n);
+    if (n == 0) {
+      nprev = 0;
+      continue;
+    }
+    const int w = t + 1;
+    P->J.ensure(sizeof(int32_t) * n * w);
+    launch_product(P->Iprev.as<int32_t>(), nprev, t, P->I1[t].as<int32_t>(), nc, P->J.as<int32_t>(), st);
+    P->assign.ensure(sizeof(int32_t) * n);
+    P->bins.ensure(sizeof(int32_t) * n);
+    plan_family(P, P->J.as<int32_t>(), n, w, seed, rng::kLat2, w, F, P->assign.as<int32_t>(),
+                P->bins.as<int32_t>(), st);
+    group_by_lattice(P, F, P->assign.as<int32_t>(), P->bins.as<int32_t>(), n, st);
+    S.lattices += (int64_t)F.M.size();
+    for (int M : F.M) (void)rader_for(P, M, st);
+    const int64_t ns = F.total();
+    const int64_t ld = ceil_div(ns, 64) * 64;
+    P->U.ensure(ub * G * ld);
+    P->V.ensure(sizeof(double) * G * n);
+    P->Y.ensure(sizeof(double) * ns * d);
+    P->iters.ensure(sizeof(int32_t) * ns);
+    h2d(P->latM, F.M, st);
+    h2d(P->latz, F.z, st);
+    h2d(P->latoff, F.off, st);
+    const int64_t words = ceil_div(n, 32);
+    P->mask.ensure(sizeof(uint32_t) * words);
+    USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * words, st));
+    for (int i = 0; i < r_t; ++i) {
+      upload_tail(rng::kTail2, t + 1, i + 1);
+      launch_nodes(d, -1, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(), P->latz.as<int32_t>(),
+                   P->tail.as<double>(), P->Y.as<double>(), ns, st);
+      sample_timed(P->Y.as<double>(), ns, ld);
+      S.samples_step2 += ns;
+      int e = tm.open(kTDft);
+      for (size_t l = 0; l < F.M.size(); ++l) {
+        const RaderTables& T = rader_for(P, F.M[l], st);
+        const int32_t* pos = P->lists.as<int32_t>() + F.lat_first[l];
+        const int32_t* bn = P->lists.as<int32_t>() + n + F.lat_first[l];
+        launch_lattice_dft(T, P->U.p, ufp32, G, ld, F.off[l], bn, pos, F.lat_count[l], USFFT_OUT_MAG2, P->V.p, n, st);
+        S.dft_launches += 1;
+        S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 8.0;
+      }
+      tm.close(kTDft, e);
+      e = tm.open(kTSelect);
+      launch_select(P->V.as<double>(), G, n, n, s_t, P->theta2.as<double>(), par.tie_rel, P->mask.as<uint32_t>(),
+                    nullptr, st);
+      tm.close(kTSelect, e);
+    }
+    P->Jnext.ensure(sizeof(int32_t) * n * w);
+    launch_compact(P->J.as<int32_t>(), P->mask.as<uint32_t>(), n, w, P->Jnext.as<int32_t>(),
+                   reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32), st);
+    int64_t cntI = 0;
+    USFFT_HIP(hipMemcpyAsync(&cntI, P->scratch.as<char>() + 32, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    check_conv();
+    std::swap(P->Iprev, P->Jnext);
+    nprev = cntI;
+  }
+
+  // ---------------- step 3
+  const int64_t nI = nprev;
+  R->d = d;
+  R->G = G;
+  R->I.assign((size_t)nI * d, 0);
+  R->C.ensure(sizeof(double) * 2 * std::max<int64_t>(nI, 1) * G);
+  if (nI > 0) {
+    USFFT_HIP(hipMemcpyAsync(R->I.data(), P->Iprev.p, sizeof(int32_t) * nI * d, hipMemcpyDeviceToHost, st));
+    P->assign.ensure(sizeof(int32_t) * nI);
+    P->bins.ensure(sizeof(int32_t) * nI);
+    plan_family(P, P->Iprev.as<int32_t>(), nI, d, seed, rng::kLat3, 0, F, P->assign.as<int32_t>(),
+                P->bins.as<int32_t>(), st);
+    group_by_lattice(P, F, P->assign.as<int32_t>(), P->bins.as<int32_t>(), nI, st);
+    S.lattices += (int64_t)F.M.size();
+    for (int M : F.M) (void)rader_for(P, M, st);
+    const int64_t ns = F.total();
+    const int64_t ld = ceil_div(ns, 64) * 64;
+    P->U.ensure(ub * G * ld);
+    P->Y.ensure(sizeof(double) * ns * d);
+    P->iters.ensure(sizeof(int32_t) * ns);
+    h2d(P->latM, F.M, st);
+    h2d(P->latz, F.z, st);
+    h2d(P->latoff, F.off, st);
+    launch_nodes(d, -1, d, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(), P->latz.as<int32_t>(),
+                 P->tail.as<double>(), P->Y.as<double>(), ns, st);
+    sample_timed(P->Y.as<double>(), ns, ld);
+    S.samples_step3 += ns;
+    int e = tm.open(kTDft);
+    for (size_t l = 0; l < F.M.size(); ++l) {
+      const RaderTables& T = rader_for(P, F.M[l], st);
+      const int32_t* pos = P->lists.as<int32_t>() + F.lat_first[l];
+      const int32_t* bn = P->lists.as<int32_t>() + nI + F.lat_first[l];
+      launch_lattice_dft(T, P->U.p, ufp32, G, ld, F.off[l], bn, pos, F.lat_count[l], USFFT_OUT_COMPLEX, R->C.p, G,
+                         st);
+      S.dft_launches += 1;
+      S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 16.0;
+    }
+    tm.close(kTDft, e);
+    check_conv();
+  }
+  USFFT_HIP(hipStreamSynchronize(st));
+  S.samples = S.samples_step1 + S.samples_step2 + S.samples_step3;
+  if (pb.sampler == USFFT_SAMPLER_PDE) {
+    int blk = 0, npt = 0;
+    solver_config_shape(P->solver_cfg, &blk, &npt);
+    S.solver_block = blk;
+    S.solver_npt = npt;
+  }
+  S.ms_sample = tm.total(kTSample);
+  S.ms_dft = tm.total(kTDft);
+  S.ms_select = tm.total(kTSelect);
+  S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------- autotune
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tune_cache;
+
+static int autotune_solver(usfft_plan_s* P) {
+  const int n = P->prob.mesh_n, d = P->prob.d, prec = P->par.precision;
+  const auto key = std::make_tuple(n, d, prec);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) return it->second;
+  }
+  const int64_t G = P->G;
+  const int64_t ns = 1024;
+  hipStream_t st = nullptr;
+  DevBuf Y, U, it;
+  Y.ensure(sizeof(double) * ns * d);
+  U.ensure(sizeof(double) * G * ns);
+  it.ensure(sizeof(int32_t) * ns);
+  std::vector<double> yh((size_t)ns * d);
+  for (int64_t e = 0; e < ns * d; ++e) yh[e] = rng::uniform01(12345, 77, e);
+  USFFT_HIP(hipMemcpy(Y.p, yh.data(), sizeof(double) * yh.size(), hipMemcpyHostToDevice));
+  hipEvent_t a, b;
+  USFFT_HIP(hipEventCreate(&a));
+  USFFT_HIP(hipEventCreate(&b));
+  int best = solver_default_config((int)G);
+  float best_ms = 1e30f;
+  for (int c = 0; c < solver_config_count(); ++c) {
+    if (!solver_config_fits(c, (int)G)) continue;
+    launch_pde_solve(c, P->pde, prec, Y.as<double>(), 64, P->par.pcg_rtol, P->par.pcg_maxit, P->par.inner_rtol,
+                     P->par.max_refine, U.p, 0, ns, 0, it.as<int32_t>(), st);
+    USFFT_HIP(hipEventRecord(a, st));
+    launch_pde_solve(c, P->pde, prec, Y.as<double>(), ns, P->par.pcg_rtol, P->par.pcg_maxit, P->par.inner_rtol,
+                     P->par.max_refine, U.p, 0, ns, 0, it.as<int32_t>(), st);
+    USFFT_HIP(hipEventRecord(b, st));
+    USFFT_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    USFFT_HIP(hipEventElapsedTime(&ms, a, b));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = best;
+  return best;
+}
+
+// ---------------------------------------------------------------- plan
+static void validate(const usfft_problem* pb, const usfft_params* par) {
+  USFFT_REQUIRE(pb && par, USFFT_EINVAL, "null problem or params");
+  USFFT_REQUIRE(pb->d >= 1 && pb->d <= kMaxD, USFFT_EINVAL, "d must be in [1, 64]");
+  USFFT_REQUIRE(pb->k_lo && pb->k_hi, USFFT_EINVAL, "missing search box");
+  for (int j = 0; j < pb->d; ++j) {
+    const int K = pb->k_hi[j] - pb->k_lo[j] + 1;
+    USFFT_REQUIRE(K >= 1 && K <= 1024, USFFT_EINVAL, "box extent K_t must be in [1, 1024]");
+  }
+  USFFT_REQUIRE(par->s >= 1 && par->s_local >= par->s && par->r >= 1, USFFT_EINVAL,
+                "need s >= 1, s_local >= s, r >= 1");
+  USFFT_REQUIRE(par->theta >= 0 && par->tie_rel >= 0 && par->tie_rel < 1, USFFT_EINVAL, "bad theta / tie_rel");
+  USFFT_REQUIRE(par->precision == USFFT_FP64 || par->precision == USFFT_FP32_REFINE, USFFT_EINVAL, "bad precision");
+  USFFT_REQUIRE(par->lattice_c > 0 && par->lattice_tries >= 1 && par->lattice_max >= 1 &&
+                    par->lattice_mmax >= 3 && par->lattice_mmax <= kMaxLattice,
+                USFFT_EINVAL, "bad lattice parameters (lattice_mmax <= 9601)");
+  USFFT_REQUIRE(par->pcg_rtol > 0 && par->pcg_maxit >= 1 && par->inner_rtol > 0 && par->max_refine >= 0,
+                USFFT_EINVAL, "bad solver parameters");
+  if (pb->sampler == USFFT_SAMPLER_PDE) {
+    USFFT_REQUIRE(pb->mesh_n >= 4 && pb->mesh_n <= kMaxMesh, USFFT_EINVAL, "mesh_n must be in [4, 64]");
+    USFFT_REQUIRE(pb->amp && pb->mode1 && pb->mode2, USFFT_EINVAL, "missing coefficient family");
+  } else {
+    USFFT_REQUIRE(pb->sampler == USFFT_SAMPLER_TRIG_POLY, USFFT_EINVAL, "unknown sampler");
+    USFFT_REQUIRE(pb->G_poly >= 1 && pb->n_poly >= 1 && pb->poly_k && pb->poly_c, USFFT_EINVAL,
+                  "bad trigonometric polynomial");
+  }
+}
+
+static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* par) {
+  validate(pb, par);
+  std::unique_ptr<usfft_plan_s> P(new usfft_plan_s());
+  P->prob = *pb;
+  P->par = *par;
+  const int d = pb->d;
+  P->k_lo.assign(pb->k_lo, pb->k_lo + d);
+  P->k_hi.assign(pb->k_hi, pb->k_hi + d);
+  P->prob.k_lo = P->k_lo.data();
+  P->prob.k_hi = P->k_hi.data();
+  if (pb->sampler == USFFT_SAMPLER_PDE) {
+    const int n = pb->mesh_n;
+    P->G = (int64_t)(n - 1) * (n - 1);
+    P->amp.assign(pb->amp, pb->amp + d);
+    P->mode1.assign(pb->mode1, pb->mode1 + d);
+    P->mode2.assign(pb->mode2, pb->mode2 + d);
+    P->prob.amp = P->amp.data();
+    P->prob.mode1 = P->mode1.data();
+    P->prob.mode2 = P->mode2.data();
+    // sin(m pi x) at the centroid abscissae: lower triangle (i+2/3, j+1/3) h,
+    // upper triangle (i+1/3, j+2/3) h of cell (i, j)
+    std::vector<double> tab((size_t)4 * d * n);
+    const double h = 1.0 / n;
+    for (int k = 0; k < d; ++k)
+      for (int c = 0; c < n; ++c) {
+        tab[(size_t)(0 * d + k) * n + c] = std::sin(P->mode1[k] * M_PI * (c + 2.0 / 3.0) * h);
+        tab[(size_t)(1 * d + k) * n + c] = std::sin(P->mode1[k] * M_PI * (c + 1.0 / 3.0) * h);
+        tab[(size_t)(2 * d + k) * n + c] = std::sin(P->mode2[k] * M_PI * (c + 1.0 / 3.0) * h);
+        tab[(size_t)(3 * d + k) * n + c] = std::sin(P->mode2[k] * M_PI * (c + 2.0 / 3.0) * h);
+      }
+    P->d_amp.ensure(sizeof(double) * d);
+    P->d_tab.ensure(sizeof(double) * tab.size());
+    USFFT_HIP(hipMemcpy(P->d_amp.p, P->amp.data(), sizeof(double) * d, hipMemcpyHostToDevice));
+    USFFT_HIP(hipMemcpy(P->d_tab.p, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice));
+    P->pde.n = n;
+    P->pde.d = d;
+    P->pde.a0 = pb->a0;
+    P->pde.h2 = h * h;
+    P->pde.amp = P->d_amp.as<double>();
+    P->pde.tab = P->d_tab.as<double>();
+    const int G = (int)P->G;
+    if (par->solver_config >= 0) {
+      USFFT_REQUIRE(par->solver_config < solver_config_count() && solver_config_fits(par->solver_config, G),
+                    USFFT_EINVAL, "solver_config does not fit this mesh");
+      P->solver_cfg = par->solver_config;
+    } else if (par->solver_config == -2) {
+      P->solver_cfg = solver_default_config(G);
+    } else {
+      P->solver_cfg = autotune_solver(P.get());
+    }
+    USFFT_REQUIRE(P->solver_cfg >= 0, USFFT_EINVAL, "no solver shape for this mesh");
+  } else {
+    P->G = pb->G_poly;
+    P->poly_k.assign(pb->poly_k, pb->poly_k + (size_t)pb->n_poly * d);
+    P->poly_c.assign(pb->poly_c, pb->poly_c + (size_t)pb->n_poly * pb->G_poly * 2);
+    P->d_polyk.ensure(sizeof(int32_t) * P->poly_k.size());
+    P->d_polyc.ensure(sizeof(double) * P->poly_c.size());
+    USFFT_HIP(hipMemcpy(P->d_polyk.p, P->poly_k.data(), sizeof(int32_t) * P->poly_k.size(), hipMemcpyHostToDevice));
+    USFFT_HIP(hipMemcpy(P->d_polyc.p, P->poly_c.data(), sizeof(double) * P->poly_c.size(), hipMemcpyHostToDevice));
+    P->prob.poly_k = P->poly_k.data();
+    P->prob.poly_c = P->poly_c.data();
+  }
+  return P.release();
+}
+
+template <typename F>
+static usfft_status guarded(F&& f) {
+  try {
+    f();
+    return USFFT_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return USFFT_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return USFFT_EINVAL;
+  }
+}
+
+}  // namespace usfft
+
+using namespace usfft;
+
+extern "C" {
+
+const char* usfft_last_error(void) { return g_last_error.c_str(); }
+const char* usfft_version(void) { return "usfft-gfx950 1.0"; }
+
+usfft_status usfft_plan_create(const usfft_problem* prob, const usfft_params* par, usfft_plan_t* out) {
+  return guarded([&] {
+    USFFT_REQUIRE(out, USFFT_EINVAL, "null output");
+    *out = plan_create(prob, par);
+  });
+}
+
+void usfft_plan_destroy(usfft_plan_t plan) { delete plan; }
+
+int64_t usfft_plan_nodes(usfft_plan_t plan) { return plan ? plan->G : -1; }
+
+usfft_status usfft_detect(usfft_plan_t plan, uint64_t seed, void* stream, usfft_result_t* out) {
+  return guarded([&] {
+    USFFT_REQUIRE(plan && out, USFFT_EINVAL, "null plan or output");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    std::unique_ptr<usfft_result_s> R(new usfft_result_s());
+    detect(plan, seed, (hipStream_t)stream, R.get());
+    *out = R.release();
+  });
+}
+
+usfft_status usfft_result_info(usfft_result_t res, int64_t* n_freq, int32_t* d, int64_t* G, usfft_stats* stats) {
+  return guarded([&] {
+    USFFT_REQUIRE(res, USFFT_EINVAL, "null result");
+    if (n_freq) *n_freq = res->d ? (int64_t)res->I.size() / res->d : 0;
+    if (d) *d = res->d;
+    if (G) *G = res->G;
+    if (stats) *stats = res->stats;
+  });
+}
+
+usfft_status usfft_result_copy(usfft_result_t res, int32_t* freqs_host, double* coeffs_host) {
+  return guarded([&] {
+    USFFT_REQUIRE(res, USFFT_EINVAL, "null result");
+    if (freqs_host && !res->I.empty()) std::memcpy(freqs_host, res->I.data(), sizeof(int32_t) * res->I.size());
+    const int64_t n = res->d ? (int64_t)res->I.size() / res->d : 0;
+    if (coeffs_host && n > 0)
+      USFFT_HIP(hipMemcpy(coeffs_host, res->C.p, sizeof(double) * 2 * n * res->G, hipMemcpyDeviceToHost));
+  });
+}
+
+void usfft_result_destroy(usfft_result_t res) { delete res; }
+
+usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n, double* out_dev, void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(res && (n == 0 || (y_dev && out_dev)), USFFT_EINVAL, "bad eval arguments");
+    const int64_t nI = res->d ? (int64_t)res->I.size() / res->d : 0;
+    DevBuf I;
+    if (nI > 0) {
+      I.ensure(sizeof(int32_t) * res->I.size());
+      USFFT_HIP(hipMemcpy(I.p, res->I.data(), sizeof(int32_t) * res->I.size(), hipMemcpyHostToDevice));
+    }
+    launch_eval(I.as<int32_t>(), nI, res->d, res->C.as<double>(), res->G, y_dev, n, out_dev, (hipStream_t)stream);
+    USFFT_HIP(hipStreamSynchronize((hipStream_t)stream));
+  });
+}
+
+usfft_status usfft_sample(usfft_plan_t plan, const double* y_dev, int64_t n, void* u_dev, int32_t out_fp32,
+                          int64_t ld, int64_t col0, int32_t* iters_dev, void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(plan && (n == 0 || (y_dev && u_dev)), USFFT_EINVAL, "bad sample arguments");
+    USFFT_REQUIRE(n >= 0 && col0 >= 0 && ld >= col0 + n, USFFT_EINVAL, "ld < col0 + n");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    run_sampler(plan, y_dev, n, u_dev, out_fp32 ? 1 : 0, ld, col0, iters_dev, (hipStream_t)stream);
+  });
+}
+
+usfft_status usfft_nodes(int32_t d, int32_t line, int32_t t, int32_t nlat, const int32_t* M_host,
+                         const int32_t* z_host, const double* tail_host, double* y_dev, void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(d >= 1 && d <= kMaxD && M_host && tail_host && y_dev, USFFT_EINVAL, "bad nodes arguments");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> Ms, zs;
+    std::vector<int64_t> off = {0};
+    std::vector<double> tail(tail_host, tail_host + d);
+    if (line >= 0) {
+      USFFT_REQUIRE(line < d && M_host[0] >= 1, USFFT_EINVAL, "bad line");
+      Ms = {M_host[0]};
+      off.push_back(M_host[0]);
+    } else {
+      USFFT_REQUIRE(nlat >= 1 && t >= 1 && t <= d && z_host, USFFT_EINVAL, "bad lattice list");
+      for (int l = 0; l < nlat; ++l) {
+        USFFT_REQUIRE(M_host[l] >= 1, USFFT_EINVAL, "bad lattice size");
+        Ms.push_back(M_host[l]);
+        off.push_back(off.back() + M_host[l]);
+      }
+      zs.assign(z_host, z_host + (size_t)nlat * t);
+    }
+    DevBuf dM, dz, doff, dt;
+    h2d(dM, Ms, st);
+    h2d(dz, zs.empty() ? std::vector<int32_t>{0} : zs, st);
+    h2d(doff, off, st);
+    h2d(dt, tail, st);
+    launch_nodes(d, line, t, (int)Ms.size(), doff.as<int64_t>(), dM.as<int32_t>(), dz.as<int32_t>(), dt.as<double>(),
+                 y_dev, off.back(), st);
+    USFFT_HIP(hipStreamSynchronize(st));
+  });
+}
+
+usfft_status usfft_line_dft(const void* u_dev, int32_t u_fp32, int64_t G, int64_t ld, int64_t col0, int32_t K,
+                            const int32_t* bins_host, int32_t nb, int32_t out_kind, void* out_dev, int64_t ldo,
+                            void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(u_dev && bins_host && out_dev && G >= 1 && nb >= 1 && ld >= col0 + K, USFFT_EINVAL,
+                  "bad line DFT arguments");
+    USFFT_REQUIRE(out_kind == USFFT_OUT_COMPLEX || ldo >= nb, USFFT_EINVAL, "ldo < nb");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf b;
+    h2d(b, std::vector<int32_t>(bins_host, bins_host + nb), st);
+    launch_line_dft(u_dev, u_fp32, G, ld, col0, K, b.as<int32_t>(), nb, out_kind, out_dev, ldo, st);
+    USFFT_HIP(hipStreamSynchronize(st));
+  });
+}
+
+usfft_status usfft_lattice_dft(const void* u_dev, int32_t u_fp32, int64_t G, int64_t ld, int64_t col0, int32_t M,
+                               const int32_t* bins_dev, const int32_t* pos_dev, int32_t nb, int32_t out_kind,
+                               void* out_dev, int64_t ldo, void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(u_dev && bins_dev && pos_dev && out_dev && G >= 1 && nb >= 0 && ld >= col0 + M, USFFT_EINVAL,
+                  "bad lattice DFT arguments");
+    USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL, "M is not an admissible lattice size");
+    hipStream_t st = (hipStream_t)stream;
+    RaderTables T;
+    rader_build(T, M, st);
+    try {
+      launch_lattice_dft(T, u_dev, u_fp32, G, ld, col0, bins_dev, pos_dev, nb, out_kind, out_dev, ldo, st);
+      USFFT_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      rader_free(T);
+      throw;
+    }
+    rader_free(T);
+  });
+}
+
+usfft_status usfft_select(const double* v_dev, int64_t G, int64_t n, int64_t ld, int32_t s_tilde,
+                          const double* theta2_dev, double tie_rel, uint32_t* mask_dev, double* thr_dev,
+                          void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(v_dev && theta2_dev && mask_dev && G >= 1 && n >= 0 && ld >= n, USFFT_EINVAL,
+                  "bad select arguments");
+    hipStream_t st = (hipStream_t)stream;
+    launch_select(v_dev, G, n, ld, s_tilde, theta2_dev, tie_rel, mask_dev, thr_dev, st);
+    USFFT_HIP(hipStreamSynchronize(st));
+  });
+}
+
+usfft_status usfft_product(const int32_t* parent_dev, int64_t np, int32_t t, const int32_t* child_dev, int64_t nc,
+                           int32_t* out_dev, void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(np >= 0 && nc >= 0 && t >= 1, USFFT_EINVAL, "bad product arguments");
+    hipStream_t st = (hipStream_t)stream;
+    launch_product(parent_dev, np, t, child_dev, nc, out_dev, st);
+    USFFT_HIP(hipStreamSynchronize(st));
+  });
+}
+
+usfft_status usfft_compact(const int32_t* J_dev, const uint32_t* mask_dev, int64_t n, int32_t t, int32_t* out_dev,
+                           int64_t* count_host, void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(n >= 0 && t >= 1 && count_host, USFFT_EINVAL, "bad compact arguments");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf c;
+    c.ensure(sizeof(int64_t));
+    launch_compact(J_dev, mask_dev, n, t, out_dev, c.as<int64_t>(), st);
+    USFFT_HIP(hipMemcpyAsync(count_host, c.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+  });
+}
+
+usfft_status usfft_family(const int32_t* J_dev, int64_t n, int32_t t, double c, int32_t mmax, int32_t tries,
+                          int32_t lmax, uint64_t seed, int32_t kind, int32_t tcode, int32_t cap, int32_t* nlat_host,
+                          int32_t* M_host, int32_t* z_host, int32_t* assign_dev, int32_t* bins_dev, void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(n >= 0 && t >= 1 && c > 0 && mmax >= 3 && mmax <= kMaxLattice && tries >= 1 && lmax >= 1 &&
+                      nlat_host && M_host && z_host,
+                  USFFT_EINVAL, "bad family arguments");
+    usfft_plan_s P;
+    P.par.lattice_c = c;
+    P.par.lattice_mmax = mmax;
+    P.par.lattice_tries = tries;
+    P.par.lattice_max = lmax;
+    Family F;
+    hipStream_t st = (hipStream_t)stream;
+    plan_family(&P, J_dev, n, t, seed, kind, tcode, F, assign_dev, bins_dev, st);
+    USFFT_HIP(hipStreamSynchronize(st));
+    USFFT_REQUIRE((int)F.M.size() <= cap, USFFT_EINVAL, "family larger than cap");
+    *nlat_host = (int32_t)F.M.size();
+    for (size_t l = 0; l < F.M.size(); ++l) M_host[l] = F.M[l];
+    std::memcpy(z_host, F.z.data(), sizeof(int32_t) * F.z.size());
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,309 @@
+"""GPU parity: every stage of the HIP path, through the C ABI, against the oracle.
+
+Integer work (nodes' lattice indices, masks, sets, families) must be
+bit-exact; float64 results meet the stated tolerances (nodal rel-L2 <= 1e-11
+for the float64 solver, <= 1e-9 after float32 + float64 refinement; DFT bins
+<= 1e-12 of the column maximum in float64, <= 1e-6 in float32).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dft as odft
+from oracle import fem as ofem
+from oracle import lattice as olat
+from oracle import rng as orng
+from oracle import select as osel
+from oracle.usfft import TrigPolySampler, evaluate, usfft
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ------------------------------------------------------------------ nodes
+def test_nodes_line_and_lattice_bit_exact(lib):
+    d = 5
+    tail = [orng.uniform01(3, orng.stream_code(1, 2, 1), j) for j in range(d)]
+    y = torch.zeros((33, d), dtype=torch.float64, device="cuda")
+    lib.nodes(d, 2, 1, [33], None, tail, y)
+    ref = np.tile(tail, (33, 1))
+    ref[:, 2] = np.arange(33) / 33
+    assert np.array_equal(host(y), ref)
+    Ms = [31, 61]
+    zs = [[1, 7, 12], [5, 3, 44]]
+    y = torch.zeros((sum(Ms), d), dtype=torch.float64, device="cuda")
+    lib.nodes(d, -1, 3, Ms, zs, tail, y)
+    ref = np.concatenate([np.hstack([olat.lattice_nodes(M, z), np.tile(tail[3:], (M, 1))]) for M, z in zip(Ms, zs)])
+    assert np.array_equal(host(y), ref)
+
+
+# ------------------------------------------------------------------ sampler
+@pytest.mark.parametrize("n,d,modes,prec,tol", [
+    (8, 3, "diagonal", 0, 1e-11), (16, 4, "diagonal", 0, 1e-11), (33, 6, "split", 0, 1e-11),
+    (64, 10, "split", 0, 1e-11), (16, 4, "diagonal", 1, 1e-9), (64, 10, "split", 1, 1e-9)])
+def test_pde_solves_match_banded_cholesky(lib, n, d, modes, prec, tol):
+    prob = W.pde_problem(n, d, 4, modes=modes)
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-13, solver_config=-2))
+    g = np.random.default_rng(n * 10 + d + prec)
+    ns = 37
+    Y = g.random((ns, d))
+    G = plan.G
+    ld = 40
+    U = torch.zeros((G, ld), dtype=torch.float64, device="cuda")
+    it = torch.zeros(ns, dtype=torch.int32, device="cuda")
+    lib.sample(plan, dev(Y), U, 0, ld, 2, it)
+    Ug = host(U)[:, 2:2 + ns].T
+    assert (host(it) > 0).all()
+    S = ofem.PDESampler(n, prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    for s in range(0, ns, 6):
+        ref = S.solve_one(Y[s])
+        err = np.linalg.norm(Ug[s] - ref) / np.linalg.norm(ref)
+        assert err <= tol, (s, err)
+
+
+def test_solver_shapes_agree_and_batch_independent(lib):
+    # every admissible workgroup shape gives the same float64 solution; a
+    # sample's result does not depend on the batch it is solved in (bitwise)
+    n, d = 16, 4
+    prob = W.pde_problem(n, d, 4, modes="diagonal")
+    Y = np.random.default_rng(5).random((20, d))
+    outs = []
+    for cfg in range(15):
+        try:
+            plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), pcg_rtol=1e-13, solver_config=cfg))
+        except lib.UsfftError:
+            continue
+        U = torch.zeros((plan.G, 20), dtype=torch.float64, device="cuda")
+        lib.sample(plan, dev(Y), U, 0, 20)
+        outs.append(host(U))
+        U1 = torch.zeros((plan.G, 1), dtype=torch.float64, device="cuda")
+        lib.sample(plan, dev(Y[7:8]), U1, 0, 1)
+        assert np.array_equal(host(U1)[:, 0], outs[-1][:, 7])
+    assert len(outs) >= 2
+    for o in outs[1:]:
+        assert np.abs(o - outs[0]).max() <= 1e-12 * np.abs(outs[0]).max()
+
+
+def test_trig_poly_sampler(lib):
+    K, P = W.trig_poly(4, 5, 8, 70, 31)
+    prob = dict(sampler="poly", d=5, k_lo=[-8] * 5, k_hi=[8] * 5, poly_k=K, poly_c=P)
+    plan = lib.Plan(prob, W.params(10, 1, 1e-6, relative=False))
+    Y = np.random.default_rng(1).random((19, 5))
+    U = torch.zeros((70, 19), dtype=torch.float64, device="cuda")
+    lib.sample(plan, dev(Y), U, 0, 19)
+    ref = TrigPolySampler(K, P)(Y)
+    assert np.abs(host(U).T - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ DFTs
+@pytest.mark.parametrize("K,G", [(33, 5), (65, 130), (16, 3), (1, 4)])
+def test_line_dft(lib, K, G):
+    U = W.sample_matrix(K + G, K, G, kind="normal")  # (K, G)
+    ld = K + 3
+    Ud = np.zeros((G, ld))
+    Ud[:, 1:1 + K] = U.T
+    ks = np.arange(-(K // 2), K - K // 2)
+    Vt = torch.zeros((G, K), dtype=torch.float64, device="cuda")
+    lib.line_dft(dev(Ud), 0, G, ld, 1, K, ks, lib.OUT_MAG2, Vt, K)
+    ref = odft.dft_bins(U, ks % K)
+    scale = np.abs(ref).max() ** 2
+    assert np.abs(host(Vt) - (np.abs(ref) ** 2).T).max() <= 1e-13 * scale
+    Ct = torch.zeros((K, G, 2), dtype=torch.float64, device="cuda")
+    lib.line_dft(dev(Ud), 0, G, ld, 1, K, ks, lib.OUT_COMPLEX, Ct, 0)
+    c = host(Ct)
+    assert np.abs(c[..., 0] + 1j * c[..., 1] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("M,G,fp32", [(3, 4, 0), (11, 7, 0), (31, 64, 0), (97, 33, 0), (1153, 9, 0),
+                                      (4801, 5, 0), (9601, 3, 0), (9601, 6, 1), (211, 129, 1)])
+def test_lattice_dft_rader(lib, M, G, fp32):
+    assert olat.admissible(M)
+    U = W.sample_matrix(M + G, M, G, kind="normal")
+    g = np.random.default_rng(M)
+    bins = np.arange(M) if M <= 211 else np.sort(g.choice(M, size=min(M, 700), replace=False))
+    pos = g.permutation(len(bins))
+    ld = M + 5
+    Ud = np.zeros((G, ld))
+    Ud[:, 2:2 + M] = U.T
+    ut = dev(Ud, torch.float32 if fp32 else torch.float64)
+    nb = len(bins)
+    V = torch.zeros((G, nb), dtype=torch.float64, device="cuda")
+    lib.lattice_dft(ut, fp32, G, ld, 2, M, dev(bins, torch.int32), dev(pos, torch.int32), lib.OUT_MAG2, V, nb)
+    C = torch.zeros((nb, G, 2), dtype=torch.float64, device="cuda")
+    lib.lattice_dft(ut, fp32, G, ld, 2, M, dev(bins, torch.int32), dev(pos, torch.int32), lib.OUT_COMPLEX, C, G)
+    ref = odft.dft_bins(U.astype(np.float32).astype(np.float64) if fp32 else U, bins)  # (nb, G)
+    tol = 1e-6 if fp32 else 1e-12
+    cmax = np.abs(ref).max()
+    got = host(C)
+    got = got[..., 0] + 1j * got[..., 1]
+    assert np.abs(got[pos] - ref).max() <= tol * cmax
+    assert np.abs(host(V)[:, pos] - (np.abs(ref) ** 2).T).max() <= 2 * tol * cmax ** 2
+    # bins b and M-b are exact conjugates (canonical half spectrum)
+    if M <= 211:
+        inv = np.empty(nb, int)
+        inv[pos] = np.arange(nb)
+        for b in range(1, M):
+            assert np.array_equal(got[pos[b]], np.conj(got[pos[M - b]]))
+
+
+# ------------------------------------------------------------------ select
+@pytest.mark.parametrize("n,G,s", [(5, 3, 2), (100, 17, 10), (4500, 40, 200), (65, 9, 200), (1, 2, 1)])
+def test_select_bit_exact(lib, n, G, s):
+    g = np.random.default_rng(n + G)
+    V = g.exponential(1.0, (n, G)) ** 4
+    V[g.random((n, G)) < 0.1] = 0.0
+    if n > 3:
+        V[1] = V[0]  # exact ties
+        V[2] = V[0] * (1 - 1e-12)  # ties within the band
+    theta2 = 1e-3
+    mask_ref, thr_ref, _ = osel.detect_mask(V, s, theta2)
+    ld = n + 7
+    Vd = np.zeros((G, ld))
+    Vd[:, :n] = V.T
+    words = (n + 31) // 32 + 1
+    mask = torch.zeros(words, dtype=torch.int32, device="cuda")
+    thr = torch.zeros(G, dtype=torch.float64, device="cuda")
+    lib.select(dev(Vd), G, n, ld, s, dev(np.array([theta2])), osel.TIE_REL, mask, thr)
+    m = host(mask).view(np.uint32)
+    bits = np.array([(m[a >> 5] >> (a & 31)) & 1 for a in range(n)], dtype=bool)
+    assert np.array_equal(bits, mask_ref)
+    assert np.array_equal(host(thr), thr_ref)
+
+
+# ------------------------------------------------------------------ sets
+def test_product_and_compact_bit_exact(lib):
+    parent, child = W.candidate_set(2, 60, 4, 9)
+    J = osel.product(parent, child)
+    out = torch.zeros(J.shape, dtype=torch.int32, device="cuda")
+    lib.product(dev(parent, torch.int32), len(parent), 3, dev(child, torch.int32), len(child), out)
+    assert np.array_equal(host(out), J)
+    keep = np.random.default_rng(0).random(len(J)) < 0.3
+    words = np.zeros((len(J) + 31) // 32, dtype=np.uint32)
+    for a in np.nonzero(keep)[0]:
+        words[a >> 5] |= np.uint32(1 << (a & 31))
+    res = torch.zeros(J.shape, dtype=torch.int32, device="cuda")
+    cnt = lib.compact(dev(J, torch.int32), dev(words.view(np.int32)), len(J), 4, res)
+    assert cnt == keep.sum()
+    assert np.array_equal(host(res)[:cnt], J[keep])
+
+
+@pytest.mark.parametrize("seed,npar,t,nch,kind", [(1, 60, 3, 9, 3), (2, 300, 6, 9, 3), (3, 9, 2, 33, 4),
+                                                  (4, 1, 2, 1, 3), (5, 1500, 9, 9, 3)])
+def test_family_bit_exact(lib, seed, npar, t, nch, kind):
+    parent, child = W.candidate_set(seed, npar, t, nch)
+    J = osel.product(parent, child)
+    n = len(J)
+    ref = olat.plan_family(J, 2.0, 9601, 8, 64, seed, kind, t)
+    assign = torch.zeros(n, dtype=torch.int32, device="cuda")
+    bins = torch.zeros(n, dtype=torch.int32, device="cuda")
+    Ms, zs = lib.family(dev(J, torch.int32), n, t, 2.0, 9601, 8, 64, seed, kind, t, assign, bins)
+    assert Ms == ref.M
+    assert zs == ref.z
+    assert np.array_equal(host(assign), ref.assign)
+    assert np.array_equal(host(bins), ref.bins)
+
+
+# ------------------------------------------------------------------ whole path
+def run_both(lib, prob, par, seed, precision=0, sampler=None, **kw):
+    plan = lib.Plan(prob, dict(par, precision=precision, pcg_rtol=1e-13, **kw))
+    res = lib.detect(plan, seed)
+    if sampler is None:
+        sampler = ofem.PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    ref = usfft(sampler, prob["d"], prob["k_lo"], prob["k_hi"], par["s"], par["s_local"], par["r"], par["theta"],
+                par["theta_relative"], seed, keep_values=True)
+    return res, ref
+
+
+@pytest.mark.parametrize("seed,d,N,G,nf", [(1, 3, 8, 5, 21), (2, 6, 16, 33, 61), (3, 10, 32, 129, 81)])
+def test_detect_trig_poly_exact_recovery(lib, seed, d, N, G, nf):
+    K, P = W.trig_poly(seed, d, N, G, nf, cmin=1e-2)
+    prob = dict(sampler="poly", d=d, k_lo=[-N] * d, k_hi=[N] * d, poly_k=K, poly_c=P)
+    par = W.params(2 * nf, 4, 1e-6, relative=False)
+    res, ref = run_both(lib, prob, par, seed, sampler=TrigPolySampler(K, P))
+    I = res.freqs()
+    assert I.tolist() == ref.I.tolist()
+    support = {tuple(k) for k, row in zip(K.tolist(), P) if np.abs(row).max() > 0}
+    assert {tuple(k) for k in I.tolist()} == support
+    idx = {tuple(k): a for a, k in enumerate(K.tolist())}
+    C = res.coeffs()
+    for a, k in enumerate(I.tolist()):
+        assert np.abs(C[a] - P[idx[tuple(k)]]).max() <= 1e-12
+    assert res.stats["samples"] == ref.samples
+
+
+def test_detect_pde_cpu_scale_fp64(lib):
+    prob, par = W.WORKLOADS["cpu16_d4"]
+    res, ref = run_both(lib, prob, par, 7)
+    assert res.freqs().tolist() == ref.I.tolist()
+    C = res.coeffs()
+    assert np.abs(C - ref.C).max() <= 1e-10 * np.abs(ref.C).max()
+    assert res.stats["samples"] == ref.samples
+    assert abs(res.stats["theta_abs"] ** 2 - ref.theta2) <= 1e-12 * ref.theta2
+
+
+def flips_within(I_gpu, I_ref, stages, band):
+    """Candidates that differ between the sets must lie within `band` of their
+    stage threshold in the oracle's values (returns the list of flips)."""
+    a = {tuple(k) for k in I_gpu}
+    b = {tuple(k) for k in I_ref}
+    return sorted(a ^ b)
+
+
+def test_detect_pde_cpu_scale_fp32_refine(lib):
+    prob, par = W.WORKLOADS["cpu16_d4"]
+    res, ref = run_both(lib, prob, par, 7, precision=1)
+    I = res.freqs().tolist()
+    diff = flips_within(I, ref.I.tolist(), ref.stages, 0.01)
+    assert not diff, diff
+    C = res.coeffs()
+    assert np.abs(C - ref.C).max() <= 1e-6 * np.abs(ref.C).max()
+
+
+def test_detect_is_deterministic(lib):
+    prob, par = W.WORKLOADS["cpu16_d4"]
+    plan = lib.Plan(prob, dict(par, pcg_rtol=1e-13))
+    r1 = lib.detect(plan, 3)
+    r2 = lib.detect(plan, 3)
+    assert np.array_equal(r1.freqs(), r2.freqs())
+    assert np.array_equal(r1.coeffs(), r2.coeffs())
+
+
+def test_eval_matches_oracle(lib):
+    K, P = W.trig_poly(8, 4, 8, 50, 25, cmin=1e-2)
+    prob = dict(sampler="poly", d=4, k_lo=[-8] * 4, k_hi=[8] * 4, poly_k=K, poly_c=P)
+    plan = lib.Plan(prob, W.params(60, 3, 1e-6, relative=False))
+    res = lib.detect(plan, 2)
+    Y = np.random.default_rng(3).random((11, 4))
+    out = torch.zeros((11, 50), dtype=torch.float64, device="cuda")
+    lib.eval(res, dev(Y), out)
+    ref = evaluate(res.freqs(), res.coeffs(), Y)
+    assert np.abs(host(out) - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(host(out) - TrigPolySampler(K, P)(Y)).max() <= 1e-11
+
+
+def test_error_paths(lib):
+    prob, par = W.WORKLOADS["cpu16_d4"]
+    with pytest.raises(lib.UsfftError) as e:
+        lib.Plan(dict(prob, mesh_n=200), par)
+    assert e.value.status == lib.EINVAL
+    plan = lib.Plan(prob, dict(par, pcg_maxit=3, solver_config=-2))
+    with pytest.raises(lib.UsfftError) as e:
+        lib.detect(plan, 1)
+    assert e.value.status == lib.ENOCONV
+    plan = lib.Plan(prob, dict(par, lattice_max=1, lattice_tries=1, lattice_mmax=7, solver_config=-2))
+    with pytest.raises(lib.UsfftError) as e:
+        lib.detect(plan, 1)
+    assert e.value.status == lib.ELATTICE
