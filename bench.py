@@ -146,6 +146,7 @@ def main():
         "p99_job_s": pct(lat32, 99),
         "fft_GBps": fft_gbps,
         "pcg_iters_per_solve": iters / max(1, samples),
+        "fp32_vs_fp64_samples_per_s": (value / out["fp64_path"]["samples_per_s"]) if out else None,
         "roofline": {"kernel": "pcg32r (batched float32 Jacobi-PCG + float64 refinement)",
                      "bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS["f32"], "traffic": None,

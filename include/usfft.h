@@ -93,8 +93,10 @@ typedef struct {
   int32_t lattice_mmax;    /* largest lattice size (<= 9601)                 */
   double pcg_rtol;         /* relative residual of every solve (1e-12)       */
   int32_t pcg_maxit;       /* PCG iterations per solve (or inner solve)      */
-  double inner_rtol;       /* FP32_REFINE: inner float32 PCG tolerance (1e-5) */
-  int32_t max_refine;      /* FP32_REFINE: float64 residual corrections (8)  */
+  double inner_rtol;       /* FP32_REFINE: float32 residual drop that triggers
+                              a float64 true-residual replacement (1e-3)    */
+  int32_t refine_every;    /* FP32_REFINE: a float64 true residual at least
+                              every this many iterations (200)              */
   int32_t solver_config;   /* -1: autotune at plan time, -2: built-in choice,
                               >= 0: force that workgroup shape              */
 } usfft_params;

@@ -38,7 +38,7 @@ class _Params(C.Structure):
                 ("theta_relative", C.c_int32), ("tie_rel", C.c_double), ("precision", C.c_int32),
                 ("lattice_c", C.c_double), ("lattice_tries", C.c_int32), ("lattice_max", C.c_int32),
                 ("lattice_mmax", C.c_int32), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32),
-                ("inner_rtol", C.c_double), ("max_refine", C.c_int32), ("solver_config", C.c_int32)]
+                ("inner_rtol", C.c_double), ("refine_every", C.c_int32), ("solver_config", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -124,7 +124,7 @@ def version():
 
 DEFAULT_PARAMS = dict(s=50, s_local=50, r=5, theta=1e-12, theta_relative=False, tie_rel=2.0 ** -30,
                       precision=FP64, lattice_c=2.0, lattice_tries=8, lattice_max=64, lattice_mmax=9601,
-                      pcg_rtol=1e-12, pcg_maxit=4000, inner_rtol=1e-5, max_refine=8, solver_config=-1)
+                      pcg_rtol=1e-12, pcg_maxit=4000, inner_rtol=1e-3, refine_every=200, solver_config=-1)
 
 
 class Plan:

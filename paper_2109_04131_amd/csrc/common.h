@@ -50,6 +50,44 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Cross-lane moves through DPP (data-parallel primitives of GFX9): lanes the
+// row/bank mask disables receive 0.
+template <int CTRL, int ROW = 0xF, int BANK = 0xF>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW, BANK, false));
+}
+template <int CTRL, int ROW = 0xF, int BANK = 0xF>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, ROW, BANK, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW, BANK, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+__device__ __forceinline__ double lane63(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Wave sum in registers: pairs, quads (quad_perm), 8 lanes (row_half_mirror),
+// 16-lane rows (row_mirror), then row_bcast15 / row_bcast31 carry the row
+// sums up so lane 63 holds the total, which is broadcast.  Fixed order, so
+// the result is deterministic.
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T v) {
+  v += dpp_mov<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);       // row_half_mirror
+  v += dpp_mov<0x140>(v);       // row_mirror
+  v += dpp_mov<0x142, 0xA>(v);  // row_bcast15 into rows 1, 3
+  v += dpp_mov<0x143, 0xC>(v);  // row_bcast31 into rows 2, 3
+  return lane63(v);
+}
+__device__ __forceinline__ float wave_sum(float v) { return wave_sum_dpp(v); }
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
+
 // Block-wide sum in a fixed order: every thread returns the same value
 // (wave sums are combined in wave order), so control decisions taken on it
 // are uniform and results do not depend on which block runs a sample.

@@ -20,11 +20,11 @@ struct PdeDev {
 void launch_nodes(int d, int line, int t, int nlat, const int64_t* off, const int32_t* Ms, const int32_t* zs,
                   const double* tail, double* Y, int64_t ns, hipStream_t st);
 int solver_config_count();
-bool solver_config_fits(int c, int G);
+bool solver_config_fits(int c, int n);  // n = mesh_n
 void solver_config_shape(int c, int* block, int* npt);
-int solver_default_config(int G);
+int solver_default_config(int n);
 void launch_pde_solve(int cfg, const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol,
-                      int maxit, double inner_rtol, int max_refine, void* out, int out_fp32, int64_t ld,
+                      int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
                       int64_t col0, int* iters, hipStream_t st);
 void launch_trigpoly(int d, const double* Y, int64_t ns, const int32_t* K, int64_t np, const double* C,
                      int64_t G, void* out, int out_fp32, int64_t ld, int64_t col0, hipStream_t st);

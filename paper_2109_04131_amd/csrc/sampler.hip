@@ -49,6 +49,7 @@ __device__ __forceinline__ double tri_coef(const PdeDev& P, const double* coef, 
   const double* tx = P.tab + (size_t)(q) * P.d * P.n;
   const double* ty = P.tab + (size_t)(2 + q) * P.d * P.n;
   double a = P.a0;
+#pragma unroll 1
   for (int k = 0; k < P.d; ++k) a += coef[k] * tx[k * P.n + ci] * ty[k * P.n + cj];
   return a;
 }
@@ -68,6 +69,31 @@ __device__ __forceinline__ void node_weights(const PdeDev& P, const double* coef
   wS = 0.5 * (aU_ijm + aL_imjm);  // edge (i,j-1)-(i,j)
 }
 
+// Weight of horizontal edge (i,j)-(i+1,j), 0 <= i <= n-1: lower triangle of
+// cell (i,j) and upper triangle of cell (i,j-1).
+__device__ __forceinline__ double edge_h(const PdeDev& P, const double* coef, int i, int j) {
+  return 0.5 * (tri_coef(P, coef, 0, i, j) + tri_coef(P, coef, 1, i, j - 1));
+}
+// Weight of vertical edge (i,j)-(i,j+1), 0 <= j <= n-1: upper triangle of
+// cell (i,j) and lower triangle of cell (i-1,j).
+__device__ __forceinline__ double edge_v(const PdeDev& P, const double* coef, int i, int j) {
+  return 0.5 * (tri_coef(P, coef, 1, i, j) + tri_coef(P, coef, 0, i - 1, j));
+}
+
+// Fill the edge grids of one sample in LDS: eh[j*P1 + i] = edge_h(i, j) for
+// 0 <= i <= n-1, 1 <= j <= n-1 and ev[j*P1 + i] = edge_v(i, j) for
+// 1 <= i <= n-1, 0 <= j <= n-1 (every edge touching an interior node).
+template <typename T>
+__device__ void fill_edges(const PdeDev& P, const double* coef, T* eh, T* ev) {
+  const int n = P.n, P1 = n + 1, cnt = n * (n - 1);
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int i = e % n, j = e / n + 1;  // horizontal: i in [0, n-1], j in [1, n-1]
+    eh[j * P1 + i] = (T)edge_h(P, coef, i, j);
+    const int vi = e / n + 1, vj = e % n;  // vertical: i in [1, n-1], j in [0, n-1]
+    ev[vj * P1 + vi] = (T)edge_v(P, coef, vi, vj);
+  }
+}
+
 __device__ __forceinline__ void load_coef(const PdeDev& P, const double* __restrict__ Y, int64_t s,
                                           double* coef) {
   for (int k = threadIdx.x; k < P.d; k += blockDim.x) coef[k] = P.amp[k] * sinpi(2.0 * Y[s * P.d + k]);
@@ -82,8 +108,10 @@ __device__ __forceinline__ void store_sample(void* out, int out_fp32, int64_t id
 }
 
 // ---------------------------------------------------------------- FP64 PCG
-template <int BLOCK, int NPT>
-__global__ __launch_bounds__(BLOCK) void pcg64_kernel(PdeDev P, const double* __restrict__ Y, int64_t ns,
+// WPE: requested waves per SIMD (0 = compiler's choice); WPE = 2 * BLOCK / 256
+// asks for two resident workgroups per CU.
+template <int BLOCK, int NPT, int WPE, int NC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void pcg64_kernel(PdeDev P, const double* __restrict__ Y, int64_t ns,
                                                       double rtol, int maxit, void* __restrict__ out,
                                                       int out_fp32, int64_t ld, int64_t col0,
                                                       int* __restrict__ iters) {
@@ -92,23 +120,53 @@ __global__ __launch_bounds__(BLOCK) void pcg64_kernel(PdeDev P, const double* __
   __shared__ double red0[2 * (BLOCK / kWave)];
   __shared__ double red1[2 * (BLOCK / kWave)];
   const int64_t s = xcd_remap(blockIdx.x, gridDim.x);
-  const int n = P.n, m = n - 1, G = m * m, P1 = n + 1;
+  const int n = NC > 0 ? NC : P.n, m = n - 1, G = m * m, P1 = n + 1;
   load_coef(P, Y, s, coef);
   for (int e = threadIdx.x; e < P1 * P1; e += BLOCK) sp[e] = 0.0;
   __syncthreads();
 
   double x[NPT], r[NPT], p[NPT], wE[NPT], wW[NPT], wN[NPT], wS[NPT], di[NPT];
   int li[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int g = threadIdx.x + k * BLOCK;
+    li[k] = (g < G) ? (g / m + 1) * P1 + (g % m + 1) : P1 + 1;  // padding slots read in bounds
+  }
+  // edge weights through LDS, one direction at a time (the p buffer holds one grid)
+  {
+    const int cnt = n * (n - 1);
+    for (int e = threadIdx.x; e < cnt; e += BLOCK) {
+      const int i = e % n, j = e / n + 1;
+      sp[j * P1 + i] = edge_h(P, coef, i, j);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      wE[k] = sp[li[k]];
+      wW[k] = sp[li[k] - 1];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt; e += BLOCK) {
+      const int i = e / n + 1, j = e % n;
+      sp[j * P1 + i] = edge_v(P, coef, i, j);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      wN[k] = sp[li[k]];
+      wS[k] = sp[li[k] - P1];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P1 * P1; e += BLOCK) sp[e] = 0.0;
+    __syncthreads();
+  }
   double rz = 0.0, bb = 0.0;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int g = threadIdx.x + k * BLOCK;
     x[k] = 0.0;
     if (g < G) {
-      const int i = g % m + 1, j = g / m + 1;
-      node_weights(P, coef, i, j, wE[k], wW[k], wN[k], wS[k]);
       di[k] = 1.0 / (wE[k] + wW[k] + wN[k] + wS[k]);
-      li[k] = j * P1 + i;
       r[k] = P.h2;
       p[k] = di[k] * r[k];
       rz += r[k] * p[k];
@@ -116,7 +174,6 @@ __global__ __launch_bounds__(BLOCK) void pcg64_kernel(PdeDev P, const double* __
     } else {
       wE[k] = wW[k] = wN[k] = wS[k] = di[k] = 0.0;
       r[k] = p[k] = 0.0;
-      li[k] = P1 + 1;  // any interior slot: keeps the unused neighbour reads in bounds
     }
   }
   block_sum2<BLOCK>(rz, bb, red1);
@@ -168,23 +225,33 @@ __global__ __launch_bounds__(BLOCK) void pcg64_kernel(PdeDev P, const double* __
 }
 
 // ------------------------------------------ FP32 PCG with FP64 refinement
-// Outer loop in float64: r = b - A(y) x with weights recomputed in float64;
-// inner loop: float32 Jacobi-PCG on A d = r / |r| to inner_rtol; x += |r| d.
-template <int BLOCK, int NPT>
-__global__ __launch_bounds__(BLOCK) void pcg32r_kernel(PdeDev P, const double* __restrict__ Y, int64_t ns,
-                                                       double rtol, int maxit, double inner_rtol,
-                                                       int max_refine, void* __restrict__ out,
-                                                       int out_fp32, int64_t ld, int64_t col0,
-                                                       int* __restrict__ iters) {
+
+// One float32 Jacobi-PCG run with "reliable updates" (Sleijpen & van der
+// Vorst 1996): the float64 iterate x lives in LDS, the float32 correction dx
+// accumulated since the last update lives in registers.  Whenever the float32
+// recursive residual has dropped by inner_rtol since the last reference (or
+// every refine_every iterations, a guard against float32 stagnation), x +=
+// dx and the true residual b - A(y) x is formed in float64 (weights
+// recomputed in float64 from the centroid tables, edge-difference form) and
+// replaces the float32 one; the search direction is kept.  The solve stops on
+// the float64 true residual.  Dot products are accumulated in float64.  The
+// float32 state is small enough for two resident samples per CU, which hide
+// each other's barrier and reduction latency.
+// Jacobi scaling of the float32 path: hardware reciprocal (1 ulp), a fixed
+// deterministic diagonal preconditioner; padding slots (zero diagonal) get 0.
+__device__ __forceinline__ float jacobi_rcp(float dg) { return dg > 0.0f ? __builtin_amdgcn_rcpf(dg) : 0.0f; }
+
+template <int BLOCK, int NPT, int WPE, int NC>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void pcg32r_kernel(
+    PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, double inner_rtol, int refine_every,
+    void* __restrict__ out, int out_fp32, int64_t ld, int64_t col0, int* __restrict__ iters) {
   extern __shared__ double lds[];
-  const int n = P.n, m = n - 1, G = m * m, P1 = n + 1;
-  double* sx = lds;                                   // (n+1)^2 float64: x for the residual
-  float* sp = reinterpret_cast<float*>(lds + P1 * P1);  // (n+1)^2 float32: p of the inner loop
+  const int n = NC > 0 ? NC : P.n, m = n - 1, G = m * m, P1 = n + 1;
+  double* sx = lds;                                     // (n+1)^2 float64 iterate x (zero halo)
+  float* sp = reinterpret_cast<float*>(lds + P1 * P1);  // (n+1)^2 float32 search direction
   __shared__ double coef[kMaxD];
   __shared__ double red0[2 * (BLOCK / kWave)];
   __shared__ double red1[2 * (BLOCK / kWave)];
-  __shared__ float fred0[2 * (BLOCK / kWave)];
-  __shared__ float fred1[2 * (BLOCK / kWave)];
   const int64_t s = xcd_remap(blockIdx.x, gridDim.x);
   load_coef(P, Y, s, coef);
   for (int e = threadIdx.x; e < P1 * P1; e += BLOCK) {
@@ -193,131 +260,138 @@ __global__ __launch_bounds__(BLOCK) void pcg32r_kernel(PdeDev P, const double* _
   }
   __syncthreads();
 
-  double x[NPT];
-  float r[NPT], p[NPT], dx[NPT], wE[NPT], wW[NPT], wN[NPT], wS[NPT], di[NPT];
+  float r[NPT], p[NPT], dx[NPT], wE[NPT], wW[NPT], wN[NPT], wS[NPT];
   int li[NPT];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int g = threadIdx.x + k * BLOCK;
-    x[k] = 0.0;
-    if (g < G) {
-      const int i = g % m + 1, j = g / m + 1;
-      double e, w, nn, so;
-      node_weights(P, coef, i, j, e, w, nn, so);
-      wE[k] = (float)e;
-      wW[k] = (float)w;
-      wN[k] = (float)nn;
-      wS[k] = (float)so;
-      di[k] = (float)(1.0 / (e + w + nn + so));
-      li[k] = j * P1 + i;
-    } else {
-      wE[k] = wW[k] = wN[k] = wS[k] = di[k] = 0.0f;
-      li[k] = P1 + 1;  // any interior slot: keeps the unused neighbour reads in bounds
-    }
+    li[k] = (g < G) ? (g / m + 1) * P1 + (g % m + 1) : P1 + 1;  // padding slots read in bounds
   }
-  double bb = 0.0;
-#pragma unroll
-  for (int k = 0; k < NPT; ++k)
-    if (threadIdx.x + k * BLOCK < G) bb += P.h2 * P.h2;
-  bb = block_sum<BLOCK>(bb, red0);
-  const double stop = rtol * rtol * bb;
-  int total = 0;
-  bool conv = false;
-  for (int ref = 0; ref <= max_refine; ++ref) {
-    // float64 residual r = b - A x
-    double r64[NPT];
-    double rr64 = 0.0;
-    if (ref == 0) {
-#pragma unroll
-      for (int k = 0; k < NPT; ++k) {
-        r64[k] = (threadIdx.x + k * BLOCK < G) ? P.h2 : 0.0;
-        rr64 += r64[k] * r64[k];
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < NPT; ++k)
-        if (threadIdx.x + k * BLOCK < G) sx[li[k]] = x[k];
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < NPT; ++k) {
-        const int g = threadIdx.x + k * BLOCK;
-        r64[k] = 0.0;
-        if (g < G) {
-          const int i = g % m + 1, j = g / m + 1, l = li[k];
-          double e, w, nn, so;
-          node_weights(P, coef, i, j, e, w, nn, so);
-          const double ax = (e + w + nn + so) * x[k] -
-                            (e * sx[l + 1] + w * sx[l - 1] + nn * sx[l + P1] + so * sx[l - P1]);
-          r64[k] = P.h2 - ax;
-        }
-        rr64 += r64[k] * r64[k];
-      }
-    }
-    rr64 = block_sum<BLOCK>(rr64, red1);
-    if (rr64 <= stop) {
-      conv = true;
-      break;
-    }
-    if (ref == max_refine) break;
-    // inner float32 PCG on the scaled residual
-    const double rn = sqrt(rr64);
-    const float inv = (float)(1.0 / rn);
-    float rz = 0.0f, rr0 = 0.0f;
+  {
+    // float32 edge grids in the (still unused) float64 iterate region
+    float* eh = reinterpret_cast<float*>(sx);
+    float* ev = eh + P1 * P1;
+    fill_edges<float>(P, coef, eh, ev);
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      r[k] = (float)r64[k] * inv;
-      dx[k] = 0.0f;
-      p[k] = di[k] * r[k];
-      rz += r[k] * p[k];
-      rr0 += r[k] * r[k];
+      wE[k] = eh[li[k]];
+      wW[k] = eh[li[k] - 1];
+      wN[k] = ev[li[k]];
+      wS[k] = ev[li[k] - P1];
     }
-    block_sum2<BLOCK>(rz, rr0, fred1);
-    const float istop = (float)(inner_rtol * inner_rtol) * rr0;
-    int it = 0;
-    while (it < maxit) {
-#pragma unroll
-      for (int k = 0; k < NPT; ++k)
-        if (threadIdx.x + k * BLOCK < G) sp[li[k]] = p[k];
-      __syncthreads();
-      float q[NPT];
-      float pq = 0.0f;
-#pragma unroll
-      for (int k = 0; k < NPT; ++k) {
-        const int l = li[k];
-        q[k] = (wE[k] + wW[k] + wN[k] + wS[k]) * p[k] -
-               (wE[k] * sp[l + 1] + wW[k] * sp[l - 1] + wN[k] * sp[l + P1] + wS[k] * sp[l - P1]);
-        if (threadIdx.x + k * BLOCK >= G) q[k] = 0.0f;
-        pq += p[k] * q[k];
-      }
-      pq = block_sum<BLOCK>(pq, fred0);
-      const float alpha = rz / pq;
-      float rz2 = 0.0f, rr = 0.0f;
-#pragma unroll
-      for (int k = 0; k < NPT; ++k) {
-        dx[k] += alpha * p[k];
-        r[k] -= alpha * q[k];
-        rz2 += r[k] * (di[k] * r[k]);
-        rr += r[k] * r[k];
-      }
-      block_sum2<BLOCK>(rz2, rr, fred1);
-      ++it;
-      if (rr <= istop) break;
-      const float beta = rz2 / rz;
-      rz = rz2;
-#pragma unroll
-      for (int k = 0; k < NPT; ++k) p[k] = di[k] * r[k] + beta * p[k];
-    }
-    total += it;
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) x[k] += rn * (double)dx[k];
-    __syncthreads();  // sx may be rewritten only after every thread left the last residual
+    __syncthreads();
+    for (int e = threadIdx.x; e < P1 * P1; e += BLOCK) sx[e] = 0.0;
+    __syncthreads();
   }
+  double rz = 0.0, rr = 0.0, bb = 0.0;
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int g = threadIdx.x + k * BLOCK;
-    if (g < G) store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, x[k]);
+    dx[k] = 0.0f;
+    if (g < G) {
+      r[k] = (float)P.h2;
+      bb += P.h2 * P.h2;
+    } else {
+      wE[k] = wW[k] = wN[k] = wS[k] = 0.0f;
+      r[k] = 0.0f;
+    }
+    p[k] = r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k]);
+    rz += (double)(r[k] * p[k]);
+    rr += (double)(r[k] * r[k]);
   }
-  if (threadIdx.x == 0 && iters) iters[s] = conv ? total : -1;
+  block_sum2<BLOCK>(rz, rr, red1);
+  bb = block_sum<BLOCK>(bb, red0);
+  const double stop = rtol * rtol * bb;
+  const double drop = inner_rtol * inner_rtol;
+  double rr_ref = rr;  // float32 residual norm^2 right after the last true residual
+  int it = 0, last_update = 0;
+  bool conv = false;
+  while (it < maxit) {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+      if (threadIdx.x + k * BLOCK < G) sp[li[k]] = p[k];
+    __syncthreads();
+    float q[NPT];
+    double pq = 0.0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int l = li[k];
+      q[k] = wE[k] * (p[k] - sp[l + 1]) + wW[k] * (p[k] - sp[l - 1]) + wN[k] * (p[k] - sp[l + P1]) +
+             wS[k] * (p[k] - sp[l - P1]);
+      if (threadIdx.x + k * BLOCK >= G) q[k] = 0.0f;
+      pq += (double)(p[k] * q[k]);
+    }
+    pq = block_sum<BLOCK>(pq, red0);
+    const float alpha = (float)(rz / pq);
+    double rz2 = 0.0;
+    rr = 0.0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      dx[k] += alpha * p[k];
+      r[k] -= alpha * q[k];
+      rz2 += (double)(r[k] * (r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k])));
+      rr += (double)(r[k] * r[k]);
+    }
+    block_sum2<BLOCK>(rz2, rr, red1);
+    ++it;
+    if (rr <= drop * rr_ref || it - last_update >= refine_every) {
+      // x += dx in float64; the float64 true residual replaces the float32 one
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        if (threadIdx.x + k * BLOCK < G) sx[li[k]] += (double)dx[k];
+        dx[k] = 0.0f;
+      }
+      __syncthreads();
+      // plain (not unrolled) pass over the nodes: float64 weights from the
+      // centroid tables, edge-difference form (no cancellation between the
+      // diagonal and neighbour terms), float32 residual staged in sp
+      double rr64 = 0.0, rz3 = 0.0, rr3 = 0.0;
+      for (int g = threadIdx.x; g < G; g += BLOCK) {
+        int i = g % m + 1, j = g / m + 1;
+        // opaque to the optimiser: keeps the weight evaluation inside the loop
+        asm volatile("" : "+v"(i), "+v"(j));
+        const int l = j * P1 + i;
+        double e, w, nn, so;
+        node_weights(P, coef, i, j, e, w, nn, so);
+        const double xc = sx[l];
+        const double ax = e * (xc - sx[l + 1]) + w * (xc - sx[l - 1]) + nn * (xc - sx[l + P1]) +
+                          so * (xc - sx[l - P1]);
+        const double r64 = P.h2 - ax;
+        rr64 += r64 * r64;
+        sp[l] = (float)r64;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        if (threadIdx.x + k * BLOCK < G) {
+          r[k] = sp[li[k]];
+          rz3 += (double)(r[k] * (r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k])));
+          rr3 += (double)(r[k] * r[k]);
+        }
+      }
+      rr64 = block_sum<BLOCK>(rr64, red0);
+      block_sum2<BLOCK>(rz3, rr3, red1);
+      last_update = it;
+      if (rr64 <= stop) {
+        conv = true;
+        break;
+      }
+      rz2 = rz3;
+      rr_ref = rr3;
+    }
+    const float beta = (float)(rz2 / rz);
+    rz = rz2;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) p[k] = r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k]) + beta * p[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int g = threadIdx.x + k * BLOCK;
+    if (g < G) store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, sx[li[k]]);
+  }
+  if (threadIdx.x == 0 && iters) iters[s] = conv ? it : -1;
 }
 
 // ---------------------------------------------------------------- trig poly
@@ -370,39 +444,50 @@ using Pcg32Fn = void (*)(PdeDev, const double*, int64_t, double, int, double, in
                          int64_t, int*);
 
 struct SolverCfg {
-  int block, npt;
+  int block, npt, wpe, nc;  // nc: mesh size compiled in (0 = any)
   Pcg64Fn f64;
   Pcg32Fn f32;
 };
 
-#define USFFT_CFG(B, N) SolverCfg{B, N, pcg64_kernel<B, N>, pcg32r_kernel<B, N>}
+#define USFFT_CFG(B, N, W, NC) SolverCfg{B, N, W, NC, pcg64_kernel<B, N, W, NC>, pcg32r_kernel<B, N, W, NC>}
 static const SolverCfg kSolverCfgs[] = {
-    USFFT_CFG(64, 1),   USFFT_CFG(64, 2),   USFFT_CFG(128, 1),  USFFT_CFG(128, 2),
-    USFFT_CFG(128, 4),  USFFT_CFG(256, 1),  USFFT_CFG(256, 2),  USFFT_CFG(256, 4),
-    USFFT_CFG(256, 8),  USFFT_CFG(256, 16), USFFT_CFG(512, 2),  USFFT_CFG(512, 4),
-    USFFT_CFG(512, 8),  USFFT_CFG(1024, 4), USFFT_CFG(1024, 2),
+    // any mesh size
+    USFFT_CFG(64, 1, 0, 0), USFFT_CFG(64, 2, 0, 0), USFFT_CFG(128, 1, 0, 0), USFFT_CFG(128, 2, 0, 0),
+    USFFT_CFG(128, 4, 0, 0), USFFT_CFG(256, 1, 0, 0), USFFT_CFG(256, 2, 0, 0), USFFT_CFG(256, 4, 0, 0),
+    USFFT_CFG(256, 8, 0, 0), USFFT_CFG(256, 16, 0, 0), USFFT_CFG(512, 2, 0, 0), USFFT_CFG(512, 4, 0, 0),
+    USFFT_CFG(512, 8, 0, 0), USFFT_CFG(1024, 4, 0, 0), USFFT_CFG(1024, 2, 0, 0),
+    // h = 1/64 (G = 3969)
+    USFFT_CFG(512, 8, 0, 64), USFFT_CFG(512, 8, 4, 64), USFFT_CFG(256, 16, 0, 64), USFFT_CFG(256, 16, 2, 64),
+    USFFT_CFG(1024, 4, 0, 64),
+    // h = 1/32 (G = 961)
+    USFFT_CFG(256, 4, 0, 32), USFFT_CFG(128, 8, 0, 32), USFFT_CFG(512, 2, 0, 32), USFFT_CFG(128, 8, 2, 32),
+    // h = 1/16 (G = 225)
+    USFFT_CFG(256, 1, 0, 16), USFFT_CFG(128, 2, 0, 16), USFFT_CFG(64, 4, 0, 16), USFFT_CFG(64, 4, 2, 16),
 };
 #undef USFFT_CFG
 
 int solver_config_count() { return (int)(sizeof(kSolverCfgs) / sizeof(kSolverCfgs[0])); }
 
-bool solver_config_fits(int c, int G) {
+bool solver_config_fits(int c, int n) {
   const SolverCfg& k = kSolverCfgs[c];
+  const int G = (n - 1) * (n - 1);
+  if (k.nc != 0 && k.nc != n) return false;
   const int cap = k.block * k.npt;
   return cap >= G && cap < 2 * G + 2 * k.block && cap <= 4 * G + k.block;
 }
 
 void solver_config_shape(int c, int* block, int* npt) {
   *block = kSolverCfgs[c].block;
-  *npt = kSolverCfgs[c].npt;
+  *npt = kSolverCfgs[c].npt * 100 + kSolverCfgs[c].wpe * 10 + (kSolverCfgs[c].nc ? 1 : 0);
 }
 
-int solver_default_config(int G) {
-  // smallest block whose capacity covers G with at most 8 nodes per thread
+int solver_default_config(int n) {
+  // smallest generic block whose capacity covers G with at most 8 nodes per thread
+  const int G = (n - 1) * (n - 1);
   int best = -1;
   for (int c = 0; c < solver_config_count(); ++c) {
     const SolverCfg& k = kSolverCfgs[c];
-    if (k.block * k.npt < G || k.npt > 8) continue;
+    if (k.block * k.npt < G || k.npt > 8 || k.wpe != 0 || k.nc != 0) continue;
     if (best < 0 || k.block * k.npt < kSolverCfgs[best].block * kSolverCfgs[best].npt ||
         (k.block * k.npt == kSolverCfgs[best].block * kSolverCfgs[best].npt && k.npt > kSolverCfgs[best].npt))
       best = c;
@@ -411,7 +496,7 @@ int solver_default_config(int G) {
 }
 
 void launch_pde_solve(int cfg, const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol,
-                      int maxit, double inner_rtol, int max_refine, void* out, int out_fp32, int64_t ld,
+                      int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
                       int64_t col0, int* iters, hipStream_t st) {
   if (ns <= 0) return;
   const SolverCfg& k = kSolverCfgs[cfg];
@@ -421,7 +506,7 @@ void launch_pde_solve(int cfg, const PdeDev& P, int precision, const double* Y, 
                        maxit, out, out_fp32, ld, col0, iters);
   } else {
     hipLaunchKernelGGL(k.f32, dim3((unsigned)ns), dim3(k.block), P1 * (sizeof(double) + sizeof(float)), st,
-                       P, Y, ns, rtol, maxit, inner_rtol, max_refine, out, out_fp32, ld, col0, iters);
+                       P, Y, ns, rtol, maxit, inner_rtol, refine_every, out, out_fp32, ld, col0, iters);
   }
   USFFT_HIP(hipGetLastError());
 }

@@ -247,7 +247,7 @@ static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
   const usfft_params& par = P->par;
   if (P->prob.sampler == USFFT_SAMPLER_PDE) {
     launch_pde_solve(P->solver_cfg, P->pde, par.precision, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
-                     par.max_refine, U, out_fp32, ld, col0, iters, st);
+                     par.refine_every, U, out_fp32, ld, col0, iters, st);
   } else {
     launch_trigpoly(P->prob.d, Y, ns, P->d_polyk.as<int32_t>(), P->prob.n_poly, P->d_polyc.as<double>(), P->G, U,
                     out_fp32, ld, col0, st);
@@ -560,15 +560,15 @@ static int autotune_solver(usfft_plan_s* P) {
   hipEvent_t a, b;
   USFFT_HIP(hipEventCreate(&a));
   USFFT_HIP(hipEventCreate(&b));
-  int best = solver_default_config((int)G);
+  int best = solver_default_config(n);
   float best_ms = 1e30f;
   for (int c = 0; c < solver_config_count(); ++c) {
-    if (!solver_config_fits(c, (int)G)) continue;
+    if (!solver_config_fits(c, n)) continue;
     launch_pde_solve(c, P->pde, prec, Y.as<double>(), 64, P->par.pcg_rtol, P->par.pcg_maxit, P->par.inner_rtol,
-                     P->par.max_refine, U.p, 0, ns, 0, it.as<int32_t>(), st);
+                     P->par.refine_every, U.p, 0, ns, 0, it.as<int32_t>(), st);
     USFFT_HIP(hipEventRecord(a, st));
     launch_pde_solve(c, P->pde, prec, Y.as<double>(), ns, P->par.pcg_rtol, P->par.pcg_maxit, P->par.inner_rtol,
-                     P->par.max_refine, U.p, 0, ns, 0, it.as<int32_t>(), st);
+                     P->par.refine_every, U.p, 0, ns, 0, it.as<int32_t>(), st);
     USFFT_HIP(hipEventRecord(b, st));
     USFFT_HIP(hipEventSynchronize(b));
     float ms = 0;
@@ -601,7 +601,7 @@ static void validate(const usfft_problem* pb, const usfft_params* par) {
   USFFT_REQUIRE(par->lattice_c > 0 && par->lattice_tries >= 1 && par->lattice_max >= 1 &&
                     par->lattice_mmax >= 3 && par->lattice_mmax <= kMaxLattice,
                 USFFT_EINVAL, "bad lattice parameters (lattice_mmax <= 9601)");
-  USFFT_REQUIRE(par->pcg_rtol > 0 && par->pcg_maxit >= 1 && par->inner_rtol > 0 && par->max_refine >= 0,
+  USFFT_REQUIRE(par->pcg_rtol > 0 && par->pcg_maxit >= 1 && par->inner_rtol > 0 && par->refine_every >= 1,
                 USFFT_EINVAL, "bad solver parameters");
   if (pb->sampler == USFFT_SAMPLER_PDE) {
     USFFT_REQUIRE(pb->mesh_n >= 4 && pb->mesh_n <= kMaxMesh, USFFT_EINVAL, "mesh_n must be in [4, 64]");
@@ -653,13 +653,12 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     P->pde.h2 = h * h;
     P->pde.amp = P->d_amp.as<double>();
     P->pde.tab = P->d_tab.as<double>();
-    const int G = (int)P->G;
     if (par->solver_config >= 0) {
-      USFFT_REQUIRE(par->solver_config < solver_config_count() && solver_config_fits(par->solver_config, G),
+      USFFT_REQUIRE(par->solver_config < solver_config_count() && solver_config_fits(par->solver_config, n),
                     USFFT_EINVAL, "solver_config does not fit this mesh");
       P->solver_cfg = par->solver_config;
     } else if (par->solver_config == -2) {
-      P->solver_cfg = solver_default_config(G);
+      P->solver_cfg = solver_default_config(n);
     } else {
       P->solver_cfg = autotune_solver(P.get());
     }

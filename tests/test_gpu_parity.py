@@ -56,7 +56,8 @@ def test_nodes_line_and_lattice_bit_exact(lib):
     (64, 10, "split", 0, 1e-11), (16, 4, "diagonal", 1, 1e-9), (64, 10, "split", 1, 1e-9)])
 def test_pde_solves_match_banded_cholesky(lib, n, d, modes, prec, tol):
     prob = W.pde_problem(n, d, 4, modes=modes)
-    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-13, solver_config=-2))
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-13 if prec == 0 else 1e-12,
+                               solver_config=-2))
     g = np.random.default_rng(n * 10 + d + prec)
     ns = 37
     Y = g.random((ns, d))
@@ -218,7 +219,7 @@ def test_family_bit_exact(lib, seed, npar, t, nch, kind):
 
 # ------------------------------------------------------------------ whole path
 def run_both(lib, prob, par, seed, precision=0, sampler=None, **kw):
-    plan = lib.Plan(prob, dict(par, precision=precision, pcg_rtol=1e-13, **kw))
+    plan = lib.Plan(prob, dict(par, precision=precision, pcg_rtol=1e-13 if precision == 0 else 1e-12, **kw))
     res = lib.detect(plan, seed)
     if sampler is None:
         sampler = ofem.PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
