@@ -51,6 +51,25 @@ def run_path(U, plan, seed, steps, warmup):
     return wall, lat, stats, n
 
 
+def measured_traffic():
+    """HBM bytes per solver launch from the committed rocprof counter summary,
+    only while the solver source is the one the counters were taken on."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2109_04131_amd", "csrc", "sampler.hip")
+    prof = os.path.join(ROOT, "profiles", "pcg32r_rader_mesh64_d10_hbm_counters.md")
+    try:
+        text = open(prof).read()
+        digest = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+    except OSError:
+        return None
+    m = re.search(r"sha1 prefix `([0-9a-f]+)`", text)
+    t = re.search(r"traffic_bytes_per_launch [^:]*: (\d+)", text)
+    if not m or not t or m.group(1) != digest:
+        return None
+    return float(t.group(1))
+
+
 def cpu_baseline(prob, budget_s):
     """Oracle solves (banded Cholesky, float64) on the host, one thread."""
     import numpy as np
@@ -149,7 +168,8 @@ def main():
         "fp32_vs_fp64_samples_per_s": (value / out["fp64_path"]["samples_per_s"]) if out else None,
         "roofline": {"kernel": "pcg32r (batched float32 Jacobi-PCG + float64 refinement)",
                      "bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS["f32"], "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS["f32"], "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per launch (rocprof FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                      "avg_launch_ms": avg_ms, "launches": launches,
                      "workgroup": [st32[0]["solver_block"], st32[0]["solver_npt"]]},
     }

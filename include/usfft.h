@@ -46,6 +46,7 @@ enum { USFFT_OUT_MAG2 = 0, USFFT_OUT_COMPLEX = 1 };
 
 typedef struct usfft_plan_s* usfft_plan_t;
 typedef struct usfft_result_s* usfft_result_t;
+typedef struct usfft_server_s* usfft_server_t;
 
 /* Problem of Alg. 1 ("Input": Gamma, u, T_G).  All arrays are host memory and
  * are copied by usfft_plan_create.
@@ -232,6 +233,39 @@ usfft_status usfft_family(const int32_t* J_dev, int64_t n, int32_t t, double c, 
                           int32_t tcode, int32_t cap, int32_t* nlat_host, int32_t* M_host,
                           int32_t* z_host, int32_t* assign_dev, int32_t* bins_dev,
                           void* stream);
+
+/* ---- Serving: continuous batching of whole usFFT jobs ----
+ * A server runs up to max_active jobs at once, each on its own worker thread
+ * and non-blocking HIP stream, so the kernels of different jobs overlap on the
+ * device.  Jobs are admitted in arrival order as soon as a slot is free and
+ * their estimated device footprint fits in hbm_budget bytes next to the
+ * running jobs (the estimate, from G, s, the box and the precision, bounds the
+ * sample matrix and candidate magnitudes of the largest stage).  A job's plan
+ * and workspaces are released when it finishes; its result stays with the
+ * server until taken by usfft_server_poll.  Each job's result is the same as
+ * running it alone (all per-sample and per-node arithmetic is independent of
+ * what else runs). */
+typedef struct {
+  int32_t max_active;   /* concurrent jobs (>= 1)                            */
+  uint64_t hbm_budget;  /* bytes the running jobs may occupy (0 = no limit)  */
+} usfft_server_cfg;
+
+usfft_status usfft_server_create(const usfft_server_cfg* cfg, usfft_server_t* out);
+/* Copies problem and params; returns the job id.  Errors: EINVAL (the job
+ * alone exceeds hbm_budget, or invalid problem). */
+usfft_status usfft_server_submit(usfft_server_t srv, const usfft_problem* prob, const usfft_params* par,
+                                 uint64_t seed, uint64_t* job);
+/* Non-blocking (wait = 0) or blocking (wait = 1) completion check.  When the
+ * job has finished: *out receives the result (ownership passes to the caller;
+ * NULL if the job failed), *job_status the job's status, *latency_s the time
+ * from submit to completion and *queue_s the time spent waiting for
+ * admission; the call returns USFFT_OK.  When still pending (wait = 0) *out
+ * is set to NULL and the call returns USFFT_OK with *job_status = 1. */
+usfft_status usfft_server_poll(usfft_server_t srv, uint64_t job, int32_t wait, usfft_result_t* out,
+                               int32_t* job_status, double* latency_s, double* queue_s);
+/* Waits for every submitted job, then stops the workers; untaken results are
+ * destroyed. */
+void usfft_server_destroy(usfft_server_t srv);
 
 #ifdef __cplusplus
 }

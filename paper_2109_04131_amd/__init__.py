@@ -76,6 +76,11 @@ _sigs = {
     "usfft_select": (C.c_int, [_vp, C.c_int64, C.c_int64, C.c_int64, C.c_int32, _vp, C.c_double, _vp, _vp, _vp]),
     "usfft_product": (C.c_int, [_vp, C.c_int64, C.c_int32, _vp, C.c_int64, _vp, _vp]),
     "usfft_compact": (C.c_int, [_vp, _vp, C.c_int64, C.c_int32, _vp, C.POINTER(C.c_int64), _vp]),
+    "usfft_server_create": (C.c_int, [_vp, C.POINTER(_vp)]),
+    "usfft_server_submit": (C.c_int, [_vp, _vp, _vp, C.c_uint64, C.POINTER(C.c_uint64)]),
+    "usfft_server_poll": (C.c_int, [_vp, C.c_uint64, C.c_int32, C.POINTER(_vp), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "usfft_server_destroy": (None, [_vp]),
     "usfft_family": (C.c_int, [_vp, C.c_int64, C.c_int32, C.c_double, C.c_int32, C.c_int32, C.c_int32,
                                C.c_uint64, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
 }
@@ -127,41 +132,47 @@ DEFAULT_PARAMS = dict(s=50, s_local=50, r=5, theta=1e-12, theta_relative=False, 
                       pcg_rtol=1e-12, pcg_maxit=4000, inner_rtol=1e-3, refine_every=200, solver_config=-1)
 
 
+def _marshal(problem, params):
+    """Problem and params structures plus the numpy arrays they point into."""
+    p = dict(DEFAULT_PARAMS)
+    p.update({k: v for k, v in params.items() if k in DEFAULT_PARAMS})
+    keep = []
+
+    def arr(v, dt):
+        a = np.ascontiguousarray(np.asarray(v, dtype=dt))
+        keep.append(a)
+        return a.ctypes.data_as(_P32 if dt == np.int32 else _PD)
+
+    pr = _Problem()
+    pr.d = int(problem["d"])
+    pr.k_lo = arr(problem["k_lo"], np.int32)
+    pr.k_hi = arr(problem["k_hi"], np.int32)
+    if problem.get("sampler", "pde") == "pde":
+        pr.sampler = SAMPLER_PDE
+        pr.mesh_n = int(problem["mesh_n"])
+        pr.a0 = float(problem.get("a0", 1.0))
+        pr.amp = arr(problem["amp"], np.float64)
+        pr.mode1 = arr(problem["mode1"], np.int32)
+        pr.mode2 = arr(problem["mode2"], np.int32)
+    else:
+        pr.sampler = SAMPLER_TRIG_POLY
+        K = np.asarray(problem["poly_k"])
+        P = np.asarray(problem["poly_c"], dtype=np.complex128)
+        pr.n_poly, pr.G_poly = P.shape
+        pr.poly_k = arr(K, np.int32)
+        pr.poly_c = arr(np.stack([P.real, P.imag], -1), np.float64)
+    pa = _Params()
+    for k in DEFAULT_PARAMS:
+        setattr(pa, k, type(DEFAULT_PARAMS[k])(p[k]) if not isinstance(DEFAULT_PARAMS[k], bool) else int(p[k]))
+    return pr, pa, keep, p
+
+
 class Plan:
     """usfft_plan_create / usfft_plan_destroy."""
 
     def __init__(self, problem, params):
-        p = dict(DEFAULT_PARAMS)
-        p.update({k: v for k, v in params.items() if k in DEFAULT_PARAMS})
-        self.d = int(problem["d"])
-        keep = []
-
-        def arr(v, dt):
-            a = np.ascontiguousarray(np.asarray(v, dtype=dt))
-            keep.append(a)
-            return a.ctypes.data_as(_P32 if dt == np.int32 else _PD)
-
-        pr = _Problem()
-        pr.d = self.d
-        pr.k_lo = arr(problem["k_lo"], np.int32)
-        pr.k_hi = arr(problem["k_hi"], np.int32)
-        if problem.get("sampler", "pde") == "pde":
-            pr.sampler = SAMPLER_PDE
-            pr.mesh_n = int(problem["mesh_n"])
-            pr.a0 = float(problem.get("a0", 1.0))
-            pr.amp = arr(problem["amp"], np.float64)
-            pr.mode1 = arr(problem["mode1"], np.int32)
-            pr.mode2 = arr(problem["mode2"], np.int32)
-        else:
-            pr.sampler = SAMPLER_TRIG_POLY
-            K = np.asarray(problem["poly_k"])
-            P = np.asarray(problem["poly_c"], dtype=np.complex128)
-            pr.n_poly, pr.G_poly = P.shape
-            pr.poly_k = arr(K, np.int32)
-            pr.poly_c = arr(np.stack([P.real, P.imag], -1), np.float64)
-        pa = _Params()
-        for k in DEFAULT_PARAMS:
-            setattr(pa, k, type(DEFAULT_PARAMS[k])(p[k]) if not isinstance(DEFAULT_PARAMS[k], bool) else int(p[k]))
+        pr, pa, keep, p = _marshal(problem, params)
+        self.d = pr.d
         h = _vp()
         _check(_lib.usfft_plan_create(C.byref(pr), C.byref(pa), C.byref(h)))
         self.handle = h
@@ -171,6 +182,46 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.usfft_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+class _ServerCfg(C.Structure):
+    _fields_ = [("max_active", C.c_int32), ("hbm_budget", C.c_uint64)]
+
+
+class Server:
+    """usfft_server_*: continuous batching of whole jobs on worker streams."""
+
+    def __init__(self, max_active=4, hbm_budget=0):
+        cfg = _ServerCfg(max_active, hbm_budget)
+        h = _vp()
+        _check(_lib.usfft_server_create(C.byref(cfg), C.byref(h)))
+        self.handle = h
+
+    def submit(self, problem, params, seed):
+        pr, pa, keep, _ = _marshal(problem, params)
+        job = C.c_uint64()
+        _check(_lib.usfft_server_submit(self.handle, C.byref(pr), C.byref(pa), C.c_uint64(seed), C.byref(job)))
+        return job.value
+
+    def poll(self, job, wait=False):
+        """(Result or None, status, latency_s, queue_s); status 1 = pending."""
+        h = _vp()
+        st = C.c_int32()
+        lat = C.c_double()
+        q = C.c_double()
+        _check(_lib.usfft_server_poll(self.handle, C.c_uint64(job), int(wait), C.byref(h), C.byref(st),
+                                      C.byref(lat), C.byref(q)))
+        res = Result(h) if h.value else None
+        err = _lib.usfft_last_error().decode() if st.value not in (OK, 1) else ""
+        return res, st.value, lat.value, q.value, err
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.usfft_server_destroy(self.handle)
         self.handle = None
 
     def __del__(self):

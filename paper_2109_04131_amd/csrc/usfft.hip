@@ -8,10 +8,13 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -894,6 +897,206 @@ usfft_status usfft_family(const int32_t* J_dev, int64_t n, int32_t t, double c, 
     for (size_t l = 0; l < F.M.size(); ++l) M_host[l] = F.M[l];
     std::memcpy(z_host, F.z.data(), sizeof(int32_t) * F.z.size());
   });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- serving
+namespace usfft {
+
+// Owning copy of a problem + params (the caller's arrays may go away).
+struct JobSpec {
+  usfft_problem prob{};
+  usfft_params par{};
+  std::vector<int32_t> k_lo, k_hi, mode1, mode2, poly_k;
+  std::vector<double> amp, poly_c;
+  void copy(const usfft_problem* pb, const usfft_params* pa) {
+    validate(pb, pa);
+    prob = *pb;
+    par = *pa;
+    const int d = pb->d;
+    k_lo.assign(pb->k_lo, pb->k_lo + d);
+    k_hi.assign(pb->k_hi, pb->k_hi + d);
+    prob.k_lo = k_lo.data();
+    prob.k_hi = k_hi.data();
+    if (pb->sampler == USFFT_SAMPLER_PDE) {
+      amp.assign(pb->amp, pb->amp + d);
+      mode1.assign(pb->mode1, pb->mode1 + d);
+      mode2.assign(pb->mode2, pb->mode2 + d);
+      prob.amp = amp.data();
+      prob.mode1 = mode1.data();
+      prob.mode2 = mode2.data();
+    } else {
+      poly_k.assign(pb->poly_k, pb->poly_k + (size_t)pb->n_poly * d);
+      poly_c.assign(pb->poly_c, pb->poly_c + (size_t)pb->n_poly * pb->G_poly * 2);
+      prob.poly_k = poly_k.data();
+      prob.poly_c = poly_c.data();
+    }
+  }
+};
+
+// Admission estimate of a job's device footprint (bytes): the largest stage
+// holds the sample matrix (G x samples) and the candidate magnitudes
+// (G x |J|).  |J| <= |I^(1..t-1)| |I^(t)| is bounded by 3 s_local (detected
+// sets grow to a few times s, Remark 4.1) times min(K_t, 17) (1-D projections
+// stay small, Sec. 4.2); a lattice family takes about 12 |J| samples.
+static uint64_t estimate_footprint(const usfft_problem* pb, const usfft_params* pa) {
+  const uint64_t G = pb->sampler == USFFT_SAMPLER_PDE ? (uint64_t)(pb->mesh_n - 1) * (pb->mesh_n - 1)
+                                                      : (uint64_t)pb->G_poly;
+  const uint64_t ub = pa->precision == USFFT_FP32_REFINE ? 4 : 8;
+  int kmax = 1;
+  for (int j = 0; j < pb->d; ++j) kmax = std::max(kmax, pb->k_hi[j] - pb->k_lo[j] + 1);
+  const uint64_t J = 3ull * (uint64_t)pa->s_local * (uint64_t)std::min(kmax, 17);
+  const uint64_t samples = std::min<uint64_t>(12 * J, 64ull * (uint64_t)pa->lattice_mmax) + (uint64_t)kmax;
+  return G * samples * ub + G * J * 8 + samples * (uint64_t)pb->d * 8 + (64ull << 20);
+}
+
+struct Job {
+  uint64_t id = 0;
+  JobSpec spec;
+  uint64_t seed = 0;
+  uint64_t footprint = 0;
+  int state = 0;  // 0 queued, 1 running, 2 done
+  usfft_status st = USFFT_OK;
+  std::string err;
+  usfft_result_s* res = nullptr;
+  std::chrono::steady_clock::time_point t_submit, t_start, t_done;
+  ~Job() { delete res; }
+};
+
+}  // namespace usfft
+
+struct usfft_server_s {
+  usfft_server_cfg cfg{};
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<usfft::Job*> queue;
+  std::map<uint64_t, std::unique_ptr<usfft::Job>> jobs;
+  uint64_t in_use = 0, next_id = 1;
+  int active = 0;
+  bool stop = false;
+  std::vector<std::thread> workers;
+};
+
+namespace usfft {
+
+static void server_worker(usfft_server_s* S) {
+  hipStream_t st = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    S->cv_work.wait(lk, [&] {
+      if (S->stop && S->queue.empty()) return true;
+      if (S->queue.empty() || S->active >= S->cfg.max_active) return false;
+      const uint64_t fp = S->queue.front()->footprint;
+      return S->cfg.hbm_budget == 0 || S->active == 0 || S->in_use + fp <= S->cfg.hbm_budget;
+    });
+    if (S->queue.empty()) break;
+    Job* J = S->queue.front();
+    S->queue.pop_front();
+    S->active++;
+    S->in_use += J->footprint;
+    J->state = 1;
+    J->t_start = std::chrono::steady_clock::now();
+    lk.unlock();
+    usfft_status status = USFFT_OK;
+    std::string err;
+    std::unique_ptr<usfft_result_s> R(new usfft_result_s());
+    try {
+      USFFT_REQUIRE(st != nullptr, USFFT_EHIP, "worker stream creation failed");
+      std::unique_ptr<usfft_plan_s> P(plan_create(&J->spec.prob, &J->spec.par));
+      std::lock_guard<std::mutex> pl(P->mu);
+      detect(P.get(), J->seed, st, R.get());
+    } catch (const Error& e) {
+      status = e.st;
+      err = e.msg;
+    } catch (const std::exception& e) {
+      status = USFFT_EINVAL;
+      err = e.what();
+    }
+    lk.lock();
+    J->st = status;
+    J->err = err;
+    J->res = status == USFFT_OK ? R.release() : nullptr;
+    J->t_done = std::chrono::steady_clock::now();
+    J->state = 2;
+    S->active--;
+    S->in_use -= J->footprint;
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+  }
+  lk.unlock();
+  if (st) (void)hipStreamDestroy(st);
+}
+
+}  // namespace usfft
+
+extern "C" {
+
+usfft_status usfft_server_create(const usfft_server_cfg* cfg, usfft_server_t* out) {
+  return guarded([&] {
+    USFFT_REQUIRE(cfg && out && cfg->max_active >= 1 && cfg->max_active <= 64, USFFT_EINVAL,
+                  "max_active must be in [1, 64]");
+    std::unique_ptr<usfft_server_s> S(new usfft_server_s());
+    S->cfg = *cfg;
+    for (int i = 0; i < cfg->max_active; ++i) S->workers.emplace_back(server_worker, S.get());
+    *out = S.release();
+  });
+}
+
+usfft_status usfft_server_submit(usfft_server_t srv, const usfft_problem* prob, const usfft_params* par,
+                                 uint64_t seed, uint64_t* job) {
+  return guarded([&] {
+    USFFT_REQUIRE(srv && job, USFFT_EINVAL, "null server or job");
+    std::unique_ptr<Job> J(new Job());
+    J->spec.copy(prob, par);
+    J->seed = seed;
+    J->footprint = estimate_footprint(&J->spec.prob, &J->spec.par);
+    USFFT_REQUIRE(srv->cfg.hbm_budget == 0 || J->footprint <= srv->cfg.hbm_budget, USFFT_EINVAL,
+                  "job footprint " + std::to_string(J->footprint) + " B exceeds the server's HBM budget");
+    J->t_submit = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    J->id = srv->next_id++;
+    *job = J->id;
+    srv->queue.push_back(J.get());
+    srv->jobs[J->id] = std::move(J);
+    srv->cv_work.notify_all();
+  });
+}
+
+usfft_status usfft_server_poll(usfft_server_t srv, uint64_t job, int32_t wait, usfft_result_t* out,
+                               int32_t* job_status, double* latency_s, double* queue_s) {
+  return guarded([&] {
+    USFFT_REQUIRE(srv && out, USFFT_EINVAL, "null server or output");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->jobs.find(job);
+    USFFT_REQUIRE(it != srv->jobs.end(), USFFT_EINVAL, "unknown or already taken job id");
+    Job* J = it->second.get();
+    if (wait) srv->cv_done.wait(lk, [&] { return J->state == 2; });
+    if (J->state != 2) {
+      *out = nullptr;
+      if (job_status) *job_status = 1;
+      return;
+    }
+    *out = J->res;
+    J->res = nullptr;
+    if (job_status) *job_status = J->st;
+    if (latency_s) *latency_s = std::chrono::duration<double>(J->t_done - J->t_submit).count();
+    if (queue_s) *queue_s = std::chrono::duration<double>(J->t_start - J->t_submit).count();
+    if (J->st != USFFT_OK) set_error(J->err);
+    srv->jobs.erase(it);
+  });
+}
+
+void usfft_server_destroy(usfft_server_t srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+    srv->cv_work.notify_all();
+  }
+  for (auto& t : srv->workers) t.join();
+  delete srv;
 }
 
 }  // extern "C"
