@@ -6,6 +6,8 @@ namespace usfft {
 
 constexpr int kMaxD = 64;          // largest parameter dimension d
 constexpr int kMaxMesh = 64;       // largest mesh_n of the on-chip solver
+constexpr int kMaxMeshStream = 512;  // largest mesh_n of the streaming solver
+constexpr int kStreamBlocks = 512;   // persistent workgroups of the streaming solver
 constexpr int kMaxLattice = 9601;  // largest lattice size (L = M-1 complex values in LDS)
 
 // PDE sampler tables on the device (see sampler.hip).
@@ -26,6 +28,10 @@ int solver_default_config(int n);
 void launch_pde_solve(int cfg, const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol,
                       int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
                       int64_t col0, int* iters, hipStream_t st);
+int64_t stream_workspace_doubles(int n, int blocks);
+void launch_pde_solve_stream(const PdeDev& P, const double* Y, int64_t ns, double rtol, int maxit, void* out,
+                             int out_fp32, int64_t ld, int64_t col0, int* iters, double* ws, int blocks,
+                             hipStream_t st);
 void launch_trigpoly(int d, const double* Y, int64_t ns, const int32_t* K, int64_t np, const double* C,
                      int64_t G, void* out, int out_fp32, int64_t ld, int64_t col0, hipStream_t st);
 

@@ -394,6 +394,111 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE > 0 ?
   if (threadIdx.x == 0 && iters) iters[s] = conv ? it : -1;
 }
 
+// ------------------------------------------ streaming FP64 PCG (large meshes)
+// For meshes whose per-sample state exceeds one CU (h < 1/64): persistent
+// workgroups, each owning a workspace in global memory (iterate, residual,
+// search direction with zero halo, A p, edge grids, Jacobi scaling), loop over
+// samples s = blockIdx.x + k gridDim.x.  Same Jacobi-PCG and fixed-order
+// reductions as the on-chip kernels; bound by L2 / Infinity Cache / HBM
+// traffic, not by ALU.
+constexpr int kStreamBlock = 1024;
+constexpr int kStreamArrays = 7;
+
+__global__ __launch_bounds__(kStreamBlock) void pcg_stream_kernel(PdeDev P, const double* __restrict__ Y,
+                                                                  int64_t ns, double rtol, int maxit,
+                                                                  void* __restrict__ out, int out_fp32,
+                                                                  int64_t ld, int64_t col0,
+                                                                  int* __restrict__ iters,
+                                                                  double* __restrict__ ws, int64_t gp) {
+  __shared__ double coef[kMaxD];
+  __shared__ double red0[2 * (kStreamBlock / kWave)];
+  __shared__ double red1[2 * (kStreamBlock / kWave)];
+  const int n = P.n, m = n - 1, G = m * m, P1 = n + 1;
+  double* x = ws + (size_t)blockIdx.x * kStreamArrays * gp;
+  double* r = x + gp;
+  double* p = r + gp;   // (n+1)^2 grid, zero halo
+  double* q = p + gp;
+  double* eh = q + gp;  // (n+1)^2 horizontal edge grid
+  double* ev = eh + gp; // (n+1)^2 vertical edge grid
+  double* di = ev + gp;
+  for (int64_t s = blockIdx.x; s < ns; s += gridDim.x) {
+    __syncthreads();  // previous sample finished with coef and the workspace
+    load_coef(P, Y, s, coef);
+    for (int e = threadIdx.x; e < P1 * P1; e += kStreamBlock) p[e] = 0.0;
+    __syncthreads();
+    fill_edges<double>(P, coef, eh, ev);
+    __syncthreads();
+    double rz = 0.0, bb = 0.0;
+    for (int g = threadIdx.x; g < G; g += kStreamBlock) {
+      const int l = (g / m + 1) * P1 + (g % m + 1);
+      const double dinv = 1.0 / (eh[l] + eh[l - 1] + ev[l] + ev[l - P1]);
+      di[g] = dinv;
+      x[g] = 0.0;
+      r[g] = P.h2;
+      p[l] = dinv * P.h2;
+      rz += P.h2 * dinv * P.h2;
+      bb += P.h2 * P.h2;
+    }
+    block_sum2<kStreamBlock>(rz, bb, red1);
+    const double stop = rtol * rtol * bb;
+    int it = 0;
+    bool conv = false;
+    while (it < maxit) {
+      double pq = 0.0;
+      for (int g = threadIdx.x; g < G; g += kStreamBlock) {
+        const int l = (g / m + 1) * P1 + (g % m + 1);
+        const double pc = p[l];
+        const double qq = eh[l] * (pc - p[l + 1]) + eh[l - 1] * (pc - p[l - 1]) + ev[l] * (pc - p[l + P1]) +
+                          ev[l - P1] * (pc - p[l - P1]);
+        q[g] = qq;
+        pq += pc * qq;
+      }
+      pq = block_sum<kStreamBlock>(pq, red0);
+      const double alpha = rz / pq;
+      double rz2 = 0.0, rr = 0.0;
+      for (int g = threadIdx.x; g < G; g += kStreamBlock) {
+        const int l = (g / m + 1) * P1 + (g % m + 1);
+        x[g] += alpha * p[l];
+        const double rg = r[g] - alpha * q[g];
+        r[g] = rg;
+        rz2 += rg * (di[g] * rg);
+        rr += rg * rg;
+      }
+      block_sum2<kStreamBlock>(rz2, rr, red1);
+      ++it;
+      if (rr <= stop) {
+        conv = true;
+        break;
+      }
+      const double beta = rz2 / rz;
+      rz = rz2;
+      for (int g = threadIdx.x; g < G; g += kStreamBlock) {
+        const int l = (g / m + 1) * P1 + (g % m + 1);
+        p[l] = di[g] * r[g] + beta * p[l];
+      }
+      __syncthreads();
+    }
+    for (int g = threadIdx.x; g < G; g += kStreamBlock) store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, x[g]);
+    if (threadIdx.x == 0 && iters) iters[s] = conv ? it : -1;
+  }
+}
+
+int64_t stream_workspace_doubles(int n, int blocks) {
+  const int64_t gp = ((int64_t)(n + 1) * (n + 1) + 63) / 64 * 64;
+  return gp * kStreamArrays * blocks;
+}
+
+void launch_pde_solve_stream(const PdeDev& P, const double* Y, int64_t ns, double rtol, int maxit, void* out,
+                             int out_fp32, int64_t ld, int64_t col0, int* iters, double* ws, int blocks,
+                             hipStream_t st) {
+  if (ns <= 0) return;
+  const int64_t gp = ((int64_t)(P.n + 1) * (P.n + 1) + 63) / 64 * 64;
+  const unsigned grid = (unsigned)std::min<int64_t>(blocks, ns);
+  hipLaunchKernelGGL(pcg_stream_kernel, dim3(grid), dim3(kStreamBlock), 0, st, P, Y, ns, rtol, maxit, out,
+                     out_fp32, ld, col0, iters, ws, gp);
+  USFFT_HIP(hipGetLastError());
+}
+
 // ---------------------------------------------------------------- trig poly
 // u_g(y) = Re sum_a c[a,g] exp(2 pi i k_a . y); phases of one sample staged in LDS.
 constexpr int kPolyChunk = 1024;

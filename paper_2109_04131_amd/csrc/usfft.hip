@@ -116,7 +116,8 @@ struct usfft_plan_s {
   int64_t G = 0;
   int solver_cfg = 0;
   // static device tables
-  usfft::DevBuf d_amp, d_tab, d_polyk, d_polyc;
+  usfft::DevBuf d_amp, d_tab, d_polyk, d_polyc, d_stream;
+  bool streaming = false;  // mesh larger than the on-chip solver holds
   usfft::PdeDev pde{};
   // Rader tables per lattice size
   std::map<int, usfft::RaderTables> rader;
@@ -248,7 +249,10 @@ static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
                         int64_t col0, int32_t* iters, hipStream_t st) {
   if (ns <= 0) return;
   const usfft_params& par = P->par;
-  if (P->prob.sampler == USFFT_SAMPLER_PDE) {
+  if (P->prob.sampler == USFFT_SAMPLER_PDE && P->streaming) {
+    launch_pde_solve_stream(P->pde, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
+                            P->d_stream.as<double>(), kStreamBlocks, st);
+  } else if (P->prob.sampler == USFFT_SAMPLER_PDE) {
     launch_pde_solve(P->solver_cfg, P->pde, par.precision, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
                      par.refine_every, U, out_fp32, ld, col0, iters, st);
   } else {
@@ -526,7 +530,7 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
   }
   USFFT_HIP(hipStreamSynchronize(st));
   S.samples = S.samples_step1 + S.samples_step2 + S.samples_step3;
-  if (pb.sampler == USFFT_SAMPLER_PDE) {
+  if (pb.sampler == USFFT_SAMPLER_PDE && !P->streaming) {
     int blk = 0, npt = 0;
     solver_config_shape(P->solver_cfg, &blk, &npt);
     S.solver_block = blk;
@@ -607,7 +611,7 @@ static void validate(const usfft_problem* pb, const usfft_params* par) {
   USFFT_REQUIRE(par->pcg_rtol > 0 && par->pcg_maxit >= 1 && par->inner_rtol > 0 && par->refine_every >= 1,
                 USFFT_EINVAL, "bad solver parameters");
   if (pb->sampler == USFFT_SAMPLER_PDE) {
-    USFFT_REQUIRE(pb->mesh_n >= 4 && pb->mesh_n <= kMaxMesh, USFFT_EINVAL, "mesh_n must be in [4, 64]");
+    USFFT_REQUIRE(pb->mesh_n >= 4 && pb->mesh_n <= kMaxMeshStream, USFFT_EINVAL, "mesh_n must be in [4, 512]");
     USFFT_REQUIRE(pb->amp && pb->mode1 && pb->mode2, USFFT_EINVAL, "missing coefficient family");
   } else {
     USFFT_REQUIRE(pb->sampler == USFFT_SAMPLER_TRIG_POLY, USFFT_EINVAL, "unknown sampler");
@@ -656,7 +660,12 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     P->pde.h2 = h * h;
     P->pde.amp = P->d_amp.as<double>();
     P->pde.tab = P->d_tab.as<double>();
-    if (par->solver_config >= 0) {
+    if (n > kMaxMesh) {
+      // per-sample state exceeds one CU: streaming float64 solver
+      P->streaming = true;
+      P->solver_cfg = -1;
+      P->d_stream.ensure(sizeof(double) * (size_t)stream_workspace_doubles(n, kStreamBlocks));
+    } else if (par->solver_config >= 0) {
       USFFT_REQUIRE(par->solver_config < solver_config_count() && solver_config_fits(par->solver_config, n),
                     USFFT_EINVAL, "solver_config does not fit this mesh");
       P->solver_cfg = par->solver_config;
@@ -665,7 +674,7 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     } else {
       P->solver_cfg = autotune_solver(P.get());
     }
-    USFFT_REQUIRE(P->solver_cfg >= 0, USFFT_EINVAL, "no solver shape for this mesh");
+    USFFT_REQUIRE(P->streaming || P->solver_cfg >= 0, USFFT_EINVAL, "no solver shape for this mesh");
   } else {
     P->G = pb->G_poly;
     P->poly_k.assign(pb->poly_k, pb->poly_k + (size_t)pb->n_poly * d);

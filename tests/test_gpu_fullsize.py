@@ -1,0 +1,110 @@
+"""Stage parity at the workloads' full sizes, in the launch configuration of
+the benchmark, on outputs the oracle can compute one by one (sampled solves,
+sampled columns), plus the largest meshes of the streaming solver."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dft as odft
+from oracle import fem as ofem
+from oracle import rng as orng
+from oracle import select as osel
+from oracle.usfft import tail as otail
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t.to(dtype) if dtype is not None else t).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,prec,tol,check", [("mesh64_d10", 0, 1e-11, 4), ("mesh64_d10", 1, 1e-9, 4),
+                                                 ("mesh128_d20", 0, 1e-11, 2)])
+def test_first_detection_stage_full_size(lib, name, prec, tol, check):
+    """Alg. 1 stage (t=1, i=1) at full size: nodes, solves, length-K DFT and
+    selection through the ABI vs the oracle (solves sampled; DFT and selection
+    on the oracle's own samples for sampled nodes)."""
+    prob, par = W.WORKLOADS[name]
+    d = prob["d"]
+    K = prob["k_hi"][0] - prob["k_lo"][0] + 1
+    plan = lib.Plan(prob, dict(par, precision=prec, pcg_rtol=1e-13 if prec == 0 else 1e-12))
+    G = plan.G
+    tail = otail(7, orng.KIND_TAIL1, 1, 1, d)
+    y = torch.zeros((K, d), dtype=torch.float64, device="cuda")
+    lib.nodes(d, 0, 1, [K], None, tail, y)
+    Yo = np.tile(tail, (K, 1))
+    Yo[:, 0] = np.arange(K) / K
+    assert np.array_equal(host(y), Yo)
+    ld = (K + 63) // 64 * 64
+    U = torch.zeros((G, ld), dtype=torch.float64, device="cuda")
+    it = torch.zeros(K, dtype=torch.int32, device="cuda")
+    lib.sample(plan, y, U, 0, ld, 0, it)
+    assert (host(it) > 0).all()
+    S = ofem.PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    Ug = host(U)[:, :K]
+    picks = np.linspace(0, K - 1, check).astype(int)
+    for l in picks:
+        ref = S.solve_one(Yo[l])
+        assert np.linalg.norm(Ug[:, l] - ref) / np.linalg.norm(ref) <= tol
+    ks = np.arange(prob["k_lo"][0], prob["k_hi"][0] + 1)
+    V = torch.zeros((G, K), dtype=torch.float64, device="cuda")
+    lib.line_dft(U, 0, G, ld, 0, K, ks, lib.OUT_MAG2, V, K)
+    Vg = host(V)
+    # the DFT stage on the GPU's samples vs the oracle's DFT of the same samples
+    cols = np.linspace(0, G - 1, 9).astype(int)
+    ref = np.abs(odft.dft_bins(Ug[cols].T, ks % K)) ** 2  # (K, ncols)
+    assert np.abs(Vg[cols].T - ref).max() <= 1e-13 * ref.max()
+    # selection on the GPU magnitudes vs the oracle's rule on the same values
+    theta2 = np.array([par["theta"] ** 2 * Vg.max()])
+    mask = torch.zeros((K + 31) // 32 + 1, dtype=torch.int32, device="cuda")
+    thr = torch.zeros(G, dtype=torch.float64, device="cuda")
+    lib.select(V, G, K, K, par["s_local"], dev(theta2), osel.TIE_REL, mask, thr)
+    m_ref, thr_ref, _ = osel.detect_mask(Vg.T, par["s_local"], theta2[0])
+    m = host(mask).view(np.uint32)
+    bits = np.array([(m[a >> 5] >> (a & 31)) & 1 for a in range(K)], dtype=bool)
+    assert np.array_equal(bits, m_ref)
+    assert np.array_equal(host(thr), thr_ref)
+
+
+@pytest.mark.parametrize("G,M,fp32", [(3969, 9601, 0), (3969, 9601, 1), (16129, 4801, 1), (16129, 9601, 0)])
+def test_lattice_dft_full_size(lib, G, M, fp32):
+    """Lattice DFT at the full node counts and the largest lattice size; the
+    oracle checks sampled nodes (all requested bins)."""
+    g = np.random.default_rng(G + M)
+    Uf = (0.05 + 1e-3 * g.standard_normal((G, M))).astype(np.float32 if fp32 else np.float64)
+    nb = min(2000, M)
+    bins = np.sort(g.choice(M, size=nb, replace=False)).astype(np.int32)
+    pos = np.arange(nb, dtype=np.int32)
+    V = torch.zeros((G, nb), dtype=torch.float64, device="cuda")
+    lib.lattice_dft(dev(Uf), fp32, G, M, 0, M, dev(bins), dev(pos), lib.OUT_MAG2, V, nb)
+    Vg = host(V)
+    cols = np.concatenate([np.arange(3), g.choice(G, 5, replace=False), [G - 1]])
+    ref = np.abs(odft.dft_bins(Uf[cols].astype(np.float64).T, bins)) ** 2
+    # tolerances are relative to the node's largest coefficient (here the mean,
+    # bin 0): |X|^2 errors are then bounded by 3 tol Xmax^2
+    xmax = max(np.abs(Uf[cols].astype(np.float64).mean(axis=1)).max(), np.sqrt(ref.max()))
+    tol = 1e-6 if fp32 else 1e-12
+    assert np.abs(Vg[cols].T - ref).max() <= 3 * tol * xmax ** 2
+
+
+@pytest.mark.parametrize("n,d,ns", [(96, 10, 6), (128, 20, 5), (256, 12, 2)])
+def test_streaming_solver_large_meshes(lib, n, d, ns):
+    prob = W.pde_problem(n, d, 8)
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), pcg_rtol=1e-13, pcg_maxit=8000))
+    Y = np.random.default_rng(n + d).random((ns, d))
+    U = torch.zeros((plan.G, ns + 1), dtype=torch.float64, device="cuda")
+    it = torch.zeros(ns, dtype=torch.int32, device="cuda")
+    lib.sample(plan, dev(Y), U, 0, ns + 1, 1, it)
+    assert (host(it) > 0).all()
+    Ug = host(U)
+    S = ofem.PDESampler(n, prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    for s in range(0, ns, max(1, ns // 2)):
+        ref = S.solve_one(Y[s])
+        assert np.linalg.norm(Ug[:, 1 + s] - ref) / np.linalg.norm(ref) <= 1e-11
