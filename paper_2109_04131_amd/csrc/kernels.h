@@ -25,9 +25,13 @@ int solver_config_count();
 bool solver_config_fits(int c, int n);  // n = mesh_n
 void solver_config_shape(int c, int* block, int* npt);
 int solver_default_config(int n);
+// Float32 solves run persistent: wscr holds 2 (n+1)^2 (rounded) doubles per
+// workgroup for wblocks = persistent_blocks(cfg, n) workgroups.
+int persistent_blocks(int cfg, int n);
+int64_t edge_scratch_doubles(int n, int blocks);
 void launch_pde_solve(int cfg, const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol,
                       int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
-                      int64_t col0, int* iters, hipStream_t st);
+                      int64_t col0, int* iters, double* wscr, int wblocks, hipStream_t st);
 int64_t stream_workspace_doubles(int n, int blocks);
 void launch_pde_solve_stream(const PdeDev& P, const double* Y, int64_t ns, double rtol, int maxit, void* out,
                              int out_fp32, int64_t ld, int64_t col0, int* iters, double* ws, int blocks,

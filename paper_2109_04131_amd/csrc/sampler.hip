@@ -228,7 +228,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE > 0 ?
 
 // One float32 Jacobi-PCG run with "reliable updates" (Sleijpen & van der
 // Vorst 1996): the float64 iterate x lives in LDS, the float32 correction dx
-// accumulated since the last update lives in registers.  Whenever the float32
+// accumulated since the last update lives in registers.  The kernel is
+// persistent (one workgroup per resident slot, looping over samples), so each
+// workgroup keeps its sample's exact float64 edge grids in a private global
+// scratch slot that stays in L2; updates read them instead of recomputing.  Whenever the float32
 // recursive residual has dropped by inner_rtol since the last reference (or
 // every refine_every iterations, a guard against float32 stagnation), x +=
 // dx and the true residual b - A(y) x is formed in float64 (weights
@@ -244,154 +247,143 @@ __device__ __forceinline__ float jacobi_rcp(float dg) { return dg > 0.0f ? __bui
 template <int BLOCK, int NPT, int WPE, int NC>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void pcg32r_kernel(
     PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, double inner_rtol, int refine_every,
-    void* __restrict__ out, int out_fp32, int64_t ld, int64_t col0, int* __restrict__ iters) {
+    void* __restrict__ out, int out_fp32, int64_t ld, int64_t col0, int* __restrict__ iters,
+    double* __restrict__ wscr, int64_t wstride) {
   extern __shared__ double lds[];
   const int n = NC > 0 ? NC : P.n, m = n - 1, G = m * m, P1 = n + 1;
   double* sx = lds;                                     // (n+1)^2 float64 iterate x (zero halo)
   float* sp = reinterpret_cast<float*>(lds + P1 * P1);  // (n+1)^2 float32 search direction
+  double* eh = wscr + (size_t)blockIdx.x * 2 * wstride;  // this workgroup's float64 edge grids
+  double* ev = eh + wstride;
   __shared__ double coef[kMaxD];
   __shared__ double red0[2 * (BLOCK / kWave)];
   __shared__ double red1[2 * (BLOCK / kWave)];
-  const int64_t s = xcd_remap(blockIdx.x, gridDim.x);
-  load_coef(P, Y, s, coef);
-  for (int e = threadIdx.x; e < P1 * P1; e += BLOCK) {
-    sx[e] = 0.0;
-    sp[e] = 0.0f;
-  }
-  __syncthreads();
-
-  float r[NPT], p[NPT], dx[NPT], wE[NPT], wW[NPT], wN[NPT], wS[NPT];
   int li[NPT];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int g = threadIdx.x + k * BLOCK;
     li[k] = (g < G) ? (g / m + 1) * P1 + (g % m + 1) : P1 + 1;  // padding slots read in bounds
   }
-  {
-    // float32 edge grids in the (still unused) float64 iterate region
-    float* eh = reinterpret_cast<float*>(sx);
-    float* ev = eh + P1 * P1;
-    fill_edges<float>(P, coef, eh, ev);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      wE[k] = eh[li[k]];
-      wW[k] = eh[li[k] - 1];
-      wN[k] = ev[li[k]];
-      wS[k] = ev[li[k] - P1];
+  // persistent: consecutive samples stay on one XCD within each round
+  for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
+    __syncthreads();  // the previous sample is done with LDS, coef and the edge grids
+    load_coef(P, Y, s, coef);
+    for (int e = threadIdx.x; e < P1 * P1; e += BLOCK) {
+      sx[e] = 0.0;
+      sp[e] = 0.0f;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < P1 * P1; e += BLOCK) sx[e] = 0.0;
+    fill_edges<double>(P, coef, eh, ev);
     __syncthreads();
-  }
-  double rz = 0.0, rr = 0.0, bb = 0.0;
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int g = threadIdx.x + k * BLOCK;
-    dx[k] = 0.0f;
-    if (g < G) {
-      r[k] = (float)P.h2;
-      bb += P.h2 * P.h2;
-    } else {
-      wE[k] = wW[k] = wN[k] = wS[k] = 0.0f;
-      r[k] = 0.0f;
-    }
-    p[k] = r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k]);
-    rz += (double)(r[k] * p[k]);
-    rr += (double)(r[k] * r[k]);
-  }
-  block_sum2<BLOCK>(rz, rr, red1);
-  bb = block_sum<BLOCK>(bb, red0);
-  const double stop = rtol * rtol * bb;
-  const double drop = inner_rtol * inner_rtol;
-  double rr_ref = rr;  // float32 residual norm^2 right after the last true residual
-  int it = 0, last_update = 0;
-  bool conv = false;
-  while (it < maxit) {
-#pragma unroll
-    for (int k = 0; k < NPT; ++k)
-      if (threadIdx.x + k * BLOCK < G) sp[li[k]] = p[k];
-    __syncthreads();
-    float q[NPT];
-    double pq = 0.0;
+    float r[NPT], p[NPT], dx[NPT], wE[NPT], wW[NPT], wN[NPT], wS[NPT];
+    double rz = 0.0, rr = 0.0, bb = 0.0;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      const int l = li[k];
-      q[k] = wE[k] * (p[k] - sp[l + 1]) + wW[k] * (p[k] - sp[l - 1]) + wN[k] * (p[k] - sp[l + P1]) +
-             wS[k] * (p[k] - sp[l - P1]);
-      if (threadIdx.x + k * BLOCK >= G) q[k] = 0.0f;
-      pq += (double)(p[k] * q[k]);
-    }
-    pq = block_sum<BLOCK>(pq, red0);
-    const float alpha = (float)(rz / pq);
-    double rz2 = 0.0;
-    rr = 0.0;
-#pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      dx[k] += alpha * p[k];
-      r[k] -= alpha * q[k];
-      rz2 += (double)(r[k] * (r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k])));
+      const int g = threadIdx.x + k * BLOCK;
+      dx[k] = 0.0f;
+      if (g < G) {
+        wE[k] = (float)eh[li[k]];
+        wW[k] = (float)eh[li[k] - 1];
+        wN[k] = (float)ev[li[k]];
+        wS[k] = (float)ev[li[k] - P1];
+        r[k] = (float)P.h2;
+        bb += P.h2 * P.h2;
+      } else {
+        wE[k] = wW[k] = wN[k] = wS[k] = 0.0f;
+        r[k] = 0.0f;
+      }
+      p[k] = r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k]);
+      rz += (double)(r[k] * p[k]);
       rr += (double)(r[k] * r[k]);
     }
-    block_sum2<BLOCK>(rz2, rr, red1);
-    ++it;
-    if (rr <= drop * rr_ref || it - last_update >= refine_every) {
-      // x += dx in float64; the float64 true residual replaces the float32 one
+    block_sum2<BLOCK>(rz, rr, red1);
+    bb = block_sum<BLOCK>(bb, red0);
+    const double stop = rtol * rtol * bb;
+    const double drop = inner_rtol * inner_rtol;
+    double rr_ref = rr;  // float32 residual norm^2 right after the last true residual
+    int it = 0, last_update = 0;
+    bool conv = false;
+    while (it < maxit) {
+#pragma unroll
+      for (int k = 0; k < NPT; ++k)
+        if (threadIdx.x + k * BLOCK < G) sp[li[k]] = p[k];
+      __syncthreads();
+      float q[NPT];
+      double pq = 0.0;
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
-        if (threadIdx.x + k * BLOCK < G) sx[li[k]] += (double)dx[k];
-        dx[k] = 0.0f;
+        const int l = li[k];
+        q[k] = wE[k] * (p[k] - sp[l + 1]) + wW[k] * (p[k] - sp[l - 1]) + wN[k] * (p[k] - sp[l + P1]) +
+               wS[k] * (p[k] - sp[l - P1]);
+        if (threadIdx.x + k * BLOCK >= G) q[k] = 0.0f;
+        pq += (double)(p[k] * q[k]);
       }
-      __syncthreads();
-      // plain (not unrolled) pass over the nodes: float64 weights from the
-      // centroid tables, edge-difference form (no cancellation between the
-      // diagonal and neighbour terms), float32 residual staged in sp
-      double rr64 = 0.0, rz3 = 0.0, rr3 = 0.0;
-      for (int g = threadIdx.x; g < G; g += BLOCK) {
-        int i = g % m + 1, j = g / m + 1;
-        // opaque to the optimiser: keeps the weight evaluation inside the loop
-        asm volatile("" : "+v"(i), "+v"(j));
-        const int l = j * P1 + i;
-        double e, w, nn, so;
-        node_weights(P, coef, i, j, e, w, nn, so);
-        const double xc = sx[l];
-        const double ax = e * (xc - sx[l + 1]) + w * (xc - sx[l - 1]) + nn * (xc - sx[l + P1]) +
-                          so * (xc - sx[l - P1]);
-        const double r64 = P.h2 - ax;
-        rr64 += r64 * r64;
-        sp[l] = (float)r64;
-      }
-      __syncthreads();
+      pq = block_sum<BLOCK>(pq, red0);
+      const float alpha = (float)(rz / pq);
+      double rz2 = 0.0;
+      rr = 0.0;
 #pragma unroll
       for (int k = 0; k < NPT; ++k) {
-        if (threadIdx.x + k * BLOCK < G) {
-          r[k] = sp[li[k]];
-          rz3 += (double)(r[k] * (r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k])));
-          rr3 += (double)(r[k] * r[k]);
+        dx[k] += alpha * p[k];
+        r[k] -= alpha * q[k];
+        rz2 += (double)(r[k] * (r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k])));
+        rr += (double)(r[k] * r[k]);
+      }
+      block_sum2<BLOCK>(rz2, rr, red1);
+      ++it;
+      if (rr <= drop * rr_ref || it - last_update >= refine_every) {
+        // x += dx in float64; the float64 true residual (exact float64 edge
+        // grids, edge-difference form) replaces the float32 one
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+          if (threadIdx.x + k * BLOCK < G) sx[li[k]] += (double)dx[k];
+          dx[k] = 0.0f;
         }
+        __syncthreads();
+        // plain pass over the nodes (keeps the per-node register arrays out of
+        // it); the float32 residual is staged in sp
+        double rr64 = 0.0, rz3 = 0.0, rr3 = 0.0;
+        for (int g = threadIdx.x; g < G; g += BLOCK) {
+          const int l = (g / m + 1) * P1 + (g % m + 1);
+          const double xc = sx[l];
+          const double ax = eh[l] * (xc - sx[l + 1]) + eh[l - 1] * (xc - sx[l - 1]) + ev[l] * (xc - sx[l + P1]) +
+                            ev[l - P1] * (xc - sx[l - P1]);
+          const double r64 = P.h2 - ax;
+          rr64 += r64 * r64;
+          sp[l] = (float)r64;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+          if (threadIdx.x + k * BLOCK < G) {
+            r[k] = sp[li[k]];
+            rz3 += (double)(r[k] * (r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k])));
+            rr3 += (double)(r[k] * r[k]);
+          }
+        }
+        rr64 = block_sum<BLOCK>(rr64, red0);
+        block_sum2<BLOCK>(rz3, rr3, red1);
+        last_update = it;
+        if (rr64 <= stop) {
+          conv = true;
+          break;
+        }
+        rz2 = rz3;
+        rr_ref = rr3;
       }
-      rr64 = block_sum<BLOCK>(rr64, red0);
-      block_sum2<BLOCK>(rz3, rr3, red1);
-      last_update = it;
-      if (rr64 <= stop) {
-        conv = true;
-        break;
-      }
-      rz2 = rz3;
-      rr_ref = rr3;
+      const float beta = (float)(rz2 / rz);
+      rz = rz2;
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) p[k] = r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k]) + beta * p[k];
     }
-    const float beta = (float)(rz2 / rz);
-    rz = rz2;
+    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) p[k] = r[k] * jacobi_rcp(wE[k] + wW[k] + wN[k] + wS[k]) + beta * p[k];
+    for (int k = 0; k < NPT; ++k) {
+      const int g = threadIdx.x + k * BLOCK;
+      if (g < G) store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, sx[li[k]]);
+    }
+    if (threadIdx.x == 0 && iters) iters[s] = conv ? it : -1;
   }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const int g = threadIdx.x + k * BLOCK;
-    if (g < G) store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, sx[li[k]]);
-  }
-  if (threadIdx.x == 0 && iters) iters[s] = conv ? it : -1;
 }
 
 // ------------------------------------------ streaming FP64 PCG (large meshes)
@@ -546,7 +538,7 @@ void launch_nodes(int d, int line, int t, int nlat, const int64_t* off, const in
 
 using Pcg64Fn = void (*)(PdeDev, const double*, int64_t, double, int, void*, int, int64_t, int64_t, int*);
 using Pcg32Fn = void (*)(PdeDev, const double*, int64_t, double, int, double, int, void*, int, int64_t,
-                         int64_t, int*);
+                         int64_t, int*, double*, int64_t);
 
 struct SolverCfg {
   int block, npt, wpe, nc;  // nc: mesh size compiled in (0 = any)
@@ -600,9 +592,30 @@ int solver_default_config(int n) {
   return best;
 }
 
+// Workgroups of the persistent float32 kernel: CUs x resident workgroups per CU.
+int persistent_blocks(int cfg, int n) {
+  static int cache[64] = {0};
+  if (cfg < 0 || cfg >= 64) return 256;
+  if (cache[cfg] > 0) return cache[cfg];
+  const SolverCfg& k = kSolverCfgs[cfg];
+  const size_t P1 = (size_t)(n + 1) * (n + 1);
+  int per_cu = 0, cus = 0, dev = 0;
+  USFFT_HIP(hipGetDevice(&dev));
+  USFFT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  USFFT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k.f32), k.block,
+                                                         P1 * (sizeof(double) + sizeof(float))));
+  cache[cfg] = std::max(1, per_cu) * std::max(1, cus);
+  return cache[cfg];
+}
+
+int64_t edge_scratch_doubles(int n, int blocks) {
+  const int64_t ws = ((int64_t)(n + 1) * (n + 1) + 31) / 32 * 32;
+  return 2 * ws * blocks;
+}
+
 void launch_pde_solve(int cfg, const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol,
                       int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
-                      int64_t col0, int* iters, hipStream_t st) {
+                      int64_t col0, int* iters, double* wscr, int wblocks, hipStream_t st) {
   if (ns <= 0) return;
   const SolverCfg& k = kSolverCfgs[cfg];
   const size_t P1 = (size_t)(P.n + 1) * (P.n + 1);
@@ -610,8 +623,10 @@ void launch_pde_solve(int cfg, const PdeDev& P, int precision, const double* Y, 
     hipLaunchKernelGGL(k.f64, dim3((unsigned)ns), dim3(k.block), P1 * sizeof(double), st, P, Y, ns, rtol,
                        maxit, out, out_fp32, ld, col0, iters);
   } else {
-    hipLaunchKernelGGL(k.f32, dim3((unsigned)ns), dim3(k.block), P1 * (sizeof(double) + sizeof(float)), st,
-                       P, Y, ns, rtol, maxit, inner_rtol, refine_every, out, out_fp32, ld, col0, iters);
+    const int64_t ws = ((int64_t)(P.n + 1) * (P.n + 1) + 31) / 32 * 32;
+    const unsigned grid = (unsigned)std::min<int64_t>(ns, wblocks);
+    hipLaunchKernelGGL(k.f32, dim3(grid), dim3(k.block), P1 * (sizeof(double) + sizeof(float)), st, P, Y, ns,
+                       rtol, maxit, inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws);
   }
   USFFT_HIP(hipGetLastError());
 }

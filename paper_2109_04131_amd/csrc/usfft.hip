@@ -116,7 +116,8 @@ struct usfft_plan_s {
   int64_t G = 0;
   int solver_cfg = 0;
   // static device tables
-  usfft::DevBuf d_amp, d_tab, d_polyk, d_polyc, d_stream;
+  usfft::DevBuf d_amp, d_tab, d_polyk, d_polyc, d_stream, d_wscr;
+  int wblocks = 0;  // persistent workgroups of the float32 solver
   bool streaming = false;  // mesh larger than the on-chip solver holds
   usfft::PdeDev pde{};
   // Rader tables per lattice size
@@ -254,7 +255,7 @@ static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
                             P->d_stream.as<double>(), kStreamBlocks, st);
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE) {
     launch_pde_solve(P->solver_cfg, P->pde, par.precision, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
-                     par.refine_every, U, out_fp32, ld, col0, iters, st);
+                     par.refine_every, U, out_fp32, ld, col0, iters, P->d_wscr.as<double>(), P->wblocks, st);
   } else {
     launch_trigpoly(P->prob.d, Y, ns, P->d_polyk.as<int32_t>(), P->prob.n_poly, P->d_polyc.as<double>(), P->G, U,
                     out_fp32, ld, col0, st);
@@ -569,13 +570,16 @@ static int autotune_solver(usfft_plan_s* P) {
   USFFT_HIP(hipEventCreate(&b));
   int best = solver_default_config(n);
   float best_ms = 1e30f;
+  DevBuf scr;
   for (int c = 0; c < solver_config_count(); ++c) {
     if (!solver_config_fits(c, n)) continue;
+    const int wb = persistent_blocks(c, n);
+    scr.ensure(sizeof(double) * (size_t)edge_scratch_doubles(n, wb));
     launch_pde_solve(c, P->pde, prec, Y.as<double>(), 64, P->par.pcg_rtol, P->par.pcg_maxit, P->par.inner_rtol,
-                     P->par.refine_every, U.p, 0, ns, 0, it.as<int32_t>(), st);
+                     P->par.refine_every, U.p, 0, ns, 0, it.as<int32_t>(), scr.as<double>(), wb, st);
     USFFT_HIP(hipEventRecord(a, st));
     launch_pde_solve(c, P->pde, prec, Y.as<double>(), ns, P->par.pcg_rtol, P->par.pcg_maxit, P->par.inner_rtol,
-                     P->par.refine_every, U.p, 0, ns, 0, it.as<int32_t>(), st);
+                     P->par.refine_every, U.p, 0, ns, 0, it.as<int32_t>(), scr.as<double>(), wb, st);
     USFFT_HIP(hipEventRecord(b, st));
     USFFT_HIP(hipEventSynchronize(b));
     float ms = 0;
@@ -675,6 +679,10 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
       P->solver_cfg = autotune_solver(P.get());
     }
     USFFT_REQUIRE(P->streaming || P->solver_cfg >= 0, USFFT_EINVAL, "no solver shape for this mesh");
+    if (!P->streaming) {
+      P->wblocks = persistent_blocks(P->solver_cfg, n);
+      P->d_wscr.ensure(sizeof(double) * (size_t)edge_scratch_doubles(n, P->wblocks));
+    }
   } else {
     P->G = pb->G_poly;
     P->poly_k.assign(pb->poly_k, pb->poly_k + (size_t)pb->n_poly * d);

@@ -298,7 +298,7 @@ def test_eval_matches_oracle(lib):
 def test_error_paths(lib):
     prob, par = W.WORKLOADS["cpu16_d4"]
     with pytest.raises(lib.UsfftError) as e:
-        lib.Plan(dict(prob, mesh_n=200), par)
+        lib.Plan(dict(prob, mesh_n=600), par)
     assert e.value.status == lib.EINVAL
     plan = lib.Plan(prob, dict(par, pcg_maxit=3, solver_config=-2))
     with pytest.raises(lib.UsfftError) as e:
