@@ -51,6 +51,38 @@ def run_path(U, plan, seed, steps, warmup):
     return wall, lat, stats, n
 
 
+def serving_run(U, jobs, rate, seed, max_active):
+    """Poisson arrivals (mean `rate` jobs/s) into the continuous-batching
+    server; returns jobs/s, p50/p99 latency and aggregate solves/s."""
+    import workloads as W
+    stream = W.serving_stream(seed=seed, rate=rate, jobs=jobs)
+    srv = U.Server(max_active=max_active)
+    t0 = time.perf_counter()
+    ids = []
+    for t_arr, prob, par, s in stream:
+        delay = t_arr - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(prob, dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=256), s))
+    lat, qs, solves, failed = [], [], 0, 0
+    for jid in ids:
+        res, st, l, q, err = srv.poll(jid, wait=True)
+        if st != U.OK:
+            failed += 1
+            continue
+        lat.append(l)
+        qs.append(q)
+        solves += res.stats["samples"]
+        res.close()
+    wall = time.perf_counter() - t0
+    srv.close()
+    return {"jobs": len(stream), "failed": failed, "arrival_rate_per_s": rate, "max_active": max_active,
+            "jobs_per_s": len(lat) / wall, "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
+            "p50_queue_s": pct(qs, 50), "samples_per_s": solves / wall, "wall_s": wall,
+            "stream": "Poisson(4/s) jobs, meshes 16^2..64^2, d 4..10, N 16..32, s 50..200, "
+                      "float32+refine, seed %d" % seed}
+
+
 def measured_traffic():
     """HBM bytes per solver launch from the committed rocprof counter summary,
     only while the solver source is the one the counters were taken on."""
@@ -100,6 +132,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=16,
+                    help="jobs of the Poisson serving run reported beside the headline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof byte counters)")
     args = ap.parse_args()
@@ -174,6 +208,8 @@ def main():
                      "workgroup": [st32[0]["solver_block"], st32[0]["solver_npt"]]},
     }
     res.update(out)
+    if args.serving_jobs > 0:
+        res["serving"] = serving_run(U, args.serving_jobs, 4.0, args.seed, 4)
     if args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(res))

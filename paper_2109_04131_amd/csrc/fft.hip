@@ -14,9 +14,10 @@
 // coalesced, and writes only the requested bins: HBM traffic is the
 // algorithmic minimum, M reads and n_bins writes per node.
 //
-// FFT in LDS: Stockham autosort radix passes (the formulation of Govindaraju
-// et al., SC 2008), one buffer: each pass reads its butterfly inputs into
-// registers, barrier, writes the outputs, barrier.
+// FFT in LDS: in-place mixed-radix decimation-in-frequency stages forward and
+// decimation-in-time stages back, with the convolution's pointwise product in
+// the digit-reversed order in between (no reordering pass, one LDS buffer,
+// R registers per butterfly).
 //
 // Line DFT: the length-K_t DFT of the 1-D detection, evaluated directly.
 #include "kernels.h"
@@ -116,79 +117,107 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
   }
 }
 
-// One Stockham pass of radix R over buf[0..L).  Input element q of butterfly
-// j is buf[j + q L/R] (or buf[perm[.] - 1] for the Rader input permutation);
-// output p goes to (j / Ns) Ns R + j % Ns + p Ns.  With `mulB` the outputs are
-// multiplied by B and conjugated (the forward half of the convolution, set up
-// for the inverse transform by conjugation).
-template <typename T, int R>
-__device__ void fft_pass(cplx<T>* buf, int L, int Ns, const cplx<T>* __restrict__ tw,
-                         const int32_t* __restrict__ perm, const cplx<T>* __restrict__ mulB) {
-  constexpr int MAXB = (kLMax / R + kFftBlock - 1) / kFftBlock;
-  const int nb = L / R;
-  const int stride = L / (Ns * R);
-  cplx<T> v[MAXB][R];
-#pragma unroll
-  for (int b = 0; b < MAXB; ++b) {
-    const int j = threadIdx.x + b * kFftBlock;
-    if (j < nb) {
-      const int k = j % Ns;
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int idx = j + q * nb;
-        cplx<T> a = perm ? buf[perm[idx] - 1] : buf[idx];
-        if (q > 0 && k > 0) a = cmul(a, tw[q * k * stride]);
-        v[b][q] = a;
-      }
-      dft_small<T, R>(v[b]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int b = 0; b < MAXB; ++b) {
-    const int j = threadIdx.x + b * kFftBlock;
-    if (j < nb) {
-      const int k = j % Ns;
-      const int base = (j / Ns) * Ns * R + k;
-#pragma unroll
-      for (int p = 0; p < R; ++p) {
-        const int idx = base + p * Ns;
-        cplx<T> o = v[b][p];
-        if (mulB) o = conjc(cmul(o, mulB[idx]));
-        buf[idx] = o;
-      }
-    }
-  }
-  __syncthreads();
-}
-
 struct FftPlanDev {
   int L, nrad;
   int radix[24];
 };
 
+// In-place mixed-radix FFT stages on buf[0..L) (no extra buffer, R registers
+// per butterfly).  Stage s has block size N_s = L / (R_0 ... R_{s-1}) and
+// M_s = N_s / R_s; butterfly (blk, j) touches base + m M_s, base = blk N_s + j.
+//  DIF stage: butterfly over m, then twiddle w_{N_s}^{j q}; running all
+//    stages forward turns natural order into digit-reversed order, A = Pi F x.
+//  DIT stage: twiddle first, then butterfly (the transpose of a DIF stage);
+//    running the stages backwards on Pi y gives F y, because F is symmetric
+//    and so F = S_0^T ... S_{S-1}^T Pi.
+// A convolution therefore never needs natural order in between: forward DIF,
+// pointwise product with a spectrum produced by the same DIF, DIT back.
+template <typename T, int R>
+__device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw,
+                          const cplx<T>* __restrict__ mulB) {
+  const int nb = L / R, ts = L / N;
+  for (int b = threadIdx.x; b < nb; b += kFftBlock) {
+    const int blk = b / M, j = b - blk * M, base = blk * N + j;
+    cplx<T> v[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) v[m] = buf[base + m * M];
+    dft_small<T, R>(v);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      cplx<T> o = v[q];
+      if (q > 0 && j > 0) o = cmul(o, tw[j * q * ts]);
+      if (mulB) o = conjc(cmul(o, mulB[base + q * M]));
+      buf[base + q * M] = o;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int R>
+__device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw) {
+  const int nb = L / R, ts = L / N;
+  for (int b = threadIdx.x; b < nb; b += kFftBlock) {
+    const int blk = b / M, j = b - blk * M, base = blk * N + j;
+    cplx<T> v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      cplx<T> a = buf[base + q * M];
+      if (q > 0 && j > 0) a = cmul(a, tw[j * q * ts]);
+      v[q] = a;
+    }
+    dft_small<T, R>(v);
+#pragma unroll
+    for (int m = 0; m < R; ++m) buf[base + m * M] = v[m];
+  }
+  __syncthreads();
+}
+
+// Forward DIF over all stages; with mulB, the last stage multiplies by mulB
+// and conjugates (the forward half of a convolution, set up for the inverse
+// transform by conjugation).
 template <typename T>
-__device__ void fft_run(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, const int32_t* perm,
-                        const cplx<T>* mulB) {
-  int Ns = 1;
+__device__ void fft_dif(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, const cplx<T>* mulB) {
+  int N = F.L;
   for (int s = 0; s < F.nrad; ++s) {
-    const int R = F.radix[s];
-    const int32_t* pm = (s == 0) ? perm : nullptr;
+    const int R = F.radix[s], M = N / R;
     const cplx<T>* mb = (s == F.nrad - 1) ? mulB : nullptr;
     switch (R) {
-      case 2: fft_pass<T, 2>(buf, F.L, Ns, tw, pm, mb); break;
-      case 3: fft_pass<T, 3>(buf, F.L, Ns, tw, pm, mb); break;
-      case 4: fft_pass<T, 4>(buf, F.L, Ns, tw, pm, mb); break;
-      case 5: fft_pass<T, 5>(buf, F.L, Ns, tw, pm, mb); break;
-      case 7: fft_pass<T, 7>(buf, F.L, Ns, tw, pm, mb); break;
-      default: fft_pass<T, 8>(buf, F.L, Ns, tw, pm, mb); break;
+      case 2: dif_stage<T, 2>(buf, F.L, N, M, tw, mb); break;
+      case 3: dif_stage<T, 3>(buf, F.L, N, M, tw, mb); break;
+      case 4: dif_stage<T, 4>(buf, F.L, N, M, tw, mb); break;
+      case 5: dif_stage<T, 5>(buf, F.L, N, M, tw, mb); break;
+      case 7: dif_stage<T, 7>(buf, F.L, N, M, tw, mb); break;
+      default: dif_stage<T, 8>(buf, F.L, N, M, tw, mb); break;
     }
-    Ns *= R;
+    N = M;
+  }
+}
+
+// Forward DIT over all stages in reverse order (digit-reversed in, natural out).
+template <typename T>
+__device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
+  int Ns[24];
+  int N = F.L;
+  for (int s = 0; s < F.nrad; ++s) {
+    Ns[s] = N;
+    N /= F.radix[s];
+  }
+  for (int s = F.nrad - 1; s >= 0; --s) {
+    const int R = F.radix[s], Nn = Ns[s], M = Nn / R;
+    switch (R) {
+      case 2: dit_stage<T, 2>(buf, F.L, Nn, M, tw); break;
+      case 3: dit_stage<T, 3>(buf, F.L, Nn, M, tw); break;
+      case 4: dit_stage<T, 4>(buf, F.L, Nn, M, tw); break;
+      case 5: dit_stage<T, 5>(buf, F.L, Nn, M, tw); break;
+      case 7: dit_stage<T, 7>(buf, F.L, Nn, M, tw); break;
+      default: dit_stage<T, 8>(buf, F.L, Nn, M, tw); break;
+    }
   }
 }
 
 // ---------------------------------------------------------------- setup
-// B = DFT_L(b) / L for b_j = exp(-2 pi i gen^-j / M), gen^-j = perm[(L - j) % L].
+// B = DFT_L(b) / L for b_j = exp(-2 pi i gen^-j / M), gen^-j = perm[(L - j) % L],
+// stored in the digit-reversed order the forward DIF produces.
 __global__ __launch_bounds__(kFftBlock) void rader_setup_kernel(FftPlanDev F, int M, const int32_t* __restrict__ perm,
                                                                const cplx<double>* __restrict__ tw,
                                                                cplx<double>* __restrict__ B64,
@@ -204,7 +233,7 @@ __global__ __launch_bounds__(kFftBlock) void rader_setup_kernel(FftPlanDev F, in
     buf[j] = {c, s};
   }
   __syncthreads();
-  fft_run<double>(buf, F, tw, nullptr, nullptr);
+  fft_dif<double>(buf, F, tw, nullptr);  // spectrum in the DIF (digit-reversed) order
   const double invL = 1.0 / (double)L;
   for (int k = threadIdx.x; k < L; k += kFftBlock) {
     const cplx<double> v = {buf[k].x * invL, buf[k].y * invL};
@@ -315,8 +344,8 @@ __global__ __launch_bounds__(kFftBlock) void rader_kernel(FftPlanDev F, int M, c
                                                           const cplx<T>* __restrict__ B, const T* __restrict__ u,
                                                           int64_t G, int64_t ld, int64_t col0,
                                                           const int32_t* __restrict__ bins,
-                                                          const int32_t* __restrict__ pos, int nb, int out_kind,
-                                                          void* __restrict__ out, int64_t ldo) {
+                                                          const int32_t* __restrict__ pos, int pos_base, int nb,
+                                                          int out_kind, void* __restrict__ out, int64_t ldo) {
   extern __shared__ char smem[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   __shared__ double red[2 * (kFftBlock / kWave)];
@@ -326,24 +355,27 @@ __global__ __launch_bounds__(kFftBlock) void rader_kernel(FftPlanDev F, int M, c
   const T* u1 = u + g1 * ld + col0;
   const T* u2 = u + (has2 ? g2 : g1) * ld + col0;
   const int L = F.L;
-  // coalesced load of x[1..M-1] into buf[0..L), partial sums for X[0]
+  // Rader input a_q = x[g^q], gathered straight from the two rows (each row
+  // segment is read once from HBM; the permuted order is served by the
+  // caches), plus the sums for X[0]
   double s1 = 0.0, s2 = 0.0;
-  for (int m = 1 + threadIdx.x; m < M; m += kFftBlock) {
-    const T a = u1[m];
-    const T b = has2 ? u2[m] : (T)0;
-    buf[m - 1] = {a, b};
+  for (int q = threadIdx.x; q < L; q += kFftBlock) {
+    const int mq = perm[q];
+    const T a = u1[mq];
+    const T b = has2 ? u2[mq] : (T)0;
+    buf[q] = {a, b};
     s1 += (double)a;
     s2 += (double)b;
   }
   const T x01 = u1[0];
   const T x02 = has2 ? u2[0] : (T)0;
-  block_sum2<kFftBlock>(s1, s2, red);  // also orders the LDS writes before the first pass
+  block_sum2<kFftBlock>(s1, s2, red);  // also orders the LDS writes before the first stage
   s1 += (double)x01;
   s2 += (double)x02;
-  // c = a (*) b: forward FFT (input permuted by perm), times B, conjugate,
-  // forward FFT again; buf then holds conj(c).
-  fft_run<T>(buf, F, tw, perm, B);
-  fft_run<T>(buf, F, tw, nullptr, nullptr);
+  // c = a (*) b: forward DIF, times B (same order), conjugate, forward DIT;
+  // buf then holds conj(c) in natural order.
+  fft_dif<T>(buf, F, tw, B);
+  fft_dit<T>(buf, F, tw);
   const double invM = 1.0 / (double)M;
   for (int a = threadIdx.x; a < nb; a += kFftBlock) {
     const int b = bins[a];
@@ -370,7 +402,7 @@ __global__ __launch_bounds__(kFftBlock) void rader_kernel(FftPlanDev F, int M, c
       X1i = -X1i;
       X2i = -X2i;
     }
-    const int64_t c = pos[a];
+    const int64_t c = pos ? pos[a] : pos_base + a;  // contiguous when pos is null
     if (out_kind == USFFT_OUT_MAG2) {
       double* o = static_cast<double*>(out);
       o[g1 * ldo + c] = X1r * X1r + X1i * X1i;
@@ -388,8 +420,8 @@ __global__ __launch_bounds__(kFftBlock) void rader_kernel(FftPlanDev F, int M, c
 }
 
 void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0,
-                        const int32_t* bins, const int32_t* pos, int nb, int out_kind, void* out, int64_t ldo,
-                        hipStream_t st) {
+                        const int32_t* bins, const int32_t* pos, int pos_base, int nb, int out_kind, void* out,
+                        int64_t ldo, hipStream_t st) {
   if (G <= 0 || nb <= 0) return;
   FftPlanDev F;
   F.L = T.L;
@@ -399,11 +431,11 @@ void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t
   if (u_fp32) {
     hipLaunchKernelGGL(rader_kernel<float>, dim3(grid), dim3(kFftBlock), sizeof(cplx<float>) * T.L, st, F, T.M,
                        T.perm, T.outidx, (const cplx<float>*)T.tw32, (const cplx<float>*)T.B32,
-                       (const float*)u, G, ld, col0, bins, pos, nb, out_kind, out, ldo);
+                       (const float*)u, G, ld, col0, bins, pos, pos_base, nb, out_kind, out, ldo);
   } else {
     hipLaunchKernelGGL(rader_kernel<double>, dim3(grid), dim3(kFftBlock), sizeof(cplx<double>) * T.L, st, F,
                        T.M, T.perm, T.outidx, (const cplx<double>*)T.tw64, (const cplx<double>*)T.B64,
-                       (const double*)u, G, ld, col0, bins, pos, nb, out_kind, out, ldo);
+                       (const double*)u, G, ld, col0, bins, pos, pos_base, nb, out_kind, out, ldo);
   }
   USFFT_HIP(hipGetLastError());
 }

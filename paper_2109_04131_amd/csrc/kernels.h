@@ -55,9 +55,12 @@ struct RaderTables {
 bool lattice_size_ok(int M);
 void rader_build(RaderTables& T, int M, hipStream_t st);  // allocates + fills (synchronous)
 void rader_free(RaderTables& T);
+// Output column of candidate a: pos[a], or pos_base + a when pos is null.
 void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0,
-                        const int32_t* bins, const int32_t* pos, int nb, int out_kind, void* out, int64_t ldo,
-                        hipStream_t st);
+                        const int32_t* bins, const int32_t* pos, int pos_base, int nb, int out_kind, void* out,
+                        int64_t ldo, hipStream_t st);
+// mask_out bit pos[q] |= mask_in bit q, q < n (grouped order back to candidate order).
+void launch_ungroup_mask(const uint32_t* mask_in, const int32_t* pos, int64_t n, uint32_t* mask_out, hipStream_t st);
 void launch_line_dft(const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0, int K, const int32_t* bins,
                      int nb, int out_kind, void* out, int64_t ldo, hipStream_t st);
 

@@ -5,7 +5,8 @@
 // tau_g^2, the s~-th largest squared magnitude of column g (with
 // multiplicity), is found by an exact MSB-first radix select on the bit
 // patterns of the non-negative float64 values (their unsigned order is the
-// numeric order): 8 passes of 8-bit digits with an LDS histogram.  A
+// numeric order): 8 passes of 8-bit digits with an LDS histogram, over the
+// column staged once in LDS when it fits.  A
 // candidate is kept when v >= max(theta^2, (1 - tie) tau_g^2); each wave ORs
 // its 64 keep bits into the global candidate mask with two word atomics.
 #include "kernels.h"
@@ -14,15 +15,24 @@ namespace usfft {
 
 constexpr int kSelBlock = 256;
 
+constexpr int kSelLds = 8192;  // columns up to this length are staged in LDS (64 KB)
+
+template <bool STAGE>
 __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restrict__ v, int64_t G, int64_t n,
                                                            int64_t ld, int s_tilde,
                                                            const double* __restrict__ theta2p, double tie_rel,
                                                            uint32_t* __restrict__ mask, double* __restrict__ thr_out) {
+  extern __shared__ uint64_t stage[];
   __shared__ uint32_t hist[256];
   __shared__ uint64_t s_prefix;
   __shared__ int64_t s_rank;
   const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
-  const uint64_t* keys = reinterpret_cast<const uint64_t*>(v + g * ld);
+  const uint64_t* gkeys = reinterpret_cast<const uint64_t*>(v + g * ld);
+  if (STAGE) {
+    for (int64_t a = threadIdx.x; a < n; a += kSelBlock) stage[a] = gkeys[a];
+    __syncthreads();
+  }
+  const uint64_t* keys = STAGE ? stage : gkeys;
   double tau2 = 0.0;
   if (s_tilde > 0 && n >= s_tilde) {
     uint64_t prefix = 0;   // digits fixed so far
@@ -31,23 +41,53 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
       for (int i = threadIdx.x; i < 256; i += kSelBlock) hist[i] = 0;
       __syncthreads();
       const uint64_t hmask = (shift == 56) ? 0ull : (~0ull << (shift + 8));
-      for (int64_t a = threadIdx.x; a < n; a += kSelBlock) {
-        const uint64_t k = keys[a];
-        if ((k & hmask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+      const int lane = threadIdx.x & (kWave - 1);
+      for (int64_t a0 = threadIdx.x - lane; a0 < n; a0 += kSelBlock) {
+        // wave-aggregated increments: the digits of a column concentrate on a
+        // few bins (shared exponent bits), so the wave's most common case
+        // (the first active lane's digit) is counted with one atomic
+        const int64_t a = a0 + lane;
+        const uint64_t k = a < n ? keys[a] : 0ull;
+        const bool act = a < n && (k & hmask) == prefix;
+        const uint32_t dg = (uint32_t)(k >> shift) & 255u;
+        const uint64_t actm = __ballot(act);
+        if (actm) {
+          const int first = __ffsll((unsigned long long)actm) - 1;
+          const uint32_t lead = __shfl(dg, first, kWave);
+          const uint64_t same = __ballot(act && dg == lead);
+          if (lane == first) atomicAdd(&hist[lead], (uint32_t)__popcll(same));
+          if (act && dg != lead) atomicAdd(&hist[dg], 1u);
+        }
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        int64_t acc = 0;
-        int dsel = 0;
-        for (int dgt = 255; dgt >= 0; --dgt) {
-          if (acc + hist[dgt] >= rank) {
-            dsel = dgt;
-            break;
-          }
-          acc += hist[dgt];
+      if (threadIdx.x < kWave) {
+        // wave 0 finds the digit holding the rank-th largest key: lane l owns
+        // bins 255-4l .. 252-4l, an inclusive prefix over lanes gives the
+        // count of larger keys, exactly one lane contains the rank.
+        const int l = threadIdx.x;
+        uint32_t h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = hist[255 - 4 * l - i];
+        const uint32_t c = h[0] + h[1] + h[2] + h[3];
+        uint32_t inc = c;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const uint32_t t = __shfl_up(inc, o, kWave);
+          if (l >= o) inc += t;
         }
-        s_prefix = prefix | ((uint64_t)dsel << shift);
-        s_rank = rank - acc;
+        const int64_t exc = (int64_t)(inc - c);
+        if (exc < rank && (int64_t)inc >= rank) {
+          int64_t acc = exc;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (acc + h[i] >= rank) {
+              s_prefix = prefix | ((uint64_t)(255 - 4 * l - i) << shift);
+              s_rank = rank - acc;
+              break;
+            }
+            acc += h[i];
+          }
+        }
       }
       __syncthreads();
       prefix = s_prefix;
@@ -58,7 +98,7 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
   }
   const double thr = fmax(*theta2p, (1.0 - tie_rel) * tau2);
   if (thr_out && threadIdx.x == 0) thr_out[g] = thr;
-  const double* col = v + g * ld;
+  const double* col = STAGE ? reinterpret_cast<const double*>(stage) : v + g * ld;
   const int lane = threadIdx.x & (kWave - 1);
   for (int64_t a0 = (int64_t)(threadIdx.x - lane); a0 < n; a0 += kSelBlock) {
     const int64_t a = a0 + lane;
@@ -76,8 +116,12 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
 void launch_select(const double* v, int64_t G, int64_t n, int64_t ld, int s_tilde, const double* theta2,
                    double tie_rel, uint32_t* mask, double* thr, hipStream_t st) {
   if (G <= 0 || n <= 0) return;
-  hipLaunchKernelGGL(select_kernel, dim3((unsigned)G), dim3(kSelBlock), 0, st, v, G, n, ld, s_tilde, theta2, tie_rel,
-                     mask, thr);
+  if (n <= kSelLds)
+    hipLaunchKernelGGL(select_kernel<true>, dim3((unsigned)G), dim3(kSelBlock), (size_t)n * sizeof(uint64_t), st, v,
+                       G, n, ld, s_tilde, theta2, tie_rel, mask, thr);
+  else
+    hipLaunchKernelGGL(select_kernel<false>, dim3((unsigned)G), dim3(kSelBlock), 0, st, v, G, n, ld, s_tilde,
+                       theta2, tie_rel, mask, thr);
   USFFT_HIP(hipGetLastError());
 }
 

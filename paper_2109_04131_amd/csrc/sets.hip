@@ -139,4 +139,21 @@ void launch_lattice_take(const int32_t* bins, const int32_t* counts, uint8_t* co
   USFFT_HIP(hipGetLastError());
 }
 
+__global__ void ungroup_mask_kernel(const uint32_t* __restrict__ in, const int32_t* __restrict__ pos, int64_t n,
+                                    uint32_t* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  if ((in[q >> 5] >> (q & 31)) & 1u) {
+    const int32_t a = pos[q];
+    atomicOr(&out[a >> 5], 1u << (a & 31));
+  }
+}
+
+void launch_ungroup_mask(const uint32_t* mask_in, const int32_t* pos, int64_t n, uint32_t* mask_out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(ungroup_mask_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, mask_in, pos, n,
+                     mask_out);
+  USFFT_HIP(hipGetLastError());
+}
+
 }  // namespace usfft

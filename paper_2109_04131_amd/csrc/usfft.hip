@@ -123,7 +123,7 @@ struct usfft_plan_s {
   // Rader tables per lattice size
   std::map<int, usfft::RaderTables> rader;
   // workspaces (grown on demand, kept across calls)
-  usfft::DevBuf Y, U, V, iters, cnt, theta2, scratch, J, Jnext, Iprev, mask, cands, assign, bins, famz, fambins,
+  usfft::DevBuf Y, U, V, iters, cnt, theta2, scratch, J, Jnext, Iprev, mask, gmask, cands, assign, bins, famz, fambins,
       famcounts, famcov, famscores, lists, latM, latz, latoff, tail;
   std::vector<usfft::DevBuf> I1;  // step-1 sets per coordinate
   std::vector<int64_t> I1n;
@@ -455,9 +455,14 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     h2d(P->latM, F.M, st);
     h2d(P->latz, F.z, st);
     h2d(P->latoff, F.off, st);
+    // V holds the stage's magnitudes in lattice-grouped candidate order (each
+    // lattice's bins contiguous per node); the mask is built in that order and
+    // mapped back to candidate order before compaction.
     const int64_t words = ceil_div(n, 32);
     P->mask.ensure(sizeof(uint32_t) * words);
+    P->gmask.ensure(sizeof(uint32_t) * words);
     USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * words, st));
+    USFFT_HIP(hipMemsetAsync(P->gmask.p, 0, sizeof(uint32_t) * words, st));
     for (int i = 0; i < r_t; ++i) {
       upload_tail(rng::kTail2, t + 1, i + 1);
       launch_nodes(d, -1, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(), P->latz.as<int32_t>(),
@@ -469,16 +474,19 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
         const RaderTables& T = rader_for(P, F.M[l], st);
         const int32_t* pos = P->lists.as<int32_t>() + F.lat_first[l];
         const int32_t* bn = P->lists.as<int32_t>() + n + F.lat_first[l];
-        launch_lattice_dft(T, P->U.p, ufp32, G, ld, F.off[l], bn, pos, F.lat_count[l], USFFT_OUT_MAG2, P->V.p, n, st);
+        (void)pos;
+        launch_lattice_dft(T, P->U.p, ufp32, G, ld, F.off[l], bn, nullptr, F.lat_first[l], F.lat_count[l],
+                           USFFT_OUT_MAG2, P->V.p, n, st);
         S.dft_launches += 1;
         S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 8.0;
       }
       tm.close(kTDft, e);
       e = tm.open(kTSelect);
-      launch_select(P->V.as<double>(), G, n, n, s_t, P->theta2.as<double>(), par.tie_rel, P->mask.as<uint32_t>(),
+      launch_select(P->V.as<double>(), G, n, n, s_t, P->theta2.as<double>(), par.tie_rel, P->gmask.as<uint32_t>(),
                     nullptr, st);
       tm.close(kTSelect, e);
     }
+    launch_ungroup_mask(P->gmask.as<uint32_t>(), P->lists.as<int32_t>(), n, P->mask.as<uint32_t>(), st);
     P->Jnext.ensure(sizeof(int32_t) * n * w);
     launch_compact(P->J.as<int32_t>(), P->mask.as<uint32_t>(), n, w, P->Jnext.as<int32_t>(),
                    reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32), st);
@@ -521,8 +529,8 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       const RaderTables& T = rader_for(P, F.M[l], st);
       const int32_t* pos = P->lists.as<int32_t>() + F.lat_first[l];
       const int32_t* bn = P->lists.as<int32_t>() + nI + F.lat_first[l];
-      launch_lattice_dft(T, P->U.p, ufp32, G, ld, F.off[l], bn, pos, F.lat_count[l], USFFT_OUT_COMPLEX, R->C.p, G,
-                         st);
+      launch_lattice_dft(T, P->U.p, ufp32, G, ld, F.off[l], bn, pos, 0, F.lat_count[l], USFFT_OUT_COMPLEX, R->C.p,
+                         G, st);
       S.dft_launches += 1;
       S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 16.0;
     }
@@ -848,7 +856,7 @@ usfft_status usfft_lattice_dft(const void* u_dev, int32_t u_fp32, int64_t G, int
     RaderTables T;
     rader_build(T, M, st);
     try {
-      launch_lattice_dft(T, u_dev, u_fp32, G, ld, col0, bins_dev, pos_dev, nb, out_kind, out_dev, ldo, st);
+      launch_lattice_dft(T, u_dev, u_fp32, G, ld, col0, bins_dev, pos_dev, 0, nb, out_kind, out_dev, ldo, st);
       USFFT_HIP(hipStreamSynchronize(st));
     } catch (...) {
       rader_free(T);

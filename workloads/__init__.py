@@ -62,7 +62,7 @@ def uneven_batch(seed=1, jobs=12):
     return out
 
 
-def serving_stream(seed=1, rate=4.0, jobs=20, meshes=(32, 64), dims=(4, 30), Ns=(16, 64), ss=(50, 800)):
+def serving_stream(seed=1, rate=4.0, jobs=20, meshes=(16, 32, 64), dims=(4, 10), Ns=(16, 32), ss=(50, 200)):
     """Poisson arrivals (mean `rate` jobs/s) of jobs with random mesh, d, N and s."""
     g = np.random.default_rng(seed)
     t = 0.0
