@@ -134,6 +134,9 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=16,
                     help="jobs of the Poisson serving run reported beside the headline (0 = skip)")
+    ap.add_argument("--solver-config", type=int, default=-1,
+                    help="solver shape index (-1 = autotune); profiler runs pin one so that every "
+                         "counter pass sees the same kernel")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof byte counters)")
     args = ap.parse_args()
@@ -155,11 +158,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     prob, par = W.WORKLOADS[args.workload]
-    plan32 = U.Plan(prob, dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12))
+    plan32 = U.Plan(prob, dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12, solver_config=args.solver_config))
     wall32, lat32, st32, nI = run_path(U, plan32, args.seed, args.steps, args.warmup)
     out = {}
     if not args.skip_fp64:
-        plan64 = U.Plan(prob, dict(par, precision=U.FP64, pcg_rtol=1e-12))
+        plan64 = U.Plan(prob, dict(par, precision=U.FP64, pcg_rtol=1e-12, solver_config=args.solver_config))
         wall64, lat64, st64, _ = run_path(U, plan64, args.seed, args.steps, args.warmup)
         s64 = sum(s["samples"] for s in st64)
         out["fp64_path"] = {

@@ -43,6 +43,7 @@ typedef enum {
 enum { USFFT_SAMPLER_PDE = 0, USFFT_SAMPLER_TRIG_POLY = 1 };
 enum { USFFT_FP64 = 0, USFFT_FP32_REFINE = 1 };
 enum { USFFT_OUT_MAG2 = 0, USFFT_OUT_COMPLEX = 1 };
+enum { USFFT_PRECOND_DST = 0, USFFT_PRECOND_JACOBI = 1 };
 
 typedef struct usfft_plan_s* usfft_plan_t;
 typedef struct usfft_result_s* usfft_result_t;
@@ -98,8 +99,12 @@ typedef struct {
                               a float64 true-residual replacement (1e-3)    */
   int32_t refine_every;    /* FP32_REFINE: a float64 true residual at least
                               every this many iterations (200)              */
-  int32_t solver_config;   /* -1: autotune at plan time, -2: built-in choice,
-                              >= 0: force that workgroup shape              */
+  int32_t solver_config;   /* Jacobi solver: -1 autotune at plan time, -2
+                              built-in choice, >= 0 force that shape        */
+  int32_t precond;         /* USFFT_PRECOND_DST (fast-Poisson preconditioner,
+                              meshes with mesh_n <= 65) or USFFT_PRECOND_JACOBI;
+                              larger meshes always use the streaming Jacobi
+                              solver                                         */
 } usfft_params;
 
 /* Statistics of one usfft_detect run. */
@@ -115,6 +120,8 @@ typedef struct {
   int64_t dft_launches;     /* line + lattice DFT kernel launches            */
   int64_t solver_block;     /* workgroup size of the PDE solver              */
   int64_t solver_npt;       /* mesh nodes per thread of the PDE solver       */
+  int64_t solver_kind;      /* 0 DST-preconditioned PCG, 1 Jacobi PCG on
+                               chip, 2 streaming Jacobi PCG, -1 no PDE solve */
   double theta_abs;         /* absolute threshold used                       */
   double ms_sample;         /* device time in the sampler kernels            */
   double ms_dft;            /* device time in DFT kernels                    */

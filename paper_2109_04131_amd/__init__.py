@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, ELATTICE = 0, -1, -2, -3, -4, -5
 SAMPLER_PDE, SAMPLER_TRIG_POLY = 0, 1
 FP64, FP32_REFINE = 0, 1
 OUT_MAG2, OUT_COMPLEX = 0, 1
+PRECOND_DST, PRECOND_JACOBI = 0, 1
 KIND_LAT2, KIND_LAT3 = 3, 4
 
 _P32 = C.POINTER(C.c_int32)
@@ -38,14 +39,15 @@ class _Params(C.Structure):
                 ("theta_relative", C.c_int32), ("tie_rel", C.c_double), ("precision", C.c_int32),
                 ("lattice_c", C.c_double), ("lattice_tries", C.c_int32), ("lattice_max", C.c_int32),
                 ("lattice_mmax", C.c_int32), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32),
-                ("inner_rtol", C.c_double), ("refine_every", C.c_int32), ("solver_config", C.c_int32)]
+                ("inner_rtol", C.c_double), ("refine_every", C.c_int32), ("solver_config", C.c_int32),
+                ("precond", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("samples", C.c_int64), ("samples_step1", C.c_int64), ("samples_step2", C.c_int64),
                 ("samples_step3", C.c_int64), ("lattices", C.c_int64), ("max_candidates", C.c_int64),
                 ("pcg_iterations", C.c_int64), ("sample_launches", C.c_int64), ("dft_launches", C.c_int64),
-                ("solver_block", C.c_int64), ("solver_npt", C.c_int64),
+                ("solver_block", C.c_int64), ("solver_npt", C.c_int64), ("solver_kind", C.c_int64),
                 ("theta_abs", C.c_double), ("ms_sample", C.c_double),
                 ("ms_dft", C.c_double), ("ms_select", C.c_double), ("ms_total", C.c_double),
                 ("dft_bytes", C.c_double)]
@@ -129,7 +131,8 @@ def version():
 
 DEFAULT_PARAMS = dict(s=50, s_local=50, r=5, theta=1e-12, theta_relative=False, tie_rel=2.0 ** -30,
                       precision=FP64, lattice_c=2.0, lattice_tries=8, lattice_max=64, lattice_mmax=9601,
-                      pcg_rtol=1e-12, pcg_maxit=4000, inner_rtol=1e-3, refine_every=200, solver_config=-1)
+                      pcg_rtol=1e-12, pcg_maxit=4000, inner_rtol=1e-3, refine_every=200, solver_config=-1,
+                      precond=0)
 
 
 def _marshal(problem, params):

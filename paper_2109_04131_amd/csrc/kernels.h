@@ -36,6 +36,16 @@ int64_t stream_workspace_doubles(int n, int blocks);
 void launch_pde_solve_stream(const PdeDev& P, const double* Y, int64_t ns, double rtol, int maxit, void* out,
                              int out_fp32, int64_t ld, int64_t col0, int* iters, double* ws, int blocks,
                              hipStream_t st);
+// ---- pcgdst.hip: DST-preconditioned solver for meshes with n - 1 <= 64
+int dst_padded(int n);             // MP = 32 or 64, 0 if the mesh is too large
+int64_t dst_frag_bytes(int mp);    // S fragment table of one mesh size
+void dst_tables_build(int n, void* frag, float* lam, hipStream_t st);  // lam: MP floats
+int dst_persistent_blocks(int n, int precision);
+int64_t dst_edge_stride(int mp);   // doubles per edge grid; the scratch holds 2 per workgroup
+void launch_pde_solve_dst(const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol, int maxit,
+                          double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld, int64_t col0,
+                          int* iters, double* wscr, int wblocks, const void* frag, const float* lam,
+                          hipStream_t st);
 void launch_trigpoly(int d, const double* Y, int64_t ns, const int32_t* K, int64_t np, const double* C,
                      int64_t G, void* out, int out_fp32, int64_t ld, int64_t col0, hipStream_t st);
 

@@ -1,0 +1,477 @@
+// Batched PDE solves with a fast-Poisson preconditioner on the matrix cores.
+//
+// The sampler of the usFFT (Sec. 2.1, Alg. 1 steps 1&2a, 2c, 3) solves one
+// P1 system A(y) u = b per sampling node.  A(y) is the 5-point operator of
+// the uniform mesh whose off-diagonal weights are edge weights
+// w_e = (a_T1 + a_T2)/2, with the diagonal equal to the sum of the four edge
+// weights of a node and b = h^2 for f = 1.  The paper treats the solver as a
+// black box; here it is conjugate gradients on the symmetrically scaled system
+//     At = D^-1/2 A D^-1/2,  bt = D^-1/2 b,  u = D^-1/2 ut,  D = diag(A) / 4,
+// whose diagonal is exactly 4, preconditioned by the inverse of the
+// constant-coefficient 5-point Laplacian L (Dirichlet, m = n-1 nodes per
+// line).  L is diagonalised by the orthonormal DST-I matrix
+//     S[i][k] = sqrt(2/n) sin(pi (i+1)(k+1) / n),  S S = I,
+// with eigenvalues lambda_p + lambda_q, lambda_p = 4 sin^2(pi (p+1) / (2n)),
+// so  L^-1 R = S (Lam o (S R S)) S,  Lam[p][q] = 1 / (lambda_p + lambda_q),
+// for the grid function R as an m x m matrix.  For the smooth coefficients of
+// the workloads the scaled operator is close to L, and CG needs about ten
+// iterations to 1e-12 instead of a few hundred with Jacobi scaling.
+//
+// One workgroup owns one sample at a time (persistent over samples).  The
+// grid is padded to MP x MP (MP = 32 or 64); wave w owns the 16-column strip
+// c = 16 w + (lane & 15) and lane l holds rows 16 t + 4 (l >> 4) + v of it,
+// t < MP/16, v < 4: exactly the accumulator layout of the 16x16 MFMA tiles.
+// The four 64x64x64 products of one preconditioner application run as
+// v_mfma_f32_16x16x32_f16 in this layout:
+//     T1 = R^T S   (the residual registers are the A operand of R^T),
+//     Wt = S T1    (T1 moved through LDS to column strips),
+//     Yt = Lam o Wt,
+//     T3 = Y S     (the accumulators are the A operand of Y),
+//     Z  = S T3    (T3 moved through LDS), Z in the residual's layout.
+// Inputs are scaled by a power of two from the last residual norm before the
+// conversion to fp16, so every operand stays in fp16's range; the
+// preconditioner only steers the iteration, the residual that decides
+// convergence is formed in the solver's own precision.
+//
+// Float64 solves keep every vector and the weights in float64.  Float32
+// solves keep them in float32 with float64 reliable updates (the float64
+// iterate u lives in LDS; whenever the float32 recursive residual has dropped
+// by inner_rtol, u += D^-1/2 dx and the true residual b - A u is formed in
+// float64 from the exact float64 edge grids).  Both stop on the scaled
+// residual |D^-1/2 (b - A u)| <= rtol |D^-1/2 b|; float32 solves stop only on
+// a float64 true residual.  Reductions combine wave partials in a fixed order.
+#include <type_traits>
+
+#include "kernels.h"
+#include "pde_device.h"
+
+namespace usfft {
+
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Slot j (0..7) of lane group q in a 32-deep contraction block stands for
+// index kappa(q, j) of that block: rows 4q..4q+3 of its first and of its
+// second 16-row tile, which are the two accumulator fragments a lane holds.
+// Any bijection works as long as both operands use the same one.
+__host__ __device__ constexpr int kappa(int q, int j) { return j < 4 ? 4 * q + j : 16 + 4 * q + (j - 4); }
+
+int dst_padded(int n) {
+  const int m = n - 1;
+  return m <= 32 ? 32 : (m <= 64 ? 64 : 0);
+}
+
+int64_t dst_frag_bytes(int mp) { return (int64_t)(mp / 32) * (mp / 16) * 64 * (int64_t)sizeof(half8); }
+
+// frag[(kb * NT + t) * 64 + lane][j] = S[32 kb + kappa(q, j)][16 t + (lane & 15)]
+// (zero outside the m x m block); lam[p] = lambda_p (1 on padding, where the
+// transformed residual is exactly zero).
+__global__ void dst_tables_kernel(int n, int mp, half8* __restrict__ frag, float* __restrict__ lam) {
+  const int nt = mp / 16, nkb = mp / 32, m = n - 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nkb * nt * 64) {
+    const int lane = e & 63, f = e >> 6, kb = f / nt, t = f % nt;
+    const int q = lane >> 4, col = 16 * t + (lane & 15);
+    const double sc = sqrt(2.0 / n);
+    half8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int row = 32 * kb + kappa(q, j);
+      const double s = (row < m && col < m) ? sc * sinpi((double)((row + 1) * (col + 1)) / n) : 0.0;
+      v[j] = (_Float16)(float)s;
+    }
+    frag[e] = v;
+  }
+  if (e < mp) {
+    const double sv = sinpi((e + 1) / (2.0 * n));
+    lam[e] = e < m ? (float)(4.0 * sv * sv) : 1.0f;
+  }
+}
+
+void dst_tables_build(int n, void* frag, float* lam, hipStream_t st) {
+  const int mp = dst_padded(n);
+  const int cnt = (mp / 32) * (mp / 16) * 64;
+  hipLaunchKernelGGL(dst_tables_kernel, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, n, mp,
+                     static_cast<half8*>(frag), lam);
+  USFFT_HIP(hipGetLastError());
+}
+
+__device__ __forceinline__ void store_h4(_Float16* p, floatx4 a) {
+  half4 h = {(_Float16)a[0], (_Float16)a[1], (_Float16)a[2], (_Float16)a[3]};
+  *reinterpret_cast<half4*>(p) = h;
+}
+
+// B-operand fragment of a column-major exchange tile: rows r0 + 0..3 and
+// r0 + 16..19 of one column.
+__device__ __forceinline__ half8 load_h8(const _Float16* p) {
+  const half4 lo = *reinterpret_cast<const half4*>(p);
+  const half4 hi = *reinterpret_cast<const half4*>(p + 16);
+  return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+// z = L^-1 r for the wave's strip (see the file comment).  r and z are in
+// the node layout; sc scales r before the fp16 conversion (z is scaled back).
+template <int MP, typename T>
+__device__ __forceinline__ void dst_apply(const T (&r)[MP / 4], float sc, float (&z)[MP / 4],
+                                          const half8 (&sf)[(MP / 32) * (MP / 16)], _Float16* xa, _Float16* xb,
+                                          const float* lam) {
+  constexpr int NT = MP / 16, KB = MP / 32, LDX = MP + 4;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
+  half8 a[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[kb][j] = (_Float16)((float)r[4 * (2 * kb + (j >> 2)) + (j & 3)] * sc);
+  floatx4 acc[NT];
+  // T1 = R^T S: row strip w of T1
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[kb], sf[kb * NT + t], acc[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) store_h4(xa + (16 * t + c16) * LDX + 16 * w + 4 * q, acc[t]);
+  __syncthreads();
+  // Wt = S T1: column strip w of Wt, then Yt = Lam o Wt
+  half8 b[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) b[kb] = load_h8(xa + (16 * w + c16) * LDX + 32 * kb + 4 * q);
+  const float lc = lam[16 * w + c16];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(sf[kb * NT + t], b[kb], acc[t], 0, 0, 0);
+    const floatx4 lr = *reinterpret_cast<const floatx4*>(lam + 16 * t + 4 * q);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[t][v] *= __builtin_amdgcn_rcpf(lr[v] + lc);
+  }
+  // T3 = Y S: row strip w of T3
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[kb][j] = (_Float16)acc[2 * kb + (j >> 2)][j & 3];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[kb], sf[kb * NT + t], acc[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) store_h4(xb + (16 * t + c16) * LDX + 16 * w + 4 * q, acc[t]);
+  __syncthreads();
+  // Z = S T3: column strip w of Z, the node layout
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) b[kb] = load_h8(xb + (16 * w + c16) * LDX + 32 * kb + 4 * q);
+  const float isc = 1.0f / sc;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    acc[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(sf[kb * NT + t], b[kb], acc[t], 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) z[4 * t + v] = acc[t][v] * isc;
+  }
+}
+
+// 2^-round(log2 |r|) from |r|^2, so the scaled residual has norm ~1.
+__device__ __forceinline__ float pow2_scale(double rr) {
+  if (!(rr > 0.0) || !(rr < 1e300)) return 1.0f;
+  const int e = ilogb(rr) / 2;
+  return ldexpf(1.0f, -(e < -100 ? -100 : (e > 100 ? 100 : e)));
+}
+
+// D^-1/2 at grid index l from the exact float64 edge grids.
+__device__ __forceinline__ double jacobi_isqrt(const double* eh, const double* ev, int l, int P1) {
+  return 1.0 / sqrt(0.25 * (eh[l] + eh[l - 1] + ev[l] + ev[l - P1]));
+}
+
+// LDS grids of one workgroup have the compile-time pitch PP = MP + 2 >= n + 1
+// (zero halo at rows/columns 0 and n, unused space beyond), so every stencil
+// access is a base register plus an immediate offset.
+__host__ __device__ constexpr int dst_pitch(int mp) { return mp + 2; }
+__host__ __device__ constexpr int64_t dst_grid_elems(int mp) {
+  return ((int64_t)dst_pitch(mp) * dst_pitch(mp) + 3) / 4 * 4;
+}
+
+// Resident waves per SIMD the register allocation targets: float32 state fits
+// two 64-wide strips per SIMD (two samples per CU at MP = 64), float64 state
+// one.
+template <typename T, int MP>
+constexpr int dst_waves() {
+  return std::is_same<T, float>::value ? (MP == 64 ? 2 : 3) : (MP == 64 ? 1 : 2);
+}
+
+// Doubles of one workgroup's edge grid in the global scratch (pitch PP).
+int64_t dst_edge_stride(int mp) { return ((int64_t)dst_pitch(mp) * dst_pitch(mp) + 31) / 32 * 32; }
+
+// Dynamic LDS bytes of one workgroup.
+int64_t dst_lds_bytes(int n, int precision) {
+  const int mp = dst_padded(n);
+  const int64_t g = dst_grid_elems(mp);
+  const int64_t grids = precision == USFFT_FP64 ? g * 8 : g * 8 + g * 4;
+  return grids + 2 * (int64_t)mp * (mp + 4) * 2;
+}
+
+template <typename T, int MP>
+__global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_waves<T, MP>()))) void pcgdst_kernel(
+    PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, double inner_rtol, int refine_every,
+    void* __restrict__ out, int out_fp32, int64_t ld, int64_t col0, int* __restrict__ iters,
+    double* __restrict__ wscr, int64_t wstride, const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
+  constexpr int NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
+  constexpr int PP = dst_pitch(MP);
+  constexpr int64_t GE = dst_grid_elems(MP);
+  constexpr bool REFINE = std::is_same<T, float>::value;
+  extern __shared__ double lds[];
+  __shared__ double coef[kMaxD];
+  __shared__ double red0[2 * (BLOCK / kWave)];
+  __shared__ double red1[2 * (BLOCK / kWave)];
+  __shared__ __attribute__((aligned(16))) float slam[MP];
+  const int n = P.n, m = n - 1;
+  double* sx = lds;                                          // float32 path: float64 iterate u
+  T* sp = reinterpret_cast<T*>(lds + (REFINE ? GE : 0));    // search direction (zero halo), staging
+  _Float16* xa = reinterpret_cast<_Float16*>(sp + GE);      // exchange tiles, column-major
+  _Float16* xb = xa + MP * LDX;
+  double* sd = REFINE ? sx : reinterpret_cast<double*>(sp);  // D^-1/2 during set-up
+  // this workgroup's float64 edge grids, pitch PP like the LDS grids
+  double* eh = wscr + (size_t)blockIdx.x * 2 * wstride;
+  double* ev = eh + wstride;
+
+  const int lane = threadIdx.x & 63;
+  half8 sf[KB * NT];
+#pragma unroll
+  for (int f = 0; f < KB * NT; ++f) sf[f] = sfrag[f * 64 + lane];
+  for (int i = threadIdx.x; i < MP; i += BLOCK) slam[i] = lamtab[i];
+  for (int64_t e = threadIdx.x; e < GE; e += BLOCK) {
+    sp[e] = (T)0;
+    if (REFINE) sx[e] = 0.0;
+  }
+
+  for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
+    // lane coordinates are re-derived per sample (opaque to the optimiser):
+    // hoisted out of the sample loop, per-node addresses would spill
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int q = (tid & 63) >> 4, c = 16 * (tid >> 6) + (tid & 15);
+    // node e = 4 t + v of this lane: row 16 t + 4 q + v, column c, grid index
+    // base + off(e); padding nodes (row or column >= m) carry zeros, their
+    // slots lie on the zero halo or beyond it
+    const int base = (4 * q + 1) * PP + c + 1;
+    T* spl = sp + base;
+    auto off = [](int e) { return (16 * (e >> 2) + (e & 3)) * PP; };
+    __syncthreads();  // the previous sample is done with LDS, coef and the edge grids
+    load_coef(P, Y, s, coef);
+    __syncthreads();
+    fill_edges<double>(P, coef, eh, ev, PP);
+    __syncthreads();
+    for (int g = tid; g < m * m; g += BLOCK) {
+      const int k = (g / m + 1) * PP + g % m + 1;
+      sd[k] = jacobi_isqrt(eh, ev, k, PP);
+    }
+    __syncthreads();
+    // scaled weights: wE, wW, wS per node; wN(v) = wS(v + 1) inside a 4-row
+    // group, so only the top row of each group keeps its own (wN4)
+    T wE[E], wW[E], wS[E], wN4[NT], r[E], p[E], dx[E];
+    double bb = 0.0;
+    {
+      const double* sdl = sd + base;
+      const double* ehl = eh + base;
+      const double* evl = ev + base;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int t = e >> 2, v = e & 3, row = 16 * t + 4 * q + v, o = off(e);
+        dx[e] = (T)0;
+        wE[e] = wW[e] = wS[e] = r[e] = (T)0;
+        if (v == 3) wN4[t] = (T)0;
+        if (row < m && c < m) {
+          const double di = sdl[o];
+          wE[e] = (T)(ehl[o] * di * sdl[o + 1]);
+          wW[e] = (T)(ehl[o - 1] * di * sdl[o - 1]);
+          wS[e] = (T)(evl[o - PP] * di * sdl[o - PP]);
+          if (v == 3) wN4[t] = (T)(evl[o] * di * sdl[o + PP]);
+          const double bt = di * P.h2;
+          r[e] = (T)bt;
+          bb += bt * bt;
+        }
+      }
+    }
+    bb = block_sum<BLOCK>(bb, red0);  // its barrier also ends the reads of sd
+    for (int g = tid; g < m * m; g += BLOCK) sd[(g / m + 1) * PP + g % m + 1] = 0.0;  // u = 0 / p = 0
+    float z[E];
+    dst_apply<MP, T>(r, pow2_scale(bb), z, sf, xa, xb, slam);
+    double rz = 0.0, rr = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      p[e] = (T)z[e];
+      rz += (double)r[e] * (double)z[e];
+      rr += (double)r[e] * (double)r[e];
+    }
+    block_sum2<BLOCK>(rz, rr, red1);
+    const double stop = rtol * rtol * bb;
+    const double drop = inner_rtol * inner_rtol;
+    double rr_ref = rr;
+    int it = 0, last_update = 0;
+    bool conv = !(bb > 0.0);
+    while (!conv && it < maxit) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) spl[off(e)] = p[e];
+      __syncthreads();
+      T qv[E];
+      double pq = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int o = off(e);
+        const T wn = (e & 3) == 3 ? wN4[e >> 2] : wS[e + 1];
+        qv[e] = (T)4 * p[e] - (wE[e] * spl[o + 1] + wW[e] * spl[o - 1] + wn * spl[o + PP] + wS[e] * spl[o - PP]);
+        pq += (double)(p[e] * qv[e]);
+      }
+      pq = block_sum<BLOCK>(pq, red0);
+      const T alpha = (T)(rz / pq);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        dx[e] += alpha * p[e];
+        r[e] -= alpha * qv[e];
+      }
+      dst_apply<MP, T>(r, pow2_scale(rr), z, sf, xa, xb, slam);
+      double rz2 = 0.0;
+      rr = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        rz2 += (double)r[e] * (double)z[e];
+        rr += (double)r[e] * (double)r[e];
+      }
+      block_sum2<BLOCK>(rz2, rr, red1);
+      ++it;
+      if (REFINE) {
+        if (rr <= drop * rr_ref || it - last_update >= refine_every) {
+          // u += D^-1/2 dx in float64 (dx staged in LDS), then the float64 true
+          // residual (scaled) replaces the float32 one; the search direction
+          // is kept
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            spl[off(e)] = dx[e];
+            dx[e] = (T)0;
+          }
+          __syncthreads();
+          for (int g = tid; g < m * m; g += BLOCK) {
+            const int k = (g / m + 1) * PP + g % m + 1;
+            sx[k] += jacobi_isqrt(eh, ev, k, PP) * (double)sp[k];
+          }
+          __syncthreads();
+          double rr64 = 0.0;
+          for (int g = tid; g < m * m; g += BLOCK) {
+            const int k = (g / m + 1) * PP + g % m + 1;
+            const double xc = sx[k];
+            const double ax = eh[k] * (xc - sx[k + 1]) + eh[k - 1] * (xc - sx[k - 1]) +
+                              ev[k] * (xc - sx[k + PP]) + ev[k - PP] * (xc - sx[k - PP]);
+            const double rs = jacobi_isqrt(eh, ev, k, PP) * (P.h2 - ax);
+            rr64 += rs * rs;
+            sp[k] = (T)rs;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int e = 0; e < E; ++e) r[e] = spl[off(e)];
+          rr64 = block_sum<BLOCK>(rr64, red0);
+          last_update = it;
+          if (rr64 <= stop) {
+            conv = true;
+            break;
+          }
+          dst_apply<MP, T>(r, pow2_scale(rr64), z, sf, xa, xb, slam);
+          rz2 = 0.0;
+          rr = 0.0;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            rz2 += (double)r[e] * (double)z[e];
+            rr += (double)r[e] * (double)r[e];
+          }
+          block_sum2<BLOCK>(rz2, rr, red1);
+          rr_ref = rr;
+        }
+      } else if (rr <= stop) {
+        conv = true;
+        break;
+      }
+      const T beta = (T)(rz2 / rz);
+      rz = rz2;
+#pragma unroll
+      for (int e = 0; e < E; ++e) p[e] = (T)z[e] + beta * p[e];
+    }
+    // u = D^-1/2 ut: float64 solves hold ut in dx, float32 solves the
+    // correction not yet folded into u
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) spl[off(e)] = dx[e];
+    __syncthreads();
+    for (int g = tid; g < m * m; g += BLOCK) {
+      const int k = (g / m + 1) * PP + g % m + 1;
+      const double d = jacobi_isqrt(eh, ev, k, PP) * (double)sp[k];
+      store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, REFINE ? sx[k] + d : d);
+    }
+    if (tid == 0 && iters) iters[s] = conv ? it : -1;
+  }
+}
+
+template <typename T, int MP>
+static int dst_occupancy(int n) {
+  int per_cu = 0;
+  USFFT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(pcgdst_kernel<T, MP>), 4 * MP,
+      dst_lds_bytes(n, std::is_same<T, float>::value ? USFFT_FP32_REFINE : USFFT_FP64)));
+  return std::max(1, per_cu);
+}
+
+int dst_persistent_blocks(int n, int precision) {
+  static int cache[2][2] = {{0, 0}, {0, 0}};  // [fp32?][mp == 64?]
+  const int mp = dst_padded(n);
+  const int a = precision == USFFT_FP64 ? 0 : 1, b = mp == 64 ? 1 : 0;
+  if (cache[a][b] == 0) {
+    int cus = 0, dev = 0;
+    USFFT_HIP(hipGetDevice(&dev));
+    USFFT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = 1;
+    if (a == 0)
+      per_cu = b ? dst_occupancy<double, 64>(n) : dst_occupancy<double, 32>(n);
+    else
+      per_cu = b ? dst_occupancy<float, 64>(n) : dst_occupancy<float, 32>(n);
+    cache[a][b] = per_cu * std::max(1, cus);
+  }
+  return cache[a][b];
+}
+
+void launch_pde_solve_dst(const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol, int maxit,
+                          double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld, int64_t col0,
+                          int* iters, double* wscr, int wblocks, const void* frag, const float* lam,
+                          hipStream_t st) {
+  if (ns <= 0) return;
+  const int mp = dst_padded(P.n);
+  USFFT_REQUIRE(mp > 0, USFFT_EINVAL, "mesh too large for the DST-preconditioned solver");
+  const int64_t ws = dst_edge_stride(mp);
+  const unsigned grid = (unsigned)std::min<int64_t>(ns, wblocks);
+  const size_t lds = (size_t)dst_lds_bytes(P.n, precision);
+  const half8* sf = static_cast<const half8*>(frag);
+  if (precision == USFFT_FP64) {
+    if (mp == 64)
+      hipLaunchKernelGGL((pcgdst_kernel<double, 64>), dim3(grid), dim3(256), lds, st, P, Y, ns, rtol, maxit,
+                         inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+    else
+      hipLaunchKernelGGL((pcgdst_kernel<double, 32>), dim3(grid), dim3(128), lds, st, P, Y, ns, rtol, maxit,
+                         inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+  } else {
+    if (mp == 64)
+      hipLaunchKernelGGL((pcgdst_kernel<float, 64>), dim3(grid), dim3(256), lds, st, P, Y, ns, rtol, maxit,
+                         inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+    else
+      hipLaunchKernelGGL((pcgdst_kernel<float, 32>), dim3(grid), dim3(128), lds, st, P, Y, ns, rtol, maxit,
+                         inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+  }
+  USFFT_HIP(hipGetLastError());
+}
+
+}  // namespace usfft

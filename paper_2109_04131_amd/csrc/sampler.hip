@@ -12,6 +12,7 @@
 // fixed order, so a sample's result does not depend on which block or batch
 // runs it.
 #include "kernels.h"
+#include "pde_device.h"
 
 namespace usfft {
 
@@ -39,72 +40,6 @@ __global__ void nodes_kernel(int d, int line, int t, int nlat, const int64_t* __
     y = (double)r / (double)M;
   }
   Y[e] = y;
-}
-
-// ---------------------------------------------------------------- weights
-// Centroid value of a on the lower (q=0) / upper (q=1) triangle of cell (ci, cj).
-// tab holds sin(m1 pi x1), sin(m2 pi x2) at the centroid abscissae:
-// [0] x1 of lower, [1] x1 of upper, [2] x2 of lower, [3] x2 of upper; each d x n.
-__device__ __forceinline__ double tri_coef(const PdeDev& P, const double* coef, int q, int ci, int cj) {
-  const double* tx = P.tab + (size_t)(q) * P.d * P.n;
-  const double* ty = P.tab + (size_t)(2 + q) * P.d * P.n;
-  double a = P.a0;
-#pragma unroll 1
-  for (int k = 0; k < P.d; ++k) a += coef[k] * tx[k * P.n + ci] * ty[k * P.n + cj];
-  return a;
-}
-
-// The four edge weights of interior node (i, j), 1 <= i, j <= n-1.
-__device__ __forceinline__ void node_weights(const PdeDev& P, const double* coef, int i, int j,
-                                             double& wE, double& wW, double& wN, double& wS) {
-  const double aL_ij = tri_coef(P, coef, 0, i, j);
-  const double aU_ij = tri_coef(P, coef, 1, i, j);
-  const double aU_ijm = tri_coef(P, coef, 1, i, j - 1);
-  const double aL_imj = tri_coef(P, coef, 0, i - 1, j);
-  const double aU_imjm = tri_coef(P, coef, 1, i - 1, j - 1);
-  const double aL_imjm = tri_coef(P, coef, 0, i - 1, j - 1);
-  wE = 0.5 * (aL_ij + aU_ijm);    // edge (i,j)-(i+1,j): lower of cell (i,j), upper of (i,j-1)
-  wW = 0.5 * (aL_imj + aU_imjm);  // edge (i-1,j)-(i,j)
-  wN = 0.5 * (aU_ij + aL_imj);    // edge (i,j)-(i,j+1): upper of cell (i,j), lower of (i-1,j)
-  wS = 0.5 * (aU_ijm + aL_imjm);  // edge (i,j-1)-(i,j)
-}
-
-// Weight of horizontal edge (i,j)-(i+1,j), 0 <= i <= n-1: lower triangle of
-// cell (i,j) and upper triangle of cell (i,j-1).
-__device__ __forceinline__ double edge_h(const PdeDev& P, const double* coef, int i, int j) {
-  return 0.5 * (tri_coef(P, coef, 0, i, j) + tri_coef(P, coef, 1, i, j - 1));
-}
-// Weight of vertical edge (i,j)-(i,j+1), 0 <= j <= n-1: upper triangle of
-// cell (i,j) and lower triangle of cell (i-1,j).
-__device__ __forceinline__ double edge_v(const PdeDev& P, const double* coef, int i, int j) {
-  return 0.5 * (tri_coef(P, coef, 1, i, j) + tri_coef(P, coef, 0, i - 1, j));
-}
-
-// Fill the edge grids of one sample in LDS: eh[j*P1 + i] = edge_h(i, j) for
-// 0 <= i <= n-1, 1 <= j <= n-1 and ev[j*P1 + i] = edge_v(i, j) for
-// 1 <= i <= n-1, 0 <= j <= n-1 (every edge touching an interior node).
-template <typename T>
-__device__ void fill_edges(const PdeDev& P, const double* coef, T* eh, T* ev) {
-  const int n = P.n, P1 = n + 1, cnt = n * (n - 1);
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-    const int i = e % n, j = e / n + 1;  // horizontal: i in [0, n-1], j in [1, n-1]
-    eh[j * P1 + i] = (T)edge_h(P, coef, i, j);
-    const int vi = e / n + 1, vj = e % n;  // vertical: i in [1, n-1], j in [0, n-1]
-    ev[vj * P1 + vi] = (T)edge_v(P, coef, vi, vj);
-  }
-}
-
-__device__ __forceinline__ void load_coef(const PdeDev& P, const double* __restrict__ Y, int64_t s,
-                                          double* coef) {
-  for (int k = threadIdx.x; k < P.d; k += blockDim.x) coef[k] = P.amp[k] * sinpi(2.0 * Y[s * P.d + k]);
-}
-
-template <typename T>
-__device__ __forceinline__ void store_sample(void* out, int out_fp32, int64_t idx, T v) {
-  if (out_fp32)
-    static_cast<float*>(out)[idx] = (float)v;
-  else
-    static_cast<double*>(out)[idx] = (double)v;
 }
 
 // ---------------------------------------------------------------- FP64 PCG

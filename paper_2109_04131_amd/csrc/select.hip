@@ -8,7 +8,8 @@
 // numeric order): 8 passes of 8-bit digits with an LDS histogram, over the
 // column staged once in LDS when it fits.  A
 // candidate is kept when v >= max(theta^2, (1 - tie) tau_g^2); each wave ORs
-// its 64 keep bits into the global candidate mask with two word atomics.
+// its 64 keep bits into the global candidate mask, with an atomic only for
+// bits not yet set.
 #include "kernels.h"
 
 namespace usfft {
@@ -105,10 +106,16 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
     const bool keep = a < n && col[a] >= thr;
     const uint64_t bal = __ballot(keep);
     if (lane == 0 && bal) {
+      // Most nodes keep the same candidates, so most bits are already set by
+      // other workgroups: check the word first (bits are only ever set, so a
+      // stale read can only cost an unneeded atomic) and skip the atomic --
+      // all G workgroups would otherwise serialise on the same few words.
       const int64_t w = a0 >> 5;  // a0 is a multiple of 64
       const uint32_t lo = (uint32_t)(bal & 0xffffffffull), hi = (uint32_t)(bal >> 32);
-      if (lo) atomicOr(&mask[w], lo);
-      if (hi) atomicOr(&mask[w + 1], hi);
+      if (lo && (__hip_atomic_load(&mask[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & lo) != lo)
+        atomicOr(&mask[w], lo);
+      if (hi && (__hip_atomic_load(&mask[w + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & hi) != hi)
+        atomicOr(&mask[w + 1], hi);
     }
   }
 }

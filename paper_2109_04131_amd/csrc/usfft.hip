@@ -116,9 +116,10 @@ struct usfft_plan_s {
   int64_t G = 0;
   int solver_cfg = 0;
   // static device tables
-  usfft::DevBuf d_amp, d_tab, d_polyk, d_polyc, d_stream, d_wscr;
-  int wblocks = 0;  // persistent workgroups of the float32 solver
-  bool streaming = false;  // mesh larger than the on-chip solver holds
+  usfft::DevBuf d_amp, d_tab, d_polyk, d_polyc, d_stream, d_wscr, d_sfrag, d_lam;
+  int wblocks = 0;  // persistent workgroups of the float32 / DST solver
+  bool streaming = false;  // mesh larger than the on-chip solvers hold
+  bool dst = false;        // DST-preconditioned solver
   usfft::PdeDev pde{};
   // Rader tables per lattice size
   std::map<int, usfft::RaderTables> rader;
@@ -250,7 +251,11 @@ static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
                         int64_t col0, int32_t* iters, hipStream_t st) {
   if (ns <= 0) return;
   const usfft_params& par = P->par;
-  if (P->prob.sampler == USFFT_SAMPLER_PDE && P->streaming) {
+  if (P->prob.sampler == USFFT_SAMPLER_PDE && P->dst) {
+    launch_pde_solve_dst(P->pde, par.precision, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
+                         par.refine_every, U, out_fp32, ld, col0, iters, P->d_wscr.as<double>(), P->wblocks,
+                         P->d_sfrag.p, P->d_lam.as<float>(), st);
+  } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->streaming) {
     launch_pde_solve_stream(P->pde, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
                             P->d_stream.as<double>(), kStreamBlocks, st);
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE) {
@@ -539,11 +544,19 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
   }
   USFFT_HIP(hipStreamSynchronize(st));
   S.samples = S.samples_step1 + S.samples_step2 + S.samples_step3;
-  if (pb.sampler == USFFT_SAMPLER_PDE && !P->streaming) {
+  S.solver_kind = -1;
+  if (pb.sampler == USFFT_SAMPLER_PDE && P->dst) {
+    S.solver_block = 4 * dst_padded(P->prob.mesh_n);
+    S.solver_npt = dst_padded(P->prob.mesh_n) / 4;
+    S.solver_kind = 0;
+  } else if (pb.sampler == USFFT_SAMPLER_PDE && !P->streaming) {
     int blk = 0, npt = 0;
     solver_config_shape(P->solver_cfg, &blk, &npt);
     S.solver_block = blk;
     S.solver_npt = npt;
+    S.solver_kind = 1;
+  } else if (pb.sampler == USFFT_SAMPLER_PDE) {
+    S.solver_kind = 2;
   }
   S.ms_sample = tm.total(kTSample);
   S.ms_dft = tm.total(kTDft);
@@ -622,6 +635,8 @@ static void validate(const usfft_problem* pb, const usfft_params* par) {
                 USFFT_EINVAL, "bad lattice parameters (lattice_mmax <= 9601)");
   USFFT_REQUIRE(par->pcg_rtol > 0 && par->pcg_maxit >= 1 && par->inner_rtol > 0 && par->refine_every >= 1,
                 USFFT_EINVAL, "bad solver parameters");
+  USFFT_REQUIRE(par->precond == USFFT_PRECOND_DST || par->precond == USFFT_PRECOND_JACOBI, USFFT_EINVAL,
+                "bad preconditioner");
   if (pb->sampler == USFFT_SAMPLER_PDE) {
     USFFT_REQUIRE(pb->mesh_n >= 4 && pb->mesh_n <= kMaxMeshStream, USFFT_EINVAL, "mesh_n must be in [4, 512]");
     USFFT_REQUIRE(pb->amp && pb->mode1 && pb->mode2, USFFT_EINVAL, "missing coefficient family");
@@ -672,7 +687,18 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     P->pde.h2 = h * h;
     P->pde.amp = P->d_amp.as<double>();
     P->pde.tab = P->d_tab.as<double>();
-    if (n > kMaxMesh) {
+    if (par->precond == USFFT_PRECOND_DST && dst_padded(n) > 0) {
+      // fast-Poisson preconditioned PCG on the matrix cores
+      P->dst = true;
+      P->solver_cfg = -1;
+      const int mp = dst_padded(n);
+      P->d_sfrag.ensure((size_t)dst_frag_bytes(mp));
+      P->d_lam.ensure(sizeof(float) * mp);
+      dst_tables_build(n, P->d_sfrag.p, P->d_lam.as<float>(), nullptr);
+      USFFT_HIP(hipStreamSynchronize(nullptr));
+      P->wblocks = dst_persistent_blocks(n, par->precision);
+      P->d_wscr.ensure(sizeof(double) * 2 * (size_t)dst_edge_stride(mp) * P->wblocks);
+    } else if (n > kMaxMesh) {
       // per-sample state exceeds one CU: streaming float64 solver
       P->streaming = true;
       P->solver_cfg = -1;
@@ -686,8 +712,8 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     } else {
       P->solver_cfg = autotune_solver(P.get());
     }
-    USFFT_REQUIRE(P->streaming || P->solver_cfg >= 0, USFFT_EINVAL, "no solver shape for this mesh");
-    if (!P->streaming) {
+    USFFT_REQUIRE(P->dst || P->streaming || P->solver_cfg >= 0, USFFT_EINVAL, "no solver shape for this mesh");
+    if (!P->streaming && !P->dst) {
       P->wblocks = persistent_blocks(P->solver_cfg, n);
       P->d_wscr.ensure(sizeof(double) * (size_t)edge_scratch_doubles(n, P->wblocks));
     }

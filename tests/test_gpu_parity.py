@@ -51,13 +51,18 @@ def test_nodes_line_and_lattice_bit_exact(lib):
 
 
 # ------------------------------------------------------------------ sampler
+@pytest.mark.parametrize("precond", [0, 1], ids=["dst", "jacobi"])
 @pytest.mark.parametrize("n,d,modes,prec,tol", [
-    (8, 3, "diagonal", 0, 1e-11), (16, 4, "diagonal", 0, 1e-11), (33, 6, "split", 0, 1e-11),
-    (64, 10, "split", 0, 1e-11), (16, 4, "diagonal", 1, 1e-9), (64, 10, "split", 1, 1e-9)])
-def test_pde_solves_match_banded_cholesky(lib, n, d, modes, prec, tol):
+    (4, 2, "diagonal", 0, 1e-11), (8, 3, "diagonal", 0, 1e-11), (16, 4, "diagonal", 0, 1e-11),
+    (33, 6, "split", 0, 1e-11), (34, 6, "split", 0, 1e-11), (64, 10, "split", 0, 1e-11),
+    (65, 10, "split", 0, 1e-11), (16, 4, "diagonal", 1, 1e-9), (33, 6, "split", 1, 1e-9),
+    (64, 10, "split", 1, 1e-9), (65, 10, "split", 1, 1e-9)])
+def test_pde_solves_match_banded_cholesky(lib, n, d, modes, prec, tol, precond):
+    # n = 33 and 65 fill the padded 32 / 64 transform exactly, n = 34 is the
+    # first mesh padded to 64, n = 4 the smallest (Jacobi: n = 65 streams)
     prob = W.pde_problem(n, d, 4, modes=modes)
     plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-13 if prec == 0 else 1e-12,
-                               solver_config=-2))
+                               solver_config=-2, precond=precond))
     g = np.random.default_rng(n * 10 + d + prec)
     ns = 37
     Y = g.random((ns, d))
@@ -84,7 +89,7 @@ def test_solver_shapes_agree_and_batch_independent(lib):
     outs = []
     for cfg in range(15):
         try:
-            plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), pcg_rtol=1e-13, solver_config=cfg))
+            plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), pcg_rtol=1e-13, solver_config=cfg, precond=1))
         except lib.UsfftError:
             continue
         U = torch.zeros((plan.G, 20), dtype=torch.float64, device="cuda")
@@ -96,6 +101,43 @@ def test_solver_shapes_agree_and_batch_independent(lib):
     assert len(outs) >= 2
     for o in outs[1:]:
         assert np.abs(o - outs[0]).max() <= 1e-12 * np.abs(outs[0]).max()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dst_solver_batch_independent_and_fast(lib, prec):
+    # a sample's DST-PCG solution does not depend on the batch or workgroup
+    # that solves it (bitwise), and the fast-Poisson preconditioner keeps the
+    # iteration count of the h = 1/64, d = 10 workload small
+    prob, _ = W.WORKLOADS["mesh64_d10"]
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-12))
+    Y = np.random.default_rng(11).random((300, prob["d"]))
+    U = torch.zeros((plan.G, 300), dtype=torch.float64, device="cuda")
+    it = torch.zeros(300, dtype=torch.int32, device="cuda")
+    lib.sample(plan, dev(Y), U, 0, 300, 0, it)
+    its = host(it)
+    assert (its > 0).all() and its.max() <= 30, (its.min(), its.max())
+    for s in (0, 123, 299):
+        U1 = torch.zeros((plan.G, 1), dtype=torch.float64, device="cuda")
+        lib.sample(plan, dev(Y[s:s + 1]), U1, 0, 1)
+        assert np.array_equal(host(U1)[:, 0], host(U)[:, s])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dst_preconditioner_is_exact_for_constant_coefficient(lib, prec):
+    # a = 1: the scaled operator is the 5-point Laplacian itself, which the
+    # preconditioner inverts up to fp16 rounding, so a few iterations suffice
+    # and the solution is the oracle's (the same for every y)
+    n, d = 64, 3
+    prob = dict(W.pde_problem(n, d, 4), amp=[0.0] * d)
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-12))
+    Y = np.random.default_rng(2).random((4, d))
+    U = torch.zeros((plan.G, 4), dtype=torch.float64, device="cuda")
+    it = torch.zeros(4, dtype=torch.int32, device="cuda")
+    lib.sample(plan, dev(Y), U, 0, 4, 0, it)
+    assert (host(it) > 0).all() and host(it).max() <= 6, host(it)
+    ref = ofem.PDESampler(n, 1.0, [0.0] * d, prob["mode1"], prob["mode2"]).solve_one(Y[0])
+    for s in range(4):
+        assert np.linalg.norm(host(U)[:, s] - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
 def test_trig_poly_sampler(lib):
