@@ -41,7 +41,7 @@ int dst_padded(int n);             // MP = 32 or 64, 0 if the mesh is too large
 int64_t dst_frag_bytes(int mp);    // S fragment table of one mesh size
 void dst_tables_build(int n, void* frag, float* lam, hipStream_t st);  // lam: MP floats
 int dst_persistent_blocks(int n, int precision);
-int64_t dst_edge_stride(int mp);   // doubles per edge grid; the scratch holds 2 per workgroup
+int64_t dst_edge_stride(int mp);   // doubles per scratch grid; 3 grids per workgroup
 void launch_pde_solve_dst(const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol, int maxit,
                           double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld, int64_t col0,
                           int* iters, double* wscr, int wblocks, const void* frag, const float* lam,

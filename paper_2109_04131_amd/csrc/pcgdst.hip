@@ -187,11 +187,6 @@ __device__ __forceinline__ float pow2_scale(double rr) {
   return ldexpf(1.0f, -(e < -100 ? -100 : (e > 100 ? 100 : e)));
 }
 
-// D^-1/2 at grid index l from the exact float64 edge grids.
-__device__ __forceinline__ double jacobi_isqrt(const double* eh, const double* ev, int l, int P1) {
-  return 1.0 / sqrt(0.25 * (eh[l] + eh[l - 1] + ev[l] + ev[l - P1]));
-}
-
 // LDS grids of one workgroup have the compile-time pitch PP = MP + 2 >= n + 1
 // (zero halo at rows/columns 0 and n, unused space beyond), so every stencil
 // access is a base register plus an immediate offset.
@@ -208,7 +203,8 @@ constexpr int dst_waves() {
   return std::is_same<T, float>::value ? (MP == 64 ? 2 : 3) : (MP == 64 ? 1 : 2);
 }
 
-// Doubles of one workgroup's edge grid in the global scratch (pitch PP).
+// Doubles of one grid of a workgroup's global scratch (pitch PP); the
+// scratch holds three per workgroup: eh, ev and D^-1/2.
 int64_t dst_edge_stride(int mp) { return ((int64_t)dst_pitch(mp) * dst_pitch(mp) + 31) / 32 * 32; }
 
 // Dynamic LDS bytes of one workgroup.
@@ -217,6 +213,73 @@ int64_t dst_lds_bytes(int n, int precision) {
   const int64_t g = dst_grid_elems(mp);
   const int64_t grids = precision == USFFT_FP64 ? g * 8 : g * 8 + g * 4;
   return grids + 2 * (int64_t)mp * (mp + 4) * 2;
+}
+
+// Assembly of one sample (eq. (1.2) at the triangle centroids): the edge
+// grids eh[j PP + i] = (aL(i,j) + aU(i,j-1))/2 (i < n, 1 <= j < n) and
+// ev[j PP + i] = (aU(i,j) + aL(i-1,j))/2 (1 <= i < n, j < n), and the Jacobi
+// scaling D^-1/2 of every interior node, written to sd (LDS) and dg (global).
+// Lane = cell column ci (chunks of 64), each wave sweeps blocks of 8 cell
+// rows cj (plus the row below).  a(ci, cj) = a0 + sum_k (coef_k x_k(ci)) y_k(cj)
+// is separable: with k outermost, the per-lane factors are loaded once per k
+// and the row factors are wave-uniform (scalar loads).  Each thread forms the
+// coefficients of column ci and of column ci-1, so every edge around its
+// nodes is available in registers.
+template <int NWAVE>
+__device__ void assemble(const PdeDev& P, const double* coef, double* __restrict__ eh, double* __restrict__ ev,
+                         double* __restrict__ dg, double* sd, int PP, int tid) {
+  constexpr int CB = 8;
+  const int n = P.n, d = P.d, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double* txL = P.tab;                  // x1 factor, lower triangles
+  const double* txU = P.tab + (size_t)d * n;  // x1 factor, upper triangles
+  // the row factors are wave-uniform and read-only: scalar loads through the
+  // constant address space
+  typedef const __attribute__((address_space(4))) double* cdp;
+  const cdp tyL = (cdp)(P.tab + (size_t)2 * d * n);
+  const cdp tyU = (cdp)(P.tab + (size_t)3 * d * n);
+  for (int ci0 = 0; ci0 < n; ci0 += 64) {
+    const int ci = ci0 + lane;
+    const bool act = ci < n, left = act && ci >= 1;
+    for (int cb = wave * CB; cb < n; cb += NWAVE * CB) {
+      // row u of the block is cell row cj = cb - 1 + u
+      double aL[CB + 1], aU[CB + 1], aLm[CB + 1], aUm[CB + 1];
+#pragma unroll
+      for (int u = 0; u <= CB; ++u) aL[u] = aU[u] = aLm[u] = aUm[u] = P.a0;
+#pragma unroll 2
+      for (int k = 0; k < d; ++k) {
+        const double ck = coef[k];
+        const double xl = act ? ck * txL[k * n + ci] : 0.0, xu = act ? ck * txU[k * n + ci] : 0.0;
+        const double xlm = left ? ck * txL[k * n + ci - 1] : 0.0, xum = left ? ck * txU[k * n + ci - 1] : 0.0;
+        // rows outside [0, n) are clamped (their values are never used), so
+        // the loop has no branches and all loads of one k are in flight at once
+#pragma unroll
+        for (int u = 0; u <= CB; ++u) {
+          const int cj = min(max(cb - 1 + u, 0), n - 1);
+          const double yl = tyL[k * n + cj], yu = tyU[k * n + cj];
+          aL[u] += xl * yl;
+          aU[u] += xu * yu;
+          aLm[u] += xlm * yl;
+          aUm[u] += xum * yu;
+        }
+      }
+#pragma unroll
+      for (int u = 1; u <= CB; ++u) {
+        const int cj = cb - 1 + u;
+        if (cj >= n || !act) continue;
+        const double ehc = 0.5 * (aL[u] + aU[u - 1]);   // eh(ci, cj)
+        const double evc = 0.5 * (aU[u] + aLm[u]);      // ev(ci, cj)
+        if (cj >= 1) eh[cj * PP + ci] = ehc;
+        if (ci >= 1) ev[cj * PP + ci] = evc;
+        if (ci >= 1 && cj >= 1) {
+          const double ehm = 0.5 * (aLm[u] + aUm[u - 1]);   // eh(ci-1, cj)
+          const double evm = 0.5 * (aU[u - 1] + aLm[u - 1]);  // ev(ci, cj-1)
+          const double di = 1.0 / sqrt(0.25 * (ehc + ehm + evc + evm));
+          sd[cj * PP + ci] = di;
+          dg[cj * PP + ci] = di;
+        }
+      }
+    }
+  }
 }
 
 template <typename T, int MP>
@@ -239,9 +302,11 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
   _Float16* xa = reinterpret_cast<_Float16*>(sp + GE);      // exchange tiles, column-major
   _Float16* xb = xa + MP * LDX;
   double* sd = REFINE ? sx : reinterpret_cast<double*>(sp);  // D^-1/2 during set-up
-  // this workgroup's float64 edge grids, pitch PP like the LDS grids
-  double* eh = wscr + (size_t)blockIdx.x * 2 * wstride;
+  // this workgroup's float64 edge grids and Jacobi scaling, pitch PP like
+  // the LDS grids
+  double* eh = wscr + (size_t)blockIdx.x * 3 * wstride;
   double* ev = eh + wstride;
+  double* dg = ev + wstride;
 
   const int lane = threadIdx.x & 63;
   half8 sf[KB * NT];
@@ -268,12 +333,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
     __syncthreads();  // the previous sample is done with LDS, coef and the edge grids
     load_coef(P, Y, s, coef);
     __syncthreads();
-    fill_edges<double>(P, coef, eh, ev, PP);
-    __syncthreads();
-    for (int g = tid; g < m * m; g += BLOCK) {
-      const int k = (g / m + 1) * PP + g % m + 1;
-      sd[k] = jacobi_isqrt(eh, ev, k, PP);
-    }
+    assemble<BLOCK / 64>(P, coef, eh, ev, dg, sd, PP, tid);
     __syncthreads();
     // scaled weights: wE, wW, wS per node; wN(v) = wS(v + 1) inside a 4-row
     // group, so only the top row of each group keeps its own (wN4)
@@ -283,22 +343,21 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
       const double* sdl = sd + base;
       const double* ehl = eh + base;
       const double* evl = ev + base;
+      // padding slots read in-bounds garbage (unwritten scratch) that the
+      // selects discard; without branches all loads are in flight together
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int t = e >> 2, v = e & 3, row = 16 * t + 4 * q + v, o = off(e);
+        const bool ok = row < m && c < m;
+        const double di = sdl[o];
         dx[e] = (T)0;
-        wE[e] = wW[e] = wS[e] = r[e] = (T)0;
-        if (v == 3) wN4[t] = (T)0;
-        if (row < m && c < m) {
-          const double di = sdl[o];
-          wE[e] = (T)(ehl[o] * di * sdl[o + 1]);
-          wW[e] = (T)(ehl[o - 1] * di * sdl[o - 1]);
-          wS[e] = (T)(evl[o - PP] * di * sdl[o - PP]);
-          if (v == 3) wN4[t] = (T)(evl[o] * di * sdl[o + PP]);
-          const double bt = di * P.h2;
-          r[e] = (T)bt;
-          bb += bt * bt;
-        }
+        wE[e] = ok ? (T)(ehl[o] * di * sdl[o + 1]) : (T)0;
+        wW[e] = ok ? (T)(ehl[o - 1] * di * sdl[o - 1]) : (T)0;
+        wS[e] = ok ? (T)(evl[o - PP] * di * sdl[o - PP]) : (T)0;
+        if (v == 3) wN4[t] = ok ? (T)(evl[o] * di * sdl[o + PP]) : (T)0;
+        const double bt = ok ? di * P.h2 : 0.0;
+        r[e] = (T)bt;
+        bb += bt * bt;
       }
     }
     bb = block_sum<BLOCK>(bb, red0);  // its barrier also ends the reads of sd
@@ -350,33 +409,39 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
       ++it;
       if (REFINE) {
         if (rr <= drop * rr_ref || it - last_update >= refine_every) {
-          // u += D^-1/2 dx in float64 (dx staged in LDS), then the float64 true
-          // residual (scaled) replaces the float32 one; the search direction
-          // is kept
+          // u += D^-1/2 dx in float64, then the float64 true residual
+          // (scaled) replaces the float32 one; the search direction is kept.
+          // Both in the node layout; the base is opaque here so that the
+          // per-node addresses are not hoisted out of the iteration.
+          int b2 = base;
+          asm volatile("" : "+v"(b2));
+          const double* ehl = eh + b2;
+          const double* evl = ev + b2;
+          const double* dgl = dg + b2;
+          double* sxl = sx + b2;
+          // (padding slots: unconditional in-bounds loads, results discarded
+          // by selects; sx stays zero there)
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            spl[off(e)] = dx[e];
+            const bool ok = 16 * (e >> 2) + 4 * q + (e & 3) < m && c < m;
+            const double du = dgl[off(e)] * (double)dx[e];
+            sxl[off(e)] += ok ? du : 0.0;
             dx[e] = (T)0;
           }
           __syncthreads();
-          for (int g = tid; g < m * m; g += BLOCK) {
-            const int k = (g / m + 1) * PP + g % m + 1;
-            sx[k] += jacobi_isqrt(eh, ev, k, PP) * (double)sp[k];
-          }
-          __syncthreads();
           double rr64 = 0.0;
-          for (int g = tid; g < m * m; g += BLOCK) {
-            const int k = (g / m + 1) * PP + g % m + 1;
-            const double xc = sx[k];
-            const double ax = eh[k] * (xc - sx[k + 1]) + eh[k - 1] * (xc - sx[k - 1]) +
-                              ev[k] * (xc - sx[k + PP]) + ev[k - PP] * (xc - sx[k - PP]);
-            const double rs = jacobi_isqrt(eh, ev, k, PP) * (P.h2 - ax);
-            rr64 += rs * rs;
-            sp[k] = (T)rs;
-          }
-          __syncthreads();
 #pragma unroll
-          for (int e = 0; e < E; ++e) r[e] = spl[off(e)];
+          for (int e = 0; e < E; ++e) {
+            const int o = off(e);
+            const bool ok = 16 * (e >> 2) + 4 * q + (e & 3) < m && c < m;
+            const double xc = sxl[o];
+            const double ax = ehl[o] * (xc - sxl[o + 1]) + ehl[o - 1] * (xc - sxl[o - 1]) +
+                              evl[o] * (xc - sxl[o + PP]) + evl[o - PP] * (xc - sxl[o - PP]);
+            const double rsv = dgl[o] * (P.h2 - ax);
+            const double rs = ok ? rsv : 0.0;
+            rr64 += rs * rs;
+            r[e] = (T)rs;
+          }
           rr64 = block_sum<BLOCK>(rr64, red0);
           last_update = it;
           if (rr64 <= stop) {
@@ -404,15 +469,18 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
       for (int e = 0; e < E; ++e) p[e] = (T)z[e] + beta * p[e];
     }
     // u = D^-1/2 ut: float64 solves hold ut in dx, float32 solves the
-    // correction not yet folded into u
-    __syncthreads();
+    // correction not yet folded into u (each lane reads only its own nodes
+    // of sx)
+    {
+      const double* dgl = dg + base;
+      const double* sxl = sx + base;
 #pragma unroll
-    for (int e = 0; e < E; ++e) spl[off(e)] = dx[e];
-    __syncthreads();
-    for (int g = tid; g < m * m; g += BLOCK) {
-      const int k = (g / m + 1) * PP + g % m + 1;
-      const double d = jacobi_isqrt(eh, ev, k, PP) * (double)sp[k];
-      store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, REFINE ? sx[k] + d : d);
+      for (int e = 0; e < E; ++e) {
+        const int row = 16 * (e >> 2) + 4 * q + (e & 3);
+        const double dv = dgl[off(e)] * (double)dx[e];
+        const double u = REFINE ? sxl[off(e)] + dv : dv;
+        if (row < m && c < m) store_sample(out, out_fp32, ((int64_t)row * m + c) * ld + col0 + s, u);
+      }
     }
     if (tid == 0 && iters) iters[s] = conv ? it : -1;
   }

@@ -697,7 +697,7 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
       dst_tables_build(n, P->d_sfrag.p, P->d_lam.as<float>(), nullptr);
       USFFT_HIP(hipStreamSynchronize(nullptr));
       P->wblocks = dst_persistent_blocks(n, par->precision);
-      P->d_wscr.ensure(sizeof(double) * 2 * (size_t)dst_edge_stride(mp) * P->wblocks);
+      P->d_wscr.ensure(sizeof(double) * 3 * (size_t)dst_edge_stride(mp) * P->wblocks);
     } else if (n > kMaxMesh) {
       // per-sample state exceeds one CU: streaming float64 solver
       P->streaming = true;
