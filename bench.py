@@ -20,8 +20,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "PDE sample solves/s + lattice-FFT GB/s, batched-FP32 vs plain FP64; p50/p99 job"
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}  # MI355X vector peaks
-FLOPS_PER_NODE_ITER = 26  # Jacobi-PCG iteration on the 5-point operator, per node
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "f16_mfma": 2500.0}  # MI355X vector / dense matrix peaks
+# Vector work of one preconditioned CG iteration on the scaled 5-point
+# operator, per node: operator 9, two dot products 4, three updates 6, the
+# norm 2 and the scalings around the fp16 conversion 2.
+VECTOR_FLOPS_PER_NODE_ITER = 23
 
 
 def pct(v, q):
@@ -88,11 +91,14 @@ def measured_traffic():
     only while the solver source is the one the counters were taken on."""
     import hashlib
     import re
-    src = os.path.join(ROOT, "paper_2109_04131_amd", "csrc", "sampler.hip")
-    prof = os.path.join(ROOT, "profiles", "pcg32r_rader_mesh64_d10_hbm_counters.md")
+    srcs = [os.path.join(ROOT, "paper_2109_04131_amd", "csrc", f) for f in ("pcgdst.hip", "pde_device.h")]
+    prof = os.path.join(ROOT, "profiles", "pcgdst_mesh64_d10_hbm_counters.md")
     try:
         text = open(prof).read()
-        digest = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+        h = hashlib.sha1()
+        for f in srcs:
+            h.update(open(f, "rb").read())
+        digest = h.hexdigest()[:12]
     except OSError:
         return None
     m = re.search(r"sha1 prefix `([0-9a-f]+)`", text)
@@ -177,9 +183,16 @@ def main():
     launches = sum(s["sample_launches"] for s in st32)
     iters = sum(s["pcg_iterations"] for s in st32)
     G = plan32.G
-    flops = iters * G * FLOPS_PER_NODE_ITER
+    m = prob["mesh_n"] - 1
+    # dense contraction of the preconditioner: 4 products of m x m x m per
+    # application, one application per iteration plus the initial one (the
+    # re-applications after float64 updates are not counted)
+    mfma_flops = (iters + samples) * 8.0 * m ** 3
+    vec_flops = iters * G * VECTOR_FLOPS_PER_NODE_ITER
     avg_ms = ms_sample / max(1, launches)
-    achieved = (flops / max(1, launches)) / (avg_ms * 1e-3) / 1e12
+    achieved = (mfma_flops / max(1, launches)) / (avg_ms * 1e-3) / 1e12
+    vec_achieved = (vec_flops / max(1, launches)) / (avg_ms * 1e-3) / 1e12
+    per_job = {k: sum(s[k] for s in st32) / len(st32) for k in ("ms_sample", "ms_dft", "ms_select", "ms_total")}
     fft_gbps = sum(s["dft_bytes"] for s in st32) / max(1e-9, sum(s["ms_dft"] for s in st32)) / 1e6
     res = {
         "metric": METRIC,
@@ -203,12 +216,15 @@ def main():
         "fft_GBps": fft_gbps,
         "pcg_iters_per_solve": iters / max(1, samples),
         "fp32_vs_fp64_samples_per_s": (value / out["fp64_path"]["samples_per_s"]) if out else None,
-        "roofline": {"kernel": "pcg32r (batched float32 Jacobi-PCG + float64 refinement)",
-                     "bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS["f32"], "traffic": measured_traffic(),
+        "roofline": {"kernel": "pcgdst_kernel<float,64> (DST-preconditioned float32 PCG + float64 "
+                               "reliable updates; preconditioner on fp16 MFMA)",
+                     "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f16_mfma"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_TFLOPS["f16_mfma"], "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per launch (rocprof FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                      "avg_launch_ms": avg_ms, "launches": launches,
+                     "vector_tflops": vec_achieved, "vector_frac_f32": vec_achieved / PEAK_TFLOPS["f32"],
                      "workgroup": [st32[0]["solver_block"], st32[0]["solver_npt"]]},
+        "job_breakdown_ms": per_job,
     }
     res.update(out)
     if args.serving_jobs > 0:

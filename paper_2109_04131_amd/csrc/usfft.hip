@@ -160,6 +160,9 @@ static std::vector<int> admissible_sizes(int lo, int hi) {
   return out;
 }
 
+// Largest sample matrix (bytes) one batched sampler launch of step 2 fills.
+constexpr uint64_t kSampleBatchBytes = 4ull << 30;
+
 // Small per-stage uploads; synchronous because the host vectors are reused.
 template <typename T>
 static void h2d(usfft::DevBuf& b, const std::vector<T>& v, hipStream_t st) {
@@ -353,12 +356,6 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     USFFT_HIP(hipStreamSynchronize(st));
   }
   P->tail.ensure(sizeof(double) * kMaxD);
-  std::vector<double> tail(d);
-  auto upload_tail = [&](int kind, int t, int i) {
-    for (int j = 0; j < d; ++j) tail[j] = rng::uniform01(seed, rng::stream(kind, t, i, 0), j);
-    USFFT_HIP(hipMemcpyAsync(P->tail.p, tail.data(), sizeof(double) * d, hipMemcpyHostToDevice, st));
-    USFFT_HIP(hipStreamSynchronize(st));
-  };
   auto check_conv = [&]() {
     unsigned long long h[2];
     USFFT_HIP(hipMemcpyAsync(h, P->cnt.p, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -369,53 +366,78 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
   };
 
   // ---------------- step 1 & 2a
+  // The d x r line stages are independent: their sampling nodes are
+  // generated into one batch, solved in one sampler launch, then
+  // transformed and selected line by line (the threshold of a relative theta
+  // comes from line (1, 1), which runs first).
   P->I1.resize(d);
   P->I1n.assign(d, 0);
   bool theta_set = !par.theta_relative;
-  for (int t = 0; t < d; ++t) {
-    const int K = pb.k_hi[t] - pb.k_lo[t] + 1;
-    std::vector<int32_t> ks(K);
-    for (int a = 0; a < K; ++a) ks[a] = pb.k_lo[t] + a;
-    h2d(P->cands, ks, st);
-    const int64_t ld = ceil_div(K, 64) * 64;
-    P->U.ensure(ub * G * ld);
-    P->V.ensure(sizeof(double) * G * K);
-    P->Y.ensure(sizeof(double) * K * d);
-    P->iters.ensure(sizeof(int32_t) * K);
-    const int64_t words = ceil_div(K, 32);
-    P->mask.ensure(sizeof(uint32_t) * words);
-    USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * words, st));
-    std::vector<int32_t> Kv = {K};
-    h2d(P->latM, Kv, st);
-    for (int i = 0; i < par.r; ++i) {
-      upload_tail(rng::kTail1, t + 1, i + 1);
-      launch_nodes(d, t, 1, 1, nullptr, P->latM.as<int32_t>(), nullptr, P->tail.as<double>(), P->Y.as<double>(), K,
-                   st);
-      sample_timed(P->Y.as<double>(), K, ld);
-      S.samples_step1 += K;
-      int e = tm.open(kTDft);
-      launch_line_dft(P->U.p, ufp32, G, ld, 0, K, P->cands.as<int32_t>(), K, USFFT_OUT_MAG2, P->V.p, K, st);
-      tm.close(kTDft, e);
-      S.dft_launches += 1;
-      if (!theta_set) {
-        launch_max_to_theta(P->V.as<double>(), G, K, K, par.theta, P->theta2.as<double>(), P->scratch.as<uint64_t>(),
-                            st);
-        theta_set = true;
-      }
-      e = tm.open(kTSelect);
-      launch_select(P->V.as<double>(), G, K, K, par.s_local, P->theta2.as<double>(), par.tie_rel,
-                    P->mask.as<uint32_t>(), nullptr, st);
-      tm.close(kTSelect, e);
+  {
+    const int r = par.r;
+    std::vector<int32_t> Kt(d), ks;
+    std::vector<int64_t> off(d * r + 1, 0), coff(d + 1, 0), woff(d + 1, 0);
+    int Kmax = 1;
+    for (int t = 0; t < d; ++t) {
+      Kt[t] = pb.k_hi[t] - pb.k_lo[t] + 1;
+      Kmax = std::max(Kmax, Kt[t]);
+      for (int a = 0; a < Kt[t]; ++a) ks.push_back(pb.k_lo[t] + a);
+      coff[t + 1] = coff[t] + Kt[t];
+      woff[t + 1] = woff[t] + ceil_div(Kt[t], 32);
+      for (int i = 0; i < r; ++i) off[t * r + i + 1] = off[t * r + i] + Kt[t];
     }
-    P->I1[t].ensure(sizeof(int32_t) * K);
-    P->cnt.ensure(2 * sizeof(unsigned long long));
-    P->scratch.ensure(64);
-    launch_compact(P->cands.as<int32_t>(), P->mask.as<uint32_t>(), K, 1, P->I1[t].as<int32_t>(),
-                   reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32), st);
-    int64_t cntI = 0;
-    USFFT_HIP(hipMemcpyAsync(&cntI, P->scratch.as<char>() + 32, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    const int64_t ns = off.back(), ld = ceil_div(ns, 64) * 64;
+    h2d(P->cands, ks, st);
+    h2d(P->latM, Kt, st);
+    P->U.ensure(ub * G * ld);
+    P->V.ensure(sizeof(double) * G * Kmax);
+    P->Y.ensure(sizeof(double) * ns * d);
+    P->iters.ensure(sizeof(int32_t) * ns);
+    P->mask.ensure(sizeof(uint32_t) * woff[d]);
+    USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * woff[d], st));
+    std::vector<double> tails((size_t)d * r * d);
+    for (int t = 0; t < d; ++t)
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < d; ++j)
+          tails[((size_t)t * r + i) * d + j] = rng::uniform01(seed, rng::stream(rng::kTail1, t + 1, i + 1, 0), j);
+    h2d(P->tail, tails, st);
+    for (int t = 0; t < d; ++t)
+      for (int i = 0; i < r; ++i)
+        launch_nodes(d, t, 1, 1, nullptr, P->latM.as<int32_t>() + t, nullptr,
+                     P->tail.as<double>() + ((size_t)t * r + i) * d, P->Y.as<double>() + off[t * r + i] * d, Kt[t],
+                     st);
+    sample_timed(P->Y.as<double>(), ns, ld);
+    S.samples_step1 += ns;
+    for (int t = 0; t < d; ++t) {
+      const int K = Kt[t];
+      for (int i = 0; i < r; ++i) {
+        int e = tm.open(kTDft);
+        launch_line_dft(P->U.p, ufp32, G, ld, off[t * r + i], K, P->cands.as<int32_t>() + coff[t], K,
+                        USFFT_OUT_MAG2, P->V.p, K, st);
+        tm.close(kTDft, e);
+        S.dft_launches += 1;
+        if (!theta_set) {
+          launch_max_to_theta(P->V.as<double>(), G, K, K, par.theta, P->theta2.as<double>(),
+                              P->scratch.as<uint64_t>(), st);
+          theta_set = true;
+        }
+        e = tm.open(kTSelect);
+        launch_select(P->V.as<double>(), G, K, K, par.s_local, P->theta2.as<double>(), par.tie_rel,
+                      P->mask.as<uint32_t>() + woff[t], nullptr, st);
+        tm.close(kTSelect, e);
+      }
+    }
+    P->scratch.ensure(32 + sizeof(int64_t) * d);
+    for (int t = 0; t < d; ++t) {
+      P->I1[t].ensure(sizeof(int32_t) * Kt[t]);
+      launch_compact(P->cands.as<int32_t>() + coff[t], P->mask.as<uint32_t>() + woff[t], Kt[t], 1,
+                     P->I1[t].as<int32_t>(), reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32) + t, st);
+    }
+    std::vector<int64_t> cnt(d);
+    USFFT_HIP(hipMemcpyAsync(cnt.data(), P->scratch.as<char>() + 32, sizeof(int64_t) * d, hipMemcpyDeviceToHost,
+                             st));
     check_conv();
-    P->I1n[t] = cntI;
+    for (int t = 0; t < d; ++t) P->I1n[t] = cnt[t];
   }
   {
     double th2 = 0;
@@ -452,11 +474,7 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     S.lattices += (int64_t)F.M.size();
     for (int M : F.M) (void)rader_for(P, M, st);
     const int64_t ns = F.total();
-    const int64_t ld = ceil_div(ns, 64) * 64;
-    P->U.ensure(ub * G * ld);
     P->V.ensure(sizeof(double) * G * n);
-    P->Y.ensure(sizeof(double) * ns * d);
-    P->iters.ensure(sizeof(int32_t) * ns);
     h2d(P->latM, F.M, st);
     h2d(P->latz, F.z, st);
     h2d(P->latoff, F.off, st);
@@ -468,28 +486,43 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     P->gmask.ensure(sizeof(uint32_t) * words);
     USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * words, st));
     USFFT_HIP(hipMemsetAsync(P->gmask.p, 0, sizeof(uint32_t) * words, st));
-    for (int i = 0; i < r_t; ++i) {
-      upload_tail(rng::kTail2, t + 1, i + 1);
-      launch_nodes(d, -1, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(), P->latz.as<int32_t>(),
-                   P->tail.as<double>(), P->Y.as<double>(), ns, st);
-      sample_timed(P->Y.as<double>(), ns, ld);
-      S.samples_step2 += ns;
-      int e = tm.open(kTDft);
-      for (size_t l = 0; l < F.M.size(); ++l) {
-        const RaderTables& T = rader_for(P, F.M[l], st);
-        const int32_t* pos = P->lists.as<int32_t>() + F.lat_first[l];
-        const int32_t* bn = P->lists.as<int32_t>() + n + F.lat_first[l];
-        (void)pos;
-        launch_lattice_dft(T, P->U.p, ufp32, G, ld, F.off[l], bn, nullptr, F.lat_first[l], F.lat_count[l],
-                           USFFT_OUT_MAG2, P->V.p, n, st);
-        S.dft_launches += 1;
-        S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 8.0;
+    // the r_t iterations differ only in their tails: their samples are
+    // solved together, in batches of at most kSampleBatchBytes of samples
+    int rb = r_t;
+    while (rb > 1 && ub * (uint64_t)G * (uint64_t)(rb * ns) > kSampleBatchBytes) --rb;
+    for (int i0 = 0; i0 < r_t; i0 += rb) {
+      const int nb = std::min(rb, r_t - i0);
+      const int64_t nsb = nb * ns, ldb = ceil_div(nsb, 64) * 64;
+      P->U.ensure(ub * G * ldb);
+      P->Y.ensure(sizeof(double) * nsb * d);
+      P->iters.ensure(sizeof(int32_t) * nsb);
+      std::vector<double> tails((size_t)nb * d);
+      for (int b = 0; b < nb; ++b)
+        for (int j = 0; j < d; ++j)
+          tails[(size_t)b * d + j] = rng::uniform01(seed, rng::stream(rng::kTail2, t + 1, i0 + b + 1, 0), j);
+      h2d(P->tail, tails, st);
+      for (int b = 0; b < nb; ++b)
+        launch_nodes(d, -1, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(),
+                     P->latz.as<int32_t>(), P->tail.as<double>() + (size_t)b * d, P->Y.as<double>() + b * ns * d,
+                     ns, st);
+      sample_timed(P->Y.as<double>(), nsb, ldb);
+      S.samples_step2 += nsb;
+      for (int b = 0; b < nb; ++b) {
+        int e = tm.open(kTDft);
+        for (size_t l = 0; l < F.M.size(); ++l) {
+          const RaderTables& T = rader_for(P, F.M[l], st);
+          const int32_t* bn = P->lists.as<int32_t>() + n + F.lat_first[l];
+          launch_lattice_dft(T, P->U.p, ufp32, G, ldb, b * ns + F.off[l], bn, nullptr, F.lat_first[l],
+                             F.lat_count[l], USFFT_OUT_MAG2, P->V.p, n, st);
+          S.dft_launches += 1;
+          S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 8.0;
+        }
+        tm.close(kTDft, e);
+        e = tm.open(kTSelect);
+        launch_select(P->V.as<double>(), G, n, n, s_t, P->theta2.as<double>(), par.tie_rel,
+                      P->gmask.as<uint32_t>(), nullptr, st);
+        tm.close(kTSelect, e);
       }
-      tm.close(kTDft, e);
-      e = tm.open(kTSelect);
-      launch_select(P->V.as<double>(), G, n, n, s_t, P->theta2.as<double>(), par.tie_rel, P->gmask.as<uint32_t>(),
-                    nullptr, st);
-      tm.close(kTSelect, e);
     }
     launch_ungroup_mask(P->gmask.as<uint32_t>(), P->lists.as<int32_t>(), n, P->mask.as<uint32_t>(), st);
     P->Jnext.ensure(sizeof(int32_t) * n * w);
