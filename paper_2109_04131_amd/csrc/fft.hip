@@ -132,11 +132,11 @@ struct FftPlanDev {
 //    and so F = S_0^T ... S_{S-1}^T Pi.
 // A convolution therefore never needs natural order in between: forward DIF,
 // pointwise product with a spectrum produced by the same DIF, DIT back.
-template <typename T, int R>
+template <typename T, int R, int BLOCK>
 __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw,
                           const cplx<T>* __restrict__ mulB) {
   const int nb = L / R, ts = L / N;
-  for (int b = threadIdx.x; b < nb; b += kFftBlock) {
+  for (int b = threadIdx.x; b < nb; b += BLOCK) {
     const int blk = b / M, j = b - blk * M, base = blk * N + j;
     cplx<T> v[R];
 #pragma unroll
@@ -153,10 +153,10 @@ __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
   __syncthreads();
 }
 
-template <typename T, int R>
+template <typename T, int R, int BLOCK>
 __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw) {
   const int nb = L / R, ts = L / N;
-  for (int b = threadIdx.x; b < nb; b += kFftBlock) {
+  for (int b = threadIdx.x; b < nb; b += BLOCK) {
     const int blk = b / M, j = b - blk * M, base = blk * N + j;
     cplx<T> v[R];
 #pragma unroll
@@ -175,26 +175,26 @@ __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
 // Forward DIF over all stages; with mulB, the last stage multiplies by mulB
 // and conjugates (the forward half of a convolution, set up for the inverse
 // transform by conjugation).
-template <typename T>
+template <typename T, int BLOCK>
 __device__ void fft_dif(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, const cplx<T>* mulB) {
   int N = F.L;
   for (int s = 0; s < F.nrad; ++s) {
     const int R = F.radix[s], M = N / R;
     const cplx<T>* mb = (s == F.nrad - 1) ? mulB : nullptr;
     switch (R) {
-      case 2: dif_stage<T, 2>(buf, F.L, N, M, tw, mb); break;
-      case 3: dif_stage<T, 3>(buf, F.L, N, M, tw, mb); break;
-      case 4: dif_stage<T, 4>(buf, F.L, N, M, tw, mb); break;
-      case 5: dif_stage<T, 5>(buf, F.L, N, M, tw, mb); break;
-      case 7: dif_stage<T, 7>(buf, F.L, N, M, tw, mb); break;
-      default: dif_stage<T, 8>(buf, F.L, N, M, tw, mb); break;
+      case 2: dif_stage<T, 2, BLOCK>(buf, F.L, N, M, tw, mb); break;
+      case 3: dif_stage<T, 3, BLOCK>(buf, F.L, N, M, tw, mb); break;
+      case 4: dif_stage<T, 4, BLOCK>(buf, F.L, N, M, tw, mb); break;
+      case 5: dif_stage<T, 5, BLOCK>(buf, F.L, N, M, tw, mb); break;
+      case 7: dif_stage<T, 7, BLOCK>(buf, F.L, N, M, tw, mb); break;
+      default: dif_stage<T, 8, BLOCK>(buf, F.L, N, M, tw, mb); break;
     }
     N = M;
   }
 }
 
 // Forward DIT over all stages in reverse order (digit-reversed in, natural out).
-template <typename T>
+template <typename T, int BLOCK>
 __device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
   int Ns[24];
   int N = F.L;
@@ -205,12 +205,12 @@ __device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
   for (int s = F.nrad - 1; s >= 0; --s) {
     const int R = F.radix[s], Nn = Ns[s], M = Nn / R;
     switch (R) {
-      case 2: dit_stage<T, 2>(buf, F.L, Nn, M, tw); break;
-      case 3: dit_stage<T, 3>(buf, F.L, Nn, M, tw); break;
-      case 4: dit_stage<T, 4>(buf, F.L, Nn, M, tw); break;
-      case 5: dit_stage<T, 5>(buf, F.L, Nn, M, tw); break;
-      case 7: dit_stage<T, 7>(buf, F.L, Nn, M, tw); break;
-      default: dit_stage<T, 8>(buf, F.L, Nn, M, tw); break;
+      case 2: dit_stage<T, 2, BLOCK>(buf, F.L, Nn, M, tw); break;
+      case 3: dit_stage<T, 3, BLOCK>(buf, F.L, Nn, M, tw); break;
+      case 4: dit_stage<T, 4, BLOCK>(buf, F.L, Nn, M, tw); break;
+      case 5: dit_stage<T, 5, BLOCK>(buf, F.L, Nn, M, tw); break;
+      case 7: dit_stage<T, 7, BLOCK>(buf, F.L, Nn, M, tw); break;
+      default: dit_stage<T, 8, BLOCK>(buf, F.L, Nn, M, tw); break;
     }
   }
 }
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kFftBlock) void rader_setup_kernel(FftPlanDev F, in
     buf[j] = {c, s};
   }
   __syncthreads();
-  fft_dif<double>(buf, F, tw, nullptr);  // spectrum in the DIF (digit-reversed) order
+  fft_dif<double, kFftBlock>(buf, F, tw, nullptr);  // spectrum in the DIF (digit-reversed) order
   const double invL = 1.0 / (double)L;
   for (int k = threadIdx.x; k < L; k += kFftBlock) {
     const cplx<double> v = {buf[k].x * invL, buf[k].y * invL};
@@ -265,7 +265,7 @@ static int64_t powmod(int64_t a, int64_t e, int64_t m) {
 }
 
 void rader_free(RaderTables& T) {
-  for (void* p : {(void*)T.perm, (void*)T.outidx, T.tw64, T.tw32, T.B64, T.B32})
+  for (void* p : {(void*)T.perm, (void*)T.dlog, (void*)T.outidx, T.tw64, T.tw32, T.B64, T.B32})
     if (p) (void)hipFree(p);
   T = RaderTables{};
 }
@@ -311,6 +311,7 @@ void rader_build(RaderTables& T, int M, hipStream_t st) {
     v = v * gen % M;
   }
   for (int b = 1; b < M; ++b) outidx[b] = (L - dlog[b]) % L;
+  dlog[0] = 0;  // unused: x[0] enters only the sums
   std::vector<cplx<double>> tw(L);
   for (int k = 0; k < L; ++k) {
     const double a = -2.0 * M_PI * (double)k / (double)L;
@@ -318,12 +319,14 @@ void rader_build(RaderTables& T, int M, hipStream_t st) {
   }
   USFFT_HIP(hipMalloc(&T.perm, sizeof(int32_t) * L));
   USFFT_HIP(hipMalloc(&T.outidx, sizeof(int32_t) * M));
+  USFFT_HIP(hipMalloc(&T.dlog, sizeof(int32_t) * M));
   USFFT_HIP(hipMalloc(&T.tw64, sizeof(cplx<double>) * L));
   USFFT_HIP(hipMalloc(&T.tw32, sizeof(cplx<float>) * L));
   USFFT_HIP(hipMalloc(&T.B64, sizeof(cplx<double>) * L));
   USFFT_HIP(hipMalloc(&T.B32, sizeof(cplx<float>) * L));
   USFFT_HIP(hipMemcpyAsync(T.perm, perm.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, st));
   USFFT_HIP(hipMemcpyAsync(T.outidx, outidx.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
+  USFFT_HIP(hipMemcpyAsync(T.dlog, dlog.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
   USFFT_HIP(hipMemcpyAsync(T.tw64, tw.data(), sizeof(cplx<double>) * L, hipMemcpyHostToDevice, st));
   FftPlanDev F;
   F.L = L;
@@ -337,8 +340,8 @@ void rader_build(RaderTables& T, int M, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- lattice DFT
-template <typename T>
-__global__ __launch_bounds__(kFftBlock) void rader_kernel(FftPlanDev F, int M, const int32_t* __restrict__ perm,
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void rader_kernel(FftPlanDev F, int M, const int32_t* __restrict__ dlog,
                                                           const int32_t* __restrict__ outidx,
                                                           const cplx<T>* __restrict__ tw,
                                                           const cplx<T>* __restrict__ B, const T* __restrict__ u,
@@ -348,36 +351,35 @@ __global__ __launch_bounds__(kFftBlock) void rader_kernel(FftPlanDev F, int M, c
                                                           int out_kind, void* __restrict__ out, int64_t ldo) {
   extern __shared__ char smem[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  __shared__ double red[2 * (kFftBlock / kWave)];
+  __shared__ double red[2 * (BLOCK / kWave)];
   const int64_t pair = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t g1 = 2 * pair, g2 = g1 + 1;
   const bool has2 = g2 < G;
   const T* u1 = u + g1 * ld + col0;
   const T* u2 = u + (has2 ? g2 : g1) * ld + col0;
   const int L = F.L;
-  // Rader input a_q = x[g^q], gathered straight from the two rows (each row
-  // segment is read once from HBM; the permuted order is served by the
-  // caches), plus the sums for X[0]
+  // Rader input a_q = x[g^q]: the two row segments are read in natural
+  // order (coalesced) and scattered into LDS at q = dlog m; plus the sums
+  // for X[0]
   double s1 = 0.0, s2 = 0.0;
-  for (int q = threadIdx.x; q < L; q += kFftBlock) {
-    const int mq = perm[q];
-    const T a = u1[mq];
-    const T b = has2 ? u2[mq] : (T)0;
-    buf[q] = {a, b};
+  for (int mm = 1 + threadIdx.x; mm < M; mm += BLOCK) {
+    const T a = u1[mm];
+    const T b = has2 ? u2[mm] : (T)0;
+    buf[dlog[mm]] = {a, b};
     s1 += (double)a;
     s2 += (double)b;
   }
   const T x01 = u1[0];
   const T x02 = has2 ? u2[0] : (T)0;
-  block_sum2<kFftBlock>(s1, s2, red);  // also orders the LDS writes before the first stage
+  block_sum2<BLOCK>(s1, s2, red);  // also orders the LDS writes before the first stage
   s1 += (double)x01;
   s2 += (double)x02;
   // c = a (*) b: forward DIF, times B (same order), conjugate, forward DIT;
   // buf then holds conj(c) in natural order.
-  fft_dif<T>(buf, F, tw, B);
-  fft_dit<T>(buf, F, tw);
+  fft_dif<T, BLOCK>(buf, F, tw, B);
+  fft_dit<T, BLOCK>(buf, F, tw);
   const double invM = 1.0 / (double)M;
-  for (int a = threadIdx.x; a < nb; a += kFftBlock) {
+  for (int a = threadIdx.x; a < nb; a += BLOCK) {
     const int b = bins[a];
     const int bc = min(b, M - b);
     const bool flip = b > M - b;
@@ -428,15 +430,29 @@ void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t
   F.nrad = T.nrad;
   for (int i = 0; i < 24; ++i) F.radix[i] = T.radix[i];
   const unsigned grid = (unsigned)ceil_div(G, 2);
+  // workgroup sized to the transform: about L / 8 butterflies per radix-8
+  // stage; smaller groups let more node pairs share a CU
+  const int block = T.L <= 1024 ? 128 : (T.L <= 3072 ? 256 : 512);
+#define USFFT_RADER(TT, BB, TW, BS)                                                                            \
+  hipLaunchKernelGGL((rader_kernel<TT, BB>), dim3(grid), dim3(BB), sizeof(cplx<TT>) * T.L, st, F, T.M, T.dlog, \
+                     T.outidx, (const cplx<TT>*)TW, (const cplx<TT>*)BS, (const TT*)u, G, ld, col0, bins, pos,   \
+                     pos_base, nb, out_kind, out, ldo)
   if (u_fp32) {
-    hipLaunchKernelGGL(rader_kernel<float>, dim3(grid), dim3(kFftBlock), sizeof(cplx<float>) * T.L, st, F, T.M,
-                       T.perm, T.outidx, (const cplx<float>*)T.tw32, (const cplx<float>*)T.B32,
-                       (const float*)u, G, ld, col0, bins, pos, pos_base, nb, out_kind, out, ldo);
+    if (block == 128)
+      USFFT_RADER(float, 128, T.tw32, T.B32);
+    else if (block == 256)
+      USFFT_RADER(float, 256, T.tw32, T.B32);
+    else
+      USFFT_RADER(float, 512, T.tw32, T.B32);
   } else {
-    hipLaunchKernelGGL(rader_kernel<double>, dim3(grid), dim3(kFftBlock), sizeof(cplx<double>) * T.L, st, F,
-                       T.M, T.perm, T.outidx, (const cplx<double>*)T.tw64, (const cplx<double>*)T.B64,
-                       (const double*)u, G, ld, col0, bins, pos, pos_base, nb, out_kind, out, ldo);
+    if (block == 128)
+      USFFT_RADER(double, 128, T.tw64, T.B64);
+    else if (block == 256)
+      USFFT_RADER(double, 256, T.tw64, T.B64);
+    else
+      USFFT_RADER(double, 512, T.tw64, T.B64);
   }
+#undef USFFT_RADER
   USFFT_HIP(hipGetLastError());
 }
 

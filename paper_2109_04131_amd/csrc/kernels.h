@@ -40,11 +40,14 @@ void launch_pde_solve_stream(const PdeDev& P, const double* Y, int64_t ns, doubl
 int dst_padded(int n);             // MP = 32 or 64, 0 if the mesh is too large
 int64_t dst_frag_bytes(int mp);    // S fragment table of one mesh size
 void dst_tables_build(int n, void* frag, float* lam, hipStream_t st);  // lam: MP floats
-int dst_persistent_blocks(int n, int precision);
-int64_t dst_edge_stride(int mp);   // doubles per scratch grid; 3 grids per workgroup
-void launch_pde_solve_dst(const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol, int maxit,
-                          double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld, int64_t col0,
-                          int* iters, double* wscr, int wblocks, const void* frag, const float* lam,
+// variant 0: edge grids and scaling in a global scratch slot per workgroup
+// (more resident workgroups); 1: all of it in LDS (one workgroup per CU).
+int dst_persistent_blocks(int n, int precision, int variant);
+int64_t dst_edge_stride(int mp);   // doubles per scratch grid
+int64_t dst_scratch_doubles(int n, int variant, int blocks);
+void launch_pde_solve_dst(const PdeDev& P, int precision, int variant, const double* Y, int64_t ns, double rtol,
+                          int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
+                          int64_t col0, int* iters, double* wscr, int wblocks, const void* frag, const float* lam,
                           hipStream_t st);
 void launch_trigpoly(int d, const double* Y, int64_t ns, const int32_t* K, int64_t np, const double* C,
                      int64_t G, void* out, int out_fp32, int64_t ld, int64_t col0, hipStream_t st);
@@ -56,6 +59,7 @@ struct RaderTables {
   int nrad = 0;
   int radix[24] = {0};
   int32_t* perm = nullptr;    // L: gen^q mod M
+  int32_t* dlog = nullptr;    // M: q with gen^q = m (entry 0 unused)
   int32_t* outidx = nullptr;  // M: index p with b = gen^(-p) mod M (entry 0 unused)
   void* tw64 = nullptr;       // L complex double: exp(-2 pi i k / L)
   void* tw32 = nullptr;       // L complex float

@@ -198,37 +198,49 @@ __host__ __device__ constexpr int64_t dst_grid_elems(int mp) {
 // Resident waves per SIMD the register allocation targets: float32 state fits
 // two 64-wide strips per SIMD (two samples per CU at MP = 64), float64 state
 // one.
-template <typename T, int MP>
+template <typename T, int MP, bool LR>
 constexpr int dst_waves() {
-  return std::is_same<T, float>::value ? (MP == 64 ? 2 : 3) : (MP == 64 ? 1 : 2);
+  return LR ? 1 : (std::is_same<T, float>::value ? (MP == 64 ? 2 : 3) : (MP == 64 ? 1 : 2));
 }
 
 // Doubles of one grid of a workgroup's global scratch (pitch PP); the
 // scratch holds three per workgroup: eh, ev and D^-1/2.
 int64_t dst_edge_stride(int mp) { return ((int64_t)dst_pitch(mp) * dst_pitch(mp) + 31) / 32 * 32; }
 
-// Dynamic LDS bytes of one workgroup.
-int64_t dst_lds_bytes(int n, int precision) {
+// Dynamic LDS bytes of one workgroup: [u (float32 solves), float64][p, T]
+// [exchange tiles][LDS-resident variant: eh, ev float64, D^-1/2 in T].
+int64_t dst_lds_bytes(int n, int precision, int variant) {
   const int mp = dst_padded(n);
   const int64_t g = dst_grid_elems(mp);
   const int64_t grids = precision == USFFT_FP64 ? g * 8 : g * 8 + g * 4;
-  return grids + 2 * (int64_t)mp * (mp + 4) * 2;
+  return grids + 2 * (int64_t)mp * (mp + 4) * 2 + (variant == 1 ? g * (8 + 8 + (precision == USFFT_FP64 ? 8 : 4)) : 0);
+}
+
+// One-lane shift of a wave (DPP wave_shr:1): lane l gets lane l-1's value,
+// lane 0 keeps its own.
+__device__ __forceinline__ double wave_shr1(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false));
 }
 
 // Assembly of one sample (eq. (1.2) at the triangle centroids): the edge
 // grids eh[j PP + i] = (aL(i,j) + aU(i,j-1))/2 (i < n, 1 <= j < n) and
 // ev[j PP + i] = (aU(i,j) + aL(i-1,j))/2 (1 <= i < n, j < n), and the Jacobi
-// scaling D^-1/2 of every interior node, written to sd (LDS) and dg (global).
-// Lane = cell column ci (chunks of 64), each wave sweeps blocks of 8 cell
-// rows cj (plus the row below).  a(ci, cj) = a0 + sum_k (coef_k x_k(ci)) y_k(cj)
-// is separable: with k outermost, the per-lane factors are loaded once per k
-// and the row factors are wave-uniform (scalar loads).  Each thread forms the
-// coefficients of column ci and of column ci-1, so every edge around its
-// nodes is available in registers.
-template <int NWAVE>
+// scaling D^-1/2 of every interior node, written to dg.  Float32 solves keep
+// it rounded to float32 (their float64 true residual uses the unscaled
+// operator, so the scaled diagonal need not be exactly 4 there); float64
+// solves keep it in float64, where the scaled diagonal is 4 to rounding.
+// Lane = cell column ci, each wave sweeps blocks of CB cell rows cj (plus
+// the row below).  a(ci, cj) = a0 + sum_k (coef_k x_k(ci)) y_k(cj) is
+// separable: with k outermost, the per-lane factors are loaded once per k and
+// the row factors are wave-uniform (scalar loads).  Column ci-1's
+// coefficients come from the neighbouring lane; columns are covered in
+// chunks of 64 lanes overlapping by one (lane 0 of a later chunk only
+// supplies its neighbour's values).
+template <int NWAVE, int CB, typename DT>
 __device__ void assemble(const PdeDev& P, const double* coef, double* __restrict__ eh, double* __restrict__ ev,
-                         double* __restrict__ dg, double* sd, int PP, int tid) {
-  constexpr int CB = 8;
+                         DT* __restrict__ dg, int PP, int tid) {
   const int n = P.n, d = P.d, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double* txL = P.tab;                  // x1 factor, lower triangles
   const double* txU = P.tab + (size_t)d * n;  // x1 factor, upper triangles
@@ -237,53 +249,56 @@ __device__ void assemble(const PdeDev& P, const double* coef, double* __restrict
   typedef const __attribute__((address_space(4))) double* cdp;
   const cdp tyL = (cdp)(P.tab + (size_t)2 * d * n);
   const cdp tyU = (cdp)(P.tab + (size_t)3 * d * n);
-  for (int ci0 = 0; ci0 < n; ci0 += 64) {
-    const int ci = ci0 + lane;
-    const bool act = ci < n, left = act && ci >= 1;
+  for (int c0 = 0; c0 == 0 || c0 + 1 < n; c0 += 63) {
+    const int ci = c0 + lane;
+    const bool act = ci < n, outp = act && (c0 == 0 || lane >= 1);
+    const int cic = min(ci, n - 1);  // clamped: table loads stay unconditional
     for (int cb = wave * CB; cb < n; cb += NWAVE * CB) {
       // row u of the block is cell row cj = cb - 1 + u
-      double aL[CB + 1], aU[CB + 1], aLm[CB + 1], aUm[CB + 1];
+      double aL[CB + 1], aU[CB + 1];
 #pragma unroll
-      for (int u = 0; u <= CB; ++u) aL[u] = aU[u] = aLm[u] = aUm[u] = P.a0;
+      for (int u = 0; u <= CB; ++u) aL[u] = aU[u] = P.a0;
 #pragma unroll 2
       for (int k = 0; k < d; ++k) {
         const double ck = coef[k];
-        const double xl = act ? ck * txL[k * n + ci] : 0.0, xu = act ? ck * txU[k * n + ci] : 0.0;
-        const double xlm = left ? ck * txL[k * n + ci - 1] : 0.0, xum = left ? ck * txU[k * n + ci - 1] : 0.0;
-        // rows outside [0, n) are clamped (their values are never used), so
-        // the loop has no branches and all loads of one k are in flight at once
+        const double txl = txL[k * n + cic], txu = txU[k * n + cic];
+        const double xl = act ? ck * txl : 0.0, xu = act ? ck * txu : 0.0;
+        // rows outside [0, n) are clamped (their values are never used); all
+        // row factors of one k are loaded before any is used
+        double yl[CB + 1], yu[CB + 1];
 #pragma unroll
         for (int u = 0; u <= CB; ++u) {
           const int cj = min(max(cb - 1 + u, 0), n - 1);
-          const double yl = tyL[k * n + cj], yu = tyU[k * n + cj];
-          aL[u] += xl * yl;
-          aU[u] += xu * yu;
-          aLm[u] += xlm * yl;
-          aUm[u] += xum * yu;
+          yl[u] = tyL[k * n + cj];
+          yu[u] = tyU[k * n + cj];
+        }
+#pragma unroll
+        for (int u = 0; u <= CB; ++u) {
+          aL[u] += xl * yl[u];
+          aU[u] += xu * yu[u];
         }
       }
 #pragma unroll
       for (int u = 1; u <= CB; ++u) {
         const int cj = cb - 1 + u;
-        if (cj >= n || !act) continue;
-        const double ehc = 0.5 * (aL[u] + aU[u - 1]);   // eh(ci, cj)
-        const double evc = 0.5 * (aU[u] + aLm[u]);      // ev(ci, cj)
+        const double aLm = wave_shr1(aL[u]), aUm1 = wave_shr1(aU[u - 1]), aLm1 = wave_shr1(aL[u - 1]);
+        if (cj >= n || !outp) continue;
+        const double ehc = 0.5 * (aL[u] + aU[u - 1]);  // eh(ci, cj)
+        const double evc = 0.5 * (aU[u] + aLm);        // ev(ci, cj)
         if (cj >= 1) eh[cj * PP + ci] = ehc;
         if (ci >= 1) ev[cj * PP + ci] = evc;
         if (ci >= 1 && cj >= 1) {
-          const double ehm = 0.5 * (aLm[u] + aUm[u - 1]);   // eh(ci-1, cj)
-          const double evm = 0.5 * (aU[u - 1] + aLm[u - 1]);  // ev(ci, cj-1)
-          const double di = 1.0 / sqrt(0.25 * (ehc + ehm + evc + evm));
-          sd[cj * PP + ci] = di;
-          dg[cj * PP + ci] = di;
+          const double ehm = 0.5 * (aLm + aUm1);        // eh(ci-1, cj)
+          const double evm = 0.5 * (aU[u - 1] + aLm1);  // ev(ci, cj-1)
+          dg[cj * PP + ci] = (DT)(1.0 / sqrt(0.25 * (ehc + ehm + evc + evm)));
         }
       }
     }
   }
 }
 
-template <typename T, int MP>
-__global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_waves<T, MP>()))) void pcgdst_kernel(
+template <typename T, int MP, bool LR>
+__global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_waves<T, MP, LR>()))) void pcgdst_kernel(
     PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, double inner_rtol, int refine_every,
     void* __restrict__ out, int out_fp32, int64_t ld, int64_t col0, int* __restrict__ iters,
     double* __restrict__ wscr, int64_t wstride, const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
@@ -301,12 +316,21 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
   T* sp = reinterpret_cast<T*>(lds + (REFINE ? GE : 0));    // search direction (zero halo), staging
   _Float16* xa = reinterpret_cast<_Float16*>(sp + GE);      // exchange tiles, column-major
   _Float16* xb = xa + MP * LDX;
-  double* sd = REFINE ? sx : reinterpret_cast<double*>(sp);  // D^-1/2 during set-up
-  // this workgroup's float64 edge grids and Jacobi scaling, pitch PP like
-  // the LDS grids
-  double* eh = wscr + (size_t)blockIdx.x * 3 * wstride;
-  double* ev = eh + wstride;
-  double* dg = ev + wstride;
+  // float64 edge grids and the float32 Jacobi scaling, pitch PP like the
+  // LDS grids: in LDS (LR, one workgroup per CU) or in this workgroup's slot
+  // of the global scratch
+  double* eh;
+  double* ev;
+  T* dg;
+  if constexpr (LR) {
+    eh = reinterpret_cast<double*>(xb + MP * LDX);
+    ev = eh + GE;
+    dg = reinterpret_cast<T*>(ev + GE);
+  } else {
+    eh = wscr + (size_t)blockIdx.x * 3 * wstride;
+    ev = eh + wstride;
+    dg = reinterpret_cast<T*>(ev + wstride);
+  }
 
   const int lane = threadIdx.x & 63;
   half8 sf[KB * NT];
@@ -316,6 +340,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
   for (int64_t e = threadIdx.x; e < GE; e += BLOCK) {
     sp[e] = (T)0;
     if (REFINE) sx[e] = 0.0;
+    dg[e] = (T)0;  // the halo stays zero: boundary couplings vanish in the scaled weights
   }
 
   for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
@@ -333,14 +358,19 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
     __syncthreads();  // the previous sample is done with LDS, coef and the edge grids
     load_coef(P, Y, s, coef);
     __syncthreads();
-    assemble<BLOCK / 64>(P, coef, eh, ev, dg, sd, PP, tid);
+    assemble<BLOCK / 64, LR ? 16 : 8>(P, coef, eh, ev, dg, PP, tid);
     __syncthreads();
     // scaled weights: wE, wW, wS per node; wN(v) = wS(v + 1) inside a 4-row
     // group, so only the top row of each group keeps its own (wN4)
-    T wE[E], wW[E], wS[E], wN4[NT], r[E], p[E], dx[E];
+    // diagonal of the scaled operator: exactly 4 for float64 solves; float32
+    // solves with the LDS-resident scratch keep d_i^2 A_ii (their D^-1/2 is
+    // rounded to float32), the others use 4 and leave the difference to the
+    // float64 true residual
+    constexpr bool DIAG = REFINE && LR;
+    T wE[E], wW[E], wS[E], wN4[NT], r[E], p[E], dx[E], dd[DIAG ? E : 1];
     double bb = 0.0;
     {
-      const double* sdl = sd + base;
+      const T* sdl = dg + base;
       const double* ehl = eh + base;
       const double* evl = ev + base;
       // padding slots read in-bounds garbage (unwritten scratch) that the
@@ -355,13 +385,16 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
         wW[e] = ok ? (T)(ehl[o - 1] * di * sdl[o - 1]) : (T)0;
         wS[e] = ok ? (T)(evl[o - PP] * di * sdl[o - PP]) : (T)0;
         if (v == 3) wN4[t] = ok ? (T)(evl[o] * di * sdl[o + PP]) : (T)0;
+        if constexpr (DIAG)
+          dd[e] = ok ? (T)(di * di * (ehl[o] + ehl[o - 1] + evl[o] + evl[o - PP])) : (T)0;
         const double bt = ok ? di * P.h2 : 0.0;
         r[e] = (T)bt;
         bb += bt * bt;
       }
     }
-    bb = block_sum<BLOCK>(bb, red0);  // its barrier also ends the reads of sd
-    for (int g = tid; g < m * m; g += BLOCK) sd[(g / m + 1) * PP + g % m + 1] = 0.0;  // u = 0 / p = 0
+    bb = block_sum<BLOCK>(bb, red0);
+    if (REFINE)
+      for (int g = tid; g < m * m; g += BLOCK) sx[(g / m + 1) * PP + g % m + 1] = 0.0;  // u = 0
     float z[E];
     dst_apply<MP, T>(r, pow2_scale(bb), z, sf, xa, xb, slam);
     double rz = 0.0, rr = 0.0;
@@ -387,7 +420,8 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
       for (int e = 0; e < E; ++e) {
         const int o = off(e);
         const T wn = (e & 3) == 3 ? wN4[e >> 2] : wS[e + 1];
-        qv[e] = (T)4 * p[e] - (wE[e] * spl[o + 1] + wW[e] * spl[o - 1] + wn * spl[o + PP] + wS[e] * spl[o - PP]);
+        const T diag = DIAG ? dd[DIAG ? e : 0] : (T)4;
+        qv[e] = diag * p[e] - (wE[e] * spl[o + 1] + wW[e] * spl[o - 1] + wn * spl[o + PP] + wS[e] * spl[o - PP]);
         pq += (double)(p[e] * qv[e]);
       }
       pq = block_sum<BLOCK>(pq, red0);
@@ -417,7 +451,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
           asm volatile("" : "+v"(b2));
           const double* ehl = eh + b2;
           const double* evl = ev + b2;
-          const double* dgl = dg + b2;
+          const T* dgl = dg + b2;
           double* sxl = sx + b2;
           // (padding slots: unconditional in-bounds loads, results discarded
           // by selects; sx stays zero there)
@@ -472,7 +506,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
     // correction not yet folded into u (each lane reads only its own nodes
     // of sx)
     {
-      const double* dgl = dg + base;
+      const T* dgl = dg + base;
       const double* sxl = sx + base;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -486,59 +520,65 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
   }
 }
 
-template <typename T, int MP>
+template <typename T, int MP, bool LR>
 static int dst_occupancy(int n) {
   int per_cu = 0;
   USFFT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(pcgdst_kernel<T, MP>), 4 * MP,
-      dst_lds_bytes(n, std::is_same<T, float>::value ? USFFT_FP32_REFINE : USFFT_FP64)));
+      &per_cu, reinterpret_cast<const void*>(pcgdst_kernel<T, MP, LR>), 4 * MP,
+      dst_lds_bytes(n, std::is_same<T, float>::value ? USFFT_FP32_REFINE : USFFT_FP64, LR ? 1 : 0)));
   return std::max(1, per_cu);
 }
 
-int dst_persistent_blocks(int n, int precision) {
-  static int cache[2][2] = {{0, 0}, {0, 0}};  // [fp32?][mp == 64?]
+int dst_persistent_blocks(int n, int precision, int variant) {
+  static int cache[2][2][2] = {};  // [float32?][mp == 64?][LDS-resident?]
   const int mp = dst_padded(n);
-  const int a = precision == USFFT_FP64 ? 0 : 1, b = mp == 64 ? 1 : 0;
-  if (cache[a][b] == 0) {
+  const int a = precision == USFFT_FP64 ? 0 : 1, b = mp == 64 ? 1 : 0, c = variant == 1 ? 1 : 0;
+  if (cache[a][b][c] == 0) {
     int cus = 0, dev = 0;
     USFFT_HIP(hipGetDevice(&dev));
     USFFT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = 1;
-    if (a == 0)
-      per_cu = b ? dst_occupancy<double, 64>(n) : dst_occupancy<double, 32>(n);
-    else
-      per_cu = b ? dst_occupancy<float, 64>(n) : dst_occupancy<float, 32>(n);
-    cache[a][b] = per_cu * std::max(1, cus);
+#define USFFT_OCC(TT, MM, LL) per_cu = dst_occupancy<TT, MM, LL>(n)
+    if (a == 0) {
+      if (b) { if (c) USFFT_OCC(double, 64, true); else USFFT_OCC(double, 64, false); }
+      else { if (c) USFFT_OCC(double, 32, true); else USFFT_OCC(double, 32, false); }
+    } else {
+      if (b) { if (c) USFFT_OCC(float, 64, true); else USFFT_OCC(float, 64, false); }
+      else { if (c) USFFT_OCC(float, 32, true); else USFFT_OCC(float, 32, false); }
+    }
+#undef USFFT_OCC
+    cache[a][b][c] = per_cu * std::max(1, cus);
   }
-  return cache[a][b];
+  return cache[a][b][c];
 }
 
-void launch_pde_solve_dst(const PdeDev& P, int precision, const double* Y, int64_t ns, double rtol, int maxit,
-                          double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld, int64_t col0,
-                          int* iters, double* wscr, int wblocks, const void* frag, const float* lam,
+int64_t dst_scratch_doubles(int n, int variant, int blocks) {
+  return variant == 1 ? 0 : 3 * dst_edge_stride(dst_padded(n)) * (int64_t)blocks;
+}
+
+void launch_pde_solve_dst(const PdeDev& P, int precision, int variant, const double* Y, int64_t ns, double rtol,
+                          int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
+                          int64_t col0, int* iters, double* wscr, int wblocks, const void* frag, const float* lam,
                           hipStream_t st) {
   if (ns <= 0) return;
   const int mp = dst_padded(P.n);
   USFFT_REQUIRE(mp > 0, USFFT_EINVAL, "mesh too large for the DST-preconditioned solver");
+  USFFT_REQUIRE(variant == 0 || variant == 1, USFFT_EINVAL, "bad DST solver variant");
   const int64_t ws = dst_edge_stride(mp);
   const unsigned grid = (unsigned)std::min<int64_t>(ns, wblocks);
-  const size_t lds = (size_t)dst_lds_bytes(P.n, precision);
+  const size_t lds = (size_t)dst_lds_bytes(P.n, precision, variant);
   const half8* sf = static_cast<const half8*>(frag);
+#define USFFT_DST(TT, MM, LL)                                                                                  \
+  hipLaunchKernelGGL((pcgdst_kernel<TT, MM, LL>), dim3(grid), dim3(4 * MM), lds, st, P, Y, ns, rtol, maxit,     \
+                     inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam)
   if (precision == USFFT_FP64) {
-    if (mp == 64)
-      hipLaunchKernelGGL((pcgdst_kernel<double, 64>), dim3(grid), dim3(256), lds, st, P, Y, ns, rtol, maxit,
-                         inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
-    else
-      hipLaunchKernelGGL((pcgdst_kernel<double, 32>), dim3(grid), dim3(128), lds, st, P, Y, ns, rtol, maxit,
-                         inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+    if (mp == 64) { if (variant) USFFT_DST(double, 64, true); else USFFT_DST(double, 64, false); }
+    else { if (variant) USFFT_DST(double, 32, true); else USFFT_DST(double, 32, false); }
   } else {
-    if (mp == 64)
-      hipLaunchKernelGGL((pcgdst_kernel<float, 64>), dim3(grid), dim3(256), lds, st, P, Y, ns, rtol, maxit,
-                         inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
-    else
-      hipLaunchKernelGGL((pcgdst_kernel<float, 32>), dim3(grid), dim3(128), lds, st, P, Y, ns, rtol, maxit,
-                         inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+    if (mp == 64) { if (variant) USFFT_DST(float, 64, true); else USFFT_DST(float, 64, false); }
+    else { if (variant) USFFT_DST(float, 32, true); else USFFT_DST(float, 32, false); }
   }
+#undef USFFT_DST
   USFFT_HIP(hipGetLastError());
 }
 

@@ -120,6 +120,7 @@ struct usfft_plan_s {
   int wblocks = 0;  // persistent workgroups of the float32 / DST solver
   bool streaming = false;  // mesh larger than the on-chip solvers hold
   bool dst = false;        // DST-preconditioned solver
+  int dst_variant = 1;     // 0: scratch in global memory, 1: LDS-resident
   usfft::PdeDev pde{};
   // Rader tables per lattice size
   std::map<int, usfft::RaderTables> rader;
@@ -255,7 +256,7 @@ static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
   if (ns <= 0) return;
   const usfft_params& par = P->par;
   if (P->prob.sampler == USFFT_SAMPLER_PDE && P->dst) {
-    launch_pde_solve_dst(P->pde, par.precision, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
+    launch_pde_solve_dst(P->pde, par.precision, P->dst_variant, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
                          par.refine_every, U, out_fp32, ld, col0, iters, P->d_wscr.as<double>(), P->wblocks,
                          P->d_sfrag.p, P->d_lam.as<float>(), st);
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->streaming) {
@@ -729,8 +730,15 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
       P->d_lam.ensure(sizeof(float) * mp);
       dst_tables_build(n, P->d_sfrag.p, P->d_lam.as<float>(), nullptr);
       USFFT_HIP(hipStreamSynchronize(nullptr));
-      P->wblocks = dst_persistent_blocks(n, par->precision);
-      P->d_wscr.ensure(sizeof(double) * 3 * (size_t)dst_edge_stride(mp) * P->wblocks);
+      // solver_config 0 / 1 forces the scratch placement (global scratch with
+      // more resident workgroups / LDS-resident, one workgroup per CU); the
+      // LDS-resident one is the default (the faster one at h = 1/64 in both
+      // precisions)
+      USFFT_REQUIRE(par->solver_config <= 1, USFFT_EINVAL, "solver_config of the DST solver must be <= 1");
+      P->dst_variant = par->solver_config >= 0 ? par->solver_config : 1;
+      P->wblocks = dst_persistent_blocks(n, par->precision, P->dst_variant);
+      P->d_wscr.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, dst_scratch_doubles(n, P->dst_variant,
+                                                                                         P->wblocks)));
     } else if (n > kMaxMesh) {
       // per-sample state exceeds one CU: streaming float64 solver
       P->streaming = true;

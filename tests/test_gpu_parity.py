@@ -51,18 +51,18 @@ def test_nodes_line_and_lattice_bit_exact(lib):
 
 
 # ------------------------------------------------------------------ sampler
-@pytest.mark.parametrize("precond", [0, 1], ids=["dst", "jacobi"])
+@pytest.mark.parametrize("precond,cfg", [(0, -2), (0, 0), (1, -2)], ids=["dst", "dst_global_scratch", "jacobi"])
 @pytest.mark.parametrize("n,d,modes,prec,tol", [
     (4, 2, "diagonal", 0, 1e-11), (8, 3, "diagonal", 0, 1e-11), (16, 4, "diagonal", 0, 1e-11),
     (33, 6, "split", 0, 1e-11), (34, 6, "split", 0, 1e-11), (64, 10, "split", 0, 1e-11),
     (65, 10, "split", 0, 1e-11), (16, 4, "diagonal", 1, 1e-9), (33, 6, "split", 1, 1e-9),
     (64, 10, "split", 1, 1e-9), (65, 10, "split", 1, 1e-9)])
-def test_pde_solves_match_banded_cholesky(lib, n, d, modes, prec, tol, precond):
+def test_pde_solves_match_banded_cholesky(lib, n, d, modes, prec, tol, precond, cfg):
     # n = 33 and 65 fill the padded 32 / 64 transform exactly, n = 34 is the
     # first mesh padded to 64, n = 4 the smallest (Jacobi: n = 65 streams)
     prob = W.pde_problem(n, d, 4, modes=modes)
     plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-13 if prec == 0 else 1e-12,
-                               solver_config=-2, precond=precond))
+                               solver_config=cfg, precond=precond))
     g = np.random.default_rng(n * 10 + d + prec)
     ns = 37
     Y = g.random((ns, d))
@@ -103,23 +103,28 @@ def test_solver_shapes_agree_and_batch_independent(lib):
         assert np.abs(o - outs[0]).max() <= 1e-12 * np.abs(outs[0]).max()
 
 
+@pytest.mark.parametrize("variant", [0, 1], ids=["global_scratch", "lds_resident"])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_dst_solver_batch_independent_and_fast(lib, prec):
+def test_dst_solver_batch_independent_and_fast(lib, prec, variant):
     # a sample's DST-PCG solution does not depend on the batch or workgroup
-    # that solves it (bitwise), and the fast-Poisson preconditioner keeps the
-    # iteration count of the h = 1/64, d = 10 workload small
+    # that solves it (bitwise), the fast-Poisson preconditioner keeps the
+    # iteration count of the h = 1/64, d = 10 workload small, and both
+    # scratch placements agree with the direct solve
     prob, _ = W.WORKLOADS["mesh64_d10"]
-    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-12))
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-12, solver_config=variant))
     Y = np.random.default_rng(11).random((300, prob["d"]))
     U = torch.zeros((plan.G, 300), dtype=torch.float64, device="cuda")
     it = torch.zeros(300, dtype=torch.int32, device="cuda")
     lib.sample(plan, dev(Y), U, 0, 300, 0, it)
     its = host(it)
     assert (its > 0).all() and its.max() <= 30, (its.min(), its.max())
+    S = ofem.PDESampler(64, prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
     for s in (0, 123, 299):
         U1 = torch.zeros((plan.G, 1), dtype=torch.float64, device="cuda")
         lib.sample(plan, dev(Y[s:s + 1]), U1, 0, 1)
         assert np.array_equal(host(U1)[:, 0], host(U)[:, s])
+        ref = S.solve_one(Y[s])
+        assert np.linalg.norm(host(U)[:, s] - ref) <= (1e-10 if prec == 0 else 1e-9) * np.linalg.norm(ref)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
