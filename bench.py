@@ -216,7 +216,7 @@ def main():
         "fft_GBps": fft_gbps,
         "pcg_iters_per_solve": iters / max(1, samples),
         "fp32_vs_fp64_samples_per_s": (value / out["fp64_path"]["samples_per_s"]) if out else None,
-        "roofline": {"kernel": "pcgdst_kernel<float,64> (DST-preconditioned float32 PCG + float64 "
+        "roofline": {"kernel": "pcgdst_kernel<float,64,true> (DST-preconditioned float32 PCG + float64 "
                                "reliable updates; preconditioner on fp16 MFMA)",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f16_mfma"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS["f16_mfma"], "traffic": measured_traffic(),
