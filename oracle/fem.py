@@ -18,12 +18,20 @@ The stiffness matrix is assembled triangle by triangle from the textbook
 P1 element matrix  K_T[a,b] = a_T * |T| * grad(phi_a) . grad(phi_b)  and the
 system is solved by a banded Cholesky factorisation (LAPACK via scipy).
 
-Pins (tests/test_oracle_fem.py): a = 1 against the discrete sine eigenbasis
+Coefficient models (Sec. 1 and 3.2): periodic (the default above), affine
+a = a0 + sum_j amp_j y_j psi_j and lognormal a = a0 + exp(sum_j amp_j y_j
+psi_j), with the parameter y = phi(t) of the usFFT node t given by the
+periodizations in oracle/periodization.py; psi_j = B1(m1 pi x1) B2(m2 pi x2)
+with B = sin or cos per axis.
+
+Pins (tests/test_oracle_fem.py, tests/test_oracle_periodization.py): a = 1 against the discrete sine eigenbasis
 closed form; manufactured discrete solutions; O(h^2) convergence to a smooth
 continuous solution; reflection symmetries of the mesh and coefficient.
 """
 import numpy as np
 from scipy.linalg import solveh_banded
+
+from .periodization import LOGNORMAL, PERIODIC, to_parameter
 
 
 def triangles(n):
@@ -98,14 +106,25 @@ class Mesh:
         return i * self.h, j * self.h
 
 
-def coefficient_on_triangles(mesh, a0, amp, mode1, mode2, y):
-    """Centroid values of a(x, y), eq. (1.2) with Theta_j(y) = sin(2 pi y_j)."""
+def _axis(basis, m, x):
+    """sin(m pi x) (basis 0) or cos(m pi x) (basis 1)."""
+    return np.cos(m * np.pi * x) if basis == 1 else np.sin(m * np.pi * x)
+
+
+def coefficient_on_triangles(mesh, a0, amp, mode1, mode2, y, model=PERIODIC, basis=(0, 0)):
+    """Centroid values of a(x, y) for the parameter y, with
+    psi_j(x) = B1(m1_j pi x1) B2(m2_j pi x2), B = sin or cos (eq. (1.2) and
+    the models of Sec. 1):
+      periodic:  a = a0 + sum_j amp_j sin(2 pi y_j) psi_j(x)
+      affine:    a = a0 + sum_j amp_j y_j psi_j(x)
+      lognormal: a = a0 + exp(sum_j amp_j y_j psi_j(x))."""
     cx = mesh.centroid[:, 0]
     cy = mesh.centroid[:, 1]
-    a = np.full(len(cx), float(a0))
+    b = np.zeros(len(cx))
     for j in range(len(amp)):
-        a += amp[j] * np.sin(2.0 * np.pi * y[j]) * np.sin(mode1[j] * np.pi * cx) * np.sin(mode2[j] * np.pi * cy)
-    return a
+        theta = np.sin(2.0 * np.pi * y[j]) if model == PERIODIC else y[j]
+        b += amp[j] * theta * _axis(basis[0], mode1[j], cx) * _axis(basis[1], mode2[j], cy)
+    return float(a0) + (np.exp(b) if model == LOGNORMAL else b)
 
 
 def banded_stiffness(mesh, a_tri):
@@ -137,7 +156,7 @@ def solve_banded(ab, rhs):
 class PDESampler:
     """Black-box sampler of Sec. 2.1: one solve per y gives u(x_g, y) for all g."""
 
-    def __init__(self, n, a0, amp, mode1, mode2):
+    def __init__(self, n, a0, amp, mode1, mode2, model=PERIODIC, alpha=-1.0, beta=1.0, delta=0.0, basis=(0, 0)):
         self.mesh = Mesh(n)
         self.n = n
         self.a0 = float(a0)
@@ -145,9 +164,12 @@ class PDESampler:
         self.mode1 = np.asarray(mode1)
         self.mode2 = np.asarray(mode2)
         self.G = self.mesh.G
+        self.model, self.alpha, self.beta, self.delta, self.basis = model, alpha, beta, delta, tuple(basis)
 
-    def solve_one(self, y):
-        a = coefficient_on_triangles(self.mesh, self.a0, self.amp, self.mode1, self.mode2, y)
+    def solve_one(self, t):
+        """One solve at the sampling node t in T^d (Sec. 3.2: y = phi(t))."""
+        y = to_parameter(self.model, t, self.alpha, self.beta, self.delta)
+        a = coefficient_on_triangles(self.mesh, self.a0, self.amp, self.mode1, self.mode2, y, self.model, self.basis)
         return solve_banded(banded_stiffness(self.mesh, a), self.mesh.load)
 
     def __call__(self, Y):
