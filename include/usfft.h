@@ -44,6 +44,19 @@ enum { USFFT_SAMPLER_PDE = 0, USFFT_SAMPLER_TRIG_POLY = 1 };
 enum { USFFT_FP64 = 0, USFFT_FP32_REFINE = 1 };
 enum { USFFT_OUT_MAG2 = 0, USFFT_OUT_COMPLEX = 1 };
 enum { USFFT_PRECOND_DST = 0, USFFT_PRECOND_JACOBI = 1 };
+/* Coefficient models (Sec. 1) and their periodizations (Sec. 3.2).  The
+ * usFFT samples at nodes t in [0,1)^d; the sampler maps them to the model's
+ * parameter y and usfft_eval maps evaluation points y back to t:
+ *   PERIODIC:  a = a0 + sum_j amp_j sin(2 pi t_j) psi_j,           y = t
+ *   AFFINE:    a = a0 + sum_j amp_j y_j psi_j, y_j = phi(t_j), tent
+ *              phi(t) = beta - |(beta - alpha)(1 - 2t)| (eq. (3.2)),
+ *              t = (y - alpha) / (2 (beta - alpha))
+ *   LOGNORMAL: a = a0 + exp(sum_j amp_j y_j psi_j), y_j = sqrt(2) erf^-1(2
+ *              tau(t_j)), tau the tent shifted by delta onto [-1/2, 1/2]
+ *              (eq. (3.3)), t = erf(y / sqrt(2)) / 4 + delta + 1/4.
+ * psi_j(x) = B1(mode1_j pi x1) B2(mode2_j pi x2), B = sin (basis 0) or
+ * cos (basis 1) per axis. */
+enum { USFFT_MODEL_PERIODIC = 0, USFFT_MODEL_AFFINE = 1, USFFT_MODEL_LOGNORMAL = 2 };
 
 typedef struct usfft_plan_s* usfft_plan_t;
 typedef struct usfft_result_s* usfft_result_t;
@@ -69,7 +82,7 @@ typedef struct {
   const int32_t* k_hi;
   int32_t sampler;
   /* PDE */
-  int32_t mesh_n;        /* 4 <= mesh_n <= 64                                */
+  int32_t mesh_n;        /* 4 <= mesh_n <= 512                               */
   double a0;
   const double* amp;     /* d                                                */
   const int32_t* mode1;  /* d                                                */
@@ -79,6 +92,14 @@ typedef struct {
   int64_t n_poly;
   const int32_t* poly_k; /* n_poly x d                                       */
   const double* poly_c;  /* n_poly x G_poly x 2                              */
+  /* PDE coefficient model (all zero: the periodic model with sine modes)   */
+  int32_t model;         /* USFFT_MODEL_*                                    */
+  double alpha, beta;    /* AFFINE: parameter interval, alpha < beta         */
+  double delta;          /* LOGNORMAL: tent shift in (0, 1/2); <= 0 takes
+                            1/(4 M_max), M_max = lattice_mmax (Lemma 3.1 for
+                            the largest admissible lattice: no lattice or
+                            line node falls on a pole of the map)            */
+  int32_t basis1, basis2;/* 0: sin, 1: cos along x1 / x2                     */
 } usfft_problem;
 
 /* Parameters of Alg. 1 ("Input": s, s_local, Algorithm A, theta, r) and of
@@ -156,21 +177,24 @@ usfft_status usfft_result_info(usfft_result_t res, int64_t* n_freq, int32_t* d,
 usfft_status usfft_result_copy(usfft_result_t res, int32_t* freqs_host, double* coeffs_host);
 void usfft_result_destroy(usfft_result_t res);
 
-/* Evaluation formula of Sec. 3.1 (periodic model, eq. (3.1) with phi = id):
- * out_dev[j*G + g] = Re sum_{k in I} c_k(u_{x_g}) exp(2 pi i k.y_j),
- * y_dev: n x d doubles.  Not part of the timed hot path. */
+/* Evaluation formula of Sec. 3.1 (eq. (3.1) with the model's inverse
+ * periodization of Sec. 3.2, see USFFT_MODEL_*):
+ * out_dev[j*G + g] = Re sum_{k in I} c_k(u_{x_g}) exp(2 pi i k.phi^{-1}(y_j)),
+ * y_dev: n x d doubles, parameters of the model (periodic: nodes in [0,1)).
+ * Not part of the timed hot path. */
 usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n,
                         double* out_dev, void* stream);
 
 /* ---- Stage entry points: each step of the hot path as its own call ---- */
 
 /* Black-box sampler (Sec. 2.1; Alg. 1 steps 1&2a and 2c): one solve per row
- * of y_dev (n x d doubles, components in [0,1)), sample of node g written to
+ * of y_dev (n x d doubles, sampling nodes t in [0,1)^d, mapped to the model's
+ * parameter by the periodization of Sec. 3.2), sample of node g written to
  * u_dev[g*ld + col0 + row] as float64 (out_fp32 = 0) or float32 (1).  With
- * the plan's precision: FP64 = float64 Jacobi-PCG; FP32_REFINE = float32
- * PCG with float64 residual correction.  iters_dev (n int32, may be NULL)
- * receives the iteration count of each solve (-1 = not converged).
- * Errors: EINVAL (ld < col0 + n), ENOCONV, EHIP. */
+ * the plan's precision: FP64 = float64 PCG; FP32_REFINE = float32 PCG with
+ * float64 reliable updates (preconditioner per params.precond).  iters_dev
+ * (n int32, may be NULL) receives the iteration count of each solve (-1 = not
+ * converged).  Errors: EINVAL (ld < col0 + n), ENOCONV, EHIP. */
 usfft_status usfft_sample(usfft_plan_t plan, const double* y_dev, int64_t n,
                           void* u_dev, int32_t out_fp32, int64_t ld, int64_t col0,
                           int32_t* iters_dev, void* stream);

@@ -7,6 +7,7 @@ fails loudly when the built library is missing; there is no CPU path.
 """
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -22,6 +23,7 @@ SAMPLER_PDE, SAMPLER_TRIG_POLY = 0, 1
 FP64, FP32_REFINE = 0, 1
 OUT_MAG2, OUT_COMPLEX = 0, 1
 PRECOND_DST, PRECOND_JACOBI = 0, 1
+MODEL_PERIODIC, MODEL_AFFINE, MODEL_LOGNORMAL = 0, 1, 2
 KIND_LAT2, KIND_LAT3 = 3, 4
 
 _P32 = C.POINTER(C.c_int32)
@@ -31,7 +33,9 @@ _PD = C.POINTER(C.c_double)
 class _Problem(C.Structure):
     _fields_ = [("d", C.c_int32), ("k_lo", _P32), ("k_hi", _P32), ("sampler", C.c_int32),
                 ("mesh_n", C.c_int32), ("a0", C.c_double), ("amp", _PD), ("mode1", _P32), ("mode2", _P32),
-                ("G_poly", C.c_int64), ("n_poly", C.c_int64), ("poly_k", _P32), ("poly_c", _PD)]
+                ("G_poly", C.c_int64), ("n_poly", C.c_int64), ("poly_k", _P32), ("poly_c", _PD),
+                ("model", C.c_int32), ("alpha", C.c_double), ("beta", C.c_double), ("delta", C.c_double),
+                ("basis1", C.c_int32), ("basis2", C.c_int32)]
 
 
 class _Params(C.Structure):
@@ -118,7 +122,11 @@ def _ptr(x):
 
 def _stream(stream):
     if stream is None:
-        import torch
+        # torch's current stream when the caller works with torch on the GPU,
+        # else the default stream (torch's default stream is that stream too)
+        torch = sys.modules.get("torch")
+        if torch is None or not torch.cuda.is_initialized():
+            return 0
         return torch.cuda.current_stream().cuda_stream
     if isinstance(stream, int):
         return stream
@@ -157,6 +165,12 @@ def _marshal(problem, params):
         pr.amp = arr(problem["amp"], np.float64)
         pr.mode1 = arr(problem["mode1"], np.int32)
         pr.mode2 = arr(problem["mode2"], np.int32)
+        pr.model = int(problem.get("model", MODEL_PERIODIC))
+        pr.alpha = float(problem.get("alpha", -1.0))
+        pr.beta = float(problem.get("beta", 1.0))
+        pr.delta = float(problem.get("delta", 0.0))
+        pr.basis1 = int(problem.get("basis1", 0))
+        pr.basis2 = int(problem.get("basis2", 0))
     else:
         pr.sampler = SAMPLER_TRIG_POLY
         K = np.asarray(problem["poly_k"])

@@ -132,42 +132,62 @@ struct FftPlanDev {
 //    and so F = S_0^T ... S_{S-1}^T Pi.
 // A convolution therefore never needs natural order in between: forward DIF,
 // pointwise product with a spectrum produced by the same DIF, DIT back.
-template <typename T, int R, int BLOCK>
+// COLS transforms of length L side by side (column c at buf + c L): a
+// butterfly loads its twiddles and spectrum values once for all columns.
+template <typename T, int R, int BLOCK, int COLS>
 __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw,
                           const cplx<T>* __restrict__ mulB) {
   const int nb = L / R, ts = L / N;
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
     const int blk = b / M, j = b - blk * M, base = blk * N + j;
-    cplx<T> v[R];
+    cplx<T> w[R], bq[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) v[m] = buf[base + m * M];
-    dft_small<T, R>(v);
+    for (int q = 1; q < R; ++q) w[q] = j > 0 ? tw[j * q * ts] : cplx<T>{(T)1, (T)0};
+    if (mulB) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      cplx<T> o = v[q];
-      if (q > 0 && j > 0) o = cmul(o, tw[j * q * ts]);
-      if (mulB) o = conjc(cmul(o, mulB[base + q * M]));
-      buf[base + q * M] = o;
+      for (int q = 0; q < R; ++q) bq[q] = mulB[base + q * M];
+    }
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      cplx<T>* bc = buf + c * L;
+      cplx<T> v[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[m] = bc[base + m * M];
+      dft_small<T, R>(v);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        cplx<T> o = v[q];
+        if (q > 0) o = cmul(o, w[q]);
+        if (mulB) o = conjc(cmul(o, bq[q]));
+        bc[base + q * M] = o;
+      }
     }
   }
   __syncthreads();
 }
 
-template <typename T, int R, int BLOCK>
+template <typename T, int R, int BLOCK, int COLS>
 __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw) {
   const int nb = L / R, ts = L / N;
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
     const int blk = b / M, j = b - blk * M, base = blk * N + j;
-    cplx<T> v[R];
+    cplx<T> w[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      cplx<T> a = buf[base + q * M];
-      if (q > 0 && j > 0) a = cmul(a, tw[j * q * ts]);
-      v[q] = a;
+    for (int q = 1; q < R; ++q) w[q] = j > 0 ? tw[j * q * ts] : cplx<T>{(T)1, (T)0};
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      cplx<T>* bc = buf + c * L;
+      cplx<T> v[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        cplx<T> a = bc[base + q * M];
+        if (q > 0) a = cmul(a, w[q]);
+        v[q] = a;
+      }
+      dft_small<T, R>(v);
+#pragma unroll
+      for (int m = 0; m < R; ++m) bc[base + m * M] = v[m];
     }
-    dft_small<T, R>(v);
-#pragma unroll
-    for (int m = 0; m < R; ++m) buf[base + m * M] = v[m];
   }
   __syncthreads();
 }
@@ -175,26 +195,26 @@ __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
 // Forward DIF over all stages; with mulB, the last stage multiplies by mulB
 // and conjugates (the forward half of a convolution, set up for the inverse
 // transform by conjugation).
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, int COLS>
 __device__ void fft_dif(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, const cplx<T>* mulB) {
   int N = F.L;
   for (int s = 0; s < F.nrad; ++s) {
     const int R = F.radix[s], M = N / R;
     const cplx<T>* mb = (s == F.nrad - 1) ? mulB : nullptr;
     switch (R) {
-      case 2: dif_stage<T, 2, BLOCK>(buf, F.L, N, M, tw, mb); break;
-      case 3: dif_stage<T, 3, BLOCK>(buf, F.L, N, M, tw, mb); break;
-      case 4: dif_stage<T, 4, BLOCK>(buf, F.L, N, M, tw, mb); break;
-      case 5: dif_stage<T, 5, BLOCK>(buf, F.L, N, M, tw, mb); break;
-      case 7: dif_stage<T, 7, BLOCK>(buf, F.L, N, M, tw, mb); break;
-      default: dif_stage<T, 8, BLOCK>(buf, F.L, N, M, tw, mb); break;
+      case 2: dif_stage<T, 2, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
+      case 3: dif_stage<T, 3, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
+      case 4: dif_stage<T, 4, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
+      case 5: dif_stage<T, 5, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
+      case 7: dif_stage<T, 7, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
+      default: dif_stage<T, 8, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
     }
     N = M;
   }
 }
 
 // Forward DIT over all stages in reverse order (digit-reversed in, natural out).
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, int COLS>
 __device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
   int Ns[24];
   int N = F.L;
@@ -205,12 +225,12 @@ __device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
   for (int s = F.nrad - 1; s >= 0; --s) {
     const int R = F.radix[s], Nn = Ns[s], M = Nn / R;
     switch (R) {
-      case 2: dit_stage<T, 2, BLOCK>(buf, F.L, Nn, M, tw); break;
-      case 3: dit_stage<T, 3, BLOCK>(buf, F.L, Nn, M, tw); break;
-      case 4: dit_stage<T, 4, BLOCK>(buf, F.L, Nn, M, tw); break;
-      case 5: dit_stage<T, 5, BLOCK>(buf, F.L, Nn, M, tw); break;
-      case 7: dit_stage<T, 7, BLOCK>(buf, F.L, Nn, M, tw); break;
-      default: dit_stage<T, 8, BLOCK>(buf, F.L, Nn, M, tw); break;
+      case 2: dit_stage<T, 2, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
+      case 3: dit_stage<T, 3, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
+      case 4: dit_stage<T, 4, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
+      case 5: dit_stage<T, 5, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
+      case 7: dit_stage<T, 7, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
+      default: dit_stage<T, 8, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
     }
   }
 }
@@ -233,7 +253,7 @@ __global__ __launch_bounds__(kFftBlock) void rader_setup_kernel(FftPlanDev F, in
     buf[j] = {c, s};
   }
   __syncthreads();
-  fft_dif<double, kFftBlock>(buf, F, tw, nullptr);  // spectrum in the DIF (digit-reversed) order
+  fft_dif<double, kFftBlock, 1>(buf, F, tw, nullptr);  // spectrum in the DIF (digit-reversed) order
   const double invL = 1.0 / (double)L;
   for (int k = threadIdx.x; k < L; k += kFftBlock) {
     const cplx<double> v = {buf[k].x * invL, buf[k].y * invL};
@@ -340,82 +360,119 @@ void rader_build(RaderTables& T, int M, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- lattice DFT
-template <typename T, int BLOCK>
+// Block-wide sums of N values in a fixed order (wave sums, then waves in
+// order); every thread returns the same sums.
+template <int BLOCK, int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double* red) {
+  constexpr int NW = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[w * N + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double t = red[i];
+    for (int k = 1; k < NW; ++k) t += red[k * N + i];
+    v[i] = t;
+  }
+}
+
+// COLS node pairs per workgroup, each pair packed as one complex column.
+template <typename T, int BLOCK, int COLS>
 __global__ __launch_bounds__(BLOCK) void rader_kernel(FftPlanDev F, int M, const int32_t* __restrict__ dlog,
-                                                          const int32_t* __restrict__ outidx,
-                                                          const cplx<T>* __restrict__ tw,
-                                                          const cplx<T>* __restrict__ B, const T* __restrict__ u,
-                                                          int64_t G, int64_t ld, int64_t col0,
-                                                          const int32_t* __restrict__ bins,
-                                                          const int32_t* __restrict__ pos, int pos_base, int nb,
-                                                          int out_kind, void* __restrict__ out, int64_t ldo) {
+                                                      const int32_t* __restrict__ outidx,
+                                                      const cplx<T>* __restrict__ tw,
+                                                      const cplx<T>* __restrict__ B, const T* __restrict__ u,
+                                                      int64_t G, int64_t ld, int64_t col0,
+                                                      const int32_t* __restrict__ bins,
+                                                      const int32_t* __restrict__ pos, int pos_base, int nb,
+                                                      int out_kind, void* __restrict__ out, int64_t ldo) {
   extern __shared__ char smem[];
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  __shared__ double red[2 * (BLOCK / kWave)];
-  const int64_t pair = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t g1 = 2 * pair, g2 = g1 + 1;
-  const bool has2 = g2 < G;
-  const T* u1 = u + g1 * ld + col0;
-  const T* u2 = u + (has2 ? g2 : g1) * ld + col0;
+  __shared__ double red[2 * COLS * (BLOCK / kWave)];
+  const int64_t grp = xcd_remap(blockIdx.x, gridDim.x);
   const int L = F.L;
-  // Rader input a_q = x[g^q]: the two row segments are read in natural
-  // order (coalesced) and scattered into LDS at q = dlog m; plus the sums
-  // for X[0]
-  double s1 = 0.0, s2 = 0.0;
-  for (int mm = 1 + threadIdx.x; mm < M; mm += BLOCK) {
-    const T a = u1[mm];
-    const T b = has2 ? u2[mm] : (T)0;
-    buf[dlog[mm]] = {a, b};
-    s1 += (double)a;
-    s2 += (double)b;
+  const T* r1[COLS];
+  const T* r2[COLS];
+  bool has1[COLS], has2[COLS];
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    const int64_t g1 = 2 * (grp * COLS + c), g2 = g1 + 1;
+    has1[c] = g1 < G;
+    has2[c] = g2 < G;
+    r1[c] = u + (has1[c] ? g1 : 0) * ld + col0;  // rows past G are never read
+    r2[c] = u + (has2[c] ? g2 : 0) * ld + col0;
   }
-  const T x01 = u1[0];
-  const T x02 = has2 ? u2[0] : (T)0;
-  block_sum2<BLOCK>(s1, s2, red);  // also orders the LDS writes before the first stage
-  s1 += (double)x01;
-  s2 += (double)x02;
+  // Rader input a_q = x[g^q]: each row segment is read in natural order
+  // (coalesced) and scattered into LDS at q = dlog m; plus the sums for X[0]
+  double sums[2 * COLS];
+#pragma unroll
+  for (int i = 0; i < 2 * COLS; ++i) sums[i] = 0.0;
+  for (int mm = 1 + threadIdx.x; mm < M; mm += BLOCK) {
+    const int q = dlog[mm];
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+      const T a = has1[c] ? r1[c][mm] : (T)0;
+      const T b = has2[c] ? r2[c][mm] : (T)0;
+      buf[c * L + q] = {a, b};
+      sums[2 * c] += (double)a;
+      sums[2 * c + 1] += (double)b;
+    }
+  }
+  block_sum_n<BLOCK, 2 * COLS>(sums, red);  // also orders the LDS writes before the first stage
   // c = a (*) b: forward DIF, times B (same order), conjugate, forward DIT;
   // buf then holds conj(c) in natural order.
-  fft_dif<T, BLOCK>(buf, F, tw, B);
-  fft_dit<T, BLOCK>(buf, F, tw);
+  fft_dif<T, BLOCK, COLS>(buf, F, tw, B);
+  fft_dit<T, BLOCK, COLS>(buf, F, tw);
   const double invM = 1.0 / (double)M;
-  for (int a = threadIdx.x; a < nb; a += BLOCK) {
-    const int b = bins[a];
-    const int bc = min(b, M - b);
-    const bool flip = b > M - b;
-    double X1r, X1i, X2r, X2i;
-    if (bc == 0) {
-      X1r = s1 * invM;
-      X1i = 0.0;
-      X2r = s2 * invM;
-      X2i = 0.0;
-    } else {
-      const cplx<T> cp = buf[outidx[bc]];
-      const cplx<T> cm = buf[outidx[M - bc]];
-      // X[bc] = x0 + c, X[M-bc] = x0 + c', with c = conj(buf)
-      const double Xpr = (double)x01 + (double)cp.x, Xpi = (double)x02 - (double)cp.y;
-      const double Xmr = (double)x01 + (double)cm.x, Xmi = (double)x02 - (double)cm.y;
-      X1r = 0.5 * (Xpr + Xmr) * invM;
-      X1i = 0.5 * (Xpi - Xmi) * invM;
-      X2r = 0.5 * (Xpi + Xmi) * invM;
-      X2i = -0.5 * (Xpr - Xmr) * invM;
-    }
-    if (flip) {
-      X1i = -X1i;
-      X2i = -X2i;
-    }
-    const int64_t c = pos ? pos[a] : pos_base + a;  // contiguous when pos is null
-    if (out_kind == USFFT_OUT_MAG2) {
+#pragma unroll
+  for (int c = 0; c < COLS; ++c) {
+    if (!has1[c]) continue;
+    const int64_t g1 = 2 * (grp * COLS + c), g2 = g1 + 1;
+    const double x01 = (double)r1[c][0], x02 = has2[c] ? (double)r2[c][0] : 0.0;
+    const double s1 = sums[2 * c] + x01, s2 = sums[2 * c + 1] + x02;
+    const cplx<T>* bc = buf + c * L;
+    for (int a = threadIdx.x; a < nb; a += BLOCK) {
+      const int b = bins[a];
+      const int bcn = min(b, M - b);
+      const bool flip = b > M - b;
+      double X1r, X1i, X2r, X2i;
+      if (bcn == 0) {
+        X1r = s1 * invM;
+        X1i = 0.0;
+        X2r = s2 * invM;
+        X2i = 0.0;
+      } else {
+        const cplx<T> cp = bc[outidx[bcn]];
+        const cplx<T> cm = bc[outidx[M - bcn]];
+        // X[bc] = x0 + c, X[M-bc] = x0 + c', with c = conj(buf)
+        const double Xpr = x01 + (double)cp.x, Xpi = x02 - (double)cp.y;
+        const double Xmr = x01 + (double)cm.x, Xmi = x02 - (double)cm.y;
+        X1r = 0.5 * (Xpr + Xmr) * invM;
+        X1i = 0.5 * (Xpi - Xmi) * invM;
+        X2r = 0.5 * (Xpi + Xmi) * invM;
+        X2i = -0.5 * (Xpr - Xmr) * invM;
+      }
+      if (flip) {
+        X1i = -X1i;
+        X2i = -X2i;
+      }
+      const int64_t cc = pos ? pos[a] : pos_base + a;  // contiguous when pos is null
       double* o = static_cast<double*>(out);
-      o[g1 * ldo + c] = X1r * X1r + X1i * X1i;
-      if (has2) o[g2 * ldo + c] = X2r * X2r + X2i * X2i;
-    } else {
-      double* o = static_cast<double*>(out);
-      o[(c * G + g1) * 2] = X1r;
-      o[(c * G + g1) * 2 + 1] = X1i;
-      if (has2) {
-        o[(c * G + g2) * 2] = X2r;
-        o[(c * G + g2) * 2 + 1] = X2i;
+      if (out_kind == USFFT_OUT_MAG2) {
+        o[g1 * ldo + cc] = X1r * X1r + X1i * X1i;
+        if (has2[c]) o[g2 * ldo + cc] = X2r * X2r + X2i * X2i;
+      } else {
+        o[(cc * G + g1) * 2] = X1r;
+        o[(cc * G + g1) * 2 + 1] = X1i;
+        if (has2[c]) {
+          o[(cc * G + g2) * 2] = X2r;
+          o[(cc * G + g2) * 2 + 1] = X2i;
+        }
       }
     }
   }
@@ -429,29 +486,40 @@ void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t
   F.L = T.L;
   F.nrad = T.nrad;
   for (int i = 0; i < 24; ++i) F.radix[i] = T.radix[i];
-  const unsigned grid = (unsigned)ceil_div(G, 2);
-  // workgroup sized to the transform: about L / 8 butterflies per radix-8
-  // stage; smaller groups let more node pairs share a CU
+  // workgroup sized to the transform (about L / 8 butterflies per radix-8
+  // stage); several node pairs per workgroup while their transforms fit in
+  // 64 KB of LDS, so twiddle and spectrum loads serve several columns
   const int block = T.L <= 1024 ? 128 : (T.L <= 3072 ? 256 : 512);
-#define USFFT_RADER(TT, BB, TW, BS)                                                                            \
-  hipLaunchKernelGGL((rader_kernel<TT, BB>), dim3(grid), dim3(BB), sizeof(cplx<TT>) * T.L, st, F, T.M, T.dlog, \
-                     T.outidx, (const cplx<TT>*)TW, (const cplx<TT>*)BS, (const TT*)u, G, ld, col0, bins, pos,   \
-                     pos_base, nb, out_kind, out, ldo)
-  if (u_fp32) {
-    if (block == 128)
-      USFFT_RADER(float, 128, T.tw32, T.B32);
-    else if (block == 256)
-      USFFT_RADER(float, 256, T.tw32, T.B32);
-    else
-      USFFT_RADER(float, 512, T.tw32, T.B32);
-  } else {
-    if (block == 128)
-      USFFT_RADER(double, 128, T.tw64, T.B64);
-    else if (block == 256)
-      USFFT_RADER(double, 256, T.tw64, T.B64);
-    else
-      USFFT_RADER(double, 512, T.tw64, T.B64);
+  const size_t colbytes = (size_t)T.L * (u_fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>));
+  const int cols = 4 * colbytes <= (64u << 10) ? 4 : (2 * colbytes <= (64u << 10) ? 2 : 1);
+  const unsigned grid = (unsigned)ceil_div(G, 2 * cols);
+  const size_t lds = colbytes * cols;
+#define USFFT_RADER(TT, BB, CC, TW, BS)                                                                     \
+  hipLaunchKernelGGL((rader_kernel<TT, BB, CC>), dim3(grid), dim3(BB), lds, st, F, T.M, T.dlog, T.outidx,   \
+                     (const cplx<TT>*)TW, (const cplx<TT>*)BS, (const TT*)u, G, ld, col0, bins, pos, pos_base, \
+                     nb, out_kind, out, ldo)
+#define USFFT_RADER_B(TT, CC, TW, BS)        \
+  if (block == 128)                          \
+    USFFT_RADER(TT, 128, CC, TW, BS);        \
+  else if (block == 256)                     \
+    USFFT_RADER(TT, 256, CC, TW, BS);        \
+  else                                       \
+    USFFT_RADER(TT, 512, CC, TW, BS)
+#define USFFT_RADER_C(TT, TW, BS)            \
+  if (cols == 4) {                           \
+    USFFT_RADER_B(TT, 4, TW, BS);            \
+  } else if (cols == 2) {                    \
+    USFFT_RADER_B(TT, 2, TW, BS);            \
+  } else {                                   \
+    USFFT_RADER_B(TT, 1, TW, BS);            \
   }
+  if (u_fp32) {
+    USFFT_RADER_C(float, T.tw32, T.B32)
+  } else {
+    USFFT_RADER_C(double, T.tw64, T.B64)
+  }
+#undef USFFT_RADER_C
+#undef USFFT_RADER_B
 #undef USFFT_RADER
   USFFT_HIP(hipGetLastError());
 }

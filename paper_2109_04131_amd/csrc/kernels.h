@@ -15,7 +15,9 @@ struct PdeDev {
   int n, d;
   double a0, h2;
   const double* amp;  // d
-  const double* tab;  // 4 x d x n centroid sine tables
+  const double* tab;  // 4 x d x n centroid basis tables (sin or cos per axis)
+  int model;          // USFFT_MODEL_*
+  double alpha, beta, delta;
 };
 
 // ---- sampler.hip
@@ -98,7 +100,8 @@ void launch_lattice_take(const int32_t* bins, const int32_t* counts, uint8_t* co
                          int32_t* assign, int32_t* bin_out, hipStream_t st);
 
 // ---- eval.hip
+// Y holds parameters of the model; they are mapped back to nodes of T^d.
 void launch_eval(const int32_t* I, int64_t nI, int d, const double* C, int64_t G, const double* Y, int64_t n,
-                 double* out, hipStream_t st);
+                 int model, double alpha, double beta, double delta, double* out, hipStream_t st);
 
 }  // namespace usfft

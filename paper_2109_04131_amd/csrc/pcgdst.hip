@@ -224,7 +224,8 @@ __device__ __forceinline__ double wave_shr1(double v) {
                           __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false));
 }
 
-// Assembly of one sample (eq. (1.2) at the triangle centroids): the edge
+// Assembly of one sample (eq. (1.2) at the triangle centroids; the lognormal
+// model exponentiates the sum per triangle): the edge
 // grids eh[j PP + i] = (aL(i,j) + aU(i,j-1))/2 (i < n, 1 <= j < n) and
 // ev[j PP + i] = (aU(i,j) + aL(i-1,j))/2 (1 <= i < n, j < n), and the Jacobi
 // scaling D^-1/2 of every interior node, written to dg.  Float32 solves keep
@@ -255,9 +256,11 @@ __device__ void assemble(const PdeDev& P, const double* coef, double* __restrict
     const int cic = min(ci, n - 1);  // clamped: table loads stay unconditional
     for (int cb = wave * CB; cb < n; cb += NWAVE * CB) {
       // row u of the block is cell row cj = cb - 1 + u
+      // the lognormal model sums the exponent and exponentiates below
+      const bool logn = P.model == USFFT_MODEL_LOGNORMAL;
       double aL[CB + 1], aU[CB + 1];
 #pragma unroll
-      for (int u = 0; u <= CB; ++u) aL[u] = aU[u] = P.a0;
+      for (int u = 0; u <= CB; ++u) aL[u] = aU[u] = logn ? 0.0 : P.a0;
 #pragma unroll 2
       for (int k = 0; k < d; ++k) {
         const double ck = coef[k];
@@ -276,6 +279,13 @@ __device__ void assemble(const PdeDev& P, const double* coef, double* __restrict
         for (int u = 0; u <= CB; ++u) {
           aL[u] += xl * yl[u];
           aU[u] += xu * yu[u];
+        }
+      }
+      if (logn) {
+#pragma unroll
+        for (int u = 0; u <= CB; ++u) {
+          aL[u] = P.a0 + exp(aL[u]);
+          aU[u] = P.a0 + exp(aU[u]);
         }
       }
 #pragma unroll

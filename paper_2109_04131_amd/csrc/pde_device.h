@@ -8,13 +8,15 @@ namespace usfft {
 // Centroid value of a on the lower (q=0) / upper (q=1) triangle of cell (ci, cj).
 // tab holds sin(m1 pi x1), sin(m2 pi x2) at the centroid abscissae:
 // [0] x1 of lower, [1] x1 of upper, [2] x2 of lower, [3] x2 of upper; each d x n.
+// The lognormal model exponentiates the sum (Sec. 1).
 __device__ __forceinline__ double tri_coef(const PdeDev& P, const double* coef, int q, int ci, int cj) {
   const double* tx = P.tab + (size_t)(q) * P.d * P.n;
   const double* ty = P.tab + (size_t)(2 + q) * P.d * P.n;
-  double a = P.a0;
+  const bool logn = P.model == USFFT_MODEL_LOGNORMAL;
+  double a = logn ? 0.0 : P.a0;
 #pragma unroll 1
   for (int k = 0; k < P.d; ++k) a += coef[k] * tx[k * P.n + ci] * ty[k * P.n + cj];
-  return a;
+  return logn ? P.a0 + exp(a) : a;
 }
 
 // Weight of horizontal edge (i,j)-(i+1,j), 0 <= i <= n-1: lower triangle of
@@ -43,9 +45,23 @@ __device__ void fill_edges(const PdeDev& P, const double* coef, T* eh, T* ev, in
   }
 }
 
+// Per-dimension factor of the coefficient at the sampling node t = Y[s]:
+// amp_k Theta_k(t) with Theta = sin(2 pi t) (periodic), the tent image phi(t)
+// (affine, eq. (3.2)) or sqrt(2) erf^-1(2 tau(t)) with tau the tent shifted
+// by delta (lognormal, eq. (3.3)).
+__device__ __forceinline__ double model_theta(const PdeDev& P, double t) {
+  if (P.model == USFFT_MODEL_AFFINE) return P.beta - fabs((P.beta - P.alpha) * (1.0 - 2.0 * t));
+  if (P.model == USFFT_MODEL_LOGNORMAL) {
+    const double dl = P.delta;
+    const double v = t < dl ? -0.5 - 2.0 * (t - dl) : (t < 0.5 + dl ? -0.5 + 2.0 * (t - dl) : 1.5 - 2.0 * (t - dl));
+    return 1.4142135623730951 * erfinv(2.0 * v);
+  }
+  return sinpi(2.0 * t);
+}
+
 __device__ __forceinline__ void load_coef(const PdeDev& P, const double* __restrict__ Y, int64_t s,
                                           double* coef) {
-  for (int k = threadIdx.x; k < P.d; k += blockDim.x) coef[k] = P.amp[k] * sinpi(2.0 * Y[s * P.d + k]);
+  for (int k = threadIdx.x; k < P.d; k += blockDim.x) coef[k] = P.amp[k] * model_theta(P, Y[s * P.d + k]);
 }
 
 template <typename T>

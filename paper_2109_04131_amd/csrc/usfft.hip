@@ -138,6 +138,8 @@ struct usfft_plan_s {
 struct usfft_result_s {
   int32_t d = 0;
   int64_t G = 0;
+  int32_t model = USFFT_MODEL_PERIODIC;  // evaluation maps y back to the node t
+  double alpha = -1.0, beta = 1.0, delta = 0.0;
   std::vector<int32_t> I;  // n x d
   usfft::DevBuf C;         // n x G x 2 doubles
   usfft_stats stats{};
@@ -539,6 +541,12 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
   // ---------------- step 3
   const int64_t nI = nprev;
   R->d = d;
+  if (pb.sampler == USFFT_SAMPLER_PDE) {
+    R->model = P->pde.model;
+    R->alpha = P->pde.alpha;
+    R->beta = P->pde.beta;
+    R->delta = P->pde.delta;
+  }
   R->G = G;
   R->I.assign((size_t)nI * d, 0);
   R->C.ensure(sizeof(double) * 2 * std::max<int64_t>(nI, 1) * G);
@@ -674,6 +682,14 @@ static void validate(const usfft_problem* pb, const usfft_params* par) {
   if (pb->sampler == USFFT_SAMPLER_PDE) {
     USFFT_REQUIRE(pb->mesh_n >= 4 && pb->mesh_n <= kMaxMeshStream, USFFT_EINVAL, "mesh_n must be in [4, 512]");
     USFFT_REQUIRE(pb->amp && pb->mode1 && pb->mode2, USFFT_EINVAL, "missing coefficient family");
+    USFFT_REQUIRE(pb->model >= USFFT_MODEL_PERIODIC && pb->model <= USFFT_MODEL_LOGNORMAL, USFFT_EINVAL,
+                  "unknown coefficient model");
+    USFFT_REQUIRE(pb->model != USFFT_MODEL_AFFINE || pb->beta > pb->alpha, USFFT_EINVAL,
+                  "affine model needs alpha < beta");
+    USFFT_REQUIRE((pb->basis1 == 0 || pb->basis1 == 1) && (pb->basis2 == 0 || pb->basis2 == 1), USFFT_EINVAL,
+                  "basis must be 0 (sin) or 1 (cos)");
+    USFFT_REQUIRE(pb->model != USFFT_MODEL_LOGNORMAL || pb->delta < 0.5, USFFT_EINVAL,
+                  "lognormal shift must lie in (0, 1/2)");
   } else {
     USFFT_REQUIRE(pb->sampler == USFFT_SAMPLER_TRIG_POLY, USFFT_EINVAL, "unknown sampler");
     USFFT_REQUIRE(pb->G_poly >= 1 && pb->n_poly >= 1 && pb->poly_k && pb->poly_c, USFFT_EINVAL,
@@ -700,16 +716,18 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     P->prob.amp = P->amp.data();
     P->prob.mode1 = P->mode1.data();
     P->prob.mode2 = P->mode2.data();
-    // sin(m pi x) at the centroid abscissae: lower triangle (i+2/3, j+1/3) h,
+    // sin or cos(m pi x) at the centroid abscissae: lower triangle (i+2/3, j+1/3) h,
     // upper triangle (i+1/3, j+2/3) h of cell (i, j)
     std::vector<double> tab((size_t)4 * d * n);
     const double h = 1.0 / n;
+    auto b1 = [&](double v) { return pb->basis1 == 1 ? std::cos(v) : std::sin(v); };
+    auto b2 = [&](double v) { return pb->basis2 == 1 ? std::cos(v) : std::sin(v); };
     for (int k = 0; k < d; ++k)
       for (int c = 0; c < n; ++c) {
-        tab[(size_t)(0 * d + k) * n + c] = std::sin(P->mode1[k] * M_PI * (c + 2.0 / 3.0) * h);
-        tab[(size_t)(1 * d + k) * n + c] = std::sin(P->mode1[k] * M_PI * (c + 1.0 / 3.0) * h);
-        tab[(size_t)(2 * d + k) * n + c] = std::sin(P->mode2[k] * M_PI * (c + 1.0 / 3.0) * h);
-        tab[(size_t)(3 * d + k) * n + c] = std::sin(P->mode2[k] * M_PI * (c + 2.0 / 3.0) * h);
+        tab[(size_t)(0 * d + k) * n + c] = b1(P->mode1[k] * M_PI * (c + 2.0 / 3.0) * h);
+        tab[(size_t)(1 * d + k) * n + c] = b1(P->mode1[k] * M_PI * (c + 1.0 / 3.0) * h);
+        tab[(size_t)(2 * d + k) * n + c] = b2(P->mode2[k] * M_PI * (c + 1.0 / 3.0) * h);
+        tab[(size_t)(3 * d + k) * n + c] = b2(P->mode2[k] * M_PI * (c + 2.0 / 3.0) * h);
       }
     P->d_amp.ensure(sizeof(double) * d);
     P->d_tab.ensure(sizeof(double) * tab.size());
@@ -721,6 +739,12 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     P->pde.h2 = h * h;
     P->pde.amp = P->d_amp.as<double>();
     P->pde.tab = P->d_tab.as<double>();
+    P->pde.model = pb->model;
+    P->pde.alpha = pb->alpha;
+    P->pde.beta = pb->beta;
+    // Lemma 3.1 for the largest admissible lattice: every lattice and line
+    // node (odd sizes <= lattice_mmax) stays at least delta from the poles
+    P->pde.delta = pb->delta > 0 ? pb->delta : 1.0 / (4.0 * par->lattice_mmax);
     if (par->precond == USFFT_PRECOND_DST && dst_padded(n) > 0) {
       // fast-Poisson preconditioned PCG on the matrix cores
       P->dst = true;
@@ -850,7 +874,8 @@ usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n, doub
       I.ensure(sizeof(int32_t) * res->I.size());
       USFFT_HIP(hipMemcpy(I.p, res->I.data(), sizeof(int32_t) * res->I.size(), hipMemcpyHostToDevice));
     }
-    launch_eval(I.as<int32_t>(), nI, res->d, res->C.as<double>(), res->G, y_dev, n, out_dev, (hipStream_t)stream);
+    launch_eval(I.as<int32_t>(), nI, res->d, res->C.as<double>(), res->G, y_dev, n, res->model, res->alpha,
+                res->beta, res->delta, out_dev, (hipStream_t)stream);
     USFFT_HIP(hipStreamSynchronize((hipStream_t)stream));
   });
 }

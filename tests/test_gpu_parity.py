@@ -145,6 +145,64 @@ def test_dst_preconditioner_is_exact_for_constant_coefficient(lib, prec):
         assert np.linalg.norm(host(U)[:, s] - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("precond", [0, 1], ids=["dst", "jacobi"])
+@pytest.mark.parametrize("model,n,prec,tol", [
+    ("affine", 16, 0, 1e-11), ("affine", 64, 0, 1e-11), ("affine", 64, 1, 1e-9),
+    ("lognormal", 16, 0, 1e-11), ("lognormal", 64, 0, 1e-11), ("lognormal", 64, 1, 1e-9)])
+def test_model_solves_match_oracle(lib, model, n, prec, tol, precond):
+    # affine and lognormal coefficients through their periodizations (Sec.
+    # 3.2): the sampler maps the nodes t to the parameters and solves
+    d = 6
+    prob = W.affine_problem(n, d, 4) if model == "affine" else W.lognormal_problem(n, d, 4, delta=0.01)
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, precond=precond,
+                               pcg_rtol=1e-13 if prec == 0 else 1e-12))
+    T = np.random.default_rng(n + prec).random((25, d))
+    T[0] = 0.25 + (0.01 if model == "lognormal" else 0.0)  # parameter y = 0
+    U = torch.zeros((plan.G, 25), dtype=torch.float64, device="cuda")
+    it = torch.zeros(25, dtype=torch.int32, device="cuda")
+    lib.sample(plan, dev(T), U, 0, 25, 0, it)
+    assert (host(it) > 0).all()
+    S = oracle_sampler(prob)
+    for s in range(0, 25, 4):
+        ref = S.solve_one(T[s])
+        err = np.linalg.norm(host(U)[:, s] - ref) / np.linalg.norm(ref)
+        assert err <= tol, (s, err)
+
+
+@pytest.mark.parametrize("model", ["affine", "lognormal"])
+def test_detect_models_cpu_scale(lib, model):
+    # whole job with the periodized affine / lognormal coefficient: the same
+    # sets as the oracle, coefficients to 1e-10 of the largest; evaluation at
+    # parameters y uses the inverse periodization
+    from oracle import periodization as OP
+    n, d, N = 16, 4, 8
+    delta = OP.delta_opt(9601)
+    prob = W.affine_problem(n, d, N) if model == "affine" else W.lognormal_problem(n, d, N)
+    par = W.params(30, 2, 1e-4)
+    res, ref = run_both(lib, prob, par, 5, sampler=oracle_sampler(prob, delta=delta))
+    assert res.freqs().tolist() == ref.I.tolist()
+    C = res.coeffs()
+    assert np.abs(C - ref.C).max() <= 1e-10 * np.abs(ref.C).max()
+    g = np.random.default_rng(9)
+    Yp = g.uniform(-1.0, 1.0, (7, d)) if model == "affine" else g.standard_normal((7, d))
+    out = torch.zeros((7, res.G), dtype=torch.float64, device="cuda")
+    lib.eval(res, dev(Yp), out)
+    mid = OP.to_node(prob["model"], Yp, prob.get("alpha", -1.0), prob.get("beta", 1.0), delta)
+    want = evaluate(ref.I, ref.C, mid)
+    assert np.abs(host(out) - want).max() <= 1e-9 * np.abs(want).max()
+
+
+def test_model_parameters_are_checked(lib):
+    prob = W.affine_problem(16, 4, 8)
+    par = W.params(10, 1, 1e-4)
+    for bad in (dict(model=3), dict(alpha=1.0, beta=1.0), dict(basis1=2)):
+        with pytest.raises(lib.UsfftError) as e:
+            lib.Plan(dict(prob, **bad), par)
+        assert e.value.status == lib.EINVAL
+    with pytest.raises(lib.UsfftError):
+        lib.Plan(W.lognormal_problem(16, 4, 8, delta=0.7), par)
+
+
 def test_trig_poly_sampler(lib):
     K, P = W.trig_poly(4, 5, 8, 70, 31)
     prob = dict(sampler="poly", d=5, k_lo=[-8] * 5, k_hi=[8] * 5, poly_k=K, poly_c=P)
@@ -265,11 +323,20 @@ def test_family_bit_exact(lib, seed, npar, t, nch, kind):
 
 
 # ------------------------------------------------------------------ whole path
+def oracle_sampler(prob, delta=None):
+    """The oracle's sampler for a PDE problem dict, with the same model,
+    basis and lognormal shift as the plan."""
+    return ofem.PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"],
+                           model=prob.get("model", 0), alpha=prob.get("alpha", -1.0), beta=prob.get("beta", 1.0),
+                           delta=delta if delta is not None else prob.get("delta", 0.0),
+                           basis=(prob.get("basis1", 0), prob.get("basis2", 0)))
+
+
 def run_both(lib, prob, par, seed, precision=0, sampler=None, **kw):
     plan = lib.Plan(prob, dict(par, precision=precision, pcg_rtol=1e-13 if precision == 0 else 1e-12, **kw))
     res = lib.detect(plan, seed)
     if sampler is None:
-        sampler = ofem.PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+        sampler = oracle_sampler(prob)
     ref = usfft(sampler, prob["d"], prob["k_lo"], prob["k_hi"], par["s"], par["s_local"], par["r"], par["theta"],
                 par["theta_relative"], seed, keep_values=True)
     return res, ref

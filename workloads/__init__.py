@@ -30,6 +30,33 @@ def pde_problem(n, d, N, modes="split", a0=1.0):
                 a0=a0, amp=amplitudes(d), mode1=m1, mode2=m2)
 
 
+def diagonal_enumeration(j):
+    """(m1(j), m2(j)) of the affine example (Sec. 4.3): k = floor(-1/2 +
+    sqrt(1/4 + 2j)), m1 = j - k(k+1)/2, m2 = k - m1."""
+    k = int(math.floor(-0.5 + math.sqrt(0.25 + 2 * j)))
+    m1 = j - k * (k + 1) // 2
+    return m1, k - m1
+
+
+def affine_problem(n, d, N, c=0.5, mu=2.0, alpha=-1.0, beta=1.0):
+    """Affine model shaped like the paper's affine example: a = 1 + sum_j y_j
+    c j^-mu cos(2 pi m1(j) x1) cos(2 pi m2(j) x2), y uniform on [alpha, beta]^d
+    (tent periodization); f = 1 as in every workload here."""
+    m = [diagonal_enumeration(j) for j in range(1, d + 1)]
+    return dict(sampler="pde", mesh_n=n, d=d, k_lo=[-N] * d, k_hi=[N] * d, a0=1.0,
+                amp=[c * j ** -mu for j in range(1, d + 1)], mode1=[2 * a for a, _ in m],
+                mode2=[2 * b for _, b in m], model=1, alpha=alpha, beta=beta, basis1=1, basis2=1)
+
+
+def lognormal_problem(n, d, N, delta=0.0):
+    """Lognormal model shaped like the paper's lognormal example: a =
+    exp(sum_j (1/j) y_j sin(2 pi j x1) cos(2 pi (d+1-j) x2)), y ~ N(0,1)^d
+    (shifted tent and inverse normal CDF); f = 1 as in every workload here."""
+    return dict(sampler="pde", mesh_n=n, d=d, k_lo=[-N] * d, k_hi=[N] * d, a0=0.0,
+                amp=[1.0 / j for j in range(1, d + 1)], mode1=[2 * j for j in range(1, d + 1)],
+                mode2=[2 * (d + 1 - j) for j in range(1, d + 1)], model=2, delta=delta, basis1=0, basis2=1)
+
+
 def params(s, r, theta, relative=True, **kw):
     p = dict(s=s, s_local=s, r=r, theta=theta, theta_relative=relative,
              lattice_c=2.0, lattice_tries=8, lattice_max=64, lattice_mmax=9601)
