@@ -102,7 +102,7 @@ def measured_traffic():
     except OSError:
         return None
     m = re.search(r"sha1 prefix `([0-9a-f]+)`", text)
-    t = re.search(r"traffic_bytes_per_launch [^:]*: (\d+)", text)
+    t = re.search(r"traffic_bytes_per_launch pcgdst32c_kernel<64>: (\d+)", text)
     if not m or not t or m.group(1) != digest:
         return None
     return float(t.group(1))
@@ -218,8 +218,8 @@ def main():
         "fft_GBps": fft_gbps,
         "pcg_iters_per_solve": iters / max(1, samples),
         "fp32_vs_fp64_samples_per_s": (value / out["fp64_path"]["samples_per_s"]) if out else None,
-        "roofline": {"kernel": "pcgdst_kernel<float,64,true> (DST-preconditioned float32 PCG + float64 "
-                               "reliable updates; preconditioner on fp16 MFMA)",
+        "roofline": {"kernel": "pcgdst32c_kernel<64> (DST-preconditioned float32 PCG + float64 "
+                               "reliable updates, two workgroups per CU; preconditioner on fp16 MFMA)",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f16_mfma"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS["f16_mfma"], "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per launch (rocprof FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",

@@ -121,7 +121,12 @@ typedef struct {
   int32_t refine_every;    /* FP32_REFINE: a float64 true residual at least
                               every this many iterations (200)              */
   int32_t solver_config;   /* Jacobi solver: -1 autotune at plan time, -2
-                              built-in choice, >= 0 force that shape        */
+                              built-in choice, >= 0 force that shape.
+                              DST solver: < 0 default (2 for FP32_REFINE, 1
+                              for FP64); 0 edge grids in global scratch, 1
+                              LDS-resident, 2 compact float32 (float32 edges
+                              in LDS, float64 edges in global scratch for the
+                              true residual; FP32_REFINE only)             */
   int32_t precond;         /* USFFT_PRECOND_DST (fast-Poisson preconditioner,
                               meshes with mesh_n <= 65) or USFFT_PRECOND_JACOBI;
                               larger meshes always use the streaming Jacobi

@@ -127,6 +127,32 @@ __device__ __forceinline__ void block_sum2(T& a, T& b, T* red) {
   b = sb;
 }
 
+template <int BLOCK, typename T>
+__device__ __forceinline__ void block_sum3(T& a, T& b, T& c, T* red) {
+  constexpr int NW = BLOCK / kWave;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  if (lane == 0) {
+    red[3 * w] = a;
+    red[3 * w + 1] = b;
+    red[3 * w + 2] = c;
+  }
+  __syncthreads();
+  T sa = red[0], sb = red[1], sc = red[2];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) {
+    sa += red[3 * i];
+    sb += red[3 * i + 1];
+    sc += red[3 * i + 2];
+  }
+  a = sa;
+  b = sb;
+  c = sc;
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
 // Remap so that each XCD works on one contiguous range of work items: writes
 // of neighbouring items then meet in the same L2.

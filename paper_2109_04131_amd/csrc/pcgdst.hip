@@ -207,11 +207,14 @@ constexpr int dst_waves() {
 // scratch holds three per workgroup: eh, ev and D^-1/2.
 int64_t dst_edge_stride(int mp) { return ((int64_t)dst_pitch(mp) * dst_pitch(mp) + 31) / 32 * 32; }
 
-// Dynamic LDS bytes of one workgroup: [u (float32 solves), float64][p, T]
-// [exchange tiles][LDS-resident variant: eh, ev float64, D^-1/2 in T].
+// Dynamic LDS bytes of one workgroup.  Variants 0 and 1: [u (float32
+// solves), float64][p, T][exchange tiles][variant 1: eh, ev float64,
+// D^-1/2 in T].  Variant 2 (float32 only): [overlay, GE doubles][D^-1/2,
+// float32].
 int64_t dst_lds_bytes(int n, int precision, int variant) {
   const int mp = dst_padded(n);
   const int64_t g = dst_grid_elems(mp);
+  if (variant == 2) return g * 8 + g * 4;
   const int64_t grids = precision == USFFT_FP64 ? g * 8 : g * 8 + g * 4;
   return grids + 2 * (int64_t)mp * (mp + 4) * 2 + (variant == 1 ? g * (8 + 8 + (precision == USFFT_FP64 ? 8 : 4)) : 0);
 }
@@ -239,9 +242,26 @@ __device__ __forceinline__ double wave_shr1(double v) {
 // coefficients come from the neighbouring lane; columns are covered in
 // chunks of 64 lanes overlapping by one (lane 0 of a later chunk only
 // supplies its neighbour's values).
-template <int NWAVE, int CB, typename DT>
-__device__ void assemble(const PdeDev& P, const double* coef, double* __restrict__ eh, double* __restrict__ ev,
-                         DT* __restrict__ dg, int PP, int tid) {
+// Where the assembly puts the edge weights: float64 grids (LDS or global
+// scratch), or float32 LDS grids for the float32 iteration plus float64
+// copies in global scratch for the float64 true residual.
+struct EdgesF64 {
+  double* __restrict__ eh;
+  double* __restrict__ ev;
+  __device__ __forceinline__ void h(int i, double x) const { eh[i] = x; }
+  __device__ __forceinline__ void v(int i, double x) const { ev[i] = x; }
+};
+struct EdgesSplit {
+  float* __restrict__ eh;
+  float* __restrict__ ev;
+  double* __restrict__ geh;
+  double* __restrict__ gev;
+  __device__ __forceinline__ void h(int i, double x) const { eh[i] = (float)x; geh[i] = x; }
+  __device__ __forceinline__ void v(int i, double x) const { ev[i] = (float)x; gev[i] = x; }
+};
+
+template <int NWAVE, int CB, typename DT, typename EW>
+__device__ void assemble(const PdeDev& P, const double* coef, const EW& ew, DT* __restrict__ dg, int PP, int tid) {
   const int n = P.n, d = P.d, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double* txL = P.tab;                  // x1 factor, lower triangles
   const double* txU = P.tab + (size_t)d * n;  // x1 factor, upper triangles
@@ -295,8 +315,8 @@ __device__ void assemble(const PdeDev& P, const double* coef, double* __restrict
         if (cj >= n || !outp) continue;
         const double ehc = 0.5 * (aL[u] + aU[u - 1]);  // eh(ci, cj)
         const double evc = 0.5 * (aU[u] + aLm);        // ev(ci, cj)
-        if (cj >= 1) eh[cj * PP + ci] = ehc;
-        if (ci >= 1) ev[cj * PP + ci] = evc;
+        if (cj >= 1) ew.h(cj * PP + ci, ehc);
+        if (ci >= 1) ew.v(cj * PP + ci, evc);
         if (ci >= 1 && cj >= 1) {
           const double ehm = 0.5 * (aLm + aUm1);        // eh(ci-1, cj)
           const double evm = 0.5 * (aU[u - 1] + aLm1);  // ev(ci, cj-1)
@@ -368,7 +388,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
     __syncthreads();  // the previous sample is done with LDS, coef and the edge grids
     load_coef(P, Y, s, coef);
     __syncthreads();
-    assemble<BLOCK / 64, LR ? 16 : 8>(P, coef, eh, ev, dg, PP, tid);
+    assemble<BLOCK / 64, LR ? 16 : 8>(P, coef, EdgesF64{eh, ev}, dg, PP, tid);
     __syncthreads();
     // scaled weights: wE, wW, wS per node; wN(v) = wS(v + 1) inside a 4-row
     // group, so only the top row of each group keeps its own (wN4)
@@ -530,26 +550,230 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
   }
 }
 
-template <typename T, int MP, bool LR>
-static int dst_occupancy(int n) {
+// Float32 solves in a compact LDS footprint, so that two workgroups (MP = 64)
+// share a CU and hide each other's barrier and LDS latency.  LDS holds one
+// overlay region of GE doubles and the float32 Jacobi scaling:
+//   assembly:     float32 edge grids eh, ev (the float64 edges go to this
+//                 workgroup's slot of the global scratch),
+//   iterations:   float32 search direction (zero halo) + exchange tiles,
+//   true residual: float64 u = D^-1/2 ut (zero halo).
+// The float64 scaled iterate ut stays in registers and takes alpha p every
+// iteration.  The float32 recursive residual r - alpha q has its norm from
+// one block reduction of (p.q, r.q, q.q) before the preconditioner:
+// |r - alpha q|^2 = |r|^2 - 2 alpha r.q + alpha^2 q.q.  When it has dropped
+// by inner_rtol (or after refine_every iterations) the float64 true residual
+// b - A u, formed from the float64 edges, replaces it before the
+// preconditioner runs, so no preconditioner application is spent on a
+// residual that is thrown away.  Convergence is decided on the float64 true
+// residual only.
+template <int MP>
+__global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64 ? 2 : 4))) void pcgdst32c_kernel(
+    PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, double inner_rtol, int refine_every,
+    void* __restrict__ out, int out_fp32, int64_t ld, int64_t col0, int* __restrict__ iters,
+    double* __restrict__ wscr, int64_t wstride, const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
+  constexpr int NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
+  constexpr int PP = dst_pitch(MP);
+  constexpr int64_t GE = dst_grid_elems(MP);
+  static_assert(GE * 4 + 2 * MP * LDX * 2 <= GE * 8, "exchange tiles must fit the overlay");
+  extern __shared__ double lds[];
+  __shared__ double coef[kMaxD];
+  __shared__ double red0[3 * (BLOCK / kWave)];
+  __shared__ double red1[2 * (BLOCK / kWave)];
+  __shared__ __attribute__((aligned(16))) float slam[MP];
+  const int n = P.n, m = n - 1;
+  double* su = lds;                                        // overlay: float64 u
+  float* sp = reinterpret_cast<float*>(lds);               // overlay: search direction
+  _Float16* xa = reinterpret_cast<_Float16*>(sp + GE);     // overlay: exchange tiles
+  _Float16* xb = xa + MP * LDX;
+  float* feh = sp;                                         // overlay: float32 edges
+  float* fev = sp + GE;
+  float* dg = reinterpret_cast<float*>(lds + GE);          // D^-1/2
+  double* geh = wscr + (size_t)blockIdx.x * 2 * wstride;   // float64 edges
+  double* gev = geh + wstride;
+
+  const int lane = threadIdx.x & 63;
+  half8 sf[KB * NT];
+#pragma unroll
+  for (int f = 0; f < KB * NT; ++f) sf[f] = sfrag[f * 64 + lane];
+  for (int i = threadIdx.x; i < MP; i += BLOCK) slam[i] = lamtab[i];
+  for (int64_t e = threadIdx.x; e < GE; e += BLOCK) dg[e] = 0.0f;  // zero halo: boundary couplings vanish
+  // zero ring (rows and columns 0 and PP-1) of a grid of pitch PP
+  auto zero_ring = [&](auto* g) {
+    const int t = threadIdx.x;
+    if (t < PP) {
+      g[t] = 0;
+      g[(PP - 1) * PP + t] = 0;
+      g[t * PP] = 0;
+      g[t * PP + PP - 1] = 0;
+    }
+  };
+
+  for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int q = (tid & 63) >> 4, c = 16 * (tid >> 6) + (tid & 15);
+    const int base = (4 * q + 1) * PP + c + 1;
+    auto off = [](int e) { return (16 * (e >> 2) + (e & 3)) * PP; };
+    __syncthreads();  // the previous sample is done with LDS and coef
+    load_coef(P, Y, s, coef);
+    __syncthreads();
+    assemble<BLOCK / 64, MP / 4>(P, coef, EdgesSplit{feh, fev, geh, gev}, dg, PP, tid);
+    __syncthreads();
+    float wE[E], wW[E], wS[E], wN4[NT], r[E], p[E];
+    double ux[E];
+    double bb = 0.0;
+    {
+      const float* sdl = dg + base;
+      const float* ehl = feh + base;
+      const float* evl = fev + base;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int t = e >> 2, v = e & 3, row = 16 * t + 4 * q + v, o = off(e);
+        const bool ok = row < m && c < m;
+        const float di = sdl[o];
+        ux[e] = 0.0;
+        wE[e] = ok ? ehl[o] * di * sdl[o + 1] : 0.0f;
+        wW[e] = ok ? ehl[o - 1] * di * sdl[o - 1] : 0.0f;
+        wS[e] = ok ? evl[o - PP] * di * sdl[o - PP] : 0.0f;
+        if (v == 3) wN4[t] = ok ? evl[o] * di * sdl[o + PP] : 0.0f;
+        const double bt = ok ? (double)di * P.h2 : 0.0;
+        r[e] = (float)bt;
+        bb += bt * bt;
+      }
+    }
+    bb = block_sum<BLOCK>(bb, red0);  // every lane is done with the edge grids
+    zero_ring(sp);
+    float z[E];
+    dst_apply<MP, float>(r, pow2_scale(bb), z, sf, xa, xb, slam);
+    double rz = 0.0, rr = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      p[e] = z[e];
+      rz += (double)r[e] * (double)z[e];
+      rr += (double)r[e] * (double)r[e];
+    }
+    block_sum2<BLOCK>(rz, rr, red1);
+    const double stop = rtol * rtol * bb;
+    const double drop = inner_rtol * inner_rtol;
+    double rr_ref = rr;
+    int it = 0, last_update = 0;
+    bool conv = !(bb > 0.0);
+    while (!conv && it < maxit) {
+      float* spl = sp + base;
+#pragma unroll
+      for (int e = 0; e < E; ++e) spl[off(e)] = p[e];
+      __syncthreads();
+      float qv[E];
+      double pq = 0.0, rq = 0.0, qq = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int o = off(e);
+        const float wn = (e & 3) == 3 ? wN4[e >> 2] : wS[e + 1];
+        qv[e] = 4.0f * p[e] - (wE[e] * spl[o + 1] + wW[e] * spl[o - 1] + wn * spl[o + PP] + wS[e] * spl[o - PP]);
+        pq += (double)(p[e] * qv[e]);
+        rq += (double)r[e] * (double)qv[e];
+        qq += (double)qv[e] * (double)qv[e];
+      }
+      block_sum3<BLOCK>(pq, rq, qq, red0);
+      const double alpha = rz / pq;
+      const float af = (float)alpha;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        ux[e] += alpha * (double)p[e];
+        r[e] -= af * qv[e];
+      }
+      rr = fmax(rr - 2.0 * alpha * rq + alpha * alpha * qq, 0.0);
+      ++it;
+      if (rr <= drop * rr_ref || it - last_update >= refine_every) {
+        // float64 true residual of u = D^-1/2 ut; every lane is past the
+        // stencil reads of sp (block_sum3) and the exchange tiles
+        int b2 = base;
+        asm volatile("" : "+v"(b2));
+        double* sul = su + b2;
+        const float* dgl = dg + b2;
+        zero_ring(su);
+#pragma unroll
+        for (int e = 0; e < E; ++e) sul[off(e)] = (double)dgl[off(e)] * ux[e];  // padding: ux = 0
+        __syncthreads();
+        const double* ehl = geh + b2;
+        const double* evl = gev + b2;
+        double rr64 = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int o = off(e);
+          const bool ok = 16 * (e >> 2) + 4 * q + (e & 3) < m && c < m;
+          const double xc = sul[o];
+          const double ax = ehl[o] * (xc - sul[o + 1]) + ehl[o - 1] * (xc - sul[o - 1]) +
+                            evl[o] * (xc - sul[o + PP]) + evl[o - PP] * (xc - sul[o - PP]);
+          const double rsv = (double)dgl[o] * (P.h2 - ax);
+          const double rs = ok ? rsv : 0.0;
+          rr64 += rs * rs;
+          r[e] = (float)rs;
+        }
+        rr64 = block_sum<BLOCK>(rr64, red1);  // every lane is done with su
+        last_update = it;
+        if (rr64 <= stop) {
+          conv = true;
+          break;
+        }
+        zero_ring(sp);
+        rr = rr_ref = rr64;
+      }
+      dst_apply<MP, float>(r, pow2_scale(rr), z, sf, xa, xb, slam);
+      double rz2 = 0.0, rre = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        rz2 += (double)r[e] * (double)z[e];
+        rre += (double)r[e] * (double)r[e];
+      }
+      block_sum2<BLOCK>(rz2, rre, red1);
+      rr = rre;
+      const float beta = (float)(rz2 / rz);
+      rz = rz2;
+#pragma unroll
+      for (int e = 0; e < E; ++e) p[e] = z[e] + beta * p[e];
+    }
+    {
+      const float* dgl = dg + base;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int row = 16 * (e >> 2) + 4 * q + (e & 3);
+        const double u = (double)dgl[off(e)] * ux[e];
+        if (row < m && c < m) store_sample(out, out_fp32, ((int64_t)row * m + c) * ld + col0 + s, u);
+      }
+    }
+    if (tid == 0 && iters) iters[s] = conv ? it : -1;
+  }
+}
+
+static int dst_occupancy_of(const void* kernel, int mp, int64_t lds) {
   int per_cu = 0;
-  USFFT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reinterpret_cast<const void*>(pcgdst_kernel<T, MP, LR>), 4 * MP,
-      dst_lds_bytes(n, std::is_same<T, float>::value ? USFFT_FP32_REFINE : USFFT_FP64, LR ? 1 : 0)));
+  USFFT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 4 * mp, (size_t)lds));
   return std::max(1, per_cu);
 }
 
+template <typename T, int MP, bool LR>
+static int dst_occupancy(int n) {
+  return dst_occupancy_of(reinterpret_cast<const void*>(pcgdst_kernel<T, MP, LR>), MP,
+                          dst_lds_bytes(n, std::is_same<T, float>::value ? USFFT_FP32_REFINE : USFFT_FP64, LR ? 1 : 0));
+}
+
 int dst_persistent_blocks(int n, int precision, int variant) {
-  static int cache[2][2][2] = {};  // [float32?][mp == 64?][LDS-resident?]
+  static int cache[2][2][3] = {};  // [float32?][mp == 64?][variant]
   const int mp = dst_padded(n);
-  const int a = precision == USFFT_FP64 ? 0 : 1, b = mp == 64 ? 1 : 0, c = variant == 1 ? 1 : 0;
+  const int a = precision == USFFT_FP64 ? 0 : 1, b = mp == 64 ? 1 : 0, c = variant;
+  USFFT_REQUIRE(c >= 0 && c <= 2 && !(c == 2 && a == 0), USFFT_EINVAL, "bad DST solver variant");
   if (cache[a][b][c] == 0) {
     int cus = 0, dev = 0;
     USFFT_HIP(hipGetDevice(&dev));
     USFFT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = 1;
 #define USFFT_OCC(TT, MM, LL) per_cu = dst_occupancy<TT, MM, LL>(n)
-    if (a == 0) {
+    if (c == 2) {
+      const int64_t lds = dst_lds_bytes(n, precision, 2);
+      per_cu = b ? dst_occupancy_of(reinterpret_cast<const void*>(pcgdst32c_kernel<64>), 64, lds)
+                 : dst_occupancy_of(reinterpret_cast<const void*>(pcgdst32c_kernel<32>), 32, lds);
+    } else if (a == 0) {
       if (b) { if (c) USFFT_OCC(double, 64, true); else USFFT_OCC(double, 64, false); }
       else { if (c) USFFT_OCC(double, 32, true); else USFFT_OCC(double, 32, false); }
     } else {
@@ -563,7 +787,7 @@ int dst_persistent_blocks(int n, int precision, int variant) {
 }
 
 int64_t dst_scratch_doubles(int n, int variant, int blocks) {
-  return variant == 1 ? 0 : 3 * dst_edge_stride(dst_padded(n)) * (int64_t)blocks;
+  return variant == 1 ? 0 : (variant == 2 ? 2 : 3) * dst_edge_stride(dst_padded(n)) * (int64_t)blocks;
 }
 
 void launch_pde_solve_dst(const PdeDev& P, int precision, int variant, const double* Y, int64_t ns, double rtol,
@@ -573,7 +797,8 @@ void launch_pde_solve_dst(const PdeDev& P, int precision, int variant, const dou
   if (ns <= 0) return;
   const int mp = dst_padded(P.n);
   USFFT_REQUIRE(mp > 0, USFFT_EINVAL, "mesh too large for the DST-preconditioned solver");
-  USFFT_REQUIRE(variant == 0 || variant == 1, USFFT_EINVAL, "bad DST solver variant");
+  USFFT_REQUIRE(variant == 0 || variant == 1 || (variant == 2 && precision != USFFT_FP64), USFFT_EINVAL,
+                "bad DST solver variant");
   const int64_t ws = dst_edge_stride(mp);
   const unsigned grid = (unsigned)std::min<int64_t>(ns, wblocks);
   const size_t lds = (size_t)dst_lds_bytes(P.n, precision, variant);
@@ -581,7 +806,14 @@ void launch_pde_solve_dst(const PdeDev& P, int precision, int variant, const dou
 #define USFFT_DST(TT, MM, LL)                                                                                  \
   hipLaunchKernelGGL((pcgdst_kernel<TT, MM, LL>), dim3(grid), dim3(4 * MM), lds, st, P, Y, ns, rtol, maxit,     \
                      inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam)
-  if (precision == USFFT_FP64) {
+  if (variant == 2) {
+    if (mp == 64)
+      hipLaunchKernelGGL(pcgdst32c_kernel<64>, dim3(grid), dim3(256), lds, st, P, Y, ns, rtol, maxit, inner_rtol,
+                         refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+    else
+      hipLaunchKernelGGL(pcgdst32c_kernel<32>, dim3(grid), dim3(128), lds, st, P, Y, ns, rtol, maxit, inner_rtol,
+                         refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+  } else if (precision == USFFT_FP64) {
     if (mp == 64) { if (variant) USFFT_DST(double, 64, true); else USFFT_DST(double, 64, false); }
     else { if (variant) USFFT_DST(double, 32, true); else USFFT_DST(double, 32, false); }
   } else {

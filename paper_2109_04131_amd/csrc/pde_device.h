@@ -48,8 +48,10 @@ __device__ void fill_edges(const PdeDev& P, const double* coef, T* eh, T* ev, in
 // Per-dimension factor of the coefficient at the sampling node t = Y[s]:
 // amp_k Theta_k(t) with Theta = sin(2 pi t) (periodic), the tent image phi(t)
 // (affine, eq. (3.2)) or sqrt(2) erf^-1(2 tau(t)) with tau the tent shifted
-// by delta (lognormal, eq. (3.3)).
-__device__ __forceinline__ double model_theta(const PdeDev& P, double t) {
+// by delta (lognormal, eq. (3.3)).  Not inlined: a few lanes evaluate it once
+// per sample, and inlined into a solver its polynomial constants are hoisted
+// out of the sample loop and spilled.
+__device__ __noinline__ double model_theta(const PdeDev& P, double t) {
   if (P.model == USFFT_MODEL_AFFINE) return P.beta - fabs((P.beta - P.alpha) * (1.0 - 2.0 * t));
   if (P.model == USFFT_MODEL_LOGNORMAL) {
     const double dl = P.delta;

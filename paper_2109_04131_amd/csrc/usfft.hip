@@ -120,7 +120,7 @@ struct usfft_plan_s {
   int wblocks = 0;  // persistent workgroups of the float32 / DST solver
   bool streaming = false;  // mesh larger than the on-chip solvers hold
   bool dst = false;        // DST-preconditioned solver
-  int dst_variant = 1;     // 0: scratch in global memory, 1: LDS-resident
+  int dst_variant = 1;     // 0: scratch in global memory, 1: LDS-resident, 2: compact float32
   usfft::PdeDev pde{};
   // Rader tables per lattice size
   std::map<int, usfft::RaderTables> rader;
@@ -754,12 +754,15 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
       P->d_lam.ensure(sizeof(float) * mp);
       dst_tables_build(n, P->d_sfrag.p, P->d_lam.as<float>(), nullptr);
       USFFT_HIP(hipStreamSynchronize(nullptr));
-      // solver_config 0 / 1 forces the scratch placement (global scratch with
-      // more resident workgroups / LDS-resident, one workgroup per CU); the
-      // LDS-resident one is the default (the faster one at h = 1/64 in both
-      // precisions)
-      USFFT_REQUIRE(par->solver_config <= 1, USFFT_EINVAL, "solver_config of the DST solver must be <= 1");
-      P->dst_variant = par->solver_config >= 0 ? par->solver_config : 1;
+      // solver_config 0 / 1 / 2 forces the scratch placement: 0 global
+      // scratch, 1 LDS-resident (one workgroup per CU), 2 compact float32
+      // (float32 edges in LDS, float64 edges in global scratch, two
+      // workgroups per CU at h = 1/64).  Defaults: 2 for float32 solves, 1
+      // for float64 solves.
+      USFFT_REQUIRE(par->solver_config <= 2, USFFT_EINVAL, "solver_config of the DST solver must be <= 2");
+      USFFT_REQUIRE(!(par->solver_config == 2 && par->precision == USFFT_FP64), USFFT_EINVAL,
+                    "solver_config 2 of the DST solver is float32-only");
+      P->dst_variant = par->solver_config >= 0 ? par->solver_config : (par->precision == USFFT_FP64 ? 1 : 2);
       P->wblocks = dst_persistent_blocks(n, par->precision, P->dst_variant);
       P->d_wscr.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, dst_scratch_doubles(n, P->dst_variant,
                                                                                          P->wblocks)));

@@ -51,7 +51,8 @@ def test_nodes_line_and_lattice_bit_exact(lib):
 
 
 # ------------------------------------------------------------------ sampler
-@pytest.mark.parametrize("precond,cfg", [(0, -2), (0, 0), (1, -2)], ids=["dst", "dst_global_scratch", "jacobi"])
+@pytest.mark.parametrize("precond,cfg", [(0, -2), (0, 0), (0, 1), (1, -2)],
+                         ids=["dst", "dst_global_scratch", "dst_lds_resident", "jacobi"])
 @pytest.mark.parametrize("n,d,modes,prec,tol", [
     (4, 2, "diagonal", 0, 1e-11), (8, 3, "diagonal", 0, 1e-11), (16, 4, "diagonal", 0, 1e-11),
     (33, 6, "split", 0, 1e-11), (34, 6, "split", 0, 1e-11), (64, 10, "split", 0, 1e-11),
@@ -103,15 +104,21 @@ def test_solver_shapes_agree_and_batch_independent(lib):
         assert np.abs(o - outs[0]).max() <= 1e-12 * np.abs(outs[0]).max()
 
 
-@pytest.mark.parametrize("variant", [0, 1], ids=["global_scratch", "lds_resident"])
+@pytest.mark.parametrize("variant", [0, 1, 2], ids=["global_scratch", "lds_resident", "compact_fp32"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_dst_solver_batch_independent_and_fast(lib, prec, variant):
     # a sample's DST-PCG solution does not depend on the batch or workgroup
     # that solves it (bitwise), the fast-Poisson preconditioner keeps the
-    # iteration count of the h = 1/64, d = 10 workload small, and both
-    # scratch placements agree with the direct solve
+    # iteration count of the h = 1/64, d = 10 workload small, and every
+    # scratch placement agrees with the direct solve (the compact one is
+    # float32-only)
     prob, _ = W.WORKLOADS["mesh64_d10"]
-    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-12, solver_config=variant))
+    par = dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-12, solver_config=variant)
+    if variant == 2 and prec == 0:
+        with pytest.raises(lib.UsfftError):
+            lib.Plan(prob, par)
+        return
+    plan = lib.Plan(prob, par)
     Y = np.random.default_rng(11).random((300, prob["d"]))
     U = torch.zeros((plan.G, 300), dtype=torch.float64, device="cuda")
     it = torch.zeros(300, dtype=torch.int32, device="cuda")
