@@ -51,10 +51,12 @@ __device__ void fill_edges(const PdeDev& P, const double* coef, T* eh, T* ev, in
 // by delta (lognormal, eq. (3.3)).  Not inlined: a few lanes evaluate it once
 // per sample, and inlined into a solver its polynomial constants are hoisted
 // out of the sample loop and spilled.
-__device__ __noinline__ double model_theta(const PdeDev& P, double t) {
-  if (P.model == USFFT_MODEL_AFFINE) return P.beta - fabs((P.beta - P.alpha) * (1.0 - 2.0 * t));
-  if (P.model == USFFT_MODEL_LOGNORMAL) {
-    const double dl = P.delta;
+// Its arguments are scalars: a reference to the kernel's problem structure
+// would make the callers keep a private copy of it.
+__device__ __noinline__ double model_theta(int model, double alpha, double beta, double delta, double t) {
+  if (model == USFFT_MODEL_AFFINE) return beta - fabs((beta - alpha) * (1.0 - 2.0 * t));
+  if (model == USFFT_MODEL_LOGNORMAL) {
+    const double dl = delta;
     const double v = t < dl ? -0.5 - 2.0 * (t - dl) : (t < 0.5 + dl ? -0.5 + 2.0 * (t - dl) : 1.5 - 2.0 * (t - dl));
     return 1.4142135623730951 * erfinv(2.0 * v);
   }
@@ -63,7 +65,7 @@ __device__ __noinline__ double model_theta(const PdeDev& P, double t) {
 
 __device__ __forceinline__ void load_coef(const PdeDev& P, const double* __restrict__ Y, int64_t s,
                                           double* coef) {
-  for (int k = threadIdx.x; k < P.d; k += blockDim.x) coef[k] = P.amp[k] * model_theta(P, Y[s * P.d + k]);
+  for (int k = threadIdx.x; k < P.d; k += blockDim.x) coef[k] = P.amp[k] * model_theta(P.model, P.alpha, P.beta, P.delta, Y[s * P.d + k]);
 }
 
 template <typename T>
