@@ -92,7 +92,7 @@ def measured_traffic():
     import hashlib
     import re
     srcs = [os.path.join(ROOT, "paper_2109_04131_amd", "csrc", f) for f in ("pcgdst.hip", "pde_device.h")]
-    prof = os.path.join(ROOT, "profiles", "pcgdst_mesh64_d10_hbm_counters.md")
+    prof = os.path.join(ROOT, "profiles", "pcgdst32c_mesh64_d10_hbm_counters.md")
     try:
         text = open(prof).read()
         h = hashlib.sha1()
