@@ -17,6 +17,9 @@ Modules
   dft      naive DFTs (1-D detection, lattice bins)
   select   per-node selection, uniform OR over nodes, set join
   usfft    Alg. 1 driver, trigonometric-polynomial sampler, evaluation
+  periodization  tent and lognormal maps of the affine / lognormal models
+  evaluation     error measures, variance, sensitivity indices and
+                 expectation of the approximation (Sec. 4, 4.1)
 
 Every function states the passage it follows.  Parity status of each part is
 listed in the module headers; "parity unpinned" marks parts whose only check
