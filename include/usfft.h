@@ -186,9 +186,40 @@ void usfft_result_destroy(usfft_result_t res);
  * periodization of Sec. 3.2, see USFFT_MODEL_*):
  * out_dev[j*G + g] = Re sum_{k in I} c_k(u_{x_g}) exp(2 pi i k.phi^{-1}(y_j)),
  * y_dev: n x d doubles, parameters of the model (periodic: nodes in [0,1)).
- * Not part of the timed hot path. */
+ * Computed as a float64 matrix product on the matrix cores in chunks of
+ * points; temporary device memory of at most ~256 MB per call.  Returns after
+ * the stream has finished.  Errors: EINVAL, ENOMEM, EHIP. */
 usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n,
                         double* out_dev, void* stream);
+
+/* Statistics of the approximation per node (Sec. 4, Sec. 4.1), from the
+ * result's coefficients alone.  Device outputs, each may be NULL:
+ *   mean_dev[2g], [2g+1]  Re, Im of E(u_usFFT(x_g, .)) = sum_k c_k D_k, with
+ *                         D_k = [k = 0] (periodic), prod_j D_{k_j},
+ *                         D_{k_j} = 2i/(pi k_j) for odd k_j, 1 for k_j = 0,
+ *                         0 otherwise (affine), times e^{2 pi i k_j delta}
+ *                         (lognormal, delta of the problem);
+ *   var_dev[g]            variance sum_{k != 0} |c_k|^2;
+ *   gsi_dev[(l-1)*G + g]  global sensitivity index of J_l = {k : exactly l
+ *                         nonzero components}, l = 1..d (0 where the
+ *                         variance is 0).
+ * Returns after the stream has finished.  Errors: EINVAL, EHIP. */
+usfft_status usfft_statistics(usfft_result_t res, double* mean_dev, double* var_dev,
+                              double* gsi_dev, void* stream);
+
+/* Error measures of Sec. 4 over n test parameters y_dev (n x d doubles in
+ * the model's parameter domain, drawn by the caller from its distribution):
+ * finite-element solves of plan's problem at each y (float64 results; the
+ * plan's solver and precision), the approximation at the same y, and per node
+ *   errp_dev[g]   = ( (1/n) sum_j |u_FE(x_g, y_j) - u_usFFT(x_g, y_j)|^p )^(1/p),
+ *   errinf_dev[g] = max_j |u_FE(x_g, y_j) - u_usFFT(x_g, y_j)|.
+ * res must come from a plan of the same problem (same d and G).  p >= 1.
+ * Works in chunks of points (temporary device memory up to ~1.3 GB).
+ * Returns after the stream has finished.  Errors: EINVAL, ENOMEM, ENOCONV
+ * (a test solve missed pcg_rtol), EHIP. */
+usfft_status usfft_errors(usfft_plan_t plan, usfft_result_t res, const double* y_dev,
+                          int64_t n, double p, double* errp_dev, double* errinf_dev,
+                          void* stream);
 
 /* ---- Stage entry points: each step of the hot path as its own call ---- */
 

@@ -172,6 +172,12 @@ class PDESampler:
         a = coefficient_on_triangles(self.mesh, self.a0, self.amp, self.mode1, self.mode2, y, self.model, self.basis)
         return solve_banded(banded_stiffness(self.mesh, a), self.mesh.load)
 
+    def solve_param(self, y):
+        """One solve at the parameter y itself (the test solves of Sec. 4)."""
+        a = coefficient_on_triangles(self.mesh, self.a0, self.amp, self.mode1, self.mode2,
+                                     np.asarray(y, dtype=np.float64), self.model, self.basis)
+        return solve_banded(banded_stiffness(self.mesh, a), self.mesh.load)
+
     def __call__(self, Y):
         Y = np.atleast_2d(np.asarray(Y, dtype=np.float64))
         out = np.empty((len(Y), self.G))

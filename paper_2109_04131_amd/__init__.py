@@ -73,6 +73,8 @@ _sigs = {
     "usfft_result_copy": (C.c_int, [_vp, _vp, _vp]),
     "usfft_result_destroy": (None, [_vp]),
     "usfft_eval": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
+    "usfft_statistics": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "usfft_errors": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp]),
     "usfft_sample": (C.c_int, [_vp, _vp, C.c_int64, _vp, C.c_int32, C.c_int64, C.c_int64, _vp, _vp]),
     "usfft_nodes": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
     "usfft_line_dft": (C.c_int, [_vp, C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_int32, _vp, C.c_int32,
@@ -289,6 +291,17 @@ def detect(plan, seed, stream=None):
 
 def eval(result, y, out, stream=None):
     _check(_lib.usfft_eval(result.handle, _ptr(y), y.shape[0], _ptr(out), _stream(stream)))
+
+
+def statistics(result, mean=None, var=None, gsi=None, stream=None):
+    """usfft_statistics: mean (G x 2 float64), var (G), gsi (d x G); any may be None."""
+    _check(_lib.usfft_statistics(result.handle, _ptr(mean), _ptr(var), _ptr(gsi), _stream(stream)))
+
+
+def errors(plan, result, y, p, errp, errinf, stream=None):
+    """usfft_errors: err_p and err_inf per node over the test parameters y (n x d)."""
+    _check(_lib.usfft_errors(plan.handle, result.handle, _ptr(y), y.shape[0], float(p), _ptr(errp), _ptr(errinf),
+                             _stream(stream)))
 
 
 def sample(plan, y, u, out_fp32, ld, col0=0, iters=None, stream=None):

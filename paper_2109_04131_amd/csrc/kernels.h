@@ -18,6 +18,7 @@ struct PdeDev {
   const double* tab;  // 4 x d x n centroid basis tables (sin or cos per axis)
   int model;          // USFFT_MODEL_*
   double alpha, beta, delta;
+  int raw = 0;        // 1: the solver inputs are parameters y, not sampling nodes t
 };
 
 // ---- sampler.hip
@@ -100,8 +101,24 @@ void launch_lattice_take(const int32_t* bins, const int32_t* counts, uint8_t* co
                          int32_t* assign, int32_t* bin_out, hipStream_t st);
 
 // ---- eval.hip
-// Y holds parameters of the model; they are mapped back to nodes of T^d.
-void launch_eval(const int32_t* I, int64_t nI, int d, const double* C, int64_t G, const double* Y, int64_t n,
-                 int model, double alpha, double beta, double delta, double* out, hipStream_t st);
+// Y (n x d) holds parameters of the model; T[q * ldt + j] gets phi^{-1}(Y[j]).
+void launch_node_map(const double* Y, int64_t n, int d, int model, double alpha, double beta, double delta,
+                     double* T, int64_t ldt, hipStream_t st);
+// B (2 nI x ldb): cos / -sin rows of 2 pi k_a . t_j
+void launch_phases(const int32_t* I, int64_t nI, int d, const double* T, int64_t ldt, int64_t n, double* B,
+                   int64_t ldb, hipStream_t st);
+// out[j * ldo + g] = Re sum_a c_{a,g} e^{2 pi i k_a . t_j}
+void launch_evgemm_values(const double* C, int64_t G, int64_t nI, const double* B, int64_t ldb, int64_t n,
+                          double* out, int64_t ldo, hipStream_t st);
+int64_t evgemm_tiles_j(int64_t n);
+// error partials against U (G x ldu) and their accumulation into acc_s / acc_m
+// (psum / pmax: evgemm_tiles_j(n) x G each)
+void launch_evgemm_errors(const double* C, int64_t G, int64_t nI, const double* B, int64_t ldb, int64_t n,
+                          const double* U, int64_t ldu, double p, double* psum, double* pmax, int first,
+                          double* acc_s, double* acc_m, hipStream_t st);
+void launch_err_final(double* errp, int64_t G, int64_t n, double p, hipStream_t st);
+// D (2 nI) and ord (nI) are scratch; mean (2 G), var (G), gsi (d x G) may be null
+void launch_stats(const int32_t* I, int64_t nI, int d, const double* C, int64_t G, int model, double delta,
+                  double* D, int32_t* ord, double* mean, double* var, double* gsi, hipStream_t st);
 
 }  // namespace usfft

@@ -51,9 +51,12 @@ __device__ void fill_edges(const PdeDev& P, const double* coef, T* eh, T* ev, in
 // by delta (lognormal, eq. (3.3)).  Not inlined: a few lanes evaluate it once
 // per sample, and inlined into a solver its polynomial constants are hoisted
 // out of the sample loop and spilled.
-// Its arguments are scalars: a reference to the kernel's problem structure
-// would make the callers keep a private copy of it.
-__device__ __noinline__ double model_theta(int model, double alpha, double beta, double delta, double t) {
+// With raw set, t is already the parameter y (the affine and lognormal
+// factors are y itself, the periodic one sin(2 pi y)).  Its arguments are
+// scalars: a reference to the kernel's problem structure would make the
+// callers keep a private copy of it.
+__device__ __noinline__ double model_theta(int model, int raw, double alpha, double beta, double delta, double t) {
+  if (raw && model != USFFT_MODEL_PERIODIC) return t;
   if (model == USFFT_MODEL_AFFINE) return beta - fabs((beta - alpha) * (1.0 - 2.0 * t));
   if (model == USFFT_MODEL_LOGNORMAL) {
     const double dl = delta;
@@ -65,7 +68,8 @@ __device__ __noinline__ double model_theta(int model, double alpha, double beta,
 
 __device__ __forceinline__ void load_coef(const PdeDev& P, const double* __restrict__ Y, int64_t s,
                                           double* coef) {
-  for (int k = threadIdx.x; k < P.d; k += blockDim.x) coef[k] = P.amp[k] * model_theta(P.model, P.alpha, P.beta, P.delta, Y[s * P.d + k]);
+  for (int k = threadIdx.x; k < P.d; k += blockDim.x)
+    coef[k] = P.amp[k] * model_theta(P.model, P.raw, P.alpha, P.beta, P.delta, Y[s * P.d + k]);
 }
 
 template <typename T>

@@ -253,19 +253,22 @@ static void group_by_lattice(usfft_plan_s* P, Family& F, const int32_t* assign, 
 }
 
 // Sampler call on rows [0, ns) of Y into U columns [col0, col0 + ns).
+// params: Y holds parameters y of the model instead of sampling nodes t
 static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, int out_fp32, int64_t ld,
-                        int64_t col0, int32_t* iters, hipStream_t st) {
+                        int64_t col0, int32_t* iters, hipStream_t st, bool params = false) {
   if (ns <= 0) return;
   const usfft_params& par = P->par;
+  PdeDev pde = P->pde;
+  pde.raw = params ? 1 : 0;
   if (P->prob.sampler == USFFT_SAMPLER_PDE && P->dst) {
-    launch_pde_solve_dst(P->pde, par.precision, P->dst_variant, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
+    launch_pde_solve_dst(pde, par.precision, P->dst_variant, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
                          par.refine_every, U, out_fp32, ld, col0, iters, P->d_wscr.as<double>(), P->wblocks,
                          P->d_sfrag.p, P->d_lam.as<float>(), st);
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->streaming) {
-    launch_pde_solve_stream(P->pde, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
+    launch_pde_solve_stream(pde, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
                             P->d_stream.as<double>(), kStreamBlocks, st);
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE) {
-    launch_pde_solve(P->solver_cfg, P->pde, par.precision, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
+    launch_pde_solve(P->solver_cfg, pde, par.precision, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
                      par.refine_every, U, out_fp32, ld, col0, iters, P->d_wscr.as<double>(), P->wblocks, st);
   } else {
     launch_trigpoly(P->prob.d, Y, ns, P->d_polyk.as<int32_t>(), P->prob.n_poly, P->d_polyc.as<double>(), P->G, U,
@@ -868,18 +871,103 @@ usfft_status usfft_result_copy(usfft_result_t res, int32_t* freqs_host, double* 
 
 void usfft_result_destroy(usfft_result_t res) { delete res; }
 
+namespace {
+// Points per chunk of an evaluation: the phase matrix (2 |I| rows) stays
+// within 256 MB and, with FE solutions (G rows), those within 1 GB.
+int64_t eval_chunk(int64_t n, int64_t nI, int64_t G, bool with_fe) {
+  int64_t nc = (int64_t)(256ll << 20) / std::max<int64_t>(1, 16 * nI);
+  if (with_fe) nc = std::min<int64_t>(nc, (int64_t)(1ll << 30) / std::max<int64_t>(1, 8 * G));
+  nc = std::max<int64_t>(64, nc / 64 * 64);
+  return std::min<int64_t>(nc, std::max<int64_t>(n, 1));
+}
+
+void upload_set(const usfft_result_s* res, usfft::DevBuf& I) {
+  if (res->I.empty()) return;
+  I.ensure(sizeof(int32_t) * res->I.size());
+  USFFT_HIP(hipMemcpy(I.p, res->I.data(), sizeof(int32_t) * res->I.size(), hipMemcpyHostToDevice));
+}
+}  // namespace
+
 usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n, double* out_dev, void* stream) {
   return guarded([&] {
-    USFFT_REQUIRE(res && (n == 0 || (y_dev && out_dev)), USFFT_EINVAL, "bad eval arguments");
+    USFFT_REQUIRE(res && n >= 0 && (n == 0 || (y_dev && out_dev)), USFFT_EINVAL, "bad eval arguments");
+    if (n == 0 || res->G == 0) return;
+    hipStream_t st = (hipStream_t)stream;
     const int64_t nI = res->d ? (int64_t)res->I.size() / res->d : 0;
-    DevBuf I;
-    if (nI > 0) {
-      I.ensure(sizeof(int32_t) * res->I.size());
-      USFFT_HIP(hipMemcpy(I.p, res->I.data(), sizeof(int32_t) * res->I.size(), hipMemcpyHostToDevice));
+    DevBuf I, T, B;
+    upload_set(res, I);
+    const int64_t nc = eval_chunk(n, nI, res->G, false);
+    T.ensure(sizeof(double) * (size_t)(res->d * nc));
+    B.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, 2 * nI * nc));
+    for (int64_t c0 = 0; c0 < n; c0 += nc) {
+      const int64_t m = std::min(nc, n - c0);
+      launch_node_map(y_dev + c0 * res->d, m, res->d, res->model, res->alpha, res->beta, res->delta,
+                      T.as<double>(), nc, st);
+      launch_phases(I.as<int32_t>(), nI, res->d, T.as<double>(), nc, m, B.as<double>(), nc, st);
+      launch_evgemm_values(res->C.as<double>(), res->G, nI, B.as<double>(), nc, m, out_dev + c0 * res->G, res->G,
+                           st);
     }
-    launch_eval(I.as<int32_t>(), nI, res->d, res->C.as<double>(), res->G, y_dev, n, res->model, res->alpha,
-                res->beta, res->delta, out_dev, (hipStream_t)stream);
-    USFFT_HIP(hipStreamSynchronize((hipStream_t)stream));
+    USFFT_HIP(hipStreamSynchronize(st));
+  });
+}
+
+usfft_status usfft_statistics(usfft_result_t res, double* mean_dev, double* var_dev, double* gsi_dev,
+                              void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(res, USFFT_EINVAL, "bad statistics arguments");
+    if (res->G == 0 || (!mean_dev && !var_dev && !gsi_dev)) return;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nI = res->d ? (int64_t)res->I.size() / res->d : 0;
+    DevBuf I, D, ord;
+    upload_set(res, I);
+    D.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, 2 * nI));
+    ord.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(1, nI));
+    launch_stats(I.as<int32_t>(), nI, res->d, res->C.as<double>(), res->G, res->model, res->delta, D.as<double>(),
+                 ord.as<int32_t>(), mean_dev, var_dev, gsi_dev, st);
+    USFFT_HIP(hipStreamSynchronize(st));
+  });
+}
+
+usfft_status usfft_errors(usfft_plan_t plan, usfft_result_t res, const double* y_dev, int64_t n, double p,
+                          double* errp_dev, double* errinf_dev, void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(plan && res && n >= 1 && y_dev && errp_dev && errinf_dev, USFFT_EINVAL, "bad errors arguments");
+    USFFT_REQUIRE(p >= 1.0 && std::isfinite(p), USFFT_EINVAL, "p must be finite and >= 1");
+    USFFT_REQUIRE(res->d == plan->prob.d && res->G == plan->G, USFFT_EINVAL,
+                  "the result does not belong to this plan's problem");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t G = res->G, d = res->d;
+    const int64_t nI = d ? (int64_t)res->I.size() / d : 0;
+    const int64_t nc = eval_chunk(n, nI, G, true);
+    DevBuf I, T, B, U, it, ps, pm, cnt;
+    upload_set(res, I);
+    T.ensure(sizeof(double) * (size_t)(d * nc));
+    B.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, 2 * nI * nc));
+    U.ensure(sizeof(double) * (size_t)(G * nc));
+    it.ensure(sizeof(int32_t) * (size_t)nc);
+    ps.ensure(sizeof(double) * (size_t)(evgemm_tiles_j(nc) * G));
+    pm.ensure(sizeof(double) * (size_t)(evgemm_tiles_j(nc) * G));
+    cnt.ensure(2 * sizeof(unsigned long long));
+    USFFT_HIP(hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long), st));
+    for (int64_t c0 = 0; c0 < n; c0 += nc) {
+      const int64_t m = std::min(nc, n - c0);
+      const double* Y = y_dev + c0 * d;
+      // finite-element solutions at the parameters themselves (Sec. 4)
+      run_sampler(plan, Y, m, U.p, 0, nc, 0, it.as<int32_t>(), st, true);
+      hipLaunchKernelGGL(iter_stats_kernel, dim3((unsigned)std::min<int64_t>(256, ceil_div(m, 256))), dim3(256), 0,
+                         st, it.as<int32_t>(), m, cnt.as<unsigned long long>());
+      USFFT_HIP(hipGetLastError());
+      launch_node_map(Y, m, (int)d, res->model, res->alpha, res->beta, res->delta, T.as<double>(), nc, st);
+      launch_phases(I.as<int32_t>(), nI, (int)d, T.as<double>(), nc, m, B.as<double>(), nc, st);
+      launch_evgemm_errors(res->C.as<double>(), G, nI, B.as<double>(), nc, m, U.as<double>(), nc, p, ps.as<double>(),
+                           pm.as<double>(), c0 == 0, errp_dev, errinf_dev, st);
+    }
+    launch_err_final(errp_dev, G, n, p, st);
+    unsigned long long h[2];
+    USFFT_HIP(hipMemcpyAsync(h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+    USFFT_REQUIRE(h[0] == 0, USFFT_ENOCONV, std::to_string(h[0]) + " test solves missed pcg_rtol within pcg_maxit");
   });
 }
 

@@ -108,3 +108,37 @@ def test_streaming_solver_large_meshes(lib, n, d, ns):
     for s in range(0, ns, max(1, ns // 2)):
         ref = S.solve_one(Y[s])
         assert np.linalg.norm(Ug[:, 1 + s] - ref) / np.linalg.norm(ref) <= 1e-11
+
+
+def test_errors_full_size_chunks_and_epilogue(lib):
+    # h = 1/64, d = 10 job (float32 + refinement): 40 000 test points take two
+    # chunks; err_p^p and err_inf of the whole set combine those of its parts,
+    # and on 300 points the fused error epilogue agrees with the values of
+    # usfft_eval and usfft_sample (periodic model: parameters are nodes)
+    prob, par = W.WORKLOADS["mesh64_d10"]
+    plan = lib.Plan(prob, dict(par, precision=1))
+    res = lib.detect(plan, 1)
+    G, d = res.G, prob["d"]
+    Y = np.random.default_rng(23).random((40000, d))
+
+    def errs(y, p=2.0):
+        ep = torch.zeros(G, dtype=torch.float64, device="cuda")
+        ei = torch.zeros(G, dtype=torch.float64, device="cuda")
+        lib.errors(plan, res, dev(y), p, ep, ei)
+        return host(ep), host(ei)
+
+    ea, ia = errs(Y)
+    e1, i1 = errs(Y[:30000])
+    e2, i2 = errs(Y[30000:])
+    assert np.allclose(ea ** 2, (30000 * e1 ** 2 + 10000 * e2 ** 2) / 40000, rtol=1e-10, atol=0)
+    assert np.array_equal(ia, np.maximum(i1, i2))
+    y = Y[:300]
+    U = torch.zeros((G, 300), dtype=torch.float64, device="cuda")
+    lib.sample(plan, dev(y), U, 0, 300)
+    V = torch.zeros((300, G), dtype=torch.float64, device="cuda")
+    lib.eval(res, dev(y), V)
+    D = np.abs(host(U).T - host(V))
+    for p in (2.0, 3.0):
+        ep, ei = errs(y, p)
+        assert np.allclose(ep, np.mean(D ** p, axis=0) ** (1 / p), rtol=1e-10, atol=0)
+        assert np.array_equal(ei, D.max(axis=0))

@@ -342,6 +342,7 @@ def oracle_sampler(prob, delta=None):
 def run_both(lib, prob, par, seed, precision=0, sampler=None, **kw):
     plan = lib.Plan(prob, dict(par, precision=precision, pcg_rtol=1e-13 if precision == 0 else 1e-12, **kw))
     res = lib.detect(plan, seed)
+    res.plan = plan
     if sampler is None:
         sampler = oracle_sampler(prob)
     ref = usfft(sampler, prob["d"], prob["k_lo"], prob["k_hi"], par["s"], par["s_local"], par["r"], par["theta"],
@@ -404,16 +405,102 @@ def test_detect_is_deterministic(lib):
 
 
 def test_eval_matches_oracle(lib):
-    K, P = W.trig_poly(8, 4, 8, 50, 25, cmin=1e-2)
+    # 130 nodes (three node tiles, the last ragged) and 203 points (four
+    # point tiles, the last ragged) against the oracle's own run
+    K, P = W.trig_poly(8, 4, 8, 130, 25, cmin=1e-2)
     prob = dict(sampler="poly", d=4, k_lo=[-8] * 4, k_hi=[8] * 4, poly_k=K, poly_c=P)
-    plan = lib.Plan(prob, W.params(60, 3, 1e-6, relative=False))
-    res = lib.detect(plan, 2)
-    Y = np.random.default_rng(3).random((11, 4))
-    out = torch.zeros((11, 50), dtype=torch.float64, device="cuda")
+    res, ref = run_both(lib, prob, W.params(60, 3, 1e-6, relative=False), 2, sampler=TrigPolySampler(K, P))
+    assert res.freqs().tolist() == ref.I.tolist()
+    Y = np.random.default_rng(3).random((203, 4))
+    out = torch.zeros((203, 130), dtype=torch.float64, device="cuda")
     lib.eval(res, dev(Y), out)
-    ref = evaluate(res.freqs(), res.coeffs(), Y)
-    assert np.abs(host(out) - ref).max() <= 1e-12 * np.abs(ref).max()
+    want = evaluate(ref.I, ref.C, Y)
+    assert np.abs(host(out) - want).max() <= 1e-12 * np.abs(want).max()
     assert np.abs(host(out) - TrigPolySampler(K, P)(Y)).max() <= 1e-11
+    lib.eval(res, dev(np.zeros((0, 4))), torch.zeros((0, 130), dtype=torch.float64, device="cuda"))
+
+
+def _model_case(model):
+    from oracle import periodization as OP
+    delta = OP.delta_opt(9601)
+    if model == "periodic":
+        prob, par = W.WORKLOADS["cpu16_d4"]
+        return prob, par, oracle_sampler(prob), OP.PERIODIC, 0.0
+    prob = W.affine_problem(16, 4, 8) if model == "affine" else W.lognormal_problem(16, 4, 8)
+    code = OP.AFFINE if model == "affine" else OP.LOGNORMAL
+    return prob, W.params(30, 2, 1e-4), oracle_sampler(prob, delta=delta), code, delta
+
+
+@pytest.mark.parametrize("model", ["periodic", "affine", "lognormal"])
+def test_statistics_match_oracle(lib, model):
+    # expectation with the model's D factors, variance and sensitivity
+    # indices (Sec. 4, 4.1) of the GPU result against the oracle's own run
+    from oracle import evaluation as oev
+    prob, par, sampler, code, delta = _model_case(model)
+    res, ref = run_both(lib, prob, par, 5, sampler=sampler)
+    assert res.freqs().tolist() == ref.I.tolist()
+    G, d = res.G, prob["d"]
+    mean = torch.zeros((G, 2), dtype=torch.float64, device="cuda")
+    var = torch.zeros(G, dtype=torch.float64, device="cuda")
+    gsi = torch.zeros((d, G), dtype=torch.float64, device="cuda")
+    lib.statistics(res, mean, var, gsi)
+    scale = np.abs(ref.C).max()
+    m_ref = oev.expectation(ref.I, ref.C, code, delta)
+    assert np.abs(host(mean)[:, 0] - m_ref.real).max() <= 1e-9 * scale
+    assert np.abs(host(mean)[:, 1] - m_ref.imag).max() <= 1e-9 * scale
+    v_ref = oev.variance(ref.I, ref.C)
+    assert np.abs(host(var) - v_ref).max() <= 1e-9 * v_ref.max()
+    g_ref = oev.sensitivity_indices(ref.I, ref.C)
+    live = v_ref > 1e-6 * v_ref.max()
+    assert np.abs(host(gsi)[:, live] - g_ref[:, live]).max() <= 1e-6
+    assert np.allclose(host(gsi)[:, live].sum(axis=0), 1.0, rtol=0, atol=1e-12)
+    # any output may be left out
+    var2 = torch.zeros(G, dtype=torch.float64, device="cuda")
+    lib.statistics(res, None, var2, None)
+    assert np.array_equal(host(var2), host(var))
+
+
+@pytest.mark.parametrize("model", ["periodic", "affine", "lognormal"])
+def test_errors_match_oracle(lib, model):
+    # err_p / err_inf of Sec. 4: FE solves at the test parameters themselves
+    # and the approximation at the same parameters, against the oracle's
+    # banded-Cholesky solves and its own coefficients
+    from oracle import evaluation as oev
+    prob, par, sampler, code, delta = _model_case(model)
+    res, ref = run_both(lib, prob, par, 5, sampler=sampler)
+    assert res.freqs().tolist() == ref.I.tolist()
+    g = np.random.default_rng(17)
+    n, d = 150, prob["d"]
+    alpha, beta = prob.get("alpha", -1.0), prob.get("beta", 1.0)
+    Y = {"periodic": lambda: g.random((n, d)), "affine": lambda: g.uniform(alpha, beta, (n, d)),
+         "lognormal": lambda: g.standard_normal((n, d))}[model]()
+    U_fe = np.array([sampler.solve_param(y) for y in Y])
+    U_ap = oev.approximation(ref.I, ref.C, Y, code, alpha, beta, delta)
+    for p in (2.0, 1.0, 1.5):
+        ep = torch.zeros(res.G, dtype=torch.float64, device="cuda")
+        ei = torch.zeros(res.G, dtype=torch.float64, device="cuda")
+        lib.errors(res.plan, res, dev(Y), p, ep, ei)
+        ep_ref, ei_ref = oev.errors(U_fe, U_ap, p)
+        tol = 1e-9 * np.abs(U_fe).max()
+        assert np.all(np.abs(host(ep) - ep_ref) <= tol + 1e-6 * ep_ref), (p, np.abs(host(ep) - ep_ref).max())
+        assert np.all(np.abs(host(ei) - ei_ref) <= tol + 1e-6 * ei_ref), p
+        assert np.all(host(ei) >= host(ep) * (1 - 1e-12))
+
+
+def test_errors_arguments_are_checked(lib):
+    prob, par = W.WORKLOADS["cpu16_d4"]
+    plan = lib.Plan(prob, par)
+    res = lib.detect(plan, 1)
+    ep = torch.zeros(res.G, dtype=torch.float64, device="cuda")
+    Y = dev(np.random.default_rng(0).random((5, prob["d"])))
+    for bad in (0.5, float("inf")):
+        with pytest.raises(lib.UsfftError) as e:
+            lib.errors(plan, res, Y, bad, ep, ep.clone())
+        assert e.value.status == lib.EINVAL
+    other = lib.Plan(W.pde_problem(8, prob["d"], 4), par)
+    with pytest.raises(lib.UsfftError) as e:
+        lib.errors(other, res, Y, 2.0, ep, ep.clone())
+    assert e.value.status == lib.EINVAL
 
 
 def test_error_paths(lib):
