@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "PDE sample solves/s + lattice-FFT GB/s, batched-FP32 vs plain FP64; p50/p99 job"
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "f16_mfma": 2500.0}  # MI355X vector / dense matrix peaks
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "f16_mfma": 2500.0, "f64_mfma": 78.6}  # MI355X vector / dense matrix peaks
 # Vector work of one preconditioned CG iteration on the scaled 5-point
 # operator, per node: operator 9, two dot products 4, three updates 6, the
 # norm 2 and the scalings around the fp16 conversion 2.
@@ -86,6 +86,50 @@ def serving_run(U, jobs, rate, seed, max_active):
                       "float32+refine, seed %d" % seed}
 
 
+def evaluation_run(U, torch, plan, prob, seed, n_test):
+    """Post-processing of one job's result (Sec. 4, 4.1): the error measures
+    over n_test uniform test parameters (FE solves + evaluation product on the
+    float64 matrix cores), the evaluation product alone, and the statistics."""
+    res = U.detect(plan, seed)
+    G, d = res.G, prob["d"]
+    nI = res.n
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    Y = torch.rand((n_test, d), dtype=torch.float64, device="cuda", generator=gen)
+    ep = torch.empty(G, dtype=torch.float64, device="cuda")
+    ei = torch.empty(G, dtype=torch.float64, device="cuda")
+    U.errors(plan, res, Y[:1024], 2.0, ep, ei)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U.errors(plan, res, Y, 2.0, ep, ei)
+    t_err = time.perf_counter() - t0
+    ne = min(n_test, 32768)
+    out = torch.empty((ne, G), dtype=torch.float64, device="cuda")
+    U.eval(res, Y[:1024], out[:1024])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U.eval(res, Y[:ne], out)
+    t_eval = time.perf_counter() - t0
+    flops = 2.0 * G * (2 * nI) * ne
+    mean = torch.empty((G, 2), dtype=torch.float64, device="cuda")
+    var = torch.empty(G, dtype=torch.float64, device="cuda")
+    gsi = torch.empty((d, G), dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    U.statistics(res, mean, var, gsi)
+    t_stat = time.perf_counter() - t0
+    e2, einf, m = ep.cpu().numpy(), ei.cpu().numpy(), mean[:, 0].cpu().numpy()
+    scale = float(abs(m).max())
+    return {
+        "n_test": n_test, "frequencies": nI,
+        "errors_ms": 1e3 * t_err, "test_points_per_s": n_test / t_err,
+        "err2_max_rel": float(e2.max()) / scale, "err_inf_max_rel": float(einf.max()) / scale,
+        "eval_points": ne, "eval_ms": 1e3 * t_eval, "eval_tflops": flops / t_eval / 1e12,
+        "eval_frac_f64_mfma": flops / t_eval / 1e12 / PEAK_TFLOPS["f64_mfma"],
+        "statistics_ms": 1e3 * t_stat,
+        "gsi_mean": [float(x) for x in gsi.mean(dim=1).cpu().numpy()[:4]],
+        "note": "relative to max_g |E(u(x_g, .))|; periodic model, y uniform on [0,1)^d",
+    }
+
+
 def measured_traffic():
     """HBM bytes per solver launch from the committed rocprof counter summary,
     only while the solver source is the one the counters were taken on."""
@@ -145,6 +189,8 @@ def main():
                          "counter pass sees the same kernel")
     ap.add_argument("--models", type=int, default=1,
                     help="also time one job each of the affine and lognormal models (0 = skip)")
+    ap.add_argument("--eval-points", type=int, default=100000,
+                    help="test parameters of the error measures of one job's result (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof byte counters)")
     args = ap.parse_args()
@@ -229,6 +275,8 @@ def main():
         "job_breakdown_ms": per_job,
     }
     res.update(out)
+    if args.eval_points > 0:
+        res["evaluation"] = evaluation_run(U, torch, plan32, prob, args.seed, args.eval_points)
     if args.models:
         # the periodized affine and lognormal coefficient models (Sec. 3.2) on
         # the same mesh, dimension, box and sparsity
