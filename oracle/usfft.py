@@ -128,15 +128,28 @@ def usfft(sampler, d, k_lo, k_hi, s, s_local, r, theta, theta_relative, seed,
 
     # ---- step 3: coefficients on the detected set ----
     I = Iprev
-    fam = plan_family(I, lattice_c, lattice_mmax, lattice_tries, lattice_max,
-                      seed, rng.KIND_LAT3, 0)
-    C = np.zeros((len(I), sampler.G), dtype=np.complex128)
-    for l, (M, z) in enumerate(zip(fam.M, fam.z)):
-        U = sampler(lattice_nodes(M, z))
-        res.samples += M
-        sel = fam.assign == l
-        C[sel] = dft_bins(U, fam.bins[sel])
+    C, fam, ns = coefficients(sampler, I, seed, lattice_c, lattice_tries, lattice_max, lattice_mmax)
+    res.samples += ns
     res.stages.append(dict(step=3, t=d, i=1, cand=I, family=fam))
     res.I = I
     res.C = C
     return res
+
+
+def coefficients(sampler, I, seed, lattice_c=2.0, lattice_tries=8, lattice_max=64, lattice_mmax=9601):
+    """Step 3 of Alg. 1 on the frequency set I (n x d): the lattice family of
+    I (Algorithm A, reading in lattice.py), one sample per lattice node, and
+    c_k read from k's bin of its assigned lattice.  Used on the detected set
+    and, as in Sec. 4.5, on an a-priori set.  Returns (C, family, samples)."""
+    I = np.asarray(I, dtype=np.int64)
+    C = np.zeros((len(I), sampler.G), dtype=np.complex128)
+    if len(I) == 0:
+        return C, None, 0
+    fam = plan_family(I, lattice_c, lattice_mmax, lattice_tries, lattice_max, seed, rng.KIND_LAT3, 0)
+    ns = 0
+    for l, (M, z) in enumerate(zip(fam.M, fam.z)):
+        U = sampler(lattice_nodes(M, z))
+        ns += M
+        sel = fam.assign == l
+        C[sel] = dft_bins(U, fam.bins[sel])
+    return C, fam, ns

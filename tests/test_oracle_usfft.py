@@ -40,3 +40,40 @@ def test_sets_are_lexicographic_and_symmetric_pde():
     # the mean coefficient is the largest and positive (u > 0 for f = 1)
     z = idx[tuple([0] * prob["d"])]
     assert (res.C[z].real > 0).all()
+
+
+def test_step3_on_a_given_superset_recovers_the_polynomial():
+    # Sec. 4.5: step 3 alone on an a-priori set.  On any set containing the
+    # support (here with extra frequencies, in shuffled order) the lattice
+    # family reconstructs the polynomial exactly: its coefficients, and zero
+    # on the frequencies it does not use
+    from oracle.usfft import coefficients
+    d, N = 4, 8
+    K, P = W.trig_poly(11, d, N, 6, 31, cmin=1e-2)
+    extra = W.hyperbolic_cross(d, N, [4] * d)
+    I = np.unique(np.vstack([K, extra]), axis=0)
+    I = I[np.random.default_rng(2).permutation(len(I))]
+    C, fam, ns = coefficients(TrigPolySampler(K, P), I, seed=5)
+    idx = {tuple(k): a for a, k in enumerate(K.tolist())}
+    for a, k in enumerate(I.tolist()):
+        want = P[idx[tuple(k)]] if tuple(k) in idx else 0.0
+        assert np.allclose(C[a], want, rtol=0, atol=1e-12)
+    assert ns == sum(fam.M)
+    C0, fam0, ns0 = coefficients(TrigPolySampler(K, P), np.zeros((0, d), dtype=int), seed=5)
+    assert C0.shape == (0, 6) and ns0 == 0
+
+
+def test_a_priori_sets_match_their_definitions():
+    # Sec. 4.5 index sets against brute-force enumeration of the box
+    import itertools
+    d, N = 3, 6
+    box = list(itertools.product(range(-N, N + 1), repeat=d))
+    mult = [1, 2, 3]
+    cases = [
+        (W.axis_cross(d, N), lambda k: sum(1 for v in k if v) <= 1 and sum(map(abs, k)) <= N),
+        (W.hyperbolic_cross(d, N, [4] * d), lambda k: np.prod([max(1, 4 * abs(v)) for v in k]) <= N),
+        (W.hyperbolic_cross(d, N, mult), lambda k: np.prod([max(1, m * abs(v)) for m, v in zip(mult, k)]) <= N),
+        (W.weighted_l1_ball(d, N, mult), lambda k: sum(m * abs(v) for m, v in zip(mult, k)) <= N),
+    ]
+    for got, test in cases:
+        assert got.tolist() == sorted([list(k) for k in box if test(k)])

@@ -167,3 +167,49 @@ def candidate_set(seed, n_parent, t, n_child, kmax=4, max_active=4):
     parent = np.array(sorted(S), dtype=np.int64)
     child = np.arange(-(n_child // 2), n_child // 2 + 1, dtype=np.int64)
     return parent, child
+
+
+# ---- a-priori frequency sets (Sec. 4.5), inputs of usfft_coefficients ----
+# Weights are integer multipliers m_j (weight 1/m_j), so membership is exact.
+
+def _enumerate(d, keep_prefix):
+    """All k in Z^d (lexicographic) whose every prefix passes keep_prefix."""
+    out = []
+
+    def rec(prefix):
+        if len(prefix) == d:
+            out.append(list(prefix))
+            return
+        k = 0
+        # grow |k| in the next coordinate until the prefix test fails
+        cands = [0]
+        while True:
+            k += 1
+            if not keep_prefix(prefix + [k]):
+                break
+            cands += [k, -k]
+        for v in sorted(cands):
+            rec(prefix + [v])
+
+    rec([])
+    return np.array(out, dtype=np.int32).reshape(-1, d)
+
+
+def axis_cross(d, N):
+    """{k : at most one nonzero component, ||k||_1 <= N} (the constant term kept)."""
+    return _enumerate(d, lambda p: sum(1 for v in p if v) <= 1 and sum(abs(v) for v in p) <= N)
+
+
+def hyperbolic_cross(d, N, mult):
+    """{k : prod_j max(1, m_j |k_j|) <= N}; m_j = 4 (uniform weight 1/4) or j^q."""
+    def ok(p):
+        prod = 1
+        for j, v in enumerate(p):
+            prod *= max(1, mult[j] * abs(v))
+        return prod <= N
+    return _enumerate(d, ok)
+
+
+def weighted_l1_ball(d, N, mult):
+    """{k : sum_j m_j |k_j| <= N}; m_j = j^q."""
+    return _enumerate(d, lambda p: sum(mult[j] * abs(v) for j, v in enumerate(p)) <= N)
