@@ -175,6 +175,18 @@ int64_t usfft_plan_nodes(usfft_plan_t plan);
 usfft_status usfft_detect(usfft_plan_t plan, uint64_t seed, void* stream,
                           usfft_result_t* out);
 
+/* Step 3 of Alg. 1 alone on a given frequency set (Sec. 4.5: a-priori index
+ * sets such as axis crosses, hyperbolic crosses and weighted l1 balls):
+ * freqs_host (n x d int32, row-major, no repeated rows; any order) replaces
+ * the detected set, and its coefficients for every node are computed with the
+ * multiple rank-1 lattice family of step 3 (seeded like usfft_detect's
+ * step 3).  The result lists the frequencies in the caller's order; n = 0
+ * gives an empty result.  The plan's sampler, mesh, precision and lattice
+ * parameters apply; s, s_local, r and theta are not used.
+ * Errors: EINVAL (repeated rows), ENOCONV, ELATTICE, ENOMEM, EHIP. */
+usfft_status usfft_coefficients(usfft_plan_t plan, const int32_t* freqs_host, int64_t n,
+                                uint64_t seed, void* stream, usfft_result_t* out);
+
 usfft_status usfft_result_info(usfft_result_t res, int64_t* n_freq, int32_t* d,
                                int64_t* G, usfft_stats* stats);
 /* freqs_host: n_freq x d int32 (lexicographic); coeffs_host: n_freq x G x 2

@@ -74,6 +74,7 @@ _sigs = {
     "usfft_result_destroy": (None, [_vp]),
     "usfft_eval": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
     "usfft_statistics": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "usfft_coefficients": (C.c_int, [_vp, _vp, C.c_int64, C.c_uint64, _vp, _vp]),
     "usfft_errors": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp]),
     "usfft_sample": (C.c_int, [_vp, _vp, C.c_int64, _vp, C.c_int32, C.c_int64, C.c_int64, _vp, _vp]),
     "usfft_nodes": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp]),
@@ -286,6 +287,15 @@ def plan_create(problem, params):
 def detect(plan, seed, stream=None):
     h = _vp()
     _check(_lib.usfft_detect(plan.handle, C.c_uint64(seed), _stream(stream), C.byref(h)))
+    return Result(h)
+
+
+def coefficients(plan, freqs, seed, stream=None):
+    """usfft_coefficients: step 3 alone on the given frequencies (n x d)."""
+    F = np.ascontiguousarray(np.asarray(freqs, dtype=np.int32).reshape(-1, plan.d))
+    h = _vp()
+    _check(_lib.usfft_coefficients(plan.handle, F.ctypes.data if F.size else None, F.shape[0], C.c_uint64(seed),
+                                   _stream(stream), C.byref(h)))
     return Result(h)
 
 

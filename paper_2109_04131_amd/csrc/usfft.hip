@@ -334,7 +334,9 @@ struct Timer {
 enum { kTSample = 0, kTDft = 1, kTSelect = 2 };
 
 // ---------------------------------------------------------------- Alg. 1
-static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_s* R) {
+// given: step 3 alone on the set given_I (host, given_n x d)
+static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_s* R, bool given = false,
+                   const int32_t* given_I = nullptr, int64_t given_n = 0) {
   const usfft_problem& pb = P->prob;
   const usfft_params& par = P->par;
   const int d = pb.d;
@@ -371,174 +373,184 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
                   std::to_string(h[0]) + " PCG solves missed pcg_rtol within pcg_maxit");
   };
 
-  // ---------------- step 1 & 2a
-  // The d x r line stages are independent: their sampling nodes are
-  // generated into one batch, solved in one sampler launch, then
-  // transformed and selected line by line (the threshold of a relative theta
-  // comes from line (1, 1), which runs first).
-  P->I1.resize(d);
-  P->I1n.assign(d, 0);
-  bool theta_set = !par.theta_relative;
-  {
-    const int r = par.r;
-    std::vector<int32_t> Kt(d), ks;
-    std::vector<int64_t> off(d * r + 1, 0), coff(d + 1, 0), woff(d + 1, 0);
-    int Kmax = 1;
-    for (int t = 0; t < d; ++t) {
-      Kt[t] = pb.k_hi[t] - pb.k_lo[t] + 1;
-      Kmax = std::max(Kmax, Kt[t]);
-      for (int a = 0; a < Kt[t]; ++a) ks.push_back(pb.k_lo[t] + a);
-      coff[t + 1] = coff[t] + Kt[t];
-      woff[t + 1] = woff[t] + ceil_div(Kt[t], 32);
-      for (int i = 0; i < r; ++i) off[t * r + i + 1] = off[t * r + i] + Kt[t];
-    }
-    const int64_t ns = off.back(), ld = ceil_div(ns, 64) * 64;
-    h2d(P->cands, ks, st);
-    h2d(P->latM, Kt, st);
-    P->U.ensure(ub * G * ld);
-    P->V.ensure(sizeof(double) * G * Kmax);
-    P->Y.ensure(sizeof(double) * ns * d);
-    P->iters.ensure(sizeof(int32_t) * ns);
-    P->mask.ensure(sizeof(uint32_t) * woff[d]);
-    USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * woff[d], st));
-    std::vector<double> tails((size_t)d * r * d);
-    for (int t = 0; t < d; ++t)
-      for (int i = 0; i < r; ++i)
-        for (int j = 0; j < d; ++j)
-          tails[((size_t)t * r + i) * d + j] = rng::uniform01(seed, rng::stream(rng::kTail1, t + 1, i + 1, 0), j);
-    h2d(P->tail, tails, st);
-    for (int t = 0; t < d; ++t)
-      for (int i = 0; i < r; ++i)
-        launch_nodes(d, t, 1, 1, nullptr, P->latM.as<int32_t>() + t, nullptr,
-                     P->tail.as<double>() + ((size_t)t * r + i) * d, P->Y.as<double>() + off[t * r + i] * d, Kt[t],
-                     st);
-    sample_timed(P->Y.as<double>(), ns, ld);
-    S.samples_step1 += ns;
-    for (int t = 0; t < d; ++t) {
-      const int K = Kt[t];
-      for (int i = 0; i < r; ++i) {
-        int e = tm.open(kTDft);
-        launch_line_dft(P->U.p, ufp32, G, ld, off[t * r + i], K, P->cands.as<int32_t>() + coff[t], K,
-                        USFFT_OUT_MAG2, P->V.p, K, st);
-        tm.close(kTDft, e);
-        S.dft_launches += 1;
-        if (!theta_set) {
-          launch_max_to_theta(P->V.as<double>(), G, K, K, par.theta, P->theta2.as<double>(),
-                              P->scratch.as<uint64_t>(), st);
-          theta_set = true;
-        }
-        e = tm.open(kTSelect);
-        launch_select(P->V.as<double>(), G, K, K, par.s_local, P->theta2.as<double>(), par.tie_rel,
-                      P->mask.as<uint32_t>() + woff[t], nullptr, st);
-        tm.close(kTSelect, e);
-      }
-    }
-    P->scratch.ensure(32 + sizeof(int64_t) * d);
-    for (int t = 0; t < d; ++t) {
-      P->I1[t].ensure(sizeof(int32_t) * Kt[t]);
-      launch_compact(P->cands.as<int32_t>() + coff[t], P->mask.as<uint32_t>() + woff[t], Kt[t], 1,
-                     P->I1[t].as<int32_t>(), reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32) + t, st);
-    }
-    std::vector<int64_t> cnt(d);
-    USFFT_HIP(hipMemcpyAsync(cnt.data(), P->scratch.as<char>() + 32, sizeof(int64_t) * d, hipMemcpyDeviceToHost,
-                             st));
-    check_conv();
-    for (int t = 0; t < d; ++t) P->I1n[t] = cnt[t];
-  }
-  {
-    double th2 = 0;
-    USFFT_HIP(hipMemcpyAsync(&th2, P->theta2.p, sizeof(double), hipMemcpyDeviceToHost, st));
-    USFFT_HIP(hipStreamSynchronize(st));
-    S.theta_abs = std::sqrt(th2);
-  }
-
-  // ---------------- step 2
-  int64_t nprev = P->I1n[0];
-  P->Iprev.ensure(sizeof(int32_t) * std::max<int64_t>(nprev, 1));
-  if (nprev > 0)
-    USFFT_HIP(hipMemcpyAsync(P->Iprev.p, P->I1[0].p, sizeof(int32_t) * nprev, hipMemcpyDeviceToDevice, st));
+  int64_t nprev = 0;
   Family F;
-  for (int t = 1; t < d; ++t) {
-    const bool last = t == d - 1;
-    const int r_t = last ? 1 : par.r;
-    const int s_t = last ? par.s : par.s_local;
-    const int64_t nc = P->I1n[t];
-    const int64_t n = nprev * nc;
-    S.max_candidates = std::max(S.max_candidates, n);
-    if (n == 0) {
-      nprev = 0;
-      continue;
-    }
-    const int w = t + 1;
-    P->J.ensure(sizeof(int32_t) * n * w);
-    launch_product(P->Iprev.as<int32_t>(), nprev, t, P->I1[t].as<int32_t>(), nc, P->J.as<int32_t>(), st);
-    P->assign.ensure(sizeof(int32_t) * n);
-    P->bins.ensure(sizeof(int32_t) * n);
-    plan_family(P, P->J.as<int32_t>(), n, w, seed, rng::kLat2, w, F, P->assign.as<int32_t>(),
-                P->bins.as<int32_t>(), st);
-    group_by_lattice(P, F, P->assign.as<int32_t>(), P->bins.as<int32_t>(), n, st);
-    S.lattices += (int64_t)F.M.size();
-    for (int M : F.M) (void)rader_for(P, M, st);
-    const int64_t ns = F.total();
-    P->V.ensure(sizeof(double) * G * n);
-    h2d(P->latM, F.M, st);
-    h2d(P->latz, F.z, st);
-    h2d(P->latoff, F.off, st);
-    // V holds the stage's magnitudes in lattice-grouped candidate order (each
-    // lattice's bins contiguous per node); the mask is built in that order and
-    // mapped back to candidate order before compaction.
-    const int64_t words = ceil_div(n, 32);
-    P->mask.ensure(sizeof(uint32_t) * words);
-    P->gmask.ensure(sizeof(uint32_t) * words);
-    USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * words, st));
-    USFFT_HIP(hipMemsetAsync(P->gmask.p, 0, sizeof(uint32_t) * words, st));
-    // the r_t iterations differ only in their tails: their samples are
-    // solved together, in batches of at most kSampleBatchBytes of samples
-    int rb = r_t;
-    while (rb > 1 && ub * (uint64_t)G * (uint64_t)(rb * ns) > kSampleBatchBytes) --rb;
-    for (int i0 = 0; i0 < r_t; i0 += rb) {
-      const int nb = std::min(rb, r_t - i0);
-      const int64_t nsb = nb * ns, ldb = ceil_div(nsb, 64) * 64;
-      P->U.ensure(ub * G * ldb);
-      P->Y.ensure(sizeof(double) * nsb * d);
-      P->iters.ensure(sizeof(int32_t) * nsb);
-      std::vector<double> tails((size_t)nb * d);
-      for (int b = 0; b < nb; ++b)
-        for (int j = 0; j < d; ++j)
-          tails[(size_t)b * d + j] = rng::uniform01(seed, rng::stream(rng::kTail2, t + 1, i0 + b + 1, 0), j);
-      h2d(P->tail, tails, st);
-      for (int b = 0; b < nb; ++b)
-        launch_nodes(d, -1, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(),
-                     P->latz.as<int32_t>(), P->tail.as<double>() + (size_t)b * d, P->Y.as<double>() + b * ns * d,
-                     ns, st);
-      sample_timed(P->Y.as<double>(), nsb, ldb);
-      S.samples_step2 += nsb;
-      for (int b = 0; b < nb; ++b) {
-        int e = tm.open(kTDft);
-        for (size_t l = 0; l < F.M.size(); ++l) {
-          const RaderTables& T = rader_for(P, F.M[l], st);
-          const int32_t* bn = P->lists.as<int32_t>() + n + F.lat_first[l];
-          launch_lattice_dft(T, P->U.p, ufp32, G, ldb, b * ns + F.off[l], bn, nullptr, F.lat_first[l],
-                             F.lat_count[l], USFFT_OUT_MAG2, P->V.p, n, st);
-          S.dft_launches += 1;
-          S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 8.0;
-        }
-        tm.close(kTDft, e);
-        e = tm.open(kTSelect);
-        launch_select(P->V.as<double>(), G, n, n, s_t, P->theta2.as<double>(), par.tie_rel,
-                      P->gmask.as<uint32_t>(), nullptr, st);
-        tm.close(kTSelect, e);
+  if (given) {
+    // a-priori index set (Sec. 4.5): steps 1 and 2 are skipped and step 3
+    // computes the coefficients of the caller's frequencies
+    nprev = given_n;
+    P->Iprev.ensure(sizeof(int32_t) * std::max<int64_t>(1, nprev * d));
+    if (nprev > 0)
+      USFFT_HIP(hipMemcpyAsync(P->Iprev.p, given_I, sizeof(int32_t) * nprev * d, hipMemcpyHostToDevice, st));
+  } else {
+    // ---------------- step 1 & 2a
+    // The d x r line stages are independent: their sampling nodes are
+    // generated into one batch, solved in one sampler launch, then
+    // transformed and selected line by line (the threshold of a relative theta
+    // comes from line (1, 1), which runs first).
+    P->I1.resize(d);
+    P->I1n.assign(d, 0);
+    bool theta_set = !par.theta_relative;
+    {
+      const int r = par.r;
+      std::vector<int32_t> Kt(d), ks;
+      std::vector<int64_t> off(d * r + 1, 0), coff(d + 1, 0), woff(d + 1, 0);
+      int Kmax = 1;
+      for (int t = 0; t < d; ++t) {
+        Kt[t] = pb.k_hi[t] - pb.k_lo[t] + 1;
+        Kmax = std::max(Kmax, Kt[t]);
+        for (int a = 0; a < Kt[t]; ++a) ks.push_back(pb.k_lo[t] + a);
+        coff[t + 1] = coff[t] + Kt[t];
+        woff[t + 1] = woff[t] + ceil_div(Kt[t], 32);
+        for (int i = 0; i < r; ++i) off[t * r + i + 1] = off[t * r + i] + Kt[t];
       }
+      const int64_t ns = off.back(), ld = ceil_div(ns, 64) * 64;
+      h2d(P->cands, ks, st);
+      h2d(P->latM, Kt, st);
+      P->U.ensure(ub * G * ld);
+      P->V.ensure(sizeof(double) * G * Kmax);
+      P->Y.ensure(sizeof(double) * ns * d);
+      P->iters.ensure(sizeof(int32_t) * ns);
+      P->mask.ensure(sizeof(uint32_t) * woff[d]);
+      USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * woff[d], st));
+      std::vector<double> tails((size_t)d * r * d);
+      for (int t = 0; t < d; ++t)
+        for (int i = 0; i < r; ++i)
+          for (int j = 0; j < d; ++j)
+            tails[((size_t)t * r + i) * d + j] = rng::uniform01(seed, rng::stream(rng::kTail1, t + 1, i + 1, 0), j);
+      h2d(P->tail, tails, st);
+      for (int t = 0; t < d; ++t)
+        for (int i = 0; i < r; ++i)
+          launch_nodes(d, t, 1, 1, nullptr, P->latM.as<int32_t>() + t, nullptr,
+                       P->tail.as<double>() + ((size_t)t * r + i) * d, P->Y.as<double>() + off[t * r + i] * d, Kt[t],
+                       st);
+      sample_timed(P->Y.as<double>(), ns, ld);
+      S.samples_step1 += ns;
+      for (int t = 0; t < d; ++t) {
+        const int K = Kt[t];
+        for (int i = 0; i < r; ++i) {
+          int e = tm.open(kTDft);
+          launch_line_dft(P->U.p, ufp32, G, ld, off[t * r + i], K, P->cands.as<int32_t>() + coff[t], K,
+                          USFFT_OUT_MAG2, P->V.p, K, st);
+          tm.close(kTDft, e);
+          S.dft_launches += 1;
+          if (!theta_set) {
+            launch_max_to_theta(P->V.as<double>(), G, K, K, par.theta, P->theta2.as<double>(),
+                                P->scratch.as<uint64_t>(), st);
+            theta_set = true;
+          }
+          e = tm.open(kTSelect);
+          launch_select(P->V.as<double>(), G, K, K, par.s_local, P->theta2.as<double>(), par.tie_rel,
+                        P->mask.as<uint32_t>() + woff[t], nullptr, st);
+          tm.close(kTSelect, e);
+        }
+      }
+      P->scratch.ensure(32 + sizeof(int64_t) * d);
+      for (int t = 0; t < d; ++t) {
+        P->I1[t].ensure(sizeof(int32_t) * Kt[t]);
+        launch_compact(P->cands.as<int32_t>() + coff[t], P->mask.as<uint32_t>() + woff[t], Kt[t], 1,
+                       P->I1[t].as<int32_t>(), reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32) + t, st);
+      }
+      std::vector<int64_t> cnt(d);
+      USFFT_HIP(hipMemcpyAsync(cnt.data(), P->scratch.as<char>() + 32, sizeof(int64_t) * d, hipMemcpyDeviceToHost,
+                               st));
+      check_conv();
+      for (int t = 0; t < d; ++t) P->I1n[t] = cnt[t];
     }
-    launch_ungroup_mask(P->gmask.as<uint32_t>(), P->lists.as<int32_t>(), n, P->mask.as<uint32_t>(), st);
-    P->Jnext.ensure(sizeof(int32_t) * n * w);
-    launch_compact(P->J.as<int32_t>(), P->mask.as<uint32_t>(), n, w, P->Jnext.as<int32_t>(),
-                   reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32), st);
-    int64_t cntI = 0;
-    USFFT_HIP(hipMemcpyAsync(&cntI, P->scratch.as<char>() + 32, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    check_conv();
-    std::swap(P->Iprev, P->Jnext);
-    nprev = cntI;
+    {
+      double th2 = 0;
+      USFFT_HIP(hipMemcpyAsync(&th2, P->theta2.p, sizeof(double), hipMemcpyDeviceToHost, st));
+      USFFT_HIP(hipStreamSynchronize(st));
+      S.theta_abs = std::sqrt(th2);
+    }
+
+    // ---------------- step 2
+    nprev = P->I1n[0];
+    P->Iprev.ensure(sizeof(int32_t) * std::max<int64_t>(nprev, 1));
+    if (nprev > 0)
+      USFFT_HIP(hipMemcpyAsync(P->Iprev.p, P->I1[0].p, sizeof(int32_t) * nprev, hipMemcpyDeviceToDevice, st));
+    for (int t = 1; t < d; ++t) {
+      const bool last = t == d - 1;
+      const int r_t = last ? 1 : par.r;
+      const int s_t = last ? par.s : par.s_local;
+      const int64_t nc = P->I1n[t];
+      const int64_t n = nprev * nc;
+      S.max_candidates = std::max(S.max_candidates, n);
+      if (n == 0) {
+        nprev = 0;
+        continue;
+      }
+      const int w = t + 1;
+      P->J.ensure(sizeof(int32_t) * n * w);
+      launch_product(P->Iprev.as<int32_t>(), nprev, t, P->I1[t].as<int32_t>(), nc, P->J.as<int32_t>(), st);
+      P->assign.ensure(sizeof(int32_t) * n);
+      P->bins.ensure(sizeof(int32_t) * n);
+      plan_family(P, P->J.as<int32_t>(), n, w, seed, rng::kLat2, w, F, P->assign.as<int32_t>(),
+                  P->bins.as<int32_t>(), st);
+      group_by_lattice(P, F, P->assign.as<int32_t>(), P->bins.as<int32_t>(), n, st);
+      S.lattices += (int64_t)F.M.size();
+      for (int M : F.M) (void)rader_for(P, M, st);
+      const int64_t ns = F.total();
+      P->V.ensure(sizeof(double) * G * n);
+      h2d(P->latM, F.M, st);
+      h2d(P->latz, F.z, st);
+      h2d(P->latoff, F.off, st);
+      // V holds the stage's magnitudes in lattice-grouped candidate order (each
+      // lattice's bins contiguous per node); the mask is built in that order and
+      // mapped back to candidate order before compaction.
+      const int64_t words = ceil_div(n, 32);
+      P->mask.ensure(sizeof(uint32_t) * words);
+      P->gmask.ensure(sizeof(uint32_t) * words);
+      USFFT_HIP(hipMemsetAsync(P->mask.p, 0, sizeof(uint32_t) * words, st));
+      USFFT_HIP(hipMemsetAsync(P->gmask.p, 0, sizeof(uint32_t) * words, st));
+      // the r_t iterations differ only in their tails: their samples are
+      // solved together, in batches of at most kSampleBatchBytes of samples
+      int rb = r_t;
+      while (rb > 1 && ub * (uint64_t)G * (uint64_t)(rb * ns) > kSampleBatchBytes) --rb;
+      for (int i0 = 0; i0 < r_t; i0 += rb) {
+        const int nb = std::min(rb, r_t - i0);
+        const int64_t nsb = nb * ns, ldb = ceil_div(nsb, 64) * 64;
+        P->U.ensure(ub * G * ldb);
+        P->Y.ensure(sizeof(double) * nsb * d);
+        P->iters.ensure(sizeof(int32_t) * nsb);
+        std::vector<double> tails((size_t)nb * d);
+        for (int b = 0; b < nb; ++b)
+          for (int j = 0; j < d; ++j)
+            tails[(size_t)b * d + j] = rng::uniform01(seed, rng::stream(rng::kTail2, t + 1, i0 + b + 1, 0), j);
+        h2d(P->tail, tails, st);
+        for (int b = 0; b < nb; ++b)
+          launch_nodes(d, -1, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(),
+                       P->latz.as<int32_t>(), P->tail.as<double>() + (size_t)b * d, P->Y.as<double>() + b * ns * d,
+                       ns, st);
+        sample_timed(P->Y.as<double>(), nsb, ldb);
+        S.samples_step2 += nsb;
+        for (int b = 0; b < nb; ++b) {
+          int e = tm.open(kTDft);
+          for (size_t l = 0; l < F.M.size(); ++l) {
+            const RaderTables& T = rader_for(P, F.M[l], st);
+            const int32_t* bn = P->lists.as<int32_t>() + n + F.lat_first[l];
+            launch_lattice_dft(T, P->U.p, ufp32, G, ldb, b * ns + F.off[l], bn, nullptr, F.lat_first[l],
+                               F.lat_count[l], USFFT_OUT_MAG2, P->V.p, n, st);
+            S.dft_launches += 1;
+            S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 8.0;
+          }
+          tm.close(kTDft, e);
+          e = tm.open(kTSelect);
+          launch_select(P->V.as<double>(), G, n, n, s_t, P->theta2.as<double>(), par.tie_rel,
+                        P->gmask.as<uint32_t>(), nullptr, st);
+          tm.close(kTSelect, e);
+        }
+      }
+      launch_ungroup_mask(P->gmask.as<uint32_t>(), P->lists.as<int32_t>(), n, P->mask.as<uint32_t>(), st);
+      P->Jnext.ensure(sizeof(int32_t) * n * w);
+      launch_compact(P->J.as<int32_t>(), P->mask.as<uint32_t>(), n, w, P->Jnext.as<int32_t>(),
+                     reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32), st);
+      int64_t cntI = 0;
+      USFFT_HIP(hipMemcpyAsync(&cntI, P->scratch.as<char>() + 32, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      check_conv();
+      std::swap(P->Iprev, P->Jnext);
+      nprev = cntI;
+    }
   }
 
   // ---------------- step 3
@@ -845,6 +857,23 @@ usfft_status usfft_detect(usfft_plan_t plan, uint64_t seed, void* stream, usfft_
     std::lock_guard<std::mutex> lk(plan->mu);
     std::unique_ptr<usfft_result_s> R(new usfft_result_s());
     detect(plan, seed, (hipStream_t)stream, R.get());
+    *out = R.release();
+  });
+}
+
+usfft_status usfft_coefficients(usfft_plan_t plan, const int32_t* freqs_host, int64_t n, uint64_t seed,
+                                void* stream, usfft_result_t* out) {
+  return guarded([&] {
+    USFFT_REQUIRE(plan && out && n >= 0 && (n == 0 || freqs_host), USFFT_EINVAL, "bad coefficients arguments");
+    const int d = plan->prob.d;
+    std::vector<std::vector<int32_t>> rows((size_t)n);
+    for (int64_t a = 0; a < n; ++a) rows[a].assign(freqs_host + a * d, freqs_host + (a + 1) * d);
+    std::sort(rows.begin(), rows.end());
+    USFFT_REQUIRE(std::adjacent_find(rows.begin(), rows.end()) == rows.end(), USFFT_EINVAL,
+                  "the frequency set has repeated entries");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    std::unique_ptr<usfft_result_s> R(new usfft_result_s());
+    detect(plan, seed, (hipStream_t)stream, R.get(), true, freqs_host, n);
     *out = R.release();
   });
 }

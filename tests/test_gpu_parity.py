@@ -503,6 +503,47 @@ def test_errors_arguments_are_checked(lib):
     assert e.value.status == lib.EINVAL
 
 
+def test_coefficients_on_a_given_set_trig_poly(lib):
+    # step 3 alone on a shuffled superset of the support (Sec. 4.5): the
+    # caller's order is kept, the polynomial is recovered exactly, and the
+    # values equal the oracle's step 3 on the same set and seed
+    from oracle.usfft import coefficients
+    d, N = 4, 8
+    K, P = W.trig_poly(11, d, N, 70, 31, cmin=1e-2)
+    prob = dict(sampler="poly", d=d, k_lo=[-N] * d, k_hi=[N] * d, poly_k=K, poly_c=P)
+    plan = lib.Plan(prob, W.params(10, 1, 1e-6, relative=False))
+    I = np.unique(np.vstack([K, W.hyperbolic_cross(d, N, [4] * d)]), axis=0)
+    I = I[np.random.default_rng(2).permutation(len(I))]
+    res = lib.coefficients(plan, I, 5)
+    assert res.freqs().tolist() == I.tolist()
+    C_ref, fam, ns = coefficients(TrigPolySampler(K, P), I, 5)
+    C = res.coeffs()
+    assert np.abs(C - C_ref).max() <= 1e-12 * np.abs(C_ref).max()
+    idx = {tuple(k): a for a, k in enumerate(K.tolist())}
+    want = np.array([P[idx[tuple(k)]] if tuple(k) in idx else np.zeros(70) for k in I.tolist()])
+    assert np.abs(C - want).max() <= 1e-12
+    assert res.stats["samples"] == ns and res.stats["lattices"] == len(fam.M)
+    assert lib.coefficients(plan, np.zeros((0, d), dtype=np.int32), 5).n == 0
+    with pytest.raises(lib.UsfftError) as e:
+        lib.coefficients(plan, np.vstack([I, I[:1]]), 5)
+    assert e.value.status == lib.EINVAL
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-10), (1, 1e-6)])
+def test_coefficients_on_a_hyperbolic_cross_pde(lib, prec, tol):
+    # the PDE sampler on the uniform-weight hyperbolic cross of Sec. 4.5,
+    # against the oracle's step 3 with banded-Cholesky solves
+    from oracle.usfft import coefficients
+    prob, par = W.WORKLOADS["cpu16_d4"]
+    I = W.hyperbolic_cross(prob["d"], 16, [4] * prob["d"])
+    plan = lib.Plan(prob, dict(par, precision=prec, pcg_rtol=1e-13 if prec == 0 else 1e-12))
+    res = lib.coefficients(plan, I, 3)
+    C_ref, fam, ns = coefficients(oracle_sampler(prob), I, 3)
+    assert res.freqs().tolist() == I.tolist()
+    assert np.abs(res.coeffs() - C_ref).max() <= tol * np.abs(C_ref).max()
+    assert res.stats["samples"] == ns
+
+
 def test_error_paths(lib):
     prob, par = W.WORKLOADS["cpu16_d4"]
     with pytest.raises(lib.UsfftError) as e:
