@@ -118,6 +118,16 @@ def evaluation_run(U, torch, plan, prob, seed, n_test):
     t_stat = time.perf_counter() - t0
     e2, einf, m = ep.cpu().numpy(), ei.cpu().numpy(), mean[:, 0].cpu().numpy()
     scale = float(abs(m).max())
+    # Sec. 4.5: coefficients on an a-priori set instead of the detected one
+    # (hyperbolic cross with weights 1/j, N = 32), errors on the same points
+    import workloads as W
+    A = W.hyperbolic_cross(d, 32, list(range(1, d + 1)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ra = U.coefficients(plan, A, seed)
+    t_apr = time.perf_counter() - t0
+    U.errors(plan, ra, Y, 2.0, ep, ei)
+    a_e2, a_ei = ep.cpu().numpy(), ei.cpu().numpy()
     return {
         "n_test": n_test, "frequencies": nI,
         "errors_ms": 1e3 * t_err, "test_points_per_s": n_test / t_err,
@@ -126,6 +136,9 @@ def evaluation_run(U, torch, plan, prob, seed, n_test):
         "eval_frac_f64_mfma": flops / t_eval / 1e12 / PEAK_TFLOPS["f64_mfma"],
         "statistics_ms": 1e3 * t_stat,
         "gsi_mean": [float(x) for x in gsi.mean(dim=1).cpu().numpy()[:4]],
+        "a_priori": {"set": "hyperbolic cross, weights 1/j, N = 32", "frequencies": int(len(A)),
+                     "samples": ra.stats["samples"], "coefficients_s": t_apr,
+                     "err2_max_rel": float(a_e2.max()) / scale, "err_inf_max_rel": float(a_ei.max()) / scale},
         "note": "relative to max_g |E(u(x_g, .))|; periodic model, y uniform on [0,1)^d",
     }
 
