@@ -17,6 +17,7 @@ Modules
   dft      naive DFTs (1-D detection, lattice bins)
   select   per-node selection, uniform OR over nodes, set join
   usfft    Alg. 1 driver, trigonometric-polynomial sampler, evaluation
+  fem_mesh P1 elements on a general triangulation, sparse direct solve
   periodization  tent and lognormal maps of the affine / lognormal models
   evaluation     error measures, variance, sensitivity indices and
                  expectation of the approximation (Sec. 4, 4.1)

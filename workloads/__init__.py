@@ -213,3 +213,51 @@ def hyperbolic_cross(d, N, mult):
 def weighted_l1_ball(d, N, mult):
     """{k : sum_j m_j |k_j| <= N}; m_j = j^q."""
     return _enumerate(d, lambda p: sum(mult[j] * abs(v) for j, v in enumerate(p)) <= N)
+
+
+# ---- triangulations of the unit square for the general-mesh sampler ----
+
+def uniform_mesh(n):
+    """The uniform mesh of h = 1/n as a general triangulation: vertex
+    i + (n + 1) j at (i h, j h); each cell split by its (i,j)-(i+1,j+1)
+    diagonal into {(i,j),(i+1,j),(i+1,j+1)} and {(i,j),(i,j+1),(i+1,j+1)}."""
+    h = 1.0 / n
+    j, i = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    xy = np.stack([i.ravel() * h, j.ravel() * h], -1)
+    v = lambda a, b: a + (n + 1) * b  # noqa: E731
+    ci, cj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ci, cj = ci.ravel(), cj.ravel()
+    lower = np.stack([v(ci, cj), v(ci + 1, cj), v(ci + 1, cj + 1)], -1)
+    upper = np.stack([v(ci, cj), v(ci, cj + 1), v(ci + 1, cj + 1)], -1)
+    tri = np.concatenate([lower, upper]).astype(np.int32)
+    bnd = (i.ravel() == 0) | (i.ravel() == n) | (j.ravel() == 0) | (j.ravel() == n)
+    return dict(mesh_xy=xy, mesh_tri=tri, mesh_boundary=bnd.astype(np.uint8))
+
+
+def jittered_mesh(n_bnd, n_in, seed, jitter=0.3):
+    """Delaunay triangulation of [0,1]^2 with n_bnd equispaced vertices per
+    side (4 n_bnd boundary vertices) and an n_in x n_in grid of interior
+    vertices, each moved by up to `jitter` of the grid spacing."""
+    from scipy.spatial import Delaunay
+    g = np.random.default_rng(seed)
+    s = np.arange(n_bnd) / n_bnd
+    z, o = np.zeros(n_bnd), np.ones(n_bnd)
+    bpts = np.concatenate([np.stack([s, z], -1), np.stack([o, s], -1), np.stack([1 - s, o], -1),
+                           np.stack([z, 1 - s], -1)])
+    h = 1.0 / (n_in + 1)
+    gi, gj = np.meshgrid(np.arange(1, n_in + 1), np.arange(1, n_in + 1), indexing="ij")
+    ipts = np.stack([gi.ravel() * h, gj.ravel() * h], -1) + g.uniform(-jitter * h, jitter * h, (n_in * n_in, 2))
+    xy = np.concatenate([bpts, ipts])
+    tri = Delaunay(xy).simplices.astype(np.int32)
+    P = xy[tri]
+    det = (P[:, 1, 0] - P[:, 0, 0]) * (P[:, 2, 1] - P[:, 0, 1]) - (P[:, 1, 1] - P[:, 0, 1]) * (P[:, 2, 0] - P[:, 0, 0])
+    tri = tri[np.abs(det) > 1e-14]
+    bnd = np.concatenate([np.ones(len(bpts)), np.zeros(len(ipts))]).astype(np.uint8)
+    return dict(mesh_xy=xy, mesh_tri=tri, mesh_boundary=bnd)
+
+
+def mesh_problem(mesh, d, N, a0=1.0, modes="split"):
+    """The periodic coefficient family of pde_problem on a general triangulation."""
+    m1, m2 = (modes_diagonal if modes == "diagonal" else modes_split)(d)
+    return dict(sampler="pde_mesh", d=d, k_lo=[-N] * d, k_hi=[N] * d, a0=a0, amp=amplitudes(d),
+                mode1=m1, mode2=m2, **mesh)
