@@ -40,7 +40,7 @@ typedef enum {
   USFFT_ELATTICE = -5   /* no lattice family within lattice_max attempts    */
 } usfft_status;
 
-enum { USFFT_SAMPLER_PDE = 0, USFFT_SAMPLER_TRIG_POLY = 1 };
+enum { USFFT_SAMPLER_PDE = 0, USFFT_SAMPLER_TRIG_POLY = 1, USFFT_SAMPLER_PDE_MESH = 2 };
 enum { USFFT_FP64 = 0, USFFT_FP32_REFINE = 1 };
 enum { USFFT_OUT_MAG2 = 0, USFFT_OUT_COMPLEX = 1 };
 enum { USFFT_PRECOND_DST = 0, USFFT_PRECOND_JACOBI = 1 };
@@ -73,6 +73,13 @@ typedef struct usfft_server_s* usfft_server_t;
  *  P1 elements on the uniform mesh h = 1/mesh_n, every cell split along its
  *  (i,j)-(i+1,j+1) diagonal, a evaluated at triangle centroids; T_G = the
  *  G = (mesh_n-1)^2 interior nodes, g = (j-1)(mesh_n-1) + (i-1).
+ *  PDE_MESH sampler: the same equation and coefficient family (amp, mode1,
+ *  mode2, a0, model, basis) on a general triangulation of the unit square
+ *  (the discretisation of the paper's Sec. 4): mesh_nv vertices mesh_xy
+ *  (nv x 2), mesh_nt triangles mesh_tri (nt x 3 vertex indices), mesh_boundary
+ *  (nv bytes, nonzero = Dirichlet vertex).  T_G = the other vertices in vertex
+ *  order; a at triangle centroids; float64 Jacobi-PCG per sample.  Limits:
+ *  G <= 2048 inner vertices and 8 (nt + nnz + G) <= 150 KB (EINVAL beyond).
  *  TRIG_POLY sampler (test functions of Theorem 1.1):
  *     u_g(y) = Re sum_{a<n_poly} c[a,g] exp(2 pi i poly_k[a].y),
  *  poly_c is n_poly x G x 2 doubles (re, im). */
@@ -100,6 +107,11 @@ typedef struct {
                             the largest admissible lattice: no lattice or
                             line node falls on a pole of the map)            */
   int32_t basis1, basis2;/* 0: sin, 1: cos along x1 / x2                     */
+  /* PDE_MESH (the PDE fields above give the coefficient; mesh_n unused)     */
+  int32_t mesh_nv, mesh_nt;
+  const double* mesh_xy;          /* nv x 2                                  */
+  const int32_t* mesh_tri;        /* nt x 3, vertex indices                  */
+  const uint8_t* mesh_boundary;   /* nv, nonzero: boundary (u = 0) vertex    */
 } usfft_problem;
 
 /* Parameters of Alg. 1 ("Input": s, s_local, Algorithm A, theta, r) and of

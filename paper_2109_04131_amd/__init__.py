@@ -19,7 +19,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ELATTICE = 0, -1, -2, -3, -4, -5
-SAMPLER_PDE, SAMPLER_TRIG_POLY = 0, 1
+SAMPLER_PDE, SAMPLER_TRIG_POLY, SAMPLER_PDE_MESH = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
 OUT_MAG2, OUT_COMPLEX = 0, 1
 PRECOND_DST, PRECOND_JACOBI = 0, 1
@@ -35,7 +35,9 @@ class _Problem(C.Structure):
                 ("mesh_n", C.c_int32), ("a0", C.c_double), ("amp", _PD), ("mode1", _P32), ("mode2", _P32),
                 ("G_poly", C.c_int64), ("n_poly", C.c_int64), ("poly_k", _P32), ("poly_c", _PD),
                 ("model", C.c_int32), ("alpha", C.c_double), ("beta", C.c_double), ("delta", C.c_double),
-                ("basis1", C.c_int32), ("basis2", C.c_int32)]
+                ("basis1", C.c_int32), ("basis2", C.c_int32),
+                ("mesh_nv", C.c_int32), ("mesh_nt", C.c_int32), ("mesh_xy", _PD), ("mesh_tri", _P32),
+                ("mesh_boundary", C.POINTER(C.c_uint8))]
 
 
 class _Params(C.Structure):
@@ -161,9 +163,21 @@ def _marshal(problem, params):
     pr.d = int(problem["d"])
     pr.k_lo = arr(problem["k_lo"], np.int32)
     pr.k_hi = arr(problem["k_hi"], np.int32)
-    if problem.get("sampler", "pde") == "pde":
-        pr.sampler = SAMPLER_PDE
-        pr.mesh_n = int(problem["mesh_n"])
+    kind = problem.get("sampler", "pde")
+    if kind in ("pde", "pde_mesh"):
+        if kind == "pde":
+            pr.sampler = SAMPLER_PDE
+            pr.mesh_n = int(problem["mesh_n"])
+        else:
+            pr.sampler = SAMPLER_PDE_MESH
+            xy = np.ascontiguousarray(np.asarray(problem["mesh_xy"], dtype=np.float64))
+            tri = np.ascontiguousarray(np.asarray(problem["mesh_tri"], dtype=np.int32))
+            bnd = np.ascontiguousarray(np.asarray(problem["mesh_boundary"], dtype=np.uint8))
+            keep.extend([xy, tri, bnd])
+            pr.mesh_nv, pr.mesh_nt = len(xy), len(tri)
+            pr.mesh_xy = xy.ctypes.data_as(_PD)
+            pr.mesh_tri = tri.ctypes.data_as(_P32)
+            pr.mesh_boundary = bnd.ctypes.data_as(C.POINTER(C.c_uint8))
         pr.a0 = float(problem.get("a0", 1.0))
         pr.amp = arr(problem["amp"], np.float64)
         pr.mode1 = arr(problem["mode1"], np.int32)

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libusfft.so")
-SOURCES = ["sampler.hip", "pcgdst.hip", "fft.hip", "select.hip", "sets.hip", "eval.hip", "usfft.hip"]
+SOURCES = ["sampler.hip", "pcgdst.hip", "pcgmesh.hip", "fft.hip", "select.hip", "sets.hip", "eval.hip", "usfft.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -21,6 +21,27 @@ struct PdeDev {
   int raw = 0;        // 1: the solver inputs are parameters y, not sampling nodes t
 };
 
+// General triangulation (pcgmesh.hip): CSR pattern of the inner vertices,
+// per-entry (triangle, weight) contributions, load, basis at the centroids.
+constexpr int kMaxMeshRows = 2048;          // inner vertices the solver holds
+constexpr int64_t kMaxMeshLds = 150 << 10;  // LDS of coefficients, values, direction
+struct MeshDev {
+  int G, nt, nnz;
+  const int* rowptr;  // G + 1
+  const int* col;     // nnz
+  const int* diag;    // G: CSR position of each diagonal entry
+  const int* cptr;    // nnz + 1
+  const int* ctri;    // contributions: triangle
+  const double* cw;   // contributions: |T| grad(phi_a) . grad(phi_b)
+  const double* load; // G: sum |T| / 3
+  const double* psi;  // d x nt: basis of term k at the centroid of T
+};
+int64_t mesh_lds_bytes(const MeshDev& M);
+int mesh_persistent_blocks(const MeshDev& M);
+void launch_pde_solve_mesh(const PdeDev& P, const MeshDev& M, const double* Y, int64_t ns, double rtol, int maxit,
+                           void* out, int out_fp32, int64_t ld, int64_t col0, int* iters, int blocks,
+                           hipStream_t st);
+
 // ---- sampler.hip
 void launch_nodes(int d, int line, int t, int nlat, const int64_t* off, const int32_t* Ms, const int32_t* zs,
                   const double* tail, double* Y, int64_t ns, hipStream_t st);

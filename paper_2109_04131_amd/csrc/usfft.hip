@@ -117,6 +117,10 @@ struct usfft_plan_s {
   int solver_cfg = 0;
   // static device tables
   usfft::DevBuf d_amp, d_tab, d_polyk, d_polyc, d_stream, d_wscr, d_sfrag, d_lam;
+  // general triangulation
+  usfft::DevBuf m_rowptr, m_col, m_diag, m_cptr, m_ctri, m_cw, m_load, m_psi;
+  usfft::MeshDev mesh{};
+  int mesh_blocks = 0;
   int wblocks = 0;  // persistent workgroups of the float32 / DST solver
   bool streaming = false;  // mesh larger than the on-chip solvers hold
   bool dst = false;        // DST-preconditioned solver
@@ -260,7 +264,10 @@ static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
   const usfft_params& par = P->par;
   PdeDev pde = P->pde;
   pde.raw = params ? 1 : 0;
-  if (P->prob.sampler == USFFT_SAMPLER_PDE && P->dst) {
+  if (P->prob.sampler == USFFT_SAMPLER_PDE_MESH) {
+    launch_pde_solve_mesh(pde, P->mesh, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
+                          P->mesh_blocks, st);
+  } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->dst) {
     launch_pde_solve_dst(pde, par.precision, P->dst_variant, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
                          par.refine_every, U, out_fp32, ld, col0, iters, P->d_wscr.as<double>(), P->wblocks,
                          P->d_sfrag.p, P->d_lam.as<float>(), st);
@@ -556,7 +563,7 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
   // ---------------- step 3
   const int64_t nI = nprev;
   R->d = d;
-  if (pb.sampler == USFFT_SAMPLER_PDE) {
+  if (pb.sampler != USFFT_SAMPLER_TRIG_POLY) {
     R->model = P->pde.model;
     R->alpha = P->pde.alpha;
     R->beta = P->pde.beta;
@@ -614,6 +621,9 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     S.solver_kind = 1;
   } else if (pb.sampler == USFFT_SAMPLER_PDE) {
     S.solver_kind = 2;
+  } else if (pb.sampler == USFFT_SAMPLER_PDE_MESH) {
+    S.solver_block = 256;
+    S.solver_kind = 3;
   }
   S.ms_sample = tm.total(kTSample);
   S.ms_dft = tm.total(kTDft);
@@ -694,8 +704,12 @@ static void validate(const usfft_problem* pb, const usfft_params* par) {
                 USFFT_EINVAL, "bad solver parameters");
   USFFT_REQUIRE(par->precond == USFFT_PRECOND_DST || par->precond == USFFT_PRECOND_JACOBI, USFFT_EINVAL,
                 "bad preconditioner");
-  if (pb->sampler == USFFT_SAMPLER_PDE) {
-    USFFT_REQUIRE(pb->mesh_n >= 4 && pb->mesh_n <= kMaxMeshStream, USFFT_EINVAL, "mesh_n must be in [4, 512]");
+  if (pb->sampler == USFFT_SAMPLER_PDE || pb->sampler == USFFT_SAMPLER_PDE_MESH) {
+    if (pb->sampler == USFFT_SAMPLER_PDE)
+      USFFT_REQUIRE(pb->mesh_n >= 4 && pb->mesh_n <= kMaxMeshStream, USFFT_EINVAL, "mesh_n must be in [4, 512]");
+    else
+      USFFT_REQUIRE(pb->mesh_nv >= 3 && pb->mesh_nt >= 1 && pb->mesh_xy && pb->mesh_tri && pb->mesh_boundary,
+                    USFFT_EINVAL, "bad triangulation");
     USFFT_REQUIRE(pb->amp && pb->mode1 && pb->mode2, USFFT_EINVAL, "missing coefficient family");
     USFFT_REQUIRE(pb->model >= USFFT_MODEL_PERIODIC && pb->model <= USFFT_MODEL_LOGNORMAL, USFFT_EINVAL,
                   "unknown coefficient model");
@@ -710,6 +724,148 @@ static void validate(const usfft_problem* pb, const usfft_params* par) {
     USFFT_REQUIRE(pb->G_poly >= 1 && pb->n_poly >= 1 && pb->poly_k && pb->poly_c, USFFT_EINVAL,
                   "bad trigonometric polynomial");
   }
+}
+
+// Host preparation of a general triangulation: inner-vertex numbering,
+// element geometry, the CSR pattern of inner couplings with the (triangle,
+// weight) contributions of every entry (triangles in order, vertex pairs in
+// order), the load for f = 1 and the basis of every term at the centroids.
+static void build_mesh(usfft_plan_s* P, const usfft_problem* pb, const usfft_params* par) {
+  const int d = pb->d, nv = pb->mesh_nv, nt = pb->mesh_nt;
+  P->amp.assign(pb->amp, pb->amp + d);
+  P->mode1.assign(pb->mode1, pb->mode1 + d);
+  P->mode2.assign(pb->mode2, pb->mode2 + d);
+  P->prob.amp = P->amp.data();
+  P->prob.mode1 = P->mode1.data();
+  P->prob.mode2 = P->mode2.data();
+  P->prob.mesh_xy = nullptr;
+  P->prob.mesh_tri = nullptr;
+  P->prob.mesh_boundary = nullptr;
+  std::vector<int> gid(nv, -1);
+  int G = 0;
+  for (int v = 0; v < nv; ++v)
+    if (!pb->mesh_boundary[v]) gid[v] = G++;
+  USFFT_REQUIRE(G >= 1 && G <= kMaxMeshRows, USFFT_EINVAL, "the mesh needs 1..2048 inner vertices");
+  std::vector<double> kgeo((size_t)nt * 9), area(nt), cx(nt), cy(nt);
+  for (int t = 0; t < nt; ++t) {
+    int v[3];
+    for (int a = 0; a < 3; ++a) {
+      v[a] = pb->mesh_tri[3 * t + a];
+      USFFT_REQUIRE(v[a] >= 0 && v[a] < nv, USFFT_EINVAL, "triangle vertex out of range");
+    }
+    const double x0 = pb->mesh_xy[2 * v[0]], y0 = pb->mesh_xy[2 * v[0] + 1];
+    const double e1x = pb->mesh_xy[2 * v[1]] - x0, e1y = pb->mesh_xy[2 * v[1] + 1] - y0;
+    const double e2x = pb->mesh_xy[2 * v[2]] - x0, e2y = pb->mesh_xy[2 * v[2] + 1] - y0;
+    const double det = e1x * e2y - e1y * e2x;
+    USFFT_REQUIRE(std::fabs(det) > 0.0, USFFT_EINVAL, "degenerate triangle");
+    area[t] = 0.5 * std::fabs(det);
+    // gradients of the barycentric functions (rows of the inverse Jacobian)
+    const double g[3][2] = {{-(e2y - e1y) / det, -(e1x - e2x) / det}, {e2y / det, -e2x / det},
+                            {-e1y / det, e1x / det}};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) kgeo[(size_t)t * 9 + a * 3 + b] = area[t] * (g[a][0] * g[b][0] + g[a][1] * g[b][1]);
+    cx[t] = (x0 + pb->mesh_xy[2 * v[1]] + pb->mesh_xy[2 * v[2]]) / 3.0;
+    cy[t] = (y0 + pb->mesh_xy[2 * v[1] + 1] + pb->mesh_xy[2 * v[2] + 1]) / 3.0;
+  }
+  // CSR pattern
+  std::vector<std::vector<int>> adj(G);
+  for (int t = 0; t < nt; ++t)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const int ga = gid[pb->mesh_tri[3 * t + a]], gb = gid[pb->mesh_tri[3 * t + b]];
+        if (ga >= 0 && gb >= 0) adj[ga].push_back(gb);
+      }
+  std::vector<int> rowptr(G + 1, 0), col, diag(G);
+  for (int i = 0; i < G; ++i) {
+    std::sort(adj[i].begin(), adj[i].end());
+    adj[i].erase(std::unique(adj[i].begin(), adj[i].end()), adj[i].end());
+    rowptr[i + 1] = rowptr[i] + (int)adj[i].size();
+    for (int j : adj[i]) {
+      if (j == i) diag[i] = (int)col.size();
+      col.push_back(j);
+    }
+  }
+  const int nnz = (int)col.size();
+  auto entry = [&](int i, int j) {
+    return (int)(std::lower_bound(col.begin() + rowptr[i], col.begin() + rowptr[i + 1], j) - col.begin());
+  };
+  std::vector<int> cnt(nnz + 1, 0);
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    std::vector<int> ctri(pass ? cnt[nnz] : 0);
+    std::vector<double> cw(pass ? cnt[nnz] : 0);
+    for (int t = 0; t < nt; ++t)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const int ga = gid[pb->mesh_tri[3 * t + a]], gb = gid[pb->mesh_tri[3 * t + b]];
+          if (ga < 0 || gb < 0) continue;
+          const int e = entry(ga, gb);
+          if (!pass) {
+            ++cnt[e + 1];
+          } else {
+            ctri[fill[e]] = t;
+            cw[fill[e]++] = kgeo[(size_t)t * 9 + a * 3 + b];
+          }
+        }
+    if (!pass) {
+      for (int e = 0; e < nnz; ++e) cnt[e + 1] += cnt[e];
+    } else {
+      P->m_cptr.ensure(sizeof(int) * cnt.size());
+      P->m_ctri.ensure(sizeof(int) * ctri.size());
+      P->m_cw.ensure(sizeof(double) * cw.size());
+      USFFT_HIP(hipMemcpy(P->m_cptr.p, cnt.data(), sizeof(int) * cnt.size(), hipMemcpyHostToDevice));
+      USFFT_HIP(hipMemcpy(P->m_ctri.p, ctri.data(), sizeof(int) * ctri.size(), hipMemcpyHostToDevice));
+      USFFT_HIP(hipMemcpy(P->m_cw.p, cw.data(), sizeof(double) * cw.size(), hipMemcpyHostToDevice));
+    }
+  }
+  std::vector<double> load(G, 0.0);
+  for (int t = 0; t < nt; ++t)
+    for (int a = 0; a < 3; ++a) {
+      const int ga = gid[pb->mesh_tri[3 * t + a]];
+      if (ga >= 0) load[ga] += area[t] / 3.0;
+    }
+  std::vector<double> psi((size_t)d * nt);
+  auto b1 = [&](double v) { return pb->basis1 == 1 ? std::cos(v) : std::sin(v); };
+  auto b2 = [&](double v) { return pb->basis2 == 1 ? std::cos(v) : std::sin(v); };
+  for (int k = 0; k < d; ++k)
+    for (int t = 0; t < nt; ++t)
+      psi[(size_t)k * nt + t] = b1(P->mode1[k] * M_PI * cx[t]) * b2(P->mode2[k] * M_PI * cy[t]);
+  auto up = [&](usfft::DevBuf& B, const void* src, size_t bytes) {
+    B.ensure(std::max<size_t>(bytes, 8));
+    USFFT_HIP(hipMemcpy(B.p, src, bytes, hipMemcpyHostToDevice));
+  };
+  up(P->m_rowptr, rowptr.data(), sizeof(int) * rowptr.size());
+  up(P->m_col, col.data(), sizeof(int) * col.size());
+  up(P->m_diag, diag.data(), sizeof(int) * diag.size());
+  up(P->m_load, load.data(), sizeof(double) * load.size());
+  up(P->m_psi, psi.data(), sizeof(double) * psi.size());
+  up(P->d_amp, P->amp.data(), sizeof(double) * d);
+  P->G = G;
+  MeshDev& M = P->mesh;
+  M.G = G;
+  M.nt = nt;
+  M.nnz = nnz;
+  M.rowptr = P->m_rowptr.as<int>();
+  M.col = P->m_col.as<int>();
+  M.diag = P->m_diag.as<int>();
+  M.cptr = P->m_cptr.as<int>();
+  M.ctri = P->m_ctri.as<int>();
+  M.cw = P->m_cw.as<double>();
+  M.load = P->m_load.as<double>();
+  M.psi = P->m_psi.as<double>();
+  USFFT_REQUIRE(mesh_lds_bytes(M) <= kMaxMeshLds, USFFT_EINVAL,
+                "mesh too large for the general-mesh solver (8 (nt + nnz + G) > 150 KB)");
+  P->mesh_blocks = mesh_persistent_blocks(M);
+  P->pde.n = 0;
+  P->pde.d = d;
+  P->pde.a0 = pb->a0;
+  P->pde.h2 = 0.0;
+  P->pde.amp = P->d_amp.as<double>();
+  P->pde.tab = nullptr;
+  P->pde.model = pb->model;
+  P->pde.alpha = pb->alpha;
+  P->pde.beta = pb->beta;
+  P->pde.delta = pb->delta > 0 ? pb->delta : 1.0 / (4.0 * par->lattice_mmax);
 }
 
 static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* par) {
@@ -800,6 +956,8 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
       P->wblocks = persistent_blocks(P->solver_cfg, n);
       P->d_wscr.ensure(sizeof(double) * (size_t)edge_scratch_doubles(n, P->wblocks));
     }
+  } else if (pb->sampler == USFFT_SAMPLER_PDE_MESH) {
+    build_mesh(P.get(), pb, par);
   } else {
     P->G = pb->G_poly;
     P->poly_k.assign(pb->poly_k, pb->poly_k + (size_t)pb->n_poly * d);
@@ -1145,8 +1303,9 @@ namespace usfft {
 struct JobSpec {
   usfft_problem prob{};
   usfft_params par{};
-  std::vector<int32_t> k_lo, k_hi, mode1, mode2, poly_k;
-  std::vector<double> amp, poly_c;
+  std::vector<int32_t> k_lo, k_hi, mode1, mode2, poly_k, mesh_tri;
+  std::vector<double> amp, poly_c, mesh_xy;
+  std::vector<uint8_t> mesh_boundary;
   void copy(const usfft_problem* pb, const usfft_params* pa) {
     validate(pb, pa);
     prob = *pb;
@@ -1156,13 +1315,21 @@ struct JobSpec {
     k_hi.assign(pb->k_hi, pb->k_hi + d);
     prob.k_lo = k_lo.data();
     prob.k_hi = k_hi.data();
-    if (pb->sampler == USFFT_SAMPLER_PDE) {
+    if (pb->sampler != USFFT_SAMPLER_TRIG_POLY) {
       amp.assign(pb->amp, pb->amp + d);
       mode1.assign(pb->mode1, pb->mode1 + d);
       mode2.assign(pb->mode2, pb->mode2 + d);
       prob.amp = amp.data();
       prob.mode1 = mode1.data();
       prob.mode2 = mode2.data();
+      if (pb->sampler == USFFT_SAMPLER_PDE_MESH) {
+        mesh_xy.assign(pb->mesh_xy, pb->mesh_xy + 2 * (size_t)pb->mesh_nv);
+        mesh_tri.assign(pb->mesh_tri, pb->mesh_tri + 3 * (size_t)pb->mesh_nt);
+        mesh_boundary.assign(pb->mesh_boundary, pb->mesh_boundary + pb->mesh_nv);
+        prob.mesh_xy = mesh_xy.data();
+        prob.mesh_tri = mesh_tri.data();
+        prob.mesh_boundary = mesh_boundary.data();
+      }
     } else {
       poly_k.assign(pb->poly_k, pb->poly_k + (size_t)pb->n_poly * d);
       poly_c.assign(pb->poly_c, pb->poly_c + (size_t)pb->n_poly * pb->G_poly * 2);
@@ -1178,8 +1345,12 @@ struct JobSpec {
 // sets grow to a few times s, Remark 4.1) times min(K_t, 17) (1-D projections
 // stay small, Sec. 4.2); a lattice family takes about 12 |J| samples.
 static uint64_t estimate_footprint(const usfft_problem* pb, const usfft_params* pa) {
-  const uint64_t G = pb->sampler == USFFT_SAMPLER_PDE ? (uint64_t)(pb->mesh_n - 1) * (pb->mesh_n - 1)
-                                                      : (uint64_t)pb->G_poly;
+  uint64_t G = pb->sampler == USFFT_SAMPLER_PDE ? (uint64_t)(pb->mesh_n - 1) * (pb->mesh_n - 1)
+                                                : (uint64_t)pb->G_poly;
+  if (pb->sampler == USFFT_SAMPLER_PDE_MESH) {
+    G = 0;
+    for (int v = 0; v < pb->mesh_nv; ++v) G += pb->mesh_boundary[v] ? 0 : 1;
+  }
   const uint64_t ub = pa->precision == USFFT_FP32_REFINE ? 4 : 8;
   int kmax = 1;
   for (int j = 0; j < pb->d; ++j) kmax = std::max(kmax, pb->k_hi[j] - pb->k_lo[j] + 1);

@@ -544,6 +544,95 @@ def test_coefficients_on_a_hyperbolic_cross_pde(lib, prec, tol):
     assert res.stats["samples"] == ns
 
 
+# ------------------------------------------------------------------ general triangulations
+def mesh_sampler(prob, delta=0.0):
+    from oracle import fem_mesh
+    return fem_mesh.MeshSampler(prob["mesh_xy"], prob["mesh_tri"], prob["mesh_boundary"], prob["a0"], prob["amp"],
+                                prob["mode1"], prob["mode2"], model=prob.get("model", 0),
+                                alpha=prob.get("alpha", -1.0), beta=prob.get("beta", 1.0), delta=delta,
+                                basis=(prob.get("basis1", 0), prob.get("basis2", 0)))
+
+
+@pytest.mark.parametrize("mesh,d,model,prec", [((10, 11, 1), 4, 0, 0), ((10, 11, 2), 4, 1, 1), ((10, 11, 3), 4, 2, 0),
+                                               ((26, 27, 1), 10, 0, 0), ((26, 27, 1), 10, 0, 1)])
+def test_mesh_solves_match_sparse_direct(lib, mesh, d, model, prec):
+    # jittered Delaunay meshes (121 and 729 inner vertices, the latter shaped
+    # like the paper's mesh) against the oracle's sparse direct solves; the
+    # mesh sampler solves in float64 in both precisions
+    from oracle import periodization as OP
+    prob = dict(W.mesh_problem(W.jittered_mesh(*mesh), d, 8), model=model)
+    if model == 2:
+        prob = dict(prob, a0=0.5, basis2=1)
+    delta = OP.delta_opt(9601)
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=prec, pcg_rtol=1e-13))
+    S = mesh_sampler(prob, delta)
+    assert plan.G == S.G
+    ns = 23
+    Y = np.random.default_rng(mesh[2] + d).random((ns, d))
+    U = torch.zeros((S.G, ns), dtype=torch.float64, device="cuda")
+    it = torch.zeros(ns, dtype=torch.int32, device="cuda")
+    lib.sample(plan, dev(Y), U, 0, ns, 0, it)
+    assert (host(it) > 0).all()
+    Ug = host(U).T
+    for s_ in range(0, ns, 5):
+        ref = S.solve_one(Y[s_])
+        assert np.linalg.norm(Ug[s_] - ref) <= 1e-11 * np.linalg.norm(ref), s_
+    # a sample's result does not depend on the batch it is solved in
+    U1 = torch.zeros((S.G, 1), dtype=torch.float64, device="cuda")
+    lib.sample(plan, dev(Y[7:8]), U1, 0, 1)
+    assert np.array_equal(host(U1)[:, 0], Ug[7])
+
+
+def test_uniform_mesh_through_the_mesh_sampler(lib):
+    # the uniform mesh written as a triangulation gives the structured
+    # solvers' samples
+    n, d = 16, 4
+    base = W.pde_problem(n, d, 8)
+    prob = dict(W.mesh_problem(W.uniform_mesh(n), d, 8), amp=base["amp"], mode1=base["mode1"], mode2=base["mode2"])
+    Y = np.random.default_rng(4).random((9, d))
+    outs = []
+    for pr in (base, prob):
+        plan = lib.Plan(pr, dict(W.params(10, 1, 1e-4), pcg_rtol=1e-13))
+        U = torch.zeros((plan.G, 9), dtype=torch.float64, device="cuda")
+        lib.sample(plan, dev(Y), U, 0, 9)
+        outs.append(host(U))
+    assert np.abs(outs[0] - outs[1]).max() <= 1e-11 * np.abs(outs[0]).max()
+
+
+def test_detect_on_a_mesh_cpu_scale(lib):
+    # whole job with the mesh sampler: the oracle's sets and coefficients;
+    # evaluation and error measures work on the result
+    from oracle import evaluation as oev
+    prob = W.mesh_problem(W.jittered_mesh(10, 11, 5), 4, 8)
+    par = W.params(30, 2, 1e-4)
+    res, ref = run_both(lib, prob, par, 3, sampler=mesh_sampler(prob))
+    assert res.freqs().tolist() == ref.I.tolist()
+    assert np.abs(res.coeffs() - ref.C).max() <= 1e-10 * np.abs(ref.C).max()
+    assert res.stats["solver_kind"] == 3
+    Y = np.random.default_rng(6).random((40, 4))
+    ep = torch.zeros(res.G, dtype=torch.float64, device="cuda")
+    ei = torch.zeros(res.G, dtype=torch.float64, device="cuda")
+    lib.errors(res.plan, res, dev(Y), 2.0, ep, ei)
+    S = mesh_sampler(prob)
+    e_ref, i_ref = oev.errors(np.array([S.solve_param(y) for y in Y]), oev.approximation(ref.I, ref.C, Y), 2.0)
+    assert np.abs(host(ep) - e_ref).max() <= 1e-9 * np.abs(ref.C).max() + 1e-6 * e_ref.max()
+
+
+def test_mesh_problems_are_checked(lib):
+    m = W.jittered_mesh(6, 7, 1)
+    par = W.params(10, 1, 1e-4)
+    bad_tri = m["mesh_tri"].copy()
+    bad_tri[0, 1] = bad_tri[0, 0]  # degenerate triangle
+    bad_idx = m["mesh_tri"].copy()
+    bad_idx[3, 2] = len(m["mesh_xy"])  # vertex out of range
+    big = W.jittered_mesh(50, 46, 1)  # 2116 inner vertices
+    for mesh in (dict(m, mesh_tri=bad_tri), dict(m, mesh_tri=bad_idx), big,
+                 dict(m, mesh_boundary=np.ones(len(m["mesh_xy"]), dtype=np.uint8))):
+        with pytest.raises(lib.UsfftError) as e:
+            lib.Plan(W.mesh_problem(mesh, 4, 8), par)
+        assert e.value.status == lib.EINVAL
+
+
 def test_error_paths(lib):
     prob, par = W.WORKLOADS["cpu16_d4"]
     with pytest.raises(lib.UsfftError) as e:
