@@ -204,6 +204,8 @@ def main():
                     help="also time one job each of the affine and lognormal models (0 = skip)")
     ap.add_argument("--eval-points", type=int, default=100000,
                     help="test parameters of the error measures of one job's result (0 = skip)")
+    ap.add_argument("--mesh", type=int, default=1,
+                    help="also time one job on an unstructured mesh shaped like the paper's (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof byte counters)")
     args = ap.parse_args()
@@ -308,6 +310,22 @@ def main():
                 mplan.close()
             except U.UsfftError as e:
                 res["models"][name] = {"error": str(e), "theta_rel": th}
+    if args.mesh:
+        # general-triangulation sampler on a jittered Delaunay mesh of the unit
+        # square shaped like the paper's (Sec. 4: 737 inner / 104 boundary
+        # nodes, maximal edge 0.075): 729 inner / 104 boundary vertices,
+        # maximal edge 0.067; same d, box, sparsity and threshold
+        mprob = W.mesh_problem(W.jittered_mesh(26, 27, 1), prob["d"], 32)
+        mplan = U.Plan(mprob, dict(par, precision=U.FP64, pcg_rtol=1e-12))
+        wall, lat, st, nI_m = run_path(U, mplan, args.seed, 1, 1)
+        sm = sum(x["samples"] for x in st)
+        res["mesh"] = {"workload": "jittered Delaunay mesh, 729 inner + 104 boundary vertices, 1560 triangles, "
+                                   "d=10, box [-32,32]^10, s=200, rel. threshold 1e-5, float64 Jacobi-PCG",
+                       "samples_per_s": sm / wall, "job_s": wall, "samples": sm,
+                       "pcg_iters_per_solve": sum(x["pcg_iterations"] for x in st) / max(1, sm),
+                       "solver_ms_per_launch": sum(x["ms_sample"] for x in st) / max(1, sum(x["sample_launches"] for x in st)),
+                       "detected_frequencies": nI_m}
+        mplan.close()
     if args.serving_jobs > 0:
         res["serving"] = serving_run(U, args.serving_jobs, 4.0, args.seed, 4)
     if args.cpu_seconds > 0:
