@@ -11,14 +11,18 @@
 // weight) pairs that add up to it, so a sample's matrix is a gather over
 // triangle coefficients with no atomics, in a fixed order.
 //
-// One persistent workgroup of 256 threads per sample: triangle coefficients,
-// matrix values and the search direction live in LDS; thread t owns rows
-// t, t + 256, ... (up to RMAX of them) with their iterate, residual and
-// direction in registers.  Float64 conjugate gradients with the Jacobi
-// preconditioner, stopped on the scaled residual
-//     r . D^-1 r <= rtol^2 b . D^-1 b   (D = diag(A)),
-// which CG forms anyway.  The sample of inner vertex g is written to
-// out[g * ld + col0 + s], the layout of the uniform-mesh solvers.
+// One persistent workgroup of 256 threads per sample: the matrix values and
+// one vector live in LDS (the vector overlays the triangle coefficients,
+// which are dead once the matrix is assembled); thread t owns rows t,
+// t + 256, ... (up to RMAX of them) with their iterate, residual and
+// directions in registers.  Float64 conjugate gradients with the Jacobi
+// preconditioner in the Chronopoulos-Gear arrangement: per iteration one
+// product w = A u of the preconditioned residual u = D^-1 r and one fused
+// block reduction of (r.u, w.u); the direction's product s = A p follows
+// by recursion, s = w + beta s.  Two barriers per iteration.  Stopped on
+// the scaled residual  r . D^-1 r <= rtol^2 b . D^-1 b  (D = diag(A)).  The
+// sample of inner vertex g is written to out[g * ld + col0 + s], the layout
+// of the uniform-mesh solvers.
 #include "kernels.h"
 #include "pde_device.h"
 
@@ -26,7 +30,7 @@ namespace usfft {
 
 constexpr int kMeshBlock = 256;
 
-int64_t mesh_lds_bytes(const MeshDev& M) { return 8 * ((int64_t)M.nt + M.nnz + M.G); }
+int64_t mesh_lds_bytes(const MeshDev& M) { return 8 * ((int64_t)std::max(M.nt, M.G) + M.nnz); }
 
 template <int RMAX>
 __global__ __launch_bounds__(kMeshBlock) void pcgmesh_kernel(PdeDev P, MeshDev M, const double* __restrict__ Y,
@@ -35,11 +39,10 @@ __global__ __launch_bounds__(kMeshBlock) void pcgmesh_kernel(PdeDev P, MeshDev M
                                                              int64_t col0, int* __restrict__ iters) {
   extern __shared__ double lds[];
   __shared__ double coef[kMaxD];
-  __shared__ double red0[kMeshBlock / kWave];
-  __shared__ double red1[kMeshBlock / kWave];
-  double* aT = lds;            // triangle coefficients
-  double* val = aT + M.nt;     // matrix values, CSR order
-  double* sp = val + M.nnz;    // search direction
+  __shared__ double red0[2 * (kMeshBlock / kWave)];
+  double* val = lds;           // matrix values, CSR order
+  double* aT = val + M.nnz;    // triangle coefficients (assembly)
+  double* su = aT;             // preconditioned residual (iterations)
   const int tid = threadIdx.x;
   const bool logn = P.model == USFFT_MODEL_LOGNORMAL;
   for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
@@ -58,60 +61,61 @@ __global__ __launch_bounds__(kMeshBlock) void pcgmesh_kernel(PdeDev P, MeshDev M
       val[e] = v;
     }
     __syncthreads();
-    double x[RMAX], r[RMAX], p[RMAX], dinv[RMAX];
-    double rz = 0.0;
+    double x[RMAX], r[RMAX], p[RMAX], sq[RMAX], dinv[RMAX];
 #pragma unroll
     for (int q = 0; q < RMAX; ++q) {
       const int i = tid + kMeshBlock * q;
-      x[q] = r[q] = p[q] = dinv[q] = 0.0;
+      x[q] = r[q] = p[q] = sq[q] = dinv[q] = 0.0;
       if (i < M.G) {
         dinv[q] = 1.0 / val[M.diag[i]];
         r[q] = M.load[i];
-        p[q] = dinv[q] * r[q];
-        rz += r[q] * p[q];
       }
     }
-    rz = block_sum<kMeshBlock>(rz, red0);
-    const double stop = rtol * rtol * rz;
+    double stop = 0.0, gamma_old = 1.0, alpha_old = 1.0;
     int it = 0;
-    bool conv = !(rz > 0.0);
-    while (!conv && it < maxit) {
+    bool conv = false;
+    while (true) {
+      // u = D^-1 r to LDS; w = A u; one reduction of (r.u, w.u)
 #pragma unroll
       for (int q = 0; q < RMAX; ++q) {
         const int i = tid + kMeshBlock * q;
-        if (i < M.G) sp[i] = p[q];
+        if (i < M.G) su[i] = dinv[q] * r[q];
       }
       __syncthreads();
-      double qv[RMAX];
-      double pq = 0.0;
+      double w[RMAX];
+      double gamma = 0.0, delta = 0.0;
 #pragma unroll
       for (int q = 0; q < RMAX; ++q) {
         const int i = tid + kMeshBlock * q;
         double acc = 0.0;
         if (i < M.G)
-          for (int e = M.rowptr[i]; e < M.rowptr[i + 1]; ++e) acc += val[e] * sp[M.col[e]];
-        qv[q] = acc;
-        pq += p[q] * acc;
+          for (int e = M.rowptr[i]; e < M.rowptr[i + 1]; ++e) acc += val[e] * su[M.col[e]];
+        w[q] = acc;
+        const double u = dinv[q] * r[q];
+        gamma += r[q] * u;
+        delta += acc * u;
       }
-      pq = block_sum<kMeshBlock>(pq, red0);
-      const double alpha = rz / pq;
-      double rz2 = 0.0;
-#pragma unroll
-      for (int q = 0; q < RMAX; ++q) {
-        x[q] += alpha * p[q];
-        r[q] -= alpha * qv[q];
-        rz2 += r[q] * dinv[q] * r[q];
-      }
-      rz2 = block_sum<kMeshBlock>(rz2, red1);
-      ++it;
-      if (rz2 <= stop) {
+      block_sum2<kMeshBlock>(gamma, delta, red0);
+      if (it == 0) stop = rtol * rtol * gamma;
+      if (!(gamma > stop)) {
         conv = true;
         break;
       }
-      const double beta = rz2 / rz;
-      rz = rz2;
+      if (it >= maxit) break;
+      const double beta = it == 0 ? 0.0 : gamma / gamma_old;
+      const double alpha = gamma / (delta - (it == 0 ? 0.0 : beta * gamma / alpha_old));
 #pragma unroll
-      for (int q = 0; q < RMAX; ++q) p[q] = dinv[q] * r[q] + beta * p[q];
+      for (int q = 0; q < RMAX; ++q) {
+        p[q] = dinv[q] * r[q] + beta * p[q];
+        sq[q] = w[q] + beta * sq[q];
+        x[q] += alpha * p[q];
+        r[q] -= alpha * sq[q];
+      }
+      gamma_old = gamma;
+      alpha_old = alpha;
+      ++it;
+      // the next iteration's u overwrites su: every lane is past its reads
+      // (block_sum2 above)
     }
 #pragma unroll
     for (int q = 0; q < RMAX; ++q) {
