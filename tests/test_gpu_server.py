@@ -18,6 +18,8 @@ def jobs():
     for seed, n, prec in [(4, 16, 0), (5, 12, 1), (6, 16, 1)]:
         prob = W.pde_problem(n, 4, 12, modes="diagonal")
         out.append((prob, dict(W.params(30, 2, 1e-4), precision=prec), seed))
+    # a general triangulation: the server keeps its own copy of the mesh
+    out.append((W.mesh_problem(W.jittered_mesh(8, 9, 7), 4, 8), W.params(30, 2, 1e-4), 7))
     return out
 
 
