@@ -3,6 +3,7 @@
 // is exact integer arithmetic, so results are bit-identical to any correct
 // implementation.
 #include "kernels.h"
+#include "rng.h"
 
 namespace usfft {
 
@@ -113,6 +114,67 @@ void launch_lattice_score(const int32_t* bins, const int32_t* counts, const uint
   if (n <= 0) return;
   const unsigned gx = (unsigned)std::min<int64_t>(256, ceil_div(n, 256));
   hipLaunchKernelGGL(lattice_score_kernel, dim3(gx, T), dim3(256), 0, st, bins, counts, covered, n, T, M, scores);
+  USFFT_HIP(hipGetLastError());
+}
+
+// Generators of the T tries of lattice attempt a, the draws of rng::lattice_z.
+__global__ void lattice_z_kernel(uint64_t seed, int kind, int tcode, int a, int T, int t, int M,
+                                 int32_t* __restrict__ z) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= T * t) return;
+  z[e] = rng::lattice_z(seed, kind, tcode, a, e / t, e % t, M);
+}
+
+void launch_lattice_z(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, int32_t* z, hipStream_t st) {
+  hipLaunchKernelGGL(lattice_z_kernel, dim3((unsigned)ceil_div(T * t, 64)), dim3(64), 0, st, seed, kind, tcode, a, T,
+                     t, M, z);
+  USFFT_HIP(hipGetLastError());
+}
+
+// The choice of one attempt on the device: the try that frees the most
+// still-uncovered candidates (lowest index on ties).  state[0] = uncovered
+// candidates, state[1] = lattices taken; log = (best, freed), freed = 0 when
+// the attempt takes nothing (no candidate freed, or none left).
+__global__ void lattice_pick_kernel(const int32_t* __restrict__ scores, int T, int64_t* __restrict__ state,
+                                    int32_t* __restrict__ log) {
+  if (threadIdx.x != 0) return;
+  int best = 0;
+  for (int b = 1; b < T; ++b)
+    if (scores[b] > scores[best]) best = b;
+  const int freed = state[0] > 0 ? scores[best] : 0;
+  log[0] = best;
+  log[1] = freed;
+  if (freed > 0) {
+    state[0] -= freed;
+    state[1] += 1;
+  }
+}
+
+// Commit the try chosen by lattice_pick_kernel (nothing when it freed none).
+__global__ void lattice_take_pick_kernel(const int32_t* __restrict__ bins, const int32_t* __restrict__ counts,
+                                         uint8_t* __restrict__ covered, int64_t n, int M,
+                                         const int32_t* __restrict__ log, const int64_t* __restrict__ state,
+                                         int32_t* __restrict__ assign, int32_t* __restrict__ bin_out) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n || log[1] == 0) return;
+  const int best = log[0];
+  const int lat = (int)state[1] - 1;
+  const int32_t b = bins[(int64_t)best * n + a];
+  if (!covered[a] && counts[(int64_t)best * M + b] == 1) {
+    covered[a] = 1;
+    assign[a] = lat;
+    bin_out[a] = b;
+  }
+}
+
+void launch_lattice_pick_take(const int32_t* scores, int T, int64_t* state, int32_t* log, const int32_t* bins,
+                              const int32_t* counts, uint8_t* covered, int64_t n, int M, int32_t* assign,
+                              int32_t* bin_out, hipStream_t st) {
+  hipLaunchKernelGGL(lattice_pick_kernel, dim3(1), dim3(64), 0, st, scores, T, state, log);
+  USFFT_HIP(hipGetLastError());
+  if (n <= 0) return;
+  hipLaunchKernelGGL(lattice_take_pick_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, bins, counts,
+                     covered, n, M, log, state, assign, bin_out);
   USFFT_HIP(hipGetLastError());
 }
 

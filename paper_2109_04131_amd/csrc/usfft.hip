@@ -18,36 +18,13 @@
 #include <vector>
 
 #include "kernels.h"
+#include "rng.h"
 
 namespace usfft {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-// ---------------------------------------------------------------- SplitMix64
-// Steele, Lea, Flood (OOPSLA 2014): state += 0x9E3779B97F4A7C15, output the
-// variant-13 finalizer of the state.  Keyed per use as stated in the header of
-// the draws: key = out(seed + gamma*stream), draw(idx) = out(key + gamma*idx).
-namespace rng {
-constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
-inline uint64_t fin(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-inline uint64_t stream(int kind, int t, int a, int b) {
-  return ((uint64_t)(kind & 0xFF) << 56) | ((uint64_t)(t & 0xFFFF) << 40) | ((uint64_t)(a & 0xFFFFFF) << 16) |
-         (uint64_t)(b & 0xFFFF);
-}
-inline uint64_t draw(uint64_t seed, uint64_t st, uint64_t idx) {
-  const uint64_t key = fin(seed + kGamma * (st + 1));
-  return fin(key + kGamma * (idx + 1));
-}
-inline double uniform01(uint64_t seed, uint64_t st, uint64_t idx) {
-  return (double)(draw(seed, st, idx) >> 11) * (1.0 / 9007199254740992.0);
-}
-enum { kTail1 = 1, kTail2 = 2, kLat2 = 3, kLat3 = 4 };
-}  // namespace rng
 
 // ---------------------------------------------------------------- buffers
 // Owning device buffer; move-only so that swaps and container moves never
@@ -121,6 +98,14 @@ struct usfft_plan_s {
   usfft::DevBuf m_rowptr, m_col, m_diag, m_cptr, m_ctri, m_cw, m_load, m_psi;
   usfft::MeshDev mesh{};
   int mesh_blocks = 0;
+  // pinned staging of small uploads: a copy from it needs no host wait; the
+  // arena is reused only after a stream synchronisation
+  char* stage = nullptr;
+  size_t stage_cap = 0, stage_used = 0;
+  // pinned landing buffer of small readbacks (valid until the next readback)
+  char* back = nullptr;
+  size_t back_cap = 0;
+  usfft::DevBuf famlog, famstate;
   int wblocks = 0;  // persistent workgroups of the float32 / DST solver
   bool streaming = false;  // mesh larger than the on-chip solvers hold
   bool dst = false;        // DST-preconditioned solver
@@ -136,6 +121,8 @@ struct usfft_plan_s {
   std::mutex mu;
   ~usfft_plan_s() {
     for (auto& kv : rader) usfft::rader_free(kv.second);
+    if (stage) (void)hipHostFree(stage);
+    if (back) (void)hipHostFree(back);
   }
 };
 
@@ -160,11 +147,16 @@ static const RaderTables& rader_for(usfft_plan_s* P, int M, hipStream_t st) {
   return P->rader.emplace(M, T).first->second;
 }
 
+// The admissible lattice sizes in [lo, hi], from a table built once.
 static std::vector<int> admissible_sizes(int lo, int hi) {
-  std::vector<int> out;
-  for (int m = std::max(lo, 3); m <= hi; ++m)
-    if (lattice_size_ok(m)) out.push_back(m);
-  return out;
+  static const std::vector<int> all = [] {
+    std::vector<int> v;
+    for (int m = 3; m <= kMaxLattice; ++m)
+      if (lattice_size_ok(m)) v.push_back(m);
+    return v;
+  }();
+  return std::vector<int>(std::lower_bound(all.begin(), all.end(), std::max(lo, 3)),
+                          std::upper_bound(all.begin(), all.end(), hi));
 }
 
 // Largest sample matrix (bytes) one batched sampler launch of step 2 fills.
@@ -180,8 +172,48 @@ static void h2d(usfft::DevBuf& b, const std::vector<T>& v, hipStream_t st) {
   }
 }
 
-// Greedy multiple rank-1 lattice family (reading stated in usfft.h).  The alias
-// tests run on the device; the host keeps the choice loop.
+// Upload through the plan's pinned arena, asynchronously on st.
+template <typename T>
+static void h2d_async(usfft_plan_s* P, usfft::DevBuf& b, const std::vector<T>& v, hipStream_t st) {
+  const size_t bytes = sizeof(T) * v.size();
+  b.ensure(std::max<size_t>(bytes, sizeof(T)));
+  if (bytes == 0) return;
+  if (P->stage_used + bytes > P->stage_cap) {
+    USFFT_HIP(hipStreamSynchronize(st));  // every earlier copy out of the arena is done
+    P->stage_used = 0;
+    if (bytes > P->stage_cap) {
+      if (P->stage) USFFT_HIP(hipHostFree(P->stage));
+      P->stage = nullptr;
+      P->stage_cap = 0;
+      const size_t cap = std::max<size_t>(bytes, 4u << 20);
+      USFFT_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->stage), cap, hipHostMallocDefault));
+      P->stage_cap = cap;
+    }
+  }
+  std::memcpy(P->stage + P->stage_used, v.data(), bytes);
+  USFFT_HIP(hipMemcpyAsync(b.p, P->stage + P->stage_used, bytes, hipMemcpyHostToDevice, st));
+  P->stage_used += (bytes + 255) / 256 * 256;
+}
+
+// Pinned host memory for a readback of `bytes` (grown as needed).
+static char* back_buffer(usfft_plan_s* P, size_t bytes) {
+  if (bytes > P->back_cap) {
+    if (P->back) USFFT_HIP(hipHostFree(P->back));
+    P->back = nullptr;
+    P->back_cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 1u << 20);
+    USFFT_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->back), cap, hipHostMallocDefault));
+    P->back_cap = cap;
+  }
+  return P->back;
+}
+
+// Greedy multiple rank-1 lattice family (reading stated in usfft.h).  The
+// attempts run on the device in batches: generators, alias counts, scores,
+// the choice of the best try and its commit, with one readback of the batch's
+// choices; the host rebuilds the family from them.
+constexpr int kFamilyBatch = 4;
+
 static void plan_family(usfft_plan_s* P, const int32_t* J, int64_t n, int t, uint64_t seed, int kind, int tcode,
                         Family& F, int32_t* assign, int32_t* bins_out, hipStream_t st) {
   const usfft_params& par = P->par;
@@ -198,46 +230,56 @@ static void plan_family(usfft_plan_s* P, const int32_t* J, int64_t n, int t, uin
   USFFT_HIP(hipMemsetAsync(P->famcov.p, 0, n, st));
   P->fambins.ensure(sizeof(int32_t) * n * T);
   P->famscores.ensure(sizeof(int32_t) * T);
-  int64_t remaining = n;
-  std::vector<int32_t> z((size_t)T * t), scores(T);
-  for (int attempt = 0; remaining > 0; ++attempt) {
+  P->famz.ensure(sizeof(int32_t) * (size_t)T * t);
+  P->famcounts.ensure(sizeof(int32_t) * (size_t)T * par.lattice_mmax);
+  P->famlog.ensure(sizeof(int32_t) * 2 * (size_t)par.lattice_max);
+  h2d_async(P, P->famstate, std::vector<int64_t>{n, 0}, st);
+  for (int attempt = 0;;) {
+    const int nb = std::min(kFamilyBatch, par.lattice_max - attempt);
+    for (int b = 0; b < nb; ++b) {
+      const int a = attempt + b;
+      const int M = sizes[a % sizes.size()];
+      launch_lattice_z(seed, kind, tcode, a, T, t, M, P->famz.as<int32_t>(), st);
+      USFFT_HIP(hipMemsetAsync(P->famcounts.p, 0, sizeof(int32_t) * (size_t)T * M, st));
+      USFFT_HIP(hipMemsetAsync(P->famscores.p, 0, sizeof(int32_t) * T, st));
+      launch_lattice_bins(J, n, t, P->famz.as<int32_t>(), T, M, P->fambins.as<int32_t>(),
+                          P->famcounts.as<int32_t>(), st);
+      launch_lattice_score(P->fambins.as<int32_t>(), P->famcounts.as<int32_t>(), P->famcov.as<uint8_t>(), n, T, M,
+                           P->famscores.as<int32_t>(), st);
+      launch_lattice_pick_take(P->famscores.as<int32_t>(), T, P->famstate.as<int64_t>(),
+                               P->famlog.as<int32_t>() + 2 * a, P->fambins.as<int32_t>(),
+                               P->famcounts.as<int32_t>(), P->famcov.as<uint8_t>(), n, M, assign, bins_out, st);
+    }
+    char* hb = back_buffer(P, 2 * sizeof(int64_t) + sizeof(int32_t) * 2 * kFamilyBatch);
+    int64_t* state = reinterpret_cast<int64_t*>(hb);
+    int32_t* lg = reinterpret_cast<int32_t*>(hb + 2 * sizeof(int64_t));
+    USFFT_HIP(hipMemcpyAsync(state, P->famstate.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipMemcpyAsync(lg, P->famlog.as<int32_t>() + 2 * attempt, sizeof(int32_t) * 2 * nb,
+                             hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < nb; ++b) {
+      if (lg[2 * b + 1] == 0) continue;
+      const int a = attempt + b;
+      const int M = sizes[a % sizes.size()];
+      F.M.push_back(M);
+      for (int j = 0; j < t; ++j) F.z.push_back(rng::lattice_z(seed, kind, tcode, a, lg[2 * b], j, M));
+      F.off.push_back(F.off.back() + M);
+    }
+    attempt += nb;
+    if (state[0] == 0) break;
     USFFT_REQUIRE(attempt < par.lattice_max, USFFT_ELATTICE,
                   "lattice family incomplete after " + std::to_string(par.lattice_max) + " attempts");
-    const int M = sizes[attempt % sizes.size()];
-    for (int b = 0; b < T; ++b)
-      for (int j = 0; j < t; ++j)
-        z[(size_t)b * t + j] = (int32_t)(1 + rng::draw(seed, rng::stream(kind, tcode, attempt, b), j) % (M - 1));
-    h2d(P->famz, z, st);
-    P->famcounts.ensure(sizeof(int32_t) * (size_t)T * M);
-    USFFT_HIP(hipMemsetAsync(P->famcounts.p, 0, sizeof(int32_t) * (size_t)T * M, st));
-    USFFT_HIP(hipMemsetAsync(P->famscores.p, 0, sizeof(int32_t) * T, st));
-    launch_lattice_bins(J, n, t, P->famz.as<int32_t>(), T, M, P->fambins.as<int32_t>(), P->famcounts.as<int32_t>(),
-                        st);
-    launch_lattice_score(P->fambins.as<int32_t>(), P->famcounts.as<int32_t>(), P->famcov.as<uint8_t>(), n, T, M,
-                         P->famscores.as<int32_t>(), st);
-    USFFT_HIP(hipMemcpyAsync(scores.data(), P->famscores.p, sizeof(int32_t) * T, hipMemcpyDeviceToHost, st));
-    USFFT_HIP(hipStreamSynchronize(st));
-    int best = 0;
-    for (int b = 1; b < T; ++b)
-      if (scores[b] > scores[best]) best = b;
-    if (scores[best] == 0) continue;
-    const int lat = (int)F.M.size();
-    launch_lattice_take(P->fambins.as<int32_t>() + (size_t)best * n, P->famcounts.as<int32_t>() + (size_t)best * M,
-                        P->famcov.as<uint8_t>(), n, M, lat, assign, bins_out, st);
-    F.M.push_back(M);
-    for (int j = 0; j < t; ++j) F.z.push_back(z[(size_t)best * t + j]);
-    F.off.push_back(F.off.back() + M);
-    remaining -= scores[best];
   }
 }
 
 // Group candidates by lattice: pos lists (ascending) and bins, uploaded to P->lists.
 static void group_by_lattice(usfft_plan_s* P, Family& F, const int32_t* assign, const int32_t* bins, int64_t n,
                              hipStream_t st) {
-  std::vector<int32_t> ha(n), hb(n);
+  int32_t* ha = reinterpret_cast<int32_t*>(back_buffer(P, 2 * sizeof(int32_t) * std::max<int64_t>(n, 1)));
+  int32_t* hb = ha + n;
   if (n > 0) {
-    USFFT_HIP(hipMemcpyAsync(ha.data(), assign, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
-    USFFT_HIP(hipMemcpyAsync(hb.data(), bins, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipMemcpyAsync(ha, assign, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipMemcpyAsync(hb, bins, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
     USFFT_HIP(hipStreamSynchronize(st));
   }
   const int nl = (int)F.M.size();
@@ -253,7 +295,7 @@ static void group_by_lattice(usfft_plan_s* P, Family& F, const int32_t* assign, 
     lists[n + fill[l]] = hb[a];   // bins
     fill[l]++;
   }
-  h2d(P->lists, lists, st);
+  h2d_async(P, P->lists, lists, st);
 }
 
 // Sampler call on rows [0, ns) of Y into U columns [col0, col0 + ns).
@@ -412,8 +454,8 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
         for (int i = 0; i < r; ++i) off[t * r + i + 1] = off[t * r + i] + Kt[t];
       }
       const int64_t ns = off.back(), ld = ceil_div(ns, 64) * 64;
-      h2d(P->cands, ks, st);
-      h2d(P->latM, Kt, st);
+      h2d_async(P, P->cands, ks, st);
+      h2d_async(P, P->latM, Kt, st);
       P->U.ensure(ub * G * ld);
       P->V.ensure(sizeof(double) * G * Kmax);
       P->Y.ensure(sizeof(double) * ns * d);
@@ -425,7 +467,7 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
         for (int i = 0; i < r; ++i)
           for (int j = 0; j < d; ++j)
             tails[((size_t)t * r + i) * d + j] = rng::uniform01(seed, rng::stream(rng::kTail1, t + 1, i + 1, 0), j);
-      h2d(P->tail, tails, st);
+      h2d_async(P, P->tail, tails, st);
       for (int t = 0; t < d; ++t)
         for (int i = 0; i < r; ++i)
           launch_nodes(d, t, 1, 1, nullptr, P->latM.as<int32_t>() + t, nullptr,
@@ -499,9 +541,9 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       for (int M : F.M) (void)rader_for(P, M, st);
       const int64_t ns = F.total();
       P->V.ensure(sizeof(double) * G * n);
-      h2d(P->latM, F.M, st);
-      h2d(P->latz, F.z, st);
-      h2d(P->latoff, F.off, st);
+      h2d_async(P, P->latM, F.M, st);
+      h2d_async(P, P->latz, F.z, st);
+      h2d_async(P, P->latoff, F.off, st);
       // V holds the stage's magnitudes in lattice-grouped candidate order (each
       // lattice's bins contiguous per node); the mask is built in that order and
       // mapped back to candidate order before compaction.
@@ -524,7 +566,7 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
         for (int b = 0; b < nb; ++b)
           for (int j = 0; j < d; ++j)
             tails[(size_t)b * d + j] = rng::uniform01(seed, rng::stream(rng::kTail2, t + 1, i0 + b + 1, 0), j);
-        h2d(P->tail, tails, st);
+        h2d_async(P, P->tail, tails, st);
         for (int b = 0; b < nb; ++b)
           launch_nodes(d, -1, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(),
                        P->latz.as<int32_t>(), P->tail.as<double>() + (size_t)b * d, P->Y.as<double>() + b * ns * d,
@@ -586,9 +628,9 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     P->U.ensure(ub * G * ld);
     P->Y.ensure(sizeof(double) * ns * d);
     P->iters.ensure(sizeof(int32_t) * ns);
-    h2d(P->latM, F.M, st);
-    h2d(P->latz, F.z, st);
-    h2d(P->latoff, F.off, st);
+    h2d_async(P, P->latM, F.M, st);
+    h2d_async(P, P->latz, F.z, st);
+    h2d_async(P, P->latoff, F.off, st);
     launch_nodes(d, -1, d, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(), P->latz.as<int32_t>(),
                  P->tail.as<double>(), P->Y.as<double>(), ns, st);
     sample_timed(P->Y.as<double>(), ns, ld);
