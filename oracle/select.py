@@ -41,7 +41,9 @@ def detect_mask(V, s_tilde, theta2, tie_rel=TIE_REL):
 
 def product(parent, child):
     """Parent-major Cartesian product of an (p x (t-1)) and a (c,) set."""
-    parent = np.asarray(parent, dtype=np.int64).reshape(len(parent), -1)
+    parent = np.asarray(parent, dtype=np.int64)
+    if parent.ndim == 1:
+        parent = parent[:, None]
     child = np.asarray(child, dtype=np.int64)
     P = np.repeat(parent, len(child), axis=0)
     C = np.tile(child, len(parent))[:, None]

@@ -633,6 +633,30 @@ def test_mesh_problems_are_checked(lib):
         assert e.value.status == lib.EINVAL
 
 
+@pytest.mark.parametrize("case", range(3), ids=["d1", "nothing_detected", "flat_dimension"])
+def test_degenerate_jobs_match_oracle(lib, case):
+    # d = 1 (no step 2), a threshold above every coefficient (empty result
+    # after step 1), and a box with K_t = 1 in the middle coordinate
+    name, K, P, lo, hi, theta, r = W.degenerate_trig_cases()[case]
+    d = K.shape[1]
+    prob = dict(sampler="poly", d=d, k_lo=lo, k_hi=hi, poly_k=K, poly_c=P)
+    res, ref = run_both(lib, prob, W.params(40, r, theta, relative=False), 7, sampler=TrigPolySampler(K, P))
+    assert res.freqs().tolist() == ref.I.tolist()
+    assert res.stats["samples"] == ref.samples
+    if name == "empty":
+        assert res.n == 0
+        Y = np.random.default_rng(1).random((5, d))
+        out = torch.ones((5, res.G), dtype=torch.float64, device="cuda")
+        lib.eval(res, dev(Y), out)
+        assert np.array_equal(host(out), np.zeros((5, res.G)))
+        var = torch.ones(res.G, dtype=torch.float64, device="cuda")
+        gsi = torch.ones((d, res.G), dtype=torch.float64, device="cuda")
+        lib.statistics(res, None, var, gsi)
+        assert not host(var).any() and not host(gsi).any()
+        return
+    assert np.abs(res.coeffs() - ref.C).max() <= 1e-12 * np.abs(ref.C).max()
+
+
 def test_error_paths(lib):
     prob, par = W.WORKLOADS["cpu16_d4"]
     with pytest.raises(lib.UsfftError) as e:

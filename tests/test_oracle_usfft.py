@@ -77,3 +77,19 @@ def test_a_priori_sets_match_their_definitions():
     ]
     for got, test in cases:
         assert got.tolist() == sorted([list(k) for k in box if test(k)])
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_degenerate_runs(case):
+    name, K, P, lo, hi, theta, r = W.degenerate_trig_cases()[case]
+    d = K.shape[1]
+    res = usfft(TrigPolySampler(K, P), d, lo, hi, 40, 40, r, theta, False, 7)
+    support = {tuple(k) for k, row in zip(K.tolist(), P) if np.abs(row).max() > 0}
+    if name == "empty":
+        assert res.I.shape == (0, d) and res.C.shape == (0, P.shape[1])
+        assert res.samples == d * r * 17  # step 1 only
+        return
+    assert {tuple(k) for k in res.I.tolist()} == support
+    idx = {tuple(k): a for a, k in enumerate(K.tolist())}
+    for a, k in enumerate(res.I.tolist()):
+        assert np.allclose(res.C[a], P[idx[tuple(k)]], rtol=0, atol=1e-12)

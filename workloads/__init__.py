@@ -261,3 +261,18 @@ def mesh_problem(mesh, d, N, a0=1.0, modes="split"):
     m1, m2 = (modes_diagonal if modes == "diagonal" else modes_split)(d)
     return dict(sampler="pde_mesh", d=d, k_lo=[-N] * d, k_hi=[N] * d, a0=a0, amp=amplitudes(d),
                 mode1=m1, mode2=m2, **mesh)
+
+
+def degenerate_trig_cases():
+    """Degenerate detection inputs: d = 1; a threshold above every coefficient
+    (nothing is detected); a box with a single frequency (K_t = 1) in the
+    middle coordinate.  (name, K, P, k_lo, k_hi, theta, r)."""
+    K1, P1 = trig_poly(3, 1, 8, 20, 9, cmin=1e-2)
+    K2, P2 = trig_poly(4, 3, 8, 10, 15, cmin=1e-2)
+    Kb, Pb = trig_poly(5, 2, 8, 12, 21, cmin=1e-2)
+    Kb = np.insert(Kb, 1, 0, axis=1)
+    return [
+        ("d1", K1, P1, [-8], [8], 1e-6, 3),
+        ("empty", K2, P2, [-8] * 3, [8] * 3, 1e3, 2),
+        ("flat_dim", Kb, Pb, [-8, 0, -8], [8, 0, 8], 1e-6, 3),
+    ]
