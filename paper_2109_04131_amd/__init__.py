@@ -144,7 +144,7 @@ def version():
 
 DEFAULT_PARAMS = dict(s=50, s_local=50, r=5, theta=1e-12, theta_relative=False, tie_rel=2.0 ** -30,
                       precision=FP64, lattice_c=2.0, lattice_tries=8, lattice_max=64, lattice_mmax=9601,
-                      pcg_rtol=1e-12, pcg_maxit=4000, inner_rtol=1e-3, refine_every=200, solver_config=-1,
+                      pcg_rtol=1e-12, pcg_maxit=4000, inner_rtol=2e-4, refine_every=200, solver_config=-1,
                       precond=0)
 
 
