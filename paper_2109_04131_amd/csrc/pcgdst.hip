@@ -110,12 +110,13 @@ __device__ __forceinline__ half8 load_h8(const _Float16* p) {
   return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// z = L^-1 r for the wave's strip (see the file comment).  r and z are in
-// the node layout; sc scales r before the fp16 conversion (z is scaled back).
+// z = (L + shift I)^-1 r for the wave's strip (see the file comment).  r and
+// z are in the node layout; sc scales r before the fp16 conversion (z is
+// scaled back).
 template <int MP, typename T>
 __device__ __forceinline__ void dst_apply(const T (&r)[MP / 4], float sc, float (&z)[MP / 4],
                                           const half8 (&sf)[(MP / 32) * (MP / 16)], _Float16* xa, _Float16* xb,
-                                          const float* lam) {
+                                          const float* lam, float shift) {
   constexpr int NT = MP / 16, KB = MP / 32, LDX = MP + 4;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
   half8 a[KB];
@@ -148,7 +149,7 @@ __device__ __forceinline__ void dst_apply(const T (&r)[MP / 4], float sc, float 
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(sf[kb * NT + t], b[kb], acc[t], 0, 0, 0);
     const floatx4 lr = *reinterpret_cast<const floatx4*>(lam + 16 * t + 4 * q);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[t][v] *= __builtin_amdgcn_rcpf(lr[v] + lc);
+    for (int v = 0; v < 4; ++v) acc[t][v] *= __builtin_amdgcn_rcpf(lr[v] + lc + shift);
   }
   // T3 = Y S: row strip w of T3
 #pragma unroll
@@ -185,6 +186,18 @@ __device__ __forceinline__ float pow2_scale(double rr) {
   if (!(rr > 0.0) || !(rr < 1e300)) return 1.0f;
   const int e = ilogb(rr) / 2;
   return ldexpf(1.0f, -(e < -100 ? -100 : (e > 100 ? 100 : e)));
+}
+
+// Shift of the preconditioner from the scaled weights of one sample.  For a
+// smooth coefficient the scaled operator is close to L + h^2 V with
+// V = lap(sqrt(a)) / sqrt(a) (substitute u = a^-1/2 v); its row sums away
+// from the boundary are h^2 V at the node, and their mean (clamped at 0, so
+// that the preconditioner stays positive definite) is a constant shift that
+// keeps the preconditioner diagonal in the DST basis: (L + shift I)^-1.
+__device__ __forceinline__ float potential_shift(double rowsum, int m) {
+  if (m < 3) return 0.0f;
+  const double c = rowsum / ((double)(m - 2) * (double)(m - 2));
+  return c > 0.0 ? (float)c : 0.0f;
 }
 
 // LDS grids of one workgroup have the compile-time pitch PP = MP + 2 >= n + 1
@@ -422,11 +435,20 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
         bb += bt * bt;
       }
     }
-    bb = block_sum<BLOCK>(bb, red0);
+    double rs = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int row = 16 * (e >> 2) + 4 * q + (e & 3);
+      const T wn = (e & 3) == 3 ? wN4[e >> 2] : wS[e + 1];
+      const T diag = DIAG ? dd[DIAG ? e : 0] : (T)4;
+      if (row >= 1 && row <= m - 2 && c >= 1 && c <= m - 2) rs += (double)(diag - (wE[e] + wW[e] + wn + wS[e]));
+    }
+    block_sum2<BLOCK>(bb, rs, red0);
+    const float shift = potential_shift(rs, m);
     if (REFINE)
       for (int g = tid; g < m * m; g += BLOCK) sx[(g / m + 1) * PP + g % m + 1] = 0.0;  // u = 0
     float z[E];
-    dst_apply<MP, T>(r, pow2_scale(bb), z, sf, xa, xb, slam);
+    dst_apply<MP, T>(r, pow2_scale(bb), z, sf, xa, xb, slam, shift);
     double rz = 0.0, rr = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -461,7 +483,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
         dx[e] += alpha * p[e];
         r[e] -= alpha * qv[e];
       }
-      dst_apply<MP, T>(r, pow2_scale(rr), z, sf, xa, xb, slam);
+      dst_apply<MP, T>(r, pow2_scale(rr), z, sf, xa, xb, slam, shift);
       double rz2 = 0.0;
       rr = 0.0;
 #pragma unroll
@@ -512,7 +534,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
             conv = true;
             break;
           }
-          dst_apply<MP, T>(r, pow2_scale(rr64), z, sf, xa, xb, slam);
+          dst_apply<MP, T>(r, pow2_scale(rr64), z, sf, xa, xb, slam, shift);
           rz2 = 0.0;
           rr = 0.0;
 #pragma unroll
@@ -641,10 +663,18 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
         bb += bt * bt;
       }
     }
-    bb = block_sum<BLOCK>(bb, red0);  // every lane is done with the edge grids
+    double rs = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int row = 16 * (e >> 2) + 4 * q + (e & 3);
+      const float wn = (e & 3) == 3 ? wN4[e >> 2] : wS[e + 1];
+      if (row >= 1 && row <= m - 2 && c >= 1 && c <= m - 2) rs += (double)(4.0f - (wE[e] + wW[e] + wn + wS[e]));
+    }
+    block_sum2<BLOCK>(bb, rs, red0);  // every lane is done with the edge grids
+    const float shift = potential_shift(rs, m);
     zero_ring(sp);
     float z[E];
-    dst_apply<MP, float>(r, pow2_scale(bb), z, sf, xa, xb, slam);
+    dst_apply<MP, float>(r, pow2_scale(bb), z, sf, xa, xb, slam, shift);
     double rz = 0.0, rr = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -719,7 +749,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
         zero_ring(sp);
         rr = rr_ref = rr64;
       }
-      dst_apply<MP, float>(r, pow2_scale(rr), z, sf, xa, xb, slam);
+      dst_apply<MP, float>(r, pow2_scale(rr), z, sf, xa, xb, slam, shift);
       double rz2 = 0.0, rre = 0.0;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
