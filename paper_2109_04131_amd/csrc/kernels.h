@@ -45,6 +45,12 @@ void launch_pde_solve_mesh(const PdeDev& P, const MeshDev& M, const double* Y, i
 // ---- sampler.hip
 void launch_nodes(int d, int line, int t, int nlat, const int64_t* off, const int32_t* Ms, const int32_t* zs,
                   const double* tail, double* Y, int64_t ns, hipStream_t st);
+// step 1: all d x r lines (loff: d r + 1 sample offsets, tails: d r x d)
+void launch_line_nodes(int d, int r, const int64_t* loff, const int32_t* Kt, const double* tails, double* Y,
+                       int64_t ns, hipStream_t st);
+// step 2: nrep copies of a family's nodes with tails nrep x d (copy b at Y + b ns d)
+void launch_lattice_nodes_rep(int d, int t, int nlat, const int64_t* off, const int32_t* Ms, const int32_t* zs,
+                              const double* tails, double* Y, int64_t ns, int nrep, hipStream_t st);
 int solver_config_count();
 bool solver_config_fits(int c, int n);  // n = mesh_n
 void solver_config_shape(int c, int* block, int* npt);

@@ -462,6 +462,65 @@ __global__ __launch_bounds__(256) void trigpoly_kernel(int d, const double* __re
 }
 
 // ---------------------------------------------------------------- launchers
+// All d x r detection lines of step 1 in one launch: line L = t r + i covers
+// samples [loff[L], loff[L + 1]) with coordinate t on l / K_t and tail L.
+__global__ void line_nodes_kernel(int d, int r, int nlines, const int64_t* __restrict__ loff,
+                                  const int32_t* __restrict__ Kt, const double* __restrict__ tails,
+                                  double* __restrict__ Y, int64_t ns) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ns * d) return;
+  const int64_t s = e / d;
+  const int j = (int)(e % d);
+  int lo = 0, hi = nlines - 1;  // last line with loff <= s
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (loff[mid] <= s) lo = mid; else hi = mid - 1;
+  }
+  const int t = lo / r;
+  Y[e] = j == t ? (double)(s - loff[lo]) / (double)Kt[t] : tails[(int64_t)lo * d + j];
+}
+
+void launch_line_nodes(int d, int r, const int64_t* loff, const int32_t* Kt, const double* tails, double* Y,
+                       int64_t ns, hipStream_t st) {
+  if (ns <= 0) return;
+  hipLaunchKernelGGL(line_nodes_kernel, dim3((unsigned)ceil_div(ns * d, 256)), dim3(256), 0, st, d, r, d * r, loff,
+                     Kt, tails, Y, ns);
+  USFFT_HIP(hipGetLastError());
+}
+
+// nrep copies of a lattice family's nodes, copy b with tail b: the r~
+// iterations of one step-2 stage in one launch.
+__global__ void lattice_nodes_rep_kernel(int d, int t, int nlat, const int64_t* __restrict__ off,
+                                         const int32_t* __restrict__ Ms, const int32_t* __restrict__ zs,
+                                         const double* __restrict__ tails, double* __restrict__ Y, int64_t ns,
+                                         int nrep) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ns * nrep * d) return;
+  const int64_t sg = e / d;
+  const int j = (int)(e % d);
+  const int b = (int)(sg / ns);
+  const int64_t s = sg % ns;
+  double y;
+  if (j >= t) {
+    y = tails[(int64_t)b * d + j];
+  } else {
+    int l = 0;
+    while (l + 1 < nlat && off[l + 1] <= s) ++l;
+    const int64_t M = Ms[l];
+    const int64_t m = s - off[l];
+    y = (double)((m * (int64_t)zs[(int64_t)l * t + j]) % M) / (double)M;
+  }
+  Y[e] = y;
+}
+
+void launch_lattice_nodes_rep(int d, int t, int nlat, const int64_t* off, const int32_t* Ms, const int32_t* zs,
+                              const double* tails, double* Y, int64_t ns, int nrep, hipStream_t st) {
+  if (ns <= 0 || nrep <= 0) return;
+  hipLaunchKernelGGL(lattice_nodes_rep_kernel, dim3((unsigned)ceil_div(ns * nrep * d, 256)), dim3(256), 0, st, d, t,
+                     nlat, off, Ms, zs, tails, Y, ns, nrep);
+  USFFT_HIP(hipGetLastError());
+}
+
 void launch_nodes(int d, int line, int t, int nlat, const int64_t* off, const int32_t* Ms,
                   const int32_t* zs, const double* tail, double* Y, int64_t ns, hipStream_t st) {
   if (ns <= 0) return;

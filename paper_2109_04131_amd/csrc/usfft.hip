@@ -468,11 +468,9 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
           for (int j = 0; j < d; ++j)
             tails[((size_t)t * r + i) * d + j] = rng::uniform01(seed, rng::stream(rng::kTail1, t + 1, i + 1, 0), j);
       h2d_async(P, P->tail, tails, st);
-      for (int t = 0; t < d; ++t)
-        for (int i = 0; i < r; ++i)
-          launch_nodes(d, t, 1, 1, nullptr, P->latM.as<int32_t>() + t, nullptr,
-                       P->tail.as<double>() + ((size_t)t * r + i) * d, P->Y.as<double>() + off[t * r + i] * d, Kt[t],
-                       st);
+      h2d_async(P, P->latoff, off, st);
+      launch_line_nodes(d, r, P->latoff.as<int64_t>(), P->latM.as<int32_t>(), P->tail.as<double>(),
+                        P->Y.as<double>(), ns, st);
       sample_timed(P->Y.as<double>(), ns, ld);
       S.samples_step1 += ns;
       for (int t = 0; t < d; ++t) {
@@ -567,10 +565,8 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
           for (int j = 0; j < d; ++j)
             tails[(size_t)b * d + j] = rng::uniform01(seed, rng::stream(rng::kTail2, t + 1, i0 + b + 1, 0), j);
         h2d_async(P, P->tail, tails, st);
-        for (int b = 0; b < nb; ++b)
-          launch_nodes(d, -1, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(),
-                       P->latz.as<int32_t>(), P->tail.as<double>() + (size_t)b * d, P->Y.as<double>() + b * ns * d,
-                       ns, st);
+        launch_lattice_nodes_rep(d, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(),
+                                 P->latz.as<int32_t>(), P->tail.as<double>(), P->Y.as<double>(), ns, nb, st);
         sample_timed(P->Y.as<double>(), nsb, ldb);
         S.samples_step2 += nsb;
         for (int b = 0; b < nb; ++b) {
