@@ -15,11 +15,16 @@ struct PdeDev {
   int n, d;
   double a0, h2;
   const double* amp;  // d
-  const double* tab;  // 4 x d x n centroid basis tables (sin or cos per axis)
+  const double* tab;  // centroid basis tables (sin or cos per axis), pde_device.h
   int model;          // USFFT_MODEL_*
   double alpha, beta, delta;
   int raw = 0;        // 1: the solver inputs are parameters y, not sampling nodes t
 };
+
+// Pitch of the padded x2 tables that follow the four d x n tables: entry
+// 1 + cj holds row cj, the ends repeat rows 0 and n - 1, so that any 17
+// consecutive rows starting at cj >= -1 (cj < n) are one contiguous read.
+__host__ __device__ constexpr int row_tab_pitch(int n) { return n + 16; }
 
 // General triangulation (pcgmesh.hip): CSR pattern of the inner vertices,
 // per-entry (triangle, weight) contributions, load, basis at the centroids.

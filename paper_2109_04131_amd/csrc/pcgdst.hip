@@ -113,10 +113,15 @@ __device__ __forceinline__ half8 load_h8(const _Float16* p) {
 // z = (L + shift I)^-1 r for the wave's strip (see the file comment).  r and
 // z are in the node layout; sc scales r before the fp16 conversion (z is
 // scaled back).
-template <int MP, typename T>
+// Pitch of the optional table of the diagonal 1 / (lam_a + lam_b + shift)
+// (column b, row a: entry b * (MP + 4) + a); rows of one column are
+// contiguous for the 4-wide reads, the padding spreads columns over banks.
+__host__ __device__ constexpr int dst_ilam_pitch(int mp) { return mp + 4; }
+
+template <int MP, typename T, bool TAB = false>
 __device__ __forceinline__ void dst_apply(const T (&r)[MP / 4], float sc, float (&z)[MP / 4],
                                           const half8 (&sf)[(MP / 32) * (MP / 16)], _Float16* xa, _Float16* xb,
-                                          const float* lam, float shift) {
+                                          const float* lam, float shift, const float* ilam = nullptr) {
   constexpr int NT = MP / 16, KB = MP / 32, LDX = MP + 4;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
   half8 a[KB];
@@ -147,9 +152,15 @@ __device__ __forceinline__ void dst_apply(const T (&r)[MP / 4], float sc, float 
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(sf[kb * NT + t], b[kb], acc[t], 0, 0, 0);
-    const floatx4 lr = *reinterpret_cast<const floatx4*>(lam + 16 * t + 4 * q);
+    if constexpr (TAB) {
+      const floatx4 il = *reinterpret_cast<const floatx4*>(ilam + (16 * w + c16) * dst_ilam_pitch(MP) + 16 * t + 4 * q);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[t][v] *= __builtin_amdgcn_rcpf(lr[v] + lc + shift);
+      for (int v = 0; v < 4; ++v) acc[t][v] *= il[v];
+    } else {
+      const floatx4 lr = *reinterpret_cast<const floatx4*>(lam + 16 * t + 4 * q);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[t][v] *= __builtin_amdgcn_rcpf(lr[v] + lc + shift);
+    }
   }
   // T3 = Y S: row strip w of T3
 #pragma unroll
@@ -223,11 +234,11 @@ int64_t dst_edge_stride(int mp) { return ((int64_t)dst_pitch(mp) * dst_pitch(mp)
 // Dynamic LDS bytes of one workgroup.  Variants 0 and 1: [u (float32
 // solves), float64][p, T][exchange tiles][variant 1: eh, ev float64,
 // D^-1/2 in T].  Variant 2 (float32 only): [overlay, GE doubles][D^-1/2,
-// float32].
+// float32][preconditioner diagonal, MP x (MP + 4) float32].
 int64_t dst_lds_bytes(int n, int precision, int variant) {
   const int mp = dst_padded(n);
   const int64_t g = dst_grid_elems(mp);
-  if (variant == 2) return g * 8 + g * 4;
+  if (variant == 2) return g * 8 + g * 4 + (int64_t)mp * dst_ilam_pitch(mp) * 4;
   const int64_t grids = precision == USFFT_FP64 ? g * 8 : g * 8 + g * 4;
   return grids + 2 * (int64_t)mp * (mp + 4) * 2 + (variant == 1 ? g * (8 + 8 + (precision == USFFT_FP64 ? 8 : 4)) : 0);
 }
@@ -279,10 +290,12 @@ __device__ void assemble(const PdeDev& P, const double* coef, const EW& ew, DT* 
   const double* txL = P.tab;                  // x1 factor, lower triangles
   const double* txU = P.tab + (size_t)d * n;  // x1 factor, upper triangles
   // the row factors are wave-uniform and read-only: scalar loads through the
-  // constant address space
+  // constant address space, from the padded copies where the CB + 1 rows of
+  // a block are contiguous
   typedef const __attribute__((address_space(4))) double* cdp;
-  const cdp tyL = (cdp)(P.tab + (size_t)2 * d * n);
-  const cdp tyU = (cdp)(P.tab + (size_t)3 * d * n);
+  const int S = row_tab_pitch(n);
+  const cdp tyL = (cdp)(P.tab + (size_t)4 * d * n);
+  const cdp tyU = tyL + (size_t)d * S;
   for (int c0 = 0; c0 == 0 || c0 + 1 < n; c0 += 63) {
     const int ci = c0 + lane;
     const bool act = ci < n, outp = act && (c0 == 0 || lane >= 1);
@@ -299,14 +312,16 @@ __device__ void assemble(const PdeDev& P, const double* coef, const EW& ew, DT* 
         const double ck = coef[k];
         const double txl = txL[k * n + cic], txu = txU[k * n + cic];
         const double xl = act ? ck * txl : 0.0, xu = act ? ck * txu : 0.0;
-        // rows outside [0, n) are clamped (their values are never used); all
-        // row factors of one k are loaded before any is used
+        // rows cb - 1 .. cb - 1 + CB are entries cb .. cb + CB < S of the
+        // padded rows (rows outside [0, n) repeat the end rows; their values
+        // are never used); all row factors of one k are loaded before any is
+        // used
+        const cdp yLk = tyL + k * S + cb, yUk = tyU + k * S + cb;
         double yl[CB + 1], yu[CB + 1];
 #pragma unroll
         for (int u = 0; u <= CB; ++u) {
-          const int cj = min(max(cb - 1 + u, 0), n - 1);
-          yl[u] = tyL[k * n + cj];
-          yu[u] = tyU[k * n + cj];
+          yl[u] = yLk[u];
+          yu[u] = yUk[u];
         }
 #pragma unroll
         for (int u = 0; u <= CB; ++u) {
@@ -574,7 +589,9 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
 
 // Float32 solves in a compact LDS footprint, so that two workgroups (MP = 64)
 // share a CU and hide each other's barrier and LDS latency.  LDS holds one
-// overlay region of GE doubles and the float32 Jacobi scaling:
+// overlay region of GE doubles, the float32 Jacobi scaling and the
+// sample's preconditioner diagonal 1 / (lam_a + lam_b + shift) (one
+// reciprocal per entry per sample instead of one per entry per application):
 //   assembly:     float32 edge grids eh, ev (the float64 edges go to this
 //                 workgroup's slot of the global scratch),
 //   iterations:   float32 search direction (zero halo) + exchange tiles,
@@ -610,6 +627,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
   float* feh = sp;                                         // overlay: float32 edges
   float* fev = sp + GE;
   float* dg = reinterpret_cast<float*>(lds + GE);          // D^-1/2
+  float* ilam = dg + GE;                                   // 1 / (lam_a + lam_b + shift)
   double* geh = wscr + (size_t)blockIdx.x * 2 * wstride;   // float64 edges
   double* gev = geh + wstride;
 
@@ -672,9 +690,13 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
     }
     block_sum2<BLOCK>(bb, rs, red0);  // every lane is done with the edge grids
     const float shift = potential_shift(rs, m);
+    // the diagonal of this sample's preconditioner; the first read follows
+    // the barrier inside dst_apply
+    for (int i = tid; i < MP * MP; i += BLOCK)
+      ilam[(i / MP) * dst_ilam_pitch(MP) + i % MP] = __builtin_amdgcn_rcpf(slam[i % MP] + slam[i / MP] + shift);
     zero_ring(sp);
     float z[E];
-    dst_apply<MP, float>(r, pow2_scale(bb), z, sf, xa, xb, slam, shift);
+    dst_apply<MP, float, true>(r, pow2_scale(bb), z, sf, xa, xb, slam, shift, ilam);
     double rz = 0.0, rr = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -693,17 +715,20 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
 #pragma unroll
       for (int e = 0; e < E; ++e) spl[off(e)] = p[e];
       __syncthreads();
-      float qv[E];
-      double pq = 0.0, rq = 0.0, qq = 0.0;
+      // each lane sums its E terms in float32 (the float64 true residual
+      // decides convergence; these only steer the float32 recursion), the
+      // block reduction runs in float64
+      float qv[E], pqf = 0.0f, rqf = 0.0f, qqf = 0.0f;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int o = off(e);
         const float wn = (e & 3) == 3 ? wN4[e >> 2] : wS[e + 1];
         qv[e] = 4.0f * p[e] - (wE[e] * spl[o + 1] + wW[e] * spl[o - 1] + wn * spl[o + PP] + wS[e] * spl[o - PP]);
-        pq += (double)(p[e] * qv[e]);
-        rq += (double)r[e] * (double)qv[e];
-        qq += (double)qv[e] * (double)qv[e];
+        pqf = fmaf(p[e], qv[e], pqf);
+        rqf = fmaf(r[e], qv[e], rqf);
+        qqf = fmaf(qv[e], qv[e], qqf);
       }
+      double pq = pqf, rq = rqf, qq = qqf;
       block_sum3<BLOCK>(pq, rq, qq, red0);
       const double alpha = rz / pq;
       const float af = (float)alpha;
@@ -749,13 +774,14 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
         zero_ring(sp);
         rr = rr_ref = rr64;
       }
-      dst_apply<MP, float>(r, pow2_scale(rr), z, sf, xa, xb, slam, shift);
-      double rz2 = 0.0, rre = 0.0;
+      dst_apply<MP, float, true>(r, pow2_scale(rr), z, sf, xa, xb, slam, shift, ilam);
+      float rzf = 0.0f, rrf = 0.0f;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        rz2 += (double)r[e] * (double)z[e];
-        rre += (double)r[e] * (double)r[e];
+        rzf = fmaf(r[e], z[e], rzf);
+        rrf = fmaf(r[e], r[e], rrf);
       }
+      double rz2 = rzf, rre = rrf;
       block_sum2<BLOCK>(rz2, rre, red1);
       rr = rre;
       const float beta = (float)(rz2 / rz);

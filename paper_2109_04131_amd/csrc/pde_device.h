@@ -7,7 +7,8 @@ namespace usfft {
 
 // Centroid value of a on the lower (q=0) / upper (q=1) triangle of cell (ci, cj).
 // tab holds sin(m1 pi x1), sin(m2 pi x2) at the centroid abscissae:
-// [0] x1 of lower, [1] x1 of upper, [2] x2 of lower, [3] x2 of upper; each d x n.
+// [0] x1 of lower, [1] x1 of upper, [2] x2 of lower, [3] x2 of upper; each d x n;
+// then [2] and [3] again, each d x row_tab_pitch(n) with padded rows.
 // The lognormal model exponentiates the sum (Sec. 1).
 __device__ __forceinline__ double tri_coef(const PdeDev& P, const double* coef, int q, int ci, int cj) {
   const double* tx = P.tab + (size_t)(q) * P.d * P.n;

@@ -927,7 +927,8 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     P->prob.mode2 = P->mode2.data();
     // sin or cos(m pi x) at the centroid abscissae: lower triangle (i+2/3, j+1/3) h,
     // upper triangle (i+1/3, j+2/3) h of cell (i, j)
-    std::vector<double> tab((size_t)4 * d * n);
+    const int S = usfft::row_tab_pitch(n);
+    std::vector<double> tab((size_t)4 * d * n + (size_t)2 * d * S);
     const double h = 1.0 / n;
     auto b1 = [&](double v) { return pb->basis1 == 1 ? std::cos(v) : std::sin(v); };
     auto b2 = [&](double v) { return pb->basis2 == 1 ? std::cos(v) : std::sin(v); };
@@ -938,6 +939,11 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
         tab[(size_t)(2 * d + k) * n + c] = b2(P->mode2[k] * M_PI * (c + 1.0 / 3.0) * h);
         tab[(size_t)(3 * d + k) * n + c] = b2(P->mode2[k] * M_PI * (c + 2.0 / 3.0) * h);
       }
+    for (int q = 0; q < 2; ++q)
+      for (int k = 0; k < d; ++k)
+        for (int e = 0; e < S; ++e)
+          tab[(size_t)4 * d * n + (size_t)(q * d + k) * S + e] =
+              tab[(size_t)((2 + q) * d + k) * n + std::min(std::max(e - 1, 0), n - 1)];
     P->d_amp.ensure(sizeof(double) * d);
     P->d_tab.ensure(sizeof(double) * tab.size());
     USFFT_HIP(hipMemcpy(P->d_amp.p, P->amp.data(), sizeof(double) * d, hipMemcpyHostToDevice));
