@@ -715,9 +715,8 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
 #pragma unroll
       for (int e = 0; e < E; ++e) spl[off(e)] = p[e];
       __syncthreads();
-      // each lane sums its E terms in float32 (the float64 true residual
-      // decides convergence; these only steer the float32 recursion), the
-      // block reduction runs in float64
+      // these sums only steer the float32 recursion (the float64 true
+      // residual decides convergence): float32 throughout
       float qv[E], pqf = 0.0f, rqf = 0.0f, qqf = 0.0f;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -728,8 +727,8 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
         rqf = fmaf(r[e], qv[e], rqf);
         qqf = fmaf(qv[e], qv[e], qqf);
       }
-      double pq = pqf, rq = rqf, qq = qqf;
-      block_sum3<BLOCK>(pq, rq, qq, red0);
+      block_sum3<BLOCK>(pqf, rqf, qqf, reinterpret_cast<float*>(red0));
+      const double pq = pqf, rq = rqf, qq = qqf;
       const double alpha = rz / pq;
       const float af = (float)alpha;
 #pragma unroll
@@ -781,8 +780,8 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
         rzf = fmaf(r[e], z[e], rzf);
         rrf = fmaf(r[e], r[e], rrf);
       }
-      double rz2 = rzf, rre = rrf;
-      block_sum2<BLOCK>(rz2, rre, red1);
+      block_sum2<BLOCK>(rzf, rrf, reinterpret_cast<float*>(red1));
+      const double rz2 = rzf, rre = rrf;
       rr = rre;
       const float beta = (float)(rz2 / rz);
       rz = rz2;
