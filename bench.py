@@ -148,7 +148,8 @@ def measured_traffic():
     only while the solver source is the one the counters were taken on."""
     import hashlib
     import re
-    srcs = [os.path.join(ROOT, "paper_2109_04131_amd", "csrc", f) for f in ("pcgdst.hip", "pde_device.h")]
+    srcs = [os.path.join(ROOT, "paper_2109_04131_amd", "csrc", f)
+            for f in ("pcgdst.hip", "pde_device.h", "kernels.h", "common.h")]
     prof = os.path.join(ROOT, "profiles", "pcgdst32c_mesh64_d10_hbm_counters.md")
     try:
         text = open(prof).read()
