@@ -5,8 +5,11 @@
 // tau_g^2, the s~-th largest squared magnitude of column g (with
 // multiplicity), is found by an exact MSB-first radix select on the bit
 // patterns of the non-negative float64 values (their unsigned order is the
-// numeric order): 8 passes of 8-bit digits with an LDS histogram, over the
-// column staged once in LDS when it fits.  A
+// numeric order): up to 8 passes of 8-bit digits with an LDS histogram, over
+// the column staged once in LDS when it fits.  As soon as at most kSelFew keys
+// share the digits fixed so far, they are gathered and ranked pairwise, which
+// fixes the remaining bits at once (the digits of the first passes are mostly
+// exponent bits; after two or three passes few keys remain).  A
 // candidate is kept when v >= max(theta^2, (1 - tie) tau_g^2); each wave ORs
 // its 64 keep bits into the global candidate mask, with an atomic only for
 // bits not yet set.
@@ -17,6 +20,7 @@ namespace usfft {
 constexpr int kSelBlock = 256;
 
 constexpr int kSelLds = 8192;  // columns up to this length are staged in LDS (64 KB)
+constexpr int kSelFew = 64;    // candidate count that ends the radix passes
 
 template <bool STAGE>
 __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restrict__ v, int64_t G, int64_t n,
@@ -27,6 +31,8 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
   __shared__ uint32_t hist[256];
   __shared__ uint64_t s_prefix;
   __shared__ int64_t s_rank;
+  __shared__ uint32_t s_cnt, s_nfew;
+  __shared__ uint64_t few[kSelFew];
   const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
   const uint64_t* gkeys = reinterpret_cast<const uint64_t*>(v + g * ld);
   if (STAGE) {
@@ -84,6 +90,7 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
             if (acc + h[i] >= rank) {
               s_prefix = prefix | ((uint64_t)(255 - 4 * l - i) << shift);
               s_rank = rank - acc;
+              s_cnt = h[i];  // keys that match the new prefix, rank <= h[i]
               break;
             }
             acc += h[i];
@@ -93,7 +100,36 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
       __syncthreads();
       prefix = s_prefix;
       rank = s_rank;
+      const uint32_t cnt = s_cnt;
+      if (threadIdx.x == 0) s_nfew = 0;
       __syncthreads();
+      if (shift > 0 && cnt <= (uint32_t)kSelFew) {
+        // the cnt keys whose bits from `shift` up equal the prefix; the
+        // rank-th largest of them (with multiplicity) is the key k with
+        // #{> k} < rank <= #{>= k}
+        const uint64_t fmask = ~0ull << shift;
+        for (int64_t a = threadIdx.x; a < n; a += kSelBlock) {
+          const uint64_t k = keys[a];
+          if ((k & fmask) == prefix) {
+            const uint32_t i = atomicAdd(&s_nfew, 1u);
+            if (i < (uint32_t)kSelFew) few[i] = k;
+          }
+        }
+        __syncthreads();
+        if (threadIdx.x < cnt) {
+          const uint64_t k = few[threadIdx.x];
+          uint32_t gt = 0, ge = 0;
+          for (uint32_t j = 0; j < cnt; ++j) {
+            const uint64_t o = few[j];
+            gt += o > k;
+            ge += o >= k;
+          }
+          if ((int64_t)gt < rank && rank <= (int64_t)ge) s_prefix = k;  // equal keys write the same value
+        }
+        __syncthreads();
+        prefix = s_prefix;
+        break;
+      }
     }
     tau2 = __longlong_as_double((long long)prefix);
   }
