@@ -10,6 +10,11 @@ import os
 import sys
 
 import numpy as np
+# PyTorch ships its own HIP runtime under the soname the library links
+# against.  Loading torch first lets the library bind to that runtime, so the
+# process holds one HIP runtime; loaded the other way round, both runtimes end
+# up mapped and torch then finds no GPU.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libusfft.so")

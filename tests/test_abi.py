@@ -2,6 +2,7 @@
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -42,3 +43,13 @@ def test_binding_loads_and_covers_abi(built):
     import paper_2109_04131_amd as U
     assert U.version().startswith("usfft")
     assert set(U.EXPORTED) == set(declared())
+
+
+def test_binding_shares_torchs_hip_runtime(built):
+    # one HIP runtime per process: the library binds to the one PyTorch
+    # ships (same soname), whichever module the caller imports first
+    code = ("import paper_2109_04131_amd\n"
+            "m = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(m))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True).stdout
+    assert out.strip() == "1"
