@@ -296,6 +296,36 @@ def test_select_bit_exact(lib, n, G, s):
     assert np.array_equal(host(thr), thr_ref)
 
 
+@pytest.mark.parametrize("kind,n,G,s", [("low_bits", 4500, 12, 200), ("mid_bits", 4500, 7, 200),
+                                         ("duplicates", 100, 9, 30), ("duplicates", 3000, 5, 200),
+                                         ("one_binade", 700, 6, 64)])
+def test_select_bit_exact_hard_keys(lib, kind, n, G, s):
+    # keys that agree in their leading bytes (the radix passes run long, the
+    # small-set finish starts late or never) and many equal keys (the rank
+    # with multiplicity)
+    g = np.random.default_rng(len(kind) + n + G)
+    if kind == "low_bits":  # steps below the tie band
+        V = 1.0 + g.integers(0, 300, (n, G)) * 2.0 ** -44
+    elif kind == "mid_bits":  # steps above it, keys agree in their top three bytes
+        V = 1.0 + g.integers(0, 300, (n, G)) * 2.0 ** -28
+    elif kind == "duplicates":
+        V = g.integers(1, 5, (n, G)).astype(np.float64)
+    else:
+        V = 1.0 + g.random((n, G))
+    theta2 = 1e-3
+    mask_ref, thr_ref, _ = osel.detect_mask(V, s, theta2)
+    ld = n + 3
+    Vd = np.zeros((G, ld))
+    Vd[:, :n] = V.T
+    mask = torch.zeros((n + 31) // 32 + 1, dtype=torch.int32, device="cuda")
+    thr = torch.zeros(G, dtype=torch.float64, device="cuda")
+    lib.select(dev(Vd), G, n, ld, s, dev(np.array([theta2])), osel.TIE_REL, mask, thr)
+    m = host(mask).view(np.uint32)
+    bits = np.array([(m[a >> 5] >> (a & 31)) & 1 for a in range(n)], dtype=bool)
+    assert np.array_equal(bits, mask_ref)
+    assert np.array_equal(host(thr), thr_ref)
+
+
 # ------------------------------------------------------------------ sets
 def test_product_and_compact_bit_exact(lib):
     parent, child = W.candidate_set(2, 60, 4, 9)
