@@ -1,5 +1,6 @@
 """Whole-driver pins: exact recovery of seeded sparse trigonometric polynomials
-(the event of Theorem 1.1) and invariants of the PDE run."""
+(the event of Theorem 1.1), the PDE run against the Fourier coefficients it
+approximates (full-grid DFT of the solves), and invariants of the PDE run."""
 import numpy as np
 import pytest
 
@@ -93,3 +94,49 @@ def test_degenerate_runs(case):
     idx = {tuple(k): a for a, k in enumerate(K.tolist())}
     for a, k in enumerate(res.I.tolist()):
         assert np.allclose(res.C[a], P[idx[tuple(k)]], rtol=0, atol=1e-12)
+
+
+def _full_grid_coefficients(S, d, P):
+    """c_k(x_g) of t -> u(x_g, t) by the plain d-dimensional DFT of the solves
+    on the full grid (j / P)^d: exact up to aliasing from |k|_inf >= P / 2."""
+    ax = np.arange(P) / P
+    grid = np.stack(np.meshgrid(*([ax] * d), indexing="ij"), -1).reshape(-1, d)
+    U = S(grid)
+    return np.fft.fftn(U.reshape((P,) * d + (S.G,)), axes=tuple(range(d))) / P ** d
+
+
+@pytest.mark.parametrize("d,N,P,theta", [(2, 12, 64, 1e-5), (2, 12, 64, 1e-7), (3, 10, 32, 1e-5)])
+def test_pde_run_against_full_grid_fourier_coefficients(d, N, P, theta):
+    # What the PDE run approximates, by its definition: the Fourier
+    # coefficients of the parametric solution (Sec. 1), here from a full
+    # tensor grid (for this smooth coefficient they fall below 1e-11 at
+    # |k|_inf = P / 2, so the grid values stand for the true ones to ~1e-11).
+    #  - step 3 reads c_k from a lattice on which k aliases with no other
+    #    frequency of I, so its error is at most the l1 norm T_g of the
+    #    coefficients outside I;
+    #  - the final selection keeps a frequency only where its computed value
+    #    reaches theta, so its true value is at least theta - T_g there;
+    #  - every frequency of the box whose coefficient is ten times theta is
+    #    detected.
+    # A conjugated transform, a lost 1/M, a shifted node or a dropped stage
+    # breaks the first bound by orders of magnitude.
+    prob = W.pde_problem(8, d, N)
+    S = fem.PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    res = usfft(S, d, prob["k_lo"], prob["k_hi"], 100, 100, 3, theta, True, 5)
+    F = _full_grid_coefficients(S, d, P)
+    slack = 1e-10
+    I = [tuple(k) for k in res.I.tolist()]
+    cell = lambda k: tuple(v % P for v in k)
+    outside = np.ones((P,) * d, dtype=bool)
+    for k in I:
+        outside[cell(k)] = False
+    T = np.abs(F)[outside].sum(axis=0)  # (G,)
+    th = np.sqrt(res.theta2)
+    for a, k in enumerate(I):
+        ck = F[cell(k)]
+        assert (np.abs(res.C[a] - ck) <= T + slack).all(), k
+        assert (np.abs(ck) + T + slack).max() >= th, k
+    big = [k for k in np.ndindex(*([2 * N + 1] * d))
+           if np.abs(F[cell([v - N for v in k])]).max() >= 10 * th]
+    assert {tuple(v - N for v in k) for k in big} <= set(I)
+    assert len(big) > 10
