@@ -407,9 +407,8 @@ def test_detect_pde_cpu_scale_fp64(lib):
     assert abs(res.stats["theta_abs"] ** 2 - ref.theta2) <= 1e-12 * ref.theta2
 
 
-def flips_within(I_gpu, I_ref, stages, band):
-    """Candidates that differ between the sets must lie within `band` of their
-    stage threshold in the oracle's values (returns the list of flips)."""
+def set_flips(I_gpu, I_ref):
+    """Frequencies that are in one of the two detected sets only."""
     a = {tuple(k) for k in I_gpu}
     b = {tuple(k) for k in I_ref}
     return sorted(a ^ b)
@@ -419,10 +418,49 @@ def test_detect_pde_cpu_scale_fp32_refine(lib):
     prob, par = W.WORKLOADS["cpu16_d4"]
     res, ref = run_both(lib, prob, par, 7, precision=1)
     I = res.freqs().tolist()
-    diff = flips_within(I, ref.I.tolist(), ref.stages, 0.01)
+    diff = set_flips(I, ref.I.tolist())
     assert not diff, diff
     C = res.coeffs()
     assert np.abs(C - ref.C).max() <= 1e-6 * np.abs(ref.C).max()
+
+
+def full_grid_coefficients(S, d, P):
+    """c_k(x_g) by the plain DFT of the oracle's solves on the full grid (j / P)^d."""
+    ax = np.arange(P) / P
+    grid = np.stack(np.meshgrid(*([ax] * d), indexing="ij"), -1).reshape(-1, d)
+    U = S(grid)
+    return np.fft.fftn(U.reshape((P,) * d + (S.G,)), axes=tuple(range(d))) / P ** d
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_detect_pde_against_full_grid_fourier_coefficients(lib, precision):
+    # the HIP path's run against the coefficients it approximates (d = 2; the
+    # grid coefficients fall below 1e-11 at |k|_inf = 32): step-3 values
+    # within the l1 norm T_g of the coefficients outside I, kept frequencies
+    # at least theta - T_g, every frequency above 10 theta detected; float32
+    # samples add their rounding (the 1e-6 coefficient tolerance)
+    d, N, P = 2, 12, 64
+    prob = W.pde_problem(8, d, N)
+    par = W.params(100, 3, 1e-5)
+    plan = lib.Plan(prob, dict(par, precision=precision, pcg_rtol=1e-13 if precision == 0 else 1e-12))
+    res = lib.detect(plan, 5)
+    F = full_grid_coefficients(oracle_sampler(prob), d, P)
+    slack = 1e-10 if precision == 0 else 1e-6 * np.abs(F).max()
+    I = [tuple(k) for k in res.freqs().tolist()]
+    C = res.coeffs()
+    cell = lambda k: tuple(v % P for v in k)
+    outside = np.ones((P,) * d, dtype=bool)
+    for k in I:
+        outside[cell(k)] = False
+    T = np.abs(F)[outside].sum(axis=0)
+    th = res.stats["theta_abs"]
+    for a, k in enumerate(I):
+        ck = F[cell(k)]
+        assert (np.abs(C[a] - ck) <= T + slack).all(), k
+        assert (np.abs(ck) + T + slack).max() >= th, k
+    big = {(a - N, b - N) for a in range(2 * N + 1) for b in range(2 * N + 1)
+           if np.abs(F[cell((a - N, b - N))]).max() >= 10 * th}
+    assert big <= set(I) and len(big) > 10
 
 
 def test_detect_is_deterministic(lib):
