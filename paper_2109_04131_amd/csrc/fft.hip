@@ -526,14 +526,13 @@ void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t
 
 // ---------------------------------------------------------------- line DFT
 constexpr int kLineMax = 1024;
+// The DFT of one node's line samples u[g ld + col0 + l], l < K, at the bins
+// given (the canonical half spectrum: bins b and K - b are exact conjugates).
 template <typename T>
-__global__ __launch_bounds__(256) void line_dft_kernel(const T* __restrict__ u, int64_t G, int64_t ld, int64_t col0,
-                                                       int K, const int32_t* __restrict__ bins, int nb,
-                                                       int out_kind, void* __restrict__ out, int64_t ldo) {
-  __shared__ double x[kLineMax];
-  __shared__ double cs[kLineMax];
-  __shared__ double sn[kLineMax];
-  const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void line_dft_node(const T* __restrict__ u, int64_t g, int64_t G, int64_t ld,
+                                              int64_t col0, int K, const int32_t* __restrict__ bins, int nb,
+                                              int out_kind, void* __restrict__ out, int64_t ldo, double* x,
+                                              double* cs, double* sn) {
   for (int l = threadIdx.x; l < K; l += 256) {
     x[l] = (double)u[g * ld + col0 + l];
     double s, c;
@@ -565,6 +564,53 @@ __global__ __launch_bounds__(256) void line_dft_kernel(const T* __restrict__ u, 
       o[((int64_t)a * G + g) * 2 + 1] = im;
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void line_dft_kernel(const T* __restrict__ u, int64_t G, int64_t ld, int64_t col0,
+                                                       int K, const int32_t* __restrict__ bins, int nb,
+                                                       int out_kind, void* __restrict__ out, int64_t ldo) {
+  __shared__ double x[kLineMax];
+  __shared__ double cs[kLineMax];
+  __shared__ double sn[kLineMax];
+  line_dft_node(u, xcd_remap(blockIdx.x, gridDim.x), G, ld, col0, K, bins, nb, out_kind, out, ldo, x, cs, sn);
+}
+
+// All step-1 lines in one launch: blockIdx.y = line y of coordinate
+// t = y / line_r, samples from column loff[y], its K_t = lineK[t] candidates
+// cands[sum_{j<t} K_j ..] at every bin, |.|^2 to columns y * line_stride ..
+// of out (leading dimension ldo).
+template <typename T>
+__global__ __launch_bounds__(256) void line_dft_lines_kernel(const T* __restrict__ u, int64_t G, int64_t ld,
+                                                             const int64_t* __restrict__ loff,
+                                                             const int32_t* __restrict__ lineK,
+                                                             const int32_t* __restrict__ cands, int line_r,
+                                                             int64_t line_stride, double* __restrict__ out,
+                                                             int64_t ldo) {
+  __shared__ double x[kLineMax];
+  __shared__ double cs[kLineMax];
+  __shared__ double sn[kLineMax];
+  const int y = blockIdx.y, t = y / line_r;
+  int64_t coff = 0;
+  for (int j = 0; j < t; ++j) coff += lineK[j];
+  const int K = lineK[t];
+  line_dft_node(u, xcd_remap(blockIdx.x, gridDim.x), G, ld, loff[y], K, cands + coff, K, USFFT_OUT_MAG2,
+                out + (int64_t)y * line_stride, ldo, x, cs, sn);
+}
+
+void launch_line_dft_lines(const void* u, int u_fp32, int64_t G, int64_t ld, const int64_t* loff,
+                           const int32_t* lineK, const int32_t* cands, int nlines, int line_r, int Kmax,
+                           int64_t line_stride, double* out, int64_t ldo, hipStream_t st) {
+  USFFT_REQUIRE(Kmax >= 1 && Kmax <= kLineMax && line_stride >= Kmax, USFFT_EINVAL, "line DFT length out of range");
+  if (G <= 0 || nlines <= 0) return;
+  const dim3 grid((unsigned)G, (unsigned)nlines);
+  if (u_fp32)
+    hipLaunchKernelGGL(line_dft_lines_kernel<float>, grid, dim3(256), 0, st, (const float*)u, G, ld, loff, lineK,
+                       cands, line_r, line_stride, out, ldo);
+  else
+    hipLaunchKernelGGL(line_dft_lines_kernel<double>, grid, dim3(256), 0, st, (const double*)u, G, ld, loff, lineK,
+                       cands, line_r, line_stride, out, ldo);
+  USFFT_HIP(hipGetLastError());
 }
 
 void launch_line_dft(const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0, int K, const int32_t* bins,

@@ -110,10 +110,21 @@ void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t
                         int64_t ldo, hipStream_t st);
 // mask_out bit pos[q] |= mask_in bit q, q < n (grouped order back to candidate order).
 void launch_ungroup_mask(const uint32_t* mask_in, const int32_t* pos, int64_t n, uint32_t* mask_out, hipStream_t st);
+// all d r step-1 lines at once: line y (coordinate t = y / line_r) from column
+// loff[y], K_t = lineK[t] bins from cands (coordinates in order), |X|^2 to
+// columns y * line_stride of out (G x ldo, doubles)
+void launch_line_dft_lines(const void* u, int u_fp32, int64_t G, int64_t ld, const int64_t* loff,
+                           const int32_t* lineK, const int32_t* cands, int nlines, int line_r, int Kmax,
+                           int64_t line_stride, double* out, int64_t ldo, hipStream_t st);
 void launch_line_dft(const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0, int K, const int32_t* bins,
                      int nb, int out_kind, void* out, int64_t ldo, hipStream_t st);
 
 // ---- select.hip
+// the step-1 lines of launch_line_dft_lines in one launch; line y ORs into
+// the mask words of its coordinate (after those of the coordinates before)
+void launch_select_lines(const double* v, int64_t G, int64_t ld, int nlines, int line_r, int64_t line_stride,
+                         const int32_t* lineK, int Kmax, int s_tilde, const double* theta2, double tie_rel,
+                         uint32_t* mask, hipStream_t st);
 void launch_select(const double* v, int64_t G, int64_t n, int64_t ld, int s_tilde, const double* theta2,
                    double tie_rel, uint32_t* mask, double* thr, hipStream_t st);
 void launch_max_to_theta(const double* v, int64_t G, int64_t n, int64_t ld, double theta, double* theta2,
@@ -129,7 +140,9 @@ void launch_lattice_bins(const int32_t* J, int64_t n, int t, const int32_t* z, i
                          int32_t* counts, hipStream_t st);
 void launch_lattice_score(const int32_t* bins, const int32_t* counts, const uint8_t* covered, int64_t n, int T,
                           int M, int32_t* scores, hipStream_t st);
-void launch_lattice_z(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, int32_t* z, hipStream_t st);
+// also clears counts (T x M) and scores (T) for the attempt
+void launch_lattice_z(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, int32_t* z, int32_t* counts,
+                      int32_t* scores, hipStream_t st);
 // device choice of one attempt (state: uncovered, taken; log: best, freed) and its commit
 void launch_lattice_pick_take(const int32_t* scores, int T, int64_t* state, int32_t* log, const int32_t* bins,
                               const int32_t* counts, uint8_t* covered, int64_t n, int M, int32_t* assign,

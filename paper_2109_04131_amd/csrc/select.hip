@@ -22,11 +22,25 @@ constexpr int kSelBlock = 256;
 constexpr int kSelLds = 8192;  // columns up to this length are staged in LDS (64 KB)
 constexpr int kSelFew = 64;    // candidate count that ends the radix passes
 
+// One column block per launch, or (lineK != null) the step-1 lines in one
+// launch: blockIdx.y = line y of coordinate t = y / line_r, its K_t = lineK[t]
+// candidates in columns y * line_stride .. of v, its mask words after those
+// of the coordinates before t.
 template <bool STAGE>
 __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restrict__ v, int64_t G, int64_t n,
                                                            int64_t ld, int s_tilde,
                                                            const double* __restrict__ theta2p, double tie_rel,
-                                                           uint32_t* __restrict__ mask, double* __restrict__ thr_out) {
+                                                           uint32_t* __restrict__ mask, double* __restrict__ thr_out,
+                                                           const int32_t* __restrict__ lineK, int line_r,
+                                                           int64_t line_stride) {
+  if (lineK) {
+    const int y = blockIdx.y, t = y / line_r;
+    int64_t w = 0;
+    for (int j = 0; j < t; ++j) w += (lineK[j] + 31) / 32;
+    n = lineK[t];
+    v += (int64_t)y * line_stride;
+    mask += w;
+  }
   extern __shared__ uint64_t stage[];
   __shared__ uint32_t hist[256];
   __shared__ uint64_t s_prefix;
@@ -161,10 +175,21 @@ void launch_select(const double* v, int64_t G, int64_t n, int64_t ld, int s_tild
   if (G <= 0 || n <= 0) return;
   if (n <= kSelLds)
     hipLaunchKernelGGL(select_kernel<true>, dim3((unsigned)G), dim3(kSelBlock), (size_t)n * sizeof(uint64_t), st, v,
-                       G, n, ld, s_tilde, theta2, tie_rel, mask, thr);
+                       G, n, ld, s_tilde, theta2, tie_rel, mask, thr, nullptr, 1, 0);
   else
     hipLaunchKernelGGL(select_kernel<false>, dim3((unsigned)G), dim3(kSelBlock), 0, st, v, G, n, ld, s_tilde,
-                       theta2, tie_rel, mask, thr);
+                       theta2, tie_rel, mask, thr, nullptr, 1, 0);
+  USFFT_HIP(hipGetLastError());
+}
+
+void launch_select_lines(const double* v, int64_t G, int64_t ld, int nlines, int line_r, int64_t line_stride,
+                         const int32_t* lineK, int Kmax, int s_tilde, const double* theta2, double tie_rel,
+                         uint32_t* mask, hipStream_t st) {
+  if (G <= 0 || nlines <= 0) return;
+  USFFT_REQUIRE(Kmax >= 1 && Kmax <= kSelLds && line_stride >= Kmax, USFFT_EINVAL, "bad line selection shape");
+  hipLaunchKernelGGL(select_kernel<true>, dim3((unsigned)G, (unsigned)nlines), dim3(kSelBlock),
+                     (size_t)Kmax * sizeof(uint64_t), st, v, G, (int64_t)Kmax, ld, s_tilde, theta2, tie_rel, mask,
+                     nullptr, lineK, line_r, line_stride);
   USFFT_HIP(hipGetLastError());
 }
 

@@ -117,17 +117,23 @@ void launch_lattice_score(const int32_t* bins, const int32_t* counts, const uint
   USFFT_HIP(hipGetLastError());
 }
 
-// Generators of the T tries of lattice attempt a, the draws of rng::lattice_z.
+// Generators of the T tries of lattice attempt a, the draws of rng::lattice_z;
+// the same launch clears the attempt's alias counts (T x M) and scores (T).
 __global__ void lattice_z_kernel(uint64_t seed, int kind, int tcode, int a, int T, int t, int M,
-                                 int32_t* __restrict__ z) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= T * t) return;
-  z[e] = rng::lattice_z(seed, kind, tcode, a, e / t, e % t, M);
+                                 int32_t* __restrict__ z, int32_t* __restrict__ counts,
+                                 int32_t* __restrict__ scores) {
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e0 < (int64_t)T * t) z[e0] = rng::lattice_z(seed, kind, tcode, a, (int)(e0 / t), (int)(e0 % t), M);
+  if (e0 < T) scores[e0] = 0;
+  for (int64_t e = e0; e < (int64_t)T * M; e += (int64_t)gridDim.x * blockDim.x) counts[e] = 0;
 }
 
-void launch_lattice_z(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, int32_t* z, hipStream_t st) {
-  hipLaunchKernelGGL(lattice_z_kernel, dim3((unsigned)ceil_div(T * t, 64)), dim3(64), 0, st, seed, kind, tcode, a, T,
-                     t, M, z);
+void launch_lattice_z(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, int32_t* z, int32_t* counts,
+                      int32_t* scores, hipStream_t st) {
+  const int64_t work = std::max<int64_t>((int64_t)T * t, std::max<int64_t>(T, (int64_t)T * M / 8));
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(work, 256), 1024);
+  hipLaunchKernelGGL(lattice_z_kernel, dim3(grid), dim3(256), 0, st, seed, kind, tcode, a, T, t, M, z, counts,
+                     scores);
   USFFT_HIP(hipGetLastError());
 }
 

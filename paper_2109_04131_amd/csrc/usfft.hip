@@ -239,9 +239,8 @@ static void plan_family(usfft_plan_s* P, const int32_t* J, int64_t n, int t, uin
     for (int b = 0; b < nb; ++b) {
       const int a = attempt + b;
       const int M = sizes[a % sizes.size()];
-      launch_lattice_z(seed, kind, tcode, a, T, t, M, P->famz.as<int32_t>(), st);
-      USFFT_HIP(hipMemsetAsync(P->famcounts.p, 0, sizeof(int32_t) * (size_t)T * M, st));
-      USFFT_HIP(hipMemsetAsync(P->famscores.p, 0, sizeof(int32_t) * T, st));
+      launch_lattice_z(seed, kind, tcode, a, T, t, M, P->famz.as<int32_t>(), P->famcounts.as<int32_t>(),
+                       P->famscores.as<int32_t>(), st);
       launch_lattice_bins(J, n, t, P->famz.as<int32_t>(), T, M, P->fambins.as<int32_t>(),
                           P->famcounts.as<int32_t>(), st);
       launch_lattice_score(P->fambins.as<int32_t>(), P->famcounts.as<int32_t>(), P->famcov.as<uint8_t>(), n, T, M,
@@ -457,7 +456,9 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       h2d_async(P, P->cands, ks, st);
       h2d_async(P, P->latM, Kt, st);
       P->U.ensure(ub * G * ld);
-      P->V.ensure(sizeof(double) * G * Kmax);
+      const int nl = d * r;                   // step-1 lines, line (t, i) = t r + i
+      const int64_t ldv = (int64_t)nl * Kmax;  // |X|^2 of line y in columns y Kmax ..
+      P->V.ensure(sizeof(double) * G * ldv);
       P->Y.ensure(sizeof(double) * ns * d);
       P->iters.ensure(sizeof(int32_t) * ns);
       P->mask.ensure(sizeof(uint32_t) * woff[d]);
@@ -473,25 +474,22 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
                         P->Y.as<double>(), ns, st);
       sample_timed(P->Y.as<double>(), ns, ld);
       S.samples_step1 += ns;
-      for (int t = 0; t < d; ++t) {
-        const int K = Kt[t];
-        for (int i = 0; i < r; ++i) {
-          int e = tm.open(kTDft);
-          launch_line_dft(P->U.p, ufp32, G, ld, off[t * r + i], K, P->cands.as<int32_t>() + coff[t], K,
-                          USFFT_OUT_MAG2, P->V.p, K, st);
-          tm.close(kTDft, e);
-          S.dft_launches += 1;
-          if (!theta_set) {
-            launch_max_to_theta(P->V.as<double>(), G, K, K, par.theta, P->theta2.as<double>(),
-                                P->scratch.as<uint64_t>(), st);
-            theta_set = true;
-          }
-          e = tm.open(kTSelect);
-          launch_select(P->V.as<double>(), G, K, K, par.s_local, P->theta2.as<double>(), par.tie_rel,
-                        P->mask.as<uint32_t>() + woff[t], nullptr, st);
-          tm.close(kTSelect, e);
-        }
+      // every line's DFT in one launch, then every line's selection in one
+      // launch (the relative threshold comes from line (1, 1) in between)
+      int e = tm.open(kTDft);
+      launch_line_dft_lines(P->U.p, ufp32, G, ld, P->latoff.as<int64_t>(), P->latM.as<int32_t>(),
+                            P->cands.as<int32_t>(), nl, r, Kmax, Kmax, P->V.as<double>(), ldv, st);
+      tm.close(kTDft, e);
+      S.dft_launches += 1;
+      if (!theta_set) {
+        launch_max_to_theta(P->V.as<double>(), G, Kt[0], ldv, par.theta, P->theta2.as<double>(),
+                            P->scratch.as<uint64_t>(), st);
+        theta_set = true;
       }
+      e = tm.open(kTSelect);
+      launch_select_lines(P->V.as<double>(), G, ldv, nl, r, Kmax, P->latM.as<int32_t>(), Kmax, par.s_local,
+                          P->theta2.as<double>(), par.tie_rel, P->mask.as<uint32_t>(), st);
+      tm.close(kTSelect, e);
       P->scratch.ensure(32 + sizeof(int64_t) * d);
       for (int t = 0; t < d; ++t) {
         P->I1[t].ensure(sizeof(int32_t) * Kt[t]);
@@ -1400,7 +1398,8 @@ static uint64_t estimate_footprint(const usfft_problem* pb, const usfft_params* 
   for (int j = 0; j < pb->d; ++j) kmax = std::max(kmax, pb->k_hi[j] - pb->k_lo[j] + 1);
   const uint64_t J = 3ull * (uint64_t)pa->s_local * (uint64_t)std::min(kmax, 17);
   const uint64_t samples = std::min<uint64_t>(12 * J, 64ull * (uint64_t)pa->lattice_mmax) + (uint64_t)kmax;
-  return G * samples * ub + G * J * 8 + samples * (uint64_t)pb->d * 8 + (64ull << 20);
+  const uint64_t lines = G * (uint64_t)pb->d * (uint64_t)pa->r * (uint64_t)kmax * 8;  // step-1 spectra
+  return G * samples * ub + G * J * 8 + lines + samples * (uint64_t)pb->d * 8 + (64ull << 20);
 }
 
 struct Job {
