@@ -144,11 +144,9 @@ void launch_lattice_score(const int32_t* bins, const int32_t* counts, const uint
 void launch_lattice_z(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, int32_t* z, int32_t* counts,
                       int32_t* scores, hipStream_t st);
 // device choice of one attempt (state: uncovered, taken; log: best, freed) and its commit
-void launch_lattice_pick_take(const int32_t* scores, int T, int64_t* state, int32_t* log, const int32_t* bins,
-                              const int32_t* counts, uint8_t* covered, int64_t n, int M, int32_t* assign,
-                              int32_t* bin_out, hipStream_t st);
-void launch_lattice_take(const int32_t* bins, const int32_t* counts, uint8_t* covered, int64_t n, int M, int lat,
-                         int32_t* assign, int32_t* bin_out, hipStream_t st);
+void launch_lattice_pick_take(const int32_t* scores, int T, const int64_t* state_in, int64_t* state_out,
+                              int32_t* log, const int32_t* bins, const int32_t* counts, uint8_t* covered, int64_t n,
+                              int M, int32_t* assign, int32_t* bin_out, hipStream_t st);
 
 // ---- eval.hip
 // Y (n x d) holds parameters of the model; T[q * ldt + j] gets phi^{-1}(Y[j]).

@@ -137,73 +137,46 @@ void launch_lattice_z(uint64_t seed, int kind, int tcode, int a, int T, int t, i
   USFFT_HIP(hipGetLastError());
 }
 
-// The choice of one attempt on the device: the try that frees the most
-// still-uncovered candidates (lowest index on ties).  state[0] = uncovered
-// candidates, state[1] = lattices taken; log = (best, freed), freed = 0 when
-// the attempt takes nothing (no candidate freed, or none left).
-__global__ void lattice_pick_kernel(const int32_t* __restrict__ scores, int T, int64_t* __restrict__ state,
-                                    int32_t* __restrict__ log) {
-  if (threadIdx.x != 0) return;
+// The choice and commit of one attempt on the device: the try that frees
+// the most still-uncovered candidates (lowest index on ties).  Every
+// workgroup finds it from the T scores.  state_in = (uncovered candidates,
+// lattices taken) before the attempt is only read; workgroup 0 writes
+// state_out and log = (best, freed), freed = 0 when the attempt takes nothing
+// (no candidate freed, or none left).  A candidate is committed to the new
+// lattice when it was uncovered and its bin holds no other candidate.
+__global__ void lattice_pick_take_kernel(const int32_t* __restrict__ scores, int T,
+                                         const int64_t* __restrict__ state_in, int64_t* __restrict__ state_out,
+                                         int32_t* __restrict__ log, const int32_t* __restrict__ bins,
+                                         const int32_t* __restrict__ counts, uint8_t* __restrict__ covered,
+                                         int64_t n, int M, int32_t* __restrict__ assign,
+                                         int32_t* __restrict__ bin_out) {
   int best = 0;
   for (int b = 1; b < T; ++b)
     if (scores[b] > scores[best]) best = b;
-  const int freed = state[0] > 0 ? scores[best] : 0;
-  log[0] = best;
-  log[1] = freed;
-  if (freed > 0) {
-    state[0] -= freed;
-    state[1] += 1;
+  const int64_t uncovered = state_in[0], taken = state_in[1];
+  const int freed = uncovered > 0 ? scores[best] : 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    log[0] = best;
+    log[1] = freed;
+    state_out[0] = uncovered - freed;
+    state_out[1] = taken + (freed > 0 ? 1 : 0);
   }
-}
-
-// Commit the try chosen by lattice_pick_kernel (nothing when it freed none).
-__global__ void lattice_take_pick_kernel(const int32_t* __restrict__ bins, const int32_t* __restrict__ counts,
-                                         uint8_t* __restrict__ covered, int64_t n, int M,
-                                         const int32_t* __restrict__ log, const int64_t* __restrict__ state,
-                                         int32_t* __restrict__ assign, int32_t* __restrict__ bin_out) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n || log[1] == 0) return;
-  const int best = log[0];
-  const int lat = (int)state[1] - 1;
+  if (a >= n || freed == 0) return;
   const int32_t b = bins[(int64_t)best * n + a];
   if (!covered[a] && counts[(int64_t)best * M + b] == 1) {
     covered[a] = 1;
-    assign[a] = lat;
+    assign[a] = (int32_t)taken;  // index of the lattice this attempt adds
     bin_out[a] = b;
   }
 }
 
-void launch_lattice_pick_take(const int32_t* scores, int T, int64_t* state, int32_t* log, const int32_t* bins,
-                              const int32_t* counts, uint8_t* covered, int64_t n, int M, int32_t* assign,
-                              int32_t* bin_out, hipStream_t st) {
-  hipLaunchKernelGGL(lattice_pick_kernel, dim3(1), dim3(64), 0, st, scores, T, state, log);
-  USFFT_HIP(hipGetLastError());
-  if (n <= 0) return;
-  hipLaunchKernelGGL(lattice_take_pick_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, bins, counts,
-                     covered, n, M, log, state, assign, bin_out);
-  USFFT_HIP(hipGetLastError());
-}
-
-// Commit the chosen generator (bins/counts already offset to it).
-__global__ void lattice_take_kernel(const int32_t* __restrict__ bins, const int32_t* __restrict__ counts,
-                                    uint8_t* __restrict__ covered, int64_t n, int lat, int32_t* __restrict__ assign,
-                                    int32_t* __restrict__ bin_out) {
-  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n) return;
-  const int32_t b = bins[a];
-  if (!covered[a] && counts[b] == 1) {
-    covered[a] = 1;
-    assign[a] = lat;
-    bin_out[a] = b;
-  }
-}
-
-void launch_lattice_take(const int32_t* bins, const int32_t* counts, uint8_t* covered, int64_t n, int M, int lat,
-                         int32_t* assign, int32_t* bin_out, hipStream_t st) {
-  (void)M;
-  if (n <= 0) return;
-  hipLaunchKernelGGL(lattice_take_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, bins, counts, covered,
-                     n, lat, assign, bin_out);
+void launch_lattice_pick_take(const int32_t* scores, int T, const int64_t* state_in, int64_t* state_out,
+                              int32_t* log, const int32_t* bins, const int32_t* counts, uint8_t* covered, int64_t n,
+                              int M, int32_t* assign, int32_t* bin_out, hipStream_t st) {
+  const unsigned grid = (unsigned)std::max<int64_t>(1, ceil_div(n, 256));
+  hipLaunchKernelGGL(lattice_pick_take_kernel, dim3(grid), dim3(256), 0, st, scores, T, state_in, state_out, log,
+                     bins, counts, covered, n, M, assign, bin_out);
   USFFT_HIP(hipGetLastError());
 }
 

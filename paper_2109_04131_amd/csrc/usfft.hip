@@ -233,7 +233,10 @@ static void plan_family(usfft_plan_s* P, const int32_t* J, int64_t n, int t, uin
   P->famz.ensure(sizeof(int32_t) * (size_t)T * t);
   P->famcounts.ensure(sizeof(int32_t) * (size_t)T * par.lattice_mmax);
   P->famlog.ensure(sizeof(int32_t) * 2 * (size_t)par.lattice_max);
-  h2d_async(P, P->famstate, std::vector<int64_t>{n, 0}, st);
+  // (uncovered, lattices taken), double-buffered: attempt a reads slot a % 2
+  // and writes slot (a + 1) % 2
+  h2d_async(P, P->famstate, std::vector<int64_t>{n, 0, 0, 0}, st);
+  int64_t* slot = P->famstate.as<int64_t>();
   for (int attempt = 0;;) {
     const int nb = std::min(kFamilyBatch, par.lattice_max - attempt);
     for (int b = 0; b < nb; ++b) {
@@ -245,14 +248,15 @@ static void plan_family(usfft_plan_s* P, const int32_t* J, int64_t n, int t, uin
                           P->famcounts.as<int32_t>(), st);
       launch_lattice_score(P->fambins.as<int32_t>(), P->famcounts.as<int32_t>(), P->famcov.as<uint8_t>(), n, T, M,
                            P->famscores.as<int32_t>(), st);
-      launch_lattice_pick_take(P->famscores.as<int32_t>(), T, P->famstate.as<int64_t>(),
+      launch_lattice_pick_take(P->famscores.as<int32_t>(), T, slot + 2 * (a & 1), slot + 2 * ((a + 1) & 1),
                                P->famlog.as<int32_t>() + 2 * a, P->fambins.as<int32_t>(),
                                P->famcounts.as<int32_t>(), P->famcov.as<uint8_t>(), n, M, assign, bins_out, st);
     }
     char* hb = back_buffer(P, 2 * sizeof(int64_t) + sizeof(int32_t) * 2 * kFamilyBatch);
     int64_t* state = reinterpret_cast<int64_t*>(hb);
     int32_t* lg = reinterpret_cast<int32_t*>(hb + 2 * sizeof(int64_t));
-    USFFT_HIP(hipMemcpyAsync(state, P->famstate.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    USFFT_HIP(hipMemcpyAsync(state, slot + 2 * ((attempt + nb) & 1), 2 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                             st));
     USFFT_HIP(hipMemcpyAsync(lg, P->famlog.as<int32_t>() + 2 * attempt, sizeof(int32_t) * 2 * nb,
                              hipMemcpyDeviceToHost, st));
     USFFT_HIP(hipStreamSynchronize(st));
