@@ -73,6 +73,35 @@ def test_first_detection_stage_full_size(lib, name, prec, tol, check):
     assert np.array_equal(host(thr), thr_ref)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solver_in_the_benchmark_launch_configuration(lib, prec):
+    """h = 1/64, d = 10, 20 000 samples in one launch with the sample layout
+    of a job (float32 samples on the float32 path), as in the benchmark's
+    step-2 launches: every persistent workgroup solves many samples in turn,
+    reusing its LDS tables, zero rings and scratch slot.  Sampled solves from
+    the first and later rounds of the persistent loop against the oracle, and
+    bitwise against the same parameter solved alone."""
+    prob, par = W.WORKLOADS["mesh64_d10"]
+    plan = lib.Plan(prob, dict(par, precision=prec, pcg_rtol=1e-12))
+    ns = 20000
+    fp32 = prec == 1
+    Y = np.random.default_rng(5).random((ns, prob["d"]))
+    U = torch.zeros((plan.G, ns), dtype=torch.float32 if fp32 else torch.float64, device="cuda")
+    it = torch.zeros(ns, dtype=torch.int32, device="cuda")
+    lib.sample(plan, dev(Y), U, 1 if fp32 else 0, ns, 0, it)
+    its = host(it)
+    assert (its > 0).all() and its.max() <= 30, (its.min(), its.max())
+    Ug = host(U)
+    S = ofem.PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    for s in (0, 255, 256, 511, 512, 7777, ns - 1):
+        U1 = torch.zeros((plan.G, 1), dtype=torch.float64, device="cuda")
+        lib.sample(plan, dev(Y[s:s + 1]), U1, 0, 1)
+        u1 = host(U1)[:, 0]
+        assert np.array_equal(Ug[:, s], u1.astype(np.float32) if fp32 else u1), s
+        ref = S.solve_one(Y[s])
+        assert np.linalg.norm(u1 - ref) <= (1e-10 if prec == 0 else 1e-9) * np.linalg.norm(ref), s
+
+
 @pytest.mark.parametrize("G,M,fp32", [(3969, 9601, 0), (3969, 9601, 1), (16129, 4801, 1), (16129, 9601, 0)])
 def test_lattice_dft_full_size(lib, G, M, fp32):
     """Lattice DFT at the full node counts and the largest lattice size; the
