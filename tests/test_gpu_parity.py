@@ -298,7 +298,10 @@ def test_select_bit_exact(lib, n, G, s):
 
 @pytest.mark.parametrize("kind,n,G,s", [("low_bits", 4500, 12, 200), ("mid_bits", 4500, 7, 200),
                                          ("duplicates", 100, 9, 30), ("duplicates", 3000, 5, 200),
-                                         ("one_binade", 700, 6, 64)])
+                                         ("one_binade", 700, 6, 64),
+                                         # columns longer than the LDS stage: keys read from global memory
+                                         ("mid_bits", 9000, 4, 200), ("duplicates", 12000, 3, 500),
+                                         ("one_binade", 8193, 3, 100)])
 def test_select_bit_exact_hard_keys(lib, kind, n, G, s):
     # keys that agree in their leading bytes (the radix passes run long, the
     # small-set finish starts late or never) and many equal keys (the rank
