@@ -400,6 +400,24 @@ def test_detect_trig_poly_exact_recovery(lib, seed, d, N, G, nf):
     assert res.stats["samples"] == ref.samples
 
 
+def test_detect_trig_poly_uneven_box(lib):
+    # a different K_t per coordinate (odd and even, asymmetric boxes): the
+    # step-1 lines of all coordinates share one DFT and one selection launch
+    K, P = W.trig_poly(4, 4, 4, 17, 31, cmin=1e-2)
+    prob = dict(sampler="poly", d=4, k_lo=[-4, -6, -5, -9], k_hi=[4, 7, 5, 9], poly_k=K, poly_c=P)
+    par = W.params(62, 4, 1e-6, relative=False)
+    res, ref = run_both(lib, prob, par, 4, sampler=TrigPolySampler(K, P))
+    I = res.freqs()
+    assert I.tolist() == ref.I.tolist()
+    support = {tuple(k) for k, row in zip(K.tolist(), P) if np.abs(row).max() > 0}
+    assert {tuple(k) for k in I.tolist()} == support
+    idx = {tuple(k): a for a, k in enumerate(K.tolist())}
+    C = res.coeffs()
+    for a, k in enumerate(I.tolist()):
+        assert np.abs(C[a] - P[idx[tuple(k)]]).max() <= 1e-12
+    assert res.stats["samples"] == ref.samples
+
+
 def test_detect_pde_cpu_scale_fp64(lib):
     prob, par = W.WORKLOADS["cpu16_d4"]
     res, ref = run_both(lib, prob, par, 7)
