@@ -106,6 +106,9 @@ struct usfft_plan_s {
   char* back = nullptr;
   size_t back_cap = 0;
   usfft::DevBuf famlog, famstate;
+  // side stream of the lattice DFTs (default priority) and its fork/join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int wblocks = 0;  // persistent workgroups of the float32 / DST solver
   bool streaming = false;  // mesh larger than the on-chip solvers hold
   bool dst = false;        // DST-preconditioned solver
@@ -123,6 +126,9 @@ struct usfft_plan_s {
     for (auto& kv : rader) usfft::rader_free(kv.second);
     if (stage) (void)hipHostFree(stage);
     if (back) (void)hipHostFree(back);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
   }
 };
 
@@ -354,6 +360,26 @@ static void accumulate_iters(usfft_plan_s* P, int64_t ns, hipStream_t st) {
   USFFT_HIP(hipGetLastError());
 }
 
+// The lattice DFTs of one stage write disjoint output columns, so they
+// alternate between the caller's stream and the plan's side stream, and the
+// tail of one launch overlaps the next.  dft_fork orders the side stream
+// after the work enqueued on st so far and returns it; dft_join orders st
+// after everything enqueued on the side stream.
+static hipStream_t dft_fork(usfft_plan_s* P, hipStream_t st) {
+  if (!P->side) {
+    USFFT_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+    USFFT_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+    USFFT_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+  }
+  USFFT_HIP(hipEventRecord(P->ev_fork, st));
+  USFFT_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+  return P->side;
+}
+static void dft_join(usfft_plan_s* P, hipStream_t st) {
+  USFFT_HIP(hipEventRecord(P->ev_join, P->side));
+  USFFT_HIP(hipStreamWaitEvent(st, P->ev_join, 0));
+}
+
 struct Timer {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
   hipStream_t st;
@@ -573,14 +599,16 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
         S.samples_step2 += nsb;
         for (int b = 0; b < nb; ++b) {
           int e = tm.open(kTDft);
+          const hipStream_t s2 = F.M.size() > 1 ? dft_fork(P, st) : st;
           for (size_t l = 0; l < F.M.size(); ++l) {
             const RaderTables& T = rader_for(P, F.M[l], st);
             const int32_t* bn = P->lists.as<int32_t>() + n + F.lat_first[l];
             launch_lattice_dft(T, P->U.p, ufp32, G, ldb, b * ns + F.off[l], bn, nullptr, F.lat_first[l],
-                               F.lat_count[l], USFFT_OUT_MAG2, P->V.p, n, st);
+                               F.lat_count[l], USFFT_OUT_MAG2, P->V.p, n, (l & 1) ? s2 : st);
             S.dft_launches += 1;
             S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 8.0;
           }
+          if (s2 != st) dft_join(P, st);
           tm.close(kTDft, e);
           e = tm.open(kTSelect);
           launch_select(P->V.as<double>(), G, n, n, s_t, P->theta2.as<double>(), par.tie_rel,
@@ -634,15 +662,17 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     sample_timed(P->Y.as<double>(), ns, ld);
     S.samples_step3 += ns;
     int e = tm.open(kTDft);
+    const hipStream_t s2 = F.M.size() > 1 ? dft_fork(P, st) : st;
     for (size_t l = 0; l < F.M.size(); ++l) {
       const RaderTables& T = rader_for(P, F.M[l], st);
       const int32_t* pos = P->lists.as<int32_t>() + F.lat_first[l];
       const int32_t* bn = P->lists.as<int32_t>() + nI + F.lat_first[l];
       launch_lattice_dft(T, P->U.p, ufp32, G, ld, F.off[l], bn, pos, 0, F.lat_count[l], USFFT_OUT_COMPLEX, R->C.p,
-                         G, st);
+                         G, (l & 1) ? s2 : st);
       S.dft_launches += 1;
       S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 16.0;
     }
+    if (s2 != st) dft_join(P, st);
     tm.close(kTDft, e);
     check_conv();
   }
