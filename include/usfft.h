@@ -16,7 +16,13 @@
  *    caller pointer beyond the call.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Work
  *    is enqueued on it; calls that must read sizes back (detect, family,
- *    compact) synchronise that stream before returning.
+ *    compact) synchronise that stream before returning.  detect and
+ *    coefficients also run lattice transforms on a side stream of the plan
+ *    (default priority), forked from `stream` and joined back to it with
+ *    events before they return.
+ *  - A plan holds workspaces and that side stream: calls on one plan must not
+ *    overlap (one thread at a time).  Different plans may run concurrently,
+ *    each on its own stream.
  *  - Index sets are int32 row-major (n x t) and lexicographically ordered
  *    where stated.  Coefficient/sample matrices are row-major with an explicit
  *    leading dimension.
