@@ -722,7 +722,12 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
       for (int e = 0; e < E; ++e) {
         const int o = off(e);
         const float wn = (e & 3) == 3 ? wN4[e >> 2] : wS[e + 1];
-        qv[e] = 4.0f * p[e] - (wE[e] * spl[o + 1] + wW[e] * spl[o - 1] + wn * spl[o + PP] + wS[e] * spl[o - PP]);
+        // a lane's rows 4q .. 4q+3 of a tile are consecutive: the row above
+        // and below come from its own registers except at the group ends
+        // (the same values the lane stored to sp before the barrier)
+        const float pN = (e & 3) == 3 ? spl[o + PP] : p[(e & 3) == 3 ? e : e + 1];
+        const float pS = (e & 3) == 0 ? spl[o - PP] : p[(e & 3) == 0 ? e : e - 1];
+        qv[e] = 4.0f * p[e] - (wE[e] * spl[o + 1] + wW[e] * spl[o - 1] + wn * pN + wS[e] * pS);
         pqf = fmaf(p[e], qv[e], pqf);
         rqf = fmaf(r[e], qv[e], rqf);
         qqf = fmaf(qv[e], qv[e], qqf);
