@@ -150,6 +150,9 @@ typedef struct {
                               meshes with mesh_n <= 65) or USFFT_PRECOND_JACOBI;
                               larger meshes always use the streaming Jacobi
                               solver                                         */
+  int32_t trace;           /* nonzero: usfft_detect keeps the detected sets of
+                              every increment (usfft_result_trace); costs one
+                              small readback per increment                  */
 } usfft_params;
 
 /* Statistics of one usfft_detect run. */
@@ -211,6 +214,15 @@ usfft_status usfft_result_info(usfft_result_t res, int64_t* n_freq, int32_t* d,
 /* freqs_host: n_freq x d int32 (lexicographic); coeffs_host: n_freq x G x 2
  * doubles (re, im), may be NULL. */
 usfft_status usfft_result_copy(usfft_result_t res, int32_t* freqs_host, double* coeffs_host);
+/* Detection trace of a usfft_detect result made with params.trace != 0: the
+ * intermediate sets of Alg. 1.  stage in [0, d): the 1-D set I^(t) of step
+ * 1&2a, t = stage + 1 (width 1, n_cand = K_t, the box extent); stage in
+ * [d, 2d - 1): the set I^(1..t) of step 2e, t = stage - d + 2 (width t,
+ * n_cand = |J_t| = |I^(1..t-1)| |I^(t)|), lexicographic.  *n receives the
+ * set size; set_host (n x width int32) may be NULL to query sizes first.
+ * Errors: EINVAL (no trace kept, stage out of range). */
+usfft_status usfft_result_trace(usfft_result_t res, int32_t stage, int64_t* n, int32_t* width,
+                                int64_t* n_cand, int32_t* set_host);
 void usfft_result_destroy(usfft_result_t res);
 
 /* Evaluation formula of Sec. 3.1 (eq. (3.1) with the model's inverse

@@ -76,6 +76,11 @@ def usfft(sampler, d, k_lo, k_hi, s, s_local, r, theta, theta_relative, seed,
     theta2 = None if theta_relative else float(theta) ** 2
 
     def record(**kw):
+        # keep ratio of every candidate: max over nodes of |c|^2 over the
+        # node's keep threshold (kept exactly when >= 1); a diagnostic that
+        # locates decisions close to the threshold, not part of the method
+        with np.errstate(divide="ignore", invalid="ignore"):
+            kw["ratio"] = (kw["V"] / kw["thr"][None, :]).max(axis=1) if kw["V"].size else np.zeros(0)
         if not keep_values:
             kw.pop("V", None)
         res.stages.append(kw)

@@ -51,7 +51,7 @@ class _Params(C.Structure):
                 ("lattice_c", C.c_double), ("lattice_tries", C.c_int32), ("lattice_max", C.c_int32),
                 ("lattice_mmax", C.c_int32), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32),
                 ("inner_rtol", C.c_double), ("refine_every", C.c_int32), ("solver_config", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("trace", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -79,6 +79,8 @@ _sigs = {
                                     C.POINTER(Stats)]),
     "usfft_result_copy": (C.c_int, [_vp, _vp, _vp]),
     "usfft_result_destroy": (None, [_vp]),
+    "usfft_result_trace": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int64), _vp]),
     "usfft_eval": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
     "usfft_statistics": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "usfft_coefficients": (C.c_int, [_vp, _vp, C.c_int64, C.c_uint64, _vp, _vp]),
@@ -150,7 +152,7 @@ def version():
 DEFAULT_PARAMS = dict(s=50, s_local=50, r=5, theta=1e-12, theta_relative=False, tie_rel=2.0 ** -30,
                       precision=FP64, lattice_c=2.0, lattice_tries=8, lattice_max=64, lattice_mmax=9601,
                       pcg_rtol=1e-12, pcg_maxit=4000, inner_rtol=2e-4, refine_every=200, solver_config=-1,
-                      precond=0)
+                      precond=0, trace=False)
 
 
 def _marshal(problem, params):
@@ -289,6 +291,21 @@ class Result:
         out = np.zeros((self.n, self.G, 2), dtype=np.float64)
         _check(_lib.usfft_result_copy(self.handle, None, out.ctypes.data if self.n else None))
         return out[..., 0] + 1j * out[..., 1]
+
+    def trace(self):
+        """usfft_result_trace: [(set (n x width int32), n_cand)] for the d
+        step-1 sets I^(t), then the d - 1 step-2 sets I^(1..t)."""
+        out = []
+        for stage in range(2 * self.d - 1):
+            n = C.c_int64()
+            w = C.c_int32()
+            nc = C.c_int64()
+            _check(_lib.usfft_result_trace(self.handle, stage, C.byref(n), C.byref(w), C.byref(nc), None))
+            a = np.zeros((n.value, w.value), dtype=np.int32)
+            _check(_lib.usfft_result_trace(self.handle, stage, C.byref(n), C.byref(w), C.byref(nc),
+                                           a.ctypes.data if a.size else None))
+            out.append((a, nc.value))
+        return out
 
     def close(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -140,6 +140,11 @@ struct usfft_result_s {
   std::vector<int32_t> I;  // n x d
   usfft::DevBuf C;         // n x G x 2 doubles
   usfft_stats stats{};
+  // detection trace (params.trace): the step-1 sets I^(t), t = 1..d, then the
+  // step-2 sets I^(1..t), t = 2..d, each with its width and candidate count
+  std::vector<std::vector<int32_t>> trace_set;
+  std::vector<int32_t> trace_width;
+  std::vector<int64_t> trace_cand;
 };
 
 namespace usfft {
@@ -531,6 +536,17 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
                                st));
       check_conv();
       for (int t = 0; t < d; ++t) P->I1n[t] = cnt[t];
+      if (par.trace) {
+        for (int t = 0; t < d; ++t) {
+          std::vector<int32_t> v((size_t)cnt[t]);
+          if (cnt[t] > 0)
+            USFFT_HIP(hipMemcpyAsync(v.data(), P->I1[t].p, sizeof(int32_t) * cnt[t], hipMemcpyDeviceToHost, st));
+          R->trace_set.push_back(std::move(v));
+          R->trace_width.push_back(1);
+          R->trace_cand.push_back(Kt[t]);
+        }
+        USFFT_HIP(hipStreamSynchronize(st));
+      }
     }
     {
       double th2 = 0;
@@ -553,6 +569,11 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       S.max_candidates = std::max(S.max_candidates, n);
       if (n == 0) {
         nprev = 0;
+        if (par.trace) {
+          R->trace_set.emplace_back();
+          R->trace_width.push_back(t + 1);
+          R->trace_cand.push_back(0);
+        }
         continue;
       }
       const int w = t + 1;
@@ -625,6 +646,16 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       check_conv();
       std::swap(P->Iprev, P->Jnext);
       nprev = cntI;
+      if (par.trace) {
+        std::vector<int32_t> v((size_t)(cntI * w));
+        if (cntI > 0) {
+          USFFT_HIP(hipMemcpyAsync(v.data(), P->Iprev.p, sizeof(int32_t) * cntI * w, hipMemcpyDeviceToHost, st));
+          USFFT_HIP(hipStreamSynchronize(st));
+        }
+        R->trace_set.push_back(std::move(v));
+        R->trace_width.push_back(w);
+        R->trace_cand.push_back(n);
+      }
     }
   }
 
@@ -1132,6 +1163,20 @@ usfft_status usfft_result_copy(usfft_result_t res, int32_t* freqs_host, double* 
   });
 }
 
+usfft_status usfft_result_trace(usfft_result_t res, int32_t stage, int64_t* n, int32_t* width, int64_t* n_cand,
+                                int32_t* set_host) {
+  return guarded([&] {
+    USFFT_REQUIRE(res && n && width && n_cand, USFFT_EINVAL, "bad trace arguments");
+    USFFT_REQUIRE(!res->trace_set.empty(), USFFT_EINVAL, "no detection trace was kept (params.trace = 0)");
+    USFFT_REQUIRE(stage >= 0 && stage < (int32_t)res->trace_set.size(), USFFT_EINVAL, "trace stage out of range");
+    const std::vector<int32_t>& v = res->trace_set[stage];
+    *width = res->trace_width[stage];
+    *n = (int64_t)v.size() / std::max(1, *width);
+    *n_cand = res->trace_cand[stage];
+    if (set_host && !v.empty()) std::memcpy(set_host, v.data(), sizeof(int32_t) * v.size());
+  });
+}
+
 void usfft_result_destroy(usfft_result_t res) { delete res; }
 
 namespace {
@@ -1149,6 +1194,7 @@ void upload_set(const usfft_result_s* res, usfft::DevBuf& I) {
   I.ensure(sizeof(int32_t) * res->I.size());
   USFFT_HIP(hipMemcpy(I.p, res->I.data(), sizeof(int32_t) * res->I.size(), hipMemcpyHostToDevice));
 }
+
 }  // namespace
 
 usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n, double* out_dev, void* stream) {

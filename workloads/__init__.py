@@ -71,6 +71,8 @@ WORKLOADS = {
     "cpu16_d4": (pde_problem(16, 4, 16, modes="diagonal"), params(50, 3, 1e-4)),
     # h = 1/64 (3969 nodes), d = 10, box [-32,32]^10, s = 200, rel. threshold 1e-5, r = 5
     "mesh64_d10": (pde_problem(64, 10, 32), params(200, 5, 1e-5)),
+    # the h = 1/64 workload's box, sparsity and threshold on the h = 1/16 mesh
+    "mesh16_d10": (pde_problem(16, 10, 32), params(200, 5, 1e-5)),
     # h = 1/128 (16129 nodes), d = 20, box [-64,64]^20, s = 500, rel. threshold 1e-6, r = 5
     "mesh128_d20": (pde_problem(128, 20, 64), params(500, 5, 1e-6)),
 }
