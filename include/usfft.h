@@ -235,6 +235,22 @@ void usfft_result_destroy(usfft_result_t res);
 usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n,
                         double* out_dev, void* stream);
 
+/* usfft_eval without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same evaluation and the same kernels, with the
+ * frequency set, the mapped points and the phase matrix of each chunk held
+ * in a fixed 64 MiB device array of the library instead of temporary
+ * buffers.  Limit: the frequency set (n_freq x d int32, padded to 256
+ * bytes) plus 64 points x (d + 2 n_freq) doubles must fit in 64 MiB, i.e.
+ * up to about 65 000 frequencies; larger results give EINVAL and leave the
+ * output untouched.  Each GPU holds one such array for the life of the
+ * process (looked up on its first call on that device), and every call on
+ * that GPU shares it: calls that overlap on one GPU (other threads, other
+ * streams) race and must be serialised by the caller.  Returns after the
+ * stream has finished.  Errors: EINVAL, EHIP. */
+usfft_status usfft_eval_noalloc(usfft_result_t res, const double* y_dev, int64_t n,
+                                double* out_dev, void* stream);
+
 /* Statistics of the approximation per node (Sec. 4, Sec. 4.1), from the
  * result's coefficients alone.  Device outputs, each may be NULL:
  *   mean_dev[2g], [2g+1]  Re, Im of E(u_usFFT(x_g, .)) = sum_k c_k D_k, with

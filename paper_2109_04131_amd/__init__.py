@@ -82,6 +82,7 @@ _sigs = {
     "usfft_result_trace": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int64), _vp]),
     "usfft_eval": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
+    "usfft_eval_noalloc": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
     "usfft_statistics": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "usfft_coefficients": (C.c_int, [_vp, _vp, C.c_int64, C.c_uint64, _vp, _vp]),
     "usfft_errors": (C.c_int, [_vp, _vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp]),
@@ -337,6 +338,11 @@ def coefficients(plan, freqs, seed, stream=None):
 
 def eval(result, y, out, stream=None):
     _check(_lib.usfft_eval(result.handle, _ptr(y), y.shape[0], _ptr(out), _stream(stream)))
+
+
+def eval_noalloc(result, y, out, stream=None):
+    """usfft_eval_noalloc: usfft_eval with the library's fixed device scratch."""
+    _check(_lib.usfft_eval_noalloc(result.handle, _ptr(y), y.shape[0], _ptr(out), _stream(stream)))
 
 
 def statistics(result, mean=None, var=None, gsi=None, stream=None):

@@ -1195,6 +1195,32 @@ void upload_set(const usfft_result_s* res, usfft::DevBuf& I) {
   USFFT_HIP(hipMemcpy(I.p, res->I.data(), sizeof(int32_t) * res->I.size(), hipMemcpyHostToDevice));
 }
 
+// Fixed scratch of usfft_eval_noalloc, for callers that cannot allocate
+// device memory.  Each GPU the library runs on holds its own copy of this
+// array for the life of the process.  Host code never uses the array's name
+// as an address: the device address is looked up once per device with
+// hipGetSymbolAddress and kept in g_noalloc_ptr.
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device.
+void* noalloc_scratch() {
+  int dev = 0;
+  USFFT_HIP(hipGetDevice(&dev));
+  USFFT_REQUIRE(dev >= 0 && dev < kMaxDevices, USFFT_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    USFFT_REQUIRE(e == hipSuccess && p, USFFT_EHIP,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_noalloc_ptr[dev] = p;
+  }
+  return g_noalloc_ptr[dev];
+}
 }  // namespace
 
 usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n, double* out_dev, void* stream) {
@@ -1215,6 +1241,40 @@ usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n, doub
       launch_phases(I.as<int32_t>(), nI, res->d, T.as<double>(), nc, m, B.as<double>(), nc, st);
       launch_evgemm_values(res->C.as<double>(), res->G, nI, B.as<double>(), nc, m, out_dev + c0 * res->G, res->G,
                            st);
+    }
+    USFFT_HIP(hipStreamSynchronize(st));
+  });
+}
+
+usfft_status usfft_eval_noalloc(usfft_result_t res, const double* y_dev, int64_t n, double* out_dev,
+                                void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(res && n >= 0 && (n == 0 || (y_dev && out_dev)), USFFT_EINVAL, "bad eval arguments");
+    if (n == 0 || res->G == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t d = res->d;
+    const int64_t nI = d ? (int64_t)res->I.size() / d : 0;
+    // scratch layout: the frequency set, then per chunk of nc points the
+    // mapped nodes (d x nc) and the phase matrix (2 nI x nc)
+    const size_t set_bytes = (sizeof(int32_t) * (size_t)(nI * d) + 255) / 256 * 256;
+    const size_t per_point = sizeof(double) * (size_t)(d + 2 * nI);
+    USFFT_REQUIRE(set_bytes + 64 * per_point <= kNoAllocScratchBytes, USFFT_EINVAL,
+                  "the result's frequency set needs " + std::to_string(set_bytes + 64 * per_point) +
+                      " bytes of scratch for one 64-point chunk; usfft_eval_noalloc holds " +
+                      std::to_string(kNoAllocScratchBytes));
+    const int64_t nc = std::min<int64_t>((int64_t)((kNoAllocScratchBytes - set_bytes) / per_point) / 64 * 64,
+                                         ceil_div(n, 64) * 64);
+    char* base = static_cast<char*>(noalloc_scratch());
+    int32_t* I = reinterpret_cast<int32_t*>(base);
+    double* T = reinterpret_cast<double*>(base + set_bytes);
+    double* B = T + d * nc;
+    if (nI > 0)
+      USFFT_HIP(hipMemcpyAsync(I, res->I.data(), sizeof(int32_t) * res->I.size(), hipMemcpyHostToDevice, st));
+    for (int64_t c0 = 0; c0 < n; c0 += nc) {
+      const int64_t m = std::min(nc, n - c0);
+      launch_node_map(y_dev + c0 * d, m, (int)d, res->model, res->alpha, res->beta, res->delta, T, nc, st);
+      launch_phases(I, nI, (int)d, T, nc, m, B, nc, st);
+      launch_evgemm_values(res->C.as<double>(), res->G, nI, B, nc, m, out_dev + c0 * res->G, res->G, st);
     }
     USFFT_HIP(hipStreamSynchronize(st));
   });
