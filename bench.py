@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "PDE sample solves/s + lattice-FFT GB/s, batched-FP32 vs plain FP64; p50/p99 job"
+HBM_GBPS = 8000.0  # MI355X HBM3E peak
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "f16_mfma": 2500.0, "f64_mfma": 78.6}  # MI355X vector / dense matrix peaks
 # Vector work of one preconditioned CG iteration on the scaled 5-point
 # operator, per node: operator 9, two dot products 4, three updates 6, the
@@ -166,25 +167,158 @@ def measured_traffic():
     return float(t.group(1))
 
 
+def host_info():
+    """Core count and CPU model of the host the oracle runs on."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info[k.strip()] = v.strip()
+    except (OSError, ValueError):
+        pass
+    try:
+        info["sched_cores"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    return info
+
+
 def cpu_baseline(prob, budget_s):
-    """Oracle solves (banded Cholesky, float64) on the host, one thread."""
+    """The float64 oracle on the host cores: banded-Cholesky solves of the
+    benchmark workload for a bounded time (all cores and one thread), and the
+    full CPU-scale job (Alg. 1 on h = 1/16, d = 4) single-threaded and on
+    all cores, with the time its naive DFTs take."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
+    import oracle.usfft as ou
+    import workloads as W
     from oracle.fem import PDESampler
+    from oracle.pool import PooledSampler
 
     S = PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    # worker processes share the process's open device files, so stay well
+    # inside the box's per-GPU process allowance and CPU share
+    cores = min(8, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1))
     g = np.random.default_rng(0)
-    done = 0
+    Y = g.random((4096, prob["d"]))
     with threadpool_limits(limits=1):
+        done = 0
         t0 = time.perf_counter()
-        while time.perf_counter() - t0 < budget_s:
-            S.solve_one(g.random(prob["d"]))
+        while time.perf_counter() - t0 < budget_s / 3:
+            S.solve_one(Y[done % len(Y)])
             done += 1
-        dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": "%d float64 banded-Cholesky P1 solves of the h=1/64, d=10 problem at random y "
-                      "(%.1f s, one thread)" % (done, dt)}
+        one = done / (time.perf_counter() - t0)
+    with PooledSampler(S, cores, chunk=8) as PS:
+        PS(Y[:cores * 8])  # workers up
+        n_all = max(cores * 8, int(one * cores * budget_s / 3) // (cores * 8) * (cores * 8))
+        n_all = min(n_all, len(Y))
+        t0 = time.perf_counter()
+        PS(Y[:n_all])
+        allc = n_all / (time.perf_counter() - t0)
+    # the full CPU-scale job: wall time, solves/s and the naive-DFT rate
+    cprob, cpar = W.WORKLOADS["cpu16_d4"]
+    CS = PDESampler(cprob["mesh_n"], cprob["a0"], cprob["amp"], cprob["mode1"], cprob["mode2"])
+    dft_t = [0.0, 0.0]
+    real_dft = ou.dft_bins
+
+    def timed_dft(U, bins):
+        t = time.perf_counter()
+        F = real_dft(U, bins)
+        dft_t[0] += time.perf_counter() - t
+        dft_t[1] += U.shape[0] * U.shape[1] * 8.0 + F.size * 16.0
+        return F
+
+    def job(sampler):
+        ou.dft_bins = timed_dft
+        try:
+            dft_t[0] = dft_t[1] = 0.0
+            t = time.perf_counter()
+            r = ou.usfft(sampler, cprob["d"], cprob["k_lo"], cprob["k_hi"], cpar["s"], cpar["s_local"], cpar["r"],
+                         cpar["theta"], cpar["theta_relative"], 1)
+            return time.perf_counter() - t, r.samples, dft_t[1] / max(dft_t[0], 1e-12) / 1e9
+        finally:
+            ou.dft_bins = real_dft
+
+    with threadpool_limits(limits=1):
+        j1 = job(CS)
+    with PooledSampler(CS, cores, chunk=16) as PS:
+        jn = job(PS)
+    return {"value": allc, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": "float64 banded-Cholesky P1 solves of the h=1/64, d=10 problem at %d seeded y, one "
+                      "process per core (%d cores); the whole job's solves are independent like these" % (n_all, cores),
+            "single_thread_samples_per_s": one,
+            "cpu16_d4_full_job": {"workload": "h=1/16 (G=225), d=4, box [-16,16]^4, s=50, rel. 1e-4, r=3, seed 1",
+                                  "samples": j1[1],
+                                  "single_thread_s": j1[0], "single_thread_samples_per_s": j1[1] / j1[0],
+                                  "all_core_s": jn[0], "all_core_samples_per_s": jn[1] / jn[0],
+                                  "dft_GBps_single_thread": j1[2], "dft_GBps_all_core": jn[2]},
+            "host": host_info()}
+
+
+def parity_block(U, prob, par, seed, precisions):
+    """The benchmark job (seed 1) against the oracle's stored whole-job
+    outputs (tests/golden/wholejob_<workload>.npz, written by an oracle-only
+    script): intermediate and final sets, flips with their oracle keep
+    ratio, coefficient error at the stored nodes relative to the largest."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "wholejob_mesh64_d10.npz")
+    if seed != 1 or not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        fx = {k: z[k] for k in z.files}
+    d = prob["d"]
+    out = {"reference": "float64 oracle (banded Cholesky, naive DFT), seed 1"}
+    for name, prec in precisions:
+        plan = U.Plan(prob, dict(par, precision=prec, pcg_rtol=1e-12, trace=True))
+        res = U.detect(plan, seed)
+        tr = res.trace()
+        flips, same = [], True
+        for t in range(d):
+            got, ref = tr[t][0][:, 0], fx["s1_I_%d" % t]
+            if not np.array_equal(got, ref):
+                for k in sorted(set(got.tolist()) ^ set(ref.tolist())):
+                    flips.append({"stage": "step1 t=%d" % (t + 1), "k": [k],
+                                  "oracle_keep_ratio": float(fx["s1_ratio_%d" % t][k - prob["k_lo"][t]])})
+                same = False
+                break
+        if same:
+            prev = fx["s1_I_0"][:, None]
+            for t in range(1, d):
+                got, ref = tr[d + t - 1][0], fx["s2_I_%d" % t]
+                if not np.array_equal(got, ref):
+                    child = fx["s1_I_%d" % t]
+                    index = {tuple(p.tolist()) + (int(c),): a * len(child) + b
+                             for a, p in enumerate(prev) for b, c in enumerate(child)}
+                    ga = {tuple(r.tolist()) for r in got}
+                    ra = {tuple(r.tolist()) for r in ref}
+                    for k in sorted(ga ^ ra):
+                        flips.append({"stage": "step2 t=%d" % (t + 1), "k": list(k),
+                                      "oracle_keep_ratio": float(fx["s2_ratio_%d" % t][index[k]])})
+                    same = False
+                    break
+                prev = ref
+        entry = {"sets_identical": same and np.array_equal(res.freqs(), fx["I"]), "flips": flips,
+                 "frequencies": res.n, "oracle_frequencies": int(len(fx["I"])),
+                 "samples": res.stats["samples"], "oracle_samples": int(fx["samples"])}
+        if entry["sets_identical"]:
+            C = res.coeffs()[:, fx["nodes"]]
+            entry["coef_max_rel_err"] = float(np.abs(C - (fx["C_re"] + 1j * fx["C_im"])).max() / float(fx["Cmax"]))
+        import torch
+        y = torch.from_numpy(fx["y_solve"]).cuda()
+        Ub = torch.zeros((plan.G, 64), dtype=torch.float64, device="cuda")
+        U.sample(plan, y, Ub, 0, 64, 0)
+        torch.cuda.synchronize()
+        Ug = Ub.cpu().numpy()[:, :len(fx["y_solve"])].T
+        entry["nodal_rel_l2_max"] = float((np.linalg.norm(Ug - fx["u_solve"], axis=1)
+                                           / np.linalg.norm(fx["u_solve"], axis=1)).max())
+        out[name] = entry
+        res.close()
+        plan.close()
+    return out
 
 
 def main():
@@ -207,6 +341,8 @@ def main():
                     help="test parameters of the error measures of one job's result (0 = skip)")
     ap.add_argument("--mesh", type=int, default=1,
                     help="also time one job on an unstructured mesh shaped like the paper's (0 = skip)")
+    ap.add_argument("--parity", type=int, default=1,
+                    help="compare the seed-1 job of both precisions with the stored oracle outputs (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof byte counters)")
     args = ap.parse_args()
@@ -247,14 +383,13 @@ def main():
     launches = sum(s["sample_launches"] for s in st32)
     iters = sum(s["pcg_iterations"] for s in st32)
     G = plan32.G
-    m = prob["mesh_n"] - 1
-    # dense contraction of the preconditioner: 4 products of m x m x m per
-    # application, one application per iteration plus the initial one (the
-    # re-applications after float64 updates are not counted)
-    mfma_flops = (iters + samples) * 8.0 * m ** 3
+    # Algorithmic HBM bytes of the matrix-free solver (the coefficient is
+    # rebuilt from y on chip): per iteration one read and one write of a
+    # float32 node vector, 2 G b, plus the float32 sample row it writes.
+    alg_bytes = iters * 2.0 * G * 4 + samples * G * 4.0
     vec_flops = iters * G * VECTOR_FLOPS_PER_NODE_ITER
     avg_ms = ms_sample / max(1, launches)
-    achieved = (mfma_flops / max(1, launches)) / (avg_ms * 1e-3) / 1e12
+    achieved = (alg_bytes / max(1, launches)) / (avg_ms * 1e-3) / 1e9
     vec_achieved = (vec_flops / max(1, launches)) / (avg_ms * 1e-3) / 1e12
     per_job = {k: sum(s[k] for s in st32) / len(st32) for k in ("ms_sample", "ms_dft", "ms_select", "ms_total")}
     fft_gbps = sum(s["dft_bytes"] for s in st32) / max(1e-9, sum(s["ms_dft"] for s in st32)) / 1e6
@@ -281,13 +416,18 @@ def main():
         "pcg_iters_per_solve": iters / max(1, samples),
         "fp32_vs_fp64_samples_per_s": (value / out["fp64_path"]["samples_per_s"]) if out else None,
         "roofline": {"kernel": "pcgdst32c_kernel<64> (DST-preconditioned float32 PCG + float64 "
-                               "reliable updates, two workgroups per CU; preconditioner on fp16 MFMA)",
-                     "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["f16_mfma"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS["f16_mfma"], "traffic": measured_traffic(),
-                     "traffic_unit": "HBM bytes per launch (rocprof FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+                               "reliable updates, two workgroups per CU)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_GBPS, "traffic": measured_traffic(),
+                     "algorithmic_bytes_per_launch": alg_bytes / max(1, launches),
+                     "algorithmic_unit": "2 G 4 B per PCG iteration + G 4 B sample write, per solve",
+                     "traffic_unit": "HBM bytes per launch (rocprof FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "avg_launch_ms": avg_ms, "launches": launches,
                      "vector_tflops": vec_achieved, "vector_frac_f32": vec_achieved / PEAK_TFLOPS["f32"],
                      "workgroup": [st32[0]["solver_block"], st32[0]["solver_npt"]]},
+        "roofline_dft": {"kernel": "lattice DFT (Rader convolution in LDS, bins gathered)", "bound": "hbm",
+                         "achieved": fft_gbps, "peak": HBM_GBPS, "unit": "GB/s", "frac": fft_gbps / HBM_GBPS,
+                         "algorithmic_unit": "M G b read + n G 8 B magnitudes written, per lattice"},
         "job_breakdown_ms": per_job,
     }
     res.update(out)
@@ -333,6 +473,8 @@ def main():
         mplan.close()
     if args.serving_jobs > 0:
         res["serving"] = serving_run(U, args.serving_jobs, 4.0, args.seed, 4)
+    if args.parity and args.workload == "mesh64_d10":
+        res["parity"] = parity_block(U, prob, par, args.seed, [("fp32_refine", U.FP32_REFINE), ("fp64", U.FP64)])
     if args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(res))
