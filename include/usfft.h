@@ -16,13 +16,10 @@
  *    caller pointer beyond the call.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Work
  *    is enqueued on it; calls that must read sizes back (detect, family,
- *    compact) synchronise that stream before returning.  detect and
- *    coefficients also run lattice transforms on a side stream of the plan
- *    (default priority), forked from `stream` and joined back to it with
- *    events before they return.
- *  - A plan holds workspaces and that side stream: calls on one plan must not
- *    overlap (one thread at a time).  Different plans may run concurrently,
- *    each on its own stream.
+ *    compact) synchronise that stream before returning.
+ *  - A plan holds workspaces: calls on one plan must not overlap (one thread
+ *    at a time).  Different plans may run concurrently, each on its own
+ *    stream.
  *  - Index sets are int32 row-major (n x t) and lexicographically ordered
  *    where stated.  Coefficient/sample matrices are row-major with an explicit
  *    leading dimension.
@@ -176,6 +173,12 @@ typedef struct {
   double ms_select;         /* device time in selection kernels              */
   double ms_total;          /* wall time of the call                         */
   double dft_bytes;         /* algorithmic bytes moved by lattice DFTs       */
+  int64_t max_batch;        /* largest sampler batch (samples in one launch) */
+  int64_t max_family;       /* largest lattice family (samples of one
+                               iteration): the smallest samples_max of the
+                               _ws calls that runs this job                  */
+  int64_t workspace_bytes;  /* _ws calls: bytes of the caller's workspace the
+                               bounds took (usfft_plan_workspace's value)    */
 } usfft_stats;
 
 const char* usfft_last_error(void);
@@ -196,6 +199,35 @@ int64_t usfft_plan_nodes(usfft_plan_t plan);
  * ENOMEM, EHIP. */
 usfft_status usfft_detect(usfft_plan_t plan, uint64_t seed, void* stream,
                           usfft_result_t* out);
+
+/* Caller-provided device workspace (Alg. 1 "Input"/"Output" unchanged).
+ * usfft_plan_workspace returns the bytes of device memory that
+ * usfft_detect_ws / usfft_coefficients_ws need on this plan for jobs whose
+ * candidate sets (every |J_t| and the output set) have at most n_cand_max
+ * entries and whose sampler batches hold at most samples_max samples (a
+ * batch is one lattice family of an increment, repeated for as many of its r
+ * iterations as fit; step 1 always runs as one batch of r sum_t K_t line
+ * samples, which the size includes; a smaller samples_max only splits the
+ * r iterations over more sampler launches, down to one family per launch).
+ * A run reports its largest |J_t|, batch and family in usfft_stats
+ * (max_candidates, max_batch, max_family).
+ * The _ws calls carve every transient buffer (sample matrix, magnitudes,
+ * sets, lattice-planner state) and the output coefficient matrix from ws_dev
+ * (256-byte aligned, ws_bytes long, owned by the caller) and allocate no
+ * device memory: the plan already holds its static tables and the lattice
+ * tables of every admissible size (built into that memory on first use).
+ * The result's coefficients live in the workspace: they stay valid while the
+ * caller keeps the workspace and does not reuse it for another call.
+ * Results are the same as usfft_detect / usfft_coefficients.  Errors: ENOMEM
+ * (ws_bytes below the size for these bounds, or a job that exceeds them:
+ * the message names the bound), EINVAL, ENOCONV, ELATTICE, EHIP. */
+usfft_status usfft_plan_workspace(usfft_plan_t plan, int64_t n_cand_max, int64_t samples_max,
+                                  size_t* bytes);
+usfft_status usfft_detect_ws(usfft_plan_t plan, uint64_t seed, int64_t n_cand_max, int64_t samples_max,
+                             void* ws_dev, size_t ws_bytes, void* stream, usfft_result_t* out);
+usfft_status usfft_coefficients_ws(usfft_plan_t plan, const int32_t* freqs_host, int64_t n, uint64_t seed,
+                                   int64_t n_cand_max, int64_t samples_max, void* ws_dev,
+                                   size_t ws_bytes, void* stream, usfft_result_t* out);
 
 /* Step 3 of Alg. 1 alone on a given frequency set (Sec. 4.5: a-priori index
  * sets such as axis crosses, hyperbolic crosses and weighted l1 balls):
@@ -323,6 +355,22 @@ usfft_status usfft_lattice_dft(const void* u_dev, int32_t u_fp32, int64_t G, int
                                int64_t col0, int32_t M, const int32_t* bins_dev,
                                const int32_t* pos_dev, int32_t nb, int32_t out_kind,
                                void* out_dev, int64_t ldo, void* stream);
+
+/* Algorithm A alone (App. A): the coefficients of the candidates J_dev
+ * (n x t int32 device array, row-major) read from one rank-1 lattice of
+ * prime size M (M - 1 7-smooth, M <= 9601) with generator z_host (t int64,
+ * host): for every node g and candidate a with bin b_a = k_a.z mod M
+ * (computed here in exact 64-bit arithmetic),
+ *   out_dev[(a G + g) 2 + {0,1}] = Re, Im of (1/M) sum_m u[g ld + col0 + m]
+ *                                  exp(-2 pi i m b_a / M),
+ * read through the canonical bin min(b, M - b) (conjugated above M/2).  u_dev
+ * holds the samples at the lattice nodes (m z mod M)/M, m < M, node-major
+ * (float64, or float32 with u_fp32 = 1).  A coefficient is exact for
+ * functions supported on candidates whose bins no other candidate shares.
+ * Synchronises `stream`.  Errors: EINVAL. */
+usfft_status usfft_lattice_coeffs(const void* u_dev, int32_t u_fp32, int64_t G, int64_t ld,
+                                  int64_t col0, int32_t M, int32_t t, const int64_t* z_host,
+                                  const int32_t* J_dev, int64_t n, double* out_dev, void* stream);
 
 /* Per-node selection and uniform union (Alg. 1 step 1&2a and 2d/2e): for
  * every node g, tau_g^2 = s_tilde-th largest of v_dev[g*ld + a], a < n

@@ -61,7 +61,8 @@ class Stats(C.Structure):
                 ("solver_block", C.c_int64), ("solver_npt", C.c_int64), ("solver_kind", C.c_int64),
                 ("theta_abs", C.c_double), ("ms_sample", C.c_double),
                 ("ms_dft", C.c_double), ("ms_select", C.c_double), ("ms_total", C.c_double),
-                ("dft_bytes", C.c_double)]
+                ("dft_bytes", C.c_double), ("max_batch", C.c_int64), ("max_family", C.c_int64),
+                ("workspace_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +76,10 @@ _sigs = {
     "usfft_plan_destroy": (None, [_vp]),
     "usfft_plan_nodes": (C.c_int64, [_vp]),
     "usfft_detect": (C.c_int, [_vp, C.c_uint64, _vp, C.POINTER(_vp)]),
+    "usfft_plan_workspace": (C.c_int, [_vp, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "usfft_detect_ws": (C.c_int, [_vp, C.c_uint64, C.c_int64, C.c_int64, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "usfft_coefficients_ws": (C.c_int, [_vp, _vp, C.c_int64, C.c_uint64, C.c_int64, C.c_int64, _vp, C.c_size_t,
+                                        _vp, C.POINTER(_vp)]),
     "usfft_result_info": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                     C.POINTER(Stats)]),
     "usfft_result_copy": (C.c_int, [_vp, _vp, _vp]),
@@ -92,6 +97,8 @@ _sigs = {
                                  C.c_int32, _vp, C.c_int64, _vp]),
     "usfft_lattice_dft": (C.c_int, [_vp, C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_int32, _vp, _vp,
                                     C.c_int32, C.c_int32, _vp, C.c_int64, _vp]),
+    "usfft_lattice_coeffs": (C.c_int, [_vp, C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _vp,
+                                       _vp, C.c_int64, _vp, _vp]),
     "usfft_select": (C.c_int, [_vp, C.c_int64, C.c_int64, C.c_int64, C.c_int32, _vp, C.c_double, _vp, _vp, _vp]),
     "usfft_product": (C.c_int, [_vp, C.c_int64, C.c_int32, _vp, C.c_int64, _vp, _vp]),
     "usfft_compact": (C.c_int, [_vp, _vp, C.c_int64, C.c_int32, _vp, C.POINTER(C.c_int64), _vp]),
@@ -327,6 +334,33 @@ def detect(plan, seed, stream=None):
     return Result(h)
 
 
+def plan_workspace(plan, n_cand_max, samples_max):
+    """usfft_plan_workspace: device bytes of the _ws calls for these bounds."""
+    b = C.c_size_t()
+    _check(_lib.usfft_plan_workspace(plan.handle, int(n_cand_max), int(samples_max), C.byref(b)))
+    return b.value
+
+
+def detect_ws(plan, seed, n_cand_max, samples_max, ws, ws_bytes=None, stream=None):
+    """usfft_detect_ws: usfft_detect inside the caller's workspace (a device
+    tensor); the result's coefficients live in that workspace."""
+    nb = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    h = _vp()
+    _check(_lib.usfft_detect_ws(plan.handle, C.c_uint64(seed), int(n_cand_max), int(samples_max), _ptr(ws), nb,
+                                _stream(stream), C.byref(h)))
+    return Result(h)
+
+
+def coefficients_ws(plan, freqs, seed, n_cand_max, samples_max, ws, ws_bytes=None, stream=None):
+    """usfft_coefficients_ws: usfft_coefficients inside the caller's workspace."""
+    F = np.ascontiguousarray(np.asarray(freqs, dtype=np.int32).reshape(-1, plan.d))
+    nb = ws.numel() * ws.element_size() if ws_bytes is None else ws_bytes
+    h = _vp()
+    _check(_lib.usfft_coefficients_ws(plan.handle, F.ctypes.data if F.size else None, F.shape[0], C.c_uint64(seed),
+                                      int(n_cand_max), int(samples_max), _ptr(ws), nb, _stream(stream), C.byref(h)))
+    return Result(h)
+
+
 def coefficients(plan, freqs, seed, stream=None):
     """usfft_coefficients: step 3 alone on the given frequencies (n x d)."""
     F = np.ascontiguousarray(np.asarray(freqs, dtype=np.int32).reshape(-1, plan.d))
@@ -378,6 +412,13 @@ def line_dft(u, u_fp32, G, ld, col0, K, bins, out_kind, out, ldo, stream=None):
 def lattice_dft(u, u_fp32, G, ld, col0, M, bins, pos, out_kind, out, ldo, stream=None):
     _check(_lib.usfft_lattice_dft(_ptr(u), int(u_fp32), G, ld, col0, M, _ptr(bins), _ptr(pos), bins.shape[0],
                                   out_kind, _ptr(out), ldo, _stream(stream)))
+
+
+def lattice_coeffs(u, u_fp32, G, ld, col0, M, z, J, out, stream=None):
+    """usfft_lattice_coeffs: Algorithm A on one lattice (M, z) for the candidates J (device, n x t)."""
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.int64).reshape(-1))
+    _check(_lib.usfft_lattice_coeffs(_ptr(u), int(u_fp32), G, ld, col0, int(M), len(z), z.ctypes.data, _ptr(J),
+                                     J.shape[0], _ptr(out), _stream(stream)))
 
 
 def select(v, G, n, ld, s_tilde, theta2, tie_rel, mask, thr=None, stream=None):

@@ -117,10 +117,6 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
   }
 }
 
-struct FftPlanDev {
-  int L, nrad;
-  int radix[24];
-};
 
 // In-place mixed-radix FFT stages on buf[0..L) (no extra buffer, R registers
 // per butterfly).  Stage s has block size N_s = L / (R_0 ... R_{s-1}) and
@@ -134,6 +130,8 @@ struct FftPlanDev {
 // pointwise product with a spectrum produced by the same DIF, DIT back.
 // COLS transforms of length L side by side (column c at buf + c L): a
 // butterfly loads its twiddles and spectrum values once for all columns.
+// tw[0] = 1 exactly, so butterflies with j = 0 read their unit twiddles from
+// the table like the others (no branch around the loads).
 template <typename T, int R, int BLOCK, int COLS>
 __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw,
                           const cplx<T>* __restrict__ mulB) {
@@ -142,7 +140,7 @@ __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
     const int blk = b / M, j = b - blk * M, base = blk * N + j;
     cplx<T> w[R], bq[R];
 #pragma unroll
-    for (int q = 1; q < R; ++q) w[q] = j > 0 ? tw[j * q * ts] : cplx<T>{(T)1, (T)0};
+    for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
     if (mulB) {
 #pragma unroll
       for (int q = 0; q < R; ++q) bq[q] = mulB[base + q * M];
@@ -173,7 +171,7 @@ __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
     const int blk = b / M, j = b - blk * M, base = blk * N + j;
     cplx<T> w[R];
 #pragma unroll
-    for (int q = 1; q < R; ++q) w[q] = j > 0 ? tw[j * q * ts] : cplx<T>{(T)1, (T)0};
+    for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
       cplx<T>* bc = buf + c * L;
@@ -284,15 +282,62 @@ static int64_t powmod(int64_t a, int64_t e, int64_t m) {
   return r;
 }
 
+// Byte offsets of the tables of one size inside its memory block.
+namespace {
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+struct RaderLayout {
+  size_t perm, outidx, dlog, tw64, tw32, B64, B32, total;
+  explicit RaderLayout(int M) {
+    const size_t L = (size_t)(M - 1);
+    size_t o = 0;
+    perm = o;
+    o += align256(sizeof(int32_t) * L);
+    outidx = o;
+    o += align256(sizeof(int32_t) * M);
+    dlog = o;
+    o += align256(sizeof(int32_t) * M);
+    tw64 = o;
+    o += align256(sizeof(cplx<double>) * L);
+    tw32 = o;
+    o += align256(sizeof(cplx<float>) * L);
+    B64 = o;
+    o += align256(sizeof(cplx<double>) * L);
+    B32 = o;
+    o += align256(sizeof(cplx<float>) * L);
+    total = o;
+  }
+};
+}  // namespace
+
+size_t rader_table_bytes(int M) { return RaderLayout(M).total; }
+
 void rader_free(RaderTables& T) {
-  for (void* p : {(void*)T.perm, (void*)T.dlog, (void*)T.outidx, T.tw64, T.tw32, T.B64, T.B32})
-    if (p) (void)hipFree(p);
+  if (T.owned && T.base) (void)hipFree(T.base);
   T = RaderTables{};
 }
 
 void rader_build(RaderTables& T, int M, hipStream_t st) {
   USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL,
                 "lattice size " + std::to_string(M) + " is not a prime <= 9601 with 7-smooth M-1");
+  void* mem = nullptr;
+  USFFT_HIP(hipMalloc(&mem, rader_table_bytes(M)));
+  try {
+    rader_build_at(T, M, mem, st);
+  } catch (...) {
+    (void)hipFree(mem);
+    throw;
+  }
+  T.owned = true;
+}
+
+void rader_build_at(RaderTables& T, int M, void* mem, hipStream_t st) {
+  USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL,
+                "lattice size " + std::to_string(M) + " is not a prime <= 9601 with 7-smooth M-1");
+  const RaderLayout Lay(M);
+  char* base = static_cast<char*>(mem);
+  T = RaderTables{};
+  T.base = mem;
+  T.owned = false;
   T.M = M;
   T.L = M - 1;
   const int L = T.L;
@@ -337,13 +382,13 @@ void rader_build(RaderTables& T, int M, hipStream_t st) {
     const double a = -2.0 * M_PI * (double)k / (double)L;
     tw[k] = {std::cos(a), std::sin(a)};
   }
-  USFFT_HIP(hipMalloc(&T.perm, sizeof(int32_t) * L));
-  USFFT_HIP(hipMalloc(&T.outidx, sizeof(int32_t) * M));
-  USFFT_HIP(hipMalloc(&T.dlog, sizeof(int32_t) * M));
-  USFFT_HIP(hipMalloc(&T.tw64, sizeof(cplx<double>) * L));
-  USFFT_HIP(hipMalloc(&T.tw32, sizeof(cplx<float>) * L));
-  USFFT_HIP(hipMalloc(&T.B64, sizeof(cplx<double>) * L));
-  USFFT_HIP(hipMalloc(&T.B32, sizeof(cplx<float>) * L));
+  T.perm = reinterpret_cast<int32_t*>(base + Lay.perm);
+  T.outidx = reinterpret_cast<int32_t*>(base + Lay.outidx);
+  T.dlog = reinterpret_cast<int32_t*>(base + Lay.dlog);
+  T.tw64 = base + Lay.tw64;
+  T.tw32 = base + Lay.tw32;
+  T.B64 = base + Lay.B64;
+  T.B32 = base + Lay.B32;
   USFFT_HIP(hipMemcpyAsync(T.perm, perm.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, st));
   USFFT_HIP(hipMemcpyAsync(T.outidx, outidx.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
   USFFT_HIP(hipMemcpyAsync(T.dlog, dlog.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
@@ -381,20 +426,16 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N], double* red) {
   }
 }
 
-// COLS node pairs per workgroup, each pair packed as one complex column.
+// One lattice DFT for COLS node pairs (workgroup grp of the lattice), each
+// pair packed as one complex column.
 template <typename T, int BLOCK, int COLS>
-__global__ __launch_bounds__(BLOCK) void rader_kernel(FftPlanDev F, int M, const int32_t* __restrict__ dlog,
-                                                      const int32_t* __restrict__ outidx,
-                                                      const cplx<T>* __restrict__ tw,
-                                                      const cplx<T>* __restrict__ B, const T* __restrict__ u,
-                                                      int64_t G, int64_t ld, int64_t col0,
-                                                      const int32_t* __restrict__ bins,
-                                                      const int32_t* __restrict__ pos, int pos_base, int nb,
-                                                      int out_kind, void* __restrict__ out, int64_t ldo) {
-  extern __shared__ char smem[];
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  __shared__ double red[2 * COLS * (BLOCK / kWave)];
-  const int64_t grp = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void rader_body(const FftPlanDev& F, int M, const int32_t* __restrict__ dlog,
+                                           const int32_t* __restrict__ outidx, const cplx<T>* __restrict__ tw,
+                                           const cplx<T>* __restrict__ B, const T* __restrict__ u, int64_t G,
+                                           int64_t ld, int64_t col0, const int32_t* __restrict__ bins,
+                                           const int32_t* __restrict__ pos, int pos_base, int nb, int out_kind,
+                                           void* __restrict__ out, int64_t ldo, int64_t grp, cplx<T>* buf,
+                                           double* red) {
   const int L = F.L;
   const T* r1[COLS];
   const T* r2[COLS];
@@ -478,6 +519,42 @@ __global__ __launch_bounds__(BLOCK) void rader_kernel(FftPlanDev F, int M, const
   }
 }
 
+// One lattice (the stage entry point usfft_lattice_dft).
+template <typename T, int BLOCK, int COLS>
+__global__ __launch_bounds__(BLOCK) void rader_kernel(FftPlanDev F, int M, const int32_t* __restrict__ dlog,
+                                                      const int32_t* __restrict__ outidx,
+                                                      const cplx<T>* __restrict__ tw,
+                                                      const cplx<T>* __restrict__ B, const T* __restrict__ u,
+                                                      int64_t G, int64_t ld, int64_t col0,
+                                                      const int32_t* __restrict__ bins,
+                                                      const int32_t* __restrict__ pos, int pos_base, int nb,
+                                                      int out_kind, void* __restrict__ out, int64_t ldo) {
+  extern __shared__ char smem[];
+  __shared__ double red[2 * COLS * (BLOCK / kWave)];
+  rader_body<T, BLOCK, COLS>(F, M, dlog, outidx, tw, B, u, G, ld, col0, bins, pos, pos_base, nb, out_kind, out, ldo,
+                             xcd_remap(blockIdx.x, gridDim.x), reinterpret_cast<cplx<T>*>(smem), red);
+}
+
+// Every lattice of a stage, and every iteration of a sampler batch, in one
+// launch: workgroup w serves item w / wpi (wpi workgroups per item, all of
+// the same G), node-pair group w % wpi.  Items of one XCD are contiguous, so
+// an item's tables stay in one L2.
+template <typename T, int BLOCK, int COLS>
+__global__ __launch_bounds__(BLOCK) void rader_batch_kernel(const LatItem* __restrict__ items, int64_t wpi,
+                                                            const T* __restrict__ u, int64_t G, int64_t ld,
+                                                            int out_kind, void* __restrict__ out, int64_t ldo) {
+  extern __shared__ char smem[];
+  __shared__ double red[2 * COLS * (BLOCK / kWave)];
+  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
+  // the item stays in global memory: its radix plan is indexed by stage at
+  // run time (scalar loads), which a private copy would send to scratch
+  const LatItem& it = items[w / wpi];
+  rader_body<T, BLOCK, COLS>(it.F, it.M, it.dlog, it.outidx, static_cast<const cplx<T>*>(it.tw),
+                             static_cast<const cplx<T>*>(it.B), u, G, ld, it.col0, it.bins, it.pos, it.pos_base,
+                             it.nb, out_kind, static_cast<double*>(out) + it.out_off, ldo, w % wpi,
+                             reinterpret_cast<cplx<T>*>(smem), red);
+}
+
 void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0,
                         const int32_t* bins, const int32_t* pos, int pos_base, int nb, int out_kind, void* out,
                         int64_t ldo, hipStream_t st) {
@@ -521,6 +598,64 @@ void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t
 #undef USFFT_RADER_C
 #undef USFFT_RADER_B
 #undef USFFT_RADER
+  USFFT_HIP(hipGetLastError());
+}
+
+// Workgroup shape of a batch whose largest transform has length Lmax (the
+// same rule as one lattice).
+static void rader_shape(int Lmax, int u_fp32, int* block, int* cols, size_t* lds) {
+  *block = Lmax <= 1024 ? 128 : (Lmax <= 3072 ? 256 : 512);
+  const size_t colbytes = (size_t)Lmax * (u_fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>));
+  *cols = 4 * colbytes <= (64u << 10) ? 4 : (2 * colbytes <= (64u << 10) ? 2 : 1);
+  *lds = colbytes * (size_t)*cols;
+}
+
+void fill_lat_item(LatItem& it, const RaderTables& T, int u_fp32) {
+  it.F.L = T.L;
+  it.F.nrad = T.nrad;
+  for (int i = 0; i < 24; ++i) it.F.radix[i] = T.radix[i];
+  it.M = T.M;
+  it.dlog = T.dlog;
+  it.outidx = T.outidx;
+  it.tw = u_fp32 ? T.tw32 : T.tw64;
+  it.B = u_fp32 ? T.B32 : T.B64;
+}
+
+void launch_lattice_dft_batch(const LatItem* items, int nitems, int Lmax, const void* u, int u_fp32, int64_t G,
+                              int64_t ld, int out_kind, void* out, int64_t ldo, hipStream_t st) {
+  if (G <= 0 || nitems <= 0) return;
+  USFFT_REQUIRE(Lmax >= 2 && Lmax <= kLMax, USFFT_EINVAL, "lattice transform length out of range");
+  int block = 0, cols = 0;
+  size_t lds = 0;
+  rader_shape(Lmax, u_fp32, &block, &cols, &lds);
+  const int64_t wpi = ceil_div(G, 2 * cols);
+  const unsigned grid = (unsigned)(wpi * nitems);
+#define USFFT_RB(TT, BB, CC) \
+  hipLaunchKernelGGL((rader_batch_kernel<TT, BB, CC>), dim3(grid), dim3(BB), lds, st, items, wpi, (const TT*)u, G, ld, \
+                     out_kind, out, ldo)
+#define USFFT_RB_B(TT, CC)  \
+  if (block == 128)         \
+    USFFT_RB(TT, 128, CC);  \
+  else if (block == 256)    \
+    USFFT_RB(TT, 256, CC);  \
+  else                      \
+    USFFT_RB(TT, 512, CC)
+#define USFFT_RB_C(TT)   \
+  if (cols == 4) {       \
+    USFFT_RB_B(TT, 4);   \
+  } else if (cols == 2) { \
+    USFFT_RB_B(TT, 2);   \
+  } else {               \
+    USFFT_RB_B(TT, 1);   \
+  }
+  if (u_fp32) {
+    USFFT_RB_C(float)
+  } else {
+    USFFT_RB_C(double)
+  }
+#undef USFFT_RB_C
+#undef USFFT_RB_B
+#undef USFFT_RB
   USFFT_HIP(hipGetLastError());
 }
 

@@ -90,6 +90,8 @@ void launch_trigpoly(int d, const double* Y, int64_t ns, const int32_t* K, int64
 // ---- fft.hip
 // Per-size tables of Rader's algorithm for a prime M with smooth L = M-1.
 struct RaderTables {
+  void* base = nullptr;       // one block holding every table below
+  bool owned = false;         // base was allocated by rader_build
   int M = 0, L = 0, gen = 0;
   int nrad = 0;
   int radix[24] = {0};
@@ -101,13 +103,42 @@ struct RaderTables {
   void* B64 = nullptr;        // L complex double: DFT_L(b) / L, b_j = exp(-2 pi i gen^(-j) / M)
   void* B32 = nullptr;        // L complex float
 };
+// Radix plan of one length-L transform.
+struct FftPlanDev {
+  int L, nrad;
+  int radix[24];
+};
+// One lattice DFT of a batched launch: the tables of its size, its samples
+// (columns col0 .. col0 + M of every node row), the bins of its candidates
+// and where their values go (output column pos[a] or pos_base + a, in the
+// block that starts out_off elements into the output).
+struct LatItem {
+  FftPlanDev F;
+  int M;
+  const int32_t* dlog;
+  const int32_t* outidx;
+  const void* tw;  // twiddles and kernel spectrum in the launch's precision
+  const void* B;
+  int64_t col0;
+  const int32_t* bins;
+  const int32_t* pos;
+  int pos_base, nb;
+  int64_t out_off;
+};
 bool lattice_size_ok(int M);
+size_t rader_table_bytes(int M);                        // bytes of one size's tables
 void rader_build(RaderTables& T, int M, hipStream_t st);  // allocates + fills (synchronous)
-void rader_free(RaderTables& T);
+void rader_build_at(RaderTables& T, int M, void* mem, hipStream_t st);  // fills mem (synchronous)
+void rader_free(RaderTables& T);                        // frees what rader_build allocated
 // Output column of candidate a: pos[a], or pos_base + a when pos is null.
 void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0,
                         const int32_t* bins, const int32_t* pos, int pos_base, int nb, int out_kind, void* out,
                         int64_t ldo, hipStream_t st);
+void fill_lat_item(LatItem& it, const RaderTables& T, int u_fp32);  // F, M and the table pointers
+// Every item of items_dev (device array) in one launch; Lmax = the largest
+// transform length L = M - 1 among them.
+void launch_lattice_dft_batch(const LatItem* items_dev, int nitems, int Lmax, const void* u, int u_fp32, int64_t G,
+                              int64_t ld, int out_kind, void* out, int64_t ldo, hipStream_t st);
 // mask_out bit pos[q] |= mask_in bit q, q < n (grouped order back to candidate order).
 void launch_ungroup_mask(const uint32_t* mask_in, const int32_t* pos, int64_t n, uint32_t* mask_out, hipStream_t st);
 // all d r step-1 lines at once: line y (coordinate t = y / line_r) from column
@@ -127,6 +158,10 @@ void launch_select_lines(const double* v, int64_t G, int64_t ld, int nlines, int
                          uint32_t* mask, hipStream_t st);
 void launch_select(const double* v, int64_t G, int64_t n, int64_t ld, int s_tilde, const double* theta2,
                    double tie_rel, uint32_t* mask, double* thr, hipStream_t st);
+// niter column blocks of n candidates (block b at columns b * iter_stride)
+// in one launch, all ORed into the same mask
+void launch_select_iters(const double* v, int64_t G, int64_t n, int64_t ld, int niter, int64_t iter_stride,
+                         int s_tilde, const double* theta2, double tie_rel, uint32_t* mask, hipStream_t st);
 void launch_max_to_theta(const double* v, int64_t G, int64_t n, int64_t ld, double theta, double* theta2,
                          uint64_t* scratch, hipStream_t st);
 

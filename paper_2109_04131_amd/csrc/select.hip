@@ -33,7 +33,9 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
                                                            uint32_t* __restrict__ mask, double* __restrict__ thr_out,
                                                            const int32_t* __restrict__ lineK, int line_r,
                                                            int64_t line_stride) {
-  if (lineK) {
+  if (!lineK) {
+    v += (int64_t)blockIdx.y * line_stride;  // iteration blocks (one block: y = 0)
+  } else {
     const int y = blockIdx.y, t = y / line_r;
     int64_t w = 0;
     for (int j = 0; j < t; ++j) w += (lineK[j] + 31) / 32;
@@ -179,6 +181,19 @@ void launch_select(const double* v, int64_t G, int64_t n, int64_t ld, int s_tild
   else
     hipLaunchKernelGGL(select_kernel<false>, dim3((unsigned)G), dim3(kSelBlock), 0, st, v, G, n, ld, s_tilde,
                        theta2, tie_rel, mask, thr, nullptr, 1, 0);
+  USFFT_HIP(hipGetLastError());
+}
+
+void launch_select_iters(const double* v, int64_t G, int64_t n, int64_t ld, int niter, int64_t iter_stride,
+                         int s_tilde, const double* theta2, double tie_rel, uint32_t* mask, hipStream_t st) {
+  if (G <= 0 || n <= 0 || niter <= 0) return;
+  const dim3 grid((unsigned)G, (unsigned)niter);
+  if (n <= kSelLds)
+    hipLaunchKernelGGL(select_kernel<true>, grid, dim3(kSelBlock), (size_t)n * sizeof(uint64_t), st, v, G, n, ld,
+                       s_tilde, theta2, tie_rel, mask, nullptr, nullptr, 1, iter_stride);
+  else
+    hipLaunchKernelGGL(select_kernel<false>, grid, dim3(kSelBlock), 0, st, v, G, n, ld, s_tilde, theta2, tie_rel,
+                       mask, nullptr, nullptr, 1, iter_stride);
   USFFT_HIP(hipGetLastError());
 }
 

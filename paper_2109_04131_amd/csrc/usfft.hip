@@ -29,28 +29,44 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 // ---------------------------------------------------------------- buffers
 // Owning device buffer; move-only so that swaps and container moves never
 // duplicate (and later double-free) an allocation.
+// A borrowed buffer is a slice of a caller's workspace: it never grows (a
+// larger request is USFFT_ENOMEM) and is never freed.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), borrowed(o.borrowed) {
     o.p = nullptr;
     o.bytes = 0;
+    o.borrowed = false;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p;
       bytes = o.bytes;
+      borrowed = o.borrowed;
       o.p = nullptr;
       o.bytes = 0;
+      o.borrowed = false;
     }
     return *this;
   }
+  void borrow(void* q, size_t b) {
+    release();
+    p = q;
+    bytes = b;
+    borrowed = true;
+  }
   void ensure(size_t b) {
     if (b <= bytes) return;
+    if (borrowed)
+      throw Error{USFFT_ENOMEM, "the caller's workspace is too small: a buffer of " + std::to_string(bytes) +
+                                    " bytes needs " + std::to_string(b) +
+                                    " (raise n_cand_max / samples_max of usfft_plan_workspace)"};
     if (p) USFFT_HIP(hipFree(p));
     p = nullptr;
     bytes = 0;
@@ -67,9 +83,10 @@ struct DevBuf {
     return static_cast<T*>(p);
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !borrowed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    borrowed = false;
   }
   ~DevBuf() { release(); }
 };
@@ -105,30 +122,33 @@ struct usfft_plan_s {
   // pinned landing buffer of small readbacks (valid until the next readback)
   char* back = nullptr;
   size_t back_cap = 0;
+  std::vector<char> back_host;
   usfft::DevBuf famlog, famstate;
-  // side stream of the lattice DFTs (default priority) and its fork/join events
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int wblocks = 0;  // persistent workgroups of the float32 / DST solver
   bool streaming = false;  // mesh larger than the on-chip solvers hold
   bool dst = false;        // DST-preconditioned solver
   int dst_variant = 1;     // 0: scratch in global memory, 1: LDS-resident, 2: compact float32
   usfft::PdeDev pde{};
-  // Rader tables per lattice size
+  // Rader tables per lattice size, built on first use into the plan's table
+  // arena (every admissible size up to lattice_mmax has its slot, sized at
+  // plan creation, so no call allocates them later)
   std::map<int, usfft::RaderTables> rader;
+  std::map<int, size_t> rader_off;
+  usfft::DevBuf d_rader;
+  // caller workspace mode (usfft_detect_ws / usfft_coefficients_ws): every
+  // transient buffer is a borrowed slice; sampler batches hold at most
+  // ws_nsamp samples
+  bool ws_mode = false;
+  int64_t ws_nsamp = 0, ws_ncand = 0;
   // workspaces (grown on demand, kept across calls)
   usfft::DevBuf Y, U, V, iters, cnt, theta2, scratch, J, Jnext, Iprev, mask, gmask, cands, assign, bins, famz, fambins,
-      famcounts, famcov, famscores, lists, latM, latz, latoff, tail;
+      famcounts, famcov, famscores, lists, latM, latz, latoff, tail, latitems;
   std::vector<usfft::DevBuf> I1;  // step-1 sets per coordinate
   std::vector<int64_t> I1n;
   std::mutex mu;
   ~usfft_plan_s() {
-    for (auto& kv : rader) usfft::rader_free(kv.second);
     if (stage) (void)hipHostFree(stage);
     if (back) (void)hipHostFree(back);
-    if (side) (void)hipStreamDestroy(side);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
   }
 };
 
@@ -153,8 +173,10 @@ namespace usfft {
 static const RaderTables& rader_for(usfft_plan_s* P, int M, hipStream_t st) {
   auto it = P->rader.find(M);
   if (it != P->rader.end()) return it->second;
+  auto o = P->rader_off.find(M);
+  USFFT_REQUIRE(o != P->rader_off.end(), USFFT_EINVAL, "lattice size " + std::to_string(M) + " has no table slot");
   RaderTables T;
-  rader_build(T, M, st);
+  rader_build_at(T, M, P->d_rader.as<char>() + o->second, st);
   return P->rader.emplace(M, T).first->second;
 }
 
@@ -192,7 +214,7 @@ static void h2d_async(usfft_plan_s* P, usfft::DevBuf& b, const std::vector<T>& v
   if (P->stage_used + bytes > P->stage_cap) {
     USFFT_HIP(hipStreamSynchronize(st));  // every earlier copy out of the arena is done
     P->stage_used = 0;
-    if (bytes > P->stage_cap) {
+    if (bytes > P->stage_cap && !P->ws_mode) {
       if (P->stage) USFFT_HIP(hipHostFree(P->stage));
       P->stage = nullptr;
       P->stage_cap = 0;
@@ -201,6 +223,12 @@ static void h2d_async(usfft_plan_s* P, usfft::DevBuf& b, const std::vector<T>& v
       P->stage_cap = cap;
     }
   }
+  if (P->ws_mode && bytes > P->stage_cap) {
+    // no new pinned memory in workspace mode: a synchronous pageable copy
+    USFFT_HIP(hipMemcpyAsync(b.p, v.data(), bytes, hipMemcpyHostToDevice, st));
+    USFFT_HIP(hipStreamSynchronize(st));
+    return;
+  }
   std::memcpy(P->stage + P->stage_used, v.data(), bytes);
   USFFT_HIP(hipMemcpyAsync(b.p, P->stage + P->stage_used, bytes, hipMemcpyHostToDevice, st));
   P->stage_used += (bytes + 255) / 256 * 256;
@@ -208,6 +236,11 @@ static void h2d_async(usfft_plan_s* P, usfft::DevBuf& b, const std::vector<T>& v
 
 // Pinned host memory for a readback of `bytes` (grown as needed).
 static char* back_buffer(usfft_plan_s* P, size_t bytes) {
+  if (bytes > P->back_cap && P->ws_mode) {
+    // no new pinned memory in workspace mode: pageable landing buffer
+    P->back_host.resize(bytes);
+    return P->back_host.data();
+  }
   if (bytes > P->back_cap) {
     if (P->back) USFFT_HIP(hipHostFree(P->back));
     P->back = nullptr;
@@ -340,6 +373,19 @@ static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
   }
 }
 
+// Bin k.z mod M of every candidate (App. A), in exact 64-bit arithmetic.
+struct GenVec {
+  int64_t z[kMaxD];
+};
+__global__ void lattice_bin_kernel(const int32_t* __restrict__ J, int64_t n, int t, GenVec z, int64_t M,
+                                   int32_t* __restrict__ bins) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  int64_t b = 0;
+  for (int j = 0; j < t; ++j) b = (b + (int64_t)J[a * t + j] * z.z[j] % M) % M;
+  bins[a] = (int32_t)((b + M) % M);
+}
+
 __global__ void iter_stats_kernel(const int32_t* __restrict__ it, int64_t n, unsigned long long* __restrict__ acc) {
   unsigned long long bad = 0, sum = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -363,26 +409,6 @@ static void accumulate_iters(usfft_plan_s* P, int64_t ns, hipStream_t st) {
   hipLaunchKernelGGL(iter_stats_kernel, dim3(grid), dim3(256), 0, st, P->iters.as<int32_t>(), ns,
                      P->cnt.as<unsigned long long>());
   USFFT_HIP(hipGetLastError());
-}
-
-// The lattice DFTs of one stage write disjoint output columns, so they
-// alternate between the caller's stream and the plan's side stream, and the
-// tail of one launch overlaps the next.  dft_fork orders the side stream
-// after the work enqueued on st so far and returns it; dft_join orders st
-// after everything enqueued on the side stream.
-static hipStream_t dft_fork(usfft_plan_s* P, hipStream_t st) {
-  if (!P->side) {
-    USFFT_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
-    USFFT_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
-    USFFT_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
-  }
-  USFFT_HIP(hipEventRecord(P->ev_fork, st));
-  USFFT_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
-  return P->side;
-}
-static void dft_join(usfft_plan_s* P, hipStream_t st) {
-  USFFT_HIP(hipEventRecord(P->ev_join, P->side));
-  USFFT_HIP(hipStreamWaitEvent(st, P->ev_join, 0));
 }
 
 struct Timer {
@@ -432,6 +458,7 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     const int e = tm.open(kTSample);
     run_sampler(P, Y, ns, P->U.p, ufp32, ld, 0, P->iters.as<int32_t>(), st);
     tm.close(kTSample, e);
+    S.max_batch = std::max(S.max_batch, ns);
     accumulate_iters(P, ns, st);
     S.sample_launches += ns > 0 ? 1 : 0;
   };
@@ -577,6 +604,9 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
         continue;
       }
       const int w = t + 1;
+      USFFT_REQUIRE(!P->ws_mode || n <= P->ws_ncand, USFFT_ENOMEM,
+                    "increment t = " + std::to_string(t + 1) + " has " + std::to_string(n) +
+                        " candidates; the workspace holds " + std::to_string(P->ws_ncand) + " (raise n_cand_max)");
       P->J.ensure(sizeof(int32_t) * n * w);
       launch_product(P->Iprev.as<int32_t>(), nprev, t, P->I1[t].as<int32_t>(), nc, P->J.as<int32_t>(), st);
       P->assign.ensure(sizeof(int32_t) * n);
@@ -587,7 +617,6 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       S.lattices += (int64_t)F.M.size();
       for (int M : F.M) (void)rader_for(P, M, st);
       const int64_t ns = F.total();
-      P->V.ensure(sizeof(double) * G * n);
       h2d_async(P, P->latM, F.M, st);
       h2d_async(P, P->latz, F.z, st);
       h2d_async(P, P->latoff, F.off, st);
@@ -601,8 +630,17 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       USFFT_HIP(hipMemsetAsync(P->gmask.p, 0, sizeof(uint32_t) * words, st));
       // the r_t iterations differ only in their tails: their samples are
       // solved together, in batches of at most kSampleBatchBytes of samples
+      S.max_family = std::max(S.max_family, ns);
       int rb = r_t;
-      while (rb > 1 && ub * (uint64_t)G * (uint64_t)(rb * ns) > kSampleBatchBytes) --rb;
+      if (P->ws_mode) {
+        USFFT_REQUIRE(ns <= P->ws_nsamp, USFFT_ENOMEM,
+                      "the lattice family of increment t = " + std::to_string(t + 1) + " needs " + std::to_string(ns) +
+                          " samples; the workspace holds " + std::to_string(P->ws_nsamp) + " (raise samples_max)");
+        rb = (int)std::min<int64_t>(r_t, P->ws_nsamp / ns);
+      } else {
+        while (rb > 1 && ub * (uint64_t)G * (uint64_t)(rb * ns) > kSampleBatchBytes) --rb;
+      }
+      P->V.ensure(sizeof(double) * G * n * rb);
       for (int i0 = 0; i0 < r_t; i0 += rb) {
         const int nb = std::min(rb, r_t - i0);
         const int64_t nsb = nb * ns, ldb = ceil_div(nsb, 64) * 64;
@@ -618,24 +656,36 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
                                  P->latz.as<int32_t>(), P->tail.as<double>(), P->Y.as<double>(), ns, nb, st);
         sample_timed(P->Y.as<double>(), nsb, ldb);
         S.samples_step2 += nsb;
-        for (int b = 0; b < nb; ++b) {
-          int e = tm.open(kTDft);
-          const hipStream_t s2 = F.M.size() > 1 ? dft_fork(P, st) : st;
+        // every lattice of every iteration of the batch in one DFT launch
+        // (iteration b's magnitudes in columns b n .. of V), then every
+        // iteration's selection in one launch
+        std::vector<LatItem> items;
+        int Lmax = 2;
+        for (int b = 0; b < nb; ++b)
           for (size_t l = 0; l < F.M.size(); ++l) {
-            const RaderTables& T = rader_for(P, F.M[l], st);
-            const int32_t* bn = P->lists.as<int32_t>() + n + F.lat_first[l];
-            launch_lattice_dft(T, P->U.p, ufp32, G, ldb, b * ns + F.off[l], bn, nullptr, F.lat_first[l],
-                               F.lat_count[l], USFFT_OUT_MAG2, P->V.p, n, (l & 1) ? s2 : st);
-            S.dft_launches += 1;
+            if (F.lat_count[l] == 0) continue;
+            LatItem it{};
+            fill_lat_item(it, rader_for(P, F.M[l], st), ufp32);
+            it.col0 = b * ns + F.off[l];
+            it.bins = P->lists.as<int32_t>() + n + F.lat_first[l];
+            it.pos = nullptr;
+            it.pos_base = F.lat_first[l];
+            it.nb = F.lat_count[l];
+            it.out_off = (int64_t)b * n;
+            items.push_back(it);
+            Lmax = std::max(Lmax, F.M[l] - 1);
             S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 8.0;
           }
-          if (s2 != st) dft_join(P, st);
-          tm.close(kTDft, e);
-          e = tm.open(kTSelect);
-          launch_select(P->V.as<double>(), G, n, n, s_t, P->theta2.as<double>(), par.tie_rel,
-                        P->gmask.as<uint32_t>(), nullptr, st);
-          tm.close(kTSelect, e);
-        }
+        h2d_async(P, P->latitems, items, st);
+        int e = tm.open(kTDft);
+        launch_lattice_dft_batch(P->latitems.as<LatItem>(), (int)items.size(), Lmax, P->U.p, ufp32, G, ldb,
+                                 USFFT_OUT_MAG2, P->V.p, (int64_t)nb * n, st);
+        tm.close(kTDft, e);
+        S.dft_launches += 1;
+        e = tm.open(kTSelect);
+        launch_select_iters(P->V.as<double>(), G, n, (int64_t)nb * n, nb, n, s_t, P->theta2.as<double>(),
+                            par.tie_rel, P->gmask.as<uint32_t>(), st);
+        tm.close(kTSelect, e);
       }
       launch_ungroup_mask(P->gmask.as<uint32_t>(), P->lists.as<int32_t>(), n, P->mask.as<uint32_t>(), st);
       P->Jnext.ensure(sizeof(int32_t) * n * w);
@@ -682,6 +732,10 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     for (int M : F.M) (void)rader_for(P, M, st);
     const int64_t ns = F.total();
     const int64_t ld = ceil_div(ns, 64) * 64;
+    S.max_family = std::max(S.max_family, ns);
+    USFFT_REQUIRE(!P->ws_mode || ns <= P->ws_nsamp, USFFT_ENOMEM,
+                  "the step-3 lattice family needs " + std::to_string(ns) + " samples; the workspace holds " +
+                      std::to_string(P->ws_nsamp) + " (raise samples_max)");
     P->U.ensure(ub * G * ld);
     P->Y.ensure(sizeof(double) * ns * d);
     P->iters.ensure(sizeof(int32_t) * ns);
@@ -692,19 +746,28 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
                  P->tail.as<double>(), P->Y.as<double>(), ns, st);
     sample_timed(P->Y.as<double>(), ns, ld);
     S.samples_step3 += ns;
-    int e = tm.open(kTDft);
-    const hipStream_t s2 = F.M.size() > 1 ? dft_fork(P, st) : st;
+    std::vector<LatItem> items;
+    int Lmax = 2;
     for (size_t l = 0; l < F.M.size(); ++l) {
-      const RaderTables& T = rader_for(P, F.M[l], st);
-      const int32_t* pos = P->lists.as<int32_t>() + F.lat_first[l];
-      const int32_t* bn = P->lists.as<int32_t>() + nI + F.lat_first[l];
-      launch_lattice_dft(T, P->U.p, ufp32, G, ld, F.off[l], bn, pos, 0, F.lat_count[l], USFFT_OUT_COMPLEX, R->C.p,
-                         G, (l & 1) ? s2 : st);
-      S.dft_launches += 1;
+      if (F.lat_count[l] == 0) continue;
+      LatItem it{};
+      fill_lat_item(it, rader_for(P, F.M[l], st), ufp32);
+      it.col0 = F.off[l];
+      it.bins = P->lists.as<int32_t>() + nI + F.lat_first[l];
+      it.pos = P->lists.as<int32_t>() + F.lat_first[l];
+      it.pos_base = 0;
+      it.nb = F.lat_count[l];
+      it.out_off = 0;
+      items.push_back(it);
+      Lmax = std::max(Lmax, F.M[l] - 1);
       S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 16.0;
     }
-    if (s2 != st) dft_join(P, st);
+    h2d_async(P, P->latitems, items, st);
+    int e = tm.open(kTDft);
+    launch_lattice_dft_batch(P->latitems.as<LatItem>(), (int)items.size(), Lmax, P->U.p, ufp32, G, ld,
+                             USFFT_OUT_COMPLEX, R->C.p, G, st);
     tm.close(kTDft, e);
+    S.dft_launches += 1;
     check_conv();
   }
   USFFT_HIP(hipStreamSynchronize(st));
@@ -730,6 +793,114 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
   S.ms_dft = tm.total(kTDft);
   S.ms_select = tm.total(kTSelect);
   S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------- caller workspace
+// Every transient device buffer of detect(), in a fixed order, with its
+// largest size for candidate sets of at most ncand entries (|J_t| and the
+// output set) and sampler batches of at most nsamp samples (step 1 always
+// runs as one batch of its r sum_t K_t line samples); the last entry is the
+// output coefficient matrix.
+struct WsItem {
+  DevBuf* buf;
+  size_t bytes;
+};
+
+static std::vector<WsItem> ws_items(usfft_plan_s* P, DevBuf* C, int64_t ncand, int64_t nsamp) {
+  const usfft_problem& pb = P->prob;
+  const usfft_params& par = P->par;
+  const int64_t d = pb.d, r = par.r, G = P->G, T = par.lattice_tries, Lm = par.lattice_max;
+  const int64_t ub = par.precision == USFFT_FP32_REFINE ? 4 : 8;
+  int64_t sumK = 0, Kmax = 1, woff = 0;
+  for (int t = 0; t < d; ++t) {
+    const int64_t K = pb.k_hi[t] - pb.k_lo[t] + 1;
+    sumK += K;
+    Kmax = std::max(Kmax, K);
+    woff += ceil_div(K, 32);
+  }
+  const int64_t ns1 = r * sumK, nl = d * r;
+  const int64_t nsb = ceil_div(std::max(ns1, nsamp), 64) * 64;
+  const int64_t nc = std::max<int64_t>(ncand, 1);
+  P->I1.resize(d);
+  auto sz = [](int64_t b) { return (size_t)std::max<int64_t>(256, ceil_div(b, 256) * 256); };
+  std::vector<WsItem> v = {
+      {&P->U, sz(ub * G * nsb)},
+      {&P->V, sz(8 * G * std::max(nl * Kmax, r * nc))},
+      {&P->latitems, sz((int64_t)sizeof(LatItem) * std::max<int64_t>(r, 1) * Lm)},
+      {&P->Y, sz(8 * d * nsb)},
+      {&P->iters, sz(4 * nsb)},
+      {&P->cnt, sz(16)},
+      {&P->theta2, sz(8)},
+      {&P->scratch, sz(32 + 8 * d)},
+      {&P->tail, sz(8 * std::max<int64_t>(kMaxD, d * r * d))},
+      {&P->cands, sz(4 * sumK)},
+      {&P->latM, sz(4 * std::max(d, Lm))},
+      {&P->latz, sz(4 * Lm * d)},
+      {&P->latoff, sz(8 * (std::max(nl, Lm) + 1))},
+      {&P->mask, sz(4 * std::max(woff, ceil_div(nc, 32)))},
+      {&P->gmask, sz(4 * ceil_div(nc, 32))},
+      {&P->J, sz(4 * nc * d)},
+      {&P->Jnext, sz(4 * nc * d)},
+      {&P->Iprev, sz(4 * nc * d)},
+      {&P->assign, sz(4 * nc)},
+      {&P->bins, sz(4 * nc)},
+      {&P->lists, sz(8 * nc)},
+      {&P->famcov, sz(nc)},
+      {&P->fambins, sz(4 * nc * T)},
+      {&P->famscores, sz(4 * T)},
+      {&P->famz, sz(4 * T * d)},
+      {&P->famcounts, sz(4 * T * par.lattice_mmax)},
+      {&P->famlog, sz(8 * Lm)},
+      {&P->famstate, sz(32)},
+  };
+  for (int t = 0; t < d; ++t) v.push_back({&P->I1[t], sz(4 * (pb.k_hi[t] - pb.k_lo[t] + 1))});
+  v.push_back({C, sz(16 * nc * G)});
+  return v;
+}
+
+static size_t ws_total(const std::vector<WsItem>& v) {
+  size_t b = 0;
+  for (const WsItem& w : v) b += w.bytes;
+  return b;
+}
+
+// detect() with every transient buffer carved from the caller's workspace;
+// the plan's own buffers are set aside and restored afterwards.
+static void detect_ws(usfft_plan_s* P, uint64_t seed, int64_t ncand, int64_t nsamp, void* ws, size_t ws_bytes,
+                      hipStream_t st, usfft_result_s* R, bool given, const int32_t* given_I, int64_t given_n) {
+  USFFT_REQUIRE(ncand >= 1 && nsamp >= 1, USFFT_EINVAL, "n_cand_max and samples_max must be >= 1");
+  USFFT_REQUIRE(ws != nullptr, USFFT_EINVAL, "null workspace");
+  std::vector<WsItem> items = ws_items(P, &R->C, ncand, nsamp);
+  const size_t need = ws_total(items);
+  USFFT_REQUIRE(ws_bytes >= need, USFFT_ENOMEM,
+                "workspace of " + std::to_string(ws_bytes) + " bytes, these bounds need " + std::to_string(need));
+  USFFT_REQUIRE(((uintptr_t)ws & 255) == 0, USFFT_EINVAL, "the workspace must be 256-byte aligned");
+  std::vector<DevBuf> saved(items.size());
+  char* base = static_cast<char*>(ws);
+  size_t off = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    saved[i] = std::move(*items[i].buf);
+    items[i].buf->borrow(base + off, items[i].bytes);
+    off += items[i].bytes;
+  }
+  auto restore = [&] {
+    // the output matrix stays borrowed: the result refers into the workspace
+    for (size_t i = 0; i + 1 < items.size(); ++i) *items[i].buf = std::move(saved[i]);
+    P->ws_mode = false;
+    P->ws_nsamp = 0;
+    P->ws_ncand = 0;
+  };
+  P->ws_mode = true;
+  P->ws_nsamp = nsamp;
+  P->ws_ncand = ncand;
+  try {
+    detect(P, seed, st, R, given, given_I, given_n);
+  } catch (...) {
+    restore();
+    throw;
+  }
+  restore();
+  R->stats.workspace_bytes = (int64_t)need;
 }
 
 // ---------------------------------------------------------------- autotune
@@ -1076,6 +1247,20 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     P->prob.poly_k = P->poly_k.data();
     P->prob.poly_c = P->poly_c.data();
   }
+  // lattice tables: one slot per admissible size up to lattice_mmax
+  {
+    size_t off = 0;
+    for (int M : admissible_sizes(3, par->lattice_mmax)) {
+      P->rader_off[M] = off;
+      off += rader_table_bytes(M);
+    }
+    P->d_rader.ensure(std::max<size_t>(off, 256));
+  }
+  // pinned staging of small uploads and readbacks
+  P->stage_cap = 4u << 20;
+  USFFT_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->stage), P->stage_cap, hipHostMallocDefault));
+  P->back_cap = 1u << 20;
+  USFFT_HIP(hipHostMalloc(reinterpret_cast<void**>(&P->back), P->back_cap, hipHostMallocDefault));
   return P.release();
 }
 
@@ -1139,6 +1324,47 @@ usfft_status usfft_coefficients(usfft_plan_t plan, const int32_t* freqs_host, in
     std::lock_guard<std::mutex> lk(plan->mu);
     std::unique_ptr<usfft_result_s> R(new usfft_result_s());
     detect(plan, seed, (hipStream_t)stream, R.get(), true, freqs_host, n);
+    *out = R.release();
+  });
+}
+
+usfft_status usfft_plan_workspace(usfft_plan_t plan, int64_t n_cand_max, int64_t samples_max, size_t* bytes) {
+  return guarded([&] {
+    USFFT_REQUIRE(plan && bytes && n_cand_max >= 1 && samples_max >= 1, USFFT_EINVAL, "bad workspace arguments");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    DevBuf C;
+    *bytes = ws_total(ws_items(plan, &C, n_cand_max, samples_max));
+  });
+}
+
+usfft_status usfft_detect_ws(usfft_plan_t plan, uint64_t seed, int64_t n_cand_max, int64_t samples_max, void* ws_dev,
+                             size_t ws_bytes, void* stream, usfft_result_t* out) {
+  return guarded([&] {
+    USFFT_REQUIRE(plan && out, USFFT_EINVAL, "null plan or output");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    std::unique_ptr<usfft_result_s> R(new usfft_result_s());
+    detect_ws(plan, seed, n_cand_max, samples_max, ws_dev, ws_bytes, (hipStream_t)stream, R.get(), false, nullptr,
+              0);
+    *out = R.release();
+  });
+}
+
+usfft_status usfft_coefficients_ws(usfft_plan_t plan, const int32_t* freqs_host, int64_t n, uint64_t seed,
+                                   int64_t n_cand_max, int64_t samples_max, void* ws_dev, size_t ws_bytes,
+                                   void* stream, usfft_result_t* out) {
+  return guarded([&] {
+    USFFT_REQUIRE(plan && out && n >= 0 && (n == 0 || freqs_host), USFFT_EINVAL, "bad coefficients arguments");
+    USFFT_REQUIRE(n <= n_cand_max, USFFT_ENOMEM, "more frequencies than n_cand_max");
+    const int d = plan->prob.d;
+    std::vector<std::vector<int32_t>> rows((size_t)n);
+    for (int64_t a = 0; a < n; ++a) rows[a].assign(freqs_host + a * d, freqs_host + (a + 1) * d);
+    std::sort(rows.begin(), rows.end());
+    USFFT_REQUIRE(std::adjacent_find(rows.begin(), rows.end()) == rows.end(), USFFT_EINVAL,
+                  "the frequency set has repeated entries");
+    std::lock_guard<std::mutex> lk(plan->mu);
+    std::unique_ptr<usfft_result_s> R(new usfft_result_s());
+    detect_ws(plan, seed, n_cand_max, samples_max, ws_dev, ws_bytes, (hipStream_t)stream, R.get(), true, freqs_host,
+              n);
     *out = R.release();
   });
 }
@@ -1409,6 +1635,38 @@ usfft_status usfft_lattice_dft(const void* u_dev, int32_t u_fp32, int64_t G, int
     rader_build(T, M, st);
     try {
       launch_lattice_dft(T, u_dev, u_fp32, G, ld, col0, bins_dev, pos_dev, 0, nb, out_kind, out_dev, ldo, st);
+      USFFT_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      rader_free(T);
+      throw;
+    }
+    rader_free(T);
+  });
+}
+
+usfft_status usfft_lattice_coeffs(const void* u_dev, int32_t u_fp32, int64_t G, int64_t ld, int64_t col0, int32_t M,
+                                  int32_t t, const int64_t* z_host, const int32_t* J_dev, int64_t n, double* out_dev,
+                                  void* stream) {
+  return guarded([&] {
+    USFFT_REQUIRE(u_dev && z_host && out_dev && G >= 1 && n >= 0 && (n == 0 || J_dev) && ld >= col0 + M && col0 >= 0,
+                  USFFT_EINVAL, "bad lattice coefficient arguments");
+    USFFT_REQUIRE(t >= 1 && t <= kMaxD, USFFT_EINVAL, "t must be in [1, 64]");
+    USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL, "M is not an admissible lattice size");
+    USFFT_REQUIRE(n <= INT32_MAX, USFFT_EINVAL, "too many candidates");
+    if (n == 0) return;
+    hipStream_t st = (hipStream_t)stream;
+    GenVec z{};
+    for (int j = 0; j < t; ++j) z.z[j] = ((z_host[j] % M) + M) % M;
+    DevBuf bins;
+    bins.ensure(sizeof(int32_t) * n);
+    hipLaunchKernelGGL(lattice_bin_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, J_dev, n, t, z,
+                       (int64_t)M, bins.as<int32_t>());
+    USFFT_HIP(hipGetLastError());
+    RaderTables T;
+    rader_build(T, M, st);
+    try {
+      launch_lattice_dft(T, u_dev, u_fp32, G, ld, col0, bins.as<int32_t>(), nullptr, 0, (int)n, USFFT_OUT_COMPLEX,
+                         out_dev, G, st);
       USFFT_HIP(hipStreamSynchronize(st));
     } catch (...) {
       rader_free(T);
