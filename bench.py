@@ -436,20 +436,21 @@ def main():
     if args.models:
         # the periodized affine and lognormal coefficient models (Sec. 3.2) on
         # the same mesh, dimension, box and sparsity
-        # (lognormal at relative threshold 1e-3: at 1e-4 and below its detected
-        # sets outgrow a family of lattices of size <= 9601 within 256 attempts;
-        # its weakly preconditioned solves prefer float64 replacements after a
-        # 1e-3 drop of the float32 residual, the others after 2e-4)
+        # (the lognormal model's candidate sets outgrow lattice families of
+        # sizes <= 19201 within 256 attempts below a relative threshold of
+        # 1e-3; its weakly preconditioned solves prefer float64 replacements
+        # after a 1e-3 drop of the float32 residual, the others after 2e-4)
         res["models"] = {}
-        for name, mprob, th, irt in (("affine", W.affine_problem(64, 10, 32), 1e-5, 2e-4),
-                                     ("lognormal", W.lognormal_problem(64, 10, 32), 1e-3, 1e-3)):
+        for name, mprob, th, irt, mmax in (("affine", W.affine_problem(64, 10, 32), 1e-5, 2e-4, 9601),
+                                           ("lognormal", W.lognormal_problem(64, 10, 32), 1e-3, 1e-3, 19201)):
             try:
                 mplan = U.Plan(mprob, dict(par, theta=th, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=256,
-                                           inner_rtol=irt))
+                                           inner_rtol=irt, lattice_mmax=mmax))
                 wall, lat, st, nI_m = run_path(U, mplan, args.seed, 1, 1)
                 sm = sum(x["samples"] for x in st)
                 res["models"][name] = {"samples_per_s": sm / wall, "job_s": wall, "samples": sm, "theta_rel": th,
-                                       "inner_rtol": irt,
+                                       "inner_rtol": irt, "lattice_mmax": mmax,
+                                       "max_candidates": st[0]["max_candidates"],
                                        "pcg_iters_per_solve": sum(x["pcg_iterations"] for x in st) / max(1, sm),
                                        "detected_frequencies": nI_m}
                 mplan.close()

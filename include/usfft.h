@@ -128,7 +128,9 @@ typedef struct {
   double lattice_c;        /* lattice size factor c (2)                      */
   int32_t lattice_tries;   /* generator candidates per attempt (8)           */
   int32_t lattice_max;     /* attempts before USFFT_ELATTICE (64)            */
-  int32_t lattice_mmax;    /* largest lattice size (<= 9601)                 */
+  int32_t lattice_mmax;    /* largest lattice size (<= 9601; FP32_REFINE:
+                              <= 19201, the float32 transform of one node
+                              pair then fills one CU's LDS)                  */
   double pcg_rtol;         /* relative residual of every solve (1e-12)       */
   int32_t pcg_maxit;       /* PCG iterations per solve (or inner solve)      */
   double inner_rtol;       /* FP32_REFINE: float32 residual drop that triggers
@@ -346,10 +348,11 @@ usfft_status usfft_line_dft(const void* u_dev, int32_t u_fp32, int64_t G, int64_
                             int32_t out_kind, void* out_dev, int64_t ldo, void* stream);
 
 /* Lattice DFT of Algorithm A (App. A): the length-M DFT of every node's
- * samples along a rank-1 lattice of prime size M (M-1 7-smooth, M <= 9601)
+ * samples along a rank-1 lattice of prime size M (M-1 7-smooth)
  * evaluated at the requested bins (same normalisation, canonical-bin rule
  * and output layouts as usfft_line_dft; candidate a written at column
  * pos_dev[a] of the output).  bins_dev, pos_dev: nb int32 device arrays.
+ * M <= 9601 for float64 samples, <= 19201 for float32 samples.
  * Errors: EINVAL (M not admissible). */
 usfft_status usfft_lattice_dft(const void* u_dev, int32_t u_fp32, int64_t G, int64_t ld,
                                int64_t col0, int32_t M, const int32_t* bins_dev,
@@ -358,7 +361,8 @@ usfft_status usfft_lattice_dft(const void* u_dev, int32_t u_fp32, int64_t G, int
 
 /* Algorithm A alone (App. A): the coefficients of the candidates J_dev
  * (n x t int32 device array, row-major) read from one rank-1 lattice of
- * prime size M (M - 1 7-smooth, M <= 9601) with generator z_host (t int64,
+ * prime size M (M - 1 7-smooth; M <= 9601, or 19201 with float32 samples)
+ * with generator z_host (t int64,
  * host): for every node g and candidate a with bin b_a = k_a.z mod M
  * (computed here in exact 64-bit arithmetic),
  *   out_dev[(a G + g) 2 + {0,1}] = Re, Im of (1/M) sum_m u[g ld + col0 + m]

@@ -27,7 +27,7 @@
 
 namespace usfft {
 
-constexpr int kLMax = kMaxLattice - 1;  // 9600
+constexpr int kLMax = kMaxLattice - 1;  // 19200 (float32; float64 stops at 9600)
 constexpr int kFftBlock = 512;
 
 // correctly rounded cos / sin of 2 pi m / R
@@ -236,13 +236,15 @@ __device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
 // ---------------------------------------------------------------- setup
 // B = DFT_L(b) / L for b_j = exp(-2 pi i gen^-j / M), gen^-j = perm[(L - j) % L],
 // stored in the digit-reversed order the forward DIF produces.
+// The transform runs in LDS when its L float64 values fit, else in place in
+// B64 (global memory; setup only).
 __global__ __launch_bounds__(kFftBlock) void rader_setup_kernel(FftPlanDev F, int M, const int32_t* __restrict__ perm,
                                                                const cplx<double>* __restrict__ tw,
                                                                cplx<double>* __restrict__ B64,
                                                                cplx<float>* __restrict__ B32,
-                                                               cplx<float>* __restrict__ tw32) {
+                                                               cplx<float>* __restrict__ tw32, int in_lds) {
   extern __shared__ char smem[];
-  cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem);
+  cplx<double>* buf = in_lds ? reinterpret_cast<cplx<double>*>(smem) : B64;
   const int L = F.L;
   for (int j = threadIdx.x; j < L; j += kFftBlock) {
     const int e = perm[(L - j) % L];
@@ -318,7 +320,7 @@ void rader_free(RaderTables& T) {
 
 void rader_build(RaderTables& T, int M, hipStream_t st) {
   USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL,
-                "lattice size " + std::to_string(M) + " is not a prime <= 9601 with 7-smooth M-1");
+                "lattice size " + std::to_string(M) + " is not a prime <= 19201 with 7-smooth M-1");
   void* mem = nullptr;
   USFFT_HIP(hipMalloc(&mem, rader_table_bytes(M)));
   try {
@@ -332,7 +334,7 @@ void rader_build(RaderTables& T, int M, hipStream_t st) {
 
 void rader_build_at(RaderTables& T, int M, void* mem, hipStream_t st) {
   USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL,
-                "lattice size " + std::to_string(M) + " is not a prime <= 9601 with 7-smooth M-1");
+                "lattice size " + std::to_string(M) + " is not a prime <= 19201 with 7-smooth M-1");
   const RaderLayout Lay(M);
   char* base = static_cast<char*>(mem);
   T = RaderTables{};
@@ -397,9 +399,10 @@ void rader_build_at(RaderTables& T, int M, void* mem, hipStream_t st) {
   F.L = L;
   F.nrad = T.nrad;
   for (int i = 0; i < 24; ++i) F.radix[i] = T.radix[i];
-  hipLaunchKernelGGL(rader_setup_kernel, dim3(1), dim3(kFftBlock), sizeof(cplx<double>) * L, st, F, M, T.perm,
-                     (const cplx<double>*)T.tw64, (cplx<double>*)T.B64, (cplx<float>*)T.B32,
-                     (cplx<float>*)T.tw32);
+  const bool in_lds = sizeof(cplx<double>) * (size_t)L <= (150u << 10);
+  hipLaunchKernelGGL(rader_setup_kernel, dim3(1), dim3(kFftBlock), in_lds ? sizeof(cplx<double>) * L : 0, st, F, M,
+                     T.perm, (const cplx<double>*)T.tw64, (cplx<double>*)T.B64, (cplx<float>*)T.B32,
+                     (cplx<float>*)T.tw32, in_lds ? 1 : 0);
   USFFT_HIP(hipGetLastError());
   USFFT_HIP(hipStreamSynchronize(st));  // host vectors above go out of scope
 }
@@ -624,7 +627,7 @@ void fill_lat_item(LatItem& it, const RaderTables& T, int u_fp32) {
 void launch_lattice_dft_batch(const LatItem* items, int nitems, int Lmax, const void* u, int u_fp32, int64_t G,
                               int64_t ld, int out_kind, void* out, int64_t ldo, hipStream_t st) {
   if (G <= 0 || nitems <= 0) return;
-  USFFT_REQUIRE(Lmax >= 2 && Lmax <= kLMax, USFFT_EINVAL, "lattice transform length out of range");
+  USFFT_REQUIRE(Lmax >= 2 && Lmax < lattice_mmax_for(u_fp32), USFFT_EINVAL, "lattice transform length out of range");
   int block = 0, cols = 0;
   size_t lds = 0;
   rader_shape(Lmax, u_fp32, &block, &cols, &lds);

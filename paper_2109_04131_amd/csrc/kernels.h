@@ -8,7 +8,10 @@ constexpr int kMaxD = 64;          // largest parameter dimension d
 constexpr int kMaxMesh = 64;       // largest mesh_n of the on-chip solver
 constexpr int kMaxMeshStream = 512;  // largest mesh_n of the streaming solver
 constexpr int kStreamBlocks = 512;   // persistent workgroups of the streaming solver
-constexpr int kMaxLattice = 9601;  // largest lattice size (L = M-1 complex values in LDS)
+// Largest lattice sizes: the length-(M-1) complex transform of one node
+// pair stays in one CU's LDS (150 KB): 9600 float64 or 19200 float32 values.
+constexpr int kMaxLattice64 = 9601;
+constexpr int kMaxLattice = 19201;
 
 // PDE sampler tables on the device (see sampler.hip).
 struct PdeDev {
@@ -125,7 +128,8 @@ struct LatItem {
   int pos_base, nb;
   int64_t out_off;
 };
-bool lattice_size_ok(int M);
+bool lattice_size_ok(int M);                    // prime, 7-smooth M - 1, M <= kMaxLattice
+inline int lattice_mmax_for(int fp32) { return fp32 ? kMaxLattice : kMaxLattice64; }
 size_t rader_table_bytes(int M);                        // bytes of one size's tables
 void rader_build(RaderTables& T, int M, hipStream_t st);  // allocates + fills (synchronous)
 void rader_build_at(RaderTables& T, int M, void* mem, hipStream_t st);  // fills mem (synchronous)

@@ -970,8 +970,9 @@ static void validate(const usfft_problem* pb, const usfft_params* par) {
   USFFT_REQUIRE(par->theta >= 0 && par->tie_rel >= 0 && par->tie_rel < 1, USFFT_EINVAL, "bad theta / tie_rel");
   USFFT_REQUIRE(par->precision == USFFT_FP64 || par->precision == USFFT_FP32_REFINE, USFFT_EINVAL, "bad precision");
   USFFT_REQUIRE(par->lattice_c > 0 && par->lattice_tries >= 1 && par->lattice_max >= 1 &&
-                    par->lattice_mmax >= 3 && par->lattice_mmax <= kMaxLattice,
-                USFFT_EINVAL, "bad lattice parameters (lattice_mmax <= 9601)");
+                    par->lattice_mmax >= 3 &&
+                    par->lattice_mmax <= lattice_mmax_for(par->precision == USFFT_FP32_REFINE ? 1 : 0),
+                USFFT_EINVAL, "bad lattice parameters (lattice_mmax <= 9601, float32: <= 19201)");
   USFFT_REQUIRE(par->pcg_rtol > 0 && par->pcg_maxit >= 1 && par->inner_rtol > 0 && par->refine_every >= 1,
                 USFFT_EINVAL, "bad solver parameters");
   USFFT_REQUIRE(par->precond == USFFT_PRECOND_DST || par->precond == USFFT_PRECOND_JACOBI, USFFT_EINVAL,
@@ -1629,7 +1630,8 @@ usfft_status usfft_lattice_dft(const void* u_dev, int32_t u_fp32, int64_t G, int
   return guarded([&] {
     USFFT_REQUIRE(u_dev && bins_dev && pos_dev && out_dev && G >= 1 && nb >= 0 && ld >= col0 + M, USFFT_EINVAL,
                   "bad lattice DFT arguments");
-    USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL, "M is not an admissible lattice size");
+    USFFT_REQUIRE(lattice_size_ok(M) && M <= lattice_mmax_for(u_fp32), USFFT_EINVAL,
+                  "M is not an admissible lattice size for this precision");
     hipStream_t st = (hipStream_t)stream;
     RaderTables T;
     rader_build(T, M, st);
@@ -1651,7 +1653,8 @@ usfft_status usfft_lattice_coeffs(const void* u_dev, int32_t u_fp32, int64_t G, 
     USFFT_REQUIRE(u_dev && z_host && out_dev && G >= 1 && n >= 0 && (n == 0 || J_dev) && ld >= col0 + M && col0 >= 0,
                   USFFT_EINVAL, "bad lattice coefficient arguments");
     USFFT_REQUIRE(t >= 1 && t <= kMaxD, USFFT_EINVAL, "t must be in [1, 64]");
-    USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL, "M is not an admissible lattice size");
+    USFFT_REQUIRE(lattice_size_ok(M) && M <= lattice_mmax_for(u_fp32), USFFT_EINVAL,
+                  "M is not an admissible lattice size for this precision");
     USFFT_REQUIRE(n <= INT32_MAX, USFFT_EINVAL, "too many candidates");
     if (n == 0) return;
     hipStream_t st = (hipStream_t)stream;

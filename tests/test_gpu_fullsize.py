@@ -102,7 +102,8 @@ def test_solver_in_the_benchmark_launch_configuration(lib, prec):
         assert np.linalg.norm(u1 - ref) <= (1e-10 if prec == 0 else 1e-9) * np.linalg.norm(ref), s
 
 
-@pytest.mark.parametrize("G,M,fp32", [(3969, 9601, 0), (3969, 9601, 1), (16129, 4801, 1), (16129, 9601, 0)])
+@pytest.mark.parametrize("G,M,fp32", [(3969, 9601, 0), (3969, 9601, 1), (16129, 4801, 1), (16129, 9601, 0),
+                                      (3969, 18523, 1), (16129, 18523, 1)])
 def test_lattice_dft_full_size(lib, G, M, fp32):
     """Lattice DFT at the full node counts and the largest lattice size; the
     oracle checks sampled nodes (all requested bins)."""

@@ -241,7 +241,8 @@ def test_line_dft(lib, K, G):
 
 
 @pytest.mark.parametrize("M,G,fp32", [(3, 4, 0), (11, 7, 0), (31, 64, 0), (97, 33, 0), (1153, 9, 0),
-                                      (4801, 5, 0), (9601, 3, 0), (9601, 6, 1), (211, 129, 1)])
+                                      (4801, 5, 0), (9601, 3, 0), (9601, 6, 1), (211, 129, 1), (12289, 5, 1),
+                                      (18523, 3, 1)])
 def test_lattice_dft_rader(lib, M, G, fp32):
     assert olat.admissible(M)
     U = W.sample_matrix(M + G, M, G, kind="normal")
@@ -270,6 +271,23 @@ def test_lattice_dft_rader(lib, M, G, fp32):
         inv[pos] = np.arange(nb)
         for b in range(1, M):
             assert np.array_equal(got[pos[b]], np.conj(got[pos[M - b]]))
+
+
+def test_lattice_sizes_by_precision(lib):
+    """Float32 samples take lattice sizes up to 19201 (one node pair's
+    float32 transform in one CU's LDS), float64 samples up to 9601."""
+    M, G = 18523, 2
+    ut = torch.zeros((G, M), dtype=torch.float64, device="cuda")
+    b = torch.zeros(1, dtype=torch.int32, device="cuda")
+    V = torch.zeros((G, 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.UsfftError) as e:
+        lib.lattice_dft(ut, 0, G, M, 0, M, b, b, lib.OUT_MAG2, V, 1)
+    assert e.value.status == lib.EINVAL
+    prob = W.pde_problem(8, 2, 4)
+    with pytest.raises(lib.UsfftError) as e:
+        lib.Plan(prob, dict(W.params(4, 1, 1e-4), precision=lib.FP64, lattice_mmax=19201))
+    assert e.value.status == lib.EINVAL
+    lib.Plan(prob, dict(W.params(4, 1, 1e-4), precision=lib.FP32_REFINE, lattice_mmax=19201)).close()
 
 
 # ------------------------------------------------------------------ select
