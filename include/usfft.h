@@ -115,6 +115,17 @@ typedef struct {
   const double* mesh_xy;          /* nv x 2                                  */
   const int32_t* mesh_tri;        /* nt x 3, vertex indices                  */
   const uint8_t* mesh_boundary;   /* nv, nonzero: boundary (u = 0) vertex    */
+  /* Node set T_G given by points (Sec. 3.1: the solver's values at nodes
+   * that are not mesh vertices are interpolated).  n_nodes = 0: T_G = the
+   * mesh's inner vertices (as above).  n_nodes > 0 (PDE and PDE_MESH
+   * samplers): T_G = the points nodes_xy (n_nodes x 2, in [0,1]^2); every
+   * sample is the P1 solution at the points, sum over the vertices of the
+   * containing triangle of barycentric coordinate x vertex value (0 at
+   * boundary vertices), computed on the device from the solve at the mesh
+   * vertices.  G = n_nodes everywhere (results, usfft_sample rows, eval).
+   * EINVAL for points outside the domain or the triangulation. */
+  int64_t n_nodes;
+  const double* nodes_xy;
 } usfft_problem;
 
 /* Parameters of Alg. 1 ("Input": s, s_local, Algorithm A, theta, r) and of

@@ -42,7 +42,7 @@ class _Problem(C.Structure):
                 ("model", C.c_int32), ("alpha", C.c_double), ("beta", C.c_double), ("delta", C.c_double),
                 ("basis1", C.c_int32), ("basis2", C.c_int32),
                 ("mesh_nv", C.c_int32), ("mesh_nt", C.c_int32), ("mesh_xy", _PD), ("mesh_tri", _P32),
-                ("mesh_boundary", C.POINTER(C.c_uint8))]
+                ("mesh_boundary", C.POINTER(C.c_uint8)), ("n_nodes", C.c_int64), ("nodes_xy", _PD)]
 
 
 class _Params(C.Structure):
@@ -203,6 +203,11 @@ def _marshal(problem, params):
         pr.delta = float(problem.get("delta", 0.0))
         pr.basis1 = int(problem.get("basis1", 0))
         pr.basis2 = int(problem.get("basis2", 0))
+        if problem.get("nodes_xy") is not None:
+            pts = np.ascontiguousarray(np.asarray(problem["nodes_xy"], dtype=np.float64).reshape(-1, 2))
+            keep.append(pts)
+            pr.n_nodes = len(pts)
+            pr.nodes_xy = pts.ctypes.data_as(_PD)
     else:
         pr.sampler = SAMPLER_TRIG_POLY
         K = np.asarray(problem["poly_k"])

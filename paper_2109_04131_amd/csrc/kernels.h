@@ -87,6 +87,10 @@ void launch_pde_solve_dst(const PdeDev& P, int precision, int variant, const dou
                           int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
                           int64_t col0, int* iters, double* wscr, int wblocks, const void* frag, const float* lam,
                           hipStream_t st);
+// samples at a point set from samples at the mesh's inner vertices (G points,
+// three (vertex row or -1, weight) pairs each; um: rows of ldm, same type as out)
+void launch_interp(const void* um, int fp32, int64_t ldm, const int32_t* idx, const double* w, int64_t G, int64_t ns,
+                   void* out, int64_t ld, int64_t col0, hipStream_t st);
 void launch_trigpoly(int d, const double* Y, int64_t ns, const int32_t* K, int64_t np, const double* C,
                      int64_t G, void* out, int out_fp32, int64_t ld, int64_t col0, hipStream_t st);
 

@@ -633,4 +633,39 @@ void launch_trigpoly(int d, const double* Y, int64_t ns, const int32_t* K, int64
   USFFT_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- node set
+// u(x_g) = sum_a w[3 g + a] u_mesh(v_a) for every point g and sample s: three
+// rows of the mesh-vertex samples per point (neighbouring points share
+// vertices, so the rows mostly come from L2), one coalesced output row.
+template <typename T>
+__global__ __launch_bounds__(256) void interp_kernel(const T* __restrict__ um, int64_t ldm,
+                                                     const int32_t* __restrict__ idx, const double* __restrict__ w,
+                                                     int64_t G, int64_t ns, T* __restrict__ out, int64_t ld,
+                                                     int64_t col0) {
+  const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (s >= ns) return;
+  for (int64_t g = blockIdx.y; g < G; g += gridDim.y) {
+    double v = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int r = idx[3 * g + a];
+      if (r >= 0) v += w[3 * g + a] * (double)um[(int64_t)r * ldm + s];
+    }
+    out[g * ld + col0 + s] = (T)v;
+  }
+}
+
+void launch_interp(const void* um, int fp32, int64_t ldm, const int32_t* idx, const double* w, int64_t G, int64_t ns,
+                   void* out, int64_t ld, int64_t col0, hipStream_t st) {
+  if (G <= 0 || ns <= 0) return;
+  const dim3 grid((unsigned)ceil_div(ns, 256), (unsigned)std::min<int64_t>(G, 65535));
+  if (fp32)
+    hipLaunchKernelGGL(interp_kernel<float>, grid, dim3(256), 0, st, (const float*)um, ldm, idx, w, G, ns,
+                       (float*)out, ld, col0);
+  else
+    hipLaunchKernelGGL(interp_kernel<double>, grid, dim3(256), 0, st, (const double*)um, ldm, idx, w, G, ns,
+                       (double*)out, ld, col0);
+  USFFT_HIP(hipGetLastError());
+}
+
 }  // namespace usfft

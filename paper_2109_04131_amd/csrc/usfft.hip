@@ -113,6 +113,12 @@ struct usfft_plan_s {
   usfft::DevBuf d_amp, d_tab, d_polyk, d_polyc, d_stream, d_wscr, d_sfrag, d_lam;
   // general triangulation
   usfft::DevBuf m_rowptr, m_col, m_diag, m_cptr, m_ctri, m_cw, m_load, m_psi;
+  // node set T_G given by points (Sec. 3.1): the solver's values at the
+  // mesh's inner vertices (G_mesh of them, in Umesh) are interpolated to the
+  // G points through three (inner vertex or -1, weight) pairs per point
+  bool interp = false;
+  int64_t G_mesh = 0;
+  usfft::DevBuf d_iidx, d_iw, Umesh;
   usfft::MeshDev mesh{};
   int mesh_blocks = 0;
   // pinned staging of small uploads: a copy from it needs no host wait; the
@@ -345,11 +351,28 @@ static void group_by_lattice(usfft_plan_s* P, Family& F, const int32_t* assign, 
   h2d_async(P, P->lists, lists, st);
 }
 
-// Sampler call on rows [0, ns) of Y into U columns [col0, col0 + ns).
-// params: Y holds parameters y of the model instead of sampling nodes t
+// One solver launch at the mesh's own nodes.  params: Y holds parameters y
+// of the model instead of sampling nodes t.
+static void solve_batch(usfft_plan_s* P, const double* Y, int64_t ns, void* U, int out_fp32, int64_t ld,
+                        int64_t col0, int32_t* iters, hipStream_t st, bool params);
+
+// Sampler call on rows [0, ns) of Y into U columns [col0, col0 + ns): the
+// solver's values at the nodes T_G (interpolated when T_G is a point set).
 static void run_sampler(usfft_plan_s* P, const double* Y, int64_t ns, void* U, int out_fp32, int64_t ld,
                         int64_t col0, int32_t* iters, hipStream_t st, bool params = false) {
   if (ns <= 0) return;
+  if (!P->interp) {
+    solve_batch(P, Y, ns, U, out_fp32, ld, col0, iters, st, params);
+    return;
+  }
+  const int64_t ldm = ceil_div(ns, 64) * 64;
+  P->Umesh.ensure((out_fp32 ? sizeof(float) : sizeof(double)) * P->G_mesh * ldm);
+  solve_batch(P, Y, ns, P->Umesh.p, out_fp32, ldm, 0, iters, st, params);
+  launch_interp(P->Umesh.p, out_fp32, ldm, P->d_iidx.as<int32_t>(), P->d_iw.as<double>(), P->G, ns, U, ld, col0, st);
+}
+
+static void solve_batch(usfft_plan_s* P, const double* Y, int64_t ns, void* U, int out_fp32, int64_t ld,
+                        int64_t col0, int32_t* iters, hipStream_t st, bool params) {
   const usfft_params& par = P->par;
   PdeDev pde = P->pde;
   pde.raw = params ? 1 : 0;
@@ -854,6 +877,7 @@ static std::vector<WsItem> ws_items(usfft_plan_s* P, DevBuf* C, int64_t ncand, i
       {&P->famstate, sz(32)},
   };
   for (int t = 0; t < d; ++t) v.push_back({&P->I1[t], sz(4 * (pb.k_hi[t] - pb.k_lo[t] + 1))});
+  if (P->interp) v.push_back({&P->Umesh, sz(ub * P->G_mesh * nsb)});
   v.push_back({C, sz(16 * nc * G)});
   return v;
 }
@@ -977,6 +1001,7 @@ static void validate(const usfft_problem* pb, const usfft_params* par) {
                 USFFT_EINVAL, "bad solver parameters");
   USFFT_REQUIRE(par->precond == USFFT_PRECOND_DST || par->precond == USFFT_PRECOND_JACOBI, USFFT_EINVAL,
                 "bad preconditioner");
+  USFFT_REQUIRE(pb->n_nodes >= 0 && pb->n_nodes <= (int64_t)1 << 30, USFFT_EINVAL, "bad n_nodes");
   if (pb->sampler == USFFT_SAMPLER_PDE || pb->sampler == USFFT_SAMPLER_PDE_MESH) {
     if (pb->sampler == USFFT_SAMPLER_PDE)
       USFFT_REQUIRE(pb->mesh_n >= 4 && pb->mesh_n <= kMaxMeshStream, USFFT_EINVAL, "mesh_n must be in [4, 512]");
@@ -1141,6 +1166,95 @@ static void build_mesh(usfft_plan_s* P, const usfft_problem* pb, const usfft_par
   P->pde.delta = pb->delta > 0 ? pb->delta : 1.0 / (4.0 * par->lattice_mmax);
 }
 
+// Interpolation of the P1 solution to the caller's points (Sec. 3.1): the
+// containing triangle of every point and its barycentric coordinates.
+// Uniform mesh: the cell from the scaled coordinates, then the triangle below
+// or above the cell's diagonal.  General triangulation: candidate triangles
+// from a bucket grid over the unit square, in triangle order.  Boundary
+// vertices carry the Dirichlet value 0 and drop out.
+static void build_interp(usfft_plan_s* P, const usfft_problem* pb) {
+  const int64_t np = pb->n_nodes;
+  USFFT_REQUIRE(pb->nodes_xy != nullptr, USFFT_EINVAL, "n_nodes > 0 needs nodes_xy");
+  USFFT_REQUIRE(pb->sampler == USFFT_SAMPLER_PDE || pb->sampler == USFFT_SAMPLER_PDE_MESH, USFFT_EINVAL,
+                "a node set T_G given by points needs a PDE sampler");
+  std::vector<int32_t> idx((size_t)np * 3, -1);
+  std::vector<double> w((size_t)np * 3, 0.0);
+  auto inside_unit = [](double x) { return x >= 0.0 && x <= 1.0; };
+  if (pb->sampler == USFFT_SAMPLER_PDE) {
+    const int n = pb->mesh_n;
+    auto inner = [n](int a, int b) { return (a >= 1 && a <= n - 1 && b >= 1 && b <= n - 1) ? (b - 1) * (n - 1) + (a - 1) : -1; };
+    for (int64_t p = 0; p < np; ++p) {
+      const double x = pb->nodes_xy[2 * p], y = pb->nodes_xy[2 * p + 1];
+      USFFT_REQUIRE(inside_unit(x) && inside_unit(y), USFFT_EINVAL, "a node lies outside the unit square");
+      const int i = std::min((int)std::floor(x * n), n - 1), j = std::min((int)std::floor(y * n), n - 1);
+      const double xi = x * n - i, eta = y * n - j;
+      int v[3][2];
+      double l[3];
+      if (xi >= eta) {  // triangle (i,j), (i+1,j), (i+1,j+1)
+        v[0][0] = i; v[0][1] = j; v[1][0] = i + 1; v[1][1] = j; v[2][0] = i + 1; v[2][1] = j + 1;
+        l[0] = 1.0 - xi; l[1] = xi - eta; l[2] = eta;
+      } else {          // triangle (i,j), (i,j+1), (i+1,j+1)
+        v[0][0] = i; v[0][1] = j; v[1][0] = i; v[1][1] = j + 1; v[2][0] = i + 1; v[2][1] = j + 1;
+        l[0] = 1.0 - eta; l[1] = eta - xi; l[2] = xi;
+      }
+      for (int a = 0; a < 3; ++a) {
+        idx[3 * p + a] = inner(v[a][0], v[a][1]);
+        w[3 * p + a] = idx[3 * p + a] >= 0 ? l[a] : 0.0;
+      }
+    }
+    P->G_mesh = (int64_t)(n - 1) * (n - 1);
+  } else {
+    const int nv = pb->mesh_nv, nt = pb->mesh_nt;
+    std::vector<int> gid(nv, -1);
+    int gm = 0;
+    for (int v = 0; v < nv; ++v)
+      if (!pb->mesh_boundary[v]) gid[v] = gm++;
+    constexpr int NB = 64;
+    std::vector<std::vector<int>> bucket(NB * NB);
+    auto cell = [](double c) { return std::min(NB - 1, std::max(0, (int)std::floor(c * NB))); };
+    for (int t = 0; t < nt; ++t) {
+      double x0 = 2, x1 = -1, y0 = 2, y1 = -1;
+      for (int a = 0; a < 3; ++a) {
+        const int v = pb->mesh_tri[3 * t + a];
+        x0 = std::min(x0, pb->mesh_xy[2 * v]);
+        x1 = std::max(x1, pb->mesh_xy[2 * v]);
+        y0 = std::min(y0, pb->mesh_xy[2 * v + 1]);
+        y1 = std::max(y1, pb->mesh_xy[2 * v + 1]);
+      }
+      for (int bj = cell(y0); bj <= cell(y1); ++bj)
+        for (int bi = cell(x0); bi <= cell(x1); ++bi) bucket[bj * NB + bi].push_back(t);
+    }
+    for (int64_t p = 0; p < np; ++p) {
+      const double x = pb->nodes_xy[2 * p], y = pb->nodes_xy[2 * p + 1];
+      USFFT_REQUIRE(inside_unit(x) && inside_unit(y), USFFT_EINVAL, "a node lies outside the unit square");
+      bool found = false;
+      for (int t : bucket[cell(y) * NB + cell(x)]) {
+        const int* tv = pb->mesh_tri + 3 * t;
+        const double ax = pb->mesh_xy[2 * tv[0]], ay = pb->mesh_xy[2 * tv[0] + 1];
+        const double bx = pb->mesh_xy[2 * tv[1]] - ax, by = pb->mesh_xy[2 * tv[1] + 1] - ay;
+        const double cx = pb->mesh_xy[2 * tv[2]] - ax, cy = pb->mesh_xy[2 * tv[2] + 1] - ay;
+        const double det = bx * cy - by * cx, rx = x - ax, ry = y - ay;
+        const double l1 = (rx * cy - ry * cx) / det, l2 = (bx * ry - by * rx) / det, l0 = 1.0 - l1 - l2;
+        if (std::min(l0, std::min(l1, l2)) < -1e-12) continue;
+        const double l[3] = {l0, l1, l2};
+        for (int a = 0; a < 3; ++a) {
+          idx[3 * p + a] = gid[tv[a]];
+          w[3 * p + a] = gid[tv[a]] >= 0 ? l[a] : 0.0;
+        }
+        found = true;
+        break;
+      }
+      USFFT_REQUIRE(found, USFFT_EINVAL, "a node lies outside the triangulation");
+    }
+    P->G_mesh = gm;
+  }
+  P->d_iidx.ensure(sizeof(int32_t) * idx.size());
+  P->d_iw.ensure(sizeof(double) * w.size());
+  USFFT_HIP(hipMemcpy(P->d_iidx.p, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice));
+  USFFT_HIP(hipMemcpy(P->d_iw.p, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice));
+  P->interp = true;
+}
+
 static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* par) {
   validate(pb, par);
   std::unique_ptr<usfft_plan_s> P(new usfft_plan_s());
@@ -1248,6 +1362,11 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     P->prob.poly_k = P->poly_k.data();
     P->prob.poly_c = P->poly_c.data();
   }
+  if (pb->n_nodes > 0) {
+    build_interp(P.get(), pb);
+    P->G = pb->n_nodes;
+  }
+  P->prob.nodes_xy = nullptr;
   // lattice tables: one slot per admissible size up to lattice_mmax
   {
     size_t off = 0;
@@ -1747,7 +1866,7 @@ struct JobSpec {
   usfft_problem prob{};
   usfft_params par{};
   std::vector<int32_t> k_lo, k_hi, mode1, mode2, poly_k, mesh_tri;
-  std::vector<double> amp, poly_c, mesh_xy;
+  std::vector<double> amp, poly_c, mesh_xy, nodes_xy;
   std::vector<uint8_t> mesh_boundary;
   void copy(const usfft_problem* pb, const usfft_params* pa) {
     validate(pb, pa);
@@ -1772,6 +1891,10 @@ struct JobSpec {
         prob.mesh_xy = mesh_xy.data();
         prob.mesh_tri = mesh_tri.data();
         prob.mesh_boundary = mesh_boundary.data();
+      }
+      if (pb->n_nodes > 0 && pb->nodes_xy) {
+        nodes_xy.assign(pb->nodes_xy, pb->nodes_xy + 2 * (size_t)pb->n_nodes);
+        prob.nodes_xy = nodes_xy.data();
       }
     } else {
       poly_k.assign(pb->poly_k, pb->poly_k + (size_t)pb->n_poly * d);

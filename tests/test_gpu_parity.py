@@ -777,3 +777,64 @@ def test_error_paths(lib):
     with pytest.raises(lib.UsfftError) as e:
         lib.detect(plan, 1)
     assert e.value.status == lib.ELATTICE
+
+
+# ------------------------------------------------------------------ node sets given by points
+@pytest.mark.parametrize("kind,prec", [("uniform", 0), ("uniform", 1), ("jittered", 0)])
+def test_solves_at_points(lib, kind, prec):
+    """Sec. 3.1: solves at nodes that are not mesh vertices (P1 interpolation
+    from the containing triangle) against the oracle's solve followed by its
+    own brute-force point location; 150 seeded points plus every corner
+    region and a few vertices."""
+    from oracle import interp as oi
+    from oracle.fem_mesh import MeshSampler
+    d = 4
+    pts = np.concatenate([W.random_points(150, 8), [[0.0, 0.0], [1.0, 1.0], [0.5, 0.5], [0.25, 0.75], [1.0, 0.3]]])
+    if kind == "uniform":
+        n = 16
+        prob = dict(W.pde_problem(n, d, 4), nodes_xy=pts)
+        mesh = W.uniform_mesh(n)
+        S = ofem.PDESampler(n, prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    else:
+        mesh = W.jittered_mesh(12, 11, 2)
+        prob = dict(W.mesh_problem(mesh, d, 4), nodes_xy=pts)
+        S = MeshSampler(mesh["mesh_xy"], mesh["mesh_tri"], mesh["mesh_boundary"], prob["a0"], prob["amp"],
+                        prob["mode1"], prob["mode2"])
+    IS = oi.InterpolatingSampler(S, mesh["mesh_xy"], mesh["mesh_tri"], mesh["mesh_boundary"], pts)
+    plan = lib.Plan(prob, dict(W.params(4, 1, 1e-4), precision=prec, pcg_rtol=1e-13 if prec == 0 else 1e-12))
+    assert plan.G == len(pts)
+    Y = np.random.default_rng(3).random((9, d))
+    U = torch.zeros((plan.G, 16), dtype=torch.float64, device="cuda")
+    lib.sample(plan, dev(Y), U, 0, 16, 3)
+    Ug = host(U)[:, 3:12].T
+    ref = IS(Y)
+    err = (np.linalg.norm(Ug - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
+    assert err <= (1e-11 if prec == 0 else 1e-9), err
+
+
+def test_detect_at_points_matches_oracle(lib):
+    """A whole CPU-scale job (h = 1/16, d = 4) on 90 seeded points against the
+    oracle's Alg. 1 with the interpolating sampler: identical sets,
+    coefficients within 1e-10 of the largest."""
+    from oracle import interp as oi
+    from oracle.usfft import usfft
+    prob, par = W.WORKLOADS["cpu16_d4"]
+    pts = W.random_points(90, 21)
+    prob = dict(prob, nodes_xy=pts)
+    mesh = W.uniform_mesh(prob["mesh_n"])
+    S = ofem.PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    IS = oi.InterpolatingSampler(S, mesh["mesh_xy"], mesh["mesh_tri"], mesh["mesh_boundary"], pts)
+    plan = lib.Plan(prob, dict(par, precision=lib.FP64, pcg_rtol=1e-13))
+    res = lib.detect(plan, 6)
+    ref = usfft(IS, prob["d"], prob["k_lo"], prob["k_hi"], par["s"], par["s_local"], par["r"], par["theta"], True, 6)
+    assert res.freqs().tolist() == ref.I.tolist()
+    assert res.stats["samples"] == ref.samples
+    err = np.abs(res.coeffs() - ref.C).max() / np.abs(ref.C).max()
+    assert err <= 1e-10, err
+
+
+def test_points_outside_rejected(lib):
+    prob = dict(W.pde_problem(8, 2, 4), nodes_xy=[[0.5, 0.5], [1.5, 0.2]])
+    with pytest.raises(lib.UsfftError) as e:
+        lib.Plan(prob, W.params(4, 1, 1e-4))
+    assert e.value.status == lib.EINVAL

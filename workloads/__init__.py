@@ -258,6 +258,11 @@ def jittered_mesh(n_bnd, n_in, seed, jitter=0.3):
     return dict(mesh_xy=xy, mesh_tri=tri, mesh_boundary=bnd)
 
 
+def random_points(n, seed):
+    """n seeded points uniform in the open unit square (a node set T_G)."""
+    return np.random.default_rng(seed).uniform(0.0, 1.0, (n, 2))
+
+
 def mesh_problem(mesh, d, N, a0=1.0, modes="split"):
     """The periodic coefficient family of pde_problem on a general triangulation."""
     m1, m2 = (modes_diagonal if modes == "diagonal" else modes_split)(d)
