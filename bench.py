@@ -57,34 +57,46 @@ def run_path(U, plan, seed, steps, warmup):
 
 def serving_run(U, jobs, rate, seed, max_active):
     """Poisson arrivals (mean `rate` jobs/s) into the continuous-batching
-    server; returns jobs/s, p50/p99 latency and aggregate solves/s."""
+    server: jobs/s, p50/p99 latency and aggregate solves/s; then the same jobs
+    submitted at once (the server's capacity, every job queued from t = 0)."""
     import workloads as W
     stream = W.serving_stream(seed=seed, rate=rate, jobs=jobs)
-    srv = U.Server(max_active=max_active)
-    t0 = time.perf_counter()
-    ids = []
-    for t_arr, prob, par, s in stream:
-        delay = t_arr - (time.perf_counter() - t0)
-        if delay > 0:
-            time.sleep(delay)
-        ids.append(srv.submit(prob, dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=256), s))
-    lat, qs, solves, failed = [], [], 0, 0
-    for jid in ids:
-        res, st, l, q, err = srv.poll(jid, wait=True)
-        if st != U.OK:
-            failed += 1
-            continue
-        lat.append(l)
-        qs.append(q)
-        solves += res.stats["samples"]
-        res.close()
-    wall = time.perf_counter() - t0
-    srv.close()
+
+    def run(arrivals):
+        srv = U.Server(max_active=max_active)
+        t0 = time.perf_counter()
+        ids = []
+        for (t_arr, prob, par, s) in stream:
+            delay = (t_arr if arrivals else 0.0) - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(prob, dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=256), s))
+        lat, qs, solves, failed, reused = [], [], 0, 0, 0
+        for jid in ids:
+            res, st, l, q, err = srv.poll(jid, wait=True)
+            if st != U.OK:
+                failed += 1
+                continue
+            lat.append(l)
+            qs.append(q)
+            solves += res.stats["samples"]
+            reused += res.stats["plan_reused"]
+            res.close()
+        wall = time.perf_counter() - t0
+        srv.close()
+        return lat, qs, solves, failed, reused, wall
+
+    lat, qs, solves, failed, reused, wall = run(True)
+    blat, bqs, bsolves, bfailed, breused, bwall = run(False)
     return {"jobs": len(stream), "failed": failed, "arrival_rate_per_s": rate, "max_active": max_active,
             "jobs_per_s": len(lat) / wall, "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
-            "p50_queue_s": pct(qs, 50), "samples_per_s": solves / wall, "wall_s": wall,
+            "p50_queue_s": pct(qs, 50), "samples_per_s": solves / wall, "wall_s": wall, "plans_reused": reused,
             "stream": "Poisson(4/s) jobs, meshes 16^2..64^2, d 4..10, N 16..32, s 50..200, "
-                      "float32+refine, seed %d" % seed}
+                      "float32+refine, seed %d" % seed,
+            "burst": {"jobs_per_s": len(blat) / bwall, "p50_latency_s": pct(blat, 50),
+                      "p99_latency_s": pct(blat, 99), "samples_per_s": bsolves / bwall, "failed": bfailed,
+                      "plans_reused": breused,
+                      "note": "the same jobs submitted at once: capacity of the server"}}
 
 
 def evaluation_run(U, torch, plan, prob, seed, n_test):

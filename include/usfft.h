@@ -192,6 +192,8 @@ typedef struct {
                                _ws calls that runs this job                  */
   int64_t workspace_bytes;  /* _ws calls: bytes of the caller's workspace the
                                bounds took (usfft_plan_workspace's value)    */
+  int64_t plan_reused;      /* server jobs: 1 when the job ran on a pooled
+                               plan of an earlier job                        */
 } usfft_stats;
 
 const char* usfft_last_error(void);
@@ -428,12 +430,17 @@ usfft_status usfft_family(const int32_t* J_dev, int64_t n, int32_t t, double c, 
  * and non-blocking HIP stream, so the kernels of different jobs overlap on the
  * device.  Jobs are admitted in arrival order as soon as a slot is free and
  * their estimated device footprint fits in hbm_budget bytes next to the
- * running jobs (the estimate, from G, s, the box and the precision, bounds the
- * sample matrix and candidate magnitudes of the largest stage).  A job's plan
- * and workspaces are released when it finishes; its result stays with the
- * server until taken by usfft_server_poll.  Each job's result is the same as
- * running it alone (all per-sample and per-node arithmetic is independent of
- * what else runs). */
+ * running jobs and the idle plans (the estimate, from G, s, the box and the
+ * precision, bounds the sample matrix and candidate magnitudes of the largest
+ * stage).  A finished job's plan, with its tables and workspaces, stays in a
+ * pool (at most 2 max_active idle plans; the oldest are freed first when an
+ * admission needs their memory) and serves the next job of the same sampler,
+ * coefficient family, mesh, node set, precision and solver parameters; the
+ * box, s, s_local, r, theta and the lattice-planner parameters are set per
+ * job.  A job's result stays with the server until taken by
+ * usfft_server_poll.  Each job's result is the same as running it alone on a
+ * new plan (all per-sample and per-node arithmetic is independent of what
+ * else runs, and every workspace is rewritten before it is read). */
 typedef struct {
   int32_t max_active;   /* concurrent jobs (>= 1)                            */
   uint64_t hbm_budget;  /* bytes the running jobs may occupy (0 = no limit)  */

@@ -62,7 +62,7 @@ class Stats(C.Structure):
                 ("theta_abs", C.c_double), ("ms_sample", C.c_double),
                 ("ms_dft", C.c_double), ("ms_select", C.c_double), ("ms_total", C.c_double),
                 ("dft_bytes", C.c_double), ("max_batch", C.c_int64), ("max_family", C.c_int64),
-                ("workspace_bytes", C.c_int64)]
+                ("workspace_bytes", C.c_int64), ("plan_reused", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1926,6 +1926,80 @@ static uint64_t estimate_footprint(const usfft_problem* pb, const usfft_params* 
   return G * samples * ub + G * J * 8 + lines + samples * (uint64_t)pb->d * 8 + (64ull << 20);
 }
 
+// Plans are pooled by everything that fixes their device tables: the
+// sampler and its coefficient family, mesh and node set, and the parameters
+// read at plan creation.  The box, the sparsity parameters, the threshold
+// and the lattice-planner and solver knobs that detect() reads per call are
+// rebound for every job.
+static std::string plan_key(const usfft_problem* pb, const usfft_params* pa) {
+  std::string k;
+  auto put = [&k](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+  auto put_i = [&](int64_t v) { put(&v, sizeof v); };
+  auto put_d = [&](double v) { put(&v, sizeof v); };
+  put_i(pb->sampler);
+  put_i(pb->d);
+  put_i(pb->n_nodes);
+  if (pb->n_nodes > 0) put(pb->nodes_xy, sizeof(double) * 2 * (size_t)pb->n_nodes);
+  if (pb->sampler == USFFT_SAMPLER_TRIG_POLY) {
+    put_i(pb->G_poly);
+    put_i(pb->n_poly);
+    put(pb->poly_k, sizeof(int32_t) * (size_t)pb->n_poly * pb->d);
+    put(pb->poly_c, sizeof(double) * 2 * (size_t)pb->n_poly * pb->G_poly);
+  } else {
+    put_i(pb->mesh_n);
+    put_d(pb->a0);
+    put(pb->amp, sizeof(double) * pb->d);
+    put(pb->mode1, sizeof(int32_t) * pb->d);
+    put(pb->mode2, sizeof(int32_t) * pb->d);
+    put_i(pb->model);
+    put_d(pb->alpha);
+    put_d(pb->beta);
+    put_d(pb->delta);
+    put_i(pb->basis1);
+    put_i(pb->basis2);
+    if (pb->sampler == USFFT_SAMPLER_PDE_MESH) {
+      put_i(pb->mesh_nv);
+      put_i(pb->mesh_nt);
+      put(pb->mesh_xy, sizeof(double) * 2 * (size_t)pb->mesh_nv);
+      put(pb->mesh_tri, sizeof(int32_t) * 3 * (size_t)pb->mesh_nt);
+      put(pb->mesh_boundary, (size_t)pb->mesh_nv);
+    }
+  }
+  put_i(pa->precision);
+  put_i(pa->lattice_mmax);
+  put_i(pa->solver_config);
+  put_i(pa->precond);
+  put_d(pa->pcg_rtol);
+  put_i(pa->pcg_maxit);
+  put_d(pa->inner_rtol);
+  put_i(pa->refine_every);
+  return k;
+}
+
+// A pooled plan takes a new job's box and per-call parameters.
+static void plan_rebind(usfft_plan_s* P, const usfft_problem* pb, const usfft_params* pa) {
+  P->par = *pa;
+  P->k_lo.assign(pb->k_lo, pb->k_lo + pb->d);
+  P->k_hi.assign(pb->k_hi, pb->k_hi + pb->d);
+  P->prob.k_lo = P->k_lo.data();
+  P->prob.k_hi = P->k_hi.data();
+}
+
+// Device bytes a plan holds (static tables, lattice tables, workspaces).
+static uint64_t plan_bytes(const usfft_plan_s* P) {
+  uint64_t b = 0;
+  for (const DevBuf* x : {&P->d_amp, &P->d_tab, &P->d_polyk, &P->d_polyc, &P->d_stream, &P->d_wscr, &P->d_sfrag,
+                          &P->d_lam, &P->m_rowptr, &P->m_col, &P->m_diag, &P->m_cptr, &P->m_ctri, &P->m_cw, &P->m_load,
+                          &P->m_psi, &P->d_iidx, &P->d_iw, &P->Umesh, &P->d_rader, &P->famlog, &P->famstate, &P->Y,
+                          &P->U, &P->V, &P->iters, &P->cnt, &P->theta2, &P->scratch, &P->J, &P->Jnext, &P->Iprev,
+                          &P->mask, &P->gmask, &P->cands, &P->assign, &P->bins, &P->famz, &P->fambins, &P->famcounts,
+                          &P->famcov, &P->famscores, &P->lists, &P->latM, &P->latz, &P->latoff, &P->tail,
+                          &P->latitems})
+    b += x->bytes;
+  for (const DevBuf& x : P->I1) b += x.bytes;
+  return b;
+}
+
 struct Job {
   uint64_t id = 0;
   JobSpec spec;
@@ -1951,9 +2025,31 @@ struct usfft_server_s {
   int active = 0;
   bool stop = false;
   std::vector<std::thread> workers;
+  // idle plans by key, oldest first; their device bytes count against the
+  // budget and are released (oldest first) when an admission needs them
+  struct Pooled {
+    std::string key;
+    std::unique_ptr<usfft_plan_s> plan;
+    uint64_t bytes;
+  };
+  std::deque<Pooled> pool;
+  uint64_t pooled_bytes = 0;
+  int64_t plans_created = 0, plans_reused = 0;
+  ~usfft_server_s() {
+    pool.clear();
+  }
 };
 
 namespace usfft {
+
+// Frees pooled plans, oldest first, until `need` more bytes fit the budget
+// (called with the server lock held).
+static void pool_make_room(usfft_server_s* S, uint64_t need) {
+  while (!S->pool.empty() && S->cfg.hbm_budget > 0 && S->in_use + S->pooled_bytes + need > S->cfg.hbm_budget) {
+    S->pooled_bytes -= S->pool.front().bytes;
+    S->pool.pop_front();
+  }
+}
 
 static void server_worker(usfft_server_s* S) {
   hipStream_t st = nullptr;
@@ -1964,7 +2060,8 @@ static void server_worker(usfft_server_s* S) {
       if (S->stop && S->queue.empty()) return true;
       if (S->queue.empty() || S->active >= S->cfg.max_active) return false;
       const uint64_t fp = S->queue.front()->footprint;
-      return S->cfg.hbm_budget == 0 || S->active == 0 || S->in_use + fp <= S->cfg.hbm_budget;
+      pool_make_room(S, fp);
+      return S->cfg.hbm_budget == 0 || S->active == 0 || S->in_use + S->pooled_bytes + fp <= S->cfg.hbm_budget;
     });
     if (S->queue.empty()) break;
     Job* J = S->queue.front();
@@ -1973,23 +2070,49 @@ static void server_worker(usfft_server_s* S) {
     S->in_use += J->footprint;
     J->state = 1;
     J->t_start = std::chrono::steady_clock::now();
+    // an idle plan of the same key, if any (the most recently returned)
+    const std::string key = plan_key(&J->spec.prob, &J->spec.par);
+    std::unique_ptr<usfft_plan_s> P;
+    for (auto it = S->pool.rbegin(); it != S->pool.rend(); ++it)
+      if (it->key == key) {
+        P = std::move(it->plan);
+        S->pooled_bytes -= it->bytes;
+        S->pool.erase(std::next(it).base());
+        break;
+      }
+    const bool reused = P != nullptr;
+    if (reused) S->plans_reused++; else S->plans_created++;
     lk.unlock();
     usfft_status status = USFFT_OK;
     std::string err;
     std::unique_ptr<usfft_result_s> R(new usfft_result_s());
     try {
       USFFT_REQUIRE(st != nullptr, USFFT_EHIP, "worker stream creation failed");
-      std::unique_ptr<usfft_plan_s> P(plan_create(&J->spec.prob, &J->spec.par));
+      if (!P) P.reset(plan_create(&J->spec.prob, &J->spec.par));
+      plan_rebind(P.get(), &J->spec.prob, &J->spec.par);
       std::lock_guard<std::mutex> pl(P->mu);
       detect(P.get(), J->seed, st, R.get());
+      R->stats.plan_reused = reused ? 1 : 0;
     } catch (const Error& e) {
       status = e.st;
       err = e.msg;
+      P.reset();  // a failed job's plan is not pooled
     } catch (const std::exception& e) {
       status = USFFT_EINVAL;
       err = e.what();
+      P.reset();
     }
     lk.lock();
+    if (P) {
+      // keep at most 2 max_active idle plans
+      const uint64_t b = plan_bytes(P.get());
+      S->pool.push_back({key, std::move(P), b});
+      S->pooled_bytes += b;
+      while ((int)S->pool.size() > 2 * S->cfg.max_active) {
+        S->pooled_bytes -= S->pool.front().bytes;
+        S->pool.pop_front();
+      }
+    }
     J->st = status;
     J->err = err;
     J->res = status == USFFT_OK ? R.release() : nullptr;

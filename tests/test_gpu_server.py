@@ -69,3 +69,27 @@ def test_server_reports_job_errors(lib):
     res, st, *_ = srv.poll(good, wait=True)
     assert st == lib.OK and res.n > 0
     srv.close()
+
+
+def test_server_reuses_plans(lib):
+    """Jobs that share the sampler, coefficient family, mesh and precision run
+    on a pooled plan of an earlier job, with their own box, s, r and
+    threshold, and still equal the job run alone on a new plan."""
+    base = W.pde_problem(16, 4, 12, modes="diagonal")
+    specs = [(dict(base, k_lo=[-N] * 4, k_hi=[N] * 4), dict(W.params(s, r, th), precision=1), seed)
+             for N, s, r, th, seed in [(12, 30, 2, 1e-4, 11), (8, 20, 3, 1e-3, 12), (16, 40, 2, 1e-4, 13),
+                                       (12, 30, 2, 1e-4, 14)]]
+    alone = []
+    for prob, par, seed in specs:
+        r = lib.detect(lib.Plan(prob, par), seed)
+        alone.append((r.freqs(), r.coeffs()))
+    srv = lib.Server(max_active=1)
+    reused = []
+    for (prob, par, seed), (I, C) in zip(specs, alone):
+        res, st, lat, q, err = srv.poll(srv.submit(prob, par, seed), wait=True)
+        assert st == lib.OK, err
+        assert np.array_equal(res.freqs(), I)
+        assert np.array_equal(res.coeffs(), C)
+        reused.append(res.stats["plan_reused"])
+    srv.close()
+    assert reused == [0, 1, 1, 1]
