@@ -355,6 +355,10 @@ def main():
                     help="also time one job on an unstructured mesh shaped like the paper's (0 = skip)")
     ap.add_argument("--parity", type=int, default=1,
                     help="compare the seed-1 job of both precisions with the stored oracle outputs (0 = skip)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="use the committed tuning cache and time missing kernel choices (0 = built-in choices)")
+    ap.add_argument("--tune-out", default="",
+                    help="write the tuning cache (JSON) to this path at the end")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof byte counters)")
     args = ap.parse_args()
@@ -376,6 +380,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     prob, par = W.WORKLOADS[args.workload]
+    # kernel choices: the committed tuning cache of this GPU, completed by
+    # timing whatever it lacks (autotune); the parity block runs the same
+    tune_file = os.path.join(ROOT, "paper_2109_04131_amd", "tune", "mi355x.json")
+    if args.autotune and os.path.exists(tune_file):
+        U.tune_load(tune_file)
+    par = dict(par, autotune=args.autotune)
     plan32 = U.Plan(prob, dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12, solver_config=args.solver_config))
     wall32, lat32, st32, nI = run_path(U, plan32, args.seed, args.steps, args.warmup)
     out = {}
@@ -490,6 +500,8 @@ def main():
         res["parity"] = parity_block(U, prob, par, args.seed, [("fp32_refine", U.FP32_REFINE), ("fp64", U.FP64)])
     if args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    if args.tune_out:
+        U.tune_save(args.tune_out)
     print(json.dumps(res))
 
 

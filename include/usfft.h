@@ -163,6 +163,15 @@ typedef struct {
   int32_t trace;           /* nonzero: usfft_detect keeps the detected sets of
                               every increment (usfft_result_trace); costs one
                               small readback per increment                  */
+  int32_t autotune;        /* nonzero: time the candidates of every kernel
+                              choice not yet in the tuning cache (the DST
+                              solver's scratch variant at plan creation when
+                              solver_config < 0, the lattice-DFT workgroup
+                              shape per transform length on first use) and
+                              keep the fastest; 0: cached or built-in
+                              choices.  Choices change only rounding (bin 0
+                              of a transform, the solver's arithmetic within
+                              pcg_rtol); a saved cache makes them repeatable */
 } usfft_params;
 
 /* Statistics of one usfft_detect run. */
@@ -198,6 +207,18 @@ typedef struct {
 
 const char* usfft_last_error(void);
 const char* usfft_version(void);
+
+/* Tuning cache (process-wide; see usfft_params.autotune): usfft_tune_save
+ * writes it as JSON ({"version": 1, "entries": [{"key", "a", "b",
+ * "time_ms"}, ...]}), usfft_tune_load merges such a file into it (entries of
+ * the file win), usfft_tune_clear empties it.  Keys name the choice and its
+ * shape: "jacobi n= d= prec=" (a = Jacobi solver shape), "dst n= d= prec=
+ * model=" (a = DST solver scratch variant), "rader L= fp32= G=" (a =
+ * workgroup size, b = node pairs per workgroup of the lattice DFT).
+ * Errors: EINVAL (unreadable or malformed file). */
+usfft_status usfft_tune_save(const char* path);
+usfft_status usfft_tune_load(const char* path);
+usfft_status usfft_tune_clear(void);
 
 /* Plan: validate and copy the problem, upload static tables (coefficient
  * tables of eq. (1.2) at triangle centroids, polynomial coefficients), size

@@ -51,7 +51,7 @@ class _Params(C.Structure):
                 ("lattice_c", C.c_double), ("lattice_tries", C.c_int32), ("lattice_max", C.c_int32),
                 ("lattice_mmax", C.c_int32), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32),
                 ("inner_rtol", C.c_double), ("refine_every", C.c_int32), ("solver_config", C.c_int32),
-                ("precond", C.c_int32), ("trace", C.c_int32)]
+                ("precond", C.c_int32), ("trace", C.c_int32), ("autotune", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -74,6 +74,9 @@ _sigs = {
     "usfft_version": (C.c_char_p, []),
     "usfft_plan_create": (C.c_int, [C.POINTER(_Problem), C.POINTER(_Params), C.POINTER(_vp)]),
     "usfft_plan_destroy": (None, [_vp]),
+    "usfft_tune_save": (C.c_int, [C.c_char_p]),
+    "usfft_tune_load": (C.c_int, [C.c_char_p]),
+    "usfft_tune_clear": (C.c_int, []),
     "usfft_plan_nodes": (C.c_int64, [_vp]),
     "usfft_detect": (C.c_int, [_vp, C.c_uint64, _vp, C.POINTER(_vp)]),
     "usfft_plan_workspace": (C.c_int, [_vp, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
@@ -160,7 +163,7 @@ def version():
 DEFAULT_PARAMS = dict(s=50, s_local=50, r=5, theta=1e-12, theta_relative=False, tie_rel=2.0 ** -30,
                       precision=FP64, lattice_c=2.0, lattice_tries=8, lattice_max=64, lattice_mmax=9601,
                       pcg_rtol=1e-12, pcg_maxit=4000, inner_rtol=2e-4, refine_every=200, solver_config=-1,
-                      precond=0, trace=False)
+                      precond=0, trace=False, autotune=False)
 
 
 def _marshal(problem, params):
@@ -327,6 +330,20 @@ class Result:
 
     def __del__(self):
         self.close()
+
+
+def tune_save(path):
+    """usfft_tune_save: the tuning cache as JSON."""
+    _check(_lib.usfft_tune_save(os.fsencode(path)))
+
+
+def tune_load(path):
+    """usfft_tune_load: merge a saved tuning cache."""
+    _check(_lib.usfft_tune_load(os.fsencode(path)))
+
+
+def tune_clear():
+    _check(_lib.usfft_tune_clear())
 
 
 def plan_create(problem, params):

@@ -624,13 +624,25 @@ void fill_lat_item(LatItem& it, const RaderTables& T, int u_fp32) {
   it.B = u_fp32 ? T.B32 : T.B64;
 }
 
+bool rader_shape_ok(int Lmax, int u_fp32, int block, int cols) {
+  if (!(block == 128 || block == 256 || block == 512) || !(cols == 1 || cols == 2 || cols == 4)) return false;
+  const size_t colbytes = (size_t)Lmax * (u_fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>));
+  return colbytes * (size_t)cols <= (150u << 10);
+}
+
 void launch_lattice_dft_batch(const LatItem* items, int nitems, int Lmax, const void* u, int u_fp32, int64_t G,
-                              int64_t ld, int out_kind, void* out, int64_t ldo, hipStream_t st) {
+                              int64_t ld, int out_kind, void* out, int64_t ldo, hipStream_t st, int shape_block,
+                              int shape_cols) {
   if (G <= 0 || nitems <= 0) return;
   USFFT_REQUIRE(Lmax >= 2 && Lmax < lattice_mmax_for(u_fp32), USFFT_EINVAL, "lattice transform length out of range");
   int block = 0, cols = 0;
   size_t lds = 0;
   rader_shape(Lmax, u_fp32, &block, &cols, &lds);
+  if (shape_block > 0 && rader_shape_ok(Lmax, u_fp32, shape_block, shape_cols)) {
+    block = shape_block;
+    cols = shape_cols;
+    lds = (size_t)Lmax * (u_fp32 ? sizeof(cplx<float>) : sizeof(cplx<double>)) * (size_t)cols;
+  }
   const int64_t wpi = ceil_div(G, 2 * cols);
   const unsigned grid = (unsigned)(wpi * nitems);
 #define USFFT_RB(TT, BB, CC) \

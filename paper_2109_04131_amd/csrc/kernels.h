@@ -145,8 +145,12 @@ void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t
 void fill_lat_item(LatItem& it, const RaderTables& T, int u_fp32);  // F, M and the table pointers
 // Every item of items_dev (device array) in one launch; Lmax = the largest
 // transform length L = M - 1 among them.
+// shape_block / shape_cols > 0 choose the workgroup size (128, 256, 512) and
+// node pairs per workgroup (1, 2, 4) instead of the built-in rule
 void launch_lattice_dft_batch(const LatItem* items_dev, int nitems, int Lmax, const void* u, int u_fp32, int64_t G,
-                              int64_t ld, int out_kind, void* out, int64_t ldo, hipStream_t st);
+                              int64_t ld, int out_kind, void* out, int64_t ldo, hipStream_t st, int shape_block = 0,
+                              int shape_cols = 0);
+bool rader_shape_ok(int Lmax, int u_fp32, int block, int cols);
 // mask_out bit pos[q] |= mask_in bit q, q < n (grouped order back to candidate order).
 void launch_ungroup_mask(const uint32_t* mask_in, const int32_t* pos, int64_t n, uint32_t* mask_out, hipStream_t st);
 // all d r step-1 lines at once: line y (coordinate t = y / line_r) from column

@@ -11,6 +11,9 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <fstream>
+#include <functional>
+#include <sstream>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -465,6 +468,9 @@ struct Timer {
 };
 enum { kTSample = 0, kTDft = 1, kTSelect = 2 };
 
+static std::pair<int, int> rader_tuned_shape(usfft_plan_s* P, int Lmax, int ufp32, int64_t G,
+                                             const std::function<void(int, int)>& launch, hipStream_t st);
+
 // ---------------------------------------------------------------- Alg. 1
 // given: step 3 alone on the set given_I (host, given_n x d)
 static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_s* R, bool given = false,
@@ -700,9 +706,13 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
             S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 8.0;
           }
         h2d_async(P, P->latitems, items, st);
+        auto dft = [&](int blk, int cols) {
+          launch_lattice_dft_batch(P->latitems.as<LatItem>(), (int)items.size(), Lmax, P->U.p, ufp32, G, ldb,
+                                   USFFT_OUT_MAG2, P->V.p, (int64_t)nb * n, st, blk, cols);
+        };
+        const std::pair<int, int> shape = rader_tuned_shape(P, Lmax, ufp32, G, dft, st);
         int e = tm.open(kTDft);
-        launch_lattice_dft_batch(P->latitems.as<LatItem>(), (int)items.size(), Lmax, P->U.p, ufp32, G, ldb,
-                                 USFFT_OUT_MAG2, P->V.p, (int64_t)nb * n, st);
+        dft(shape.first, shape.second);
         tm.close(kTDft, e);
         S.dft_launches += 1;
         e = tm.open(kTSelect);
@@ -786,9 +796,13 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       S.dft_bytes += (double)G * (double)F.M[l] * (double)ub + (double)G * F.lat_count[l] * 16.0;
     }
     h2d_async(P, P->latitems, items, st);
+    auto dft = [&](int blk, int cols) {
+      launch_lattice_dft_batch(P->latitems.as<LatItem>(), (int)items.size(), Lmax, P->U.p, ufp32, G, ld,
+                               USFFT_OUT_COMPLEX, R->C.p, G, st, blk, cols);
+    };
+    const std::pair<int, int> shape = rader_tuned_shape(P, Lmax, ufp32, G, dft, st);
     int e = tm.open(kTDft);
-    launch_lattice_dft_batch(P->latitems.as<LatItem>(), (int)items.size(), Lmax, P->U.p, ufp32, G, ld,
-                             USFFT_OUT_COMPLEX, R->C.p, G, st);
+    dft(shape.first, shape.second);
     tm.close(kTDft, e);
     S.dft_launches += 1;
     check_conv();
@@ -928,56 +942,155 @@ static void detect_ws(usfft_plan_s* P, uint64_t seed, int64_t ncand, int64_t nsa
 }
 
 // ---------------------------------------------------------------- autotune
+// One process-wide tuning cache, persisted as JSON by usfft_tune_save and
+// read back by usfft_tune_load:
+//   {"version": 1, "entries": [{"key": "...", "a": A, "b": B, "time_ms": T}, ...]}
+// Keys: "jacobi n=.. d=.. prec=.." (a = solver shape), "dst n=.. d=.. prec=..
+// model=.." (a = scratch variant), "rader L=.. fp32=.. G=.." (a = workgroup
+// size, b = node pairs per workgroup).  Entries are filled on first use by
+// timing every candidate on the device; a loaded entry is used as is.
+struct TuneEntry {
+  int a = 0, b = 0;
+  double time_ms = 0.0;
+};
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int>, int> g_tune_cache;
+static std::map<std::string, TuneEntry> g_tune;
 
-static int autotune_solver(usfft_plan_s* P) {
-  const int n = P->prob.mesh_n, d = P->prob.d, prec = P->par.precision;
-  const auto key = std::make_tuple(n, d, prec);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) return it->second;
-  }
-  const int64_t G = P->G;
-  const int64_t ns = 1024;
-  hipStream_t st = nullptr;
-  DevBuf Y, U, it;
-  Y.ensure(sizeof(double) * ns * d);
-  U.ensure(sizeof(double) * G * ns);
-  it.ensure(sizeof(int32_t) * ns);
-  std::vector<double> yh((size_t)ns * d);
-  for (int64_t e = 0; e < ns * d; ++e) yh[e] = rng::uniform01(12345, 77, e);
-  USFFT_HIP(hipMemcpy(Y.p, yh.data(), sizeof(double) * yh.size(), hipMemcpyHostToDevice));
+static bool tune_get(const std::string& key, TuneEntry* e) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *e = it->second;
+  return true;
+}
+static void tune_put(const std::string& key, const TuneEntry& e) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = e;
+}
+
+// Device time of f() on st (ms), after one untimed call.
+template <typename F>
+static float time_on(hipStream_t st, F&& f) {
   hipEvent_t a, b;
   USFFT_HIP(hipEventCreate(&a));
   USFFT_HIP(hipEventCreate(&b));
-  int best = solver_default_config(n);
-  float best_ms = 1e30f;
-  DevBuf scr;
+  float ms = 0;
+  try {
+    f();
+    USFFT_HIP(hipEventRecord(a, st));
+    f();
+    USFFT_HIP(hipEventRecord(b, st));
+    USFFT_HIP(hipEventSynchronize(b));
+    USFFT_HIP(hipEventElapsedTime(&ms, a, b));
+  } catch (...) {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    throw;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms;
+}
+
+// Seeded sampling nodes for tuning runs (ns x d, uniform on [0,1)).
+static void tune_nodes(DevBuf& Y, int64_t ns, int d) {
+  std::vector<double> yh((size_t)ns * d);
+  for (int64_t e = 0; e < ns * d; ++e) yh[e] = rng::uniform01(12345, 77, e);
+  Y.ensure(sizeof(double) * yh.size());
+  USFFT_HIP(hipMemcpy(Y.p, yh.data(), sizeof(double) * yh.size(), hipMemcpyHostToDevice));
+}
+
+static int autotune_solver(usfft_plan_s* P) {
+  const int n = P->prob.mesh_n, d = P->prob.d, prec = P->par.precision;
+  const std::string key =
+      "jacobi n=" + std::to_string(n) + " d=" + std::to_string(d) + " prec=" + std::to_string(prec);
+  TuneEntry e;
+  if (tune_get(key, &e)) return e.a;
+  const int64_t G = P->G;
+  const int64_t ns = 1024;
+  hipStream_t st = nullptr;
+  DevBuf Y, U, it, scr;
+  tune_nodes(Y, ns, d);
+  U.ensure(sizeof(double) * G * ns);
+  it.ensure(sizeof(int32_t) * ns);
+  e.a = solver_default_config(n);
+  e.time_ms = 1e30;
   for (int c = 0; c < solver_config_count(); ++c) {
     if (!solver_config_fits(c, n)) continue;
     const int wb = persistent_blocks(c, n);
     scr.ensure(sizeof(double) * (size_t)edge_scratch_doubles(n, wb));
-    launch_pde_solve(c, P->pde, prec, Y.as<double>(), 64, P->par.pcg_rtol, P->par.pcg_maxit, P->par.inner_rtol,
-                     P->par.refine_every, U.p, 0, ns, 0, it.as<int32_t>(), scr.as<double>(), wb, st);
-    USFFT_HIP(hipEventRecord(a, st));
-    launch_pde_solve(c, P->pde, prec, Y.as<double>(), ns, P->par.pcg_rtol, P->par.pcg_maxit, P->par.inner_rtol,
-                     P->par.refine_every, U.p, 0, ns, 0, it.as<int32_t>(), scr.as<double>(), wb, st);
-    USFFT_HIP(hipEventRecord(b, st));
-    USFFT_HIP(hipEventSynchronize(b));
-    float ms = 0;
-    USFFT_HIP(hipEventElapsedTime(&ms, a, b));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = c;
+    const float ms = time_on(st, [&] {
+      launch_pde_solve(c, P->pde, prec, Y.as<double>(), ns, P->par.pcg_rtol, P->par.pcg_maxit, P->par.inner_rtol,
+                       P->par.refine_every, U.p, 0, ns, 0, it.as<int32_t>(), scr.as<double>(), wb, st);
+    });
+    if (ms < e.time_ms) {
+      e.time_ms = ms;
+      e.a = c;
     }
   }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = best;
-  return best;
+  tune_put(key, e);
+  return e.a;
+}
+
+// Scratch variant of the DST-preconditioned solver (0 global scratch, 1
+// LDS-resident, 2 compact float32), timed on 2048 seeded solves.
+static int autotune_dst_variant(usfft_plan_s* P, int fallback) {
+  const int n = P->prob.mesh_n, d = P->prob.d, prec = P->par.precision;
+  const std::string key = "dst n=" + std::to_string(n) + " d=" + std::to_string(d) + " prec=" +
+                          std::to_string(prec) + " model=" + std::to_string(P->prob.model);
+  TuneEntry e;
+  if (tune_get(key, &e) && e.a >= 0 && e.a <= (prec == USFFT_FP32_REFINE ? 2 : 1)) return e.a;
+  if (!P->par.autotune) return fallback;
+  const int64_t ns = 2048, G = (int64_t)(n - 1) * (n - 1);
+  hipStream_t st = nullptr;
+  DevBuf Y, U, it, scr;
+  tune_nodes(Y, ns, d);
+  const int ufp32 = prec == USFFT_FP32_REFINE ? 1 : 0;
+  U.ensure((ufp32 ? sizeof(float) : sizeof(double)) * G * ns);
+  it.ensure(sizeof(int32_t) * ns);
+  e.a = fallback;
+  e.time_ms = 1e30;
+  for (int v = 0; v <= (ufp32 ? 2 : 1); ++v) {
+    const int wb = dst_persistent_blocks(n, prec, v);
+    scr.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, dst_scratch_doubles(n, v, wb)));
+    const float ms = time_on(st, [&] {
+      launch_pde_solve_dst(P->pde, prec, v, Y.as<double>(), ns, P->par.pcg_rtol, P->par.pcg_maxit,
+                           P->par.inner_rtol, P->par.refine_every, U.p, ufp32, ns, 0, it.as<int32_t>(),
+                           scr.as<double>(), wb, P->d_sfrag.p, P->d_lam.as<float>(), st);
+    });
+    if (ms < e.time_ms) {
+      e.time_ms = ms;
+      e.a = v;
+    }
+  }
+  tune_put(key, e);
+  return e.a;
+}
+
+// Workgroup shape of a batched lattice DFT whose longest transform is Lmax:
+// the cached one, else (autotune on) every admissible (block, cols) timed on
+// the launch itself (the transforms only read the samples, so repeating them
+// leaves the same output), else the built-in rule (0, 0).
+static std::pair<int, int> rader_tuned_shape(usfft_plan_s* P, int Lmax, int ufp32, int64_t G,
+                                             const std::function<void(int, int)>& launch, hipStream_t st) {
+  const std::string key = "rader L=" + std::to_string(Lmax) + " fp32=" + std::to_string(ufp32) + " G=" +
+                          std::to_string(G);
+  TuneEntry e;
+  if (tune_get(key, &e) && rader_shape_ok(Lmax, ufp32, e.a, e.b)) return {e.a, e.b};
+  if (!P->par.autotune) return {0, 0};
+  e.time_ms = 1e30;
+  for (int blk : {128, 256, 512})
+    for (int cols : {1, 2, 4}) {
+      if (!rader_shape_ok(Lmax, ufp32, blk, cols)) continue;
+      const float ms = time_on(st, [&] { launch(blk, cols); });
+      if (ms < e.time_ms) {
+        e.time_ms = ms;
+        e.a = blk;
+        e.b = cols;
+      }
+    }
+  tune_put(key, e);
+  return {e.a, e.b};
 }
 
 // ---------------------------------------------------------------- plan
@@ -1327,6 +1440,7 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
       USFFT_REQUIRE(!(par->solver_config == 2 && par->precision == USFFT_FP64), USFFT_EINVAL,
                     "solver_config 2 of the DST solver is float32-only");
       P->dst_variant = par->solver_config >= 0 ? par->solver_config : (par->precision == USFFT_FP64 ? 1 : 2);
+      if (par->solver_config < 0) P->dst_variant = autotune_dst_variant(P.get(), P->dst_variant);
       P->wblocks = dst_persistent_blocks(n, par->precision, P->dst_variant);
       P->d_wscr.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, dst_scratch_doubles(n, P->dst_variant,
                                                                                          P->wblocks)));
@@ -1445,6 +1559,71 @@ usfft_status usfft_coefficients(usfft_plan_t plan, const int32_t* freqs_host, in
     std::unique_ptr<usfft_result_s> R(new usfft_result_s());
     detect(plan, seed, (hipStream_t)stream, R.get(), true, freqs_host, n);
     *out = R.release();
+  });
+}
+
+usfft_status usfft_tune_save(const char* path) {
+  return guarded([&] {
+    USFFT_REQUIRE(path, USFFT_EINVAL, "null path");
+    std::ostringstream o;
+    o.precision(9);
+    o << "{\"version\": 1, \"entries\": [";
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      bool first = true;
+      for (const auto& kv : g_tune) {
+        o << (first ? "\n  " : ",\n  ") << "{\"key\": \"" << kv.first << "\", \"a\": " << kv.second.a
+          << ", \"b\": " << kv.second.b << ", \"time_ms\": " << kv.second.time_ms << "}";
+        first = false;
+      }
+    }
+    o << "\n]}\n";
+    std::ofstream f(path);
+    USFFT_REQUIRE(f.good(), USFFT_EINVAL, std::string("cannot write ") + path);
+    f << o.str();
+  });
+}
+
+usfft_status usfft_tune_load(const char* path) {
+  return guarded([&] {
+    USFFT_REQUIRE(path, USFFT_EINVAL, "null path");
+    std::ifstream f(path);
+    USFFT_REQUIRE(f.good(), USFFT_EINVAL, std::string("cannot read ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    // every {...} object that holds a "key": its string and the numbers of
+    // "a", "b" and "time_ms" (the file usfft_tune_save writes)
+    auto num = [&](const std::string& obj, const char* name, double dflt) {
+      const std::string pat = std::string("\"") + name + "\":";
+      const size_t p = obj.find(pat);
+      if (p == std::string::npos) return dflt;
+      return std::strtod(obj.c_str() + p + pat.size(), nullptr);
+    };
+    std::map<std::string, TuneEntry> got;
+    for (size_t p = t.find('{', 1); p != std::string::npos; p = t.find('{', p + 1)) {
+      const size_t q = t.find('}', p);
+      USFFT_REQUIRE(q != std::string::npos, USFFT_EINVAL, "malformed tuning file");
+      const std::string obj = t.substr(p, q - p + 1);
+      const size_t k = obj.find("\"key\":");
+      if (k == std::string::npos) continue;
+      const size_t k0 = obj.find('"', k + 6), k1 = obj.find('"', k0 + 1);
+      USFFT_REQUIRE(k0 != std::string::npos && k1 != std::string::npos, USFFT_EINVAL, "malformed tuning key");
+      TuneEntry e;
+      e.a = (int)num(obj, "a", 0);
+      e.b = (int)num(obj, "b", 0);
+      e.time_ms = num(obj, "time_ms", 0);
+      got[obj.substr(k0 + 1, k1 - k0 - 1)] = e;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : got) g_tune[kv.first] = kv.second;
+  });
+}
+
+usfft_status usfft_tune_clear(void) {
+  return guarded([&] {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
   });
 }
 

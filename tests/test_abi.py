@@ -53,3 +53,29 @@ def test_binding_shares_torchs_hip_runtime(built):
             "print(len(m))\n")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, check=True).stdout
     assert out.strip() == "1"
+
+
+def test_tuning_cache_json_round_trip(built, tmp_path):
+    """usfft_tune_load / usfft_tune_save (host only): the JSON format keeps
+    every entry's key and numbers; loading merges, the file's entries win."""
+    import json
+
+    import paper_2109_04131_amd as U
+    src = tmp_path / "in.json"
+    src.write_text(json.dumps({"version": 1, "entries": [
+        {"key": "rader L=2592 fp32=1 G=3969", "a": 256, "b": 1, "time_ms": 0.081},
+        {"key": "dst n=64 d=10 prec=1 model=0", "a": 2, "b": 0, "time_ms": 2.5}]}))
+    U.tune_clear()
+    U.tune_load(str(src))
+    U.tune_load(str(src))  # merging the same entries again changes nothing
+    out = tmp_path / "out.json"
+    U.tune_save(str(out))
+    got = {e["key"]: e for e in json.loads(out.read_text())["entries"]}
+    assert set(got) == {"rader L=2592 fp32=1 G=3969", "dst n=64 d=10 prec=1 model=0"}
+    assert (got["rader L=2592 fp32=1 G=3969"]["a"], got["rader L=2592 fp32=1 G=3969"]["b"]) == (256, 1)
+    assert got["dst n=64 d=10 prec=1 model=0"]["a"] == 2
+    U.tune_clear()
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": [{"key": "x", "a": 1')
+    with pytest.raises(U.UsfftError):
+        U.tune_load(str(bad))

@@ -72,15 +72,19 @@ def compare_trace(fx, tr, d, k_lo):
     return flips
 
 
-@pytest.mark.parametrize("name", ["mesh16_d10", "mesh64_d10"])
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp32_refine"])
-def test_whole_job_against_oracle(lib, name, prec):
+@pytest.mark.parametrize("name,prec,autotune", [("mesh16_d10", 0, 0), ("mesh16_d10", 1, 0), ("mesh64_d10", 0, 0),
+                                                ("mesh64_d10", 1, 0), ("mesh64_d10", 1, 1)])
+def test_whole_job_against_oracle(lib, name, prec, autotune):
     fx = fixture(name)
     prob, par = W.WORKLOADS[name]
     d = prob["d"]
-    print("whole job %s precision %d seed %d" % (name, prec, SEED), flush=True)
-    plan = lib.Plan(prob, dict(par, precision=prec, pcg_rtol=1e-12, trace=True))
-    res = lib.detect(plan, SEED)
+    print("whole job %s precision %d autotune %d seed %d" % (name, prec, autotune, SEED), flush=True)
+    plan = lib.Plan(prob, dict(par, precision=prec, pcg_rtol=1e-12, trace=True, autotune=autotune))
+    try:
+        res = lib.detect(plan, SEED)
+    finally:
+        if autotune:
+            lib.tune_clear()  # later tests keep the built-in choices
     flips = compare_trace(fx, res.trace(), d, prob["k_lo"])
     for f in flips:
         print("flip at %s: k = %s, oracle keep ratio %.6f, kept by the oracle: %s" % f)
