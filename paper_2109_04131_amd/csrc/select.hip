@@ -52,7 +52,22 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
   const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
   const uint64_t* gkeys = reinterpret_cast<const uint64_t*>(v + g * ld);
   if (STAGE) {
-    for (int64_t a = threadIdx.x; a < n; a += kSelBlock) stage[a] = gkeys[a];
+    // eight loads in flight per thread before their LDS stores: the column
+    // comes from HBM, and one load at a time would wait out its latency
+    constexpr int U = 8;
+    for (int64_t a0 = threadIdx.x; a0 < n; a0 += U * kSelBlock) {
+      uint64_t k[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t a = a0 + u * kSelBlock;
+        k[u] = a < n ? gkeys[a] : 0ull;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t a = a0 + u * kSelBlock;
+        if (a < n) stage[a] = k[u];
+      }
+    }
     __syncthreads();
   }
   const uint64_t* keys = STAGE ? stage : gkeys;
