@@ -99,6 +99,38 @@ def serving_run(U, jobs, rate, seed, max_active):
                       "note": "the same jobs submitted at once: capacity of the server"}}
 
 
+def uneven_run(U, seed, autotune):
+    """Twelve uneven jobs (meshes 32^2 and 64^2, d 8 or 10, boxes [-16,16]^d or
+    [-32,32]^d, s 100 or 200, relative threshold 1e-5, r = 5, float32 +
+    refinement) one after another, then together with their solver launches
+    fused (usfft_detect_batch); the results must agree bitwise."""
+    import numpy as np
+    import workloads as W
+    jobs = W.uneven_batch(seed=seed, jobs=12, meshes=(32, 64), dims=(8, 10), Ns=(16, 32), ss=(100, 200))
+    pars = [dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=256, autotune=autotune)
+            for _, par, _ in jobs]
+    plans = [U.Plan(prob, pa) for (prob, _, _), pa in zip(jobs, pars)]
+    seeds = [sd for _, _, sd in jobs]
+    for p, sd in zip(plans, seeds):  # warm-up: tables, tuning, workspaces
+        U.detect(p, sd).close()
+    U.detect_batch(plans, seeds)
+    t0 = time.perf_counter()
+    alone = [U.detect(p, sd) for p, sd in zip(plans, seeds)]
+    t_alone = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res, sts, fs = U.detect_batch(plans, seeds)
+    t_batch = time.perf_counter() - t0
+    same = all(st == U.OK for st in sts) and all(
+        np.array_equal(a.freqs(), b.freqs()) and np.array_equal(a.coeffs(), b.coeffs()) for a, b in zip(alone, res))
+    samples = sum(a.stats["samples"] for a in alone)
+    return {"jobs": len(jobs), "workload": "meshes 32^2/64^2, d 8/10, N 16/32, s 100/200, rel. 1e-5, r = 5, "
+                                           "float32 + refinement, seed %d" % seed,
+            "one_by_one_s": t_alone, "fused_s": t_batch, "one_by_one_jobs_per_s": len(jobs) / t_alone,
+            "fused_jobs_per_s": len(jobs) / t_batch, "fused_samples_per_s": samples / t_batch,
+            "solver_launches": fs[0], "fused_launches": fs[1], "job_segments": fs[2],
+            "results_identical": bool(same)}
+
+
 def evaluation_run(U, torch, plan, prob, seed, n_test):
     """Post-processing of one job's result (Sec. 4, 4.1): the error measures
     over n_test uniform test parameters (FE solves + evaluation product on the
@@ -359,6 +391,8 @@ def main():
                     help="use the committed tuning cache and time missing kernel choices (0 = built-in choices)")
     ap.add_argument("--tune-out", default="",
                     help="write the tuning cache (JSON) to this path at the end")
+    ap.add_argument("--uneven", type=int, default=1,
+                    help="also run twelve uneven jobs one by one and fused (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprof byte counters)")
     args = ap.parse_args()
@@ -494,6 +528,8 @@ def main():
                        "solver_ms_per_launch": sum(x["ms_sample"] for x in st) / max(1, sum(x["sample_launches"] for x in st)),
                        "detected_frequencies": nI_m}
         mplan.close()
+    if args.uneven:
+        res["uneven_batch"] = uneven_run(U, args.seed, args.autotune)
     if args.serving_jobs > 0:
         res["serving"] = serving_run(U, args.serving_jobs, 4.0, args.seed, 4)
     if args.parity and args.workload == "mesh64_d10":

@@ -265,6 +265,24 @@ usfft_status usfft_coefficients_ws(usfft_plan_t plan, const int32_t* freqs_host,
                                    int64_t n_cand_max, int64_t samples_max, void* ws_dev,
                                    size_t ws_bytes, void* stream, usfft_result_t* out);
 
+/* Several jobs (one plan each, distinct plans) run together: each on its own
+ * thread and stream, with the PDE solves of every sampler batch fused across
+ * the jobs.  Whenever a job needs solves it waits until every other job
+ * still running needs its next batch of solves (or has finished); then one
+ * persistent solver launch per class of jobs (same mesh_n, precision, DST
+ * solver variant and solver tolerances; the coefficient family, d, box, s
+ * and the batch sizes may differ) serves all of their batches through a
+ * table of (job, sample
+ * range) segments.  Jobs whose plans do not use the DST-preconditioned
+ * solver run alone, unfused.  Results are those of usfft_detect on each job
+ * alone (a solve does not depend on its batch).  out[i] receives job i's
+ * result (NULL if it failed), statuses[i] (may be NULL) its status;
+ * fuse_stats (may be NULL): solver launches, launches that served more than
+ * one job, and job segments over all launches.  Returns after every job has
+ * finished: USFFT_OK, or the status of the first failed job.  1 <= n <= 64. */
+usfft_status usfft_detect_batch(usfft_plan_t* plans, int32_t n, const uint64_t* seeds,
+                                usfft_result_t* out, usfft_status* statuses, int64_t* fuse_stats);
+
 /* Step 3 of Alg. 1 alone on a given frequency set (Sec. 4.5: a-priori index
  * sets such as axis crosses, hyperbolic crosses and weighted l1 balls):
  * freqs_host (n x d int32, row-major, no repeated rows; any order) replaces

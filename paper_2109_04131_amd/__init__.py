@@ -79,6 +79,7 @@ _sigs = {
     "usfft_tune_clear": (C.c_int, []),
     "usfft_plan_nodes": (C.c_int64, [_vp]),
     "usfft_detect": (C.c_int, [_vp, C.c_uint64, _vp, C.POINTER(_vp)]),
+    "usfft_detect_batch": (C.c_int, [_vp, C.c_int32, _vp, _vp, _vp, _vp]),
     "usfft_plan_workspace": (C.c_int, [_vp, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "usfft_detect_ws": (C.c_int, [_vp, C.c_uint64, C.c_int64, C.c_int64, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "usfft_coefficients_ws": (C.c_int, [_vp, _vp, C.c_int64, C.c_uint64, C.c_int64, C.c_int64, _vp, C.c_size_t,
@@ -381,6 +382,22 @@ def coefficients_ws(plan, freqs, seed, n_cand_max, samples_max, ws, ws_bytes=Non
     _check(_lib.usfft_coefficients_ws(plan.handle, F.ctypes.data if F.size else None, F.shape[0], C.c_uint64(seed),
                                       int(n_cand_max), int(samples_max), _ptr(ws), nb, _stream(stream), C.byref(h)))
     return Result(h)
+
+
+def detect_batch(plans, seeds):
+    """usfft_detect_batch: jobs run together with their solver launches fused.
+    Returns ([Result or None], [status], (launches, fused launches, segments))."""
+    n = len(plans)
+    hs = (_vp * n)(*[p.handle.value for p in plans])
+    sd = (C.c_uint64 * n)(*seeds)
+    outs = (_vp * n)()
+    sts = (C.c_int * n)()
+    fs = (C.c_int64 * 3)()
+    st = _lib.usfft_detect_batch(hs, n, sd, outs, sts, fs)
+    res = [Result(_vp(outs[i])) if outs[i] else None for i in range(n)]
+    if st != OK and all(r is None for r in res):
+        _check(st)
+    return res, list(sts), tuple(fs)
 
 
 def coefficients(plan, freqs, seed, stream=None):

@@ -83,10 +83,23 @@ void dst_tables_build(int n, void* frag, float* lam, hipStream_t st);  // lam: M
 int dst_persistent_blocks(int n, int precision, int variant);
 int64_t dst_edge_stride(int mp);   // doubles per scratch grid
 int64_t dst_scratch_doubles(int n, int variant, int blocks);
-void launch_pde_solve_dst(const PdeDev& P, int precision, int variant, const double* Y, int64_t ns, double rtol,
-                          int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
-                          int64_t col0, int* iters, double* wscr, int wblocks, const void* frag, const float* lam,
-                          hipStream_t st);
+// One job's batch of solves in a DST solver launch: samples begin ..
+// begin + (next segment's begin) of the launch, sampling nodes Y (rows from
+// 0), node g of local sample j written to out[g ld + col0 + j], iteration
+// counts to iters[j].  Every segment of a launch has the same mesh; the
+// coefficient family (d, amplitudes, model) may differ.
+struct SolveSeg {
+  PdeDev pde;
+  const double* Y;
+  void* out;
+  int64_t ld, col0, begin;
+  int* iters;
+};
+// segs: device array of nseg segments, ascending begin, segs[0].begin = 0;
+// ns = all samples of the launch; n = the segments' mesh_n
+void launch_pde_solve_dst(const SolveSeg* segs, int nseg, int n, int precision, int variant, int64_t ns,
+                          double rtol, int maxit, double inner_rtol, int refine_every, int out_fp32, double* wscr,
+                          int wblocks, const void* frag, const float* lam, hipStream_t st);
 // samples at a point set from samples at the mesh's inner vertices (G points,
 // three (vertex row or -1, weight) pairs each; um: rows of ldm, same type as out)
 void launch_interp(const void* um, int fp32, int64_t ldm, const int32_t* idx, const double* w, int64_t G, int64_t ns,

@@ -357,8 +357,8 @@ __device__ void assemble(const PdeDev& P, const double* coef, const EW& ew, DT* 
 
 template <typename T, int MP, bool LR>
 __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_waves<T, MP, LR>()))) void pcgdst_kernel(
-    PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, double inner_rtol, int refine_every,
-    void* __restrict__ out, int out_fp32, int64_t ld, int64_t col0, int* __restrict__ iters,
+    const SolveSeg* __restrict__ segs, int nseg, int64_t ns, double rtol, int maxit, double inner_rtol,
+    int refine_every, int out_fp32,
     double* __restrict__ wscr, int64_t wstride, const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
   constexpr int NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
   constexpr int PP = dst_pitch(MP);
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
   __shared__ double red0[2 * (BLOCK / kWave)];
   __shared__ double red1[2 * (BLOCK / kWave)];
   __shared__ __attribute__((aligned(16))) float slam[MP];
-  const int n = P.n, m = n - 1;
+  const int n = segs[0].pde.n, m = n - 1;  // every segment has this mesh
   double* sx = lds;                                          // float32 path: float64 iterate u
   T* sp = reinterpret_cast<T*>(lds + (REFINE ? GE : 0));    // search direction (zero halo), staging
   _Float16* xa = reinterpret_cast<_Float16*>(sp + GE);      // exchange tiles, column-major
@@ -413,10 +413,16 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
     const int base = (4 * q + 1) * PP + c + 1;
     T* spl = sp + base;
     auto off = [](int e) { return (16 * (e >> 2) + (e & 3)) * PP; };
+    // the job segment of sample s (a fused launch serves several jobs'
+    // batches; each segment has its coefficient family, nodes and output)
+    int ks = 0;
+    for (int a = 1; a < nseg; ++a) ks = segs[a].begin <= s ? a : ks;
+    const SolveSeg& sg = segs[ks];
+    const int64_t sl = s - sg.begin;
     __syncthreads();  // the previous sample is done with LDS, coef and the edge grids
-    load_coef(P, Y, s, coef);
+    load_coef(sg.pde, sg.Y, sl, coef);
     __syncthreads();
-    assemble<BLOCK / 64, LR ? 16 : 8>(P, coef, EdgesF64{eh, ev}, dg, PP, tid);
+    assemble<BLOCK / 64, LR ? 16 : 8>(sg.pde, coef, EdgesF64{eh, ev}, dg, PP, tid);
     __syncthreads();
     // scaled weights: wE, wW, wS per node; wN(v) = wS(v + 1) inside a 4-row
     // group, so only the top row of each group keeps its own (wN4)
@@ -445,7 +451,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
         if (v == 3) wN4[t] = ok ? (T)(evl[o] * di * sdl[o + PP]) : (T)0;
         if constexpr (DIAG)
           dd[e] = ok ? (T)(di * di * (ehl[o] + ehl[o - 1] + evl[o] + evl[o - PP])) : (T)0;
-        const double bt = ok ? di * P.h2 : 0.0;
+        const double bt = ok ? di * sg.pde.h2 : 0.0;
         r[e] = (T)bt;
         bb += bt * bt;
       }
@@ -538,7 +544,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
             const double xc = sxl[o];
             const double ax = ehl[o] * (xc - sxl[o + 1]) + ehl[o - 1] * (xc - sxl[o - 1]) +
                               evl[o] * (xc - sxl[o + PP]) + evl[o - PP] * (xc - sxl[o - PP]);
-            const double rsv = dgl[o] * (P.h2 - ax);
+            const double rsv = dgl[o] * (sg.pde.h2 - ax);
             const double rs = ok ? rsv : 0.0;
             rr64 += rs * rs;
             r[e] = (T)rs;
@@ -580,10 +586,10 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
         const int row = 16 * (e >> 2) + 4 * q + (e & 3);
         const double dv = dgl[off(e)] * (double)dx[e];
         const double u = REFINE ? sxl[off(e)] + dv : dv;
-        if (row < m && c < m) store_sample(out, out_fp32, ((int64_t)row * m + c) * ld + col0 + s, u);
+        if (row < m && c < m) store_sample(sg.out, out_fp32, ((int64_t)row * m + c) * sg.ld + sg.col0 + sl, u);
       }
     }
-    if (tid == 0 && iters) iters[s] = conv ? it : -1;
+    if (tid == 0 && sg.iters) sg.iters[sl] = conv ? it : -1;
   }
 }
 
@@ -607,8 +613,8 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
 // residual only.
 template <int MP>
 __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64 ? 2 : 4))) void pcgdst32c_kernel(
-    PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, double inner_rtol, int refine_every,
-    void* __restrict__ out, int out_fp32, int64_t ld, int64_t col0, int* __restrict__ iters,
+    const SolveSeg* __restrict__ segs, int nseg, int64_t ns, double rtol, int maxit, double inner_rtol,
+    int refine_every, int out_fp32,
     double* __restrict__ wscr, int64_t wstride, const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
   constexpr int NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
   constexpr int PP = dst_pitch(MP);
@@ -619,7 +625,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
   __shared__ double red0[3 * (BLOCK / kWave)];
   __shared__ double red1[2 * (BLOCK / kWave)];
   __shared__ __attribute__((aligned(16))) float slam[MP];
-  const int n = P.n, m = n - 1;
+  const int n = segs[0].pde.n, m = n - 1;  // every segment has this mesh
   double* su = lds;                                        // overlay: float64 u
   float* sp = reinterpret_cast<float*>(lds);               // overlay: search direction
   _Float16* xa = reinterpret_cast<_Float16*>(sp + GE);     // overlay: exchange tiles
@@ -654,10 +660,16 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
     const int q = (tid & 63) >> 4, c = 16 * (tid >> 6) + (tid & 15);
     const int base = (4 * q + 1) * PP + c + 1;
     auto off = [](int e) { return (16 * (e >> 2) + (e & 3)) * PP; };
+    // the job segment of sample s (a fused launch serves several jobs'
+    // batches; each segment has its coefficient family, nodes and output)
+    int ks = 0;
+    for (int a = 1; a < nseg; ++a) ks = segs[a].begin <= s ? a : ks;
+    const SolveSeg& sg = segs[ks];
+    const int64_t sl = s - sg.begin;
     __syncthreads();  // the previous sample is done with LDS and coef
-    load_coef(P, Y, s, coef);
+    load_coef(sg.pde, sg.Y, sl, coef);
     __syncthreads();
-    assemble<BLOCK / 64, MP / 4>(P, coef, EdgesSplit{feh, fev, geh, gev}, dg, PP, tid);
+    assemble<BLOCK / 64, MP / 4>(sg.pde, coef, EdgesSplit{feh, fev, geh, gev}, dg, PP, tid);
     __syncthreads();
     float wE[E], wW[E], wS[E], wN4[NT], r[E], p[E];
     double ux[E];
@@ -676,7 +688,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
         wW[e] = ok ? ehl[o - 1] * di * sdl[o - 1] : 0.0f;
         wS[e] = ok ? evl[o - PP] * di * sdl[o - PP] : 0.0f;
         if (v == 3) wN4[t] = ok ? evl[o] * di * sdl[o + PP] : 0.0f;
-        const double bt = ok ? (double)di * P.h2 : 0.0;
+        const double bt = ok ? (double)di * sg.pde.h2 : 0.0;
         r[e] = (float)bt;
         bb += bt * bt;
       }
@@ -764,7 +776,7 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
           const double xc = sul[o];
           const double ax = ehl[o] * (xc - sul[o + 1]) + ehl[o - 1] * (xc - sul[o - 1]) +
                             evl[o] * (xc - sul[o + PP]) + evl[o - PP] * (xc - sul[o - PP]);
-          const double rsv = (double)dgl[o] * (P.h2 - ax);
+          const double rsv = (double)dgl[o] * (sg.pde.h2 - ax);
           const double rs = ok ? rsv : 0.0;
           rr64 += rs * rs;
           r[e] = (float)rs;
@@ -799,10 +811,10 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
       for (int e = 0; e < E; ++e) {
         const int row = 16 * (e >> 2) + 4 * q + (e & 3);
         const double u = (double)dgl[off(e)] * ux[e];
-        if (row < m && c < m) store_sample(out, out_fp32, ((int64_t)row * m + c) * ld + col0 + s, u);
+        if (row < m && c < m) store_sample(sg.out, out_fp32, ((int64_t)row * m + c) * sg.ld + sg.col0 + sl, u);
       }
     }
-    if (tid == 0 && iters) iters[s] = conv ? it : -1;
+    if (tid == 0 && sg.iters) sg.iters[sl] = conv ? it : -1;
   }
 }
 
@@ -850,29 +862,29 @@ int64_t dst_scratch_doubles(int n, int variant, int blocks) {
   return variant == 1 ? 0 : (variant == 2 ? 2 : 3) * dst_edge_stride(dst_padded(n)) * (int64_t)blocks;
 }
 
-void launch_pde_solve_dst(const PdeDev& P, int precision, int variant, const double* Y, int64_t ns, double rtol,
-                          int maxit, double inner_rtol, int refine_every, void* out, int out_fp32, int64_t ld,
-                          int64_t col0, int* iters, double* wscr, int wblocks, const void* frag, const float* lam,
-                          hipStream_t st) {
+void launch_pde_solve_dst(const SolveSeg* segs, int nseg, int n, int precision, int variant, int64_t ns,
+                          double rtol, int maxit, double inner_rtol, int refine_every, int out_fp32, double* wscr,
+                          int wblocks, const void* frag, const float* lam, hipStream_t st) {
   if (ns <= 0) return;
-  const int mp = dst_padded(P.n);
+  const int mp = dst_padded(n);
   USFFT_REQUIRE(mp > 0, USFFT_EINVAL, "mesh too large for the DST-preconditioned solver");
+  USFFT_REQUIRE(nseg >= 1, USFFT_EINVAL, "no solver segment");
   USFFT_REQUIRE(variant == 0 || variant == 1 || (variant == 2 && precision != USFFT_FP64), USFFT_EINVAL,
                 "bad DST solver variant");
   const int64_t ws = dst_edge_stride(mp);
   const unsigned grid = (unsigned)std::min<int64_t>(ns, wblocks);
-  const size_t lds = (size_t)dst_lds_bytes(P.n, precision, variant);
+  const size_t lds = (size_t)dst_lds_bytes(n, precision, variant);
   const half8* sf = static_cast<const half8*>(frag);
 #define USFFT_DST(TT, MM, LL)                                                                                  \
-  hipLaunchKernelGGL((pcgdst_kernel<TT, MM, LL>), dim3(grid), dim3(4 * MM), lds, st, P, Y, ns, rtol, maxit,     \
-                     inner_rtol, refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam)
+  hipLaunchKernelGGL((pcgdst_kernel<TT, MM, LL>), dim3(grid), dim3(4 * MM), lds, st, segs, nseg, ns, rtol, maxit, \
+                     inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam)
   if (variant == 2) {
     if (mp == 64)
-      hipLaunchKernelGGL(pcgdst32c_kernel<64>, dim3(grid), dim3(256), lds, st, P, Y, ns, rtol, maxit, inner_rtol,
-                         refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+      hipLaunchKernelGGL(pcgdst32c_kernel<64>, dim3(grid), dim3(256), lds, st, segs, nseg, ns, rtol, maxit,
+                         inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam);
     else
-      hipLaunchKernelGGL(pcgdst32c_kernel<32>, dim3(grid), dim3(128), lds, st, P, Y, ns, rtol, maxit, inner_rtol,
-                         refine_every, out, out_fp32, ld, col0, iters, wscr, ws, sf, lam);
+      hipLaunchKernelGGL(pcgdst32c_kernel<32>, dim3(grid), dim3(128), lds, st, segs, nseg, ns, rtol, maxit,
+                         inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam);
   } else if (precision == USFFT_FP64) {
     if (mp == 64) { if (variant) USFFT_DST(double, 64, true); else USFFT_DST(double, 64, false); }
     else { if (variant) USFFT_DST(double, 32, true); else USFFT_DST(double, 32, false); }

@@ -94,6 +94,8 @@ struct DevBuf {
   ~DevBuf() { release(); }
 };
 
+struct FuseGroup;
+
 struct Family {
   std::vector<int> M;
   std::vector<int32_t> z;  // nlat x t
@@ -122,6 +124,11 @@ struct usfft_plan_s {
   bool interp = false;
   int64_t G_mesh = 0;
   usfft::DevBuf d_iidx, d_iw, Umesh;
+  // the one-segment table of this plan's own DST solver launches
+  usfft::DevBuf segbuf;
+  // set while the plan runs in usfft_detect_batch: DST solver launches go
+  // through the batch's rendezvous and are fused with the other jobs'
+  usfft::FuseGroup* fuse = nullptr;
   usfft::MeshDev mesh{};
   int mesh_blocks = 0;
   // pinned staging of small uploads: a copy from it needs no host wait; the
@@ -356,6 +363,147 @@ static void group_by_lattice(usfft_plan_s* P, Family& F, const int32_t* assign, 
 
 // One solver launch at the mesh's own nodes.  params: Y holds parameters y
 // of the model instead of sampling nodes t.
+// Rendezvous of the DST solver launches of jobs run together
+// (usfft_detect_batch).  A job's sampler call waits until every job still
+// running has made its next call or finished; the last one to arrive then
+// launches one persistent solver kernel per class (mesh, precision, solver
+// variant) over a segment table of all the waiting jobs' batches, on the
+// first such job's stream, after every job's stream has reached its call,
+// and each job's stream waits for that launch before it goes on.  Every
+// solve is independent of its batch, so each job's results are those it
+// gets alone.
+struct FuseReq {
+  usfft_plan_s* P;
+  SolveSeg seg;
+  int64_t ns;
+  int out_fp32;
+  hipStream_t st;
+  hipEvent_t ready = nullptr, done = nullptr;
+};
+struct FuseGroup {
+  std::mutex mu;
+  std::condition_variable cv;
+  int active = 0;
+  uint64_t round = 0;
+  std::vector<FuseReq*> reqs;
+  std::string error;
+  // device segment tables, a ring of slots, each reused only after the
+  // launch that read it has finished
+  static constexpr int kSlots = 4, kMaxSeg = 64;
+  DevBuf segs[kSlots];
+  hipEvent_t slot_done[kSlots] = {};
+  int next_slot = 0;
+  int64_t launches = 0, fused_launches = 0, segments = 0;
+  ~FuseGroup() {
+    for (hipEvent_t e : slot_done)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+// Launches the collected requests (called with the group's lock held).
+static void fuse_launch(FuseGroup* F) {
+  std::vector<FuseReq*> todo = F->reqs;
+  while (!todo.empty()) {
+    FuseReq* lead = todo.front();
+    usfft_plan_s* LP = lead->P;
+    std::vector<FuseReq*> cls, rest;
+    for (FuseReq* r : todo)
+      (r->P->prob.mesh_n == LP->prob.mesh_n && r->P->par.precision == LP->par.precision &&
+               r->P->dst_variant == LP->dst_variant && r->out_fp32 == lead->out_fp32 &&
+               r->P->par.pcg_rtol == LP->par.pcg_rtol && r->P->par.pcg_maxit == LP->par.pcg_maxit &&
+               r->P->par.inner_rtol == LP->par.inner_rtol && r->P->par.refine_every == LP->par.refine_every &&
+               (int)cls.size() < FuseGroup::kMaxSeg
+           ? cls
+           : rest)
+          .push_back(r);
+    todo.swap(rest);
+    std::vector<SolveSeg> tab;
+    int64_t ns = 0;
+    for (FuseReq* r : cls) {
+      SolveSeg sg = r->seg;
+      sg.begin = ns;
+      tab.push_back(sg);
+      ns += r->ns;
+    }
+    const int slot = F->next_slot;
+    F->next_slot = (F->next_slot + 1) % FuseGroup::kSlots;
+    if (F->slot_done[slot]) {
+      USFFT_HIP(hipEventSynchronize(F->slot_done[slot]));
+    } else {
+      USFFT_HIP(hipEventCreateWithFlags(&F->slot_done[slot], hipEventDisableTiming));
+    }
+    F->segs[slot].ensure(sizeof(SolveSeg) * FuseGroup::kMaxSeg);
+    USFFT_HIP(hipMemcpy(F->segs[slot].p, tab.data(), sizeof(SolveSeg) * tab.size(), hipMemcpyHostToDevice));
+    const hipStream_t st = lead->st;
+    for (FuseReq* r : cls) USFFT_HIP(hipStreamWaitEvent(st, r->ready, 0));
+    const usfft_params& par = LP->par;
+    launch_pde_solve_dst(F->segs[slot].as<SolveSeg>(), (int)tab.size(), LP->prob.mesh_n, par.precision,
+                         LP->dst_variant, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol, par.refine_every,
+                         lead->out_fp32, LP->d_wscr.as<double>(), LP->wblocks, LP->d_sfrag.p, LP->d_lam.as<float>(),
+                         st);
+    USFFT_HIP(hipEventRecord(F->slot_done[slot], st));
+    for (FuseReq* r : cls) USFFT_HIP(hipEventRecord(r->done, st));
+    F->launches++;
+    F->fused_launches += cls.size() > 1 ? 1 : 0;
+    F->segments += (int64_t)cls.size();
+  }
+  F->reqs.clear();
+}
+
+// The rendezvous of one sampler call (see FuseGroup).
+static void fused_solve(usfft_plan_s* P, const SolveSeg& seg, int64_t ns, int out_fp32, hipStream_t st) {
+  FuseGroup* F = P->fuse;
+  FuseReq r{P, seg, ns, out_fp32, st};
+  USFFT_HIP(hipEventCreateWithFlags(&r.ready, hipEventDisableTiming));
+  USFFT_HIP(hipEventCreateWithFlags(&r.done, hipEventDisableTiming));
+  struct Ev {
+    FuseReq& r;
+    ~Ev() {
+      (void)hipEventDestroy(r.ready);
+      (void)hipEventDestroy(r.done);
+    }
+  } ev{r};
+  USFFT_HIP(hipEventRecord(r.ready, st));
+  {
+    std::unique_lock<std::mutex> lk(F->mu);
+    USFFT_REQUIRE(F->error.empty(), USFFT_EHIP, "fused launch failed: " + F->error);
+    F->reqs.push_back(&r);
+    if ((int)F->reqs.size() == F->active) {
+      try {
+        fuse_launch(F);
+      } catch (const Error& e) {
+        F->error = e.msg;
+        F->reqs.clear();
+      }
+      F->round++;
+      F->cv.notify_all();
+    } else {
+      const uint64_t r0 = F->round;
+      F->cv.wait(lk, [&] { return F->round != r0; });
+    }
+    USFFT_REQUIRE(F->error.empty(), USFFT_EHIP, "fused launch failed: " + F->error);
+  }
+  USFFT_HIP(hipStreamWaitEvent(st, r.done, 0));
+  // the events may be destroyed now: their work is enqueued
+}
+
+// A job of the batch leaves the rendezvous (finished or failed); if every
+// job still running is waiting, their launch happens now.
+static void fuse_leave(FuseGroup* F) {
+  std::lock_guard<std::mutex> lk(F->mu);
+  F->active--;
+  if (F->active > 0 && (int)F->reqs.size() == F->active) {
+    try {
+      fuse_launch(F);
+    } catch (const Error& e) {
+      F->error = e.msg;
+      F->reqs.clear();
+    }
+    F->round++;
+    F->cv.notify_all();
+  }
+}
+
 static void solve_batch(usfft_plan_s* P, const double* Y, int64_t ns, void* U, int out_fp32, int64_t ld,
                         int64_t col0, int32_t* iters, hipStream_t st, bool params);
 
@@ -383,9 +531,15 @@ static void solve_batch(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
     launch_pde_solve_mesh(pde, P->mesh, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
                           P->mesh_blocks, st);
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->dst) {
-    launch_pde_solve_dst(pde, par.precision, P->dst_variant, Y, ns, par.pcg_rtol, par.pcg_maxit, par.inner_rtol,
-                         par.refine_every, U, out_fp32, ld, col0, iters, P->d_wscr.as<double>(), P->wblocks,
-                         P->d_sfrag.p, P->d_lam.as<float>(), st);
+    const SolveSeg seg{pde, Y, U, ld, col0, 0, iters};
+    if (P->fuse) {
+      fused_solve(P, seg, ns, out_fp32, st);
+    } else {
+      h2d_async(P, P->segbuf, std::vector<SolveSeg>{seg}, st);
+      launch_pde_solve_dst(P->segbuf.as<SolveSeg>(), 1, P->prob.mesh_n, par.precision, P->dst_variant, ns,
+                           par.pcg_rtol, par.pcg_maxit, par.inner_rtol, par.refine_every, out_fp32,
+                           P->d_wscr.as<double>(), P->wblocks, P->d_sfrag.p, P->d_lam.as<float>(), st);
+    }
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->streaming) {
     launch_pde_solve_stream(pde, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
                             P->d_stream.as<double>(), kStreamBlocks, st);
@@ -892,6 +1046,7 @@ static std::vector<WsItem> ws_items(usfft_plan_s* P, DevBuf* C, int64_t ncand, i
   };
   for (int t = 0; t < d; ++t) v.push_back({&P->I1[t], sz(4 * (pb.k_hi[t] - pb.k_lo[t] + 1))});
   if (P->interp) v.push_back({&P->Umesh, sz(ub * P->G_mesh * nsb)});
+  v.push_back({&P->segbuf, sz(sizeof(SolveSeg))});
   v.push_back({C, sz(16 * nc * G)});
   return v;
 }
@@ -1048,15 +1203,21 @@ static int autotune_dst_variant(usfft_plan_s* P, int fallback) {
   const int ufp32 = prec == USFFT_FP32_REFINE ? 1 : 0;
   U.ensure((ufp32 ? sizeof(float) : sizeof(double)) * G * ns);
   it.ensure(sizeof(int32_t) * ns);
+  DevBuf sg;
+  {
+    const SolveSeg seg{P->pde, Y.as<double>(), U.p, ns, 0, 0, it.as<int32_t>()};
+    sg.ensure(sizeof(SolveSeg));
+    USFFT_HIP(hipMemcpy(sg.p, &seg, sizeof(SolveSeg), hipMemcpyHostToDevice));
+  }
   e.a = fallback;
   e.time_ms = 1e30;
   for (int v = 0; v <= (ufp32 ? 2 : 1); ++v) {
     const int wb = dst_persistent_blocks(n, prec, v);
     scr.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, dst_scratch_doubles(n, v, wb)));
     const float ms = time_on(st, [&] {
-      launch_pde_solve_dst(P->pde, prec, v, Y.as<double>(), ns, P->par.pcg_rtol, P->par.pcg_maxit,
-                           P->par.inner_rtol, P->par.refine_every, U.p, ufp32, ns, 0, it.as<int32_t>(),
-                           scr.as<double>(), wb, P->d_sfrag.p, P->d_lam.as<float>(), st);
+      launch_pde_solve_dst(sg.as<SolveSeg>(), 1, n, prec, v, ns, P->par.pcg_rtol, P->par.pcg_maxit,
+                           P->par.inner_rtol, P->par.refine_every, ufp32, scr.as<double>(), wb, P->d_sfrag.p,
+                           P->d_lam.as<float>(), st);
     });
     if (ms < e.time_ms) {
       e.time_ms = ms;
@@ -1542,6 +1703,70 @@ usfft_status usfft_detect(usfft_plan_t plan, uint64_t seed, void* stream, usfft_
     std::unique_ptr<usfft_result_s> R(new usfft_result_s());
     detect(plan, seed, (hipStream_t)stream, R.get());
     *out = R.release();
+  });
+}
+
+usfft_status usfft_detect_batch(usfft_plan_t* plans, int32_t n, const uint64_t* seeds, usfft_result_t* out,
+                                usfft_status* statuses, int64_t* fuse_stats) {
+  return guarded([&] {
+    USFFT_REQUIRE(plans && seeds && out && n >= 1 && n <= FuseGroup::kMaxSeg, USFFT_EINVAL,
+                  "bad batch arguments (1 <= n <= 64)");
+    for (int i = 0; i < n; ++i) {
+      USFFT_REQUIRE(plans[i], USFFT_EINVAL, "null plan in batch");
+      for (int j = 0; j < i; ++j) USFFT_REQUIRE(plans[j] != plans[i], USFFT_EINVAL, "a plan appears twice in the batch");
+      out[i] = nullptr;
+    }
+    int dev = 0;
+    USFFT_HIP(hipGetDevice(&dev));
+    FuseGroup F;
+    std::vector<int> fused(n, 0);
+    for (int i = 0; i < n; ++i) {
+      fused[i] = plans[i]->prob.sampler == USFFT_SAMPLER_PDE && plans[i]->dst ? 1 : 0;
+      F.active += fused[i];
+    }
+    std::vector<usfft_status> st(n, USFFT_OK);
+    std::vector<std::string> err(n);
+    std::vector<std::unique_ptr<usfft_result_s>> res(n);
+    std::vector<std::thread> th;
+    for (int i = 0; i < n; ++i)
+      th.emplace_back([&, i] {
+        hipStream_t s = nullptr;
+        try {
+          USFFT_HIP(hipSetDevice(dev));
+          USFFT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+          std::lock_guard<std::mutex> lk(plans[i]->mu);
+          plans[i]->fuse = fused[i] ? &F : nullptr;
+          res[i].reset(new usfft_result_s());
+          detect(plans[i], seeds[i], s, res[i].get());
+        } catch (const Error& e) {
+          st[i] = e.st;
+          err[i] = e.msg;
+          res[i].reset();
+        } catch (const std::exception& e) {
+          st[i] = USFFT_EINVAL;
+          err[i] = e.what();
+          res[i].reset();
+        }
+        if (fused[i]) fuse_leave(&F);
+        if (s) {
+          (void)hipStreamSynchronize(s);
+          (void)hipStreamDestroy(s);
+        }
+      });
+    for (auto& t : th) t.join();
+    int first_bad = -1;
+    for (int i = 0; i < n; ++i) {
+      plans[i]->fuse = nullptr;
+      if (statuses) statuses[i] = st[i];
+      out[i] = res[i].release();
+      if (st[i] != USFFT_OK && first_bad < 0) first_bad = i;
+    }
+    if (fuse_stats) {
+      fuse_stats[0] = F.launches;
+      fuse_stats[1] = F.fused_launches;
+      fuse_stats[2] = F.segments;
+    }
+    if (first_bad >= 0) throw Error{st[first_bad], "job " + std::to_string(first_bad) + ": " + err[first_bad]};
   });
 }
 

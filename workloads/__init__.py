@@ -78,15 +78,16 @@ WORKLOADS = {
 }
 
 
-def uneven_batch(seed=1, jobs=12):
-    """12 jobs mixing meshes 32^2/64^2/128^2, d in {8,16,30}, N in {16,32,64}, s in {100,300,500}."""
+def uneven_batch(seed=1, jobs=12, meshes=(32, 64, 128), dims=(8, 16, 30), Ns=(16, 32, 64), ss=(100, 300, 500)):
+    """Jobs mixing meshes, d, N and s (default: 12 jobs, meshes 32^2/64^2/128^2,
+    d in {8,16,30}, N in {16,32,64}, s in {100,300,500}), each seeded."""
     g = np.random.default_rng(seed)
     out = []
     for _ in range(jobs):
-        n = int(g.choice([32, 64, 128]))
-        d = int(g.choice([8, 16, 30]))
-        N = int(g.choice([16, 32, 64]))
-        s = int(g.choice([100, 300, 500]))
+        n = int(g.choice(list(meshes)))
+        d = int(g.choice(list(dims)))
+        N = int(g.choice(list(Ns)))
+        s = int(g.choice(list(ss)))
         out.append((pde_problem(n, d, N), params(s, 5, 1e-5), int(g.integers(1, 2 ** 31))))
     return out
 
