@@ -134,6 +134,36 @@ def test_dst_solver_batch_independent_and_fast(lib, prec, variant):
         assert np.linalg.norm(host(U)[:, s] - ref) <= (1e-10 if prec == 0 else 1e-9) * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("model,n", [("pde", 5), ("pde", 16), ("pde", 17), ("pde", 33), ("pde", 34), ("pde", 48),
+                                     ("pde", 64), ("pde", 65), ("lognormal", 33), ("lognormal", 65),
+                                     ("affine", 40)])
+def test_compact_solver_edge_meshes(lib, model, n):
+    # the compact float32 solver rebuilds its float64 edge weights on the
+    # matrix cores at every true residual, with the cells beyond the waves'
+    # strips (column 16 (w + 1), row MP) kept from the assembly: meshes that
+    # fill the padded transform exactly (n = 33, 65, where row and column MP
+    # are interior), leave most of it empty (n = 5, 17, 34) or end inside a
+    # strip (n = 40, 48) must all converge to the direct solve
+    d = 6
+    if model == "pde":
+        prob = W.pde_problem(n, d, 4, modes="split")
+    elif model == "affine":
+        prob = W.affine_problem(n, d, 4)
+    else:
+        prob = W.lognormal_problem(n, d, 4, delta=0.01)
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), precision=1, pcg_rtol=1e-12, solver_config=2))
+    T = np.random.default_rng(n + 7).random((30, d))
+    U = torch.zeros((plan.G, 30), dtype=torch.float64, device="cuda")
+    it = torch.zeros(30, dtype=torch.int32, device="cuda")
+    lib.sample(plan, dev(T), U, 0, 30, 0, it)
+    assert (host(it) > 0).all() and (model == "lognormal" or host(it).max() <= 40)
+    S = oracle_sampler(prob)
+    for s in range(0, 30, 5):
+        ref = S.solve_one(T[s])
+        err = np.linalg.norm(host(U)[:, s] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-9, (s, err)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_dst_preconditioner_is_exact_for_constant_coefficient(lib, prec):
     # a = 1: the scaled operator is the 5-point Laplacian itself, which the
