@@ -307,26 +307,41 @@ __device__ void assemble(const PdeDev& P, const double* coef, const EW& ew, DT* 
       double aL[CB + 1], aU[CB + 1];
 #pragma unroll
       for (int u = 0; u <= CB; ++u) aL[u] = aU[u] = logn ? 0.0 : P.a0;
-#pragma unroll 2
-      for (int k = 0; k < d; ++k) {
-        const double ck = coef[k];
-        const double txl = txL[k * n + cic], txu = txU[k * n + cic];
-        const double xl = act ? ck * txl : 0.0, xu = act ? ck * txu : 0.0;
-        // rows cb - 1 .. cb - 1 + CB are entries cb .. cb + CB < S of the
-        // padded rows (rows outside [0, n) repeat the end rows; their values
-        // are never used); all row factors of one k are loaded before any is
-        // used
-        const cdp yLk = tyL + k * S + cb, yUk = tyU + k * S + cb;
-        double yl[CB + 1], yu[CB + 1];
+      // the per-lane factors of KC consecutive k are loaded together (a
+      // scheduling fence keeps the loads ahead of their uses), so one memory
+      // latency covers KC terms
+      constexpr int KC = 8;
+      for (int k0 = 0; k0 < d; k0 += KC) {
+        double txl[KC], txu[KC];
 #pragma unroll
-        for (int u = 0; u <= CB; ++u) {
-          yl[u] = yLk[u];
-          yu[u] = yUk[u];
+        for (int j = 0; j < KC; ++j) {
+          const int kc = min(k0 + j, d - 1);
+          txl[j] = txL[kc * n + cic];
+          txu[j] = txU[kc * n + cic];
         }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u <= CB; ++u) {
-          aL[u] += xl * yl[u];
-          aU[u] += xu * yu[u];
+        for (int j = 0; j < KC; ++j) {
+          const int k = k0 + j;
+          if (k >= d) break;
+          const double ck = coef[k];
+          const double xl = act ? ck * txl[j] : 0.0, xu = act ? ck * txu[j] : 0.0;
+          // rows cb - 1 .. cb - 1 + CB are entries cb .. cb + CB < S of the
+          // padded rows (rows outside [0, n) repeat the end rows; their
+          // values are never used); all row factors of one k are loaded
+          // before any is used
+          const cdp yLk = tyL + k * S + cb, yUk = tyU + k * S + cb;
+          double yl[CB + 1], yu[CB + 1];
+#pragma unroll
+          for (int u = 0; u <= CB; ++u) {
+            yl[u] = yLk[u];
+            yu[u] = yUk[u];
+          }
+#pragma unroll
+          for (int u = 0; u <= CB; ++u) {
+            aL[u] += xl * yl[u];
+            aU[u] += xu * yu[u];
+          }
         }
       }
       if (logn) {
@@ -348,7 +363,16 @@ __device__ void assemble(const PdeDev& P, const double* coef, const EW& ew, DT* 
         if (ci >= 1 && cj >= 1) {
           const double ehm = 0.5 * (aLm + aUm1);        // eh(ci-1, cj)
           const double evm = 0.5 * (aU[u - 1] + aLm1);  // ev(ci, cj-1)
-          dg[cj * PP + ci] = (DT)(1.0 / sqrt(0.25 * (ehc + ehm + evc + evm)));
+          const double dd = 0.25 * (ehc + ehm + evc + evm);
+          // float32 scalings: the hardware reciprocal square root refined by
+          // one float64 Newton step, then rounded (the float32 iteration
+          // takes the scaled diagonal as 4, so the scaling must be the
+          // nearest float32, not merely close)
+          if constexpr (std::is_same<DT, float>::value) {
+            const double y0 = (double)__builtin_amdgcn_rsqf((float)dd);
+            dg[cj * PP + ci] = (float)(y0 * (1.5 - 0.5 * dd * y0 * y0));
+          } else
+            dg[cj * PP + ci] = 1.0 / sqrt(dd);
         }
       }
     }
@@ -769,19 +793,44 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
         const double* ehl = geh + b2;
         const double* evl = gev + b2;
         double rr64 = 0.0;
+        // the edges of half the lane's nodes are loaded before any is used
+        // (a scheduling fence keeps them together), so their global reads
+        // overlap instead of queueing behind one another
+        constexpr int HE = E / 2;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int o = off(e);
-          const bool ok = 16 * (e >> 2) + 4 * q + (e & 3) < m && c < m;
-          const double xc = sul[o];
-          const double ax = ehl[o] * (xc - sul[o + 1]) + ehl[o - 1] * (xc - sul[o - 1]) +
-                            evl[o] * (xc - sul[o + PP]) + evl[o - PP] * (xc - sul[o - PP]);
-          const double rsv = (double)dgl[o] * (sg.pde.h2 - ax);
-          const double rs = ok ? rsv : 0.0;
-          rr64 += rs * rs;
-          r[e] = (float)rs;
+        for (int h = 0; h < 2; ++h) {
+          double we[HE], ww[HE], wn[HE], ws[HE];
+#pragma unroll
+          for (int i = 0; i < HE; ++i) {
+            const int o = off(h * HE + i);
+            we[i] = ehl[o];
+            ww[i] = ehl[o - 1];
+            wn[i] = evl[o];
+            ws[i] = evl[o - PP];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < HE; ++i) {
+            const int e = h * HE + i, o = off(e);
+            const bool ok = 16 * (e >> 2) + 4 * q + (e & 3) < m && c < m;
+            const double xc = sul[o];
+            const double ax = we[i] * (xc - sul[o + 1]) + ww[i] * (xc - sul[o - 1]) + wn[i] * (xc - sul[o + PP]) +
+                              ws[i] * (xc - sul[o - PP]);
+            const double rsv = (double)dgl[o] * (sg.pde.h2 - ax);
+            const double rs = ok ? rsv : 0.0;
+            rr64 += rs * rs;
+            r[e] = (float)rs;
+          }
         }
         rr64 = block_sum<BLOCK>(rr64, red1);  // every lane is done with su
+        {
+          // the transform fragments are read again instead of being held
+          // across the residual, whose edge loads need their registers
+          const half8* sfr = sfrag;
+          asm volatile("" : "+s"(sfr));
+#pragma unroll
+          for (int f = 0; f < KB * NT; ++f) sf[f] = sfr[f * 64 + lane];
+        }
         last_update = it;
         if (rr64 <= stop) {
           conv = true;
