@@ -452,19 +452,39 @@ __device__ __forceinline__ void rader_body(const FftPlanDev& F, int M, const int
     r2[c] = u + (has2[c] ? g2 : 0) * ld + col0;
   }
   // Rader input a_q = x[g^q]: each row segment is read in natural order
-  // (coalesced) and scattered into LDS at q = dlog m; plus the sums for X[0]
+  // (coalesced) and scattered into LDS at q = dlog m; plus the sums for X[0].
+  // A thread's next UI elements are loaded before any is stored (a
+  // scheduling fence keeps the loads together), so their latencies overlap;
+  // indices past M are clamped into the row and their values dropped.
+  constexpr int UI = 4;
   double sums[2 * COLS];
 #pragma unroll
   for (int i = 0; i < 2 * COLS; ++i) sums[i] = 0.0;
-  for (int mm = 1 + threadIdx.x; mm < M; mm += BLOCK) {
-    const int q = dlog[mm];
+  for (int m0 = 1 + threadIdx.x; m0 < M; m0 += UI * BLOCK) {
+    int qv[UI];
+    T av[UI][COLS], bv[UI][COLS];
 #pragma unroll
-    for (int c = 0; c < COLS; ++c) {
-      const T a = has1[c] ? r1[c][mm] : (T)0;
-      const T b = has2[c] ? r2[c][mm] : (T)0;
-      buf[c * L + q] = {a, b};
-      sums[2 * c] += (double)a;
-      sums[2 * c + 1] += (double)b;
+    for (int i = 0; i < UI; ++i) {
+      const int mm = m0 + i * BLOCK, mc = mm < M ? mm : 0;
+      qv[i] = dlog[mc];
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) {
+        av[i][c] = r1[c][mc];
+        bv[i][c] = r2[c][mc];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < UI; ++i) {
+      if (m0 + i * BLOCK >= M) break;
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) {
+        const T a = has1[c] ? av[i][c] : (T)0;
+        const T b = has2[c] ? bv[i][c] : (T)0;
+        buf[c * L + qv[i]] = {a, b};
+        sums[2 * c] += (double)a;
+        sums[2 * c + 1] += (double)b;
+      }
     }
   }
   block_sum_n<BLOCK, 2 * COLS>(sums, red);  // also orders the LDS writes before the first stage
@@ -473,49 +493,74 @@ __device__ __forceinline__ void rader_body(const FftPlanDev& F, int M, const int
   fft_dif<T, BLOCK, COLS>(buf, F, tw, B);
   fft_dit<T, BLOCK, COLS>(buf, F, tw);
   const double invM = 1.0 / (double)M;
+  double x01[COLS], x02[COLS], s1[COLS], s2[COLS];
 #pragma unroll
   for (int c = 0; c < COLS; ++c) {
-    if (!has1[c]) continue;
-    const int64_t g1 = 2 * (grp * COLS + c), g2 = g1 + 1;
-    const double x01 = (double)r1[c][0], x02 = has2[c] ? (double)r2[c][0] : 0.0;
-    const double s1 = sums[2 * c] + x01, s2 = sums[2 * c + 1] + x02;
-    const cplx<T>* bc = buf + c * L;
-    for (int a = threadIdx.x; a < nb; a += BLOCK) {
-      const int b = bins[a];
+    x01[c] = (double)r1[c][0];
+    x02[c] = has2[c] ? (double)r2[c][0] : 0.0;
+    s1[c] = sums[2 * c] + x01[c];
+    s2[c] = sums[2 * c + 1] + x02[c];
+  }
+  // bins in chunks of UO per thread: their table loads (bin, LDS positions,
+  // output column) are issued together and serve every column
+  constexpr int UO = 4;
+  for (int a0 = threadIdx.x; a0 < nb; a0 += UO * BLOCK) {
+    int ip[UO], im[UO];
+    bool flip[UO], zero[UO];
+    int64_t cc[UO];
+#pragma unroll
+    for (int i = 0; i < UO; ++i) {
+      const int a = a0 + i * BLOCK, ac = a < nb ? a : a0;
+      const int b = bins[ac];
       const int bcn = min(b, M - b);
-      const bool flip = b > M - b;
-      double X1r, X1i, X2r, X2i;
-      if (bcn == 0) {
-        X1r = s1 * invM;
-        X1i = 0.0;
-        X2r = s2 * invM;
-        X2i = 0.0;
-      } else {
-        const cplx<T> cp = bc[outidx[bcn]];
-        const cplx<T> cm = bc[outidx[M - bcn]];
-        // X[bc] = x0 + c, X[M-bc] = x0 + c', with c = conj(buf)
-        const double Xpr = x01 + (double)cp.x, Xpi = x02 - (double)cp.y;
-        const double Xmr = x01 + (double)cm.x, Xmi = x02 - (double)cm.y;
-        X1r = 0.5 * (Xpr + Xmr) * invM;
-        X1i = 0.5 * (Xpi - Xmi) * invM;
-        X2r = 0.5 * (Xpi + Xmi) * invM;
-        X2i = -0.5 * (Xpr - Xmr) * invM;
-      }
-      if (flip) {
-        X1i = -X1i;
-        X2i = -X2i;
-      }
-      const int64_t cc = pos ? pos[a] : pos_base + a;  // contiguous when pos is null
-      double* o = static_cast<double*>(out);
-      if (out_kind == USFFT_OUT_MAG2) {
-        o[g1 * ldo + cc] = X1r * X1r + X1i * X1i;
-        if (has2[c]) o[g2 * ldo + cc] = X2r * X2r + X2i * X2i;
-      } else {
-        o[(cc * G + g1) * 2] = X1r;
-        o[(cc * G + g1) * 2 + 1] = X1i;
-        if (has2[c]) {
-          o[(cc * G + g2) * 2] = X2r;
-          o[(cc * G + g2) * 2 + 1] = X2i;
+      flip[i] = b > M - b;
+      zero[i] = bcn == 0;
+      const int bk = zero[i] ? 1 : bcn;  // X[0] reads no transform value
+      ip[i] = outidx[bk];
+      im[i] = outidx[M - bk];
+      cc[i] = pos ? pos[ac] : pos_base + ac;  // contiguous when pos is null
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < UO; ++i) {
+      if (a0 + i * BLOCK >= nb) break;
+#pragma unroll
+      for (int c = 0; c < COLS; ++c) {
+        if (!has1[c]) continue;
+        const int64_t g1 = 2 * (grp * COLS + c), g2 = g1 + 1;
+        const cplx<T>* bc = buf + c * L;
+        double X1r, X1i, X2r, X2i;
+        if (zero[i]) {
+          X1r = s1[c] * invM;
+          X1i = 0.0;
+          X2r = s2[c] * invM;
+          X2i = 0.0;
+        } else {
+          const cplx<T> cp = bc[ip[i]];
+          const cplx<T> cm = bc[im[i]];
+          // X[bc] = x0 + c, X[M-bc] = x0 + c', with c = conj(buf)
+          const double Xpr = x01[c] + (double)cp.x, Xpi = x02[c] - (double)cp.y;
+          const double Xmr = x01[c] + (double)cm.x, Xmi = x02[c] - (double)cm.y;
+          X1r = 0.5 * (Xpr + Xmr) * invM;
+          X1i = 0.5 * (Xpi - Xmi) * invM;
+          X2r = 0.5 * (Xpi + Xmi) * invM;
+          X2i = -0.5 * (Xpr - Xmr) * invM;
+        }
+        if (flip[i]) {
+          X1i = -X1i;
+          X2i = -X2i;
+        }
+        double* o = static_cast<double*>(out);
+        if (out_kind == USFFT_OUT_MAG2) {
+          o[g1 * ldo + cc[i]] = X1r * X1r + X1i * X1i;
+          if (has2[c]) o[g2 * ldo + cc[i]] = X2r * X2r + X2i * X2i;
+        } else {
+          o[(cc[i] * G + g1) * 2] = X1r;
+          o[(cc[i] * G + g1) * 2 + 1] = X1i;
+          if (has2[c]) {
+            o[(cc[i] * G + g2) * 2] = X2r;
+            o[(cc[i] * G + g2) * 2 + 1] = X2i;
+          }
         }
       }
     }
