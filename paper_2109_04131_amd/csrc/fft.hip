@@ -99,18 +99,34 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
       v[2 * k + 1] = c[k];
     }
   } else {
+    // odd R in symmetric pairs: with s_q = v_q + v_{R-q}, d_q = v_q - v_{R-q}
+    // and t = 2 pi p q / R,  X_p = a_p - i b_p,  X_{R-p} = a_p + i b_p,
+    // a_p = v_0 + sum_q s_q cos t,  b_p = sum_q d_q sin t  (q, p <= (R-1)/2)
+    constexpr int H = (R - 1) / 2;
+    cplx<T> sp[H], dm[H];
+#pragma unroll
+    for (int q = 1; q <= H; ++q) {
+      sp[q - 1] = cadd(v[q], v[R - q]);
+      dm[q - 1] = csub(v[q], v[R - q]);
+    }
     cplx<T> o[R];
+    o[0] = v[0];
 #pragma unroll
-    for (int p = 0; p < R; ++p) {
-      cplx<T> acc = v[0];
+    for (int q = 0; q < H; ++q) o[0] = cadd(o[0], sp[q]);
 #pragma unroll
-      for (int q = 1; q < R; ++q) {
+    for (int p = 1; p <= H; ++p) {
+      cplx<T> a = v[0], b = {(T)0, (T)0};
+#pragma unroll
+      for (int q = 1; q <= H; ++q) {
         const int m = (p * q) % R;
-        const T c = (T)RootTab<R>::c[m], s = (T)RootTab<R>::s[m];
-        acc.x += v[q].x * c + v[q].y * s;
-        acc.y += v[q].y * c - v[q].x * s;
+        const T c = (T)RootTab<R>::c[m], sn = (T)RootTab<R>::s[m];
+        a.x += sp[q - 1].x * c;
+        a.y += sp[q - 1].y * c;
+        b.x += dm[q - 1].x * sn;
+        b.y += dm[q - 1].y * sn;
       }
-      o[p] = acc;
+      o[p] = {a.x + b.y, a.y - b.x};
+      o[R - p] = {a.x - b.y, a.y + b.x};
     }
 #pragma unroll
     for (int p = 0; p < R; ++p) v[p] = o[p];
