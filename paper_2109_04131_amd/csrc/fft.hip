@@ -148,16 +148,26 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
 // butterfly loads its twiddles and spectrum values once for all columns.
 // tw[0] = 1 exactly, so butterflies with j = 0 read their unit twiddles from
 // the table like the others (no branch around the loads).
-template <typename T, int R, int BLOCK, int COLS>
+// b / M for 0 <= b < 2^15: the float quotient with the hardware reciprocal is
+// within 0.01 of b / M, so its truncation is off by at most one, which the
+// remainder corrects
+__device__ __forceinline__ int div_small(int b, int M, float rM) {
+  const int q = (int)((float)b * rM);
+  const int r = b - q * M;
+  return r < 0 ? q - 1 : (r >= M ? q + 1 : q);
+}
+
+template <typename T, int R, int BLOCK, int COLS, bool MB>
 __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw,
                           const cplx<T>* __restrict__ mulB) {
   const int nb = L / R, ts = L / N;
+  const float rM = __builtin_amdgcn_rcpf((float)M);
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
-    const int blk = b / M, j = b - blk * M, base = blk * N + j;
+    const int blk = div_small(b, M, rM), j = b - blk * M, base = blk * N + j;
     cplx<T> w[R], bq[R];
 #pragma unroll
     for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
-    if (mulB) {
+    if constexpr (MB) {
 #pragma unroll
       for (int q = 0; q < R; ++q) bq[q] = mulB[base + q * M];
     }
@@ -172,7 +182,7 @@ __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
       for (int q = 0; q < R; ++q) {
         cplx<T> o = v[q];
         if (q > 0) o = cmul(o, w[q]);
-        if (mulB) o = conjc(cmul(o, bq[q]));
+        if constexpr (MB) o = conjc(cmul(o, bq[q]));
         bc[base + q * M] = o;
       }
     }
@@ -183,8 +193,9 @@ __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
 template <typename T, int R, int BLOCK, int COLS>
 __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw) {
   const int nb = L / R, ts = L / N;
+  const float rM = __builtin_amdgcn_rcpf((float)M);
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
-    const int blk = b / M, j = b - blk * M, base = blk * N + j;
+    const int blk = div_small(b, M, rM), j = b - blk * M, base = blk * N + j;
     cplx<T> w[R];
 #pragma unroll
     for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
@@ -214,14 +225,25 @@ __device__ void fft_dif(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, co
   int N = F.L;
   for (int s = 0; s < F.nrad; ++s) {
     const int R = F.radix[s], M = N / R;
-    const cplx<T>* mb = (s == F.nrad - 1) ? mulB : nullptr;
-    switch (R) {
-      case 2: dif_stage<T, 2, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
-      case 3: dif_stage<T, 3, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
-      case 4: dif_stage<T, 4, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
-      case 5: dif_stage<T, 5, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
-      case 7: dif_stage<T, 7, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
-      default: dif_stage<T, 8, BLOCK, COLS>(buf, F.L, N, M, tw, mb); break;
+    // the spectrum product is compiled only into the last stage
+    if (s == F.nrad - 1 && mulB) {
+      switch (R) {
+        case 2: dif_stage<T, 2, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
+        case 3: dif_stage<T, 3, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
+        case 4: dif_stage<T, 4, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
+        case 5: dif_stage<T, 5, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
+        case 7: dif_stage<T, 7, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
+        default: dif_stage<T, 8, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
+      }
+    } else {
+      switch (R) {
+        case 2: dif_stage<T, 2, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
+        case 3: dif_stage<T, 3, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
+        case 4: dif_stage<T, 4, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
+        case 5: dif_stage<T, 5, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
+        case 7: dif_stage<T, 7, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
+        default: dif_stage<T, 8, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
+      }
     }
     N = M;
   }
