@@ -53,6 +53,17 @@ struct RootTab<7> {
                                   -0.4338837391175581, -0.9749279121818236, -0.7818314824680298};
 };
 
+template <>
+struct RootTab<9> {
+  static constexpr double c[9] = {1.0, 0.766044443118978, 0.17364817766693036, -0.5, -0.9396926207859084, -0.9396926207859084, -0.5, 0.17364817766693036, 0.766044443118978};
+  static constexpr double s[9] = {0.0, 0.6427876096865394, 0.984807753012208, 0.8660254037844386, 0.3420201433256687, -0.3420201433256687, -0.8660254037844386, -0.984807753012208, -0.6427876096865394};
+};
+template <>
+struct RootTab<16> {
+  static constexpr double c[16] = {1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898, 0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867, -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898, 0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867};
+  static constexpr double s[16] = {0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867, 1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898, 0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867, -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898};
+};
+
 template <typename T>
 __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
@@ -71,6 +82,53 @@ __device__ __forceinline__ void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx
   a3 = csub(d02, d13);
 }
 
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cplx<T>* v);
+
+// forward DFT of length R = R1 R2 in registers (two register-level stages):
+// with n = n1 + R1 n2 and k = k2 + R2 k1,
+//   X_k = sum_n1 w_R1^(n1 k1) w_R^(n1 k2) sum_n2 v_(n1 + R1 n2) w_R2^(n2 k2)
+template <typename T, int R1, int R2>
+__device__ __forceinline__ void dft_comp(cplx<T>* v) {
+  constexpr int R = R1 * R2;
+  cplx<T> y[R1][R2];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) {
+    cplx<T> t[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) t[n2] = v[n1 + R1 * n2];
+    dft_small<T, R2>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) y[n1][k2] = t[k2];
+  }
+#pragma unroll
+  for (int n1 = 1; n1 < R1; ++n1)
+#pragma unroll
+    for (int k2 = 1; k2 < R2; ++k2) {
+      const int m = (n1 * k2) % R;
+      const cplx<T> a = y[n1][k2];
+      if (R % 4 == 0 && m == R / 4) {
+        y[n1][k2] = mul_mi(a);
+      } else if (R % 2 == 0 && m == R / 2) {
+        y[n1][k2] = {-a.x, -a.y};
+      } else if (R % 4 == 0 && m == 3 * R / 4) {
+        y[n1][k2] = {-a.y, a.x};
+      } else {
+        const T c = (T)RootTab<R>::c[m], sn = (T)RootTab<R>::s[m];
+        y[n1][k2] = {a.x * c + a.y * sn, a.y * c - a.x * sn};  // a exp(-2 pi i m / R)
+      }
+    }
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    cplx<T> t[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) t[n1] = y[n1][k2];
+    dft_small<T, R1>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) v[k2 + R2 * k1] = t[k1];
+  }
+}
+
 // forward DFT of length R on v[0..R), in place
 template <typename T, int R>
 __device__ __forceinline__ void dft_small(cplx<T>* v) {
@@ -80,6 +138,10 @@ __device__ __forceinline__ void dft_small(cplx<T>* v) {
     v[1] = csub(a, b);
   } else if constexpr (R == 4) {
     dft4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (R == 9) {
+    dft_comp<T, 3, 3>(v);
+  } else if constexpr (R == 16) {
+    dft_comp<T, 4, 4>(v);
   } else if constexpr (R == 8) {
     constexpr T h = (T)0.7071067811865476;
     cplx<T> b[4], c[4];
@@ -164,14 +226,21 @@ __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
   const float rM = __builtin_amdgcn_rcpf((float)M);
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
     const int blk = div_small(b, M, rM), j = b - blk * M, base = blk * N + j;
+    // twiddles held for all columns, except the float64 radices above 8
+    // (their registers would not fit), which read each one where it is used
+    constexpr bool WREG = sizeof(T) == 4 || R <= 8;
     cplx<T> w[R], bq[R];
+    if constexpr (WREG) {
 #pragma unroll
-    for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
+      for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
+    }
     if constexpr (MB) {
 #pragma unroll
       for (int q = 0; q < R; ++q) bq[q] = mulB[base + q * M];
     }
-#pragma unroll
+    // one column at a time: a radix-16 butterfly holds 16 values and 15
+    // twiddles, and unrolled columns would multiply the former
+#pragma unroll 1
     for (int c = 0; c < COLS; ++c) {
       cplx<T>* bc = buf + c * L;
       cplx<T> v[R];
@@ -181,7 +250,7 @@ __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         cplx<T> o = v[q];
-        if (q > 0) o = cmul(o, w[q]);
+        if (q > 0) o = cmul(o, WREG ? w[q] : tw[j * q * ts]);
         if constexpr (MB) o = conjc(cmul(o, bq[q]));
         bc[base + q * M] = o;
       }
@@ -196,17 +265,20 @@ __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
   const float rM = __builtin_amdgcn_rcpf((float)M);
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
     const int blk = div_small(b, M, rM), j = b - blk * M, base = blk * N + j;
+    constexpr bool WREG = sizeof(T) == 4 || R <= 8;  // as in dif_stage
     cplx<T> w[R];
+    if constexpr (WREG) {
 #pragma unroll
-    for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
-#pragma unroll
+      for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
+    }
+#pragma unroll 1
     for (int c = 0; c < COLS; ++c) {
       cplx<T>* bc = buf + c * L;
       cplx<T> v[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         cplx<T> a = bc[base + q * M];
-        if (q > 0) a = cmul(a, w[q]);
+        if (q > 0) a = cmul(a, WREG ? w[q] : tw[j * q * ts]);
         v[q] = a;
       }
       dft_small<T, R>(v);
@@ -217,10 +289,13 @@ __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
   __syncthreads();
 }
 
+// WIDE instantiations include the radix-9 and radix-16 stages of the float32
+// plans (the float64 transforms, whose plans have none, leave their registers
+// out).
 // Forward DIF over all stages; with mulB, the last stage multiplies by mulB
 // and conjugates (the forward half of a convolution, set up for the inverse
 // transform by conjugation).
-template <typename T, int BLOCK, int COLS>
+template <typename T, int BLOCK, int COLS, bool WIDE = sizeof(T) == 4>
 __device__ void fft_dif(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, const cplx<T>* mulB) {
   int N = F.L;
   for (int s = 0; s < F.nrad; ++s) {
@@ -233,6 +308,8 @@ __device__ void fft_dif(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, co
         case 4: dif_stage<T, 4, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
         case 5: dif_stage<T, 5, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
         case 7: dif_stage<T, 7, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
+        case 9: if constexpr (WIDE) dif_stage<T, 9, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
+        case 16: if constexpr (WIDE) dif_stage<T, 16, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
         default: dif_stage<T, 8, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
       }
     } else {
@@ -242,6 +319,8 @@ __device__ void fft_dif(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, co
         case 4: dif_stage<T, 4, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
         case 5: dif_stage<T, 5, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
         case 7: dif_stage<T, 7, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
+        case 9: if constexpr (WIDE) dif_stage<T, 9, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
+        case 16: if constexpr (WIDE) dif_stage<T, 16, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
         default: dif_stage<T, 8, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
       }
     }
@@ -250,7 +329,7 @@ __device__ void fft_dif(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, co
 }
 
 // Forward DIT over all stages in reverse order (digit-reversed in, natural out).
-template <typename T, int BLOCK, int COLS>
+template <typename T, int BLOCK, int COLS, bool WIDE = sizeof(T) == 4>
 __device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
   int Ns[24];
   int N = F.L;
@@ -266,6 +345,8 @@ __device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
       case 4: dit_stage<T, 4, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
       case 5: dit_stage<T, 5, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
       case 7: dit_stage<T, 7, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
+      case 9: if constexpr (WIDE) dit_stage<T, 9, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
+      case 16: if constexpr (WIDE) dit_stage<T, 16, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
       default: dit_stage<T, 8, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
     }
   }
@@ -291,7 +372,7 @@ __global__ __launch_bounds__(kFftBlock) void rader_setup_kernel(FftPlanDev F, in
     buf[j] = {c, s};
   }
   __syncthreads();
-  fft_dif<double, kFftBlock, 1>(buf, F, tw, nullptr);  // spectrum in the DIF (digit-reversed) order
+  fft_dif<double, kFftBlock, 1, true>(buf, F, tw, nullptr);  // spectrum in the DIF (digit-reversed) order
   const double invL = 1.0 / (double)L;
   for (int k = threadIdx.x; k < L; k += kFftBlock) {
     const cplx<double> v = {buf[k].x * invL, buf[k].y * invL};
@@ -356,13 +437,13 @@ void rader_free(RaderTables& T) {
   T = RaderTables{};
 }
 
-void rader_build(RaderTables& T, int M, hipStream_t st) {
+void rader_build(RaderTables& T, int M, bool wide, hipStream_t st) {
   USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL,
                 "lattice size " + std::to_string(M) + " is not a prime <= 19201 with 7-smooth M-1");
   void* mem = nullptr;
   USFFT_HIP(hipMalloc(&mem, rader_table_bytes(M)));
   try {
-    rader_build_at(T, M, mem, st);
+    rader_build_at(T, M, wide, mem, st);
   } catch (...) {
     (void)hipFree(mem);
     throw;
@@ -370,7 +451,7 @@ void rader_build(RaderTables& T, int M, hipStream_t st) {
   T.owned = true;
 }
 
-void rader_build_at(RaderTables& T, int M, void* mem, hipStream_t st) {
+void rader_build_at(RaderTables& T, int M, bool wide, void* mem, hipStream_t st) {
   USFFT_REQUIRE(lattice_size_ok(M), USFFT_EINVAL,
                 "lattice size " + std::to_string(M) + " is not a prime <= 19201 with 7-smooth M-1");
   const RaderLayout Lay(M);
@@ -390,24 +471,40 @@ void rader_build_at(RaderTables& T, int M, void* mem, hipStream_t st) {
     if (ok) break;
   }
   T.gen = gen;
-  // radix plan: 8s, then 4 / 2, then 3s, 5s, 7s
+  // radix plan, fewest stages: the 2^c2 factor in ceil(c2 / e) stages of
+  // radix 2^e or less (the exponent spread evenly), e = 4 for wide plans and
+  // 3 otherwise, then (wide) 9s and a 3, or 3s, then 5s and 7s (radices 9
+  // and 16 run two levels in registers)
   int r = L, c2 = 0;
   while (r % 2 == 0) {
     r /= 2;
     ++c2;
   }
   T.nrad = 0;
-  while (c2 >= 3) {
-    T.radix[T.nrad++] = 8;
-    c2 -= 3;
+  const int e2 = wide ? 4 : 3;
+  for (int ns2 = (c2 + e2 - 1) / e2, left = c2; ns2 > 0; --ns2) {
+    const int e = (left + ns2 - 1) / ns2;
+    T.radix[T.nrad++] = 1 << e;
+    left -= e;
   }
-  if (c2 == 2) T.radix[T.nrad++] = 4;
-  if (c2 == 1) T.radix[T.nrad++] = 2;
-  for (int p : {3, 5, 7})
-    while (r % p == 0) {
-      T.radix[T.nrad++] = p;
-      r /= p;
+  {
+    int c = 0;
+    while (r % 3 == 0) {
+      r /= 3;
+      ++c;
     }
+    if (wide)
+      for (; c >= 2; c -= 2) T.radix[T.nrad++] = 9;
+    for (; c >= 1; --c) T.radix[T.nrad++] = 3;
+  }
+  while (r % 5 == 0) {
+    T.radix[T.nrad++] = 5;
+    r /= 5;
+  }
+  while (r % 7 == 0) {
+    T.radix[T.nrad++] = 7;
+    r /= 7;
+  }
   std::vector<int32_t> perm(L), dlog(M, -1), outidx(M, 0);
   int64_t v = 1;
   for (int q = 0; q < L; ++q) {

@@ -148,8 +148,10 @@ struct LatItem {
 bool lattice_size_ok(int M);                    // prime, 7-smooth M - 1, M <= kMaxLattice
 inline int lattice_mmax_for(int fp32) { return fp32 ? kMaxLattice : kMaxLattice64; }
 size_t rader_table_bytes(int M);                        // bytes of one size's tables
-void rader_build(RaderTables& T, int M, hipStream_t st);  // allocates + fills (synchronous)
-void rader_build_at(RaderTables& T, int M, void* mem, hipStream_t st);  // fills mem (synchronous)
+// wide: the radix plan of float32 transforms (radices 9 and 16 run two levels
+// in registers); float64 transforms keep radices up to 8 (register budget)
+void rader_build(RaderTables& T, int M, bool wide, hipStream_t st);  // allocates + fills (synchronous)
+void rader_build_at(RaderTables& T, int M, bool wide, void* mem, hipStream_t st);  // fills mem (synchronous)
 void rader_free(RaderTables& T);                        // frees what rader_build allocated
 // Output column of candidate a: pos[a], or pos_base + a when pos is null.
 void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t G, int64_t ld, int64_t col0,

@@ -192,7 +192,7 @@ static const RaderTables& rader_for(usfft_plan_s* P, int M, hipStream_t st) {
   auto o = P->rader_off.find(M);
   USFFT_REQUIRE(o != P->rader_off.end(), USFFT_EINVAL, "lattice size " + std::to_string(M) + " has no table slot");
   RaderTables T;
-  rader_build_at(T, M, P->d_rader.as<char>() + o->second, st);
+  rader_build_at(T, M, P->par.precision == USFFT_FP32_REFINE, P->d_rader.as<char>() + o->second, st);
   return P->rader.emplace(M, T).first->second;
 }
 
@@ -2157,7 +2157,7 @@ usfft_status usfft_lattice_dft(const void* u_dev, int32_t u_fp32, int64_t G, int
                   "M is not an admissible lattice size for this precision");
     hipStream_t st = (hipStream_t)stream;
     RaderTables T;
-    rader_build(T, M, st);
+    rader_build(T, M, u_fp32 != 0, st);
     try {
       launch_lattice_dft(T, u_dev, u_fp32, G, ld, col0, bins_dev, pos_dev, 0, nb, out_kind, out_dev, ldo, st);
       USFFT_HIP(hipStreamSynchronize(st));
@@ -2189,7 +2189,7 @@ usfft_status usfft_lattice_coeffs(const void* u_dev, int32_t u_fp32, int64_t G, 
                        (int64_t)M, bins.as<int32_t>());
     USFFT_HIP(hipGetLastError());
     RaderTables T;
-    rader_build(T, M, st);
+    rader_build(T, M, u_fp32 != 0, st);
     try {
       launch_lattice_dft(T, u_dev, u_fp32, G, ld, col0, bins.as<int32_t>(), nullptr, 0, (int)n, USFFT_OUT_COMPLEX,
                          out_dev, G, st);
