@@ -383,6 +383,10 @@ def main():
                     help="also time one job each of the affine and lognormal models (0 = skip)")
     ap.add_argument("--eval-points", type=int, default=100000,
                     help="test parameters of the error measures of one job's result (0 = skip)")
+    ap.add_argument("--lognormal-theta", type=float, default=1e-3,
+                    help="relative threshold of the lognormal model job")
+    ap.add_argument("--lognormal-lattices", type=int, default=256,
+                    help="lattice attempts per family for the lognormal model job")
     ap.add_argument("--mesh", type=int, default=1,
                     help="also time one job on an unstructured mesh shaped like the paper's (0 = skip)")
     ap.add_argument("--parity", type=int, default=1,
@@ -497,15 +501,19 @@ def main():
         # 1e-3; its weakly preconditioned solves prefer float64 replacements
         # after a 1e-3 drop of the float32 residual, the others after 2e-4)
         res["models"] = {}
-        for name, mprob, th, irt, mmax in (("affine", W.affine_problem(64, 10, 32), 1e-5, 2e-4, 9601),
-                                           ("lognormal", W.lognormal_problem(64, 10, 32), 1e-3, 1e-3, 19201)):
+        # (--lognormal-theta 1e-5 with --lognormal-lattices 4096: the family
+        # grows to the candidate set, about 1.7e8 solves and 110 s a job)
+        for name, mprob, th, irt, mmax, lmax in (
+                ("affine", W.affine_problem(64, 10, 32), 1e-5, 2e-4, 9601, 256),
+                ("lognormal", W.lognormal_problem(64, 10, 32), args.lognormal_theta, 1e-3, 19201,
+                 args.lognormal_lattices)):
             try:
-                mplan = U.Plan(mprob, dict(par, theta=th, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=256,
+                mplan = U.Plan(mprob, dict(par, theta=th, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=lmax,
                                            inner_rtol=irt, lattice_mmax=mmax))
                 wall, lat, st, nI_m = run_path(U, mplan, args.seed, 1, 1)
                 sm = sum(x["samples"] for x in st)
                 res["models"][name] = {"samples_per_s": sm / wall, "job_s": wall, "samples": sm, "theta_rel": th,
-                                       "inner_rtol": irt, "lattice_mmax": mmax,
+                                       "inner_rtol": irt, "lattice_mmax": mmax, "lattice_max": lmax,
                                        "max_candidates": st[0]["max_candidates"],
                                        "pcg_iters_per_solve": sum(x["pcg_iterations"] for x in st) / max(1, sm),
                                        "detected_frequencies": nI_m}
