@@ -81,8 +81,10 @@ typedef struct usfft_server_s* usfft_server_t;
  *  (the discretisation of the paper's Sec. 4): mesh_nv vertices mesh_xy
  *  (nv x 2), mesh_nt triangles mesh_tri (nt x 3 vertex indices), mesh_boundary
  *  (nv bytes, nonzero = Dirichlet vertex).  T_G = the other vertices in vertex
- *  order; a at triangle centroids; float64 Jacobi-PCG per sample.  Limits:
- *  G <= 2048 inner vertices and 8 (nt + nnz + G) <= 150 KB (EINVAL beyond).
+ *  order; a at triangle centroids; float64 Jacobi-PCG per sample, with the
+ *  sample's matrix and vectors in LDS up to G = 2048 inner vertices and
+ *  8 (nt + nnz + G) <= 150 KB, else in a plan-owned global scratch of
+ *  8 (nnz + nt + 7 G) bytes per resident workgroup (two per CU).
  *  TRIG_POLY sampler (test functions of Theorem 1.1):
  *     u_g(y) = Re sum_{a<n_poly} c[a,g] exp(2 pi i poly_k[a].y),
  *  poly_c is n_poly x G x 2 doubles (re, im). */

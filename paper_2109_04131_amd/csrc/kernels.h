@@ -31,7 +31,7 @@ __host__ __device__ constexpr int row_tab_pitch(int n) { return n + 16; }
 
 // General triangulation (pcgmesh.hip): CSR pattern of the inner vertices,
 // per-entry (triangle, weight) contributions, load, basis at the centroids.
-constexpr int kMaxMeshRows = 2048;          // inner vertices the solver holds
+constexpr int kMaxMeshRows = 2048;          // inner vertices the LDS solver holds
 constexpr int64_t kMaxMeshLds = 150 << 10;  // LDS of coefficients, values, direction
 struct MeshDev {
   int G, nt, nnz;
@@ -45,9 +45,11 @@ struct MeshDev {
   const double* psi;  // d x nt: basis of term k at the centroid of T
 };
 int64_t mesh_lds_bytes(const MeshDev& M);
+bool mesh_fits_lds(const MeshDev& M);             // else the global-scratch solver runs
+int64_t mesh_scratch_doubles(const MeshDev& M);  // per workgroup, global-scratch solver
 int mesh_persistent_blocks(const MeshDev& M);
 void launch_pde_solve_mesh(const PdeDev& P, const MeshDev& M, const double* Y, int64_t ns, double rtol, int maxit,
-                           void* out, int out_fp32, int64_t ld, int64_t col0, int* iters, int blocks,
+                           void* out, int out_fp32, int64_t ld, int64_t col0, int* iters, int blocks, double* scr,
                            hipStream_t st);
 
 // ---- sampler.hip

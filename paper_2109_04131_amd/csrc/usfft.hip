@@ -529,7 +529,7 @@ static void solve_batch(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
   pde.raw = params ? 1 : 0;
   if (P->prob.sampler == USFFT_SAMPLER_PDE_MESH) {
     launch_pde_solve_mesh(pde, P->mesh, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
-                          P->mesh_blocks, st);
+                          P->mesh_blocks, mesh_fits_lds(P->mesh) ? nullptr : P->d_wscr.as<double>(), st);
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->dst) {
     const SolveSeg seg{pde, Y, U, ld, col0, 0, iters};
     if (P->fuse) {
@@ -1317,7 +1317,7 @@ static void build_mesh(usfft_plan_s* P, const usfft_problem* pb, const usfft_par
   int G = 0;
   for (int v = 0; v < nv; ++v)
     if (!pb->mesh_boundary[v]) gid[v] = G++;
-  USFFT_REQUIRE(G >= 1 && G <= kMaxMeshRows, USFFT_EINVAL, "the mesh needs 1..2048 inner vertices");
+  USFFT_REQUIRE(G >= 1, USFFT_EINVAL, "the mesh needs at least one inner vertex");
   std::vector<double> kgeo((size_t)nt * 9), area(nt), cx(nt), cy(nt);
   for (int t = 0; t < nt; ++t) {
     int v[3];
@@ -1425,9 +1425,10 @@ static void build_mesh(usfft_plan_s* P, const usfft_problem* pb, const usfft_par
   M.cw = P->m_cw.as<double>();
   M.load = P->m_load.as<double>();
   M.psi = P->m_psi.as<double>();
-  USFFT_REQUIRE(mesh_lds_bytes(M) <= kMaxMeshLds, USFFT_EINVAL,
-                "mesh too large for the general-mesh solver (8 (nt + nnz + G) > 150 KB)");
   P->mesh_blocks = mesh_persistent_blocks(M);
+  // meshes beyond the LDS solver keep each workgroup's state in a scratch slot
+  if (!mesh_fits_lds(M))
+    P->d_wscr.ensure(sizeof(double) * (size_t)mesh_scratch_doubles(M) * (size_t)P->mesh_blocks);
   P->pde.n = 0;
   P->pde.d = d;
   P->pde.a0 = pb->a0;

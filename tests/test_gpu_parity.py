@@ -691,10 +691,13 @@ def mesh_sampler(prob, delta=0.0):
 
 
 @pytest.mark.parametrize("mesh,d,model,prec", [((10, 11, 1), 4, 0, 0), ((10, 11, 2), 4, 1, 1), ((10, 11, 3), 4, 2, 0),
-                                               ((26, 27, 1), 10, 0, 0), ((26, 27, 1), 10, 0, 1)])
+                                               ((26, 27, 1), 10, 0, 0), ((26, 27, 1), 10, 0, 1),
+                                               ((30, 44, 6), 4, 0, 1), ((30, 46, 2), 4, 2, 0),
+                                               ((40, 55, 4), 6, 0, 0)])
 def test_mesh_solves_match_sparse_direct(lib, mesh, d, model, prec):
     # jittered Delaunay meshes (121 and 729 inner vertices, the latter shaped
-    # like the paper's mesh) against the oracle's sparse direct solves; the
+    # like the paper's mesh; 1936, 2116 and 3025, beyond the LDS solver, on
+    # the global-scratch one) against the oracle's sparse direct solves; the
     # mesh sampler solves in float64 in both precisions
     from oracle import periodization as OP
     prob = dict(W.mesh_problem(W.jittered_mesh(*mesh), d, 8), model=model)
@@ -718,6 +721,17 @@ def test_mesh_solves_match_sparse_direct(lib, mesh, d, model, prec):
     U1 = torch.zeros((S.G, 1), dtype=torch.float64, device="cuda")
     lib.sample(plan, dev(Y[7:8]), U1, 0, 1)
     assert np.array_equal(host(U1)[:, 0], Ug[7])
+
+
+def test_detect_on_a_large_mesh(lib):
+    # whole job on a mesh of 3025 inner vertices (the global-scratch solver):
+    # the oracle's sets and coefficients
+    prob = W.mesh_problem(W.jittered_mesh(40, 55, 8), 3, 6)
+    par = W.params(15, 1, 1e-3)
+    res, ref = run_both(lib, prob, par, 2, sampler=mesh_sampler(prob))
+    assert res.G == 3025
+    assert res.freqs().tolist() == ref.I.tolist()
+    assert np.abs(res.coeffs() - ref.C).max() <= 1e-10 * np.abs(ref.C).max()
 
 
 def test_uniform_mesh_through_the_mesh_sampler(lib):
@@ -762,8 +776,8 @@ def test_mesh_problems_are_checked(lib):
     bad_tri[0, 1] = bad_tri[0, 0]  # degenerate triangle
     bad_idx = m["mesh_tri"].copy()
     bad_idx[3, 2] = len(m["mesh_xy"])  # vertex out of range
-    big = W.jittered_mesh(50, 46, 1)  # 2116 inner vertices
-    for mesh in (dict(m, mesh_tri=bad_tri), dict(m, mesh_tri=bad_idx), big,
+    # (meshes beyond 2048 inner vertices are accepted: the global-scratch solver)
+    for mesh in (dict(m, mesh_tri=bad_tri), dict(m, mesh_tri=bad_idx),
                  dict(m, mesh_boundary=np.ones(len(m["mesh_xy"]), dtype=np.uint8))):
         with pytest.raises(lib.UsfftError) as e:
             lib.Plan(W.mesh_problem(mesh, 4, 8), par)
