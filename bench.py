@@ -536,6 +536,26 @@ def main():
                        "solver_ms_per_launch": sum(x["ms_sample"] for x in st) / max(1, sum(x["sample_launches"] for x in st)),
                        "detected_frequencies": nI_m}
         mplan.close()
+        # beyond the LDS solver: 3025 inner vertices, state in global scratch
+        # (one launch of 4096 seeded solves)
+        import numpy as np
+        bprob = W.mesh_problem(W.jittered_mesh(40, 55, 4), prob["d"], 32)
+        bplan = U.Plan(bprob, dict(par, precision=U.FP64, pcg_rtol=1e-12))
+        nsb = 4096
+        Yb = torch.from_numpy(np.random.default_rng(args.seed).random((nsb, prob["d"]))).cuda()
+        Ub = torch.empty((bplan.G, nsb), dtype=torch.float64, device="cuda")
+        itb = torch.zeros(nsb, dtype=torch.int32, device="cuda")
+        U.sample(bplan, Yb, Ub, 0, nsb, 0, itb)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U.sample(bplan, Yb, Ub, 0, nsb, 0, itb)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        res["mesh"]["large_mesh"] = {"workload": "jittered Delaunay mesh, 3025 inner vertices, 6208 triangles, d=10, "
+                                                 "4096 solves in one launch, float64 Jacobi-PCG, global scratch",
+                                     "samples_per_s": nsb / tb, "launch_ms": 1e3 * tb,
+                                     "pcg_iters_per_solve": float(itb.float().mean().item())}
+        bplan.close()
     if args.uneven:
         res["uneven_batch"] = uneven_run(U, args.seed, args.autotune)
     if args.serving_jobs > 0:
