@@ -311,6 +311,10 @@ usfft_status usfft_result_copy(usfft_result_t res, int32_t* freqs_host, double* 
  * Errors: EINVAL (no trace kept, stage out of range). */
 usfft_status usfft_result_trace(usfft_result_t res, int32_t stage, int64_t* n, int32_t* width,
                                 int64_t* n_cand, int32_t* set_host);
+/* Destroys a result.  Its device coefficient buffer goes back to a per-device
+ * pool of the library (up to 1 GiB in all) for later results, after a device
+ * synchronization (as a device free would do); beyond the pool it is freed.
+ * NULL is ignored. */
 void usfft_result_destroy(usfft_result_t res);
 
 /* Evaluation formula of Sec. 3.1 (eq. (3.1) with the model's inverse

@@ -169,6 +169,7 @@ struct usfft_plan_s {
 };
 
 struct usfft_result_s {
+  int dev = -1;  // device of C when it came from the result buffer pool
   int32_t d = 0;
   int64_t G = 0;
   int32_t model = USFFT_MODEL_PERIODIC;  // evaluation maps y back to the node t
@@ -186,6 +187,68 @@ struct usfft_result_s {
 namespace usfft {
 
 // ---------------------------------------------------------------- helpers
+// Coefficient buffers of destroyed results, kept per device for the next
+// results (at most kResultPoolBytes in all): a job then neither allocates its
+// output nor pays its predecessor's free.  A buffer is handed back after a
+// device synchronization, as a free would do, so no kernel still reads it.
+struct PooledBuf {
+  int dev;
+  void* p;
+  size_t bytes;
+};
+constexpr size_t kResultPoolBytes = size_t(1) << 30;
+static std::mutex g_rpool_mu;
+static std::vector<PooledBuf>* const g_rpool = new std::vector<PooledBuf>();  // never destroyed
+static size_t g_rpool_bytes = 0;
+
+static void result_buffer(usfft_result_s* R, size_t need) {
+  DevBuf& C = R->C;
+  if (C.borrowed || C.bytes >= need) {
+    C.ensure(need);
+    return;
+  }
+  int dev = 0;
+  USFFT_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_rpool_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_rpool->size(); ++i) {
+      const PooledBuf& b = (*g_rpool)[i];
+      if (b.dev == dev && b.bytes >= need && b.bytes <= 2 * need + (size_t(1) << 20) &&
+          (best < 0 || b.bytes < (*g_rpool)[best].bytes))
+        best = i;
+    }
+    if (best >= 0) {
+      C.release();
+      C.p = (*g_rpool)[best].p;
+      C.bytes = (*g_rpool)[best].bytes;
+      g_rpool_bytes -= C.bytes;
+      g_rpool->erase(g_rpool->begin() + best);
+      R->dev = dev;
+      return;
+    }
+  }
+  C.ensure(need);
+  R->dev = dev;
+}
+
+static void result_recycle(usfft_result_s* R) {
+  DevBuf& C = R->C;
+  if (!C.p || C.borrowed || R->dev < 0) return;
+  std::lock_guard<std::mutex> lk(g_rpool_mu);
+  if (g_rpool_bytes + C.bytes > kResultPoolBytes) return;  // the destructor frees it
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return;
+  if (cur != R->dev && hipSetDevice(R->dev) != hipSuccess) return;
+  const bool idle = hipDeviceSynchronize() == hipSuccess;
+  if (cur != R->dev) (void)hipSetDevice(cur);
+  if (!idle) return;
+  g_rpool->push_back(PooledBuf{R->dev, C.p, C.bytes});
+  g_rpool_bytes += C.bytes;
+  C.p = nullptr;
+  C.bytes = 0;
+}
+
 static const RaderTables& rader_for(usfft_plan_s* P, int M, hipStream_t st) {
   auto it = P->rader.find(M);
   if (it != P->rader.end()) return it->second;
@@ -907,7 +970,7 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
   }
   R->G = G;
   R->I.assign((size_t)nI * d, 0);
-  R->C.ensure(sizeof(double) * 2 * std::max<int64_t>(nI, 1) * G);
+  result_buffer(R, sizeof(double) * 2 * std::max<int64_t>(nI, 1) * G);
   if (nI > 0) {
     USFFT_HIP(hipMemcpyAsync(R->I.data(), P->Iprev.p, sizeof(int32_t) * nI * d, hipMemcpyDeviceToHost, st));
     P->assign.ensure(sizeof(int32_t) * nI);
@@ -1928,7 +1991,10 @@ usfft_status usfft_result_trace(usfft_result_t res, int32_t stage, int64_t* n, i
   });
 }
 
-void usfft_result_destroy(usfft_result_t res) { delete res; }
+void usfft_result_destroy(usfft_result_t res) {
+  if (res) usfft::result_recycle(res);
+  delete res;
+}
 
 namespace {
 // Points per chunk of an evaluation: the phase matrix (2 |I| rows) stays
