@@ -99,7 +99,8 @@ def test_solver_in_the_benchmark_launch_configuration(lib, prec):
         u1 = host(U1)[:, 0]
         assert np.array_equal(Ug[:, s], u1.astype(np.float32) if fp32 else u1), s
         ref = S.solve_one(Y[s])
-        assert np.linalg.norm(u1 - ref) <= (1e-10 if prec == 0 else 1e-9) * np.linalg.norm(ref), s
+        # the float64 contract (nodal 1e-11) at the benchmark's pcg_rtol
+        assert np.linalg.norm(u1 - ref) <= (1e-11 if prec == 0 else 1e-9) * np.linalg.norm(ref), s
 
 
 @pytest.mark.parametrize("G,M,fp32", [(3969, 9601, 0), (3969, 9601, 1), (16129, 4801, 1), (16129, 9601, 0),
