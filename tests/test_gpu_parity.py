@@ -321,7 +321,8 @@ def test_lattice_sizes_by_precision(lib):
 
 
 # ------------------------------------------------------------------ select
-@pytest.mark.parametrize("n,G,s", [(5, 3, 2), (100, 17, 10), (4500, 40, 200), (65, 9, 200), (1, 2, 1)])
+@pytest.mark.parametrize("n,G,s", [(5, 3, 2), (100, 17, 10), (4500, 40, 200), (65, 9, 200), (1, 2, 1),
+                                   (2000, 13, 200), (512, 5, 512), (1024, 7, 3)])
 def test_select_bit_exact(lib, n, G, s):
     g = np.random.default_rng(n + G)
     V = g.exponential(1.0, (n, G)) ** 4
@@ -347,6 +348,10 @@ def test_select_bit_exact(lib, n, G, s):
 @pytest.mark.parametrize("kind,n,G,s", [("low_bits", 4500, 12, 200), ("mid_bits", 4500, 7, 200),
                                          ("duplicates", 100, 9, 30), ("duplicates", 3000, 5, 200),
                                          ("one_binade", 700, 6, 64),
+                                         # more column lengths of the LDS-staged path
+                                         ("low_bits", 512, 9, 100), ("mid_bits", 513, 9, 100),
+                                         ("duplicates", 1024, 5, 200), ("one_binade", 1025, 6, 64),
+                                         ("low_bits", 2048, 5, 200), ("mid_bits", 2049, 5, 200),
                                          # columns longer than the LDS stage: keys read from global memory
                                          ("mid_bits", 9000, 4, 200), ("duplicates", 12000, 3, 500),
                                          ("one_binade", 8193, 3, 100)])
