@@ -158,10 +158,12 @@ typedef struct {
                               LDS-resident, 2 compact float32 (float32 edges
                               in LDS, float64 edges in global scratch for the
                               true residual; FP32_REFINE only)             */
-  int32_t precond;         /* USFFT_PRECOND_DST (fast-Poisson preconditioner,
-                              meshes with mesh_n <= 65) or USFFT_PRECOND_JACOBI;
-                              larger meshes always use the streaming Jacobi
-                              solver                                         */
+  int32_t precond;         /* USFFT_PRECOND_DST (fast-Poisson preconditioner:
+                              on chip for mesh_n <= 65, with the CG vectors
+                              in a global workspace and float64 arithmetic
+                              for 65 < mesh_n <= 129) or USFFT_PRECOND_JACOBI;
+                              meshes above 129 always use the streaming
+                              Jacobi solver                                  */
   int32_t trace;           /* nonzero: usfft_detect keeps the detected sets of
                               every increment (usfft_result_trace); costs one
                               small readback per increment                  */
@@ -190,7 +192,9 @@ typedef struct {
   int64_t solver_block;     /* workgroup size of the PDE solver              */
   int64_t solver_npt;       /* mesh nodes per thread of the PDE solver       */
   int64_t solver_kind;      /* 0 DST-preconditioned PCG, 1 Jacobi PCG on
-                               chip, 2 streaming Jacobi PCG, -1 no PDE solve */
+                               chip, 2 streaming Jacobi PCG, 3 general-mesh
+                               Jacobi PCG, 4 streaming DST-preconditioned
+                               PCG (65 < mesh_n <= 129), -1 no PDE solve */
   double theta_abs;         /* absolute threshold used                       */
   double ms_sample;         /* device time in the sampler kernels            */
   double ms_dft;            /* device time in DFT kernels                    */

@@ -78,6 +78,14 @@ void launch_pde_solve_stream(const PdeDev& P, const double* Y, int64_t ns, doubl
                              hipStream_t st);
 // ---- pcgdst.hip: DST-preconditioned solver for meshes with n - 1 <= 64
 int dst_padded(int n);             // MP = 32 or 64, 0 if the mesh is too large
+// streaming DST-preconditioned float64 PCG for 65 < mesh_n <= 129 (pcgdst.hip)
+bool dst_stream_ok(int n);
+int dst_stream_blocks();
+int64_t dst_stream_workspace_doubles(int n, int blocks);
+void dst_stream_tables_build(int n, void* frag, float* lam, hipStream_t st);  // MP = 128 fragments and eigenvalues
+void launch_pde_solve_dst_stream(const PdeDev& P, const double* Y, int64_t ns, double rtol, int maxit, void* out,
+                                 int out_fp32, int64_t ld, int64_t col0, int* iters, double* ws, int blocks,
+                                 const void* frag, const float* lam, hipStream_t st);
 int64_t dst_frag_bytes(int mp);    // S fragment table of one mesh size
 void dst_tables_build(int n, void* frag, float* lam, hipStream_t st);  // lam: MP floats
 // variant 0: edge grids and scaling in a global scratch slot per workgroup

@@ -118,10 +118,19 @@ __device__ __forceinline__ half8 load_h8(const _Float16* p) {
 // contiguous for the 4-wide reads, the padding spreads columns over banks.
 __host__ __device__ constexpr int dst_ilam_pitch(int mp) { return mp + 4; }
 
-template <int MP, typename T, bool TAB = false>
-__device__ __forceinline__ void dst_apply(const T (&r)[MP / 4], float sc, float (&z)[MP / 4],
-                                          const half8 (&sf)[(MP / 32) * (MP / 16)], _Float16* xa, _Float16* xb,
-                                          const float* lam, float shift, const float* ilam = nullptr) {
+// The transform fragments come from the lane's registers (an array of
+// (MP / 32) (MP / 16) half8) or, where they would not fit, from LDS
+// (FragLds: fragment f of the lane at p[64 f + lane]).
+struct FragLds {
+  const half8* p;
+  int lane;
+  __device__ __forceinline__ half8 operator[](int f) const { return p[f * 64 + lane]; }
+};
+
+template <int MP, typename T, bool TAB = false, typename SF>
+__device__ __forceinline__ void dst_apply(const T (&r)[MP / 4], float sc, float (&z)[MP / 4], const SF& sf,
+                                          _Float16* xa, _Float16* xb, const float* lam, float shift,
+                                          const float* ilam = nullptr) {
   constexpr int NT = MP / 16, KB = MP / 32, LDX = MP + 4;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
   half8 a[KB];
@@ -189,6 +198,70 @@ __device__ __forceinline__ void dst_apply(const T (&r)[MP / 4], float sc, float 
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(sf[kb * NT + t], b[kb], acc[t], 0, 0, 0);
 #pragma unroll
     for (int v = 0; v < 4; ++v) z[4 * t + v] = acc[t][v] * isc;
+  }
+}
+
+// dst_apply for grids whose fragments do not fit in registers (MP = 128):
+// the same four products with the fragments read from LDS where they are
+// used, the stages whose results go to LDS loop over their tiles without
+// unrolling, and the others take one tile at a time behind a scheduling
+// fence, so no more than one tile's fragments and accumulators are live.
+template <int MP>
+__device__ void dst_apply_big(const float (&r)[MP / 4], float sc, float (&z)[MP / 4], const FragLds& sf,
+                              _Float16* xa, _Float16* xb, const float* lam, float shift) {
+  constexpr int NT = MP / 16, KB = MP / 32, LDX = MP + 4;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, c16 = lane & 15;
+  half8 a[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[kb][j] = (_Float16)(r[4 * (2 * kb + (j >> 2)) + (j & 3)] * sc);
+  // T1 = R^T S: row strip w of T1
+#pragma unroll 1
+  for (int t = 0; t < NT; ++t) {
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[kb], sf[kb * NT + t], acc, 0, 0, 0);
+    store_h4(xa + (16 * t + c16) * LDX + 16 * w + 4 * q, acc);
+  }
+  __syncthreads();
+  // Wt = S T1: column strip w of Wt, then Yt = Lam o Wt, kept as the A
+  // operand of the next product
+  half8 b[KB];
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) b[kb] = load_h8(xa + (16 * w + c16) * LDX + 32 * kb + 4 * q);
+  const float lc = lam[16 * w + c16];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(sf[kb * NT + t], b[kb], acc, 0, 0, 0);
+    const floatx4 lr = *reinterpret_cast<const floatx4*>(lam + 16 * t + 4 * q);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a[t >> 1][4 * (t & 1) + v] = (_Float16)(acc[v] * __builtin_amdgcn_rcpf(lr[v] + lc + shift));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // T3 = Y S: row strip w of T3
+#pragma unroll 1
+  for (int t = 0; t < NT; ++t) {
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[kb], sf[kb * NT + t], acc, 0, 0, 0);
+    store_h4(xb + (16 * t + c16) * LDX + 16 * w + 4 * q, acc);
+  }
+  __syncthreads();
+  // Z = S T3: column strip w of Z, the node layout
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) b[kb] = load_h8(xb + (16 * w + c16) * LDX + 32 * kb + 4 * q);
+  const float isc = 1.0f / sc;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(sf[kb * NT + t], b[kb], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) z[4 * t + v] = acc[v] * isc;
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -865,6 +938,239 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
     }
     if (tid == 0 && sg.iters) sg.iters[sl] = conv ? it : -1;
   }
+}
+
+// ------------------------------------------ meshes 65 < mesh_n <= 129
+// One sample's state no longer fits a CU, so the CG vectors live in a
+// per-workgroup global workspace, as in the streaming Jacobi solver, while
+// the fast-Poisson preconditioner still runs on the matrix cores: MP = 128,
+// 512 threads, wave w owns the node strip of columns 16 w .. 16 w + 15 and a
+// lane 32 of its nodes in the accumulator layout (rows 16 t + 4 q + v), the
+// DST fragments (32 KB) and the exchange tiles in LDS.  Float64 CG with the
+// preconditioner M^-1 = D^-1/2 (L + c I)^-1 D^-1/2 (D = diag(A) / 4, c the
+// mean potential shift of the scaled operator, as in the on-chip kernels),
+// stopped on |b - A x| <= rtol |b| with b - A x the recursive residual.
+// Workspace per workgroup (doubles, pitch gp >= (n + 1)^2): x, r, q, D^-1/2
+// (node index g = row m + col), p (halo grid, zero border), eh, ev (edge
+// grids of fill_edges).
+constexpr int kDstStreamMP = 128;
+constexpr int kDstStreamArrays = 7;
+
+int64_t dst_stream_lds_bytes() {
+  constexpr int MP = kDstStreamMP;
+  return (int64_t)(MP / 32) * (MP / 16) * 64 * (int64_t)sizeof(half8) + 2 * (int64_t)MP * (MP + 4) * 2;
+}
+
+int64_t dst_stream_pitch(int n) { return ((int64_t)(n + 1) * (n + 1) + 63) / 64 * 64; }
+
+int64_t dst_stream_workspace_doubles(int n, int blocks) {
+  return dst_stream_pitch(n) * kDstStreamArrays * (int64_t)blocks;
+}
+
+__global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
+    PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, void* __restrict__ out, int out_fp32,
+    int64_t ld, int64_t col0, int* __restrict__ iters, double* __restrict__ ws, int64_t gp,
+    const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
+  constexpr int MP = kDstStreamMP, NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
+  extern __shared__ double lds[];
+  __shared__ double coef[kMaxD];
+  __shared__ double red0[2 * (BLOCK / kWave)];
+  __shared__ double red1[2 * (BLOCK / kWave)];
+  __shared__ __attribute__((aligned(16))) float slam[MP];
+  half8* sfl = reinterpret_cast<half8*>(lds);
+  _Float16* xa = reinterpret_cast<_Float16*>(sfl + KB * NT * 64);
+  _Float16* xb = xa + MP * LDX;
+  const int n = P.n, m = n - 1, P1 = n + 1;
+  double* x = ws + (size_t)blockIdx.x * kDstStreamArrays * gp;
+  double* r = x + gp;
+  double* q = r + gp;
+  double* dh = q + gp;
+  double* p = dh + gp;  // (n+1)^2 grid, zero halo
+  double* eh = p + gp;
+  double* ev = eh + gp;
+  const int lane = threadIdx.x & 63, qq = lane >> 4, c = 16 * (threadIdx.x >> 6) + (lane & 15);
+  for (int f = threadIdx.x; f < KB * NT * 64; f += BLOCK) sfl[f] = sfrag[f];
+  for (int i = threadIdx.x; i < MP; i += BLOCK) slam[i] = lamtab[i];
+  const FragLds sf{sfl, lane};
+  // node e of the lane: row 4 qq + o(e), o(e) = 16 (e >> 2) + (e & 3) (the
+  // accumulator layout), column c; its halo-grid index is bl + o P1 and its
+  // node index bg + o m, with wave-uniform offsets o P1, o m.  The bases pass
+  // through an empty asm in every loop, so the 32 nodes' addresses are not
+  // precomputed and held (they would not fit the registers).
+  auto bases = [&](int& bl, int& bg) {
+    bl = (4 * qq + 1) * P1 + c + 1;
+    bg = 4 * qq * m + c;
+    asm volatile("" : "+v"(bl), "+v"(bg));
+  };
+  auto ofs = [](int e) { return 16 * (e >> 2) + (e & 3); };
+  const bool colok = c < m;
+  for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
+    __syncthreads();  // the previous sample is done with coef and the workspace
+    load_coef(P, Y, s, coef);
+    for (int e = threadIdx.x; e < P1 * P1; e += BLOCK) p[e] = 0.0;
+    __syncthreads();
+    fill_edges<double>(P, coef, eh, ev);
+    __syncthreads();
+    int bl, bg;
+    // D^-1/2 and b
+    double bb = 0.0, rs = 0.0;
+    bases(bl, bg);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int o = ofs(e);
+      if (4 * qq + o < m && colok) {
+        const int l = bl + o * P1, g = bg + o * m;
+        dh[g] = 2.0 / sqrt(eh[l] + eh[l - 1] + ev[l] + ev[l - P1]);
+        x[g] = 0.0;
+        r[g] = P.h2;
+        bb += P.h2 * P.h2;
+      }
+    }
+    __syncthreads();  // D^-1/2 of the neighbours
+    // row sums of the scaled operator away from the boundary: the potential
+    // shift of the preconditioner
+    bases(bl, bg);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int o = ofs(e), row = 4 * qq + o;
+      if (row >= 1 && row <= m - 2 && c >= 1 && c <= m - 2) {
+        const int l = bl + o * P1, g = bg + o * m;
+        const double di = dh[g];
+        rs += 4.0 - di * (eh[l] * dh[g + 1] + eh[l - 1] * dh[g - 1] + ev[l] * dh[g + m] + ev[l - P1] * dh[g - m]);
+      }
+    }
+    block_sum2<BLOCK>(bb, rs, red0);
+    const float shift = potential_shift(rs, m);
+    const double stop = rtol * rtol * bb;
+    // z = M^-1 r into p (first direction), rz = r . M^-1 r
+    float rin[E], z[E];
+    double rr_s = 0.0;
+    bases(bl, bg);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int o = ofs(e);
+      const bool ok = 4 * qq + o < m && colok;
+      rin[e] = ok ? (float)(dh[bg + o * m] * P.h2) : 0.0f;
+      rr_s += (double)rin[e] * (double)rin[e];
+    }
+    rr_s = block_sum<BLOCK>(rr_s, red1);
+    dst_apply_big<MP>(rin, pow2_scale(rr_s), z, sf, xa, xb, slam, shift);
+    double rz = 0.0;
+    bases(bl, bg);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int o = ofs(e);
+      if (4 * qq + o < m && colok) {
+        p[bl + o * P1] = dh[bg + o * m] * (double)z[e];
+        rz += (double)rin[e] * (double)z[e];
+      }
+    }
+    rz = block_sum<BLOCK>(rz, red0);
+    int it = 0;
+    bool conv = !(bb > 0.0);
+    while (!conv && it < maxit) {
+      __syncthreads();  // every direction value is written
+      double pq = 0.0;
+      bases(bl, bg);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int o = ofs(e);
+        if (4 * qq + o < m && colok) {
+          const int l = bl + o * P1;
+          const double pc = p[l];
+          const double qv = eh[l] * (pc - p[l + 1]) + eh[l - 1] * (pc - p[l - 1]) + ev[l] * (pc - p[l + P1]) +
+                            ev[l - P1] * (pc - p[l - P1]);
+          q[bg + o * m] = qv;
+          pq += pc * qv;
+        }
+      }
+      pq = block_sum<BLOCK>(pq, red1);
+      const double alpha = rz / pq;
+      double rr = 0.0;
+      rr_s = 0.0;
+      bases(bl, bg);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int o = ofs(e);
+        const bool ok = 4 * qq + o < m && colok;
+        float ri = 0.0f;
+        if (ok) {
+          const int l = bl + o * P1, g = bg + o * m;
+          x[g] += alpha * p[l];
+          const double rg = r[g] - alpha * q[g];
+          r[g] = rg;
+          rr += rg * rg;
+          ri = (float)(dh[g] * rg);
+        }
+        rin[e] = ri;
+        rr_s += (double)ri * (double)ri;
+      }
+      block_sum2<BLOCK>(rr, rr_s, red0);
+      ++it;
+      if (rr <= stop) {
+        conv = true;
+        break;
+      }
+      dst_apply_big<MP>(rin, pow2_scale(rr_s), z, sf, xa, xb, slam, shift);
+      double rz2 = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) rz2 += (double)rin[e] * (double)z[e];  // r . M^-1 r (padding: rin = 0)
+      rz2 = block_sum<BLOCK>(rz2, red1);
+      const double beta = rz2 / rz;
+      rz = rz2;
+      bases(bl, bg);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int o = ofs(e);
+        if (4 * qq + o < m && colok) {
+          const int l = bl + o * P1;
+          p[l] = dh[bg + o * m] * (double)z[e] + beta * p[l];
+        }
+      }
+    }
+    __syncthreads();
+    bases(bl, bg);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int o = ofs(e);
+      if (4 * qq + o < m && colok) {
+        const int g = bg + o * m;
+        store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, x[g]);
+      }
+    }
+    if (threadIdx.x == 0 && iters) iters[s] = conv ? it : -1;
+  }
+}
+
+bool dst_stream_ok(int n) { return n - 1 > 64 && n - 1 <= kDstStreamMP; }
+
+int dst_stream_blocks() {
+  int cus = 0, dev = 0, per_cu = 0;
+  USFFT_HIP(hipGetDevice(&dev));
+  USFFT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  USFFT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(pcgdst_stream_kernel),
+                                                         4 * kDstStreamMP, (size_t)dst_stream_lds_bytes()));
+  return std::max(1, per_cu) * std::max(1, cus);
+}
+
+void dst_stream_tables_build(int n, void* frag, float* lam, hipStream_t st) {
+  const int mp = kDstStreamMP;
+  const int cnt = (mp / 32) * (mp / 16) * 64;
+  hipLaunchKernelGGL(dst_tables_kernel, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, n, mp,
+                     static_cast<half8*>(frag), lam);
+  USFFT_HIP(hipGetLastError());
+}
+
+void launch_pde_solve_dst_stream(const PdeDev& P, const double* Y, int64_t ns, double rtol, int maxit, void* out,
+                                 int out_fp32, int64_t ld, int64_t col0, int* iters, double* ws, int blocks,
+                                 const void* frag, const float* lam, hipStream_t st) {
+  if (ns <= 0) return;
+  USFFT_REQUIRE(dst_stream_ok(P.n), USFFT_EINVAL, "mesh outside the streaming DST solver's range");
+  const unsigned grid = (unsigned)std::min<int64_t>(ns, blocks);
+  hipLaunchKernelGGL(pcgdst_stream_kernel, dim3(grid), dim3(4 * kDstStreamMP), (size_t)dst_stream_lds_bytes(), st,
+                     P, Y, ns, rtol, maxit, out, out_fp32, ld, col0, iters, ws, dst_stream_pitch(P.n),
+                     static_cast<const half8*>(frag), lam);
+  USFFT_HIP(hipGetLastError());
 }
 
 static int dst_occupancy_of(const void* kernel, int mp, int64_t lds) {

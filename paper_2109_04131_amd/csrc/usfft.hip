@@ -142,6 +142,7 @@ struct usfft_plan_s {
   usfft::DevBuf famlog, famstate;
   int wblocks = 0;  // persistent workgroups of the float32 / DST solver
   bool streaming = false;  // mesh larger than the on-chip solvers hold
+  bool dst_stream = false; // 65 < mesh_n <= 129: streaming DST-preconditioned solver
   bool dst = false;        // DST-preconditioned solver
   int dst_variant = 1;     // 0: scratch in global memory, 1: LDS-resident, 2: compact float32
   usfft::PdeDev pde{};
@@ -603,6 +604,9 @@ static void solve_batch(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
                            par.pcg_rtol, par.pcg_maxit, par.inner_rtol, par.refine_every, out_fp32,
                            P->d_wscr.as<double>(), P->wblocks, P->d_sfrag.p, P->d_lam.as<float>(), st);
     }
+  } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->dst_stream) {
+    launch_pde_solve_dst_stream(pde, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
+                                P->d_stream.as<double>(), P->wblocks, P->d_sfrag.p, P->d_lam.as<float>(), st);
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->streaming) {
     launch_pde_solve_stream(pde, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
                             P->d_stream.as<double>(), kStreamBlocks, st);
@@ -1031,6 +1035,10 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     S.solver_block = 4 * dst_padded(P->prob.mesh_n);
     S.solver_npt = dst_padded(P->prob.mesh_n) / 4;
     S.solver_kind = 0;
+  } else if (pb.sampler == USFFT_SAMPLER_PDE && P->dst_stream) {
+    S.solver_block = 512;
+    S.solver_npt = 32;
+    S.solver_kind = 4;
   } else if (pb.sampler == USFFT_SAMPLER_PDE && !P->streaming) {
     int blk = 0, npt = 0;
     solver_config_shape(P->solver_cfg, &blk, &npt);
@@ -1669,6 +1677,17 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
       P->wblocks = dst_persistent_blocks(n, par->precision, P->dst_variant);
       P->d_wscr.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, dst_scratch_doubles(n, P->dst_variant,
                                                                                          P->wblocks)));
+    } else if (par->precond == USFFT_PRECOND_DST && dst_stream_ok(n)) {
+      // per-sample state exceeds one CU, the preconditioner still fits it:
+      // streaming float64 PCG with the fast-Poisson preconditioner (MP = 128)
+      P->dst_stream = true;
+      P->solver_cfg = -1;
+      P->d_sfrag.ensure((size_t)dst_frag_bytes(128));
+      P->d_lam.ensure(sizeof(float) * 128);
+      dst_stream_tables_build(n, P->d_sfrag.p, P->d_lam.as<float>(), nullptr);
+      USFFT_HIP(hipStreamSynchronize(nullptr));
+      P->wblocks = dst_stream_blocks();
+      P->d_stream.ensure(sizeof(double) * (size_t)dst_stream_workspace_doubles(n, P->wblocks));
     } else if (n > kMaxMesh) {
       // per-sample state exceeds one CU: streaming float64 solver
       P->streaming = true;
@@ -1683,8 +1702,9 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     } else {
       P->solver_cfg = autotune_solver(P.get());
     }
-    USFFT_REQUIRE(P->dst || P->streaming || P->solver_cfg >= 0, USFFT_EINVAL, "no solver shape for this mesh");
-    if (!P->streaming && !P->dst) {
+    USFFT_REQUIRE(P->dst || P->dst_stream || P->streaming || P->solver_cfg >= 0, USFFT_EINVAL,
+                  "no solver shape for this mesh");
+    if (!P->streaming && !P->dst && !P->dst_stream) {
       P->wblocks = persistent_blocks(P->solver_cfg, n);
       P->d_wscr.ensure(sizeof(double) * (size_t)edge_scratch_doubles(n, P->wblocks));
     }

@@ -125,20 +125,32 @@ def test_lattice_dft_full_size(lib, G, M, fp32):
     assert np.abs(Vg[cols].T - ref).max() <= 3 * tol * xmax ** 2
 
 
-@pytest.mark.parametrize("n,d,ns", [(96, 10, 6), (128, 20, 5), (256, 12, 2)])
-def test_streaming_solver_large_meshes(lib, n, d, ns):
+@pytest.mark.parametrize("n,d,ns,precond", [(96, 10, 6, 0), (128, 20, 5, 0), (66, 6, 4, 0), (129, 8, 4, 0),
+                                            (96, 10, 6, 1), (128, 20, 3, 1), (256, 12, 2, 0)])
+def test_streaming_solver_large_meshes(lib, n, d, ns, precond):
+    # meshes beyond one CU: 65 < n <= 129 with the fast-Poisson preconditioner
+    # (CG vectors in a global workspace, float64; n = 66 and 129 are the ends
+    # of its range, 129 fills the 128-point transform), Jacobi there on
+    # request and always above 129
     prob = W.pde_problem(n, d, 8)
-    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), pcg_rtol=1e-13, pcg_maxit=8000))
+    plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), pcg_rtol=1e-13, pcg_maxit=8000, precond=precond))
     Y = np.random.default_rng(n + d).random((ns, d))
     U = torch.zeros((plan.G, ns + 1), dtype=torch.float64, device="cuda")
     it = torch.zeros(ns, dtype=torch.int32, device="cuda")
     lib.sample(plan, dev(Y), U, 0, ns + 1, 1, it)
-    assert (host(it) > 0).all()
+    its = host(it)
+    assert (its > 0).all()
+    if precond == 0 and n <= 129:
+        assert its.max() <= 40, its
     Ug = host(U)
     S = ofem.PDESampler(n, prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
     for s in range(0, ns, max(1, ns // 2)):
         ref = S.solve_one(Y[s])
         assert np.linalg.norm(Ug[:, 1 + s] - ref) / np.linalg.norm(ref) <= 1e-11
+    # a sample's result does not depend on its batch
+    U1 = torch.zeros((plan.G, 1), dtype=torch.float64, device="cuda")
+    lib.sample(plan, dev(Y[ns - 1:ns]), U1, 0, 1)
+    assert np.array_equal(host(U1)[:, 0], Ug[:, ns])
 
 
 def test_errors_full_size_chunks_and_epilogue(lib):
