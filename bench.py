@@ -100,15 +100,16 @@ def serving_run(U, jobs, rate, seed, max_active):
 
 
 def uneven_run(U, seed, autotune):
-    """Twelve uneven jobs (meshes 32^2 and 64^2, d 8 or 10, boxes [-16,16]^d or
-    [-32,32]^d, s 100 or 200, relative threshold 1e-5, r = 5, float32 +
-    refinement) one after another, then together with their solver launches
-    fused (usfft_detect_batch); the results must agree bitwise."""
+    """Twelve uneven jobs (meshes 32^2, 64^2 and 128^2, d 8, 16 or 30, boxes
+    [-N,N]^d with N 16, 32 or 64, s 100, 300 or 500, relative threshold 1e-5,
+    r = 5, float32 + refinement, lattice sizes up to 19201) one after another,
+    then together with their solver launches fused (usfft_detect_batch); the
+    results must agree bitwise."""
     import numpy as np
     import workloads as W
-    jobs = W.uneven_batch(seed=seed, jobs=12, meshes=(32, 64), dims=(8, 10), Ns=(16, 32), ss=(100, 200))
-    pars = [dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=256, autotune=autotune)
-            for _, par, _ in jobs]
+    jobs = W.uneven_batch(seed=seed, jobs=12)
+    pars = [dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=4096, lattice_mmax=19201,
+                 autotune=autotune) for _, par, _ in jobs]
     plans = [U.Plan(prob, pa) for (prob, _, _), pa in zip(jobs, pars)]
     seeds = [sd for _, _, sd in jobs]
     for p, sd in zip(plans, seeds):  # warm-up: tables, tuning, workspaces
@@ -123,8 +124,8 @@ def uneven_run(U, seed, autotune):
     same = all(st == U.OK for st in sts) and all(
         np.array_equal(a.freqs(), b.freqs()) and np.array_equal(a.coeffs(), b.coeffs()) for a, b in zip(alone, res))
     samples = sum(a.stats["samples"] for a in alone)
-    return {"jobs": len(jobs), "workload": "meshes 32^2/64^2, d 8/10, N 16/32, s 100/200, rel. 1e-5, r = 5, "
-                                           "float32 + refinement, seed %d" % seed,
+    return {"jobs": len(jobs), "workload": "meshes 32^2/64^2/128^2, d 8/16/30, N 16/32/64, s 100/300/500, "
+                                           "rel. 1e-5, r = 5, float32 + refinement, seed %d" % seed,
             "one_by_one_s": t_alone, "fused_s": t_batch, "one_by_one_jobs_per_s": len(jobs) / t_alone,
             "fused_jobs_per_s": len(jobs) / t_batch, "fused_samples_per_s": samples / t_batch,
             "solver_launches": fs[0], "fused_launches": fs[1], "job_segments": fs[2],
@@ -395,6 +396,8 @@ def main():
                     help="use the committed tuning cache and time missing kernel choices (0 = built-in choices)")
     ap.add_argument("--tune-out", default="",
                     help="write the tuning cache (JSON) to this path at the end")
+    ap.add_argument("--large", type=int, default=1,
+                    help="also time one whole job at h = 1/128, d = 20, s = 500 (0 = skip)")
     ap.add_argument("--uneven", type=int, default=1,
                     help="also run twelve uneven jobs one by one and fused (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -556,6 +559,24 @@ def main():
                                      "samples_per_s": nsb / tb, "launch_ms": 1e3 * tb,
                                      "pcg_iters_per_solve": float(itb.float().mean().item())}
         bplan.close()
+    if args.large:
+        # one whole job on the h = 1/128 mesh (16129 nodes), d = 20, box
+        # [-64,64]^20, s = 500, relative threshold 1e-6, r = 5: lattice sizes
+        # up to 19201, so candidate sets of several thousand take families of
+        # up to six lattices; the solver is the streaming DST-preconditioned one
+        lprob, lpar = W.WORKLOADS["mesh128_d20"]
+        lplan = U.Plan(lprob, dict(lpar, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=4096,
+                                   lattice_mmax=19201, autotune=args.autotune))
+        wall, lat, st, nI_l = run_path(U, lplan, args.seed, 1, 0)
+        sm = sum(x["samples"] for x in st)
+        res["large"] = {"workload": "uniform mesh h=1/128 (16129 nodes), d=20, box [-64,64]^20, s=500, "
+                                    "rel. threshold 1e-6, r=5, float32 + float64 refinement, seed %d" % args.seed,
+                        "samples_per_s": sm / wall, "job_s": wall, "samples": sm, "detected_frequencies": nI_l,
+                        "lattices": st[0]["lattices"], "max_candidates": st[0]["max_candidates"],
+                        "ms_sample": st[0]["ms_sample"], "ms_dft": st[0]["ms_dft"], "ms_select": st[0]["ms_select"],
+                        "pcg_iters_per_solve": sum(x["pcg_iterations"] for x in st) / max(1, sm),
+                        "solver_kind": st[0]["solver_kind"]}
+        lplan.close()
     if args.uneven:
         res["uneven_batch"] = uneven_run(U, args.seed, args.autotune)
     if args.serving_jobs > 0:

@@ -237,8 +237,10 @@ int64_t usfft_plan_nodes(usfft_plan_t plan);
 
 /* Alg. 1, steps 1 to 3, on the device.  Output: the detected set I
  * (lexicographic) and the coefficients c_k(u_{x_g}), k in I, for every node
- * (Alg. 1 "Output").  Synchronises `stream`.  Errors: ENOCONV, ELATTICE,
- * ENOMEM, EHIP. */
+ * (Alg. 1 "Output").  Synchronises `stream`.  With the environment variable
+ * USFFT_LOG set to a non-zero value, one progress line per step and per
+ * increment t goes to stderr (candidates, lattices, samples, kept
+ * frequencies, elapsed seconds).  Errors: ENOCONV, ELATTICE, ENOMEM, EHIP. */
 usfft_status usfft_detect(usfft_plan_t plan, uint64_t seed, void* stream,
                           usfft_result_t* out);
 

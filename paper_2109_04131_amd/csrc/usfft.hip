@@ -9,6 +9,8 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <fstream>
@@ -694,6 +696,20 @@ static std::pair<int, int> rader_tuned_shape(usfft_plan_s* P, int Lmax, int ufp3
 
 // ---------------------------------------------------------------- Alg. 1
 // given: step 3 alone on the set given_I (host, given_n x d)
+// Progress lines on stderr, one per step of Alg. 1 and per increment, when
+// the environment sets USFFT_LOG to a non-zero value (read once per process).
+static bool progress_log() {
+  static const bool on = [] {
+    const char* v = std::getenv("USFFT_LOG");
+    return v != nullptr && v[0] != '\0' && v[0] != '0';
+  }();
+  return on;
+}
+
+static double seconds_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
 static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_s* R, bool given = false,
                    const int32_t* given_I = nullptr, int64_t given_n = 0) {
   const usfft_problem& pb = P->prob;
@@ -813,6 +829,13 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
                                st));
       check_conv();
       for (int t = 0; t < d; ++t) P->I1n[t] = cnt[t];
+      if (progress_log()) {
+        int64_t kept = 0;
+        for (int t = 0; t < d; ++t) kept += cnt[t];
+        std::fprintf(stderr, "usfft: step 1: %d lines, %lld samples, %lld frequencies kept, %.2f s\n", nl,
+                     (long long)ns, (long long)kept, seconds_since(t0));
+        std::fflush(stderr);
+      }
       if (par.trace) {
         for (int t = 0; t < d; ++t) {
           std::vector<int32_t> v((size_t)cnt[t]);
@@ -950,6 +973,12 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       check_conv();
       std::swap(P->Iprev, P->Jnext);
       nprev = cntI;
+      if (progress_log()) {
+        std::fprintf(stderr,
+                     "usfft: increment %d/%d: %lld candidates, %zu lattices, %lld samples x %d, %lld kept, %.2f s\n",
+                     t + 1, d, (long long)n, F.M.size(), (long long)ns, r_t, (long long)cntI, seconds_since(t0));
+        std::fflush(stderr);
+      }
       if (par.trace) {
         std::vector<int32_t> v((size_t)(cntI * w));
         if (cntI > 0) {
@@ -1027,6 +1056,11 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     tm.close(kTDft, e);
     S.dft_launches += 1;
     check_conv();
+    if (progress_log()) {
+      std::fprintf(stderr, "usfft: step 3: %lld frequencies, %zu lattices, %lld samples, %.2f s\n", (long long)nI,
+                   F.M.size(), (long long)ns, seconds_since(t0));
+      std::fflush(stderr);
+    }
   }
   USFFT_HIP(hipStreamSynchronize(st));
   S.samples = S.samples_step1 + S.samples_step2 + S.samples_step3;

@@ -1,5 +1,6 @@
 """usfft_detect_batch: uneven jobs (different meshes, d, boxes, s and
-precisions, plus an unfused trigonometric-polynomial job) run together with
+precisions, plus an unfused trigonometric-polynomial job and a 128^2-mesh
+job whose streaming solver keeps launches of its own) run together with
 their PDE solves fused into shared persistent launches; every job's result
 must equal the job run alone (each solve is independent of its batch)."""
 import numpy as np
@@ -13,7 +14,8 @@ pytestmark = pytest.mark.gpu
 def uneven_jobs():
     out = []
     for n, d, N, s, prec, seed in [(16, 4, 8, 20, 1, 1), (16, 3, 12, 30, 1, 2), (16, 6, 4, 20, 1, 3),
-                                   (33, 4, 8, 20, 0, 4), (33, 5, 8, 25, 0, 5), (64, 4, 8, 20, 1, 6)]:
+                                   (33, 4, 8, 20, 0, 4), (33, 5, 8, 25, 0, 5), (64, 4, 8, 20, 1, 6),
+                                   (128, 3, 8, 20, 1, 8)]:
         out.append((W.pde_problem(n, d, N), dict(W.params(s, 2, 1e-4), precision=prec), seed))
     K, P = W.trig_poly(7, 3, 8, 40, 21, cmin=1e-2)
     out.append((dict(sampler="poly", d=3, k_lo=[-8] * 3, k_hi=[8] * 3, poly_k=K, poly_c=P),
