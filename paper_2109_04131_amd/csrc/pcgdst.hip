@@ -950,16 +950,20 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
 // preconditioner M^-1 = D^-1/2 (L + c I)^-1 D^-1/2 (D = diag(A) / 4, c the
 // mean potential shift of the scaled operator, as in the on-chip kernels),
 // stopped on |b - A x| <= rtol |b| with b - A x the recursive residual.
-// Workspace per workgroup (doubles, pitch gp >= (n + 1)^2): x, r, q, D^-1/2
+// Workspace per workgroup (doubles, pitch gp >= (n + 1)^2): x, r, D^-1/2
 // (node index g = row m + col), p (halo grid, zero border), eh, ev (edge
-// grids of fill_edges).
+// grids of fill_edges), with D^-1/2 rounded to float (half a slot) after p;
+// A p stays in registers.
 constexpr int kDstStreamMP = 128;
-constexpr int kDstStreamArrays = 7;
+constexpr int kDstStreamArrays = 7;  // slots of gp doubles: x, r, D^-1/2, p, float D^-1/2 (half), eh, ev
 
 int64_t dst_stream_lds_bytes() {
   constexpr int MP = kDstStreamMP;
   return (int64_t)(MP / 32) * (MP / 16) * 64 * (int64_t)sizeof(half8) + 2 * (int64_t)MP * (MP + 4) * 2;
 }
+
+// the kernel's slices end at 6.5 slots (ev after the half slot of floats)
+static_assert(2 * kDstStreamArrays >= 13, "streaming DST workspace: 6.5 slots of gp doubles per workgroup");
 
 int64_t dst_stream_pitch(int n) { return ((int64_t)(n + 1) * (n + 1) + 63) / 64 * 64; }
 
@@ -983,10 +987,10 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
   const int n = P.n, m = n - 1, P1 = n + 1;
   double* x = ws + (size_t)blockIdx.x * kDstStreamArrays * gp;
   double* r = x + gp;
-  double* q = r + gp;
-  double* dh = q + gp;
+  double* dh = r + gp;  // written once per sample (the shift reads neighbours)
   double* p = dh + gp;  // (n+1)^2 grid, zero halo
-  double* eh = p + gp;
+  float* dhf = reinterpret_cast<float*>(p + gp);  // D^-1/2 rounded to float, node index
+  double* eh = p + gp + gp / 2;
   double* ev = eh + gp;
   const int lane = threadIdx.x & 63, qq = lane >> 4, c = 16 * (threadIdx.x >> 6) + (lane & 15);
   for (int f = threadIdx.x; f < KB * NT * 64; f += BLOCK) sfl[f] = sfrag[f];
@@ -1042,7 +1046,10 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
     block_sum2<BLOCK>(bb, rs, red0);
     const float shift = potential_shift(rs, m);
     const double stop = rtol * rtol * bb;
-    // z = M^-1 r into p (first direction), rz = r . M^-1 r
+    // z = M^-1 r into p (first direction), rz = r . M^-1 r.  The iteration
+    // reads D^-1/2 rounded to float: the scaled residual and the new
+    // direction both take these values, so M^-1 = D^-1/2 (L + cI)^-1 D^-1/2
+    // stays symmetric.
     float rin[E], z[E];
     double rr_s = 0.0;
     bases(bl, bg);
@@ -1050,7 +1057,12 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
     for (int e = 0; e < E; ++e) {
       const int o = ofs(e);
       const bool ok = 4 * qq + o < m && colok;
-      rin[e] = ok ? (float)(dh[bg + o * m] * P.h2) : 0.0f;
+      float df = 0.0f;
+      if (ok) {
+        df = (float)dh[bg + o * m];
+        dhf[bg + o * m] = df;
+      }
+      rin[e] = (float)((double)df * P.h2);
       rr_s += (double)rin[e] * (double)rin[e];
     }
     rr_s = block_sum<BLOCK>(rr_s, red1);
@@ -1061,31 +1073,38 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
     for (int e = 0; e < E; ++e) {
       const int o = ofs(e);
       if (4 * qq + o < m && colok) {
-        p[bl + o * P1] = dh[bg + o * m] * (double)z[e];
+        p[bl + o * P1] = (double)dhf[bg + o * m] * (double)z[e];
         rz += (double)rin[e] * (double)z[e];
       }
     }
     rz = block_sum<BLOCK>(rz, red0);
     int it = 0;
     bool conv = !(bb > 0.0);
+    // Per iteration the workspace sees the direction and both edge arrays
+    // (A p, kept in registers: its live range ends before the preconditioner's
+    // begins), the residual, then the iterate and the direction together: the
+    // step x += alpha p is taken when p is read for the next direction (and
+    // once more after the last iteration).
+    double alpha = 0.0;
     while (!conv && it < maxit) {
       __syncthreads();  // every direction value is written
-      double pq = 0.0;
+      double pq = 0.0, qa[E];
       bases(bl, bg);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int o = ofs(e);
+        qa[e] = 0.0;
         if (4 * qq + o < m && colok) {
           const int l = bl + o * P1;
           const double pc = p[l];
           const double qv = eh[l] * (pc - p[l + 1]) + eh[l - 1] * (pc - p[l - 1]) + ev[l] * (pc - p[l + P1]) +
                             ev[l - P1] * (pc - p[l - P1]);
-          q[bg + o * m] = qv;
+          qa[e] = qv;
           pq += pc * qv;
         }
       }
       pq = block_sum<BLOCK>(pq, red1);
-      const double alpha = rz / pq;
+      alpha = rz / pq;
       double rr = 0.0;
       rr_s = 0.0;
       bases(bl, bg);
@@ -1095,12 +1114,11 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
         const bool ok = 4 * qq + o < m && colok;
         float ri = 0.0f;
         if (ok) {
-          const int l = bl + o * P1, g = bg + o * m;
-          x[g] += alpha * p[l];
-          const double rg = r[g] - alpha * q[g];
+          const int g = bg + o * m;
+          const double rg = r[g] - alpha * qa[e];
           r[g] = rg;
           rr += rg * rg;
-          ri = (float)(dh[g] * rg);
+          ri = (float)((double)dhf[g] * rg);
         }
         rin[e] = ri;
         rr_s += (double)ri * (double)ri;
@@ -1123,19 +1141,24 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
       for (int e = 0; e < E; ++e) {
         const int o = ofs(e);
         if (4 * qq + o < m && colok) {
-          const int l = bl + o * P1;
-          p[l] = dh[bg + o * m] * (double)z[e] + beta * p[l];
+          const int l = bl + o * P1, g = bg + o * m;
+          const double pk = p[l];
+          x[g] += alpha * pk;
+          p[l] = (double)dhf[g] * (double)z[e] + beta * pk;
         }
       }
+      alpha = 0.0;
     }
-    __syncthreads();
+    // the last step (or none: alpha = 0 when the loop ended on maxit after a
+    // full iteration, or never ran), each lane on its own nodes
     bases(bl, bg);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int o = ofs(e);
       if (4 * qq + o < m && colok) {
         const int g = bg + o * m;
-        store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, x[g]);
+        const double xv = x[g] + alpha * p[bl + o * P1];
+        store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, xv);
       }
     }
     if (threadIdx.x == 0 && iters) iters[s] = conv ? it : -1;
