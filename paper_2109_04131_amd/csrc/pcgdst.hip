@@ -950,22 +950,40 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
 // preconditioner M^-1 = D^-1/2 (L + c I)^-1 D^-1/2 (D = diag(A) / 4, c the
 // mean potential shift of the scaled operator, as in the on-chip kernels),
 // stopped on |b - A x| <= rtol |b| with b - A x the recursive residual.
-// Workspace per workgroup (doubles, pitch gp >= (n + 1)^2): x, r, D^-1/2
-// (node index g = row m + col), p (halo grid, zero border), eh, ev (edge
-// grids of fill_edges), with D^-1/2 rounded to float (half a slot) after p;
-// A p stays in registers.
+// Workspace per workgroup, slots of gp doubles: x, r, D^-1/2 (node arrays,
+// index row NP + col, NP = m rounded up to 16), then one slot of floats: the
+// direction p (halo grid, zero border) and D^-1/2 rounded to float, then eh,
+// ev (edge grids); A p stays in registers.  The direction is stored in float:
+// A p and the step x += alpha p take the same rounded values, so the
+// recursive residual still tracks b - A x in float64, and only the search
+// direction (already built from an fp16 preconditioner) is perturbed.  The halo grids have MP + 2 rows of PP >= 144 doubles, node
+// (row, col) at (row + 1) PP + col + 16: every wave's 16-column strip starts
+// on a 128-byte line, and every lane's 32 nodes and their neighbours lie
+// inside the grid whether or not they are mesh nodes, so the passes load
+// unconditionally (values of padding nodes are discarded by selects, their
+// stores skipped) and issue a chunk's loads before its stores.  Before the
+// edges exist, the x and r slots hold the two triangle grids.
 constexpr int kDstStreamMP = 128;
-constexpr int kDstStreamArrays = 7;  // slots of gp doubles: x, r, D^-1/2, p, float D^-1/2 (half), eh, ev
+constexpr int kDstStreamArrays = 6;
+constexpr int kDstStreamOff = 15;  // halo index of node (row, col): (row + 1) PP + col + 1 + 15
+
+__host__ __device__ constexpr int dst_stream_rowpitch(int n) {
+  return ((n - 1 > kDstStreamMP - 1 ? n - 1 : kDstStreamMP - 1) + 17 + 15) / 16 * 16;
+}
 
 int64_t dst_stream_lds_bytes() {
   constexpr int MP = kDstStreamMP;
   return (int64_t)(MP / 32) * (MP / 16) * 64 * (int64_t)sizeof(half8) + 2 * (int64_t)MP * (MP + 4) * 2;
 }
 
-// the kernel's slices end at 6.5 slots (ev after the half slot of floats)
-static_assert(2 * kDstStreamArrays >= 13, "streaming DST workspace: 6.5 slots of gp doubles per workgroup");
-
-int64_t dst_stream_pitch(int n) { return ((int64_t)(n + 1) * (n + 1) + 63) / 64 * 64; }
+// a slot holds the halo grid (MP + 2 rows of PP) and the node arrays (MP
+// rows of at most MP), rounded to 512 bytes; the float slot holds the float
+// halo grid in its first half and the float node array in its second
+int64_t dst_stream_pitch(int n) {
+  const int64_t grid = (int64_t)(kDstStreamMP + 2) * dst_stream_rowpitch(n),
+                nodes = (int64_t)kDstStreamMP * kDstStreamMP;
+  return (std::max(grid, nodes) + 127) / 128 * 128;
+}
 
 int64_t dst_stream_workspace_doubles(int n, int blocks) {
   return dst_stream_pitch(n) * kDstStreamArrays * (int64_t)blocks;
@@ -976,6 +994,7 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
     int64_t ld, int64_t col0, int* __restrict__ iters, double* __restrict__ ws, int64_t gp,
     const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
   constexpr int MP = kDstStreamMP, NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
+  constexpr int EH = 8;  // nodes per load chunk of the update passes
   extern __shared__ double lds[];
   __shared__ double coef[kMaxD];
   __shared__ double red0[2 * (BLOCK / kWave)];
@@ -984,64 +1003,170 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
   half8* sfl = reinterpret_cast<half8*>(lds);
   _Float16* xa = reinterpret_cast<_Float16*>(sfl + KB * NT * 64);
   _Float16* xb = xa + MP * LDX;
-  const int n = P.n, m = n - 1, P1 = n + 1;
+  const int n = P.n, m = n - 1, PP = dst_stream_rowpitch(n);
+  // node array row pitch: m rounded up to 16 (a run-time value: with the
+  // constant 128 the compiler folds the 32 nodes' offsets and holds their
+  // addresses, 55 more registers)
+  const int NP = (m + 15) / 16 * 16;
   double* x = ws + (size_t)blockIdx.x * kDstStreamArrays * gp;
   double* r = x + gp;
   double* dh = r + gp;  // written once per sample (the shift reads neighbours)
-  double* p = dh + gp;  // (n+1)^2 grid, zero halo
-  float* dhf = reinterpret_cast<float*>(p + gp);  // D^-1/2 rounded to float, node index
-  double* eh = p + gp + gp / 2;
+  float* p = reinterpret_cast<float*>(dh + gp);  // direction, halo grid, zero border
+  float* dhf = p + gp;                            // D^-1/2 rounded to float, node index
+  double* eh = dh + 2 * gp;
   double* ev = eh + gp;
   const int lane = threadIdx.x & 63, qq = lane >> 4, c = 16 * (threadIdx.x >> 6) + (lane & 15);
   for (int f = threadIdx.x; f < KB * NT * 64; f += BLOCK) sfl[f] = sfrag[f];
   for (int i = threadIdx.x; i < MP; i += BLOCK) slam[i] = lamtab[i];
   const FragLds sf{sfl, lane};
   // node e of the lane: row 4 qq + o(e), o(e) = 16 (e >> 2) + (e & 3) (the
-  // accumulator layout), column c; its halo-grid index is bl + o P1 and its
-  // node index bg + o m, with wave-uniform offsets o P1, o m.  The bases pass
-  // through an empty asm in every loop, so the 32 nodes' addresses are not
-  // precomputed and held (they would not fit the registers).
+  // accumulator layout), column c; its halo-grid index is bl + o PP and its
+  // node-array index bg + o NP, with wave-uniform offsets o PP, o NP.  The
+  // bases pass through an empty asm in every loop, so the 32 nodes' addresses
+  // are not precomputed and held (they would not fit the registers).
   auto bases = [&](int& bl, int& bg) {
-    bl = (4 * qq + 1) * P1 + c + 1;
-    bg = 4 * qq * m + c;
+    bl = (4 * qq + 1) * PP + c + 1 + kDstStreamOff;
+    bg = 4 * qq * NP + c;
     asm volatile("" : "+v"(bl), "+v"(bg));
   };
   auto ofs = [](int e) { return 16 * (e >> 2) + (e & 3); };
   const bool colok = c < m;
+  auto node_ok = [&](int e) { return 4 * qq + ofs(e) < m && colok; };
+  // the direction grid's border (and its padding nodes) is never written
+  // afterwards: cleared once per launch
+  for (int e = threadIdx.x; e < (MP + 2) * PP; e += BLOCK) p[e] = 0.0f;
   for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
     __syncthreads();  // the previous sample is done with coef and the workspace
     load_coef(P, Y, s, coef);
-    for (int e = threadIdx.x; e < P1 * P1; e += BLOCK) p[e] = 0.0;
     __syncthreads();
-    fill_edges<double>(P, coef, eh, ev);
+    // the coefficient at the centroids of both triangles of every cell
+    // (eq. (1.2)), each evaluated once: triangle q of cell (ci, cj) into
+    // T_q[cj PP + ci] (T_0 in the x slot, T_1 in the r slot).  A lane takes
+    // one cell column and a wave-uniform block of rows, so the row factors are
+    // scalar loads and the column factor coef_k tab_k(ci) one vector load per
+    // term; the sum runs over k in order, as in the other solvers' assembly.
+    {
+      constexpr int RC = 16;  // rows per chunk
+      const int rpg = (n + 3) / 4;
+      const int cj0 = __builtin_amdgcn_readfirstlane((threadIdx.x >> 7) * rpg);
+      const int rows = min(rpg, n - cj0);
+      const bool logn = P.model == USFFT_MODEL_LOGNORMAL;
+#pragma unroll 1
+      for (int qt = 0; qt < 2; ++qt) {
+        double* T = qt == 0 ? x : r;
+#pragma unroll 1
+        for (int ci = threadIdx.x & 127; ci < n; ci += 128) {
+          const double* tx = P.tab + (size_t)qt * P.d * n + ci;
+#pragma unroll 1
+          for (int u0 = 0; u0 < rows; u0 += RC) {
+            const double* ty = P.tab + (size_t)(2 + qt) * P.d * n + cj0 + u0;
+            double acc[RC];
+#pragma unroll
+            for (int u = 0; u < RC; ++u) acc[u] = logn ? 0.0 : P.a0;
+#pragma unroll 4
+            for (int k = 0; k < P.d; ++k) {
+              const double w = coef[k] * tx[(size_t)k * n];
+              const double* tyk = ty + (size_t)k * n;
+#pragma unroll
+              for (int u = 0; u < RC; ++u)
+                if (u0 + u < rows) acc[u] += w * tyk[u];
+            }
+#pragma unroll
+            for (int u = 0; u < RC; ++u)
+              if (u0 + u < rows) T[(cj0 + u0 + u) * PP + ci] = logn ? P.a0 + exp(acc[u]) : acc[u];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // edge weights (mean of the two triangles beside the edge): horizontal
+    // edge (i, j)-(i + 1, j), 0 <= i < n, 1 <= j < n, and vertical edge
+    // (i, j)-(i, j + 1), 1 <= i < n, 0 <= j < n, at halo index j PP + i + 15;
+    // four edge pairs per thread and step, loads before stores
+    {
+      const int cnt = n * (n - 1);
+#pragma unroll 1
+      for (int e0 = threadIdx.x; e0 < cnt; e0 += 4 * BLOCK) {
+        double ta[4], tb[4], tc[4], td[4];
+        int ih[4], iv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u * BLOCK, cnt - 1);
+          const int i = e % n, j = e / n + 1;
+          ih[u] = j * PP + i;
+          iv[u] = i * PP + j;  // vertical edge (j, i)-(j, i + 1): i in [0, n), j in [1, n)
+          ta[u] = x[j * PP + i];
+          tb[u] = r[(j - 1) * PP + i];
+          tc[u] = r[i * PP + j];
+          td[u] = x[i * PP + j - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (e0 + u * BLOCK < cnt) {
+            eh[ih[u] + kDstStreamOff] = 0.5 * (ta[u] + tb[u]);
+            ev[iv[u] + kDstStreamOff] = 0.5 * (tc[u] + td[u]);
+          }
+      }
+    }
     __syncthreads();
     int bl, bg;
     // D^-1/2 and b
     double bb = 0.0, rs = 0.0;
     bases(bl, bg);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int o = ofs(e);
-      if (4 * qq + o < m && colok) {
-        const int l = bl + o * P1, g = bg + o * m;
-        dh[g] = 2.0 / sqrt(eh[l] + eh[l - 1] + ev[l] + ev[l - P1]);
-        x[g] = 0.0;
-        r[g] = P.h2;
-        bb += P.h2 * P.h2;
+    for (int h = 0; h < E; h += 8) {
+      double w4[8][4];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int l = bl + ofs(h + j) * PP;
+        w4[j][0] = eh[l];
+        w4[j][1] = eh[l - 1];
+        w4[j][2] = ev[l];
+        w4[j][3] = ev[l - PP];
       }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = h + j;
+        if (node_ok(e)) {
+          const int g = bg + ofs(e) * NP;
+          const double dg = 2.0 / sqrt(w4[j][0] + w4[j][1] + w4[j][2] + w4[j][3]);
+          dh[g] = dg;
+          dhf[g] = (float)dg;
+          x[g] = 0.0;
+          r[g] = P.h2;
+          bb += P.h2 * P.h2;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();  // D^-1/2 of the neighbours
     // row sums of the scaled operator away from the boundary: the potential
     // shift of the preconditioner
     bases(bl, bg);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int o = ofs(e), row = 4 * qq + o;
-      if (row >= 1 && row <= m - 2 && c >= 1 && c <= m - 2) {
-        const int l = bl + o * P1, g = bg + o * m;
-        const double di = dh[g];
-        rs += 4.0 - di * (eh[l] * dh[g + 1] + eh[l - 1] * dh[g - 1] + ev[l] * dh[g + m] + ev[l - P1] * dh[g - m]);
+    for (int h = 0; h < E; h += 4) {
+      double v9[4][9];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int o = ofs(h + j), l = bl + o * PP, g = bg + o * NP;
+        v9[j][0] = dh[g];
+        v9[j][1] = eh[l];
+        v9[j][2] = dh[g + 1];
+        v9[j][3] = eh[l - 1];
+        v9[j][4] = dh[g - 1];
+        v9[j][5] = ev[l];
+        v9[j][6] = dh[g + NP];
+        v9[j][7] = ev[l - PP];
+        v9[j][8] = dh[g - NP];
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = 4 * qq + ofs(h + j);
+        const double t = 4.0 - v9[j][0] * (v9[j][1] * v9[j][2] + v9[j][3] * v9[j][4] + v9[j][5] * v9[j][6] +
+                                           v9[j][7] * v9[j][8]);
+        rs += row >= 1 && row <= m - 2 && c >= 1 && c <= m - 2 ? t : 0.0;
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     block_sum2<BLOCK>(bb, rs, red0);
     const float shift = potential_shift(rs, m);
@@ -1054,28 +1179,35 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
     double rr_s = 0.0;
     bases(bl, bg);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int o = ofs(e);
-      const bool ok = 4 * qq + o < m && colok;
-      float df = 0.0f;
-      if (ok) {
-        df = (float)dh[bg + o * m];
-        dhf[bg + o * m] = df;
+    for (int h = 0; h < E; h += EH) {
+      float dv[EH];
+#pragma unroll
+      for (int j = 0; j < EH; ++j) dv[j] = dhf[bg + ofs(h + j) * NP];
+#pragma unroll
+      for (int j = 0; j < EH; ++j) {
+        const int e = h + j;
+        const float df = node_ok(e) ? dv[j] : 0.0f;
+        rin[e] = (float)((double)df * P.h2);
+        rr_s += (double)rin[e] * (double)rin[e];
       }
-      rin[e] = (float)((double)df * P.h2);
-      rr_s += (double)rin[e] * (double)rin[e];
+      __builtin_amdgcn_sched_barrier(0);
     }
     rr_s = block_sum<BLOCK>(rr_s, red1);
     dst_apply_big<MP>(rin, pow2_scale(rr_s), z, sf, xa, xb, slam, shift);
     double rz = 0.0;
     bases(bl, bg);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int o = ofs(e);
-      if (4 * qq + o < m && colok) {
-        p[bl + o * P1] = (double)dhf[bg + o * m] * (double)z[e];
-        rz += (double)rin[e] * (double)z[e];
+    for (int h = 0; h < E; h += EH) {
+      float dv[EH];
+#pragma unroll
+      for (int j = 0; j < EH; ++j) dv[j] = dhf[bg + ofs(h + j) * NP];
+#pragma unroll
+      for (int j = 0; j < EH; ++j) {
+        const int e = h + j;
+        if (node_ok(e)) p[bl + ofs(e) * PP] = (float)((double)dv[j] * (double)z[e]);
+        rz += (double)rin[e] * (double)z[e];  // padding: rin = 0
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
     rz = block_sum<BLOCK>(rz, red0);
     int it = 0;
@@ -1090,18 +1222,35 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
       __syncthreads();  // every direction value is written
       double pq = 0.0, qa[E];
       bases(bl, bg);
+      // A p by column groups of four rows (16 t + 4 qq + v, v = 0..3): their
+      // north and south neighbours are the group's own values, so a group
+      // takes 27 loads instead of 36
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int o = ofs(e);
-        qa[e] = 0.0;
-        if (4 * qq + o < m && colok) {
-          const int l = bl + o * P1;
-          const double pc = p[l];
-          const double qv = eh[l] * (pc - p[l + 1]) + eh[l - 1] * (pc - p[l - 1]) + ev[l] * (pc - p[l + P1]) +
-                            ev[l - P1] * (pc - p[l - P1]);
-          qa[e] = qv;
-          pq += pc * qv;
+      for (int t = 0; t < NT; ++t) {
+        const int l0 = bl + 16 * t * PP;
+        float pn[6], pe[4], pw[4];
+        double eo[4], ew[4], eu[4];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) pn[v] = p[l0 + (v - 1) * PP];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          pe[v] = p[l0 + v * PP + 1];
+          pw[v] = p[l0 + v * PP - 1];
+          eo[v] = eh[l0 + v * PP];
+          ew[v] = eh[l0 + v * PP - 1];
+          eu[v] = ev[l0 + v * PP];
         }
+        const double es = ev[l0 - PP];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double pc = pn[v + 1];
+          const double qv = eo[v] * (pc - (double)pe[v]) + ew[v] * (pc - (double)pw[v]) +
+                            eu[v] * (pc - (double)pn[v + 2]) + (v > 0 ? eu[v - 1] : es) * (pc - (double)pn[v]);
+          const bool ok = node_ok(4 * t + v);
+          qa[4 * t + v] = ok ? qv : 0.0;
+          pq += ok ? pc * qv : 0.0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
       pq = block_sum<BLOCK>(pq, red1);
       alpha = rz / pq;
@@ -1109,19 +1258,27 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
       rr_s = 0.0;
       bases(bl, bg);
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int o = ofs(e);
-        const bool ok = 4 * qq + o < m && colok;
-        float ri = 0.0f;
-        if (ok) {
-          const int g = bg + o * m;
-          const double rg = r[g] - alpha * qa[e];
-          r[g] = rg;
-          rr += rg * rg;
-          ri = (float)((double)dhf[g] * rg);
+      for (int h = 0; h < E; h += EH) {
+        double rv[EH];
+        float dv[EH];
+#pragma unroll
+        for (int j = 0; j < EH; ++j) {
+          const int g = bg + ofs(h + j) * NP;
+          rv[j] = r[g];
+          dv[j] = dhf[g];
         }
-        rin[e] = ri;
-        rr_s += (double)ri * (double)ri;
+#pragma unroll
+        for (int j = 0; j < EH; ++j) {
+          const int e = h + j;
+          const bool ok = node_ok(e);
+          const double rg = rv[j] - alpha * qa[e];
+          if (ok) r[bg + ofs(e) * NP] = rg;
+          rr += ok ? rg * rg : 0.0;
+          const float ri = ok ? (float)((double)dv[j] * rg) : 0.0f;
+          rin[e] = ri;
+          rr_s += (double)ri * (double)ri;
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
       block_sum2<BLOCK>(rr, rr_s, red0);
       ++it;
@@ -1138,28 +1295,47 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
       rz = rz2;
       bases(bl, bg);
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int o = ofs(e);
-        if (4 * qq + o < m && colok) {
-          const int l = bl + o * P1, g = bg + o * m;
-          const double pk = p[l];
-          x[g] += alpha * pk;
-          p[l] = (double)dhf[g] * (double)z[e] + beta * pk;
+      for (int h = 0; h < E; h += EH) {
+        double xv[EH];
+        float pv[EH], dv[EH];
+#pragma unroll
+        for (int j = 0; j < EH; ++j) {
+          const int o = ofs(h + j), g = bg + o * NP;
+          pv[j] = p[bl + o * PP];
+          xv[j] = x[g];
+          dv[j] = dhf[g];
         }
+#pragma unroll
+        for (int j = 0; j < EH; ++j) {
+          const int e = h + j, o = ofs(e);
+          if (node_ok(e)) {
+            x[bg + o * NP] = xv[j] + alpha * (double)pv[j];
+            p[bl + o * PP] = (float)((double)dv[j] * (double)z[e] + beta * (double)pv[j]);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
       alpha = 0.0;
     }
     // the last step (or none: alpha = 0 when the loop ended on maxit after a
     // full iteration, or never ran), each lane on its own nodes
     bases(bl, bg);
+    int bo = 4 * qq * m + c;  // output node index base (row m + col)
+    asm volatile("" : "+v"(bo));
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int o = ofs(e);
-      if (4 * qq + o < m && colok) {
-        const int g = bg + o * m;
-        const double xv = x[g] + alpha * p[bl + o * P1];
-        store_sample(out, out_fp32, (int64_t)g * ld + col0 + s, xv);
+    for (int h = 0; h < E; h += EH) {
+      double xv[EH];
+#pragma unroll
+      for (int j = 0; j < EH; ++j) {
+        const int o = ofs(h + j);
+        xv[j] = x[bg + o * NP] + alpha * (double)p[bl + o * PP];
       }
+#pragma unroll
+      for (int j = 0; j < EH; ++j) {
+        const int e = h + j;
+        if (node_ok(e)) store_sample(out, out_fp32, (int64_t)(bo + ofs(e) * m) * ld + col0 + s, xv[j]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (threadIdx.x == 0 && iters) iters[s] = conv ? it : -1;
   }
