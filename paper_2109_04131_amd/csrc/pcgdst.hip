@@ -971,9 +971,13 @@ __host__ __device__ constexpr int dst_stream_rowpitch(int n) {
   return ((n - 1 > kDstStreamMP - 1 ? n - 1 : kDstStreamMP - 1) + 17 + 15) / 16 * 16;
 }
 
+// LDS: the DST fragments, then either the two fp16 exchange tiles of the
+// preconditioner or (during the assembly) one padded row-factor table
+// (d rows of n + 16 doubles)
 int64_t dst_stream_lds_bytes() {
   constexpr int MP = kDstStreamMP;
-  return (int64_t)(MP / 32) * (MP / 16) * 64 * (int64_t)sizeof(half8) + 2 * (int64_t)MP * (MP + 4) * 2;
+  const int64_t tiles = 2 * (int64_t)MP * (MP + 4) * 2, table = (int64_t)kMaxD * row_tab_pitch(MP + 1) * 8;
+  return (int64_t)(MP / 32) * (MP / 16) * 64 * (int64_t)sizeof(half8) + std::max(tiles, table);
 }
 
 // a slot holds the halo grid (MP + 2 rows of PP) and the node arrays (MP
@@ -1045,67 +1049,98 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
     // one cell column and a wave-uniform block of rows, so the row factors are
     // scalar loads and the column factor coef_k tab_k(ci) one vector load per
     // term; the sum runs over k in order, as in the other solvers' assembly.
+    // The row factors come from the padded copies (rows of n + 16, row cj at
+    // 1 + cj), staged in LDS over the exchange tiles, so a chunk of 16 rows
+    // is one unconditional broadcast read even where it runs past the last
+    // row (those sums are not stored); the column factors are loaded eight
+    // terms at a time.
     {
       constexpr int RC = 16;  // rows per chunk
+      const int S = row_tab_pitch(n);
       const int rpg = (n + 3) / 4;
       const int cj0 = __builtin_amdgcn_readfirstlane((threadIdx.x >> 7) * rpg);
       const int rows = min(rpg, n - cj0);
       const bool logn = P.model == USFFT_MODEL_LOGNORMAL;
+      double* tyl = reinterpret_cast<double*>(xa);
 #pragma unroll 1
       for (int qt = 0; qt < 2; ++qt) {
         double* T = qt == 0 ? x : r;
+        __syncthreads();  // the previous table's readers are done
+        {
+          const double* tq = P.tab + (size_t)4 * P.d * n + (size_t)qt * P.d * S;
+          for (int e = threadIdx.x; e < P.d * S; e += BLOCK) tyl[e] = tq[e];
+        }
+        __syncthreads();
+        // column blocks of 128 with a wave-uniform trip count (a lane's
+        // column clamped for the loads, its stores skipped past the last)
 #pragma unroll 1
-        for (int ci = threadIdx.x & 127; ci < n; ci += 128) {
+        for (int cb = 0; cb < n; cb += 128) {
+          const int ci = min(cb + (int)(threadIdx.x & 127), n - 1);
+          const bool cok = cb + (int)(threadIdx.x & 127) < n;
           const double* tx = P.tab + (size_t)qt * P.d * n + ci;
 #pragma unroll 1
           for (int u0 = 0; u0 < rows; u0 += RC) {
-            const double* ty = P.tab + (size_t)(2 + qt) * P.d * n + cj0 + u0;
+            const double* ty = tyl + 1 + cj0 + u0;
             double acc[RC];
 #pragma unroll
             for (int u = 0; u < RC; ++u) acc[u] = logn ? 0.0 : P.a0;
-#pragma unroll 4
-            for (int k = 0; k < P.d; ++k) {
-              const double w = coef[k] * tx[(size_t)k * n];
-              const double* tyk = ty + (size_t)k * n;
+#pragma unroll 1
+            for (int k0 = 0; k0 < P.d; k0 += 8) {
+              double t8[8];
 #pragma unroll
-              for (int u = 0; u < RC; ++u)
-                if (u0 + u < rows) acc[u] += w * tyk[u];
+              for (int kk = 0; kk < 8; ++kk) t8[kk] = tx[(size_t)min(k0 + kk, P.d - 1) * n];
+#pragma unroll
+              for (int kk = 0; kk < 8; ++kk) {
+                if (k0 + kk < P.d) {
+                  const double w = coef[k0 + kk] * t8[kk];
+                  const double* tyk = ty + (k0 + kk) * S;
+#pragma unroll
+                  for (int u = 0; u < RC; ++u) acc[u] += w * tyk[u];
+                }
+              }
             }
 #pragma unroll
             for (int u = 0; u < RC; ++u)
-              if (u0 + u < rows) T[(cj0 + u0 + u) * PP + ci] = logn ? P.a0 + exp(acc[u]) : acc[u];
+              if (u0 + u < rows && cok) T[(cj0 + u0 + u) * PP + ci] = logn ? P.a0 + exp(acc[u]) : acc[u];
           }
         }
       }
     }
     __syncthreads();
-    // edge weights (mean of the two triangles beside the edge): horizontal
-    // edge (i, j)-(i + 1, j), 0 <= i < n, 1 <= j < n, and vertical edge
-    // (i, j)-(i, j + 1), 1 <= i < n, 0 <= j < n, at halo index j PP + i + 15;
-    // four edge pairs per thread and step, loads before stores
+    // edge weights (mean of the two triangles beside the edge), at halo
+    // index j PP + i + 15: horizontal edge (i, j)-(i + 1, j), 1 <= j < n,
+    // from T_0(i, j) and T_1(i, j - 1); vertical edge (i, j)-(i, j + 1),
+    // 1 <= i < n, from T_1(i, j) and T_0(i - 1, j).  A lane walks its column
+    // i through its block of rows (T_1 of the row below carried), eight rows
+    // of loads before their stores.
     {
-      const int cnt = n * (n - 1);
+      const int rpg = (n + 3) / 4;
+      const int j0 = (threadIdx.x >> 7) * rpg, j1 = min(j0 + rpg, n);
 #pragma unroll 1
-      for (int e0 = threadIdx.x; e0 < cnt; e0 += 4 * BLOCK) {
-        double ta[4], tb[4], tc[4], td[4];
-        int ih[4], iv[4];
+      for (int cb = 0; cb < n; cb += 128) {
+        const int i = min(cb + (int)(threadIdx.x & 127), n - 1);
+        const bool cok = cb + (int)(threadIdx.x & 127) < n;
+        double t1b = j0 > 0 ? r[(j0 - 1) * PP + i] : 0.0;
+#pragma unroll 1
+        for (int jb = j0; jb < j1; jb += 8) {
+          double a0[8], a1[8], aw[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = min(e0 + u * BLOCK, cnt - 1);
-          const int i = e % n, j = e / n + 1;
-          ih[u] = j * PP + i;
-          iv[u] = i * PP + j;  // vertical edge (j, i)-(j, i + 1): i in [0, n), j in [1, n)
-          ta[u] = x[j * PP + i];
-          tb[u] = r[(j - 1) * PP + i];
-          tc[u] = r[i * PP + j];
-          td[u] = x[i * PP + j - 1];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (e0 + u * BLOCK < cnt) {
-            eh[ih[u] + kDstStreamOff] = 0.5 * (ta[u] + tb[u]);
-            ev[iv[u] + kDstStreamOff] = 0.5 * (tc[u] + td[u]);
+          for (int u = 0; u < 8; ++u) {
+            const int j = min(jb + u, n - 1);
+            a0[u] = x[j * PP + i];
+            a1[u] = r[j * PP + i];
+            aw[u] = x[j * PP + max(i - 1, 0)];
           }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int j = jb + u;
+            if (j < j1 && cok) {
+              if (j >= 1) eh[j * PP + i + kDstStreamOff] = 0.5 * (a0[u] + t1b);
+              if (i >= 1) ev[j * PP + i + kDstStreamOff] = 0.5 * (a1[u] + aw[u]);
+            }
+            t1b = a1[u];
+          }
+        }
       }
     }
     __syncthreads();
