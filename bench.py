@@ -569,13 +569,20 @@ def main():
                                    lattice_mmax=19201, autotune=args.autotune))
         wall, lat, st, nI_l = run_path(U, lplan, args.seed, 1, 0)
         sm = sum(x["samples"] for x in st)
+        its = sum(x["pcg_iterations"] for x in st)
+        Gl = lplan.G
+        # streaming solver's workspace bytes: 68 per node and iteration (direction
+        # and edge grids, residual, iterate, float D^-1/2), about 140 per node and
+        # solve for the assembly, set-up and output
+        sbytes = 68.0 * Gl * its + 140.0 * Gl * sm
         res["large"] = {"workload": "uniform mesh h=1/128 (16129 nodes), d=20, box [-64,64]^20, s=500, "
                                     "rel. threshold 1e-6, r=5, float32 + float64 refinement, seed %d" % args.seed,
                         "samples_per_s": sm / wall, "job_s": wall, "samples": sm, "detected_frequencies": nI_l,
                         "lattices": st[0]["lattices"], "max_candidates": st[0]["max_candidates"],
                         "ms_sample": st[0]["ms_sample"], "ms_dft": st[0]["ms_dft"], "ms_select": st[0]["ms_select"],
-                        "pcg_iters_per_solve": sum(x["pcg_iterations"] for x in st) / max(1, sm),
-                        "solver_kind": st[0]["solver_kind"]}
+                        "pcg_iters_per_solve": its / max(1, sm), "solver_kind": st[0]["solver_kind"],
+                        "solver_GBps": sbytes / (1e-3 * st[0]["ms_sample"]) / 1e9,
+                        "solver_GBps_unit": "68 B per node-iteration + 140 B per node-solve over the sampler time"}
         lplan.close()
     if args.uneven:
         res["uneven_batch"] = uneven_run(U, args.seed, args.autotune)
