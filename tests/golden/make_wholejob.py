@@ -1,4 +1,5 @@
-"""Write the whole-job fixtures of the usFFT at two workloads with d = 10.
+"""Write the whole-job fixtures of the usFFT at d = 10 (h = 1/16, 1/64) and
+at d = 4 on the h = 1/128 mesh.
 
 Calls only the oracle (oracle/) and the seeded workload definitions
 (workloads/): Alg. 1 steps 1 to 3 in float64 on the CPU, with the solves
@@ -18,7 +19,7 @@ so the results do not depend on the split).  Stored per workload, seed 1:
   I, fam3_M, fam3_z        the output set and its step-3 family
   nodes, C_re, C_im, Cmax  coefficients at 64 nodes and max |c| over all nodes
   y_solve, u_solve         8 seeded sampling nodes and their solutions
-Usage: python tests/golden/make_wholejob.py [mesh64_d10|mesh16_d10 ...]
+Usage: python tests/golden/make_wholejob.py [mesh64_d10|mesh16_d10|mesh128_d4 ...]
 """
 import os
 import sys
@@ -109,5 +110,5 @@ def make(name, workers=None):
 
 
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or ["mesh16_d10", "mesh64_d10"]:
+    for nm in sys.argv[1:] or ["mesh16_d10", "mesh64_d10", "mesh128_d4"]:
         make(nm)

@@ -110,3 +110,34 @@ def test_lattice_coeffs_against_oracle(lib, M, fp32):
     ref = odft.dft_bins(Ud[:, 2:2 + M].T.astype(np.float32 if fp32 else np.float64), bins)
     err = np.abs(got - ref).max() / np.abs(ref).max()
     assert err <= (1e-6 if fp32 else 1e-12), err
+
+
+def test_progress_log_lines(lib):
+    """USFFT_LOG=1 (read once per process, so the job runs in a child): one
+    stderr line for step 1, one per increment t = 2 .. d and one for step 3,
+    each naming its counts; without the variable a job prints nothing."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import paper_2109_04131_amd as U, workloads as W\n"
+            "prob, par = W.WORKLOADS['cpu16_d4']\n"
+            "r = U.detect(U.Plan(prob, par), 1)\n"
+            "print('frequencies', r.n)\n")
+    d = W.WORKLOADS["cpu16_d4"][0]["d"]
+    runs = {}
+    for flag in ("1", "0"):
+        env = dict(os.environ, USFFT_LOG=flag)
+        print("child job cpu16_d4 seed 1, USFFT_LOG=%s" % flag, flush=True)
+        out = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                             timeout=150)
+        assert out.returncode == 0, out.stderr[-2000:]
+        runs[flag] = [ln for ln in out.stderr.splitlines() if ln.startswith("usfft: ")]
+        n = int(out.stdout.split()[-1])
+    lines = runs["1"]
+    assert len(lines) == d + 1, lines
+    assert lines[0].startswith("usfft: step 1: %d lines" % (d * W.WORKLOADS["cpu16_d4"][1]["r"]))
+    for t in range(2, d + 1):
+        assert lines[t - 1].startswith("usfft: increment %d/%d: " % (t, d)), lines[t - 1]
+    assert lines[-1].startswith("usfft: step 3: %d frequencies" % n)
+    assert runs["0"] == []

@@ -26,7 +26,7 @@ def host(t):
 
 
 @pytest.mark.parametrize("name,prec,tol,check", [("mesh64_d10", 0, 1e-11, 4), ("mesh64_d10", 1, 1e-9, 4),
-                                                 ("mesh128_d20", 0, 1e-11, 2)])
+                                                 ("mesh128_d20", 0, 1e-11, 2), ("mesh128_d20", 1, 1e-9, 2)])
 def test_first_detection_stage_full_size(lib, name, prec, tol, check):
     """Alg. 1 stage (t=1, i=1) at full size: nodes, solves, length-K DFT and
     selection through the ABI vs the oracle (solves sampled; DFT and selection

@@ -75,6 +75,9 @@ WORKLOADS = {
     "mesh16_d10": (pde_problem(16, 10, 32), params(200, 5, 1e-5)),
     # h = 1/128 (16129 nodes), d = 20, box [-64,64]^20, s = 500, rel. threshold 1e-6, r = 5
     "mesh128_d20": (pde_problem(128, 20, 64), params(500, 5, 1e-6)),
+    # a whole job on the h = 1/128 mesh small enough for the oracle (about
+    # 2200 solves): d = 4, box [-8,8]^4, s = 30, rel. threshold 1e-4, r = 2
+    "mesh128_d4": (pde_problem(128, 4, 8), params(30, 2, 1e-4)),
 }
 
 
