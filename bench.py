@@ -55,12 +55,20 @@ def run_path(U, plan, seed, steps, warmup):
     return wall, lat, stats, n
 
 
-def serving_run(U, jobs, rate, seed, max_active):
+SERVING_SMALL = dict(meshes=(16, 32, 64), dims=(4, 10), Ns=(16, 32), ss=(50, 200))
+# the serving configuration's ranges (meshes up to 128^2 here: above 129 points
+# per side only the Jacobi solver exists, hours for a d = 20 job)
+SERVING_WIDE = dict(meshes=(32, 64, 128), dims=(4, 30), Ns=(16, 64), ss=(50, 800))
+
+
+def serving_run(U, jobs, rate, seed, max_active, shape=SERVING_SMALL, burst=True):
     """Poisson arrivals (mean `rate` jobs/s) into the continuous-batching
-    server: jobs/s, p50/p99 latency and aggregate solves/s; then the same jobs
-    submitted at once (the server's capacity, every job queued from t = 0)."""
+    server: jobs/s, p50/p99 latency and aggregate solves/s; then (burst) the
+    same jobs submitted at once (the server's capacity, every job queued from
+    t = 0)."""
     import workloads as W
-    stream = W.serving_stream(seed=seed, rate=rate, jobs=jobs)
+    stream = W.serving_stream(seed=seed, rate=rate, jobs=jobs, **shape)
+    extra = {} if shape is SERVING_SMALL else dict(lattice_max=4096, lattice_mmax=19201)
 
     def run(arrivals):
         srv = U.Server(max_active=max_active)
@@ -70,7 +78,8 @@ def serving_run(U, jobs, rate, seed, max_active):
             delay = (t_arr if arrivals else 0.0) - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
-            ids.append(srv.submit(prob, dict(par, precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=256), s))
+            ids.append(srv.submit(prob, dict(par, **dict(dict(precision=U.FP32_REFINE, pcg_rtol=1e-12, lattice_max=256),
+                                                         **extra)), s))
         lat, qs, solves, failed, reused = [], [], 0, 0, 0
         for jid in ids:
             res, st, l, q, err = srv.poll(jid, wait=True)
@@ -87,16 +96,18 @@ def serving_run(U, jobs, rate, seed, max_active):
         return lat, qs, solves, failed, reused, wall
 
     lat, qs, solves, failed, reused, wall = run(True)
-    blat, bqs, bsolves, bfailed, breused, bwall = run(False)
-    return {"jobs": len(stream), "failed": failed, "arrival_rate_per_s": rate, "max_active": max_active,
-            "jobs_per_s": len(lat) / wall, "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
-            "p50_queue_s": pct(qs, 50), "samples_per_s": solves / wall, "wall_s": wall, "plans_reused": reused,
-            "stream": "Poisson(4/s) jobs, meshes 16^2..64^2, d 4..10, N 16..32, s 50..200, "
-                      "float32+refine, seed %d" % seed,
-            "burst": {"jobs_per_s": len(blat) / bwall, "p50_latency_s": pct(blat, 50),
-                      "p99_latency_s": pct(blat, 99), "samples_per_s": bsolves / bwall, "failed": bfailed,
-                      "plans_reused": breused,
-                      "note": "the same jobs submitted at once: capacity of the server"}}
+    out = {"jobs": len(stream), "failed": failed, "arrival_rate_per_s": rate, "max_active": max_active,
+           "jobs_per_s": len(lat) / wall, "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
+           "p50_queue_s": pct(qs, 50), "samples_per_s": solves / wall, "wall_s": wall, "plans_reused": reused,
+           "stream": "Poisson(%g/s) jobs, meshes %d^2..%d^2, d %d..%d, N %d..%d, s %d..%d, float32+refine, seed %d"
+                     % (rate, shape["meshes"][0], shape["meshes"][-1], shape["dims"][0], shape["dims"][1],
+                        shape["Ns"][0], shape["Ns"][1], shape["ss"][0], shape["ss"][1], seed)}
+    if burst:
+        blat, bqs, bsolves, bfailed, breused, bwall = run(False)
+        out["burst"] = {"jobs_per_s": len(blat) / bwall, "p50_latency_s": pct(blat, 50),
+                        "p99_latency_s": pct(blat, 99), "samples_per_s": bsolves / bwall, "failed": bfailed,
+                        "plans_reused": breused, "note": "the same jobs submitted at once: capacity of the server"}
+    return out
 
 
 def uneven_run(U, seed, autotune):
@@ -377,6 +388,9 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=16,
                     help="jobs of the Poisson serving run reported beside the headline (0 = skip)")
+    ap.add_argument("--serving-wide-jobs", type=int, default=16,
+                    help="jobs of a Poisson serving run over meshes 32^2..128^2, d 4..30, N 16..64, s 50..800 "
+                         "(0 = skip)")
     ap.add_argument("--solver-config", type=int, default=-1,
                     help="solver shape index (-1 = autotune); profiler runs pin one so that every "
                          "counter pass sees the same kernel")
@@ -588,6 +602,8 @@ def main():
         res["uneven_batch"] = uneven_run(U, args.seed, args.autotune)
     if args.serving_jobs > 0:
         res["serving"] = serving_run(U, args.serving_jobs, 4.0, args.seed, 4)
+    if args.serving_wide_jobs > 0:
+        res["serving_wide"] = serving_run(U, args.serving_wide_jobs, 4.0, args.seed, 4, SERVING_WIDE, burst=False)
     if args.parity and args.workload == "mesh64_d10":
         res["parity"] = parity_block(U, prob, par, args.seed, [("fp32_refine", U.FP32_REFINE), ("fp64", U.FP64)])
     if args.cpu_seconds > 0:

@@ -2448,7 +2448,14 @@ static uint64_t estimate_footprint(const usfft_problem* pb, const usfft_params* 
   const uint64_t J = 3ull * (uint64_t)pa->s_local * (uint64_t)std::min(kmax, 17);
   const uint64_t samples = std::min<uint64_t>(12 * J, 64ull * (uint64_t)pa->lattice_mmax) + (uint64_t)kmax;
   const uint64_t lines = G * (uint64_t)pb->d * (uint64_t)pa->r * (uint64_t)kmax * 8;  // step-1 spectra
-  return G * samples * ub + G * J * 8 + lines + samples * (uint64_t)pb->d * 8 + (64ull << 20);
+  // workspace of the streaming solvers (meshes above 65 points per side;
+  // 256 workgroups stand in for one per CU of the DST variant)
+  uint64_t solver = 0;
+  if (pb->sampler == USFFT_SAMPLER_PDE && pb->mesh_n - 1 > 64)
+    solver = 8ull * (uint64_t)(pa->precond == USFFT_PRECOND_DST && dst_stream_ok(pb->mesh_n)
+                                   ? dst_stream_workspace_doubles(pb->mesh_n, 256)
+                                   : stream_workspace_doubles(pb->mesh_n, kStreamBlocks));
+  return G * samples * ub + G * J * 8 + lines + samples * (uint64_t)pb->d * 8 + solver + (64ull << 20);
 }
 
 // Plans are pooled by everything that fixes their device tables: the
