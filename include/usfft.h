@@ -161,9 +161,12 @@ typedef struct {
   int32_t precond;         /* USFFT_PRECOND_DST (fast-Poisson preconditioner:
                               on chip for mesh_n <= 65, with the CG vectors
                               in a global workspace and float64 arithmetic
-                              for 65 < mesh_n <= 129) or USFFT_PRECOND_JACOBI;
-                              meshes above 129 always use the streaming
-                              Jacobi solver                                  */
+                              for 65 < mesh_n <= 129; for even
+                              129 < mesh_n <= 256 two-level, scaled Jacobi
+                              plus the fast-Poisson solve on the mesh of
+                              width 2h) or USFFT_PRECOND_JACOBI; odd meshes
+                              above 129 and meshes above 256 use the
+                              streaming Jacobi solver                        */
   int32_t trace;           /* nonzero: usfft_detect keeps the detected sets of
                               every increment (usfft_result_trace); costs one
                               small readback per increment                  */
@@ -194,7 +197,9 @@ typedef struct {
   int64_t solver_kind;      /* 0 DST-preconditioned PCG, 1 Jacobi PCG on
                                chip, 2 streaming Jacobi PCG, 3 general-mesh
                                Jacobi PCG, 4 streaming DST-preconditioned
-                               PCG (65 < mesh_n <= 129), -1 no PDE solve */
+                               PCG (65 < mesh_n <= 129), 5 streaming
+                               two-level PCG (even 129 < mesh_n <= 256),
+                               -1 no PDE solve                               */
   double theta_abs;         /* absolute threshold used                       */
   double ms_sample;         /* device time in the sampler kernels            */
   double ms_dft;            /* device time in DFT kernels                    */

@@ -86,6 +86,14 @@ void dst_stream_tables_build(int n, void* frag, float* lam, hipStream_t st);  //
 void launch_pde_solve_dst_stream(const PdeDev& P, const double* Y, int64_t ns, double rtol, int maxit, void* out,
                                  int out_fp32, int64_t ld, int64_t col0, int* iters, double* ws, int blocks,
                                  const void* frag, const float* lam, hipStream_t st);
+// streaming PCG with the two-level preconditioner (coarse DST at n / 2) for
+// even 129 < mesh_n <= 256 (pcgdst.hip)
+bool tl_stream_ok(int n);
+int tl_stream_blocks();
+int64_t tl_stream_workspace_doubles(int blocks);
+void launch_pde_solve_tl_stream(const PdeDev& P, const double* Y, int64_t ns, double rtol, int maxit, void* out,
+                                int out_fp32, int64_t ld, int64_t col0, int* iters, double* ws, int blocks,
+                                const void* frag, const float* lam, hipStream_t st);
 int64_t dst_frag_bytes(int mp);    // S fragment table of one mesh size
 void dst_tables_build(int n, void* frag, float* lam, hipStream_t st);  // lam: MP floats
 // variant 0: edge grids and scaling in a global scratch slot per workgroup

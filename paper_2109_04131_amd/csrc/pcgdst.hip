@@ -1376,6 +1376,436 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
   }
 }
 
+// ------------------------------------------ even meshes 129 < mesh_n <= 256
+// Beyond n = 129 the fast-Poisson preconditioner no longer fits a CU, so it
+// moves to the mesh of width 2h: an additive two-level preconditioner on the
+// scaled system, M^-1 = I / 4 + P (L_c + 4 c I)^-1 P^T, with P the bilinear
+// interpolation from the coarse mesh (n / 2, at most 127 inner points per
+// side) and L_c the unit 5-point Laplacian there, applied in LDS and registers
+// by the same fp16 matrix-core DST transform as above (MP = 128).  P^T L P is
+// close to L_c for smooth functions (the weights of P^T sum to 4 = (2h / h)^2),
+// and 4 c carries the mean potential shift of the scaled operator to the
+// coarse mesh.  The conjugate-gradient inner product splits as
+// r.z = r.r / 4 + (P^T r).z_c, so both parts come from values a pass already
+// holds.  Fine-mesh state streams from a per-workgroup workspace: seven slots
+// of gp doubles, halo grids of kTlRows x kTlPitch with vertex (i, j) at
+// j kTlPitch + i (x, r, A p, eh, ev in float64; the direction and the scaled
+// residual, then D^-1/2, in float).  The grids are sized for the largest
+// lane layout, so every pass loads without bounds branches; stores are
+// guarded.  The coarse correction goes to LDS as a float vertex grid
+// ((n / 2 + 1)^2, zero border) over the exchange tiles.
+constexpr int kTlRows = 258, kTlPitch = 272;
+
+int64_t tl_stream_pitch() { return ((int64_t)kTlRows * kTlPitch + 127) / 128 * 128; }
+
+int64_t tl_stream_workspace_doubles(int blocks) { return tl_stream_pitch() * 7 * (int64_t)blocks; }
+
+bool tl_stream_ok(int n) { return n - 1 > kDstStreamMP && n <= 2 * kDstStreamMP && n % 2 == 0; }
+
+__global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
+    PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, void* __restrict__ out, int out_fp32,
+    int64_t ld, int64_t col0, int* __restrict__ iters, double* __restrict__ ws, int64_t gp,
+    const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
+  constexpr int MP = kDstStreamMP, NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
+  constexpr int PF = kTlPitch;
+  extern __shared__ double lds[];
+  __shared__ double coef[kMaxD];
+  __shared__ double red0[2 * (BLOCK / kWave)];
+  __shared__ double red1[2 * (BLOCK / kWave)];
+  __shared__ __attribute__((aligned(16))) float slam[MP];
+  half8* sfl = reinterpret_cast<half8*>(lds);
+  _Float16* xa = reinterpret_cast<_Float16*>(sfl + KB * NT * 64);
+  _Float16* xb = xa + MP * LDX;
+  float* zc = reinterpret_cast<float*>(xa);  // coarse correction, vertex (A, B) at B PC + A
+  const int n = P.n, m = n - 1, nc = n / 2, mc = nc - 1, PC = nc + 1;
+  double* x = ws + (size_t)blockIdx.x * 7 * gp;
+  double* r = x + gp;
+  double* q = r + gp;  // A p (before the first iteration: D^-1/2 in float64)
+  double* eh = q + gp;
+  double* ev = eh + gp;
+  float* p = reinterpret_cast<float*>(ev + gp);
+  float* rt = p + gp;                                   // scaled residual D^-1/2 r
+  float* dhf = reinterpret_cast<float*>(ev + 2 * gp);  // D^-1/2 rounded to float
+  const int lane = threadIdx.x & 63, qq = lane >> 4, c = 16 * (threadIdx.x >> 6) + (lane & 15);
+  const int wv = threadIdx.x >> 6;
+  for (int f = threadIdx.x; f < KB * NT * 64; f += BLOCK) sfl[f] = sfrag[f];
+  for (int i = threadIdx.x; i < MP; i += BLOCK) slam[i] = lamtab[i];
+  const FragLds sf{sfl, lane};
+  auto ofs = [](int e) { return 16 * (e >> 2) + (e & 3); };
+  // fine passes: wave wv takes rows wv, wv + 8, ..., a lane the columns
+  // lane + 64 k; rows and columns up to 255 stay inside the halo grids
+  const int kc = (m + 63) / 64, tr = (m + 7) / 8;
+  // the halo grids' borders (and entries of no mesh node) are never written
+  // afterwards: cleared once per launch
+  for (int e = threadIdx.x; e < kTlRows * PF; e += BLOCK) {
+    p[e] = 0.0f;
+    rt[e] = 0.0f;
+  }
+  // P^T rt for the lane's coarse nodes (column c, rows 4 qq + o(e)): the
+  // 3 x 3 fine neighbourhood of fine vertex (2 (c + 1), 2 (row + 1)) with
+  // weights 1, 1/2, 1/4; the sum of squares returned
+  auto restrict_rt = [&](float (&rin)[E]) {
+    constexpr int RH = 2;  // coarse nodes per load chunk
+    double ss = 0.0;
+    int bR = (8 * qq + 2) * PF + 2 * (c + 1);
+    asm volatile("" : "+v"(bR));
+#pragma unroll
+    for (int h = 0; h < E; h += RH) {
+      float v[RH][9];
+#pragma unroll
+      for (int j = 0; j < RH; ++j) {
+        const int ci = bR + 2 * ofs(h + j) * PF;
+#pragma unroll
+        for (int dj = 0; dj < 3; ++dj)
+#pragma unroll
+          for (int di = 0; di < 3; ++di) v[j][3 * dj + di] = rt[ci + (dj - 1) * PF + di - 1];
+      }
+#pragma unroll
+      for (int j = 0; j < RH; ++j) {
+        const int e = h + j;
+        const bool ok = c < mc && 4 * qq + ofs(e) < mc;
+        const float val = v[j][4] + 0.5f * (v[j][1] + v[j][3] + v[j][5] + v[j][7]) +
+                          0.25f * (v[j][0] + v[j][2] + v[j][6] + v[j][8]);
+        rin[e] = ok ? val : 0.0f;
+        ss += (double)rin[e] * (double)rin[e];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    return ss;
+  };
+  // the coarse correction into the LDS vertex grid (after the transform is
+  // done with the tiles), zero on the border
+  auto coarse_grid = [&](const float (&z)[E]) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < PC; e += BLOCK) {
+      zc[e] = 0.0f;
+      zc[e * PC] = 0.0f;
+    }
+    int bz = (4 * qq + 1) * PC + c + 1;
+    asm volatile("" : "+v"(bz));
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int J = 4 * qq + ofs(e);
+      if (c <= mc && J <= mc) zc[bz + ofs(e) * PC] = (c < mc && J < mc) ? z[e] : 0.0f;
+    }
+    __syncthreads();
+  };
+  // p = D^-1/2 (rt / 4 + P z_c) + beta p on the fine mesh
+  auto direction = [&](double beta) {
+#pragma unroll 1
+    for (int t = 0; t < tr; ++t) {
+      const int j = wv + 8 * t;
+      float pv[4], rv[4], dv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int hf = (j + 1) * PF + lane + 64 * k + 1;
+        pv[k] = p[hf];
+        rv[k] = rt[hf];
+        dv[k] = dhf[hf];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = lane + 64 * k;
+        if (k < kc && i < m && j < m) {
+          const int iv = i + 1, jv = j + 1, a = iv >> 1, b = jv >> 1, fa = iv & 1, fb = jv & 1;
+          float pz = zc[b * PC + a];
+          if (fa) pz += zc[b * PC + a + 1];
+          if (fb) pz += zc[(b + 1) * PC + a];
+          if (fa && fb) pz += zc[(b + 1) * PC + a + 1];
+          pz *= (fa ? 0.5f : 1.0f) * (fb ? 0.5f : 1.0f);
+          const float zt = 0.25f * rv[k] + pz;
+          const double old = beta != 0.0 ? beta * (double)pv[k] : 0.0;  // the first direction ignores p
+          p[(j + 1) * PF + iv] = (float)((double)dv[k] * (double)zt + old);
+        }
+      }
+    }
+  };
+  for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
+    __syncthreads();  // the previous sample is done with coef and the workspace
+    load_coef(P, Y, s, coef);
+    __syncthreads();
+    // triangle values T_q[cj PF + ci] of eq. (1.2) (T_0 in the x slot, T_1 in
+    // the r slot), as in pcgdst_stream_kernel, the row factors read from the
+    // padded tables in global memory (a table of n + 16 rows per term would
+    // not fit LDS beside the fragments for every d)
+    {
+      constexpr int RC = 16;
+      const int S = row_tab_pitch(n);
+      const int rpg = (n + 3) / 4;
+      const int cj0 = __builtin_amdgcn_readfirstlane((threadIdx.x >> 7) * rpg);
+      const int rows = min(rpg, n - cj0);
+      const bool logn = P.model == USFFT_MODEL_LOGNORMAL;
+#pragma unroll 1
+      for (int qt = 0; qt < 2; ++qt) {
+        double* T = qt == 0 ? x : r;
+#pragma unroll 1
+        for (int cb = 0; cb < n; cb += 128) {
+          const int ci = min(cb + (int)(threadIdx.x & 127), n - 1);
+          const bool cok = cb + (int)(threadIdx.x & 127) < n;
+          const double* tx = P.tab + (size_t)qt * P.d * n + ci;
+#pragma unroll 1
+          for (int u0 = 0; u0 < rows; u0 += RC) {
+            const double* ty = P.tab + (size_t)4 * P.d * n + (size_t)qt * P.d * S + 1 + cj0 + u0;
+            double acc[RC];
+#pragma unroll
+            for (int u = 0; u < RC; ++u) acc[u] = logn ? 0.0 : P.a0;
+#pragma unroll 1
+            for (int k0 = 0; k0 < P.d; k0 += 8) {
+              double t8[8];
+#pragma unroll
+              for (int kk = 0; kk < 8; ++kk) t8[kk] = tx[(size_t)min(k0 + kk, P.d - 1) * n];
+#pragma unroll
+              for (int kk = 0; kk < 8; ++kk) {
+                if (k0 + kk < P.d) {
+                  const double w = coef[k0 + kk] * t8[kk];
+                  const double* tyk = ty + (size_t)(k0 + kk) * S;
+#pragma unroll
+                  for (int u = 0; u < RC; ++u) acc[u] += w * tyk[u];
+                }
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < RC; ++u)
+              if (u0 + u < rows && cok) T[(cj0 + u0 + u) * PF + ci] = logn ? P.a0 + exp(acc[u]) : acc[u];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // edge weights at vertex index j PF + i, as in pcgdst_stream_kernel
+    {
+      const int rpg = (n + 3) / 4;
+      const int j0 = (threadIdx.x >> 7) * rpg, j1 = min(j0 + rpg, n);
+#pragma unroll 1
+      for (int cb = 0; cb < n; cb += 128) {
+        const int i = min(cb + (int)(threadIdx.x & 127), n - 1);
+        const bool cok = cb + (int)(threadIdx.x & 127) < n;
+        double t1b = j0 > 0 ? r[(j0 - 1) * PF + i] : 0.0;
+#pragma unroll 1
+        for (int jb = j0; jb < j1; jb += 8) {
+          double a0[8], a1[8], aw[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int j = min(jb + u, n - 1);
+            a0[u] = x[j * PF + i];
+            a1[u] = r[j * PF + i];
+            aw[u] = x[j * PF + max(i - 1, 0)];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int j = jb + u;
+            if (j < j1 && cok) {
+              if (j >= 1) eh[j * PF + i] = 0.5 * (a0[u] + t1b);
+              if (i >= 1) ev[j * PF + i] = 0.5 * (a1[u] + aw[u]);
+            }
+            t1b = a1[u];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // D^-1/2 (float64 into the A p slot for the shift, float copy), x = 0,
+    // r = b, the scaled residual
+    double bb = 0.0, rtt = 0.0;
+#pragma unroll 1
+    for (int t = 0; t < tr; ++t) {
+      const int j = wv + 8 * t;
+      double w4[4][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int hf = (j + 1) * PF + lane + 64 * k + 1;
+        w4[k][0] = eh[hf];
+        w4[k][1] = eh[hf - 1];
+        w4[k][2] = ev[hf];
+        w4[k][3] = ev[hf - PF];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = lane + 64 * k;
+        if (k < kc && i < m && j < m) {
+          const int hf = (j + 1) * PF + i + 1;
+          const double dg = 2.0 / sqrt(w4[k][0] + w4[k][1] + w4[k][2] + w4[k][3]);
+          const float df = (float)dg;
+          q[hf] = dg;
+          dhf[hf] = df;
+          x[hf] = 0.0;
+          r[hf] = P.h2;
+          const float rv = (float)((double)df * P.h2);
+          rt[hf] = rv;
+          bb += P.h2 * P.h2;
+          rtt += (double)rv * (double)rv;
+        }
+      }
+    }
+    __syncthreads();  // D^-1/2 of the neighbours
+    // row sums of the scaled operator away from the boundary: the potential
+    // shift (as in the single-level solvers)
+    double rs = 0.0;
+#pragma unroll 1
+    for (int t = 0; t < tr; ++t) {
+      const int j = wv + 8 * t;
+      double v9[4][9];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int hf = (j + 1) * PF + lane + 64 * k + 1;
+        v9[k][0] = q[hf];
+        v9[k][1] = eh[hf];
+        v9[k][2] = q[hf + 1];
+        v9[k][3] = eh[hf - 1];
+        v9[k][4] = q[hf - 1];
+        v9[k][5] = ev[hf];
+        v9[k][6] = q[hf + PF];
+        v9[k][7] = ev[hf - PF];
+        v9[k][8] = q[hf - PF];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = lane + 64 * k;
+        const double tv = 4.0 - v9[k][0] * (v9[k][1] * v9[k][2] + v9[k][3] * v9[k][4] + v9[k][5] * v9[k][6] +
+                                            v9[k][7] * v9[k][8]);
+        rs += k < kc && i >= 1 && i <= m - 2 && j >= 1 && j <= m - 2 ? tv : 0.0;
+      }
+    }
+    block_sum2<BLOCK>(bb, rs, red0);
+    rtt = block_sum<BLOCK>(rtt, red1);
+    const float shift = 4.0f * potential_shift(rs, m);
+    const double stop = rtol * rtol * bb;
+    float rin[E], z[E];
+    double rr_s = restrict_rt(rin);
+    rr_s = block_sum<BLOCK>(rr_s, red0);
+    dst_apply_big<MP>(rin, pow2_scale(rr_s), z, sf, xa, xb, slam, shift);
+    double rzc = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) rzc += (double)rin[e] * (double)z[e];
+    rzc = block_sum<BLOCK>(rzc, red1);
+    double rz = 0.25 * rtt + rzc;
+    coarse_grid(z);
+    direction(0.0);
+    int it = 0;
+    bool conv = !(bb > 0.0);
+    while (!conv && it < maxit) {
+      __syncthreads();  // every direction value is written
+      double pq = 0.0;
+#pragma unroll 1
+      for (int t = 0; t < tr; ++t) {
+        const int j = wv + 8 * t;
+        float pc[4], pe[4], pw[4], pn[4], ps[4];
+        double eo[4], ew[4], eu[4], es[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int hf = (j + 1) * PF + lane + 64 * k + 1;
+          pc[k] = p[hf];
+          pe[k] = p[hf + 1];
+          pw[k] = p[hf - 1];
+          pn[k] = p[hf + PF];
+          ps[k] = p[hf - PF];
+          eo[k] = eh[hf];
+          ew[k] = eh[hf - 1];
+          eu[k] = ev[hf];
+          es[k] = ev[hf - PF];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int i = lane + 64 * k;
+          const double c0 = pc[k];
+          const double qv = eo[k] * (c0 - (double)pe[k]) + ew[k] * (c0 - (double)pw[k]) +
+                            eu[k] * (c0 - (double)pn[k]) + es[k] * (c0 - (double)ps[k]);
+          if (k < kc && i < m && j < m) {
+            q[(j + 1) * PF + i + 1] = qv;
+            pq += c0 * qv;
+          }
+        }
+      }
+      pq = block_sum<BLOCK>(pq, red0);
+      const double alpha = rz / pq;
+      double rr = 0.0;
+      rtt = 0.0;
+#pragma unroll 1
+      for (int t = 0; t < tr; ++t) {
+        const int j = wv + 8 * t;
+        double rv[4], qv[4], xv[4];
+        float pv[4], dv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int hf = (j + 1) * PF + lane + 64 * k + 1;
+          rv[k] = r[hf];
+          qv[k] = q[hf];
+          xv[k] = x[hf];
+          pv[k] = p[hf];
+          dv[k] = dhf[hf];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int i = lane + 64 * k;
+          if (k < kc && i < m && j < m) {
+            const int hf = (j + 1) * PF + i + 1;
+            const double rg = rv[k] - alpha * qv[k];
+            r[hf] = rg;
+            x[hf] = xv[k] + alpha * (double)pv[k];
+            const float rs1 = (float)((double)dv[k] * rg);
+            rt[hf] = rs1;
+            rr += rg * rg;
+            rtt += (double)rs1 * (double)rs1;
+          }
+        }
+      }
+      block_sum2<BLOCK>(rr, rtt, red1);
+      ++it;
+      if (rr <= stop) {
+        conv = true;
+        break;
+      }
+      rr_s = restrict_rt(rin);  // the barrier of block_sum2 ordered the rt writes
+      rr_s = block_sum<BLOCK>(rr_s, red0);
+      dst_apply_big<MP>(rin, pow2_scale(rr_s), z, sf, xa, xb, slam, shift);
+      rzc = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) rzc += (double)rin[e] * (double)z[e];
+      rzc = block_sum<BLOCK>(rzc, red1);
+      const double rz2 = 0.25 * rtt + rzc;
+      const double beta = rz2 / rz;
+      rz = rz2;
+      coarse_grid(z);
+      direction(beta);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int t = 0; t < tr; ++t) {
+      const int j = wv + 8 * t;
+      double xv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) xv[k] = x[(j + 1) * PF + lane + 64 * k + 1];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = lane + 64 * k;
+        if (k < kc && i < m && j < m) store_sample(out, out_fp32, (int64_t)(j * m + i) * ld + col0 + s, xv[k]);
+      }
+    }
+    if (threadIdx.x == 0 && iters) iters[s] = conv ? it : -1;
+  }
+}
+
+int tl_stream_blocks() {
+  int cus = 0, dev = 0, per_cu = 0;
+  USFFT_HIP(hipGetDevice(&dev));
+  USFFT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  USFFT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(pcgtl_stream_kernel),
+                                                         4 * kDstStreamMP, (size_t)dst_stream_lds_bytes()));
+  return std::max(1, per_cu) * std::max(1, cus);
+}
+
+void launch_pde_solve_tl_stream(const PdeDev& P, const double* Y, int64_t ns, double rtol, int maxit, void* out,
+                                int out_fp32, int64_t ld, int64_t col0, int* iters, double* ws, int blocks,
+                                const void* frag, const float* lam, hipStream_t st) {
+  if (ns <= 0) return;
+  USFFT_REQUIRE(tl_stream_ok(P.n), USFFT_EINVAL, "mesh outside the two-level streaming solver's range");
+  const unsigned grid = (unsigned)std::min<int64_t>(ns, blocks);
+  hipLaunchKernelGGL(pcgtl_stream_kernel, dim3(grid), dim3(4 * kDstStreamMP), (size_t)dst_stream_lds_bytes(), st,
+                     P, Y, ns, rtol, maxit, out, out_fp32, ld, col0, iters, ws, tl_stream_pitch(),
+                     static_cast<const half8*>(frag), lam);
+  USFFT_HIP(hipGetLastError());
+}
+
 bool dst_stream_ok(int n) { return n - 1 > 64 && n - 1 <= kDstStreamMP; }
 
 int dst_stream_blocks() {

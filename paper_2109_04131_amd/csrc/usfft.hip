@@ -145,6 +145,7 @@ struct usfft_plan_s {
   int wblocks = 0;  // persistent workgroups of the float32 / DST solver
   bool streaming = false;  // mesh larger than the on-chip solvers hold
   bool dst_stream = false; // 65 < mesh_n <= 129: streaming DST-preconditioned solver
+  bool tl_stream = false;  // even 129 < mesh_n <= 256: streaming two-level solver
   bool dst = false;        // DST-preconditioned solver
   int dst_variant = 1;     // 0: scratch in global memory, 1: LDS-resident, 2: compact float32
   usfft::PdeDev pde{};
@@ -606,6 +607,9 @@ static void solve_batch(usfft_plan_s* P, const double* Y, int64_t ns, void* U, i
                            par.pcg_rtol, par.pcg_maxit, par.inner_rtol, par.refine_every, out_fp32,
                            P->d_wscr.as<double>(), P->wblocks, P->d_sfrag.p, P->d_lam.as<float>(), st);
     }
+  } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->tl_stream) {
+    launch_pde_solve_tl_stream(pde, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
+                               P->d_stream.as<double>(), P->wblocks, P->d_sfrag.p, P->d_lam.as<float>(), st);
   } else if (P->prob.sampler == USFFT_SAMPLER_PDE && P->dst_stream) {
     launch_pde_solve_dst_stream(pde, Y, ns, par.pcg_rtol, par.pcg_maxit, U, out_fp32, ld, col0, iters,
                                 P->d_stream.as<double>(), P->wblocks, P->d_sfrag.p, P->d_lam.as<float>(), st);
@@ -1073,6 +1077,10 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     S.solver_block = 512;
     S.solver_npt = 32;
     S.solver_kind = 4;
+  } else if (pb.sampler == USFFT_SAMPLER_PDE && P->tl_stream) {
+    S.solver_block = 512;
+    S.solver_npt = 32;
+    S.solver_kind = 5;
   } else if (pb.sampler == USFFT_SAMPLER_PDE && !P->streaming) {
     int blk = 0, npt = 0;
     solver_config_shape(P->solver_cfg, &blk, &npt);
@@ -1722,6 +1730,17 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
       USFFT_HIP(hipStreamSynchronize(nullptr));
       P->wblocks = dst_stream_blocks();
       P->d_stream.ensure(sizeof(double) * (size_t)dst_stream_workspace_doubles(n, P->wblocks));
+    } else if (par->precond == USFFT_PRECOND_DST && tl_stream_ok(n)) {
+      // the fast-Poisson preconditioner moves to the mesh of width 2h
+      // (two-level, additive with scaled Jacobi); its tables are those of n / 2
+      P->tl_stream = true;
+      P->solver_cfg = -1;
+      P->d_sfrag.ensure((size_t)dst_frag_bytes(128));
+      P->d_lam.ensure(sizeof(float) * 128);
+      dst_stream_tables_build(n / 2, P->d_sfrag.p, P->d_lam.as<float>(), nullptr);
+      USFFT_HIP(hipStreamSynchronize(nullptr));
+      P->wblocks = tl_stream_blocks();
+      P->d_stream.ensure(sizeof(double) * (size_t)tl_stream_workspace_doubles(P->wblocks));
     } else if (n > kMaxMesh) {
       // per-sample state exceeds one CU: streaming float64 solver
       P->streaming = true;
@@ -1736,9 +1755,9 @@ static usfft_plan_s* plan_create(const usfft_problem* pb, const usfft_params* pa
     } else {
       P->solver_cfg = autotune_solver(P.get());
     }
-    USFFT_REQUIRE(P->dst || P->dst_stream || P->streaming || P->solver_cfg >= 0, USFFT_EINVAL,
+    USFFT_REQUIRE(P->dst || P->dst_stream || P->tl_stream || P->streaming || P->solver_cfg >= 0, USFFT_EINVAL,
                   "no solver shape for this mesh");
-    if (!P->streaming && !P->dst && !P->dst_stream) {
+    if (!P->streaming && !P->dst && !P->dst_stream && !P->tl_stream) {
       P->wblocks = persistent_blocks(P->solver_cfg, n);
       P->d_wscr.ensure(sizeof(double) * (size_t)edge_scratch_doubles(n, P->wblocks));
     }
@@ -2454,7 +2473,9 @@ static uint64_t estimate_footprint(const usfft_problem* pb, const usfft_params* 
   if (pb->sampler == USFFT_SAMPLER_PDE && pb->mesh_n - 1 > 64)
     solver = 8ull * (uint64_t)(pa->precond == USFFT_PRECOND_DST && dst_stream_ok(pb->mesh_n)
                                    ? dst_stream_workspace_doubles(pb->mesh_n, 256)
-                                   : stream_workspace_doubles(pb->mesh_n, kStreamBlocks));
+                                   : pa->precond == USFFT_PRECOND_DST && tl_stream_ok(pb->mesh_n)
+                                         ? tl_stream_workspace_doubles(256)
+                                         : stream_workspace_doubles(pb->mesh_n, kStreamBlocks));
   return G * samples * ub + G * J * 8 + lines + samples * (uint64_t)pb->d * 8 + solver + (64ull << 20);
 }
 

@@ -126,12 +126,15 @@ def test_lattice_dft_full_size(lib, G, M, fp32):
 
 
 @pytest.mark.parametrize("n,d,ns,precond", [(96, 10, 6, 0), (128, 20, 5, 0), (66, 6, 4, 0), (129, 8, 4, 0),
-                                            (96, 10, 6, 1), (128, 20, 3, 1), (256, 12, 2, 0)])
+                                            (96, 10, 6, 1), (128, 20, 3, 1), (130, 8, 3, 0), (200, 12, 3, 0),
+                                            (256, 20, 3, 0), (256, 12, 2, 1), (255, 6, 2, 0)])
 def test_streaming_solver_large_meshes(lib, n, d, ns, precond):
     # meshes beyond one CU: 65 < n <= 129 with the fast-Poisson preconditioner
     # (CG vectors in a global workspace, float64; n = 66 and 129 are the ends
-    # of its range, 129 fills the 128-point transform), Jacobi there on
-    # request and always above 129
+    # of its range, 129 fills the 128-point transform); even 129 < n <= 256
+    # with the two-level preconditioner (its coarse transform at n / 2: 130
+    # and 256 are the ends of its range); Jacobi on request and for odd n
+    # above 129
     prob = W.pde_problem(n, d, 8)
     plan = lib.Plan(prob, dict(W.params(10, 1, 1e-4), pcg_rtol=1e-13, pcg_maxit=8000, precond=precond))
     Y = np.random.default_rng(n + d).random((ns, d))
@@ -140,7 +143,8 @@ def test_streaming_solver_large_meshes(lib, n, d, ns, precond):
     lib.sample(plan, dev(Y), U, 0, ns + 1, 1, it)
     its = host(it)
     assert (its > 0).all()
-    if precond == 0 and n <= 129:
+    print("n %d d %d precond %d: iterations %s" % (n, d, precond, its.tolist()), flush=True)
+    if precond == 0 and (n <= 129 or n % 2 == 0):
         assert its.max() <= 40, its
     Ug = host(U)
     S = ofem.PDESampler(n, prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
