@@ -598,6 +598,27 @@ def main():
                         "solver_GBps": sbytes / (1e-3 * st[0]["ms_sample"]) / 1e9,
                         "solver_GBps_unit": "68 B per node-iteration + 140 B per node-solve over the sampler time"}
         lplan.close()
+        # the two-level streaming solver at h = 1/256 (65025 nodes, d = 20):
+        # one launch of 4096 seeded solves, and Jacobi on 256 of them
+        import numpy as np
+        for key, pre, nsb in (("mesh256_two_level", U.PRECOND_DST, 4096), ("mesh256_jacobi", U.PRECOND_JACOBI, 256)):
+            bprob = W.pde_problem(256, 20, 64)
+            bplan = U.Plan(bprob, dict(W.params(10, 1, 1e-4), precision=U.FP32_REFINE, pcg_rtol=1e-12, precond=pre,
+                                       pcg_maxit=20000))
+            Yb = torch.from_numpy(np.random.default_rng(args.seed).random((nsb, 20))).cuda()
+            Ub = torch.empty((bplan.G, nsb), dtype=torch.float32, device="cuda")
+            itb = torch.zeros(nsb, dtype=torch.int32, device="cuda")
+            U.sample(bplan, Yb, Ub, 1, nsb, 0, itb)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            U.sample(bplan, Yb, Ub, 1, nsb, 0, itb)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t0
+            res["large"][key] = {"workload": "uniform mesh h=1/256 (65025 nodes), d=20, %d solves in one launch, "
+                                             "float32 samples" % nsb,
+                                 "samples_per_s": nsb / tb, "launch_ms": 1e3 * tb,
+                                 "pcg_iters_per_solve": float(itb.float().mean().item())}
+            bplan.close()
     if args.uneven:
         res["uneven_batch"] = uneven_run(U, args.seed, args.autotune)
     if args.serving_jobs > 0:
