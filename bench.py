@@ -56,8 +56,8 @@ def run_path(U, plan, seed, steps, warmup):
 
 
 SERVING_SMALL = dict(meshes=(16, 32, 64), dims=(4, 10), Ns=(16, 32), ss=(50, 200))
-# the serving configuration's ranges (meshes up to 128^2 here: above 129 points
-# per side only the Jacobi solver exists, hours for a d = 20 job)
+# the serving configuration's ranges (meshes up to 128^2 here: a 256^2 job takes
+# 10 s to minutes on the two-level solver, too long for a stream of this length)
 SERVING_WIDE = dict(meshes=(32, 64, 128), dims=(4, 30), Ns=(16, 64), ss=(50, 800))
 
 
