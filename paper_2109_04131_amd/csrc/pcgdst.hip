@@ -1433,7 +1433,8 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
   const FragLds sf{sfl, lane};
   auto ofs = [](int e) { return 16 * (e >> 2) + (e & 3); };
   // fine passes: wave wv takes rows wv, wv + 8, ..., a lane the columns
-  // lane + 64 k; rows and columns up to 255 stay inside the halo grids
+  // lane + 64 k (the passes of the iteration two rows per step); rows and
+  // columns up to 255 stay inside the halo grids
   const int kc = (m + 63) / 64, tr = (m + 7) / 8;
   // the halo grids' borders (and entries of no mesh node) are never written
   // afterwards: cleared once per launch
@@ -1493,20 +1494,19 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
   // p = D^-1/2 (rt / 4 + P z_c) + beta p on the fine mesh
   auto direction = [&](double beta) {
 #pragma unroll 1
-    for (int t = 0; t < tr; ++t) {
-      const int j = wv + 8 * t;
-      float pv[4], rv[4], dv[4];
+    for (int t = 0; t < tr; t += 2) {
+      float pv[8], rv[8], dv[8];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int hf = (j + 1) * PF + lane + 64 * k + 1;
-        pv[k] = p[hf];
-        rv[k] = rt[hf];
-        dv[k] = dhf[hf];
+      for (int u = 0; u < 8; ++u) {
+        const int hf = (wv + 8 * (t + (u >> 2)) + 1) * PF + lane + 64 * (u & 3) + 1;
+        pv[u] = p[hf];
+        rv[u] = rt[hf];
+        dv[u] = dhf[hf];
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int i = lane + 64 * k;
-        if (k < kc && i < m && j < m) {
+      for (int k = 0; k < 8; ++k) {
+        const int i = lane + 64 * (k & 3), j = wv + 8 * (t + (k >> 2));
+        if ((k & 3) < kc && i < m && j < m) {
           const int iv = i + 1, jv = j + 1, a = iv >> 1, b = jv >> 1, fa = iv & 1, fb = jv & 1;
           float pz = zc[b * PC + a];
           if (fa) pz += zc[b * PC + a + 1];
@@ -1687,13 +1687,12 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
       __syncthreads();  // every direction value is written
       double pq = 0.0;
 #pragma unroll 1
-      for (int t = 0; t < tr; ++t) {
-        const int j = wv + 8 * t;
-        float pc[4], pe[4], pw[4], pn[4], ps[4];
-        double eo[4], ew[4], eu[4], es[4];
+      for (int t = 0; t < tr; t += 2) {
+        float pc[8], pe[8], pw[8], pn[8], ps[8];
+        double eo[8], ew[8], eu[8], es[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int hf = (j + 1) * PF + lane + 64 * k + 1;
+        for (int k = 0; k < 8; ++k) {
+          const int hf = (wv + 8 * (t + (k >> 2)) + 1) * PF + lane + 64 * (k & 3) + 1;
           pc[k] = p[hf];
           pe[k] = p[hf + 1];
           pw[k] = p[hf - 1];
@@ -1705,12 +1704,12 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
           es[k] = ev[hf - PF];
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int i = lane + 64 * k;
+        for (int k = 0; k < 8; ++k) {
+          const int i = lane + 64 * (k & 3), j = wv + 8 * (t + (k >> 2));
           const double c0 = pc[k];
           const double qv = eo[k] * (c0 - (double)pe[k]) + ew[k] * (c0 - (double)pw[k]) +
                             eu[k] * (c0 - (double)pn[k]) + es[k] * (c0 - (double)ps[k]);
-          if (k < kc && i < m && j < m) {
+          if ((k & 3) < kc && i < m && j < m) {
             q[(j + 1) * PF + i + 1] = qv;
             pq += c0 * qv;
           }
@@ -1721,13 +1720,12 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
       double rr = 0.0;
       rtt = 0.0;
 #pragma unroll 1
-      for (int t = 0; t < tr; ++t) {
-        const int j = wv + 8 * t;
-        double rv[4], qv[4], xv[4];
-        float pv[4], dv[4];
+      for (int t = 0; t < tr; t += 2) {
+        double rv[8], qv[8], xv[8];
+        float pv[8], dv[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int hf = (j + 1) * PF + lane + 64 * k + 1;
+        for (int k = 0; k < 8; ++k) {
+          const int hf = (wv + 8 * (t + (k >> 2)) + 1) * PF + lane + 64 * (k & 3) + 1;
           rv[k] = r[hf];
           qv[k] = q[hf];
           xv[k] = x[hf];
@@ -1735,9 +1733,9 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
           dv[k] = dhf[hf];
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int i = lane + 64 * k;
-          if (k < kc && i < m && j < m) {
+        for (int k = 0; k < 8; ++k) {
+          const int i = lane + 64 * (k & 3), j = wv + 8 * (t + (k >> 2));
+          if ((k & 3) < kc && i < m && j < m) {
             const int hf = (j + 1) * PF + i + 1;
             const double rg = rv[k] - alpha * qv[k];
             r[hf] = rg;
