@@ -1,5 +1,5 @@
 """Write the whole-job fixtures of the usFFT at d = 10 (h = 1/16, 1/64) and
-at d = 4 on the h = 1/128 mesh.
+at d = 4 on the h = 1/128 and 1/256 meshes.
 
 Calls only the oracle (oracle/) and the seeded workload definitions
 (workloads/): Alg. 1 steps 1 to 3 in float64 on the CPU, with the solves
@@ -18,8 +18,9 @@ so the results do not depend on the split).  Stored per workload, seed 1:
                            over the iterations), the lattice family
   I, fam3_M, fam3_z        the output set and its step-3 family
   nodes, C_re, C_im, Cmax  coefficients at 64 nodes and max |c| over all nodes
-  y_solve, u_solve         8 seeded sampling nodes and their solutions
-Usage: python tests/golden/make_wholejob.py [mesh64_d10|mesh16_d10|mesh128_d4 ...]
+  y_solve, u_solve         8 seeded sampling nodes and their solutions (2 when
+                           G > 20000)
+Usage: python tests/golden/make_wholejob.py [mesh64_d10|mesh16_d10|mesh128_d4|mesh256_d4 ...]
 """
 import os
 import sys
@@ -49,7 +50,7 @@ def make(name, workers=None):
                     par["theta_relative"], SEED, par["lattice_c"], par["lattice_tries"], par["lattice_max"],
                     par["lattice_mmax"])
         g = np.random.default_rng(2024)
-        y_solve = g.random((8, d))
+        y_solve = g.random((8 if S.G <= 20000 else 2, d))  # fewer stored solves on the largest meshes
         u_solve = PS(y_solve)
     out = dict(theta2=np.float64(res.theta2), samples=np.int64(res.samples))
     r = par["r"]
@@ -110,5 +111,5 @@ def make(name, workers=None):
 
 
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or ["mesh16_d10", "mesh64_d10", "mesh128_d4"]:
+    for nm in sys.argv[1:] or ["mesh16_d10", "mesh64_d10", "mesh128_d4", "mesh256_d4"]:
         make(nm)

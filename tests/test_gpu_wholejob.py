@@ -5,8 +5,9 @@ The expected values are the oracle's, written by tests/golden/make_wholejob.py
 (which calls only oracle/ and workloads/) for seed 1 at two workloads with
 the box [-32,32]^10, s = 200, relative threshold 1e-5 and r = 5: h = 1/64
 (G = 3969, the benchmark's workload) and h = 1/16 (G = 225); and on the
-h = 1/128 mesh (G = 16129, the streaming DST solver) at d = 4, box [-8,8]^4,
-s = 30, relative threshold 1e-4, r = 2.  The library
+h = 1/128 mesh (G = 16129, the streaming DST solver) and the h = 1/256 mesh
+(G = 65025, the two-level solver) at d = 4, box [-8,8]^4, s = 30, relative
+threshold 1e-4, r = 2.  The library
 runs in the benchmark's configuration (pcg_rtol 1e-12) with its detection
 trace on, so every intermediate set is compared:
   * float64: every set I^(t) of step 1 and I^(1..t) of step 2 identical to
@@ -76,7 +77,7 @@ def compare_trace(fx, tr, d, k_lo):
 
 @pytest.mark.parametrize("name,prec,autotune", [("mesh16_d10", 0, 0), ("mesh16_d10", 1, 0), ("mesh64_d10", 0, 0),
                                                 ("mesh64_d10", 1, 0), ("mesh64_d10", 1, 1), ("mesh128_d4", 0, 0),
-                                                ("mesh128_d4", 1, 0)])
+                                                ("mesh128_d4", 1, 0), ("mesh256_d4", 0, 0), ("mesh256_d4", 1, 0)])
 def test_whole_job_against_oracle(lib, name, prec, autotune):
     fx = fixture(name)
     prob, par = W.WORKLOADS[name]

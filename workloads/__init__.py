@@ -78,6 +78,8 @@ WORKLOADS = {
     # a whole job on the h = 1/128 mesh small enough for the oracle (about
     # 2200 solves): d = 4, box [-8,8]^4, s = 30, rel. threshold 1e-4, r = 2
     "mesh128_d4": (pde_problem(128, 4, 8), params(30, 2, 1e-4)),
+    # the same on the h = 1/256 mesh (65025 nodes, the two-level solver)
+    "mesh256_d4": (pde_problem(256, 4, 8), params(30, 2, 1e-4)),
 }
 
 
