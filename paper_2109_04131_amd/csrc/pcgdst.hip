@@ -1446,7 +1446,7 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
   // 3 x 3 fine neighbourhood of fine vertex (2 (c + 1), 2 (row + 1)) with
   // weights 1, 1/2, 1/4; the sum of squares returned
   auto restrict_rt = [&](float (&rin)[E]) {
-    constexpr int RH = 2;  // coarse nodes per load chunk
+    constexpr int RH = 8;  // coarse nodes per load chunk
     double ss = 0.0;
     int bR = (8 * qq + 2) * PF + 2 * (c + 1);
     asm volatile("" : "+v"(bR));
@@ -1507,12 +1507,13 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
       for (int k = 0; k < 8; ++k) {
         const int i = lane + 64 * (k & 3), j = wv + 8 * (t + (k >> 2));
         if ((k & 3) < kc && i < m && j < m) {
-          const int iv = i + 1, jv = j + 1, a = iv >> 1, b = jv >> 1, fa = iv & 1, fb = jv & 1;
-          float pz = zc[b * PC + a];
-          if (fa) pz += zc[b * PC + a + 1];
-          if (fb) pz += zc[(b + 1) * PC + a];
-          if (fa && fb) pz += zc[(b + 1) * PC + a + 1];
-          pz *= (fa ? 0.5f : 1.0f) * (fb ? 0.5f : 1.0f);
+          // bilinear weights 1 (on a coarse line) or 1/2, 1/2 (between two):
+          // all four corners read (a + 1, b + 1 <= n / 2), weight 0 where unused
+          const int iv = i + 1, jv = j + 1, a = iv >> 1, b = jv >> 1;
+          const float wa1 = (iv & 1) ? 0.5f : 0.0f, wa0 = 1.0f - wa1;
+          const float wb1 = (jv & 1) ? 0.5f : 0.0f, wb0 = 1.0f - wb1;
+          const float* zr = zc + b * PC + a;
+          const float pz = wb0 * (wa0 * zr[0] + wa1 * zr[1]) + wb1 * (wa0 * zr[PC] + wa1 * zr[PC + 1]);
           const float zt = 0.25f * rv[k] + pz;
           const double old = beta != 0.0 ? beta * (double)pv[k] : 0.0;  // the first direction ignores p
           p[(j + 1) * PF + iv] = (float)((double)dv[k] * (double)zt + old);
