@@ -382,6 +382,37 @@ def test_select_bit_exact_hard_keys(lib, kind, n, G, s):
     assert np.array_equal(host(thr), thr_ref)
 
 
+@pytest.mark.parametrize("n,G,s", [(300, 64, 20), (1155, 48, 200), (9000, 6, 200)])
+def test_select_bit_exact_near_theta(lib, n, G, s):
+    # columns whose count of keys at or above theta^2 runs from well below s~
+    # to well above it, with keys exactly at theta^2, inside the tie band just
+    # above it and just below it: thresholds at theta^2 and at (1 - tie) tau^2
+    # both occur, and at the switch between them
+    g = np.random.default_rng(n * 7 + G)
+    theta2 = 1.0
+    V = g.random((n, G)) * 0.5
+    for c in range(G):
+        k = (c * (2 * s + 4)) // G  # keys placed at or above theta^2
+        rows = g.permutation(n)[:min(k, n)]
+        V[rows, c] = theta2 * (1.0 + g.random(len(rows)))
+        if len(rows) > 3:
+            V[rows[0], c] = theta2  # exactly theta^2
+            V[rows[1], c] = theta2 * (1 + 2.0 ** -33)  # inside the tie band
+            V[rows[2], c] = np.nextafter(theta2, 0.0)  # just below
+    mask_ref, thr_ref, _ = osel.detect_mask(V, s, theta2)
+    ld = n + 5
+    Vd = np.zeros((G, ld))
+    Vd[:, :n] = V.T
+    mask = torch.zeros((n + 31) // 32 + 1, dtype=torch.int32, device="cuda")
+    thr = torch.zeros(G, dtype=torch.float64, device="cuda")
+    lib.select(dev(Vd), G, n, ld, s, dev(np.array([theta2])), osel.TIE_REL, mask, thr)
+    m = host(mask).view(np.uint32)
+    bits = np.array([(m[a >> 5] >> (a & 31)) & 1 for a in range(n)], dtype=bool)
+    assert np.array_equal(bits, mask_ref)
+    assert np.array_equal(host(thr), thr_ref)
+    assert (thr_ref == theta2).any() and (thr_ref > theta2).any()
+
+
 # ------------------------------------------------------------------ sets
 def test_product_and_compact_bit_exact(lib):
     parent, child = W.candidate_set(2, 60, 4, 9)
