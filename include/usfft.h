@@ -333,8 +333,13 @@ void usfft_result_destroy(usfft_result_t res);
  * out_dev[j*G + g] = Re sum_{k in I} c_k(u_{x_g}) exp(2 pi i k.phi^{-1}(y_j)),
  * y_dev: n x d doubles, parameters of the model (periodic: nodes in [0,1)).
  * Computed as a float64 matrix product on the matrix cores in chunks of
- * points; temporary device memory of at most ~256 MB per call.  Returns after
- * the stream has finished.  Errors: EINVAL, ENOMEM, EHIP. */
+ * points.  Device workspace of at most ~256 MB (the frequency set, uploaded
+ * once, plus each chunk's points and phases) stays with the result: it is
+ * allocated on the first call, grown when a later call needs more, reused
+ * otherwise and freed by usfft_result_destroy.  Calls on one result
+ * (usfft_eval, usfft_statistics, usfft_errors) are serialised by the
+ * library.  Returns after the stream has finished.  Errors: EINVAL, ENOMEM,
+ * EHIP. */
 usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n,
                         double* out_dev, void* stream);
 
@@ -365,7 +370,8 @@ usfft_status usfft_eval_noalloc(usfft_result_t res, const double* y_dev, int64_t
  *   gsi_dev[(l-1)*G + g]  global sensitivity index of J_l = {k : exactly l
  *                         nonzero components}, l = 1..d (0 where the
  *                         variance is 0).
- * Returns after the stream has finished.  Errors: EINVAL, EHIP. */
+ * Uses the result's evaluation workspace (see usfft_eval).  Returns after
+ * the stream has finished.  Errors: EINVAL, ENOMEM, EHIP. */
 usfft_status usfft_statistics(usfft_result_t res, double* mean_dev, double* var_dev,
                               double* gsi_dev, void* stream);
 
@@ -376,7 +382,8 @@ usfft_status usfft_statistics(usfft_result_t res, double* mean_dev, double* var_
  *   errp_dev[g]   = ( (1/n) sum_j |u_FE(x_g, y_j) - u_usFFT(x_g, y_j)|^p )^(1/p),
  *   errinf_dev[g] = max_j |u_FE(x_g, y_j) - u_usFFT(x_g, y_j)|.
  * res must come from a plan of the same problem (same d and G).  p >= 1.
- * Works in chunks of points (temporary device memory up to ~1.3 GB).
+ * Works in chunks of points, in the result's evaluation workspace (see
+ * usfft_eval; up to ~1.3 GB here).
  * Returns after the stream has finished.  Errors: EINVAL, ENOMEM, ENOCONV
  * (a test solve missed pcg_rtol), EHIP. */
 usfft_status usfft_errors(usfft_plan_t plan, usfft_result_t res, const double* y_dev,

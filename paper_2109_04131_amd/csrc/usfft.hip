@@ -186,6 +186,13 @@ struct usfft_result_s {
   std::vector<std::vector<int32_t>> trace_set;
   std::vector<int32_t> trace_width;
   std::vector<int64_t> trace_cand;
+  // evaluation state kept across usfft_eval / _statistics / _errors calls:
+  // the frequency set on the device (uploaded on first use) and grow-only
+  // workspaces, so repeated calls allocate nothing; emu serialises the calls
+  std::mutex emu;
+  bool Iup = false;
+  usfft::DevBuf Idev;
+  usfft::DevBuf ews[8];
 };
 
 namespace usfft {
@@ -2079,10 +2086,16 @@ int64_t eval_chunk(int64_t n, int64_t nI, int64_t G, bool with_fe) {
   return std::min<int64_t>(nc, std::max<int64_t>(n, 1));
 }
 
-void upload_set(const usfft_result_s* res, usfft::DevBuf& I) {
-  if (res->I.empty()) return;
-  I.ensure(sizeof(int32_t) * res->I.size());
-  USFFT_HIP(hipMemcpy(I.p, res->I.data(), sizeof(int32_t) * res->I.size(), hipMemcpyHostToDevice));
+// The result's frequency set on the device (null when empty), uploaded on
+// the first evaluation call; the caller holds res->emu.
+const int32_t* result_set(usfft_result_s* res) {
+  if (res->I.empty()) return nullptr;
+  if (!res->Iup) {
+    res->Idev.ensure(sizeof(int32_t) * res->I.size());
+    USFFT_HIP(hipMemcpy(res->Idev.p, res->I.data(), sizeof(int32_t) * res->I.size(), hipMemcpyHostToDevice));
+    res->Iup = true;
+  }
+  return res->Idev.as<int32_t>();
 }
 
 // Fixed scratch of usfft_eval_noalloc, for callers that cannot allocate
@@ -2119,8 +2132,9 @@ usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n, doub
     if (n == 0 || res->G == 0) return;
     hipStream_t st = (hipStream_t)stream;
     const int64_t nI = res->d ? (int64_t)res->I.size() / res->d : 0;
-    DevBuf I, T, B;
-    upload_set(res, I);
+    std::lock_guard<std::mutex> lk(res->emu);
+    const int32_t* I = result_set(res);
+    DevBuf &T = res->ews[0], &B = res->ews[1];
     const int64_t nc = eval_chunk(n, nI, res->G, false);
     T.ensure(sizeof(double) * (size_t)(res->d * nc));
     B.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, 2 * nI * nc));
@@ -2128,7 +2142,7 @@ usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n, doub
       const int64_t m = std::min(nc, n - c0);
       launch_node_map(y_dev + c0 * res->d, m, res->d, res->model, res->alpha, res->beta, res->delta,
                       T.as<double>(), nc, st);
-      launch_phases(I.as<int32_t>(), nI, res->d, T.as<double>(), nc, m, B.as<double>(), nc, st);
+      launch_phases(I, nI, res->d, T.as<double>(), nc, m, B.as<double>(), nc, st);
       launch_evgemm_values(res->C.as<double>(), res->G, nI, B.as<double>(), nc, m, out_dev + c0 * res->G, res->G,
                            st);
     }
@@ -2177,11 +2191,12 @@ usfft_status usfft_statistics(usfft_result_t res, double* mean_dev, double* var_
     if (res->G == 0 || (!mean_dev && !var_dev && !gsi_dev)) return;
     hipStream_t st = (hipStream_t)stream;
     const int64_t nI = res->d ? (int64_t)res->I.size() / res->d : 0;
-    DevBuf I, D, ord;
-    upload_set(res, I);
+    std::lock_guard<std::mutex> lk(res->emu);
+    const int32_t* I = result_set(res);
+    DevBuf &D = res->ews[0], &ord = res->ews[1];
     D.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, 2 * nI));
     ord.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(1, nI));
-    launch_stats(I.as<int32_t>(), nI, res->d, res->C.as<double>(), res->G, res->model, res->delta, D.as<double>(),
+    launch_stats(I, nI, res->d, res->C.as<double>(), res->G, res->model, res->delta, D.as<double>(),
                  ord.as<int32_t>(), mean_dev, var_dev, gsi_dev, st);
     USFFT_HIP(hipStreamSynchronize(st));
   });
@@ -2195,12 +2210,14 @@ usfft_status usfft_errors(usfft_plan_t plan, usfft_result_t res, const double* y
     USFFT_REQUIRE(res->d == plan->prob.d && res->G == plan->G, USFFT_EINVAL,
                   "the result does not belong to this plan's problem");
     std::lock_guard<std::mutex> lk(plan->mu);
+    std::lock_guard<std::mutex> lr(res->emu);
     hipStream_t st = (hipStream_t)stream;
     const int64_t G = res->G, d = res->d;
     const int64_t nI = d ? (int64_t)res->I.size() / d : 0;
     const int64_t nc = eval_chunk(n, nI, G, true);
-    DevBuf I, T, B, U, it, ps, pm, cnt;
-    upload_set(res, I);
+    const int32_t* I = result_set(res);
+    DevBuf &T = res->ews[0], &B = res->ews[1], &U = res->ews[2], &it = res->ews[3], &ps = res->ews[4],
+           &pm = res->ews[5], &cnt = res->ews[6];
     T.ensure(sizeof(double) * (size_t)(d * nc));
     B.ensure(sizeof(double) * (size_t)std::max<int64_t>(1, 2 * nI * nc));
     U.ensure(sizeof(double) * (size_t)(G * nc));
@@ -2218,7 +2235,7 @@ usfft_status usfft_errors(usfft_plan_t plan, usfft_result_t res, const double* y
                          st, it.as<int32_t>(), m, cnt.as<unsigned long long>());
       USFFT_HIP(hipGetLastError());
       launch_node_map(Y, m, (int)d, res->model, res->alpha, res->beta, res->delta, T.as<double>(), nc, st);
-      launch_phases(I.as<int32_t>(), nI, (int)d, T.as<double>(), nc, m, B.as<double>(), nc, st);
+      launch_phases(I, nI, (int)d, T.as<double>(), nc, m, B.as<double>(), nc, st);
       launch_evgemm_errors(res->C.as<double>(), G, nI, B.as<double>(), nc, m, U.as<double>(), nc, p, ps.as<double>(),
                            pm.as<double>(), c0 == 0, errp_dev, errinf_dev, st);
     }

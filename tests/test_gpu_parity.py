@@ -131,7 +131,8 @@ def test_dst_solver_batch_independent_and_fast(lib, prec, variant):
         lib.sample(plan, dev(Y[s:s + 1]), U1, 0, 1)
         assert np.array_equal(host(U1)[:, 0], host(U)[:, s])
         ref = S.solve_one(Y[s])
-        assert np.linalg.norm(host(U)[:, s] - ref) <= (1e-10 if prec == 0 else 1e-9) * np.linalg.norm(ref)
+        # the float64 contract (nodal 1e-11) at the benchmark's pcg_rtol
+        assert np.linalg.norm(host(U)[:, s] - ref) <= (1e-11 if prec == 0 else 1e-9) * np.linalg.norm(ref)
 
 
 @pytest.mark.parametrize("model,n", [("pde", 5), ("pde", 16), ("pde", 17), ("pde", 33), ("pde", 34), ("pde", 48),
@@ -179,7 +180,7 @@ def test_dst_preconditioner_is_exact_for_constant_coefficient(lib, prec):
     assert (host(it) > 0).all() and host(it).max() <= 6, host(it)
     ref = ofem.PDESampler(n, 1.0, [0.0] * d, prob["mode1"], prob["mode2"]).solve_one(Y[0])
     for s in range(4):
-        assert np.linalg.norm(host(U)[:, s] - ref) <= 1e-10 * np.linalg.norm(ref)
+        assert np.linalg.norm(host(U)[:, s] - ref) <= (1e-11 if prec == 0 else 1e-10) * np.linalg.norm(ref)
 
 
 @pytest.mark.parametrize("precond", [0, 1], ids=["dst", "jacobi"])
@@ -591,6 +592,34 @@ def test_eval_matches_oracle(lib):
     assert np.abs(host(out) - want).max() <= 1e-12 * np.abs(want).max()
     assert np.abs(host(out) - TrigPolySampler(K, P)(Y)).max() <= 1e-11
     lib.eval(res, dev(np.zeros((0, 4))), torch.zeros((0, 130), dtype=torch.float64, device="cuda"))
+
+
+def test_eval_workspace_reused(lib):
+    # repeated evaluations and statistics of one result: the set and the
+    # workspaces stay with the result, so later calls of the same or smaller
+    # size allocate no device memory, and each call's output equals the first
+    # call's bit for bit (eq. (3.1); Sec. 4.1)
+    K, P = W.trig_poly(8, 4, 8, 130, 25, cmin=1e-2)
+    prob = dict(sampler="poly", d=4, k_lo=[-8] * 4, k_hi=[8] * 4, poly_k=K, poly_c=P)
+    plan = lib.Plan(prob, dict(W.params(60, 3, 1e-6, relative=False), precision=lib.FP64, pcg_rtol=1e-13))
+    res = lib.detect(plan, 2)
+    Y = dev(np.random.default_rng(5).random((700, 4)))
+    first = torch.zeros((700, 130), dtype=torch.float64, device="cuda")
+    out = torch.zeros((700, 130), dtype=torch.float64, device="cuda")
+    var0 = torch.zeros(130, dtype=torch.float64, device="cuda")
+    var = torch.zeros(130, dtype=torch.float64, device="cuda")
+    lib.eval(res, Y, first)
+    lib.statistics(res, None, var0, None)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for n in (700, 311, 700):
+        out.zero_()
+        lib.eval(res, Y[:n], out[:n])
+        lib.statistics(res, None, var, None)
+        torch.cuda.synchronize()
+        assert torch.equal(out[:n], first[:n]), n
+        assert torch.equal(var, var0)
+    assert torch.cuda.mem_get_info()[0] == free0
 
 
 def _model_case(model):
