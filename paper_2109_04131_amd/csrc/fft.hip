@@ -856,30 +856,41 @@ void launch_lattice_dft_batch(const LatItem* items, int nitems, int Lmax, const 
 
 // ---------------------------------------------------------------- line DFT
 constexpr int kLineMax = 1024;
-// The DFT of one node's line samples u[g ld + col0 + l], l < K, at the bins
-// given (the canonical half spectrum: bins b and K - b are exact conjugates).
+constexpr int kLineBlock = 256;
+// The DFTs of the line samples u[g ld + col0 + l], l < K, of the npb nodes
+// g0 .. g0 + npb - 1 (those below G), at the bins given (the canonical half
+// spectrum: bins b and K - b are exact conjugates).  The nodes share one
+// workgroup, so the phase table is computed once for all of them; each
+// (node, bin) pair is one thread's direct sum over l.
 template <typename T>
-__device__ __forceinline__ void line_dft_node(const T* __restrict__ u, int64_t g, int64_t G, int64_t ld,
-                                              int64_t col0, int K, const int32_t* __restrict__ bins, int nb,
-                                              int out_kind, void* __restrict__ out, int64_t ldo, double* x,
-                                              double* cs, double* sn) {
-  for (int l = threadIdx.x; l < K; l += 256) {
-    x[l] = (double)u[g * ld + col0 + l];
+__device__ __forceinline__ void line_dft_nodes(const T* __restrict__ u, int64_t g0, int npb, int64_t G, int64_t ld,
+                                               int64_t col0, int K, const int32_t* __restrict__ bins, int nb,
+                                               int out_kind, void* __restrict__ out, int64_t ldo, double* x,
+                                               double* cs, double* sn) {
+  const int nn = (int)(G - g0 < npb ? G - g0 : (int64_t)npb);
+  for (int l = threadIdx.x; l < K; l += kLineBlock) {
     double s, c;
     sincospi(2.0 * (double)l / (double)K, &s, &c);
     cs[l] = c;
     sn[l] = s;
   }
+  for (int e = threadIdx.x; e < nn * K; e += kLineBlock) {
+    const int j = e / K, l = e - j * K;
+    x[e] = (double)u[(g0 + j) * ld + col0 + l];
+  }
   __syncthreads();
   const double invK = 1.0 / (double)K;
-  for (int a = threadIdx.x; a < nb; a += 256) {
+  for (int e = threadIdx.x; e < nn * nb; e += kLineBlock) {
+    const int j = e / nb, a = e - j * nb;
+    const int64_t g = g0 + j;
+    const double* xj = x + j * K;
     const int b = ((bins[a] % K) + K) % K;
     const int bc = min(b, K - b) % K;
     double re = 0.0, im = 0.0;
     int ph = 0;
     for (int l = 0; l < K; ++l) {
-      re += x[l] * cs[ph];
-      im -= x[l] * sn[ph];
+      re += xj[l] * cs[ph];
+      im -= xj[l] * sn[ph];
       ph += bc;
       if (ph >= K) ph -= K;
     }
@@ -896,36 +907,40 @@ __device__ __forceinline__ void line_dft_node(const T* __restrict__ u, int64_t g
   }
 }
 
+// Nodes per workgroup for lines of up to K samples: their samples (npb K
+// doubles) and the phase table stay within 48 KB of LDS.
+static int line_npb(int K) { return std::max(1, std::min(32, 4096 / std::max(K, 1))); }
+static size_t line_lds(int K) { return sizeof(double) * (size_t)(line_npb(K) + 2) * (size_t)K; }
+
 template <typename T>
-__global__ __launch_bounds__(256) void line_dft_kernel(const T* __restrict__ u, int64_t G, int64_t ld, int64_t col0,
-                                                       int K, const int32_t* __restrict__ bins, int nb,
-                                                       int out_kind, void* __restrict__ out, int64_t ldo) {
-  __shared__ double x[kLineMax];
-  __shared__ double cs[kLineMax];
-  __shared__ double sn[kLineMax];
-  line_dft_node(u, xcd_remap(blockIdx.x, gridDim.x), G, ld, col0, K, bins, nb, out_kind, out, ldo, x, cs, sn);
+__global__ __launch_bounds__(kLineBlock) void line_dft_kernel(const T* __restrict__ u, int64_t G, int64_t ld,
+                                                              int64_t col0, int K, int npb,
+                                                              const int32_t* __restrict__ bins, int nb, int out_kind,
+                                                              void* __restrict__ out, int64_t ldo) {
+  extern __shared__ double lsh[];
+  line_dft_nodes(u, xcd_remap(blockIdx.x, gridDim.x) * npb, npb, G, ld, col0, K, bins, nb, out_kind, out, ldo, lsh,
+                 lsh + (size_t)npb * K, lsh + (size_t)(npb + 1) * K);
 }
 
 // All step-1 lines in one launch: blockIdx.y = line y of coordinate
 // t = y / line_r, samples from column loff[y], its K_t = lineK[t] candidates
 // cands[sum_{j<t} K_j ..] at every bin, |.|^2 to columns y * line_stride ..
-// of out (leading dimension ldo).
+// of out (leading dimension ldo).  The LDS carve-up follows Kmax.
 template <typename T>
-__global__ __launch_bounds__(256) void line_dft_lines_kernel(const T* __restrict__ u, int64_t G, int64_t ld,
-                                                             const int64_t* __restrict__ loff,
-                                                             const int32_t* __restrict__ lineK,
-                                                             const int32_t* __restrict__ cands, int line_r,
-                                                             int64_t line_stride, double* __restrict__ out,
-                                                             int64_t ldo) {
-  __shared__ double x[kLineMax];
-  __shared__ double cs[kLineMax];
-  __shared__ double sn[kLineMax];
+__global__ __launch_bounds__(kLineBlock) void line_dft_lines_kernel(const T* __restrict__ u, int64_t G, int64_t ld,
+                                                                    const int64_t* __restrict__ loff,
+                                                                    const int32_t* __restrict__ lineK,
+                                                                    const int32_t* __restrict__ cands, int line_r,
+                                                                    int64_t line_stride, double* __restrict__ out,
+                                                                    int64_t ldo, int Kmax, int npb) {
+  extern __shared__ double lsh[];
   const int y = blockIdx.y, t = y / line_r;
   int64_t coff = 0;
   for (int j = 0; j < t; ++j) coff += lineK[j];
   const int K = lineK[t];
-  line_dft_node(u, xcd_remap(blockIdx.x, gridDim.x), G, ld, loff[y], K, cands + coff, K, USFFT_OUT_MAG2,
-                out + (int64_t)y * line_stride, ldo, x, cs, sn);
+  line_dft_nodes(u, xcd_remap(blockIdx.x, gridDim.x) * npb, npb, G, ld, loff[y], K, cands + coff, K,
+                 USFFT_OUT_MAG2, out + (int64_t)y * line_stride, ldo, lsh, lsh + (size_t)npb * Kmax,
+                 lsh + (size_t)(npb + 1) * Kmax);
 }
 
 void launch_line_dft_lines(const void* u, int u_fp32, int64_t G, int64_t ld, const int64_t* loff,
@@ -933,13 +948,14 @@ void launch_line_dft_lines(const void* u, int u_fp32, int64_t G, int64_t ld, con
                            int64_t line_stride, double* out, int64_t ldo, hipStream_t st) {
   USFFT_REQUIRE(Kmax >= 1 && Kmax <= kLineMax && line_stride >= Kmax, USFFT_EINVAL, "line DFT length out of range");
   if (G <= 0 || nlines <= 0) return;
-  const dim3 grid((unsigned)G, (unsigned)nlines);
+  const int npb = line_npb(Kmax);
+  const dim3 grid((unsigned)ceil_div(G, npb), (unsigned)nlines);
   if (u_fp32)
-    hipLaunchKernelGGL(line_dft_lines_kernel<float>, grid, dim3(256), 0, st, (const float*)u, G, ld, loff, lineK,
-                       cands, line_r, line_stride, out, ldo);
+    hipLaunchKernelGGL(line_dft_lines_kernel<float>, grid, dim3(kLineBlock), line_lds(Kmax), st, (const float*)u, G,
+                       ld, loff, lineK, cands, line_r, line_stride, out, ldo, Kmax, npb);
   else
-    hipLaunchKernelGGL(line_dft_lines_kernel<double>, grid, dim3(256), 0, st, (const double*)u, G, ld, loff, lineK,
-                       cands, line_r, line_stride, out, ldo);
+    hipLaunchKernelGGL(line_dft_lines_kernel<double>, grid, dim3(kLineBlock), line_lds(Kmax), st, (const double*)u,
+                       G, ld, loff, lineK, cands, line_r, line_stride, out, ldo, Kmax, npb);
   USFFT_HIP(hipGetLastError());
 }
 
@@ -947,12 +963,14 @@ void launch_line_dft(const void* u, int u_fp32, int64_t G, int64_t ld, int64_t c
                      int nb, int out_kind, void* out, int64_t ldo, hipStream_t st) {
   USFFT_REQUIRE(K >= 1 && K <= kLineMax, USFFT_EINVAL, "line DFT length out of range");
   if (G <= 0 || nb <= 0) return;
+  const int npb = line_npb(K);
+  const unsigned grid = (unsigned)ceil_div(G, npb);
   if (u_fp32)
-    hipLaunchKernelGGL(line_dft_kernel<float>, dim3((unsigned)G), dim3(256), 0, st, (const float*)u, G, ld, col0,
-                       K, bins, nb, out_kind, out, ldo);
+    hipLaunchKernelGGL(line_dft_kernel<float>, dim3(grid), dim3(kLineBlock), line_lds(K), st, (const float*)u, G, ld,
+                       col0, K, npb, bins, nb, out_kind, out, ldo);
   else
-    hipLaunchKernelGGL(line_dft_kernel<double>, dim3((unsigned)G), dim3(256), 0, st, (const double*)u, G, ld,
-                       col0, K, bins, nb, out_kind, out, ldo);
+    hipLaunchKernelGGL(line_dft_kernel<double>, dim3(grid), dim3(kLineBlock), line_lds(K), st, (const double*)u, G,
+                       ld, col0, K, npb, bins, nb, out_kind, out, ldo);
   USFFT_HIP(hipGetLastError());
 }
 
