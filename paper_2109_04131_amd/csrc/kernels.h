@@ -216,13 +216,11 @@ void launch_product(const int32_t* parent, int64_t np, int t, const int32_t* chi
 // Compaction; *count_dev receives the row count.
 void launch_compact(const int32_t* J, const uint32_t* mask, int64_t n, int t, int32_t* out, int64_t* count_dev,
                     hipStream_t st);
-void launch_lattice_bins(const int32_t* J, int64_t n, int t, const int32_t* z, int T, int M, int32_t* bins,
-                         int32_t* counts, hipStream_t st);
-void launch_lattice_score(const int32_t* bins, const int32_t* counts, const uint8_t* covered, int64_t n, int T,
-                          int M, int32_t* scores, hipStream_t st);
-// also clears counts (T x M) and scores (T) for the attempt
-void launch_lattice_z(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, int32_t* z, int32_t* counts,
-                      int32_t* scores, hipStream_t st);
+// The T tries of lattice attempt a (one workgroup each): generators z (T x t),
+// bins (T x n), alias counts (T x M) and scores (T), all overwritten
+void launch_lattice_try(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, const int32_t* J, int64_t n,
+                        const uint8_t* covered, int32_t* z, int32_t* bins, int32_t* counts, int32_t* scores,
+                        hipStream_t st);
 // device choice of one attempt (state: uncovered, taken; log: best, freed) and its commit
 void launch_lattice_pick_take(const int32_t* scores, int T, const int64_t* state_in, int64_t* state_out,
                               int32_t* log, const int32_t* bins, const int32_t* counts, uint8_t* covered, int64_t n,

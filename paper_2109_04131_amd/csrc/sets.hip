@@ -70,70 +70,60 @@ void launch_compact(const int32_t* J, const uint32_t* mask, int64_t n, int t, in
   USFFT_HIP(hipGetLastError());
 }
 
-// bins[tr][a] = (k_a . z_tr) mod M for T candidate generators; counts[tr][b]
-// counts the candidates per bin (counts must be zero on entry).
-__global__ void lattice_bins_kernel(const int32_t* __restrict__ J, int64_t n, int t, const int32_t* __restrict__ z,
-                                    int T, int M, int32_t* __restrict__ bins, int32_t* __restrict__ counts) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * T) return;
-  const int tr = (int)(e / n);
-  const int64_t a = e % n;
-  int64_t acc = 0;
-  for (int j = 0; j < t; ++j) acc += (int64_t)J[a * t + j] * (int64_t)z[tr * t + j];
-  int64_t b = acc % M;
-  if (b < 0) b += M;
-  bins[e] = (int32_t)b;
-  atomicAdd(&counts[(int64_t)tr * M + b], 1);
-}
-
-void launch_lattice_bins(const int32_t* J, int64_t n, int t, const int32_t* z, int T, int M, int32_t* bins,
-                         int32_t* counts, hipStream_t st) {
-  const int64_t tot = n * T;
-  if (tot <= 0) return;
-  hipLaunchKernelGGL(lattice_bins_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256), 0, st, J, n, t, z, T, M,
-                     bins, counts);
-  USFFT_HIP(hipGetLastError());
-}
-
-// scores[tr] = #{a uncovered : counts[tr][bins[tr][a]] == 1}
-__global__ void lattice_score_kernel(const int32_t* __restrict__ bins, const int32_t* __restrict__ counts,
-                                     const uint8_t* __restrict__ covered, int64_t n, int T, int M,
-                                     int32_t* __restrict__ scores) {
-  const int tr = blockIdx.y;
-  int c = 0;
-  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < n; a += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t b = bins[(int64_t)tr * n + a];
-    c += (!covered[a] && counts[(int64_t)tr * M + b] == 1) ? 1 : 0;
+// The T tries of lattice attempt a, one workgroup each: the try's generator
+// z_tr (the draw of rng::lattice_z), bins[tr][a] = (k_a . z_tr) mod M of
+// every candidate, the alias counts per bin (in LDS, then copied to
+// counts[tr][.] for the commit) and the score #{a uncovered :
+// counts[tr][bins[tr][a]] == 1}.
+constexpr int kTryBlock = 1024;
+__global__ __launch_bounds__(kTryBlock) void lattice_try_kernel(uint64_t seed, int kind, int tcode, int a, int t,
+                                                                int M, const int32_t* __restrict__ J, int64_t n,
+                                                                const uint8_t* __restrict__ covered,
+                                                                int32_t* __restrict__ z, int32_t* __restrict__ bins,
+                                                                int32_t* __restrict__ counts,
+                                                                int32_t* __restrict__ scores) {
+  extern __shared__ int32_t cnt[];  // M alias counts
+  __shared__ int32_t zs[kMaxD];
+  __shared__ int32_t wsum[kTryBlock / kWave];
+  const int tr = blockIdx.x;
+  for (int i = threadIdx.x; i < M; i += kTryBlock) cnt[i] = 0;
+  if (threadIdx.x < t) {
+    const int32_t zj = rng::lattice_z(seed, kind, tcode, a, tr, threadIdx.x, M);
+    zs[threadIdx.x] = zj;
+    z[tr * t + threadIdx.x] = zj;
   }
+  __syncthreads();
+  int32_t* bt = bins + (int64_t)tr * n;
+  for (int64_t e = threadIdx.x; e < n; e += kTryBlock) {
+    int64_t acc = 0;
+    for (int j = 0; j < t; ++j) acc += (int64_t)J[e * t + j] * (int64_t)zs[j];
+    int64_t bn = acc % M;
+    if (bn < 0) bn += M;
+    bt[e] = (int32_t)bn;
+    atomicAdd(&cnt[bn], 1);
+  }
+  __syncthreads();
+  int32_t* ct = counts + (int64_t)tr * M;
+  for (int i = threadIdx.x; i < M; i += kTryBlock) ct[i] = cnt[i];
+  int c = 0;
+  for (int64_t e = threadIdx.x; e < n; e += kTryBlock) c += (!covered[e] && cnt[bt[e]] == 1) ? 1 : 0;
   c = wave_sum(c);
-  if ((threadIdx.x & (kWave - 1)) == 0 && c) atomicAdd(&scores[tr], c);
+  if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < kTryBlock / kWave; ++w) tot += wsum[w];
+    scores[tr] = tot;
+  }
 }
 
-void launch_lattice_score(const int32_t* bins, const int32_t* counts, const uint8_t* covered, int64_t n, int T,
-                          int M, int32_t* scores, hipStream_t st) {
-  if (n <= 0) return;
-  const unsigned gx = (unsigned)std::min<int64_t>(256, ceil_div(n, 256));
-  hipLaunchKernelGGL(lattice_score_kernel, dim3(gx, T), dim3(256), 0, st, bins, counts, covered, n, T, M, scores);
-  USFFT_HIP(hipGetLastError());
-}
-
-// Generators of the T tries of lattice attempt a, the draws of rng::lattice_z;
-// the same launch clears the attempt's alias counts (T x M) and scores (T).
-__global__ void lattice_z_kernel(uint64_t seed, int kind, int tcode, int a, int T, int t, int M,
-                                 int32_t* __restrict__ z, int32_t* __restrict__ counts,
-                                 int32_t* __restrict__ scores) {
-  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e0 < (int64_t)T * t) z[e0] = rng::lattice_z(seed, kind, tcode, a, (int)(e0 / t), (int)(e0 % t), M);
-  if (e0 < T) scores[e0] = 0;
-  for (int64_t e = e0; e < (int64_t)T * M; e += (int64_t)gridDim.x * blockDim.x) counts[e] = 0;
-}
-
-void launch_lattice_z(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, int32_t* z, int32_t* counts,
-                      int32_t* scores, hipStream_t st) {
-  const int64_t work = std::max<int64_t>((int64_t)T * t, std::max<int64_t>(T, (int64_t)T * M / 8));
-  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(work, 256), 1024);
-  hipLaunchKernelGGL(lattice_z_kernel, dim3(grid), dim3(256), 0, st, seed, kind, tcode, a, T, t, M, z, counts,
-                     scores);
+void launch_lattice_try(uint64_t seed, int kind, int tcode, int a, int T, int t, int M, const int32_t* J, int64_t n,
+                        const uint8_t* covered, int32_t* z, int32_t* bins, int32_t* counts, int32_t* scores,
+                        hipStream_t st) {
+  USFFT_REQUIRE(T >= 1 && t >= 1 && t <= kMaxD && M >= 1 && M <= kMaxLattice && n >= 1, USFFT_EINVAL,
+                "bad lattice try shape");
+  hipLaunchKernelGGL(lattice_try_kernel, dim3((unsigned)T), dim3(kTryBlock), sizeof(int32_t) * (size_t)M, st, seed,
+                     kind, tcode, a, t, M, J, n, covered, z, bins, counts, scores);
   USFFT_HIP(hipGetLastError());
 }
 

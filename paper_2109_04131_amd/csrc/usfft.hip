@@ -376,12 +376,8 @@ static void plan_family(usfft_plan_s* P, const int32_t* J, int64_t n, int t, uin
     for (int b = 0; b < nb; ++b) {
       const int a = attempt + b;
       const int M = sizes[a % sizes.size()];
-      launch_lattice_z(seed, kind, tcode, a, T, t, M, P->famz.as<int32_t>(), P->famcounts.as<int32_t>(),
-                       P->famscores.as<int32_t>(), st);
-      launch_lattice_bins(J, n, t, P->famz.as<int32_t>(), T, M, P->fambins.as<int32_t>(),
-                          P->famcounts.as<int32_t>(), st);
-      launch_lattice_score(P->fambins.as<int32_t>(), P->famcounts.as<int32_t>(), P->famcov.as<uint8_t>(), n, T, M,
-                           P->famscores.as<int32_t>(), st);
+      launch_lattice_try(seed, kind, tcode, a, T, t, M, J, n, P->famcov.as<uint8_t>(), P->famz.as<int32_t>(),
+                         P->fambins.as<int32_t>(), P->famcounts.as<int32_t>(), P->famscores.as<int32_t>(), st);
       launch_lattice_pick_take(P->famscores.as<int32_t>(), T, slot + 2 * (a & 1), slot + 2 * ((a + 1) & 1),
                                P->famlog.as<int32_t>() + 2 * a, P->fambins.as<int32_t>(),
                                P->famcounts.as<int32_t>(), P->famcov.as<uint8_t>(), n, M, assign, bins_out, st);
