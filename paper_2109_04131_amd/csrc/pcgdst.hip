@@ -712,7 +712,8 @@ template <int MP>
 __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64 ? 2 : 4))) void pcgdst32c_kernel(
     const SolveSeg* __restrict__ segs, int nseg, int64_t ns, double rtol, int maxit, double inner_rtol,
     int refine_every, int out_fp32,
-    double* __restrict__ wscr, int64_t wstride, const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
+    double* __restrict__ wscr, int64_t wstride, const half8* __restrict__ sfrag, const float* __restrict__ lamtab,
+    unsigned long long* __restrict__ tick) {
   constexpr int NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
   constexpr int PP = dst_pitch(MP);
   constexpr int64_t GE = dst_grid_elems(MP);
@@ -751,7 +752,20 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
     }
   };
 
-  for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
+  // Samples are drawn in order from this workgroup's share of [0, ns), one
+  // share per XCD (consecutive samples, whose strided output rows share
+  // cache lines, stay in one L2), each with a ticket counter that is zero at
+  // launch: workgroups that draw quick solves take more of them, so a
+  // launch waits for its slowest solve rather than its slowest fixed set.
+  const int nsh = gridDim.x < 8 ? (int)gridDim.x : 8, sh = (int)(blockIdx.x % nsh);
+  const int64_t s_lo = ns * sh / nsh, s_hi = ns * (sh + 1) / nsh;
+  __shared__ int64_t s_next;
+  for (;;) {
+    __syncthreads();  // the previous sample is done with LDS, coef and s_next
+    if (threadIdx.x == 0) s_next = s_lo + (int64_t)atomicAdd(&tick[sh], 1ull);
+    __syncthreads();
+    const int64_t s = s_next;
+    if (s >= s_hi) break;
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int q = (tid & 63) >> 4, c = 16 * (tid >> 6) + (tid & 15);
@@ -763,7 +777,6 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
     for (int a = 1; a < nseg; ++a) ks = segs[a].begin <= s ? a : ks;
     const SolveSeg& sg = segs[ks];
     const int64_t sl = s - sg.begin;
-    __syncthreads();  // the previous sample is done with LDS and coef
     load_coef(sg.pde, sg.Y, sl, coef);
     __syncthreads();
     assemble<BLOCK / 64, MP / 4>(sg.pde, coef, EdgesSplit{feh, fev, geh, gev}, dg, PP, tid);
@@ -1877,8 +1890,13 @@ int dst_persistent_blocks(int n, int precision, int variant) {
 }
 
 int64_t dst_scratch_doubles(int n, int variant, int blocks) {
-  return variant == 1 ? 0 : (variant == 2 ? 2 : 3) * dst_edge_stride(dst_padded(n)) * (int64_t)blocks;
+  // variant 2 also keeps its eight ticket counters after the edge slots
+  return variant == 1 ? 0
+                      : (variant == 2 ? 2 : 3) * dst_edge_stride(dst_padded(n)) * (int64_t)blocks + (variant == 2 ? 8 : 0);
 }
+
+// Clears the eight ticket counters of a compact-solver launch.
+__global__ void zero_u64x8_kernel(unsigned long long* p) { p[threadIdx.x] = 0ull; }
 
 void launch_pde_solve_dst(const SolveSeg* segs, int nseg, int n, int precision, int variant, int64_t ns,
                           double rtol, int maxit, double inner_rtol, int refine_every, int out_fp32, double* wscr,
@@ -1897,12 +1915,14 @@ void launch_pde_solve_dst(const SolveSeg* segs, int nseg, int n, int precision, 
   hipLaunchKernelGGL((pcgdst_kernel<TT, MM, LL>), dim3(grid), dim3(4 * MM), lds, st, segs, nseg, ns, rtol, maxit, \
                      inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam)
   if (variant == 2) {
+    unsigned long long* tick = reinterpret_cast<unsigned long long*>(wscr + 2 * ws * (int64_t)wblocks);
+    hipLaunchKernelGGL(zero_u64x8_kernel, dim3(1), dim3(8), 0, st, tick);
     if (mp == 64)
       hipLaunchKernelGGL(pcgdst32c_kernel<64>, dim3(grid), dim3(256), lds, st, segs, nseg, ns, rtol, maxit,
-                         inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam);
+                         inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam, tick);
     else
       hipLaunchKernelGGL(pcgdst32c_kernel<32>, dim3(grid), dim3(128), lds, st, segs, nseg, ns, rtol, maxit,
-                         inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam);
+                         inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam, tick);
   } else if (precision == USFFT_FP64) {
     if (mp == 64) { if (variant) USFFT_DST(double, 64, true); else USFFT_DST(double, 64, false); }
     else { if (variant) USFFT_DST(double, 32, true); else USFFT_DST(double, 32, false); }
