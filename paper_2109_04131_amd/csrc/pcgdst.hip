@@ -456,7 +456,8 @@ template <typename T, int MP, bool LR>
 __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_waves<T, MP, LR>()))) void pcgdst_kernel(
     const SolveSeg* __restrict__ segs, int nseg, int64_t ns, double rtol, int maxit, double inner_rtol,
     int refine_every, int out_fp32,
-    double* __restrict__ wscr, int64_t wstride, const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
+    double* __restrict__ wscr, int64_t wstride, const half8* __restrict__ sfrag, const float* __restrict__ lamtab,
+    unsigned long long* __restrict__ tick) {
   constexpr int NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
   constexpr int PP = dst_pitch(MP);
   constexpr int64_t GE = dst_grid_elems(MP);
@@ -498,7 +499,16 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
     dg[e] = (T)0;  // the halo stays zero: boundary couplings vanish in the scaled weights
   }
 
-  for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
+  // samples drawn from per-XCD ticket counters, as in pcgdst32c_kernel
+  const int nsh = gridDim.x < 8 ? (int)gridDim.x : 8, sh = (int)(blockIdx.x % nsh);
+  const int64_t s_lo = ns * sh / nsh, s_hi = ns * (sh + 1) / nsh;
+  __shared__ int64_t s_next;
+  for (;;) {
+    __syncthreads();  // the previous sample is done with LDS, coef, the edge grids and s_next
+    if (threadIdx.x == 0) s_next = s_lo + (int64_t)atomicAdd(&tick[sh], 1ull);
+    __syncthreads();
+    const int64_t s = s_next;
+    if (s >= s_hi) break;
     // lane coordinates are re-derived per sample (opaque to the optimiser):
     // hoisted out of the sample loop, per-node addresses would spill
     int tid = threadIdx.x;
@@ -516,7 +526,6 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
     for (int a = 1; a < nseg; ++a) ks = segs[a].begin <= s ? a : ks;
     const SolveSeg& sg = segs[ks];
     const int64_t sl = s - sg.begin;
-    __syncthreads();  // the previous sample is done with LDS, coef and the edge grids
     load_coef(sg.pde, sg.Y, sl, coef);
     __syncthreads();
     assemble<BLOCK / 64, LR ? 16 : 8>(sg.pde, coef, EdgesF64{eh, ev}, dg, PP, tid);
@@ -1890,12 +1899,11 @@ int dst_persistent_blocks(int n, int precision, int variant) {
 }
 
 int64_t dst_scratch_doubles(int n, int variant, int blocks) {
-  // variant 2 also keeps its eight ticket counters after the edge slots
-  return variant == 1 ? 0
-                      : (variant == 2 ? 2 : 3) * dst_edge_stride(dst_padded(n)) * (int64_t)blocks + (variant == 2 ? 8 : 0);
+  // the edge slots (none in variant 1), then eight ticket counters
+  return (variant == 1 ? 0 : (variant == 2 ? 2 : 3) * dst_edge_stride(dst_padded(n)) * (int64_t)blocks) + 8;
 }
 
-// Clears the eight ticket counters of a compact-solver launch.
+// Clears the eight ticket counters of a DST-solver launch.
 __global__ void zero_u64x8_kernel(unsigned long long* p) { p[threadIdx.x] = 0ull; }
 
 void launch_pde_solve_dst(const SolveSeg* segs, int nseg, int n, int precision, int variant, int64_t ns,
@@ -1913,10 +1921,11 @@ void launch_pde_solve_dst(const SolveSeg* segs, int nseg, int n, int precision, 
   const half8* sf = static_cast<const half8*>(frag);
 #define USFFT_DST(TT, MM, LL)                                                                                  \
   hipLaunchKernelGGL((pcgdst_kernel<TT, MM, LL>), dim3(grid), dim3(4 * MM), lds, st, segs, nseg, ns, rtol, maxit, \
-                     inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam)
+                     inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam, tick)
+  unsigned long long* tick = reinterpret_cast<unsigned long long*>(
+      wscr + (variant == 1 ? 0 : (variant == 2 ? 2 : 3) * ws * (int64_t)wblocks));
+  hipLaunchKernelGGL(zero_u64x8_kernel, dim3(1), dim3(8), 0, st, tick);
   if (variant == 2) {
-    unsigned long long* tick = reinterpret_cast<unsigned long long*>(wscr + 2 * ws * (int64_t)wblocks);
-    hipLaunchKernelGGL(zero_u64x8_kernel, dim3(1), dim3(8), 0, st, tick);
     if (mp == 64)
       hipLaunchKernelGGL(pcgdst32c_kernel<64>, dim3(grid), dim3(256), lds, st, segs, nseg, ns, rtol, maxit,
                          inner_rtol, refine_every, out_fp32, wscr, ws, sf, lam, tick);
