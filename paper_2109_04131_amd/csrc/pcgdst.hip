@@ -47,6 +47,36 @@
 
 namespace usfft {
 
+// Sample scheduling of the persistent solver kernels.  The samples [0, ns)
+// are split into one contiguous share per XCD (workgroup b serves share
+// b % 8, so consecutive samples, whose strided output rows share cache
+// lines, stay in one L2), and a workgroup takes the next sample of its share
+// from that share's ticket counter (eight counters, zero at launch):
+// workgroups that draw quick solves take more of them, so a launch waits for
+// its slowest solve rather than its slowest fixed set of solves.
+struct Tickets {
+  unsigned long long* ctr;
+  int sh;
+  int64_t lo, hi;
+  __device__ Tickets(unsigned long long* c, int64_t ns) : ctr(c) {
+    const int nsh = gridDim.x < 8 ? (int)gridDim.x : 8;
+    sh = (int)(blockIdx.x % nsh);
+    lo = ns * sh / nsh;
+    hi = ns * (sh + 1) / nsh;
+  }
+  // The workgroup's next sample (>= hi: none left).  Every thread calls it;
+  // its first barrier also ends the previous sample's use of LDS.
+  __device__ int64_t next(int64_t* slot) const {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = lo + (int64_t)atomicAdd(&ctr[sh], 1ull);
+    __syncthreads();
+    return *slot;
+  }
+};
+
+// Clears the eight ticket counters of a solver launch.
+__global__ void zero_u64x8_kernel(unsigned long long* p) { p[threadIdx.x] = 0ull; }
+
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -499,16 +529,11 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(dst_wave
     dg[e] = (T)0;  // the halo stays zero: boundary couplings vanish in the scaled weights
   }
 
-  // samples drawn from per-XCD ticket counters, as in pcgdst32c_kernel
-  const int nsh = gridDim.x < 8 ? (int)gridDim.x : 8, sh = (int)(blockIdx.x % nsh);
-  const int64_t s_lo = ns * sh / nsh, s_hi = ns * (sh + 1) / nsh;
+  const Tickets tk(tick, ns);
   __shared__ int64_t s_next;
   for (;;) {
-    __syncthreads();  // the previous sample is done with LDS, coef, the edge grids and s_next
-    if (threadIdx.x == 0) s_next = s_lo + (int64_t)atomicAdd(&tick[sh], 1ull);
-    __syncthreads();
-    const int64_t s = s_next;
-    if (s >= s_hi) break;
+    const int64_t s = tk.next(&s_next);  // the previous sample is done with LDS, coef and the edge grids
+    if (s >= tk.hi) break;
     // lane coordinates are re-derived per sample (opaque to the optimiser):
     // hoisted out of the sample loop, per-node addresses would spill
     int tid = threadIdx.x;
@@ -761,20 +786,11 @@ __global__ __launch_bounds__(4 * MP) __attribute__((amdgpu_waves_per_eu(MP == 64
     }
   };
 
-  // Samples are drawn in order from this workgroup's share of [0, ns), one
-  // share per XCD (consecutive samples, whose strided output rows share
-  // cache lines, stay in one L2), each with a ticket counter that is zero at
-  // launch: workgroups that draw quick solves take more of them, so a
-  // launch waits for its slowest solve rather than its slowest fixed set.
-  const int nsh = gridDim.x < 8 ? (int)gridDim.x : 8, sh = (int)(blockIdx.x % nsh);
-  const int64_t s_lo = ns * sh / nsh, s_hi = ns * (sh + 1) / nsh;
+  const Tickets tk(tick, ns);
   __shared__ int64_t s_next;
   for (;;) {
-    __syncthreads();  // the previous sample is done with LDS, coef and s_next
-    if (threadIdx.x == 0) s_next = s_lo + (int64_t)atomicAdd(&tick[sh], 1ull);
-    __syncthreads();
-    const int64_t s = s_next;
-    if (s >= s_hi) break;
+    const int64_t s = tk.next(&s_next);  // the previous sample is done with LDS and coef
+    if (s >= tk.hi) break;
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int q = (tid & 63) >> 4, c = 16 * (tid >> 6) + (tid & 15);
@@ -1011,14 +1027,15 @@ int64_t dst_stream_pitch(int n) {
   return (std::max(grid, nodes) + 127) / 128 * 128;
 }
 
+// the per-workgroup slots, then eight ticket counters
 int64_t dst_stream_workspace_doubles(int n, int blocks) {
-  return dst_stream_pitch(n) * kDstStreamArrays * (int64_t)blocks;
+  return dst_stream_pitch(n) * kDstStreamArrays * (int64_t)blocks + 8;
 }
 
 __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
     PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, void* __restrict__ out, int out_fp32,
     int64_t ld, int64_t col0, int* __restrict__ iters, double* __restrict__ ws, int64_t gp,
-    const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
+    const half8* __restrict__ sfrag, const float* __restrict__ lamtab, unsigned long long* __restrict__ tick) {
   constexpr int MP = kDstStreamMP, NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
   constexpr int EH = 8;  // nodes per load chunk of the update passes
   extern __shared__ double lds[];
@@ -1061,8 +1078,11 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgdst_stream_kernel(
   // the direction grid's border (and its padding nodes) is never written
   // afterwards: cleared once per launch
   for (int e = threadIdx.x; e < (MP + 2) * PP; e += BLOCK) p[e] = 0.0f;
-  for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
-    __syncthreads();  // the previous sample is done with coef and the workspace
+  const Tickets tk(tick, ns);
+  __shared__ int64_t s_next;
+  for (;;) {
+    const int64_t s = tk.next(&s_next);  // the previous sample is done with coef and the workspace
+    if (s >= tk.hi) break;
     load_coef(P, Y, s, coef);
     __syncthreads();
     // the coefficient at the centroids of both triangles of every cell
@@ -1420,14 +1440,15 @@ constexpr int kTlRows = 258, kTlPitch = 272;
 
 int64_t tl_stream_pitch() { return ((int64_t)kTlRows * kTlPitch + 127) / 128 * 128; }
 
-int64_t tl_stream_workspace_doubles(int blocks) { return tl_stream_pitch() * 7 * (int64_t)blocks; }
+// the per-workgroup slots, then eight ticket counters
+int64_t tl_stream_workspace_doubles(int blocks) { return tl_stream_pitch() * 7 * (int64_t)blocks + 8; }
 
 bool tl_stream_ok(int n) { return n - 1 > kDstStreamMP && n <= 2 * kDstStreamMP && n % 2 == 0; }
 
 __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
     PdeDev P, const double* __restrict__ Y, int64_t ns, double rtol, int maxit, void* __restrict__ out, int out_fp32,
     int64_t ld, int64_t col0, int* __restrict__ iters, double* __restrict__ ws, int64_t gp,
-    const half8* __restrict__ sfrag, const float* __restrict__ lamtab) {
+    const half8* __restrict__ sfrag, const float* __restrict__ lamtab, unsigned long long* __restrict__ tick) {
   constexpr int MP = kDstStreamMP, NT = MP / 16, KB = MP / 32, E = 4 * NT, BLOCK = 4 * MP, LDX = MP + 4;
   constexpr int PF = kTlPitch;
   extern __shared__ double lds[];
@@ -1543,8 +1564,11 @@ __global__ __launch_bounds__(4 * kDstStreamMP) void pcgtl_stream_kernel(
       }
     }
   };
-  for (int64_t s = xcd_remap(blockIdx.x, gridDim.x); s < ns; s += gridDim.x) {
-    __syncthreads();  // the previous sample is done with coef and the workspace
+  const Tickets tk(tick, ns);
+  __shared__ int64_t s_next;
+  for (;;) {
+    const int64_t s = tk.next(&s_next);  // the previous sample is done with coef and the workspace
+    if (s >= tk.hi) break;
     load_coef(P, Y, s, coef);
     __syncthreads();
     // triangle values T_q[cj PF + ci] of eq. (1.2) (T_0 in the x slot, T_1 in
@@ -1821,9 +1845,11 @@ void launch_pde_solve_tl_stream(const PdeDev& P, const double* Y, int64_t ns, do
   if (ns <= 0) return;
   USFFT_REQUIRE(tl_stream_ok(P.n), USFFT_EINVAL, "mesh outside the two-level streaming solver's range");
   const unsigned grid = (unsigned)std::min<int64_t>(ns, blocks);
+  unsigned long long* tick = reinterpret_cast<unsigned long long*>(ws + tl_stream_workspace_doubles(blocks) - 8);
+  hipLaunchKernelGGL(zero_u64x8_kernel, dim3(1), dim3(8), 0, st, tick);
   hipLaunchKernelGGL(pcgtl_stream_kernel, dim3(grid), dim3(4 * kDstStreamMP), (size_t)dst_stream_lds_bytes(), st,
                      P, Y, ns, rtol, maxit, out, out_fp32, ld, col0, iters, ws, tl_stream_pitch(),
-                     static_cast<const half8*>(frag), lam);
+                     static_cast<const half8*>(frag), lam, tick);
   USFFT_HIP(hipGetLastError());
 }
 
@@ -1852,9 +1878,12 @@ void launch_pde_solve_dst_stream(const PdeDev& P, const double* Y, int64_t ns, d
   if (ns <= 0) return;
   USFFT_REQUIRE(dst_stream_ok(P.n), USFFT_EINVAL, "mesh outside the streaming DST solver's range");
   const unsigned grid = (unsigned)std::min<int64_t>(ns, blocks);
+  unsigned long long* tick =
+      reinterpret_cast<unsigned long long*>(ws + dst_stream_workspace_doubles(P.n, blocks) - 8);
+  hipLaunchKernelGGL(zero_u64x8_kernel, dim3(1), dim3(8), 0, st, tick);
   hipLaunchKernelGGL(pcgdst_stream_kernel, dim3(grid), dim3(4 * kDstStreamMP), (size_t)dst_stream_lds_bytes(), st,
                      P, Y, ns, rtol, maxit, out, out_fp32, ld, col0, iters, ws, dst_stream_pitch(P.n),
-                     static_cast<const half8*>(frag), lam);
+                     static_cast<const half8*>(frag), lam, tick);
   USFFT_HIP(hipGetLastError());
 }
 
@@ -1902,9 +1931,6 @@ int64_t dst_scratch_doubles(int n, int variant, int blocks) {
   // the edge slots (none in variant 1), then eight ticket counters
   return (variant == 1 ? 0 : (variant == 2 ? 2 : 3) * dst_edge_stride(dst_padded(n)) * (int64_t)blocks) + 8;
 }
-
-// Clears the eight ticket counters of a DST-solver launch.
-__global__ void zero_u64x8_kernel(unsigned long long* p) { p[threadIdx.x] = 0ull; }
 
 void launch_pde_solve_dst(const SolveSeg* segs, int nseg, int n, int precision, int variant, int64_t ns,
                           double rtol, int maxit, double inner_rtol, int refine_every, int out_fp32, double* wscr,
