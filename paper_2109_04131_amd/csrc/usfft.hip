@@ -103,6 +103,11 @@ struct Family {
   std::vector<int32_t> z;  // nlat x t
   std::vector<int64_t> off;
   std::vector<int32_t> lat_first, lat_count;  // slices of the grouped (pos, bin) lists
+  // the family's offsets, sizes and generators on the device (uploaded with
+  // the grouped lists by group_by_lattice)
+  const int64_t* d_off = nullptr;
+  const int32_t* d_M = nullptr;
+  const int32_t* d_z = nullptr;
   int t = 0;
   int64_t total() const { return off.empty() ? 0 : off.back(); }
 };
@@ -161,8 +166,8 @@ struct usfft_plan_s {
   bool ws_mode = false;
   int64_t ws_nsamp = 0, ws_ncand = 0;
   // workspaces (grown on demand, kept across calls)
-  usfft::DevBuf Y, U, V, iters, cnt, theta2, scratch, J, Jnext, Iprev, mask, gmask, cands, assign, bins, famz, fambins,
-      famcounts, famcov, famscores, lists, latM, latz, latoff, tail, latitems;
+  usfft::DevBuf Y, U, V, iters, cnt, theta2, scratch, J, Jnext, Iprev, mask, gmask, cands, assign, famz, fambins,
+      famcounts, famcov, famscores, lists, latM, latoff, tail, latitems;
   std::vector<usfft::DevBuf> I1;  // step-1 sets per coordinate
   std::vector<int64_t> I1n;
   std::mutex mu;
@@ -405,14 +410,21 @@ static void plan_family(usfft_plan_s* P, const int32_t* J, int64_t n, int t, uin
   }
 }
 
-// Group candidates by lattice: pos lists (ascending) and bins, uploaded to P->lists.
+// Group candidates by lattice: pos lists (ascending) and bins, uploaded to
+// P->lists in one copy together with the family's offsets, sizes and
+// generators (F.d_off, F.d_M, F.d_z point into it).  bins = assign + n reads
+// both back in one copy.
 static void group_by_lattice(usfft_plan_s* P, Family& F, const int32_t* assign, const int32_t* bins, int64_t n,
                              hipStream_t st) {
   int32_t* ha = reinterpret_cast<int32_t*>(back_buffer(P, 2 * sizeof(int32_t) * std::max<int64_t>(n, 1)));
   int32_t* hb = ha + n;
   if (n > 0) {
-    USFFT_HIP(hipMemcpyAsync(ha, assign, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
-    USFFT_HIP(hipMemcpyAsync(hb, bins, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    if (bins == assign + n) {
+      USFFT_HIP(hipMemcpyAsync(ha, assign, 2 * sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    } else {
+      USFFT_HIP(hipMemcpyAsync(ha, assign, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+      USFFT_HIP(hipMemcpyAsync(hb, bins, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    }
     USFFT_HIP(hipStreamSynchronize(st));
   }
   const int nl = (int)F.M.size();
@@ -428,7 +440,19 @@ static void group_by_lattice(usfft_plan_s* P, Family& F, const int32_t* assign, 
     lists[n + fill[l]] = hb[a];   // bins
     fill[l]++;
   }
-  h2d_async(P, P->lists, lists, st);
+  const size_t lb = sizeof(int32_t) * lists.size();
+  const size_t o_off = (lb + 7) / 8 * 8;
+  const size_t o_M = o_off + sizeof(int64_t) * F.off.size();
+  const size_t o_z = o_M + sizeof(int32_t) * F.M.size();
+  std::vector<char> pack(o_z + sizeof(int32_t) * F.z.size());
+  std::memcpy(pack.data(), lists.data(), lb);
+  std::memcpy(pack.data() + o_off, F.off.data(), sizeof(int64_t) * F.off.size());
+  if (!F.M.empty()) std::memcpy(pack.data() + o_M, F.M.data(), sizeof(int32_t) * F.M.size());
+  if (!F.z.empty()) std::memcpy(pack.data() + o_z, F.z.data(), sizeof(int32_t) * F.z.size());
+  h2d_async(P, P->lists, pack, st);
+  F.d_off = reinterpret_cast<const int64_t*>(P->lists.as<char>() + o_off);
+  F.d_M = reinterpret_cast<const int32_t*>(P->lists.as<char>() + o_M);
+  F.d_z = reinterpret_cast<const int32_t*>(P->lists.as<char>() + o_z);
 }
 
 // One solver launch at the mesh's own nodes.  params: Y holds parameters y
@@ -863,6 +887,18 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     }
 
     // ---------------- step 2
+    {
+      // the tails of every increment's iterations, uploaded once: increment t
+      // (1 <= t < d), iteration i at ((t - 1) r + i) d
+      std::vector<double> tails((size_t)(d > 1 ? d - 1 : 0) * par.r * d);
+      for (int t = 1; t < d; ++t) {
+        const int r_t = t == d - 1 ? 1 : par.r;
+        for (int i = 0; i < r_t; ++i)
+          for (int j = 0; j < d; ++j)
+            tails[((size_t)(t - 1) * par.r + i) * d + j] = rng::uniform01(seed, rng::stream(rng::kTail2, t + 1, i + 1, 0), j);
+      }
+      h2d_async(P, P->tail, tails, st);
+    }
     nprev = P->I1n[0];
     P->Iprev.ensure(sizeof(int32_t) * std::max<int64_t>(nprev, 1));
     if (nprev > 0)
@@ -889,17 +925,13 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
                         " candidates; the workspace holds " + std::to_string(P->ws_ncand) + " (raise n_cand_max)");
       P->J.ensure(sizeof(int32_t) * n * w);
       launch_product(P->Iprev.as<int32_t>(), nprev, t, P->I1[t].as<int32_t>(), nc, P->J.as<int32_t>(), st);
-      P->assign.ensure(sizeof(int32_t) * n);
-      P->bins.ensure(sizeof(int32_t) * n);
+      P->assign.ensure(2 * sizeof(int32_t) * n);  // assignments, then bins
       plan_family(P, P->J.as<int32_t>(), n, w, seed, rng::kLat2, w, F, P->assign.as<int32_t>(),
-                  P->bins.as<int32_t>(), st);
-      group_by_lattice(P, F, P->assign.as<int32_t>(), P->bins.as<int32_t>(), n, st);
+                  P->assign.as<int32_t>() + n, st);
+      group_by_lattice(P, F, P->assign.as<int32_t>(), P->assign.as<int32_t>() + n, n, st);
       S.lattices += (int64_t)F.M.size();
       for (int M : F.M) (void)rader_for(P, M, st);
       const int64_t ns = F.total();
-      h2d_async(P, P->latM, F.M, st);
-      h2d_async(P, P->latz, F.z, st);
-      h2d_async(P, P->latoff, F.off, st);
       // V holds the stage's magnitudes in lattice-grouped candidate order (each
       // lattice's bins contiguous per node); the mask is built in that order and
       // mapped back to candidate order before compaction.
@@ -927,13 +959,9 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
         P->U.ensure(ub * G * ldb);
         P->Y.ensure(sizeof(double) * nsb * d);
         P->iters.ensure(sizeof(int32_t) * nsb);
-        std::vector<double> tails((size_t)nb * d);
-        for (int b = 0; b < nb; ++b)
-          for (int j = 0; j < d; ++j)
-            tails[(size_t)b * d + j] = rng::uniform01(seed, rng::stream(rng::kTail2, t + 1, i0 + b + 1, 0), j);
-        h2d_async(P, P->tail, tails, st);
-        launch_lattice_nodes_rep(d, w, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(),
-                                 P->latz.as<int32_t>(), P->tail.as<double>(), P->Y.as<double>(), ns, nb, st);
+        launch_lattice_nodes_rep(d, w, (int)F.M.size(), F.d_off, F.d_M, F.d_z,
+                                 P->tail.as<double>() + ((size_t)(t - 1) * par.r + i0) * d, P->Y.as<double>(), ns,
+                                 nb, st);
         sample_timed(P->Y.as<double>(), nsb, ldb);
         S.samples_step2 += nsb;
         // every lattice of every iteration of the batch in one DFT launch
@@ -1013,11 +1041,10 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
   result_buffer(R, sizeof(double) * 2 * std::max<int64_t>(nI, 1) * G);
   if (nI > 0) {
     USFFT_HIP(hipMemcpyAsync(R->I.data(), P->Iprev.p, sizeof(int32_t) * nI * d, hipMemcpyDeviceToHost, st));
-    P->assign.ensure(sizeof(int32_t) * nI);
-    P->bins.ensure(sizeof(int32_t) * nI);
+    P->assign.ensure(2 * sizeof(int32_t) * nI);  // assignments, then bins
     plan_family(P, P->Iprev.as<int32_t>(), nI, d, seed, rng::kLat3, 0, F, P->assign.as<int32_t>(),
-                P->bins.as<int32_t>(), st);
-    group_by_lattice(P, F, P->assign.as<int32_t>(), P->bins.as<int32_t>(), nI, st);
+                P->assign.as<int32_t>() + nI, st);
+    group_by_lattice(P, F, P->assign.as<int32_t>(), P->assign.as<int32_t>() + nI, nI, st);
     S.lattices += (int64_t)F.M.size();
     for (int M : F.M) (void)rader_for(P, M, st);
     const int64_t ns = F.total();
@@ -1029,11 +1056,7 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     P->U.ensure(ub * G * ld);
     P->Y.ensure(sizeof(double) * ns * d);
     P->iters.ensure(sizeof(int32_t) * ns);
-    h2d_async(P, P->latM, F.M, st);
-    h2d_async(P, P->latz, F.z, st);
-    h2d_async(P, P->latoff, F.off, st);
-    launch_nodes(d, -1, d, (int)F.M.size(), P->latoff.as<int64_t>(), P->latM.as<int32_t>(), P->latz.as<int32_t>(),
-                 P->tail.as<double>(), P->Y.as<double>(), ns, st);
+    launch_nodes(d, -1, d, (int)F.M.size(), F.d_off, F.d_M, F.d_z, P->tail.as<double>(), P->Y.as<double>(), ns, st);
     sample_timed(P->Y.as<double>(), ns, ld);
     S.samples_step3 += ns;
     std::vector<LatItem> items;
@@ -1142,16 +1165,14 @@ static std::vector<WsItem> ws_items(usfft_plan_s* P, DevBuf* C, int64_t ncand, i
       {&P->tail, sz(8 * std::max<int64_t>(kMaxD, d * r * d))},
       {&P->cands, sz(4 * sumK)},
       {&P->latM, sz(4 * std::max(d, Lm))},
-      {&P->latz, sz(4 * Lm * d)},
       {&P->latoff, sz(8 * (std::max(nl, Lm) + 1))},
       {&P->mask, sz(4 * std::max(woff, ceil_div(nc, 32)))},
       {&P->gmask, sz(4 * ceil_div(nc, 32))},
       {&P->J, sz(4 * nc * d)},
       {&P->Jnext, sz(4 * nc * d)},
       {&P->Iprev, sz(4 * nc * d)},
-      {&P->assign, sz(4 * nc)},
-      {&P->bins, sz(4 * nc)},
-      {&P->lists, sz(8 * nc)},
+      {&P->assign, sz(8 * nc)},
+      {&P->lists, sz(8 * nc + 8 * (Lm + 2) + 4 * Lm * (d + 1))},
       {&P->famcov, sz(nc)},
       {&P->fambins, sz(4 * nc * T)},
       {&P->famscores, sz(4 * T)},
@@ -2558,8 +2579,8 @@ static uint64_t plan_bytes(const usfft_plan_s* P) {
                           &P->d_lam, &P->m_rowptr, &P->m_col, &P->m_diag, &P->m_cptr, &P->m_ctri, &P->m_cw, &P->m_load,
                           &P->m_psi, &P->d_iidx, &P->d_iw, &P->Umesh, &P->d_rader, &P->famlog, &P->famstate, &P->Y,
                           &P->U, &P->V, &P->iters, &P->cnt, &P->theta2, &P->scratch, &P->J, &P->Jnext, &P->Iprev,
-                          &P->mask, &P->gmask, &P->cands, &P->assign, &P->bins, &P->famz, &P->fambins, &P->famcounts,
-                          &P->famcov, &P->famscores, &P->lists, &P->latM, &P->latz, &P->latoff, &P->tail,
+                          &P->mask, &P->gmask, &P->cands, &P->assign, &P->famz, &P->fambins, &P->famcounts,
+                          &P->famcov, &P->famscores, &P->lists, &P->latM, &P->latoff, &P->tail,
                           &P->latitems})
     b += x->bytes;
   for (const DevBuf& x : P->I1) b += x.bytes;
