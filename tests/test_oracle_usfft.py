@@ -140,3 +140,27 @@ def test_pde_run_against_full_grid_fourier_coefficients(d, N, P, theta):
            if np.abs(F[cell([v - N for v in k])]).max() >= 10 * th]
     assert {tuple(v - N for v in k) for k in big} <= set(I)
     assert len(big) > 10
+
+
+def test_relative_threshold_reading_first_stage():
+    # Reading of the relative threshold: theta_abs = theta_rel * max |u^_k(x_g)|
+    # over the first detection stage (coordinate 1, iteration 1).  Rebuilt
+    # here from the stage's definition (nodes l / K in coordinate 1, the
+    # iteration's seeded tail elsewhere) with numpy's FFT in place of the
+    # oracle's DFT, over every node and all K bins.
+    from oracle import rng
+    prob = W.pde_problem(8, 3, 4)
+    S = fem.PDESampler(prob["mesh_n"], prob["a0"], prob["amp"], prob["mode1"], prob["mode2"])
+    d, theta, seed = prob["d"], 1e-3, 7
+    res = usfft(S, d, prob["k_lo"], prob["k_hi"], 20, 20, 2, theta, True, seed)
+    K = prob["k_hi"][0] - prob["k_lo"][0] + 1
+    code = rng.stream_code(rng.KIND_TAIL1, 1, 1)
+    Y = np.array([[l / K if j == 0 else rng.uniform01(seed, code, j) for j in range(d)] for l in range(K)])
+    F = np.fft.fft(S(Y), axis=0) / K
+    want = theta ** 2 * (np.abs(F) ** 2).max()
+    assert abs(res.theta2 - want) <= 1e-12 * want
+    # a later stage's maximum gives a different threshold
+    code2 = rng.stream_code(rng.KIND_TAIL1, 2, 1)
+    Y2 = np.array([[l / K if j == 1 else rng.uniform01(seed, code2, j) for j in range(d)] for l in range(K)])
+    F2 = np.fft.fft(S(Y2), axis=0) / K
+    assert abs(theta ** 2 * (np.abs(F2) ** 2).max() - want) > 1e-9 * want
