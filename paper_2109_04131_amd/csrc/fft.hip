@@ -222,17 +222,19 @@ __device__ __forceinline__ int div_small(int b, int M, float rM) {
 template <typename T, int R, int BLOCK, int COLS, bool MB>
 __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw,
                           const cplx<T>* __restrict__ mulB) {
-  const int nb = L / R, ts = L / N;
+  const int nb = L / R;
   const float rM = __builtin_amdgcn_rcpf((float)M);
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
     const int blk = div_small(b, M, rM), j = b - blk * M, base = blk * N + j;
+    // this butterfly's R - 1 twiddles, contiguous in the stage's table
+    const cplx<T>* twj = tw + j * (R - 1);
     // twiddles held for all columns, except the float64 radices above 8
     // (their registers would not fit), which read each one where it is used
     constexpr bool WREG = sizeof(T) == 4 || R <= 8;
     cplx<T> w[R], bq[R];
     if constexpr (WREG) {
 #pragma unroll
-      for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
+      for (int q = 1; q < R; ++q) w[q] = twj[q - 1];
     }
     if constexpr (MB) {
 #pragma unroll
@@ -250,7 +252,7 @@ __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         cplx<T> o = v[q];
-        if (q > 0) o = cmul(o, WREG ? w[q] : tw[j * q * ts]);
+        if (q > 0) o = cmul(o, WREG ? w[q] : twj[q - 1]);
         if constexpr (MB) o = conjc(cmul(o, bq[q]));
         bc[base + q * M] = o;
       }
@@ -261,15 +263,16 @@ __device__ void dif_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
 
 template <typename T, int R, int BLOCK, int COLS>
 __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __restrict__ tw) {
-  const int nb = L / R, ts = L / N;
+  const int nb = L / R;
   const float rM = __builtin_amdgcn_rcpf((float)M);
   for (int b = threadIdx.x; b < nb; b += BLOCK) {
     const int blk = div_small(b, M, rM), j = b - blk * M, base = blk * N + j;
+    const cplx<T>* twj = tw + j * (R - 1);       // as in dif_stage
     constexpr bool WREG = sizeof(T) == 4 || R <= 8;  // as in dif_stage
     cplx<T> w[R];
     if constexpr (WREG) {
 #pragma unroll
-      for (int q = 1; q < R; ++q) w[q] = tw[j * q * ts];
+      for (int q = 1; q < R; ++q) w[q] = twj[q - 1];
     }
 #pragma unroll 1
     for (int c = 0; c < COLS; ++c) {
@@ -278,7 +281,7 @@ __device__ void dit_stage(cplx<T>* buf, int L, int N, int M, const cplx<T>* __re
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         cplx<T> a = bc[base + q * M];
-        if (q > 0) a = cmul(a, WREG ? w[q] : tw[j * q * ts]);
+        if (q > 0) a = cmul(a, WREG ? w[q] : twj[q - 1]);
         v[q] = a;
       }
       dft_small<T, R>(v);
@@ -303,25 +306,25 @@ __device__ void fft_dif(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw, co
     // the spectrum product is compiled only into the last stage
     if (s == F.nrad - 1 && mulB) {
       switch (R) {
-        case 2: dif_stage<T, 2, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
-        case 3: dif_stage<T, 3, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
-        case 4: dif_stage<T, 4, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
-        case 5: dif_stage<T, 5, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
-        case 7: dif_stage<T, 7, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
-        case 9: if constexpr (WIDE) dif_stage<T, 9, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
-        case 16: if constexpr (WIDE) dif_stage<T, 16, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
-        default: dif_stage<T, 8, BLOCK, COLS, true>(buf, F.L, N, M, tw, mulB); break;
+        case 2: dif_stage<T, 2, BLOCK, COLS, true>(buf, F.L, N, M, tw + F.twoff[s], mulB); break;
+        case 3: dif_stage<T, 3, BLOCK, COLS, true>(buf, F.L, N, M, tw + F.twoff[s], mulB); break;
+        case 4: dif_stage<T, 4, BLOCK, COLS, true>(buf, F.L, N, M, tw + F.twoff[s], mulB); break;
+        case 5: dif_stage<T, 5, BLOCK, COLS, true>(buf, F.L, N, M, tw + F.twoff[s], mulB); break;
+        case 7: dif_stage<T, 7, BLOCK, COLS, true>(buf, F.L, N, M, tw + F.twoff[s], mulB); break;
+        case 9: if constexpr (WIDE) dif_stage<T, 9, BLOCK, COLS, true>(buf, F.L, N, M, tw + F.twoff[s], mulB); break;
+        case 16: if constexpr (WIDE) dif_stage<T, 16, BLOCK, COLS, true>(buf, F.L, N, M, tw + F.twoff[s], mulB); break;
+        default: dif_stage<T, 8, BLOCK, COLS, true>(buf, F.L, N, M, tw + F.twoff[s], mulB); break;
       }
     } else {
       switch (R) {
-        case 2: dif_stage<T, 2, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
-        case 3: dif_stage<T, 3, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
-        case 4: dif_stage<T, 4, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
-        case 5: dif_stage<T, 5, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
-        case 7: dif_stage<T, 7, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
-        case 9: if constexpr (WIDE) dif_stage<T, 9, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
-        case 16: if constexpr (WIDE) dif_stage<T, 16, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
-        default: dif_stage<T, 8, BLOCK, COLS, false>(buf, F.L, N, M, tw, nullptr); break;
+        case 2: dif_stage<T, 2, BLOCK, COLS, false>(buf, F.L, N, M, tw + F.twoff[s], nullptr); break;
+        case 3: dif_stage<T, 3, BLOCK, COLS, false>(buf, F.L, N, M, tw + F.twoff[s], nullptr); break;
+        case 4: dif_stage<T, 4, BLOCK, COLS, false>(buf, F.L, N, M, tw + F.twoff[s], nullptr); break;
+        case 5: dif_stage<T, 5, BLOCK, COLS, false>(buf, F.L, N, M, tw + F.twoff[s], nullptr); break;
+        case 7: dif_stage<T, 7, BLOCK, COLS, false>(buf, F.L, N, M, tw + F.twoff[s], nullptr); break;
+        case 9: if constexpr (WIDE) dif_stage<T, 9, BLOCK, COLS, false>(buf, F.L, N, M, tw + F.twoff[s], nullptr); break;
+        case 16: if constexpr (WIDE) dif_stage<T, 16, BLOCK, COLS, false>(buf, F.L, N, M, tw + F.twoff[s], nullptr); break;
+        default: dif_stage<T, 8, BLOCK, COLS, false>(buf, F.L, N, M, tw + F.twoff[s], nullptr); break;
       }
     }
     N = M;
@@ -340,14 +343,14 @@ __device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
   for (int s = F.nrad - 1; s >= 0; --s) {
     const int R = F.radix[s], Nn = Ns[s], M = Nn / R;
     switch (R) {
-      case 2: dit_stage<T, 2, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
-      case 3: dit_stage<T, 3, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
-      case 4: dit_stage<T, 4, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
-      case 5: dit_stage<T, 5, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
-      case 7: dit_stage<T, 7, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
-      case 9: if constexpr (WIDE) dit_stage<T, 9, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
-      case 16: if constexpr (WIDE) dit_stage<T, 16, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
-      default: dit_stage<T, 8, BLOCK, COLS>(buf, F.L, Nn, M, tw); break;
+      case 2: dit_stage<T, 2, BLOCK, COLS>(buf, F.L, Nn, M, tw + F.twoff[s]); break;
+      case 3: dit_stage<T, 3, BLOCK, COLS>(buf, F.L, Nn, M, tw + F.twoff[s]); break;
+      case 4: dit_stage<T, 4, BLOCK, COLS>(buf, F.L, Nn, M, tw + F.twoff[s]); break;
+      case 5: dit_stage<T, 5, BLOCK, COLS>(buf, F.L, Nn, M, tw + F.twoff[s]); break;
+      case 7: dit_stage<T, 7, BLOCK, COLS>(buf, F.L, Nn, M, tw + F.twoff[s]); break;
+      case 9: if constexpr (WIDE) dit_stage<T, 9, BLOCK, COLS>(buf, F.L, Nn, M, tw + F.twoff[s]); break;
+      case 16: if constexpr (WIDE) dit_stage<T, 16, BLOCK, COLS>(buf, F.L, Nn, M, tw + F.twoff[s]); break;
+      default: dit_stage<T, 8, BLOCK, COLS>(buf, F.L, Nn, M, tw + F.twoff[s]); break;
     }
   }
 }
@@ -360,8 +363,7 @@ __device__ void fft_dit(cplx<T>* buf, const FftPlanDev& F, const cplx<T>* tw) {
 __global__ __launch_bounds__(kFftBlock) void rader_setup_kernel(FftPlanDev F, int M, const int32_t* __restrict__ perm,
                                                                const cplx<double>* __restrict__ tw,
                                                                cplx<double>* __restrict__ B64,
-                                                               cplx<float>* __restrict__ B32,
-                                                               cplx<float>* __restrict__ tw32, int in_lds) {
+                                                               cplx<float>* __restrict__ B32, int in_lds) {
   extern __shared__ char smem[];
   cplx<double>* buf = in_lds ? reinterpret_cast<cplx<double>*>(smem) : B64;
   const int L = F.L;
@@ -378,7 +380,6 @@ __global__ __launch_bounds__(kFftBlock) void rader_setup_kernel(FftPlanDev F, in
     const cplx<double> v = {buf[k].x * invL, buf[k].y * invL};
     B64[k] = v;
     B32[k] = {(float)v.x, (float)v.y};
-    tw32[k] = {(float)tw[k].x, (float)tw[k].y};
   }
 }
 
@@ -417,10 +418,10 @@ struct RaderLayout {
     o += align256(sizeof(int32_t) * M);
     dlog = o;
     o += align256(sizeof(int32_t) * M);
-    tw64 = o;
-    o += align256(sizeof(cplx<double>) * L);
+    tw64 = o;  // stage twiddles: fewer than 2 L per precision
+    o += align256(sizeof(cplx<double>) * 2 * L);
     tw32 = o;
-    o += align256(sizeof(cplx<float>) * L);
+    o += align256(sizeof(cplx<float>) * 2 * L);
     B64 = o;
     o += align256(sizeof(cplx<double>) * L);
     B32 = o;
@@ -519,6 +520,22 @@ void rader_build_at(RaderTables& T, int M, bool wide, void* mem, hipStream_t st)
     const double a = -2.0 * M_PI * (double)k / (double)L;
     tw[k] = {std::cos(a), std::sin(a)};
   }
+  // stage twiddles of the radix plan (the forward DIF stages and, in
+  // reverse, the DIT stages use the same factors)
+  std::vector<cplx<double>> st64;
+  {
+    int N = L;
+    for (int s = 0; s < T.nrad; ++s) {
+      const int R = T.radix[s], Ms = N / R, ts = L / N;
+      T.twoff[s] = (int)st64.size();
+      for (int j = 0; j < Ms; ++j)
+        for (int q = 1; q < R; ++q) st64.push_back(tw[(size_t)j * q * ts]);
+      N = Ms;
+    }
+  }
+  USFFT_REQUIRE(st64.size() <= 2 * (size_t)L, USFFT_EINVAL, "stage twiddle table overflow");
+  std::vector<cplx<float>> st32(st64.size());
+  for (size_t k = 0; k < st64.size(); ++k) st32[k] = {(float)st64[k].x, (float)st64[k].y};
   T.perm = reinterpret_cast<int32_t*>(base + Lay.perm);
   T.outidx = reinterpret_cast<int32_t*>(base + Lay.outidx);
   T.dlog = reinterpret_cast<int32_t*>(base + Lay.dlog);
@@ -529,15 +546,19 @@ void rader_build_at(RaderTables& T, int M, bool wide, void* mem, hipStream_t st)
   USFFT_HIP(hipMemcpyAsync(T.perm, perm.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, st));
   USFFT_HIP(hipMemcpyAsync(T.outidx, outidx.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
   USFFT_HIP(hipMemcpyAsync(T.dlog, dlog.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, st));
-  USFFT_HIP(hipMemcpyAsync(T.tw64, tw.data(), sizeof(cplx<double>) * L, hipMemcpyHostToDevice, st));
+  USFFT_HIP(hipMemcpyAsync(T.tw64, st64.data(), sizeof(cplx<double>) * st64.size(), hipMemcpyHostToDevice, st));
+  USFFT_HIP(hipMemcpyAsync(T.tw32, st32.data(), sizeof(cplx<float>) * st32.size(), hipMemcpyHostToDevice, st));
   FftPlanDev F;
   F.L = L;
   F.nrad = T.nrad;
-  for (int i = 0; i < 24; ++i) F.radix[i] = T.radix[i];
+  for (int i = 0; i < 24; ++i) {
+    F.radix[i] = T.radix[i];
+    F.twoff[i] = T.twoff[i];
+  }
   const bool in_lds = sizeof(cplx<double>) * (size_t)L <= (150u << 10);
   hipLaunchKernelGGL(rader_setup_kernel, dim3(1), dim3(kFftBlock), in_lds ? sizeof(cplx<double>) * L : 0, st, F, M,
                      T.perm, (const cplx<double>*)T.tw64, (cplx<double>*)T.B64, (cplx<float>*)T.B32,
-                     (cplx<float>*)T.tw32, in_lds ? 1 : 0);
+                     in_lds ? 1 : 0);
   USFFT_HIP(hipGetLastError());
   USFFT_HIP(hipStreamSynchronize(st));  // host vectors above go out of scope
 }
@@ -745,7 +766,10 @@ void launch_lattice_dft(const RaderTables& T, const void* u, int u_fp32, int64_t
   FftPlanDev F;
   F.L = T.L;
   F.nrad = T.nrad;
-  for (int i = 0; i < 24; ++i) F.radix[i] = T.radix[i];
+  for (int i = 0; i < 24; ++i) {
+    F.radix[i] = T.radix[i];
+    F.twoff[i] = T.twoff[i];
+  }
   // workgroup sized to the transform (about L / 8 butterflies per radix-8
   // stage); several node pairs per workgroup while their transforms fit in
   // 64 KB of LDS, so twiddle and spectrum loads serve several columns
@@ -796,7 +820,10 @@ static void rader_shape(int Lmax, int u_fp32, int* block, int* cols, size_t* lds
 void fill_lat_item(LatItem& it, const RaderTables& T, int u_fp32) {
   it.F.L = T.L;
   it.F.nrad = T.nrad;
-  for (int i = 0; i < 24; ++i) it.F.radix[i] = T.radix[i];
+  for (int i = 0; i < 24; ++i) {
+    it.F.radix[i] = T.radix[i];
+    it.F.twoff[i] = T.twoff[i];
+  }
   it.M = T.M;
   it.dlog = T.dlog;
   it.outidx = T.outidx;

@@ -136,8 +136,13 @@ struct RaderTables {
   int32_t* perm = nullptr;    // L: gen^q mod M
   int32_t* dlog = nullptr;    // M: q with gen^q = m (entry 0 unused)
   int32_t* outidx = nullptr;  // M: index p with b = gen^(-p) mod M (entry 0 unused)
-  void* tw64 = nullptr;       // L complex double: exp(-2 pi i k / L)
-  void* tw32 = nullptr;       // L complex float
+  // twiddles exp(-2 pi i j q ts / L) of every radix stage s (block size N_s,
+  // R_s, M_s = N_s / R_s, ts = L / N_s), stage-major: stage s from
+  // element twoff[s], butterfly j's R_s - 1 factors (q = 1 .. R_s - 1)
+  // contiguous at j (R_s - 1); at most 2 L elements
+  int twoff[24] = {0};
+  void* tw64 = nullptr;       // complex double
+  void* tw32 = nullptr;       // complex float, the same values rounded
   void* B64 = nullptr;        // L complex double: DFT_L(b) / L, b_j = exp(-2 pi i gen^(-j) / M)
   void* B32 = nullptr;        // L complex float
 };
@@ -145,6 +150,7 @@ struct RaderTables {
 struct FftPlanDev {
   int L, nrad;
   int radix[24];
+  int twoff[24];  // first element of each stage's twiddles (RaderTables::twoff)
 };
 // One lattice DFT of a batched launch: the tables of its size, its samples
 // (columns col0 .. col0 + M of every node row), the bins of its candidates
