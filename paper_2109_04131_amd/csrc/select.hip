@@ -74,12 +74,12 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
       constexpr int U = 8;
       for (int64_t a0 = threadIdx.x; a0 < n; a0 += U * kSelBlock) {
         uint64_t k[U];
-        #pragma unroll
+#pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t a = a0 + u * kSelBlock;
           k[u] = a < n ? gkeys[a] : 0ull;
         }
-        #pragma unroll
+#pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t a = a0 + u * kSelBlock;
           if (a < n) {
@@ -92,12 +92,12 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
       for (int64_t a = threadIdx.x; a < n; a += kSelBlock)
         above += keepf * __longlong_as_double((long long)gkeys[a]) >= theta2;
     }
-    #pragma unroll
+#pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) above += __shfl_xor(above, o, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) wabove[threadIdx.x / kWave] = above;
     __syncthreads();
     above = 0;
-    #pragma unroll
+#pragma unroll
     for (int w = 0; w < kSelBlock / kWave; ++w) above += wabove[w];
     const uint64_t* keys = STAGE ? stage : gkeys;
     double tau2 = 0.0;
@@ -133,11 +133,11 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
           // count of larger keys, exactly one lane contains the rank.
           const int l = threadIdx.x;
           uint32_t h[4];
-          #pragma unroll
+#pragma unroll
           for (int i = 0; i < 4; ++i) h[i] = hist[255 - 4 * l - i];
           const uint32_t c = h[0] + h[1] + h[2] + h[3];
           uint32_t inc = c;
-          #pragma unroll
+#pragma unroll
           for (int o = 1; o < kWave; o <<= 1) {
             const uint32_t t = __shfl_up(inc, o, kWave);
             if (l >= o) inc += t;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kSelBlock) void select_kernel(const double* __restr
           const int64_t exc = (int64_t)(inc - c);
           if (exc < rank && (int64_t)inc >= rank) {
             int64_t acc = exc;
-            #pragma unroll
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
               if (acc + h[i] >= rank) {
                 s_prefix = prefix | ((uint64_t)(255 - 4 * l - i) << shift);
