@@ -761,7 +761,7 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
   };
   const auto t0 = std::chrono::steady_clock::now();
 
-  P->cnt.ensure(2 * sizeof(unsigned long long));
+  P->cnt.ensure(3 * sizeof(unsigned long long));
   USFFT_HIP(hipMemsetAsync(P->cnt.p, 0, 2 * sizeof(unsigned long long), st));
   P->theta2.ensure(sizeof(double));
   P->scratch.ensure(64);
@@ -771,13 +771,17 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
     USFFT_HIP(hipStreamSynchronize(st));
   }
   P->tail.ensure(sizeof(double) * kMaxD);
-  auto check_conv = [&]() {
-    unsigned long long h[2];
-    USFFT_HIP(hipMemcpyAsync(h, P->cnt.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  // P->cnt: (solves that missed pcg_rtol, PCG iterations, rows kept by the
+  // last step-2 compaction); one pinned readback of all three
+  auto check_conv = [&]() -> int64_t {
+    const unsigned long long* h = reinterpret_cast<const unsigned long long*>(back_buffer(P, 3 * sizeof(int64_t)));
+    USFFT_HIP(hipMemcpyAsync(const_cast<unsigned long long*>(h), P->cnt.p, 3 * sizeof(int64_t),
+                             hipMemcpyDeviceToHost, st));
     USFFT_HIP(hipStreamSynchronize(st));
     S.pcg_iterations = (int64_t)h[1];
     USFFT_REQUIRE(h[0] == 0, USFFT_ENOCONV,
                   std::to_string(h[0]) + " PCG solves missed pcg_rtol within pcg_maxit");
+    return (int64_t)h[2];
   };
 
   int64_t nprev = 0;
@@ -1002,10 +1006,8 @@ static void detect(usfft_plan_s* P, uint64_t seed, hipStream_t st, usfft_result_
       launch_ungroup_mask(P->gmask.as<uint32_t>(), P->lists.as<int32_t>(), n, P->mask.as<uint32_t>(), st);
       P->Jnext.ensure(sizeof(int32_t) * n * w);
       launch_compact(P->J.as<int32_t>(), P->mask.as<uint32_t>(), n, w, P->Jnext.as<int32_t>(),
-                     reinterpret_cast<int64_t*>(P->scratch.as<char>() + 32), st);
-      int64_t cntI = 0;
-      USFFT_HIP(hipMemcpyAsync(&cntI, P->scratch.as<char>() + 32, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-      check_conv();
+                     reinterpret_cast<int64_t*>(P->cnt.as<char>() + 2 * sizeof(int64_t)), st);
+      const int64_t cntI = check_conv();
       std::swap(P->Iprev, P->Jnext);
       nprev = cntI;
       if (progress_log()) {
@@ -1159,7 +1161,7 @@ static std::vector<WsItem> ws_items(usfft_plan_s* P, DevBuf* C, int64_t ncand, i
       {&P->latitems, sz((int64_t)sizeof(LatItem) * std::max<int64_t>(r, 1) * Lm)},
       {&P->Y, sz(8 * d * nsb)},
       {&P->iters, sz(4 * nsb)},
-      {&P->cnt, sz(16)},
+      {&P->cnt, sz(24)},
       {&P->theta2, sz(8)},
       {&P->scratch, sz(32 + 8 * d)},
       {&P->tail, sz(8 * std::max<int64_t>(kMaxD, d * r * d))},
