@@ -347,8 +347,9 @@ usfft_status usfft_eval(usfft_result_t res, const double* y_dev, int64_t n,
  * allocate (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc): the same evaluation and the same kernels, with the
  * frequency set, the mapped points and the phase matrix of each chunk held
- * in a fixed 64 MiB device array of the library instead of temporary
- * buffers.  Limit: the frequency set (n_freq x d int32, padded to 256
+ * in a fixed 64 MiB device array of the library instead of the result's
+ * evaluation workspace (which usfft_eval allocates on a result's first
+ * call and grows when a call needs more).  Limit: the frequency set (n_freq x d int32, padded to 256
  * bytes) plus 64 points x (d + 2 n_freq) doubles must fit in 64 MiB, i.e.
  * up to about 65 000 frequencies; larger results give EINVAL and leave the
  * output untouched.  Each GPU holds one such array for the life of the
